@@ -1,0 +1,20 @@
+"""CPU FP64 oracle for the elastance and mobility integral equations (Rachh & Greengard,
+"Integral equation methods for elastance and mobility problems in two dimensions").
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product package imports, links or calls this package;
+only tests/, the smoke check in __graft_entry__ and the cpu_baseline leg of bench.py use it.
+It shares no code with the HIP path: inputs come from the seeded generators in
+paper_1507_05925_amd.workloads (curve samples and right-hand sides only), and every step of the
+method is written out here again, plainly, in float64.
+
+Contents
+  nystrom   dense trapezoidal Nystrom assembly of (1/2 I + K + L) and (1/2 I + Kcal + L), right-hand
+            sides, LU solve, outputs, elastance matrix P and mobility matrix M.
+  matfree   the same operators applied matrix-free by plain C loops (for node counts where the
+            dense matrix does not fit), GMRES via scipy, sampled-row applies.
+
+Parity status: every function is pinned by tests/test_oracle_*.py against closed forms, the
+paper's tables, discrete Gauss-law identities, invariants or brute force (no function is
+"parity unpinned"); the splash-test and nanocomposite values have no printed potentials, so
+those geometries are used only as inputs.
+"""

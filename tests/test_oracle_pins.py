@@ -1,0 +1,467 @@
+"""Pins of the CPU FP64 oracle against what the paper and the mathematics fix (no GPU).
+
+Each test names the passage of Rachh & Greengard it rests on. None of them re-types the oracle's
+own formula: entries are checked against independent complex-variable forms and curve limits,
+solutions against closed forms, printed tables, Gauss-law identities and invariants.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import matfree as mf
+from oracle import nystrom as ny
+from paper_1507_05925_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _geo(curves):
+    return ny.geometry_of(curves)
+
+
+def _mixed(seed=11, nbodies=4, n=64):
+    rng = np.random.default_rng(seed)
+    return wl.mixed_grid(rng, nbodies, np.full(nbodies, n))
+
+
+# ------------------------------------------------------------------------------------------
+# P1: kernel entries against independent complex-variable forms
+# ------------------------------------------------------------------------------------------
+
+def test_laplace_entries_complex_form():
+    """dG/dn_x (x, y) = -(1/2pi) Re(n / (x - y)) in complex notation (G = -(1/2pi) log|x-y|)."""
+    geo = _geo(_mixed())
+    K = ny.laplace_K(geo)
+    z = geo["x"] + 1j * geo["y"]
+    n = geo["nx"] + 1j * geo["ny"]
+    r = z[:, None] - z[None, :]
+    np.fill_diagonal(r, 1.0)
+    ref = -(1 / (2 * np.pi)) * np.real(n[:, None] / r) * geo["w"][None, :]
+    off = ~np.eye(geo["M"], dtype=bool)
+    assert np.allclose(K[off], ref[off], rtol=1e-13, atol=1e-15)
+
+
+def test_stokes_entries_complex_form():
+    """n_l T_{abl} rho_b with T = -(1/pi) r r r / |r|^4 equals, as a complex number,
+    -(1/pi) * (1/4) [conj(n) conj(rho) r / conj(r)^2 + (conj(n) rho + n conj(rho)) / conj(r) + n rho / r]."""
+    geo = _geo(_mixed(seed=12))
+    M = geo["M"]
+    K = ny.stokes_K(geo)
+    rng = np.random.default_rng(5)
+    rho = rng.standard_normal(2 * M)
+    out = (K @ rho).reshape(M, 2)
+    z = geo["x"] + 1j * geo["y"]
+    n = geo["nx"] + 1j * geo["ny"]
+    rc = rho[0::2] + 1j * rho[1::2]
+    r = z[:, None] - z[None, :]
+    np.fill_diagonal(r, 1.0)
+    rr = rc[None, :] * geo["w"][None, :]
+    nn = n[:, None]
+    v = 0.25 * (np.conj(nn) * np.conj(rr) * r / np.conj(r) ** 2
+                + (np.conj(nn) * rr + nn * np.conj(rr)) / np.conj(r) + nn * rr / r)
+    np.fill_diagonal(v, 0.0)
+    ref = -(1 / np.pi) * v.sum(1)
+    # add the diagonal blocks of K itself (pinned separately below)
+    Kd = K.reshape(M, 2, M, 2)
+    idx = np.arange(M)
+    diag = np.einsum("iab,ib->ia", Kd[idx, :, idx, :], rho.reshape(M, 2))
+    assert np.allclose(out[:, 0] - diag[:, 0], ref.real, rtol=1e-12, atol=1e-13)
+    assert np.allclose(out[:, 1] - diag[:, 1], ref.imag, rtol=1e-12, atol=1e-13)
+
+
+def _three_node_body(curve_fn, t0, eps):
+    """Samples of one curve at t0 - eps, t0, t0 + eps (one body of 3 nodes)."""
+    ts = np.array([t0 - eps, t0, t0 + eps])
+    x, y, dx, dy, ddx, ddy = curve_fn(ts)
+    return ny.geometry(np.array([3]), x, y, dx, dy, ddx, ddy)
+
+
+@pytest.mark.parametrize("t0", [0.3, 1.7, 4.0])
+def test_diagonal_limits_along_curve(t0):
+    """The principal-value diagonal equals the limit of the off-diagonal kernel as the source
+    approaches the target along the curve (reading of the K_{ii} and Kcal_{ii} definitions).
+    The symmetric average over +-eps removes the O(eps) term."""
+    def starfish(t):
+        r0, a = 0.7, 0.3
+        r = r0 * (1 + a * np.cos(5 * t))
+        dr = -r0 * a * 5 * np.sin(5 * t)
+        ddr = -r0 * a * 25 * np.cos(5 * t)
+        return wl._radial(t, 0.2, -0.1, r, dr, ddr, 0.4)
+
+    for eps, tol in ((1e-3, 1e-5), (1e-4, 1e-7)):
+        geo = _three_node_body(starfish, t0, eps)
+        K = ny.laplace_K(geo) / geo["w"][None, :]
+        assert abs(0.5 * (K[1, 0] + K[1, 2]) - K[1, 1]) < tol * max(1.0, abs(K[1, 1]))
+        Ks = (ny.stokes_K(geo) / np.repeat(geo["w"], 2)[None, :]).reshape(3, 2, 3, 2)
+        lim = 0.5 * (Ks[1, :, 0, :] + Ks[1, :, 2, :])
+        assert np.abs(lim - Ks[1, :, 1, :]).max() < tol * max(1.0, np.abs(Ks[1, :, 1, :]).max())
+
+
+# ------------------------------------------------------------------------------------------
+# P2: single disc, closed forms (exact for any node count: mu = 0 identically)
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,R,c", [(3, 1.0, (0, 0)), (16, 0.7, (0.3, -0.2)), (64, 2.3, (5.0, 1.0))])
+def test_single_disc_elastance(n, R, c):
+    """Charged disc: u = S sigma with sigma = q / (2 pi R) is constant inside and equals
+    -(q / 2 pi) log R (single-layer potential of a uniform density on a circle)."""
+    geo = _geo(wl.single_disc(n, R, *c))
+    q = 1.7
+    res = ny.elastance_solve(geo, [q])
+    assert np.abs(res["mu"]).max() < 1e-14
+    assert abs(res["phi"][0] - (-(q / (2 * np.pi)) * np.log(R))) < 1e-14
+
+
+@pytest.mark.parametrize("n,R,c", [(4, 1.0, (0, 0)), (16, 0.7, (0.3, -0.2)), (64, 2.3, (5.0, 1.0))])
+def test_single_disc_mobility(n, R, c):
+    """Rotating disc: T = 4 pi R^2 omega (torque on a cylinder rotating in Stokes flow, viscosity 1),
+    v = 0; translating disc with net force F (no-net-force condition relaxed, representation
+    unchanged): v = F (1 - 2 log R) / (8 pi), omega = 0."""
+    geo = _geo(wl.single_disc(n, R, *c))
+    F = np.array([0.3, -0.4])
+    T = 1.1
+    res = ny.mobility_solve(geo, [F[0], F[1], T])
+    assert np.abs(res["mu"]).max() < 1e-14
+    v, om = res["VW"][:2], res["VW"][2]
+    assert abs(om - T / (4 * np.pi * R * R)) < 1e-14
+    assert np.allclose(v, F * (1 - 2 * np.log(R)) / (8 * np.pi), atol=1e-14)
+
+
+# ------------------------------------------------------------------------------------------
+# P4, P5: two discs, the paper's exact bipolar solution and its two tables
+# ------------------------------------------------------------------------------------------
+
+def _bipolar_dphi_per_charge(d):
+    """Exact two-disc solution (two-disc test): with alpha = sqrt(d + d^2/4) and the near point
+    of the right disc x0 = (d/2, 0), a physical charge +q on disc 1 and -q on disc 2 gives
+    phi_1 - phi_2 = (q / pi) log((x0 + alpha) / (alpha - x0))."""
+    al = math.sqrt(d + d * d / 4)
+    x0 = d / 2
+    return math.log((x0 + al) / (al - x0)) / math.pi
+
+
+@pytest.mark.parametrize("d,n,tol", [(0.5, 192, 1e-12), (0.05, 768, 1e-9)])
+def test_two_disc_bipolar_closed_form(d, n, tol):
+    geo = _geo(wl.two_discs(d, n))
+    q = 1.3
+    phi = ny.elastance_solve(geo, [q, -q])["phi"]
+    assert abs((phi[0] - phi[1]) - q * _bipolar_dphi_per_charge(d)) < tol
+    assert abs(phi[0] + phi[1]) < 1e-12  # antisymmetry of the neutral pair
+
+
+def test_two_disc_table1():
+    """Two-disc table: the printed q1 is -q/(2 pi) in units where q = -int du/dn; with the printed
+    charges the prescribed potential difference 0.209 - (-0.123) = 0.332 is recovered to the
+    table's six printed digits (grounding differs by the constant u_inf, so differences only)."""
+    tab = json.load(open(os.path.join(GOLDEN, "two_disc_tables.json")))["elastance"]
+    dphi_paper = tab["phi1"] - tab["phi2"]
+    for row, n in zip(tab["rows"][:2], (256, 1024)):
+        geo = _geo(wl.two_discs(row["d"], n))
+        q = -2 * np.pi * row["q1"]
+        phi = ny.elastance_solve(geo, [q, -q])["phi"]
+        assert abs((phi[0] - phi[1]) - dphi_paper) / dphi_paper < 3e-6
+
+
+def test_two_disc_table2_mobility():
+    """Two-disc resistance/mobility table: the printed forces and torques, fed to the mobility
+    solve, reproduce the prescribed v_1 - v_2 and omega_1, omega_2 (velocity at infinity cancels
+    in the difference) to the table's accuracy; the literal pairing of the printed velocity
+    vectors is not reproduced."""
+    tab = json.load(open(os.path.join(GOLDEN, "two_disc_tables.json")))["mobility"]
+    dv = np.array(tab["v_body1"]) - np.array(tab["v_body2"])
+    for row, n in zip(tab["rows"][:2], (256, 1024)):
+        geo = _geo(wl.two_discs(row["d"], n))
+        FT = [row["F11"], row["F21"], row["T1"], -row["F11"], -row["F21"], row["T2"]]
+        VW = ny.mobility_solve(geo, FT)["VW"]
+        got = VW[0:2] - VW[3:5]
+        assert np.abs(got - dv).max() / np.abs(dv).max() < 5e-6
+        assert abs(VW[2] - tab["omega1"]) < 2e-5 and abs(VW[5] - tab["omega2"]) < 2e-5
+        literal = np.array([2.09 - (-1.034), 1.00 - 0.254])
+        assert np.abs(got - literal).max() > 1.0
+
+
+# ------------------------------------------------------------------------------------------
+# P3: discrete Gauss laws (double-layer identities eq. DLP2, DLP1 and their Stokes forms)
+# ------------------------------------------------------------------------------------------
+
+def test_laplace_gauss_law_columns():
+    """sum_{x in Gamma_i} w_x dG/dn_x(x, y) = -1/2 for y on Gamma_i, 0 for y on another body."""
+    geo = _geo(wl.mobility_ellipses(5, 128, seed=7)[0])
+    K = ny.laplace_K(geo) / geo["w"][None, :]
+    B = geo["body"]
+    for b in range(geo["N"]):
+        s = geo["w"][B == b] @ K[B == b]
+        assert np.abs(s[B == b] + 0.5).max() < 1e-12
+        assert np.abs(s[B != b]).max() < 1e-12
+
+
+def test_stokes_gauss_law_force_and_torque():
+    """sum_x w_x n_{x,l} T_{abl}(x, y) = -delta_ab / 2 on the same body, 0 otherwise; the torque
+    moment sum_x w_x p_x,a n_l T_{abl} = -p_y,b / 2 (eqs. DLP2Stokes, DLP2StokesTorque)."""
+    geo = _geo(wl.mobility_ellipses(4, 128, seed=8)[0])
+    M, B = geo["M"], geo["body"]
+    Ks = (ny.stokes_K(geo) / np.repeat(geo["w"], 2)[None, :]).reshape(M, 2, M, 2)
+    p = np.stack([geo["px"], geo["py"]], 1)
+    for b in range(geo["N"]):
+        m = B == b
+        s = np.einsum("i,iakc->akc", geo["w"][m], Ks[m])
+        e = np.zeros((2, M, 2))
+        e[0, m, 0] = e[1, m, 1] = -0.5
+        assert np.abs(s - e).max() < 1e-12
+        t = np.einsum("i,ia,iakc->kc", geo["w"][m], p[m], Ks[m])
+        et = np.zeros((M, 2))
+        et[m] = -0.5 * p[m]
+        assert np.abs(t - et).max() < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# P6: invariants of the solutions
+# ------------------------------------------------------------------------------------------
+
+def test_completion_constraints_hold():
+    """Solving the completed equation yields int mu = 0 per body (equivalence lemma), and for
+    Stokes int mu = 0 and int (x - x^c)^perp . mu = 0 (its Stokes counterpart)."""
+    g, q = wl.elastance_small()
+    geo = _geo(g)
+    mu = ny.elastance_solve(geo, q)["mu"]
+    assert np.abs(ny.body_charge(geo, mu)).max() < 1e-13
+    g, FT = wl.mobility_ellipses(5, 96, seed=3)
+    geo = _geo(g)
+    mu = ny.mobility_solve(geo, FT)["mu"]
+    assert np.abs(ny.body_force_torque(geo, mu)).max() < 1e-12
+
+
+def test_P_and_M_symmetric_positive():
+    """Reciprocity: P = P^T and M = M^T; energy q.Pq > 0 for neutral q (E = 1/2 q^T P q).
+    Discretely the asymmetry is a discretisation error and decays spectrally with n."""
+    geo = _geo(_mixed(seed=21, nbodies=5, n=160))
+    P = ny.elastance_matrix(geo)
+    assert np.abs(P - P.T).max() < 1e-13 * np.abs(P).max()
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        q = rng.standard_normal(geo["N"])
+        q -= q.mean()
+        assert q @ P @ q > 0
+    Mm = ny.mobility_matrix(geo)
+    assert np.abs(Mm - Mm.T).max() < 1e-13 * np.abs(Mm).max()
+    ev = np.linalg.eigvalsh(0.5 * (Mm + Mm.T))
+    # positive on zero-net-force subspace: project out the total-force directions
+    N = geo["N"]
+    Z = np.zeros((3 * N, 2))
+    Z[0::3, 0] = Z[1::3, 1] = 1.0
+    Q, _ = np.linalg.qr(Z)
+    Pp = np.eye(3 * N) - Q @ Q.T
+    evp = np.linalg.eigvalsh(Pp @ Mm @ Pp)
+    assert evp[2:].min() > 0 and ev.max() > 0
+
+
+def test_translation_rotation_permutation():
+    """P and M do not change under translation; under rotation by theta, M transforms with the
+    per-body block diag(R(theta), 1) (v, F rotate; omega, T do not); permuting bodies permutes
+    rows and columns."""
+    rng = np.random.default_rng(4)
+    n, N = 80, 4
+    shapes = [(rng.uniform(0.5, 0.9), rng.uniform(0.4, 0.8), rng.uniform(0, 6)) for _ in range(N)]
+    cen = np.array([[0, 0], [2.3, 0.2], [0.1, 2.2], [2.5, 2.4]], float)
+
+    def build(shift=(0.0, 0.0), theta=0.0, perm=range(N)):
+        c, s = math.cos(theta), math.sin(theta)
+        R = np.array([[c, -s], [s, c]])
+        samples = []
+        for j in perm:
+            a, b, th = shapes[j]
+            cc = R @ cen[j] + np.asarray(shift)
+            samples.append(wl.ellipse_samples(n, cc[0], cc[1], a, b, th + theta))
+        return _geo(wl.assemble(samples, cen, np.ones(N)))
+
+    P0, M0 = ny.elastance_matrix(build()), ny.mobility_matrix(build())
+    Pt, Mt = ny.elastance_matrix(build(shift=(3.7, -1.2))), ny.mobility_matrix(build(shift=(3.7, -1.2)))
+    assert np.abs(P0 - Pt).max() < 1e-12 and np.abs(M0 - Mt).max() < 1e-12
+    th = 0.9
+    Mr = ny.mobility_matrix(build(theta=th))
+    c, s = math.cos(th), math.sin(th)
+    Rb = np.kron(np.eye(N), np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]]))
+    assert np.abs(Mr - Rb @ M0 @ Rb.T).max() < 1e-11
+    perm = [2, 0, 3, 1]
+    Pp = ny.elastance_matrix(build(perm=perm))
+    assert np.abs(Pp - P0[np.ix_(perm, perm)]).max() < 1e-12
+
+
+def test_scale_law_elastance():
+    """Scaling the geometry by lambda: G(lambda r) = G(r) - (1/2pi) log lambda, so for the
+    representation grounded at infinity P(lambda Gamma) = P(Gamma) - (log lambda / 2pi) 1 1^T."""
+    g = _mixed(seed=31, nbodies=3, n=96)
+    lam = 2.5
+    gs = wl.Curves(g.nodes_per_body, lam * g.x, lam * g.y, lam * g.dx, lam * g.dy, lam * g.ddx,
+                   lam * g.ddy, lam * g.centers, lam * g.radii)
+    P1, P2 = ny.elastance_matrix(_geo(g)), ny.elastance_matrix(_geo(gs))
+    assert np.abs(P2 - (P1 - np.log(lam) / (2 * np.pi))).max() < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# P7: spectral convergence (a wrong diagonal would give algebraic O(h) convergence)
+# ------------------------------------------------------------------------------------------
+
+def _starfish_pair(n):
+    s = [wl.starfish_samples(n, 0, 0, 0.5, 0.0), wl.starfish_samples(n, 1.6, 0.0, 0.5, math.pi / 5)]
+    return wl.assemble(s, [[0, 0], [1.6, 0]], [0.65, 0.65])
+
+
+def test_spectral_convergence():
+    ref = ny.elastance_solve(_geo(_starfish_pair(256)), [1.0, -0.3])["phi"]
+    errs = [np.abs(ny.elastance_solve(_geo(_starfish_pair(n)), [1.0, -0.3])["phi"] - ref).max()
+            for n in (48, 64, 96, 128)]
+    assert errs[0] < 1e-5 and errs[-1] < 1e-13
+    assert all(e2 < e1 / 50 for e1, e2 in zip(errs[:-1], errs[1:]))
+    refm = ny.mobility_solve(_geo(_starfish_pair(256)), [1.0, 0.5, 0.2, -1.0, -0.5, 0.1])["VW"]
+    errm = [np.abs(ny.mobility_solve(_geo(_starfish_pair(n)), [1.0, 0.5, 0.2, -1.0, -0.5, 0.1])["VW"]
+                   - refm).max() for n in (64, 128, 160)]
+    assert errm[-1] < 1e-13 and errm[1] < errm[0] / 1e4
+
+
+# ------------------------------------------------------------------------------------------
+# P8: the matrix-free oracle against the dense one, GMRES against LU
+# ------------------------------------------------------------------------------------------
+
+def test_matfree_matches_dense():
+    g, q = wl.elastance_small()
+    geo = _geo(g)
+    rng = np.random.default_rng(9)
+    mu = rng.standard_normal(geo["M"])
+    A = ny.laplace_operator(geo)
+    assert np.abs(A @ mu - mf.laplace_apply(geo, mu)).max() < 1e-13
+    rows = np.array([0, 3, 200, 511])
+    assert np.abs((A @ mu)[rows] - mf.laplace_apply(geo, mu, rows=rows)).max() < 1e-13
+    r1, r2 = ny.elastance_solve(geo, q), mf.elastance_solve(geo, q)
+    assert np.abs(r1["phi"] - r2["phi"]).max() < 1e-12
+    g, FT = wl.mobility_ellipses(5, 96, seed=5)
+    geo = _geo(g)
+    mu = rng.standard_normal(2 * geo["M"])
+    A = ny.stokes_operator(geo)
+    assert np.abs(A @ mu - mf.stokes_apply(geo, mu)).max() < 1e-12
+    r1, r2 = ny.mobility_solve(geo, FT), mf.mobility_solve(geo, FT)
+    assert np.abs(r1["VW"] - r2["VW"]).max() < 1e-11
+
+
+# ------------------------------------------------------------------------------------------
+# Planted mistakes (in the oracle, on the CPU): the pins above must catch each
+# ------------------------------------------------------------------------------------------
+
+def test_planted_wrong_diagonal_is_caught(monkeypatch):
+    orig = ny.laplace_K
+
+    def wrong(geo):
+        K = orig(geo)
+        np.fill_diagonal(K, +geo["kappa"] * geo["w"] / (4 * np.pi))  # sign error
+        return K
+
+    monkeypatch.setattr(ny, "laplace_K", wrong)
+    with pytest.raises(AssertionError):
+        test_laplace_gauss_law_columns()
+    with pytest.raises(AssertionError):
+        test_spectral_convergence()
+
+
+def test_planted_dropped_torque_completion_is_caught(monkeypatch):
+    """Dropping the (x - x^c)^perp int (y - x^c)^perp . mu term of L leaves a rotational null
+    direction; the torque constraint on mu then fails."""
+    def wrong(geo):
+        M = geo["M"]
+        b = geo["body"]
+        S = (b[:, None] == b[None, :]) * geo["w"][None, :]
+        L = np.zeros((M, 2, M, 2))
+        L[:, 0, :, 0] = S
+        L[:, 1, :, 1] = S
+        return L.reshape(2 * M, 2 * M)
+
+    monkeypatch.setattr(ny, "stokes_L", wrong)
+    with pytest.raises((AssertionError, np.linalg.LinAlgError)):
+        test_completion_constraints_hold()
+
+
+def test_planted_stresslet_sign_is_caught(monkeypatch):
+    orig = ny.stokes_K
+
+    def wrong(geo):
+        M = geo["M"]
+        K = orig(geo).reshape(M, 2, M, 2)
+        idx = np.arange(M)
+        D = K[idx, :, idx, :].copy()
+        K = -K
+        K[idx, :, idx, :] = D
+        return K.reshape(2 * M, 2 * M)
+
+    monkeypatch.setattr(ny, "stokes_K", wrong)
+    with pytest.raises(AssertionError):
+        test_stokes_gauss_law_force_and_torque()
+    with pytest.raises(AssertionError):
+        test_two_disc_table2_mobility()
+
+
+# ------------------------------------------------------------------------------------------
+# Geometry: length, arc-length centroid and W against adaptive quadrature of the analytic curve;
+# curvature and normals against closed forms of the ellipse
+# ------------------------------------------------------------------------------------------
+
+def _ellipse_param(a, b, th, cx, cy):
+    def xy(t):
+        x, y, dx, dy, _, _ = wl._ellipse(np.atleast_1d(t), cx, cy, a, b, th)
+        return x[0], y[0], math.hypot(dx[0], dy[0])
+    return xy
+
+
+def test_geometry_against_quadrature():
+    """|Gamma| = int ds, x^c = (1/|Gamma|) int x ds (centroid of the mobility problem statement),
+    W = int |x - x^c|^2 ds (eq. rho) by scipy.integrate.quad on the analytic ellipse; the
+    curvature of an ellipse is ab / (a^2 sin^2 t + b^2 cos^2 t)^(3/2); n points outward."""
+    from scipy.integrate import quad
+    a, b, th, cx, cy = 0.9, 0.35, 0.7, 1.3, -0.4
+    g = wl.assemble([wl.ellipse_samples(64, cx, cy, a, b, th)], [[cx, cy]], [a])
+    geo = ny.geometry_of(g)
+    f = _ellipse_param(a, b, th, cx, cy)
+    L = quad(lambda t: f(t)[2], 0, 2 * np.pi, epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+    X = quad(lambda t: f(t)[0] * f(t)[2], 0, 2 * np.pi, epsabs=1e-14, epsrel=1e-14, limit=200)[0] / L
+    Y = quad(lambda t: f(t)[1] * f(t)[2], 0, 2 * np.pi, epsabs=1e-14, epsrel=1e-14, limit=200)[0] / L
+    W = quad(lambda t: ((f(t)[0] - X) ** 2 + (f(t)[1] - Y) ** 2) * f(t)[2], 0, 2 * np.pi,
+             epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+    assert abs(geo["length"][0] - L) < 1e-12
+    assert abs(geo["xc"][0, 0] - X) < 1e-12 and abs(geo["xc"][0, 1] - Y) < 1e-12
+    assert abs(geo["W"][0] - W) < 1e-12
+    t = 2 * np.pi * np.arange(64) / 64
+    kap = a * b / (a * a * np.sin(t) ** 2 + b * b * np.cos(t) ** 2) ** 1.5
+    assert np.abs(geo["kappa"] - kap).max() < 1e-12
+    out = (geo["x"] - cx) * geo["nx"] + (geo["y"] - cy) * geo["ny"]
+    assert out.min() > 0
+
+
+def test_geometry_uneven_speed_centroid():
+    """A Fourier curve with uneven parameter speed: the node average differs from the arc-length
+    centroid, and the oracle returns the latter (a planted node-average centroid fails here)."""
+    from scipy.integrate import quad
+    coeffs, beta = [0.2, 0.1, 0.05], 0.3
+
+    def f(t):
+        x, y, dx, dy, _, _ = \
+            _fourier_at(np.atleast_1d(t), coeffs, beta)
+        return x[0], y[0], math.hypot(dx[0], dy[0])
+
+    g = wl.assemble([wl.fourier_samples(96, 0.0, 0.0, coeffs, beta)], [[0, 0]], [1.4])
+    geo = ny.geometry_of(g)
+    L = quad(lambda t: f(t)[2], 0, 2 * np.pi, epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+    X = quad(lambda t: f(t)[0] * f(t)[2], 0, 2 * np.pi, epsabs=1e-14, epsrel=1e-14, limit=200)[0] / L
+    assert abs(geo["xc"][0, 0] - X) < 1e-12
+    assert abs(g.x.mean() - X) > 1e-3
+
+
+def _fourier_at(t, coeffs, beta):
+    r = np.ones_like(t)
+    dr = np.zeros_like(t)
+    ddr = np.zeros_like(t)
+    for k, a in enumerate(coeffs, start=1):
+        r = r + a * np.sin(k * t)
+        dr = dr + a * k * np.cos(k * t)
+        ddr = ddr - a * k * k * np.sin(k * t)
+    return wl._radial(t, 0.0, 0.0, r, dr, ddr, beta)
