@@ -1,0 +1,179 @@
+/* bie2d.h - C ABI of the MI355X (gfx950) second-kind integral-equation library for the 2D
+ * elastance (Laplace) and mobility (Stokes) problems of Rachh & Greengard, "Integral equation
+ * methods for elastance and mobility problems in two dimensions".
+ *
+ * Problem (elastance section): N disjoint smooth closed curves Gamma_j, positively oriented,
+ * outward normal n. Given charges q_j, find conductor potentials phi_j (phi = P q) with u
+ * harmonic outside, u = phi_j on Gamma_j, -int_{Gamma_j} du/dn = q_j, u -> 0 at infinity.
+ * Mobility section: given forces and torques (F_j, T_j) on rigid bodies in Stokes flow of
+ * viscosity 1, find rigid motions (v_j, omega_j) about the arc-length centroid x^c_j
+ * (U = M F, ordered (F_1, T_1, F_2, T_2, ...) -> (v_1, omega_1, ...)).
+ *
+ * Method: u = S(mu + sigma), sigma_j = q_j/|Gamma_j| (eq. sigma), with
+ *     (1/2 I + K + L) mu = -(1/2 I + K) sigma                          (eq. ModRep2)
+ * K = normal derivative of the single layer at the target, L_i mu = int_{Gamma_i} mu ds; and
+ * u = Scal(mu + rho), rho_j = F_j/|Gamma_j| + T_j (x - x^c_j)^perp / W_j (eq. rho), with
+ *     (1/2 I + Kcal + L) mu = -(1/2 I + Kcal) rho                      (eq. ModRep2Stokes)
+ * Kcal = stresslet traction operator, L_i mu = int mu + (x - x^c_i)^perp int (y - x^c_i)^perp . mu.
+ * Discretisation: trapezoidal Nystrom on t_k = 2 pi k / n_b, w_k = (2 pi / n_b)|x'(t_k)|;
+ * diagonal entries are the smooth kernel limits -kappa/(4 pi) and -(kappa/2 pi) tau tau^T.
+ *
+ * Conventions for every call below
+ *   - Pointers marked (device) are HIP device pointers on the geometry's device; (host) are host
+ *     memory. The caller owns every buffer it passes; the library copies what it keeps.
+ *   - `stream` is a hipStream_t (NULL = the null stream). All work is enqueued on it; calls that
+ *     return results needed on the host (iteration counts, info) synchronise that stream.
+ *   - Vector densities are node-major: entry 2k + a is component a of node k. Multiple
+ *     right-hand sides are stacked: rhs r occupies [r * len, (r + 1) * len).
+ *   - Return value: BIE_OK (0) or a negative error code; bie_last_error() gives the message of
+ *     the most recent failure on the calling thread. Outputs are written only on BIE_OK (and on
+ *     BIE_ENOCONV, where the last iterate is returned and info is filled).
+ *   - Thread safety: distinct geometries may be used from distinct threads; calls that overlap
+ *     on one geometry (it owns the workspace) race.
+ */
+#ifndef BIE2D_H
+#define BIE2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BIE_OK 0
+#define BIE_EINVAL (-1)   /* bad sizes or pointers, non-finite input, clockwise curve */
+#define BIE_ENOMEM (-2)   /* device allocation failed */
+#define BIE_ENOCONV (-3)  /* GMRES did not reach the tolerance within max_iter */
+#define BIE_EDEVICE (-4)  /* HIP runtime error */
+
+#define BIE_FP64 0   /* every step in float64 */
+#define BIE_MIXED 1  /* far-field pair sums in float32 (body-relative coordinates, float64
+                        accumulation across source bodies) inside GMRES; float64 self-body
+                        blocks, diagonal, completion, Arnoldi and refinement residuals */
+
+#define BIE_DIRECT 0 /* all-pairs direct summation */
+#define BIE_FMM 1    /* 2D fast multipole method for the far field */
+
+typedef struct bie_geom bie_geom; /* device-resident geometry + workspace (opaque) */
+
+typedef struct {
+  int precision;    /* BIE_FP64 | BIE_MIXED                                            */
+  int method;       /* BIE_DIRECT | BIE_FMM                                            */
+  double tol;       /* target relative residual ||f - A mu|| / ||f|| (float64 apply)    */
+  int restart;      /* GMRES restart length m (Krylov vectors per cycle)               */
+  int max_iter;     /* cap on GMRES iterations summed over cycles and refinements      */
+  double inner_tol; /* BIE_MIXED: relative tolerance of each inner float32-apply solve */
+  int max_refine;   /* BIE_MIXED: cap on outer refinement steps                       */
+  int fmm_order;    /* BIE_FMM: expansion order p (terms per expansion)               */
+  int fmm_leaf;     /* BIE_FMM: maximum nodes per leaf box                            */
+} bie_opts;
+
+typedef struct {
+  int iters;             /* GMRES iterations (all cycles, all refinements; max over rhs)  */
+  int refinements;       /* outer refinement steps (BIE_MIXED), else 0                     */
+  int applies_fp64;      /* float64 operator applications                                 */
+  int applies_fp32;      /* float32 far-field operator applications                        */
+  double rel_residual;   /* final true relative residual, float64 apply (max over rhs)    */
+  double seconds;        /* wall time of the call                                         */
+  long long pairs;       /* pair interactions evaluated (direct: M^2 per apply per rhs)   */
+} bie_info;
+
+/* Message of the last failure on this thread (never NULL). */
+const char *bie_last_error(void);
+
+/* Fills *o with the defaults: BIE_FP64, BIE_DIRECT, tol 1e-12, restart 100, max_iter 500,
+ * inner_tol 1e-6, max_refine 10, fmm_order 30, fmm_leaf 64. */
+int bie_default_opts(bie_opts *o);
+
+/* ---- a1: geometry and quadrature (elastance section; eq. rho for W; centroid of the mobility
+ * problem statement) ------------------------------------------------------------------------
+ * nbodies        N >= 1
+ * nodes_per_body (host) [N], each n_b >= 3; bodies are contiguous, M = sum n_b
+ * curve          (device) [6][M] float64: x, y, x'(t), y'(t), x''(t), y''(t) at t_k = 2 pi k / n_b
+ * interior       (device) [N][2] float64 points p_j inside body j at which phi_j, (v_j, omega_j)
+ *                are read off, or NULL for the arc-length centroids
+ * Computes on the device: outward normal n = (y', -x')/|x'|, curvature, weights
+ * w_k = (2 pi / n_b)|x'(t_k)|, |Gamma_j|, x^c_j = sum w x / sum w, W_j = sum w |x - x^c_j|^2,
+ * p_k = (x_k - x^c_j)^perp, float32 body-relative coordinates.
+ * Errors: BIE_EINVAL for N < 1, n_b < 3, NULL curve, non-finite samples, or a body whose
+ * signed area is not positive (clockwise). */
+int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *curve,
+                    const double *interior, void *stream, bie_geom **out);
+int bie_geom_destroy(bie_geom *g);
+int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M);
+/* Copies the per-node quadrature data (device out [8][M]: x, y, nx, ny, w, kappa, px, py) and
+ * per-body data (device out_body [4][N]: |Gamma|, xc, yc, W). Either may be NULL. */
+int bie_geom_export(const bie_geom *g, double *out, double *out_body, void *stream);
+/* Device bytes held by the geometry including its current workspace. */
+long long bie_geom_device_bytes(const bie_geom *g);
+
+/* ---- a3 + a4: the operator apply (eqs. ModRep2 / ModRep2Stokes) ----------------------------
+ * out = (1/2 I + K + L) mu      (with_L = 1)  or  (1/2 I + K) mu  (with_L = 0)
+ * Laplace: mu, out (device) [nrhs][M].  Stokes: (device) [nrhs][2M] node-major.
+ * precision: BIE_FP64, or BIE_MIXED (float32 far field, float64 self blocks and terms).
+ * method: BIE_DIRECT or BIE_FMM. mu and out must not alias. */
+int bie_laplace_apply(bie_geom *g, int precision, int method, int with_L, int nrhs,
+                      const double *mu, double *out, void *stream);
+int bie_stokes_apply(bie_geom *g, int precision, int method, int with_L, int nrhs,
+                     const double *mu, double *out, void *stream);
+
+/* ---- a2: incident densities and right-hand sides -------------------------------------------
+ * sigma_k = q_j/|Gamma_j| (eq. sigma); f = -(1/2 I + K) sigma.  q (device) [nrhs][N];
+ * sigma, f (device) [nrhs][M]; either output may be NULL.
+ * rho_k = F_j/|Gamma_j| + T_j p_k / W_j (eq. rho); f = -(1/2 I + Kcal) rho.
+ * FT (device) [nrhs][3N] as (F_1x, F_1y, T_1, ...); rho, f (device) [nrhs][2M]. */
+int bie_elastance_rhs(bie_geom *g, int nrhs, const double *q, double *sigma, double *f,
+                      void *stream);
+int bie_mobility_rhs(bie_geom *g, int nrhs, const double *FT, double *rho, double *f,
+                     void *stream);
+
+/* ---- a7: outputs read off inside the bodies (u constant, resp. a rigid motion, inside) ------
+ * phi_j = S(dens)(p_j) = -(1/2 pi) sum_k w_k dens_k log|p_j - x_k|. dens (device) [nrhs][M],
+ * phi (device) [nrhs][N].
+ * Stokes: u = Scal(dens), omega_j = half the vorticity at p_j, v_j = u(p_j) - omega_j
+ * (p_j - x^c_j)^perp. dens (device) [nrhs][2M], VW (device) [nrhs][3N] as (v_1x, v_1y, w_1, ...). */
+int bie_laplace_potential(bie_geom *g, int nrhs, const double *dens, double *phi, void *stream);
+int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *VW, void *stream);
+
+/* ---- a6 + the whole path: solves ------------------------------------------------------------
+ * Elastance: q (device) [nrhs][N] -> phi (device) [nrhs][N]; mu_out (device) [nrhs][M] or NULL.
+ * Mobility: FT (device) [nrhs][3N] -> VW (device) [nrhs][3N]; mu_out (device) [nrhs][2M] or NULL.
+ * Any q is accepted: for sum q != 0 (or sum F != 0) the same representation gives the unique
+ * field with u + (Q/2 pi) log|x| -> 0 (its potential is grounded at infinity in that sense).
+ * opts NULL = defaults; info may be NULL. BIE_ENOCONV: outputs hold the last iterate. */
+int bie_elastance_solve(bie_geom *g, int nrhs, const double *q, double *phi, double *mu_out,
+                        const bie_opts *opts, bie_info *info, void *stream);
+int bie_mobility_solve(bie_geom *g, int nrhs, const double *FT, double *VW, double *mu_out,
+                       const bie_opts *opts, bie_info *info, void *stream);
+
+/* ---- a8: assembly of P and M column by column (elastance / mobility statements) -------------
+ * P (device) [N][N] column-major: column j = phi for q = e_j.
+ * Mmat (device) [3N][3N] column-major: column j = (v_1, omega_1, ...) for (F_1, T_1, ...) = e_j.
+ * The identity right-hand-side block is solved as one multi-rhs solve in chunks of at most
+ * `max_rhs_per_pass` columns (0 = library default). */
+int bie_elastance_matrix(bie_geom *g, double *P, int max_rhs_per_pass, const bie_opts *opts,
+                         bie_info *info, void *stream);
+int bie_mobility_matrix(bie_geom *g, double *Mmat, int max_rhs_per_pass, const bie_opts *opts,
+                        bie_info *info, void *stream);
+
+/* ---- instrumentation (not a step of the method) ---------------------------------------------
+ * When enabled, the library records a pair of HIP events on the launch stream around every
+ * launch of the kernel classes below and accumulates, per class, the number of launches, their
+ * summed durations and the pair interactions they evaluate (target-source pairs times rhs).
+ * bie_profile_enable(1) clears the counters; bie_profile_read() waits for the recorded events
+ * of that class and returns the totals. Process-wide; not thread safe. */
+#define BIE_K_FAR_LAPLACE_F32 0 /* float32 far-field sweep, Laplace            */
+#define BIE_K_FAR_LAPLACE_F64 1 /* float64 far-field sweep, Laplace            */
+#define BIE_K_FAR_STOKES_F32 2  /* float32 far-field sweep, Stokes             */
+#define BIE_K_FAR_STOKES_F64 3  /* float64 far-field sweep, Stokes             */
+#define BIE_K_EPILOGUE 4        /* self blocks + diagonal + completion + sum   */
+#define BIE_K_FMM 5             /* FMM far field (all its kernels)             */
+#define BIE_K_COUNT 6
+int bie_profile_enable(int on);
+int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIE2D_H */

@@ -1,0 +1,303 @@
+"""Python binding of libbie2d (C ABI in include/bie2d.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; this module only checks tensor dtypes, devices and
+shapes, passes data pointers and the current torch stream, and converts status codes into
+exceptions. Device memory for inputs and outputs comes from torch (float64 CUDA/HIP tensors).
+If libbie2d.so has not been built, loading fails with an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbie2d.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bie2d.h")
+
+BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE = 0, -1, -2, -3, -4
+BIE_FP64, BIE_MIXED = 0, 1
+BIE_DIRECT, BIE_FMM = 0, 1
+
+
+class BieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bie2d error {code}: {msg}")
+        self.code = code
+
+
+class bie_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("method", ctypes.c_int), ("tol", ctypes.c_double),
+                ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
+                ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int)]
+
+
+class bie_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("pairs", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "bie_last_error": ([], ctypes.c_char_p),
+    "bie_default_opts": ([ctypes.POINTER(bie_opts)], _I),
+    "bie_geom_create": ([_I, _P, _P, _P, _P, ctypes.POINTER(_P)], _I),
+    "bie_geom_destroy": ([_P], _I),
+    "bie_geom_sizes": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
+    "bie_geom_export": ([_P, _P, _P, _P], _I),
+    "bie_geom_device_bytes": ([_P], ctypes.c_longlong),
+    "bie_laplace_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
+    "bie_stokes_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
+    "bie_elastance_rhs": ([_P, _I, _P, _P, _P, _P], _I),
+    "bie_mobility_rhs": ([_P, _I, _P, _P, _P, _P], _I),
+    "bie_laplace_potential": ([_P, _I, _P, _P, _P], _I),
+    "bie_stokes_rigid_motion": ([_P, _I, _P, _P, _P], _I),
+    "bie_elastance_solve": ([_P, _I, _P, _P, _P, ctypes.POINTER(bie_opts),
+                             ctypes.POINTER(bie_info), _P], _I),
+    "bie_mobility_solve": ([_P, _I, _P, _P, _P, ctypes.POINTER(bie_opts),
+                            ctypes.POINTER(bie_info), _P], _I),
+    "bie_elastance_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
+    "bie_mobility_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
+    "bie_profile_enable": ([_I], _I),
+    "bie_profile_read": ([_I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_longlong)], _I),
+}
+
+BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
+BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_COUNT = 4, 5, 6
+
+
+def bie_profile_enable(on=True):
+    _check(lib().bie_profile_enable(int(on)))
+
+
+def bie_profile_read(kclass):
+    """-> dict(launches, ms_total, pairs) for one kernel class."""
+    n, ms, pr = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_longlong()
+    _check(lib().bie_profile_read(kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(pr)))
+    return {"launches": n.value, "ms_total": ms.value, "pairs": pr.value}
+
+_lib = None
+
+
+def header_symbols(path=HEADER):
+    """Function names declared in include/bie2d.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bie_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load libbie2d.so (built by paper_1507_05925_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1507_05925_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code not in (BIE_OK,):
+        raise BieError(code, lib().bie_last_error().decode())
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, shape_last=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and t.shape[-1] != shape_last:
+        raise ValueError(f"{name}: last dimension {t.shape[-1]} != {shape_last}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw):
+    o = bie_opts()
+    _check(lib().bie_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Geometry:
+    """Owns a bie_geom (device-resident quadrature data and workspace)."""
+
+    def __init__(self, nodes_per_body, curve, interior=None):
+        self.nodes_per_body = np.ascontiguousarray(nodes_per_body, dtype=np.int32)
+        M = int(self.nodes_per_body.sum())
+        if tuple(curve.shape) != (6, M):
+            raise ValueError(f"curve must have shape (6, {M})")
+        h = ctypes.c_void_p()
+        ip = None if interior is None else _dptr(interior, 2, "interior")
+        _check(lib().bie_geom_create(len(self.nodes_per_body),
+                                     self.nodes_per_body.ctypes.data_as(ctypes.c_void_p),
+                                     _dptr(curve, M, "curve"), ip, _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.N, self.M = len(self.nodes_per_body), M
+        self.device = curve.device
+
+    @classmethod
+    def from_curves(cls, curves, device="cuda", interior=None):
+        torch = _torch()
+        c = np.stack([curves.x, curves.y, curves.dx, curves.dy, curves.ddx, curves.ddy])
+        t = torch.from_numpy(np.ascontiguousarray(c)).to(device)
+        it = None if interior is None else torch.as_tensor(np.asarray(interior, np.float64),
+                                                          device=device).reshape(-1, 2).contiguous()
+        return cls(curves.nodes_per_body, t, it)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bie_geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        n, m = _I(), _I()
+        _check(lib().bie_geom_sizes(self.handle, ctypes.byref(n), ctypes.byref(m)))
+        return n.value, m.value
+
+    def export(self):
+        torch = _torch()
+        out = torch.empty(8, self.M, dtype=torch.float64, device=self.device)
+        ob = torch.empty(4, self.N, dtype=torch.float64, device=self.device)
+        _check(lib().bie_geom_export(self.handle, _dptr(out, self.M), _dptr(ob, self.N), _stream()))
+        keys = ["x", "y", "nx", "ny", "w", "kappa", "px", "py"]
+        d = {k: out[i] for i, k in enumerate(keys)}
+        d.update({"length": ob[0], "xc": ob[1], "yc": ob[2], "W": ob[3]})
+        return d
+
+    def device_bytes(self):
+        return int(lib().bie_geom_device_bytes(self.handle))
+
+
+def _rows(t, width):
+    return 1 if t.dim() == 1 else int(np.prod(t.shape[:-1]))
+
+
+def bie_laplace_apply(g, mu, precision=BIE_FP64, method=BIE_DIRECT, with_L=True, out=None):
+    torch = _torch()
+    out = torch.empty_like(mu) if out is None else out
+    _check(lib().bie_laplace_apply(g.handle, precision, method, int(with_L), _rows(mu, g.M),
+                                   _dptr(mu, g.M, "mu"), _dptr(out, g.M, "out"), _stream()))
+    return out
+
+
+def bie_stokes_apply(g, mu, precision=BIE_FP64, method=BIE_DIRECT, with_L=True, out=None):
+    torch = _torch()
+    out = torch.empty_like(mu) if out is None else out
+    _check(lib().bie_stokes_apply(g.handle, precision, method, int(with_L), _rows(mu, 2 * g.M),
+                                  _dptr(mu, 2 * g.M, "mu"), _dptr(out, 2 * g.M, "out"), _stream()))
+    return out
+
+
+def bie_elastance_rhs(g, q):
+    torch = _torch()
+    R = _rows(q, g.N)
+    sigma = torch.empty(R, g.M, dtype=torch.float64, device=q.device)
+    f = torch.empty_like(sigma)
+    _check(lib().bie_elastance_rhs(g.handle, R, _dptr(q, g.N, "q"), _dptr(sigma), _dptr(f), _stream()))
+    return sigma.reshape(q.shape[:-1] + (g.M,)), f.reshape(q.shape[:-1] + (g.M,))
+
+
+def bie_mobility_rhs(g, FT):
+    torch = _torch()
+    R = _rows(FT, 3 * g.N)
+    rho = torch.empty(R, 2 * g.M, dtype=torch.float64, device=FT.device)
+    f = torch.empty_like(rho)
+    _check(lib().bie_mobility_rhs(g.handle, R, _dptr(FT, 3 * g.N, "FT"), _dptr(rho), _dptr(f), _stream()))
+    return rho.reshape(FT.shape[:-1] + (2 * g.M,)), f.reshape(FT.shape[:-1] + (2 * g.M,))
+
+
+def bie_laplace_potential(g, dens):
+    torch = _torch()
+    R = _rows(dens, g.M)
+    phi = torch.empty(R, g.N, dtype=torch.float64, device=dens.device)
+    _check(lib().bie_laplace_potential(g.handle, R, _dptr(dens, g.M, "dens"), _dptr(phi), _stream()))
+    return phi.reshape(dens.shape[:-1] + (g.N,))
+
+
+def bie_stokes_rigid_motion(g, dens):
+    torch = _torch()
+    R = _rows(dens, 2 * g.M)
+    VW = torch.empty(R, 3 * g.N, dtype=torch.float64, device=dens.device)
+    _check(lib().bie_stokes_rigid_motion(g.handle, R, _dptr(dens, 2 * g.M, "dens"), _dptr(VW), _stream()))
+    return VW.reshape(dens.shape[:-1] + (3 * g.N,))
+
+
+def _solve(fn, g, data, width_in, width_mu, opts, want_mu, allow_noconv):
+    torch = _torch()
+    R = _rows(data, width_in)
+    res = torch.empty(R, width_in, dtype=torch.float64, device=data.device)
+    mu = torch.empty(R, width_mu, dtype=torch.float64, device=data.device) if want_mu else None
+    info = bie_info()
+    o = opts if opts is not None else default_opts()
+    code = fn(g.handle, R, _dptr(data, width_in, "input"), _dptr(res),
+              _dptr(mu) if want_mu else None, ctypes.byref(o), ctypes.byref(info), _stream())
+    if not (code == BIE_OK or (allow_noconv and code == BIE_ENOCONV)):
+        _check(code)
+    shape = data.shape[:-1]
+    out = (res.reshape(shape + (width_in,)), info.as_dict())
+    if want_mu:
+        out = out + (mu.reshape(shape + (width_mu,)),)
+    return out
+
+
+def bie_elastance_solve(g, q, opts=None, want_mu=False, allow_noconv=False):
+    """q [.., N] -> (phi [.., N], info[, mu [.., M]])."""
+    return _solve(lib().bie_elastance_solve, g, q, g.N, g.M, opts, want_mu, allow_noconv)
+
+
+def bie_mobility_solve(g, FT, opts=None, want_mu=False, allow_noconv=False):
+    """FT [.., 3N] -> (VW [.., 3N], info[, mu [.., 2M]])."""
+    return _solve(lib().bie_mobility_solve, g, FT, 3 * g.N, 2 * g.M, opts, want_mu, allow_noconv)
+
+
+def _matrix(fn, g, n, max_rhs, opts):
+    torch = _torch()
+    out = torch.empty(n, n, dtype=torch.float64, device=g.device)  # rows = columns of the matrix
+    info = bie_info()
+    o = opts if opts is not None else default_opts()
+    _check(fn(g.handle, _dptr(out), int(max_rhs), ctypes.byref(o), ctypes.byref(info), _stream()))
+    return out.t().contiguous(), info.as_dict()  # column-major buffer -> matrix
+
+
+def bie_elastance_matrix(g, max_rhs=0, opts=None):
+    return _matrix(lib().bie_elastance_matrix, g, g.N, max_rhs, opts)
+
+
+def bie_mobility_matrix(g, max_rhs=0, opts=None):
+    return _matrix(lib().bie_mobility_matrix, g, 3 * g.N, max_rhs, opts)

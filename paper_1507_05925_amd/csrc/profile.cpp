@@ -1,0 +1,106 @@
+// Optional launch timing per kernel class (bie_profile_enable / bie_profile_read): a pair of HIP
+// events around each launch on its own stream, read back only when asked.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace bie {
+namespace {
+
+struct Rec {
+  hipEvent_t a, b;
+  long long pairs;
+};
+
+struct ClassStats {
+  std::vector<Rec> pending;
+  long long launches = 0, pairs = 0;
+  double ms = 0.0;
+};
+
+bool g_on = false;
+ClassStats g_stats[BIE_K_COUNT];
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t get_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int drain(ClassStats &c) {
+  for (Rec &r : c.pending) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return BIE_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return BIE_EDEVICE;
+    c.ms += ms;
+    c.launches += 1;
+    c.pairs += r.pairs;
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  c.pending.clear();
+  return BIE_OK;
+}
+
+}  // namespace
+
+ProfScope::ProfScope(int k, hipStream_t st, long long p) : kclass(k), s(st), pairs(p), on(g_on) {
+  if (!on) return;
+  hipEvent_t a = get_event();
+  if (!a) {
+    on = false;
+    return;
+  }
+  hipEventRecord(a, s);
+  g_stats[kclass].pending.push_back({a, nullptr, pairs});
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  hipEvent_t b = get_event();
+  Rec &r = g_stats[kclass].pending.back();
+  if (!b) {
+    g_pool.push_back(r.a);
+    g_stats[kclass].pending.pop_back();
+    return;
+  }
+  hipEventRecord(b, s);
+  r.b = b;
+}
+
+}  // namespace bie
+
+using namespace bie;
+
+extern "C" {
+
+int bie_profile_enable(int on) {
+  for (auto &c : g_stats) {
+    if (drain(c) != BIE_OK) return BIE_EDEVICE;
+    c = ClassStats();
+  }
+  g_on = on != 0;
+  return BIE_OK;
+}
+
+int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs) {
+  if (kclass < 0 || kclass >= BIE_K_COUNT) {
+    set_error("bie_profile_read: unknown kernel class");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(drain(g_stats[kclass]));
+  if (launches) *launches = g_stats[kclass].launches;
+  if (ms_total) *ms_total = g_stats[kclass].ms;
+  if (pairs) *pairs = g_stats[kclass].pairs;
+  return BIE_OK;
+}
+
+}  // extern "C"

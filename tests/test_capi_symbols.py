@@ -1,0 +1,31 @@
+"""The C-ABI library loads on a host without a GPU and exports every function that
+include/bie2d.h declares; the binding declares a signature for each of them. No compute calls."""
+import ctypes
+
+from paper_1507_05925_amd import bie2d
+
+
+def test_library_exports_header_symbols():
+    L = bie2d.lib()
+    names = bie2d.header_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(bie2d._SIGS), set(names) ^ set(bie2d._SIGS)
+
+
+def test_default_opts_and_errors_without_gpu():
+    o = bie2d.default_opts()
+    assert o.precision == bie2d.BIE_FP64 and o.method == bie2d.BIE_DIRECT
+    assert 0 < o.tol < 1e-6 and o.restart > 0
+    L = bie2d.lib()
+    assert L.bie_default_opts(None) == bie2d.BIE_EINVAL
+    assert b"NULL" in L.bie_last_error()
+    # host-side validation happens before any device call
+    h = ctypes.c_void_p()
+    assert L.bie_geom_create(0, None, None, None, None, ctypes.byref(h)) == bie2d.BIE_EINVAL
+    import numpy as np
+    npb = np.array([2], dtype=np.int32)
+    rc = L.bie_geom_create(1, npb.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(8), None, None,
+                           ctypes.byref(h))
+    assert rc == bie2d.BIE_EINVAL and b"fewer than 3" in L.bie_last_error()

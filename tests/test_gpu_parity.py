@@ -1,0 +1,297 @@
+"""GPU parity: every step of the HIP path against the float64 CPU oracle, through the C ABI.
+
+Error metric (per output kind): max |y - y_oracle| / max |y_oracle|.
+Tolerances: float64 path 1e-10 on solves (1e-13 on single applies); mixed path (float32 far
+field, float64 refinement) 1e-9 on refined solves. A single float32-far-field apply is checked
+against a bound derived from float32 rounding: each far-field body sum carries a relative error of
+a few float32 ulps (6e-8) times the number of nodes summed, so 2e-6 of the far-field magnitude.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import matfree as mf  # noqa: E402
+from oracle import nystrom as ny  # noqa: E402
+from paper_1507_05925_amd import bie2d  # noqa: E402
+from paper_1507_05925_amd import workloads as wl  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs the GPU")]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    a = np.asarray(a.detach().cpu() if hasattr(a, "detach") else a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def ragged(seed=5):
+    """Uneven bodies: node counts that are not multiples of the 64-lane wave or the 256-thread
+    workgroup, including the 3-node minimum and one body spanning several workgroups."""
+    rng = np.random.default_rng(seed)
+    return wl.mixed_grid(rng, 6, np.array([3, 67, 300, 513, 64, 129]))
+
+
+def small_cases():
+    return {"ellipses4": wl.elastance_small()[0], "ragged": ragged(),
+            "splash": wl.splash(256), "discs": wl.two_discs(0.5, 96)}
+
+
+def opts_for(precision):
+    """Tight tolerances; the splash mobility system needs ~100-200 GMRES steps (it is the
+    paper's ill-conditioned case), so the restart is long."""
+    return bie2d.default_opts(precision=precision, restart=200, max_iter=4000,
+                              tol=1e-13 if precision == bie2d.BIE_FP64 else 1e-12)
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = {}
+    for k, c in small_cases().items():
+        out[k] = (c, ny.geometry_of(c), bie2d.Geometry.from_curves(c))
+    return out
+
+
+def test_symbols_and_geometry(cases):
+    for name, (c, geo, g) in cases.items():
+        d = g.export()
+        for k in ["x", "y", "nx", "ny", "w", "kappa", "px", "py"]:
+            assert rel(d[k], geo[k]) < 1e-13, (name, k)
+        assert rel(d["length"], geo["length"]) < 1e-14
+        scale = np.abs(geo["xc"]).max()
+        assert np.abs(d["xc"].cpu().numpy() - geo["xc"][:, 0]).max() < 1e-13 * scale
+        assert np.abs(d["yc"].cpu().numpy() - geo["xc"][:, 1]).max() < 1e-13 * scale
+        assert rel(d["W"], geo["W"]) < 1e-13
+
+
+@pytest.mark.parametrize("with_L", [True, False])
+def test_laplace_apply_fp64(cases, with_L):
+    rng = np.random.default_rng(1)
+    for name, (c, geo, g) in cases.items():
+        A = 0.5 * np.eye(geo["M"]) + ny.laplace_K(geo) + (ny.laplace_L(geo) if with_L else 0)
+        for R in (1, 3, 11):  # chunks of 8, 2, 1 rhs inside the library
+            mu = rng.standard_normal((R, geo["M"]))
+            out = bie2d.bie_laplace_apply(g, dev(mu), bie2d.BIE_FP64, with_L=with_L)
+            assert rel(out, mu @ A.T) < 1e-13, (name, R)
+
+
+@pytest.mark.parametrize("with_L", [True, False])
+def test_stokes_apply_fp64(cases, with_L):
+    rng = np.random.default_rng(2)
+    for name, (c, geo, g) in cases.items():
+        A = 0.5 * np.eye(2 * geo["M"]) + ny.stokes_K(geo) + (ny.stokes_L(geo) if with_L else 0)
+        for R in (1, 2, 7):
+            mu = rng.standard_normal((R, 2 * geo["M"]))
+            out = bie2d.bie_stokes_apply(g, dev(mu), bie2d.BIE_FP64, with_L=with_L)
+            assert rel(out, mu @ A.T) < 1e-13, (name, R)
+
+
+def test_apply_mixed_far_field(cases):
+    """float32 far field: error relative to the far-field (other-body) part of the apply."""
+    rng = np.random.default_rng(3)
+    for name, (c, geo, g) in cases.items():
+        same = geo["body"][:, None] == geo["body"][None, :]
+        K = ny.laplace_K(geo)
+        far = np.where(same, 0.0, K)
+        A = 0.5 * np.eye(geo["M"]) + K + ny.laplace_L(geo)
+        mu = rng.standard_normal((2, geo["M"]))
+        out = bie2d.bie_laplace_apply(g, dev(mu), bie2d.BIE_MIXED).cpu().numpy()
+        ref = mu @ A.T
+        scale = max(np.abs(mu @ far.T).max(), 1e-300)
+        assert np.abs(out - ref).max() / scale < 2e-6, name
+        Ks = ny.stokes_K(geo)
+        same2 = np.repeat(np.repeat(same, 2, 0), 2, 1)
+        far2 = np.where(same2, 0.0, Ks)
+        A2 = 0.5 * np.eye(2 * geo["M"]) + Ks + ny.stokes_L(geo)
+        mu2 = rng.standard_normal((2, 2 * geo["M"]))
+        out2 = bie2d.bie_stokes_apply(g, dev(mu2), bie2d.BIE_MIXED).cpu().numpy()
+        scale2 = max(np.abs(mu2 @ far2.T).max(), 1e-300)
+        assert np.abs(out2 - mu2 @ A2.T).max() / scale2 < 2e-6, name
+
+
+def test_rhs_and_read_off(cases):
+    rng = np.random.default_rng(4)
+    for name, (c, geo, g) in cases.items():
+        q = rng.standard_normal((2, geo["N"]))
+        sigma, f = bie2d.bie_elastance_rhs(g, dev(q))
+        s_ref = ny.incident_charge(geo, q)
+        assert rel(sigma, s_ref) < 1e-14
+        assert rel(f, ny.laplace_rhs(geo, s_ref)) < 1e-13
+        FT = rng.standard_normal((2, 3 * geo["N"]))
+        rho, f2 = bie2d.bie_mobility_rhs(g, dev(FT))
+        r_ref = ny.incident_traction(geo, FT)
+        assert rel(rho, r_ref) < 1e-13
+        assert rel(f2, ny.stokes_rhs(geo, r_ref)) < 1e-13
+        dens = rng.standard_normal(geo["M"])
+        phi = bie2d.bie_laplace_potential(g, dev(dens))
+        assert rel(phi, ny.single_layer(geo, dens, geo["xc"])) < 1e-12
+        dens2 = rng.standard_normal(2 * geo["M"])
+        VW = bie2d.bie_stokes_rigid_motion(g, dev(dens2))
+        assert rel(VW, ny.rigid_motion(geo, dens2)) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_elastance_solve_small(cases, precision, tol):
+    rng = np.random.default_rng(6)
+    for name, (c, geo, g) in cases.items():
+        q = rng.standard_normal((3, geo["N"]))
+        ref = ny.elastance_solve(geo, q)
+        phi, info, mu = bie2d.bie_elastance_solve(g, dev(q), opts_for(precision), want_mu=True)
+        assert rel(phi, ref["phi"]) < tol, (name, info)
+        assert rel(mu, ref["mu"]) < 100 * tol, name
+        # completion constraint int mu = 0 per body (equivalence lemma); it holds to the
+        # discretisation accuracy of the discrete Gauss law, so compare with the oracle's mu
+        ch = np.stack([ny.body_charge(geo, m) for m in mu.cpu().numpy()])
+        ch_ref = np.stack([ny.body_charge(geo, m) for m in ref["mu"]])
+        assert np.abs(ch - ch_ref).max() < 1e-10 * np.abs(q).max()
+        if precision == bie2d.BIE_MIXED:
+            assert info["applies_fp32"] > 0 and info["refinements"] >= 1
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_mobility_solve_small(cases, precision, tol):
+    rng = np.random.default_rng(7)
+    for name, (c, geo, g) in cases.items():
+        FT = rng.standard_normal((2, 3 * geo["N"]))
+        ref = ny.mobility_solve(geo, FT)
+        VW, info = bie2d.bie_mobility_solve(g, dev(FT), opts_for(precision))
+        assert rel(VW, ref["VW"]) < tol, (name, info)
+
+
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_matrices(cases, precision):
+    for name in ("ellipses4", "ragged"):
+        c, geo, g = cases[name]
+        o = opts_for(precision)
+        P, _ = bie2d.bie_elastance_matrix(g, max_rhs=3, opts=o)
+        Pref = ny.elastance_matrix(geo)
+        assert float((P.cpu().numpy() - Pref).__abs__().max() / np.abs(Pref).max()) < 1e-9
+        Mm, _ = bie2d.bie_mobility_matrix(g, max_rhs=5, opts=o)
+        Mref = ny.mobility_matrix(geo)
+        assert float(np.abs(Mm.cpu().numpy() - Mref).max() / np.abs(Mref).max()) < 1e-9
+
+
+def test_single_disc_closed_form():
+    """Single disc: mu = 0 exactly, phi = -(q/2pi) log R, omega = T/(4 pi R^2)."""
+    R = 0.7
+    g = bie2d.Geometry.from_curves(wl.single_disc(3, R, 0.3, -0.2))
+    phi, info, mu = bie2d.bie_elastance_solve(g, dev([[1.7]]), want_mu=True)
+    assert abs(phi.item() - (-(1.7 / (2 * np.pi)) * np.log(R))) < 1e-14
+    assert mu.abs().max().item() < 1e-14
+    VW, _ = bie2d.bie_mobility_solve(g, dev([[0.0, 0.0, 1.1]]))
+    assert abs(VW[0, 2].item() - 1.1 / (4 * np.pi * R * R)) < 1e-14
+
+
+def test_two_disc_table():
+    tab = json.load(open(os.path.join(GOLDEN, "two_disc_tables.json")))["elastance"]
+    row = tab["rows"][0]
+    g = bie2d.Geometry.from_curves(wl.two_discs(row["d"], 256))
+    q = -2 * np.pi * row["q1"]
+    phi, _ = bie2d.bie_elastance_solve(g, dev([[q, -q]]), bie2d.default_opts(precision=bie2d.BIE_MIXED))
+    phi = phi.cpu().numpy()[0]
+    assert abs((phi[0] - phi[1]) - (tab["phi1"] - tab["phi2"])) / 0.332 < 3e-6
+
+
+def test_errors_forced_from_host():
+    c = wl.single_disc(16, 1.0)
+    cw = wl.Curves(c.nodes_per_body, c.x[::-1].copy(), c.y[::-1].copy(), -c.dx[::-1].copy(),
+                   -c.dy[::-1].copy(), c.ddx[::-1].copy(), c.ddy[::-1].copy(), c.centers, c.radii)
+    with pytest.raises(bie2d.BieError) as e:
+        bie2d.Geometry.from_curves(cw)
+    assert e.value.code == bie2d.BIE_EINVAL and "oriented" in str(e.value)
+    bad = wl.single_disc(16, 1.0)
+    bad.x[3] = np.nan
+    with pytest.raises(bie2d.BieError) as e:
+        bie2d.Geometry.from_curves(bad)
+    assert e.value.code == bie2d.BIE_EINVAL
+    g = bie2d.Geometry.from_curves(wl.elastance_small()[0])
+    o = bie2d.default_opts(max_iter=1, tol=1e-14)
+    with pytest.raises(bie2d.BieError) as e:
+        bie2d.bie_elastance_solve(g, dev([[1.0, -1.0, 0.5, 0.2]]), o)
+    assert e.value.code == bie2d.BIE_ENOCONV
+    phi, info = bie2d.bie_elastance_solve(g, dev([[1.0, -1.0, 0.5, 0.2]]), o, allow_noconv=True)
+    assert info["iters"] == 1 and info["rel_residual"] > 1e-14
+
+
+def test_deterministic(cases):
+    c, geo, g = cases["ragged"]
+    rng = np.random.default_rng(8)
+    mu = dev(rng.standard_normal((2, geo["M"])))
+    for p in (bie2d.BIE_FP64, bie2d.BIE_MIXED):
+        a = bie2d.bie_laplace_apply(g, mu, p)
+        b = bie2d.bie_laplace_apply(g, mu, p)
+        assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------------------------------
+# Full-size workloads (the benchmark configurations), sampled against the oracle
+# ------------------------------------------------------------------------------------------
+
+def _sample_rows(M, count=96, seed=0):
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([[0, M - 1], rng.choice(M, count, replace=False)]))
+    return rows.astype(np.int32)
+
+
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_full_size_apply_sampled(precision):
+    g_, q = wl.elastance_starfish()
+    geo = ny.geometry_of(g_)
+    g = bie2d.Geometry.from_curves(g_)
+    rng = np.random.default_rng(10)
+    mu = rng.standard_normal(geo["M"])
+    out = bie2d.bie_laplace_apply(g, dev(mu), precision).cpu().numpy()
+    rows = _sample_rows(geo["M"])
+    ref = mf.laplace_apply(geo, mu, rows=rows)
+    tol = 1e-12 if precision == bie2d.BIE_FP64 else 2e-6
+    assert np.abs(out[rows] - ref).max() / np.abs(ref).max() < tol
+
+
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_full_size_stokes_apply_sampled(precision):
+    g_, FT = wl.mobility_ellipses()
+    geo = ny.geometry_of(g_)
+    g = bie2d.Geometry.from_curves(g_)
+    rng = np.random.default_rng(11)
+    mu = rng.standard_normal(2 * geo["M"])
+    out = bie2d.bie_stokes_apply(g, dev(mu), precision).cpu().numpy().reshape(-1, 2)
+    rows = _sample_rows(geo["M"], seed=1)
+    ref = mf.stokes_apply(geo, mu, rows=rows).reshape(-1, 2)
+    tol = 1e-12 if precision == bie2d.BIE_FP64 else 2e-6
+    assert np.abs(out[rows] - ref).max() / np.abs(ref).max() < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_full_size_elastance_solve(precision, tol):
+    path = os.path.join(GOLDEN, "starfish_1000x256_phi.json")
+    gold = json.load(open(path))
+    g_, q = wl.elastance_starfish()
+    g = bie2d.Geometry.from_curves(g_)
+    o = bie2d.default_opts(precision=precision, tol=1e-12, restart=60)
+    phi, info = bie2d.bie_elastance_solve(g, dev(q[None]), o)
+    assert rel(phi[0], gold["phi"]) < tol, info
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_full_size_mobility_solve(precision, tol):
+    path = os.path.join(GOLDEN, "ellipses_200x512_vw.json")
+    gold = json.load(open(path))
+    g_, FT = wl.mobility_ellipses()
+    g = bie2d.Geometry.from_curves(g_)
+    o = bie2d.default_opts(precision=precision, tol=1e-12, restart=80)
+    VW, info = bie2d.bie_mobility_solve(g, dev(FT[None]), o)
+    VW = VW.cpu().numpy()[0].reshape(-1, 3)
+    ref = np.asarray(gold["VW"]).reshape(-1, 3)
+    assert rel(VW[:, :2], ref[:, :2]) < tol, info
+    assert rel(VW[:, 2], ref[:, 2]) < tol, info
