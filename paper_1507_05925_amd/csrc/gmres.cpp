@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -23,6 +25,15 @@ namespace {
 struct Op {
   int kind, precision, method;
 };
+
+// BIE_VERBOSE=1: one line per GMRES cycle and refinement step; =2: also every Arnoldi step.
+int verbosity() {
+  static int v = [] {
+    const char *e = std::getenv("BIE_VERBOSE");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
 
 struct Stats {
   int iters = 0, applies64 = 0, applies32 = 0;
@@ -104,6 +115,7 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
   const long long vs_r = n;                    // stride between rhs inside one Krylov vector
   const long long hs = m + 2;
   std::vector<double> fnorm, beta, hh1, hh2, hn;
+  if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * nrhs * n, s));
   BIE_TRY(vec_nrm2(nrhs, n, f, n, wk.nrm, wk.scratch, s));
   BIE_TRY(read_host(g, wk.nrm, nrhs, fnorm, s));
   relres.assign(nrhs, 0.0);
@@ -130,6 +142,9 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
       active[r] = !conv[r];
       nact += active[r];
     }
+    if (verbosity() >= 1)
+      std::fprintf(stderr, "[bie] gmres prec=%d cycle start: iters=%d true rel res[0]=%.3e\n",
+                   op.precision, st.iters, relres[0]);
     if (nact == 0 || st.iters >= max_iter) break;
     // V_0 = r / beta (inactive rhs: zero vector)
     for (int r = 0; r < nrhs; ++r)
@@ -176,6 +191,8 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
         gg[j + 1] = -sv[j] * gg[j];
         gg[j] = c[j] * gg[j];
         const double res = std::fabs(gg[j + 1]) / fnorm[r];
+        if (verbosity() >= 2 && r == 0)
+          std::fprintf(stderr, "[bie]   j=%d est rel res=%.3e hn=%.3e\n", j, res, hn[r]);
         if (res <= tol || hn[r] == 0.0) jdone[r] = j;
         else all_done = false;
       }
@@ -258,16 +275,24 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
         conv[r] = relres[r] <= o.tol;
         all = all && conv[r];
       }
+      if (verbosity() >= 1)
+        std::fprintf(stderr, "[bie] refinement %d: true rel res[0]=%.3e iters=%d\n", it,
+                     relres[0], st.iters);
       if (all || it >= o.max_refine || st.iters >= o.max_iter) break;
       // converged rhs get a zero residual so the inner solve leaves them untouched
-      std::vector<double> zero_mask(nrhs, 1.0);
-      for (int r = 0; r < nrhs; ++r)
+      double worst = 0.0;
+      for (int r = 0; r < nrhs; ++r) {
         if (conv[r])
           BIE_HIP_CHECK(hipMemsetAsync(rr + (size_t)r * n, 0, sizeof(double) * n, s));
+        else
+          worst = std::max(worst, relres[r]);
+      }
+      // the inner solve only has to bring the residual to what the outer tolerance needs
+      // (with a margin of 3), never tighter than inner_tol
+      const double itol = std::max(o.inner_tol, o.tol / (3.0 * worst));
       std::vector<double> irel;
       std::vector<int> iconv;
-      BIE_TRY(gmres(g, op32, nrhs, n, rr, d, true, o.inner_tol, m, o.max_iter, wk, st, irel,
-                    iconv, s));
+      BIE_TRY(gmres(g, op32, nrhs, n, rr, d, true, itol, m, o.max_iter, wk, st, irel, iconv, s));
       BIE_TRY(vec_axpby(nrhs, n, 1.0, d, 1.0, x, s));
       BIE_TRY(apply(g, op64, nrhs, x, rr, st, s));
       BIE_TRY(vec_axpby(nrhs, n, 1.0, f, -1.0, rr, s));

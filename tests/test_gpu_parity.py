@@ -295,3 +295,16 @@ def test_full_size_mobility_solve(precision, tol):
     ref = np.asarray(gold["VW"]).reshape(-1, 3)
     assert rel(VW[:, :2], ref[:, :2]) < tol, info
     assert rel(VW[:, 2], ref[:, 2]) < tol, info
+
+
+def test_mixed_refinement_iteration_budget():
+    """Iterative refinement must not cost much more than the float64 solve: each inner solve
+    starts from a zero correction and only reduces the residual as far as the outer tolerance
+    needs (regression: a stale correction once multiplied the iteration count by 4)."""
+    g_, q = wl.elastance_starfish(nbodies=200)
+    g = bie2d.Geometry.from_curves(g_)
+    qd = dev(q[None])
+    _, i64 = bie2d.bie_elastance_solve(g, qd, bie2d.default_opts(precision=bie2d.BIE_FP64, tol=1e-10))
+    _, imx = bie2d.bie_elastance_solve(g, qd, bie2d.default_opts(precision=bie2d.BIE_MIXED, tol=1e-10))
+    assert imx["applies_fp32"] <= 2 * i64["iters"] + 6, (i64, imx)
+    assert imx["refinements"] <= 3, imx
