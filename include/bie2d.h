@@ -82,7 +82,9 @@ typedef struct {
 const char *bie_last_error(void);
 
 /* Fills *o with the defaults: BIE_FP64, BIE_DIRECT, tol 1e-12, restart 100, max_iter 500,
- * inner_tol 1e-6, max_refine 10, fmm_order 30, fmm_leaf 64. */
+ * inner_tol 1e-6, max_refine 10, fmm_order 40, fmm_leaf 64. With BIE_FMM and BIE_MIXED the inner
+ * applies use order ceil(0.55 fmm_order) (about the square root of the accuracy); all FMM
+ * arithmetic is float64. fmm_order must lie in [4, 64]. */
 int bie_default_opts(bie_opts *o);
 
 /* ---- a1: geometry and quadrature (elastance section; eq. rho for W; centroid of the mobility
@@ -106,12 +108,17 @@ int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M);
 int bie_geom_export(const bie_geom *g, double *out, double *out_body, void *stream);
 /* Device bytes held by the geometry including its current workspace. */
 long long bie_geom_device_bytes(const bie_geom *g);
+/* Expansion order p (4..64) and maximum leaf population used by BIE_FMM applies on g (the solve
+ * entry points set them from bie_opts). The quadtree for each order is built on first use and
+ * kept with the geometry. */
+int bie_geom_set_fmm(bie_geom *g, int order, int leaf);
 
 /* ---- a3 + a4: the operator apply (eqs. ModRep2 / ModRep2Stokes) ----------------------------
  * out = (1/2 I + K + L) mu      (with_L = 1)  or  (1/2 I + K) mu  (with_L = 0)
  * Laplace: mu, out (device) [nrhs][M].  Stokes: (device) [nrhs][2M] node-major.
  * precision: BIE_FP64, or BIE_MIXED (float32 far field, float64 self blocks and terms).
- * method: BIE_DIRECT or BIE_FMM. mu and out must not alias. */
+ * method: BIE_DIRECT or BIE_FMM (expansion order and leaf size of the last solve on this geometry,
+ * default 40 and 64). mu and out must not alias. */
 int bie_laplace_apply(bie_geom *g, int precision, int method, int with_L, int nrhs,
                       const double *mu, double *out, void *stream);
 int bie_stokes_apply(bie_geom *g, int precision, int method, int with_L, int nrhs,

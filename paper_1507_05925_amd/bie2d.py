@@ -55,6 +55,7 @@ _SIGS = {
     "bie_geom_sizes": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "bie_geom_export": ([_P, _P, _P, _P], _I),
     "bie_geom_device_bytes": ([_P], ctypes.c_longlong),
+    "bie_geom_set_fmm": ([_P, _I, _I], _I),
     "bie_laplace_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
     "bie_stokes_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
     "bie_elastance_rhs": ([_P, _I, _P, _P, _P, _P], _I),
@@ -202,6 +203,9 @@ class Geometry:
 
     def device_bytes(self):
         return int(lib().bie_geom_device_bytes(self.handle))
+
+    def set_fmm(self, order, leaf=64):
+        _check(lib().bie_geom_set_fmm(self.handle, int(order), int(leaf)))
 
 
 def _rows(t, width):

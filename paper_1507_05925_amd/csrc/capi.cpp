@@ -80,14 +80,15 @@ static void fill_defaults(bie_opts *o) {
   o->max_iter = 500;
   o->inner_tol = 1e-6;
   o->max_refine = 10;
-  o->fmm_order = 30;
+  o->fmm_order = 40;
   o->fmm_leaf = 64;
 }
 
 static int check_opts(const bie_opts &o) {
   if ((o.precision != BIE_FP64 && o.precision != BIE_MIXED) ||
       (o.method != BIE_DIRECT && o.method != BIE_FMM) || !(o.tol > 0.0) || o.restart < 1 ||
-      o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0) {
+      o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
+      o.fmm_order > 64 || o.fmm_leaf < 1) {
     set_error("invalid bie_opts");
     return BIE_EINVAL;
   }
@@ -247,6 +248,17 @@ long long bie_geom_device_bytes(const bie_geom *g) {
                      g->ws_out.bytes);
 }
 
+int bie_geom_set_fmm(bie_geom *g, int order, int leaf) {
+  BIE_TRY(check_geom(g));
+  if (order < 4 || order > 64 || leaf < 1) {
+    set_error("bie_geom_set_fmm: order must lie in [4, 64] and leaf >= 1");
+    return BIE_EINVAL;
+  }
+  g->fmm_order = order;
+  g->fmm_leaf = leaf;
+  return BIE_OK;
+}
+
 int bie_geom_export(const bie_geom *g, double *out, double *out_body, void *stream) {
   BIE_TRY(check_geom(g));
   hipStream_t s = as_stream(stream);
@@ -345,6 +357,8 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   BIE_TRY(check_opts(o));
   hipStream_t s = as_stream(stream);
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
+  g->fmm_order = o.fmm_order;
+  g->fmm_leaf = o.fmm_leaf;
   // ws_out: dens [nrhs][len], f [nrhs][len], mu [nrhs][len]
   BIE_TRY(g->ws_out.reserve(3 * len * nrhs * 8));
   double *dens = g->ws_out.as<double>();

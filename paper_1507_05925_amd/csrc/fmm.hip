@@ -1,19 +1,601 @@
-// 2D fast multipole far field (placeholder until the tree code lands).
+// 2D fast multipole method for the far field of the operator apply (the paper accelerates the
+// layer potentials with an FMM and names it only; this design is the library's own).
+//
+// Both kernels reduce to Cauchy sums F(z) = sum_k Q_k / (z - zeta_k) over complex charges:
+//   Laplace:  n_x . sum_k s_k (x - y_k) / |x - y_k|^2 = Re(nu F(z)), nu = n1 + i n2, Q_k = s_k real.
+//   Stokes:   sum_k (r.n)(r.s_k) r / |r|^4 (as a complex number) =
+//             (1/4) [conj(nu) conj(C'(z) - conj(z) A'(z)) + conj(nu) conj(B(z)) + nu conj(A(z)) + nu A(z)]
+//             with A: Q = rho_k, B: Q = conj(rho_k), C: Q = rho_k conj(zeta_k), rho_k = s_k1 + i s_k2,
+//             all coordinates taken relative to the root-box centre (the shift cancels in C' - z A').
+// Tree: uniform quadtree over the bounding square, refined until no leaf holds more than `leaf`
+// nodes; only non-empty boxes are stored. Expansions are scaled by the box size h:
+//   multipole a_m = sum_k Q_k ((zeta_k - c)/h)^m,   F(z) = sum_m a_m h^m / (z - c)^{m+1}
+//   local     F(z) = sum_n b_n ((z - c)/h)^n
+// so the 40 M2L operators (offsets d with max(|dx|,|dy|) in {2,3}) and the 4 M2M / 4 L2L operators
+// are the same at every level (M2L carries one 1/h factor). Near field: the 3 x 3 neighbouring
+// leaves, summed directly in float64 for every pair k != i, including pairs on the same body, so
+// the epilogue adds only the diagonal limit, identity and completion. Deterministic: one wave per
+// box with one lane per coefficient; fixed list orders.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <unordered_map>
+#include <vector>
 
 #include "internal.h"
 
 namespace bie {
 
-struct FmmPlan {};
+constexpr int kMaxP = 64;
 
-int fmm_far_field(bie_geom *, int, int, int, const double *, double *, hipStream_t, int, int) {
-  set_error("BIE_FMM is not available in this build");
-  return BIE_EINVAL;
-}
+struct FmmTree {
+  int p = 0, L = 0, M = 0, nleaf = 0, nbox = 0;
+  double size = 0.0, ox = 0.0, oy = 0.0;
+  std::vector<int> level_off;  // [L+2]
+  // device
+  DevBuf buf;
+  int *perm = nullptr, *leaf_start = nullptr, *leaf_box = nullptr, *child = nullptr,
+      *parent = nullptr, *m2l_ptr = nullptr, *m2l_src = nullptr, *m2l_off = nullptr,
+      *near_ptr = nullptr, *near_leaf = nullptr, *box_level = nullptr;
+  double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
+  double2 *T_m2l = nullptr, *T_m2m = nullptr, *T_l2l = nullptr;  // transposed [.][m][n]
+  double *inv_h = nullptr;  // [L+1]
+  DevBuf work;              // charges + expansions
+};
+
+struct FmmPlan {
+  std::map<int, FmmTree *> trees;  // by order p
+  ~FmmPlan() {
+    for (auto &kv : trees) {
+      kv.second->buf.release();
+      kv.second->work.release();
+      delete kv.second;
+    }
+  }
+};
 
 void fmm_destroy(FmmPlan *p) { delete p; }
 
+namespace {
+
+using cd = std::complex<double>;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cfma(double2 a, double2 b, double2 c) {  // a*b + c
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ inline double2 cpow(double2 w, int n) {
+  double2 r = make_double2(1.0, 0.0);
+  while (n) {
+    if (n & 1) r = cmul(r, w);
+    w = cmul(w, w);
+    n >>= 1;
+  }
+  return r;
+}
+
+__device__ inline double rcp64(double a) {
+  const double y = __builtin_amdgcn_rcp(a);
+  const double e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+
+// Complex charges in sorted order. Laplace: one set per rhs; Stokes: A, B, C per rhs.
+__global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
+                         const double2 *__restrict__ xs, const double *__restrict__ s64,
+                         double2 *__restrict__ Q) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int k = perm[j];
+  for (int r = 0; r < R; ++r) {
+    if (kind == 0) {
+      Q[(size_t)r * M + j] = make_double2(s64[(size_t)r * M + k], 0.0);
+    } else {
+      const double2 rho = make_double2(s64[(size_t)r * 2 * M + 2 * k], s64[(size_t)r * 2 * M + 2 * k + 1]);
+      const double2 z = xs[j];
+      Q[(size_t)(3 * r) * M + j] = rho;
+      Q[(size_t)(3 * r + 1) * M + j] = make_double2(rho.x, -rho.y);
+      Q[(size_t)(3 * r + 2) * M + j] = cmul(rho, make_double2(z.x, -z.y));
+    }
+  }
+}
+
+// P2M at the leaves: grid (nleaf, nsets), one lane per coefficient.
+__global__ __launch_bounds__(64) void k_p2m(int p, int M, int nbox, double inv_h,
+                                           const int *__restrict__ leaf_start,
+                                           const int *__restrict__ leaf_box,
+                                           const double2 *__restrict__ center,
+                                           const double2 *__restrict__ xs,
+                                           const double2 *__restrict__ Q,
+                                           double2 *__restrict__ Mexp) {
+  const int leaf = blockIdx.x, set = blockIdx.y, n = threadIdx.x;
+  const int box = leaf_box[leaf];
+  const double2 c = center[box];
+  const double2 *q = Q + (size_t)set * M;
+  double2 a = make_double2(0.0, 0.0);
+  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
+  for (int j = j0; j < j1; ++j) {
+    const double2 z = xs[j];
+    const double2 w = make_double2((z.x - c.x) * inv_h, (z.y - c.y) * inv_h);
+    a = cfma(q[j], cpow(w, n), a);
+  }
+  if (n < p) Mexp[((size_t)set * nbox + box) * p + n] = a;
+}
+
+// M2M for one level: grid (boxes of the level, nsets).
+__global__ __launch_bounds__(64) void k_m2m(int p, int nbox, int off, const int *__restrict__ child,
+                                           const double2 *__restrict__ Tt,
+                                           double2 *__restrict__ Mexp) {
+  const int b = off + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int cpos = 0; cpos < 4; ++cpos) {
+    const int ch = child[4 * b + cpos];
+    if (ch < 0) continue;
+    const double2 *a = Mexp + ((size_t)set * nbox + ch) * p;
+    const double2 *T = Tt + (size_t)cpos * p * p;
+    for (int m = 0; m <= n && m < p; ++m) acc = cfma(T[(size_t)m * p + n], a[m], acc);
+  }
+  if (threadIdx.x < p) Mexp[((size_t)set * nbox + b) * p + n] = acc;
+}
+
+// M2L for all boxes of levels >= 2: grid (nbox - off2, nsets). Writes (initialises) Lexp.
+__global__ __launch_bounds__(64) void k_m2l(int p, int nbox, int off2, const int *__restrict__ ptr,
+                                           const int *__restrict__ src, const int *__restrict__ offs,
+                                           const int *__restrict__ box_level,
+                                           const double *__restrict__ inv_h,
+                                           const double2 *__restrict__ Tt,
+                                           const double2 *__restrict__ Mexp,
+                                           double2 *__restrict__ Lexp) {
+  const int t = off2 + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
+  double2 acc = make_double2(0.0, 0.0);
+  const int e0 = ptr[t - off2], e1 = ptr[t - off2 + 1];
+  for (int e = e0; e < e1; ++e) {
+    const double2 *a = Mexp + ((size_t)set * nbox + src[e]) * p;
+    const double2 *T = Tt + (size_t)offs[e] * p * p;
+    for (int m = 0; m < p; ++m) acc = cfma(T[(size_t)m * p + n], a[m], acc);
+  }
+  const double s = inv_h[box_level[t]];
+  if (threadIdx.x < p) Lexp[((size_t)set * nbox + t) * p + n] = make_double2(acc.x * s, acc.y * s);
+}
+
+// L2L from level l to l+1: grid (boxes of level l+1, nsets); accumulates into Lexp.
+__global__ __launch_bounds__(64) void k_l2l(int p, int nbox, int off, const int *__restrict__ parent,
+                                           const double2 *__restrict__ Tt,
+                                           double2 *__restrict__ Lexp) {
+  const int c = off + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
+  const int pc = parent[c];
+  const int cpos = pc & 3, pb = pc >> 2;
+  const double2 *b = Lexp + ((size_t)set * nbox + pb) * p;
+  const double2 *T = Tt + (size_t)cpos * p * p;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int m = 0; m < p; ++m)
+    if (m >= n) acc = cfma(T[(size_t)m * p + n], b[m], acc);
+  if (threadIdx.x < p) {
+    double2 *o = Lexp + ((size_t)set * nbox + c) * p + n;
+    *o = make_double2(o->x + acc.x, o->y + acc.y);
+  }
+}
+
+// Local expansion value F and derivative F' at w = (z - c)/h (Horner); F' includes 1/h.
+__device__ inline void eval_local(const double2 *b, int p, double2 w, double ih, double2 &F,
+                                  double2 &dF) {
+  F = b[p - 1];
+  dF = make_double2(0.0, 0.0);
+  for (int n = p - 1; n >= 1; --n) {
+    dF = cfma(dF, w, make_double2(F.x * 1.0, F.y * 1.0));
+    F = cfma(F, w, b[n - 1]);
+  }
+  dF = make_double2(dF.x * ih, dF.y * ih);
+}
+
+// L2P + near field, Laplace. grid (nleaf, R); writes -(1/2pi) n.(sum_{k != i} s_k r/|r|^2).
+__global__ __launch_bounds__(64) void k_eval_laplace(
+    int p, int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
+  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int box = leaf_box[leaf];
+  const double2 c = center[box];
+  const double2 *b = Lexp + ((size_t)r * nbox + box) * p;
+  const double2 *q = Q + (size_t)r * M;
+  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
+  for (int base = j0; base < j1; base += 64) {
+    const int j = base + threadIdx.x;
+    const bool valid = j < j1;
+    const int jj = valid ? j : j0;
+    const double2 z = xs[jj], nv = nrm[jj];
+    double2 F, dF;
+    eval_local(b, p, make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf), ih_leaf, F, dF);
+    double gx = 0.0, gy = 0.0;
+    for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
+      const int nl = near_leaf[e];
+      for (int k = leaf_start[nl]; k < leaf_start[nl + 1]; ++k) {
+        const double2 y = xs[k];
+        const double dx = z.x - y.x, dy = z.y - y.y;
+        const bool same = (k == jj);
+        const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
+        const double t = same ? 0.0 : q[k].x * inv;
+        gx = fma(dx, t, gx);
+        gy = fma(dy, t, gy);
+      }
+    }
+    const double far = nv.x * F.x - nv.y * F.y;  // Re(nu F)
+    const double v = -(far + nv.x * gx + nv.y * gy) / (2.0 * kPi);
+    if (valid) out[(size_t)r * M + perm[j]] = v;
+  }
+}
+
+// L2P + near field, Stokes. grid (nleaf, R); sets 3r, 3r+1, 3r+2 are A, B, C.
+__global__ __launch_bounds__(64) void k_eval_stokes(
+    int p, int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
+  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int box = leaf_box[leaf];
+  const double2 c = center[box];
+  const double2 *bA = Lexp + ((size_t)(3 * r) * nbox + box) * p;
+  const double2 *bB = Lexp + ((size_t)(3 * r + 1) * nbox + box) * p;
+  const double2 *bC = Lexp + ((size_t)(3 * r + 2) * nbox + box) * p;
+  const double2 *q = Q + (size_t)(3 * r) * M;  // rho in sorted order
+  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
+  for (int base = j0; base < j1; base += 64) {
+    const int j = base + threadIdx.x;
+    const bool valid = j < j1;
+    const int jj = valid ? j : j0;
+    const double2 z = xs[jj], nv = nrm[jj];
+    const double2 w = make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf);
+    double2 A, dA, B, dB, C, dC;
+    eval_local(bA, p, w, ih_leaf, A, dA);
+    eval_local(bB, p, w, ih_leaf, B, dB);
+    eval_local(bC, p, w, ih_leaf, C, dC);
+    // t1 = conj(nu) conj(C' - conj(z) A'); t2 = conj(nu) conj(B); t3 = nu conj(A) + nu A
+    const double2 zA = cmul(make_double2(z.x, -z.y), dA);
+    const double2 u = make_double2(dC.x - zA.x, -(dC.y - zA.y));  // conj(C' - conj(z) A')
+    const double2 nc = make_double2(nv.x, -nv.y);
+    const double2 t1 = cmul(nc, u);
+    const double2 t2 = cmul(nc, make_double2(B.x, -B.y));
+    const double2 t3 = cmul(nv, make_double2(2.0 * A.x, 0.0));  // conj(A) + A = 2 Re A
+    const double fx = 0.25 * (t1.x + t2.x + t3.x), fy = 0.25 * (t1.y + t2.y + t3.y);
+    double gx = 0.0, gy = 0.0;
+    for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
+      const int nl = near_leaf[e];
+      for (int k = leaf_start[nl]; k < leaf_start[nl + 1]; ++k) {
+        const double2 y = xs[k];
+        const double2 sv = q[k];
+        const double dx = z.x - y.x, dy = z.y - y.y;
+        const bool same = (k == jj);
+        const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
+        const double rn = fma(dx, nv.x, dy * nv.y);
+        const double cc = same ? 0.0 : fma(dx, sv.x, dy * sv.y) * rn * (inv * inv);
+        gx = fma(cc, dx, gx);
+        gy = fma(cc, dy, gy);
+      }
+    }
+    if (valid) {
+      const int i = perm[j];
+      out[(size_t)r * 2 * M + 2 * i] = -(fx + gx) / kPi;
+      out[(size_t)r * 2 * M + 2 * i + 1] = -(fy + gy) / kPi;
+    }
+  }
+}
+
+// ---- host: tree and translation operators ---------------------------------------------------
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
+  const int M = g->M;
+  std::vector<double> x(M), y(M), nx(M), ny(M);
+  BIE_HIP_CHECK(hipMemcpyAsync(x.data(), g->x, M * 8, hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(y.data(), g->y, M * 8, hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(nx.data(), g->nx, M * 8, hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(ny.data(), g->ny, M * 8, hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  double x0 = x[0], x1 = x[0], y0 = y[0], y1 = y[0];
+  for (int k = 0; k < M; ++k) {
+    x0 = std::min(x0, x[k]); x1 = std::max(x1, x[k]);
+    y0 = std::min(y0, y[k]); y1 = std::max(y1, y[k]);
+  }
+  t.p = p;
+  t.M = M;
+  t.size = std::max(x1 - x0, y1 - y0) * (1.0 + 1e-9) + 1e-300;
+  t.ox = 0.5 * (x0 + x1);
+  t.oy = 0.5 * (y0 + y1);
+  auto cell = [&](double v, double o, int n) {
+    long long i = (long long)std::floor((v - o + 0.5 * t.size) / t.size * n);
+    return (int)std::min<long long>(std::max<long long>(i, 0), n - 1);
+  };
+  // depth: refine until no leaf holds more than leaf_cap nodes (at most 14 levels)
+  int L = 2;
+  for (; L < 14; ++L) {
+    const int n = 1 << L;
+    std::unordered_map<long long, int> cnt;
+    cnt.reserve(M / 8 + 16);
+    int mx = 0;
+    for (int k = 0; k < M; ++k) {
+      long long key = (long long)cell(y[k], t.oy, n) * n + cell(x[k], t.ox, n);
+      mx = std::max(mx, ++cnt[key]);
+    }
+    if (mx <= leaf_cap) break;
+  }
+  t.L = L;
+  const int nL = 1 << L;
+  std::vector<long long> key(M);
+  std::vector<int> perm(M);
+  for (int k = 0; k < M; ++k) {
+    key[k] = (long long)cell(y[k], t.oy, nL) * nL + cell(x[k], t.ox, nL);
+    perm[k] = k;
+  }
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  // boxes per level: sorted unique keys
+  std::vector<std::vector<long long>> keys(L + 1);
+  std::vector<int> leaf_start;
+  for (int j = 0; j < M; ++j) {
+    const long long kk = key[perm[j]];
+    if (keys[L].empty() || keys[L].back() != kk) {
+      keys[L].push_back(kk);
+      leaf_start.push_back(j);
+    }
+  }
+  leaf_start.push_back(M);
+  for (int l = L - 1; l >= 0; --l) {
+    const int nch = 1 << (l + 1), n = 1 << l;
+    for (long long kk : keys[l + 1]) {
+      const long long iy = kk / nch, ix = kk % nch;
+      const long long pk = (iy >> 1) * n + (ix >> 1);
+      if (keys[l].empty() || keys[l].back() != pk) {
+        // children of one parent are not contiguous in row-major order: insert sorted later
+        keys[l].push_back(pk);
+      }
+    }
+    std::sort(keys[l].begin(), keys[l].end());
+    keys[l].erase(std::unique(keys[l].begin(), keys[l].end()), keys[l].end());
+  }
+  t.level_off.assign(L + 2, 0);
+  for (int l = 0; l <= L; ++l) t.level_off[l + 1] = t.level_off[l] + (int)keys[l].size();
+  t.nbox = t.level_off[L + 1];
+  t.nleaf = (int)keys[L].size();
+  auto find = [&](int l, long long kk) -> int {
+    auto it = std::lower_bound(keys[l].begin(), keys[l].end(), kk);
+    if (it == keys[l].end() || *it != kk) return -1;
+    return t.level_off[l] + (int)(it - keys[l].begin());
+  };
+  std::vector<double2> center(t.nbox);
+  std::vector<int> child(4 * t.nbox, -1), parent(t.nbox, -1), box_level(t.nbox);
+  for (int l = 0; l <= L; ++l) {
+    const int n = 1 << l;
+    const double h = t.size / n;
+    for (size_t b = 0; b < keys[l].size(); ++b) {
+      const long long kk = keys[l][b];
+      const long long iy = kk / n, ix = kk % n;
+      const int gb = t.level_off[l] + (int)b;
+      box_level[gb] = l;
+      center[gb] = make_double2(-0.5 * t.size + (ix + 0.5) * h, -0.5 * t.size + (iy + 0.5) * h);
+      if (l > 0) {
+        const int pb = find(l - 1, (iy >> 1) * (n >> 1) + (ix >> 1));
+        const int cpos = (int)((iy & 1) * 2 + (ix & 1));
+        child[4 * pb + cpos] = gb;
+        parent[gb] = pb * 4 + cpos;
+      }
+    }
+  }
+  // M2L lists (levels >= 2) and near lists (leaves)
+  std::vector<int> m2l_ptr(1, 0), m2l_src, m2l_off;
+  const int off2 = t.level_off[std::min(2, L)];
+  for (int l = 2; l <= L; ++l) {
+    const int n = 1 << l;
+    for (long long kk : keys[l]) {
+      const int iy = (int)(kk / n), ix = (int)(kk % n);
+      const int py = iy >> 1, px = ix >> 1, np = n >> 1;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int qy = py + dy, qx = px + dx;
+          if (qy < 0 || qx < 0 || qy >= np || qx >= np) continue;
+          for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+              const int sy = 2 * qy + cy, sx = 2 * qx + cx;
+              if (std::max(std::abs(sx - ix), std::abs(sy - iy)) < 2) continue;
+              const int sb = find(l, (long long)sy * n + sx);
+              if (sb < 0) continue;
+              m2l_src.push_back(sb);
+              m2l_off.push_back((ix - sx + 3) * 7 + (iy - sy + 3));
+            }
+        }
+      m2l_ptr.push_back((int)m2l_src.size());
+    }
+  }
+  std::vector<int> near_ptr(1, 0), near_leaf, leaf_box(t.nleaf);
+  for (int b = 0; b < t.nleaf; ++b) {
+    const long long kk = keys[L][b];
+    const int iy = (int)(kk / nL), ix = (int)(kk % nL);
+    leaf_box[b] = t.level_off[L] + b;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int qy = iy + dy, qx = ix + dx;
+        if (qy < 0 || qx < 0 || qy >= nL || qx >= nL) continue;
+        const int nb = find(L, (long long)qy * nL + qx);
+        if (nb >= 0) near_leaf.push_back(nb - t.level_off[L]);
+      }
+    near_ptr.push_back((int)near_leaf.size());
+  }
+  // translation operators, transposed to [m][n]
+  std::vector<double2> Tm2l((size_t)49 * p * p, make_double2(0, 0)), Tm2m((size_t)4 * p * p),
+      Tl2l((size_t)4 * p * p);
+  for (int dx = -3; dx <= 3; ++dx)
+    for (int dy = -3; dy <= 3; ++dy) {
+      if (std::max(std::abs(dx), std::abs(dy)) < 2) continue;
+      const cd d(dx, dy), dinv = 1.0 / d;
+      std::vector<cd> dp(2 * p + 2);
+      dp[0] = 1.0;
+      for (int i = 1; i < 2 * p + 2; ++i) dp[i] = dp[i - 1] * dinv;
+      const int o = (dx + 3) * 7 + (dy + 3);
+      for (int n = 0; n < p; ++n)
+        for (int m = 0; m < p; ++m) {
+          const cd v = ((n & 1) ? -1.0 : 1.0) * binom(m + n, n) * dp[m + n + 1];
+          Tm2l[((size_t)o * p + m) * p + n] = make_double2(v.real(), v.imag());
+        }
+    }
+  for (int cpos = 0; cpos < 4; ++cpos) {
+    const cd delta(((cpos & 1) ? 0.25 : -0.25), ((cpos & 2) ? 0.25 : -0.25));
+    std::vector<cd> dp(p + 1);
+    dp[0] = 1.0;
+    for (int i = 1; i <= p; ++i) dp[i] = dp[i - 1] * delta;
+    for (int n = 0; n < p; ++n)
+      for (int m = 0; m < p; ++m) {
+        cd mm = 0.0, ll = 0.0;
+        if (m <= n) mm = binom(n, m) * std::pow(0.5, m) * dp[n - m];
+        if (m >= n) ll = binom(m, n) * std::pow(0.5, n) * dp[m - n];
+        Tm2m[((size_t)cpos * p + m) * p + n] = make_double2(mm.real(), mm.imag());
+        Tl2l[((size_t)cpos * p + m) * p + n] = make_double2(ll.real(), ll.imag());
+      }
+  }
+  std::vector<double> inv_h(L + 1);
+  for (int l = 0; l <= L; ++l) inv_h[l] = (double)(1 << l) / t.size;
+  std::vector<double2> xs(M), nrm(M);
+  std::vector<int> perm_i(M);
+  for (int j = 0; j < M; ++j) {
+    const int k = perm[j];
+    xs[j] = make_double2(x[k] - t.ox, y[k] - t.oy);
+    nrm[j] = make_double2(nx[k], ny[k]);
+    perm_i[j] = k;
+  }
+  // upload (one arena)
+  const size_t nm2l = std::max<size_t>(m2l_src.size(), 1), nnear = std::max<size_t>(near_leaf.size(), 1);
+  const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
+                      m2l_ptr.size() + 2 * nm2l + near_ptr.size() + nnear + t.nbox;
+  const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)57 * p * p;
+  const size_t bytes = d2 * 16 + (L + 1) * 8 + ints * 4 + 32 * 256;
+  BIE_TRY(t.buf.reserve(bytes));
+  char *q = t.buf.as<char>();
+  auto take = [&](size_t nbytes) {
+    char *r = q;
+    q += (nbytes + 255) & ~size_t(255);
+    return r;
+  };
+  t.xs = (double2 *)take(M * 16);
+  t.nrm = (double2 *)take(M * 16);
+  t.center = (double2 *)take(t.nbox * 16);
+  t.T_m2l = (double2 *)take((size_t)49 * p * p * 16);
+  t.T_m2m = (double2 *)take((size_t)4 * p * p * 16);
+  t.T_l2l = (double2 *)take((size_t)4 * p * p * 16);
+  t.inv_h = (double *)take((L + 1) * 8);
+  t.perm = (int *)take(M * 4);
+  t.leaf_start = (int *)take((t.nleaf + 1) * 4);
+  t.leaf_box = (int *)take(t.nleaf * 4);
+  t.child = (int *)take(4 * (size_t)t.nbox * 4);
+  t.parent = (int *)take(t.nbox * 4);
+  t.box_level = (int *)take(t.nbox * 4);
+  t.m2l_ptr = (int *)take(m2l_ptr.size() * 4);
+  t.m2l_src = (int *)take(nm2l * 4);
+  t.m2l_off = (int *)take(nm2l * 4);
+  t.near_ptr = (int *)take(near_ptr.size() * 4);
+  t.near_leaf = (int *)take(nnear * 4);
+  if ((size_t)(q - t.buf.as<char>()) > t.buf.bytes) {
+    set_error("fmm: arena overflow");
+    return BIE_EINVAL;
+  }
+  auto up = [&](void *dst, const void *src, size_t nbytes) -> int {
+    if (nbytes == 0) return BIE_OK;
+    BIE_HIP_CHECK(hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, s));
+    return BIE_OK;
+  };
+  BIE_TRY(up(t.xs, xs.data(), M * 16));
+  BIE_TRY(up(t.nrm, nrm.data(), M * 16));
+  BIE_TRY(up(t.center, center.data(), t.nbox * 16));
+  BIE_TRY(up(t.T_m2l, Tm2l.data(), Tm2l.size() * 16));
+  BIE_TRY(up(t.T_m2m, Tm2m.data(), Tm2m.size() * 16));
+  BIE_TRY(up(t.T_l2l, Tl2l.data(), Tl2l.size() * 16));
+  BIE_TRY(up(t.inv_h, inv_h.data(), (L + 1) * 8));
+  BIE_TRY(up(t.perm, perm_i.data(), M * 4));
+  BIE_TRY(up(t.leaf_start, leaf_start.data(), leaf_start.size() * 4));
+  BIE_TRY(up(t.leaf_box, leaf_box.data(), t.nleaf * 4));
+  BIE_TRY(up(t.child, child.data(), child.size() * 4));
+  BIE_TRY(up(t.parent, parent.data(), t.nbox * 4));
+  BIE_TRY(up(t.box_level, box_level.data(), t.nbox * 4));
+  BIE_TRY(up(t.m2l_ptr, m2l_ptr.data(), m2l_ptr.size() * 4));
+  BIE_TRY(up(t.m2l_src, m2l_src.data(), m2l_src.size() * 4));
+  BIE_TRY(up(t.m2l_off, m2l_off.data(), m2l_off.size() * 4));
+  BIE_TRY(up(t.near_ptr, near_ptr.data(), near_ptr.size() * 4));
+  BIE_TRY(up(t.near_leaf, near_leaf.data(), near_leaf.size() * 4));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));  // host vectors go out of scope
+  (void)off2;
+  return BIE_OK;
+}
+
+}  // namespace
+
 int fmm_current_order() { return 0; }
+
+// Far field of all pairs k != i (sets: Laplace R, Stokes 3R) into partial [R][len] (nsplit 1).
+int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64, double *partial,
+                  hipStream_t s, int order, int leaf) {
+  int p = order > 0 ? order : 40;
+  if (precision == BIE_MIXED) p = std::max(8, (p * 11 + 19) / 20);  // about sqrt of the accuracy
+  p = std::min(p, kMaxP);
+  if (leaf <= 0) leaf = 64;
+  if (!g->fmm) g->fmm = new FmmPlan();
+  FmmTree *&tp = g->fmm->trees[p];
+  if (!tp) {
+    tp = new FmmTree();
+    const int rc = build_tree(g, p, leaf, *tp, s);
+    if (rc != BIE_OK) {
+      tp->buf.release();
+      delete tp;
+      tp = nullptr;
+      return rc;
+    }
+  }
+  FmmTree &t = *tp;
+  const int M = t.M;
+  const int nsets = kind == 0 ? R : 3 * R;
+  const size_t need = ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * 16 + 512;
+  BIE_TRY(t.work.reserve(need));
+  double2 *Q = t.work.as<double2>();
+  double2 *Mexp = Q + (size_t)nsets * M;
+  double2 *Lexp = Mexp + (size_t)nsets * t.nbox * p;
+  ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
+  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q);
+  const double ih_leaf = (double)(1 << t.L) / t.size;
+  hipLaunchKernelGGL(k_p2m, dim3(t.nleaf, nsets), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
+                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, Mexp);
+  for (int l = t.L - 1; l >= 2; --l) {
+    const int nb = t.level_off[l + 1] - t.level_off[l];
+    hipLaunchKernelGGL(k_m2m, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l], t.child,
+                       t.T_m2m, Mexp);
+  }
+  const int off2 = t.level_off[2];
+  const int n2 = t.nbox - off2;
+  if (n2 > 0)
+    hipLaunchKernelGGL(k_m2l, dim3(n2, nsets), dim3(64), 0, s, p, t.nbox, off2, t.m2l_ptr,
+                       t.m2l_src, t.m2l_off, t.box_level, t.inv_h, t.T_m2l, Mexp, Lexp);
+  for (int l = 2; l < t.L; ++l) {
+    const int nb = t.level_off[l + 2] - t.level_off[l + 1];
+    hipLaunchKernelGGL(k_l2l, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l + 1],
+                       t.parent, t.T_l2l, Lexp);
+  }
+  if (kind == 0)
+    hipLaunchKernelGGL(k_eval_laplace, dim3(t.nleaf, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
+                       t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
+                       t.near_leaf, Q, Lexp, partial);
+  else
+    hipLaunchKernelGGL(k_eval_stokes, dim3(t.nleaf, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
+                       t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
+                       t.near_leaf, Q, Lexp, partial);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
 
 }  // namespace bie

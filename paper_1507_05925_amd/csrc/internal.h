@@ -73,6 +73,8 @@ struct bie_geom {
   double *h_pinned = nullptr;  // pinned host staging for small reads
   size_t h_pinned_bytes = 0;
   bie::FmmPlan *fmm = nullptr;
+  int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
+  int fmm_leaf = 64;   // maximum nodes per leaf box
 };
 
 namespace bie {

@@ -36,12 +36,11 @@ __device__ inline double block_sum(double v, double *sh) {
   return t;
 }
 
-// float64 reciprocal: hardware estimate refined by two Newton steps (quadratic convergence).
+// float64 reciprocal: the hardware estimate (relative error below 5e-8 on gfx950, measured)
+// refined by one Newton step, which squares the error (about 2e-15, measured).
 __device__ inline double rcp64(double a) {
-  double y = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-a, y, 1.0);
+  const double y = __builtin_amdgcn_rcp(a);
+  const double e = fma(-a, y, 1.0);
   return fma(y, e, y);
 }
 
@@ -363,11 +362,12 @@ __global__ __launch_bounds__(kBlock) void k_lap_epilogue(
     int M, int nsplit, int R, const int *__restrict__ body_ptr, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ nx, const double *__restrict__ ny,
     const double *__restrict__ w, const double *__restrict__ kappa, const double *__restrict__ mu,
-    const double *__restrict__ s64, const double *__restrict__ partial, int with_L, double alpha,
-    double *__restrict__ out) {
+    const double *__restrict__ s64, const double *__restrict__ partial, int with_L, int self_block,
+    double alpha, double *__restrict__ out) {
   __shared__ double sh[4];
   const int b = blockIdx.x, r = blockIdx.y;
   const int k0 = body_ptr[b], k1 = body_ptr[b + 1];
+  const int kend = self_block ? k1 : k0;  // the FMM far field already holds same-body pairs
   const double *s = s64 + (size_t)r * M;
   const double *m = mu + (size_t)r * M;
   double part = 0.0;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_lap_epilogue(
     const int ii = valid ? i : k0;
     const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
     double gx = 0.0, gy = 0.0;
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0; k < kend; ++k) {
       const double dx = xi - x[k], dy = yi - y[k];
       const bool same = (k == ii);
       const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
@@ -399,10 +399,11 @@ __global__ __launch_bounds__(kBlock) void k_stk_epilogue(
     const double *__restrict__ y, const double *__restrict__ nx, const double *__restrict__ ny,
     const double *__restrict__ kappa, const double *__restrict__ px, const double *__restrict__ py,
     const double *__restrict__ mu, const double *__restrict__ s64, const double *__restrict__ partial,
-    int with_L, double alpha, double *__restrict__ out) {
+    int with_L, int self_block, double alpha, double *__restrict__ out) {
   __shared__ double sh[4];
   const int b = blockIdx.x, r = blockIdx.y;
   const int k0 = body_ptr[b], k1 = body_ptr[b + 1];
+  const int kend = self_block ? k1 : k0;
   const double *s = s64 + (size_t)r * 2 * M;
   const double *m = mu + (size_t)r * 2 * M;
   double f1 = 0.0, f2 = 0.0, tq = 0.0;
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_stk_epilogue(
     const int ii = valid ? i : k0;
     const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
     double gx = 0.0, gy = 0.0;
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0; k < kend; ++k) {
       const double dx = xi - x[k], dy = yi - y[k];
       const bool same = (k == ii);
       const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
@@ -608,7 +609,8 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
     const int R = left >= maxR ? maxR : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
     const size_t off = (size_t)r0 * len;
     if (method == BIE_FMM) {
-      BIE_TRY(fmm_far_field(g, kind, precision, R, s64 + off, partial, st, 0, 0));
+      BIE_TRY(fmm_far_field(g, kind, precision, R, s64 + off, partial, st, g->fmm_order,
+                            g->fmm_leaf));
     } else {
       switch (R) {
         case 8: launch_far<8>(g, kind, precision, s64, s32, partial, st, off); break;
@@ -623,11 +625,11 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
     if (kind == 0)
       hipLaunchKernelGGL(k_lap_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, g->body_ptr,
                          g->x, g->y, g->nx, g->ny, g->w, g->kappa, mu + off, s64 + off, partial,
-                         with_L, alpha, out + off);
+                         with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
     else
       hipLaunchKernelGGL(k_stk_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, g->body_ptr,
                          g->x, g->y, g->nx, g->ny, g->kappa, g->px, g->py, mu + off, s64 + off,
-                         partial, with_L, alpha, out + off);
+                         partial, with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
     BIE_HIP_CHECK(hipGetLastError());
     r0 += R;
   }

@@ -1,0 +1,109 @@
+"""GPU: the 2D FMM far field against the direct sweep and against the float64 oracle.
+
+The paper names the FMM without describing it, so it is pinned only against the direct sum: the
+error must fall geometrically with the expansion order p (about 0.55^p for the one-box-separation
+interaction lists) and reach the float64 solve tolerances at the default order.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import matfree as mf  # noqa: E402
+from oracle import nystrom as ny  # noqa: E402
+from paper_1507_05925_amd import bie2d  # noqa: E402
+from paper_1507_05925_amd import workloads as wl  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs the GPU")]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _cases():
+    rng = np.random.default_rng(5)
+    return {"ragged": wl.mixed_grid(rng, 6, np.array([3, 67, 300, 513, 64, 129])),
+            "splash": wl.splash(256), "starfish100": wl.elastance_starfish(nbodies=100)[0],
+            "ellipses30": wl.mobility_ellipses(nbodies=30, n=256)[0]}
+
+
+@pytest.mark.parametrize("kind", ["laplace", "stokes"])
+def test_fmm_error_decays_with_order(kind):
+    rng = np.random.default_rng(1)
+    for name, c in _cases().items():
+        g = bie2d.Geometry.from_curves(c)
+        n = g.M if kind == "laplace" else 2 * g.M
+        mu = dev(rng.standard_normal((2, n)))
+        f = bie2d.bie_laplace_apply if kind == "laplace" else bie2d.bie_stokes_apply
+        ref = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_DIRECT)
+        errs = []
+        for p in (12, 20, 28, 40, 52):
+            g.set_fmm(p, 48)
+            out = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
+            errs.append(float((out - ref).abs().max() / ref.abs().max()))
+        assert errs[-1] < 1e-12, (name, errs)
+        assert errs[3] < 1e-10, (name, errs)
+        assert errs[0] > 10 * errs[2], (name, errs)  # converging, not accidentally exact
+
+
+@pytest.mark.parametrize("kind", ["laplace", "stokes"])
+def test_fmm_multi_rhs_and_with_L(kind):
+    c = wl.elastance_small()[0]
+    geo = ny.geometry_of(c)
+    g = bie2d.Geometry.from_curves(c)
+    g.set_fmm(48, 16)
+    rng = np.random.default_rng(2)
+    if kind == "laplace":
+        A = 0.5 * np.eye(geo["M"]) + ny.laplace_K(geo)
+        for with_L in (True, False):
+            AA = A + (ny.laplace_L(geo) if with_L else 0)
+            mu = rng.standard_normal((5, geo["M"]))
+            out = bie2d.bie_laplace_apply(g, dev(mu), bie2d.BIE_FP64, bie2d.BIE_FMM, with_L=with_L)
+            assert float(np.abs(out.cpu().numpy() - mu @ AA.T).max() / np.abs(mu @ AA.T).max()) < 1e-12
+    else:
+        A = 0.5 * np.eye(2 * geo["M"]) + ny.stokes_K(geo) + ny.stokes_L(geo)
+        mu = rng.standard_normal((5, 2 * geo["M"]))
+        out = bie2d.bie_stokes_apply(g, dev(mu), bie2d.BIE_FP64, bie2d.BIE_FMM)
+        assert float(np.abs(out.cpu().numpy() - mu @ A.T).max() / np.abs(mu @ A.T).max()) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_fmm_solves_small(precision, tol):
+    rng = np.random.default_rng(3)
+    for name in ("ragged", "starfish100"):
+        c = _cases()[name]
+        geo = ny.geometry_of(c)
+        g = bie2d.Geometry.from_curves(c)
+        o = bie2d.default_opts(precision=precision, method=bie2d.BIE_FMM, fmm_order=48,
+                               tol=1e-12, restart=200, max_iter=4000)
+        if geo["M"] <= 3000:
+            q = rng.standard_normal((2, geo["N"]))
+            phi, info = bie2d.bie_elastance_solve(g, dev(q), o)
+            ref = ny.elastance_solve(geo, q)["phi"]
+            assert float(np.abs(phi.cpu().numpy() - ref).max() / np.abs(ref).max()) < tol, info
+            FT = rng.standard_normal((1, 3 * geo["N"]))
+            VW, info = bie2d.bie_mobility_solve(g, dev(FT), o)
+            refm = ny.mobility_solve(geo, FT)["VW"]
+            assert float(np.abs(VW.cpu().numpy() - refm).max() / np.abs(refm).max()) < tol, info
+        else:
+            q = rng.standard_normal(geo["N"])
+            phi, info = bie2d.bie_elastance_solve(g, dev(q[None]), o)
+            ref = mf.elastance_solve(geo, q)["phi"]
+            assert float(np.abs(phi.cpu().numpy()[0] - ref).max() / np.abs(ref).max()) < tol, info
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_fmm_full_size_elastance(precision, tol):
+    gold = json.load(open(os.path.join(GOLDEN, "starfish_1000x256_phi.json")))
+    c, q = wl.elastance_starfish()
+    g = bie2d.Geometry.from_curves(c)
+    o = bie2d.default_opts(precision=precision, method=bie2d.BIE_FMM, tol=1e-12, restart=100)
+    phi, info = bie2d.bie_elastance_solve(g, dev(q[None]), o)
+    err = float(np.abs(phi.cpu().numpy()[0] - np.asarray(gold["phi"])).max() / np.abs(gold["phi"]).max())
+    assert err < tol, (err, info)
