@@ -166,7 +166,8 @@ int bie_mobility_matrix(bie_geom *g, double *Mmat, int max_rhs_per_pass, const b
 /* ---- instrumentation (not a step of the method) ---------------------------------------------
  * When enabled, the library records a pair of HIP events on the launch stream around every
  * launch of the kernel classes below and accumulates, per class, the number of launches, their
- * summed durations and the pair interactions they evaluate (target-source pairs times rhs).
+ * summed durations and the work units they process (target-source pairs times rhs unless the
+ * class says otherwise).
  * bie_profile_enable(1) clears the counters; bie_profile_read() waits for the recorded events
  * of that class and returns the totals. Process-wide; not thread safe. */
 #define BIE_K_FAR_LAPLACE_F32 0 /* float32 far-field sweep, Laplace            */
@@ -174,8 +175,10 @@ int bie_mobility_matrix(bie_geom *g, double *Mmat, int max_rhs_per_pass, const b
 #define BIE_K_FAR_STOKES_F32 2  /* float32 far-field sweep, Stokes             */
 #define BIE_K_FAR_STOKES_F64 3  /* float64 far-field sweep, Stokes             */
 #define BIE_K_EPILOGUE 4        /* self blocks + diagonal + completion + sum   */
-#define BIE_K_FMM 5             /* FMM far field (all its kernels)             */
-#define BIE_K_COUNT 6
+#define BIE_K_FMM 5             /* FMM far field, all its kernels; units: M^2 per rhs (equivalent pairs) */
+#define BIE_K_FMM_M2L 6         /* FMM multipole-to-local; units: complex multiply-adds */
+#define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
+#define BIE_K_COUNT 8
 int bie_profile_enable(int on);
 int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs);
 

@@ -74,7 +74,7 @@ _SIGS = {
 }
 
 BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
-BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_COUNT = 4, 5, 6
+BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL, BIE_K_COUNT = 4, 5, 6, 7, 8
 
 
 def bie_profile_enable(on=True):

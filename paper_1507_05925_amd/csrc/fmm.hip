@@ -7,8 +7,9 @@
 //             (1/4) [conj(nu) conj(C'(z) - conj(z) A'(z)) + conj(nu) conj(B(z)) + nu conj(A(z)) + nu A(z)]
 //             with A: Q = rho_k, B: Q = conj(rho_k), C: Q = rho_k conj(zeta_k), rho_k = s_k1 + i s_k2,
 //             all coordinates taken relative to the root-box centre (the shift cancels in C' - z A').
-// Tree: uniform quadtree over the bounding square, refined until no leaf holds more than `leaf`
-// nodes; only non-empty boxes are stored. Expansions are scaled by the box size h:
+// Tree: uniform quadtree over the bounding square whose depth makes the mean population of the
+// non-empty leaves closest to `leaf` (nodes lie on curves, so populations are uneven); only
+// non-empty boxes are stored, in Morton order, so each box is a contiguous run of sorted nodes. Expansions are scaled by the box size h:
 //   multipole a_m = sum_k Q_k ((zeta_k - c)/h)^m,   F(z) = sum_m a_m h^m / (z - c)^{m+1}
 //   local     F(z) = sum_n b_n ((z - c)/h)^n
 // so the 40 M2L operators (offsets d with max(|dx|,|dy|) in {2,3}) and the 4 M2M / 4 L2L operators
@@ -39,7 +40,10 @@ struct FmmTree {
   DevBuf buf;
   int *perm = nullptr, *leaf_start = nullptr, *leaf_box = nullptr, *child = nullptr,
       *parent = nullptr, *m2l_ptr = nullptr, *m2l_src = nullptr, *m2l_off = nullptr,
-      *near_ptr = nullptr, *near_leaf = nullptr, *box_level = nullptr;
+      *near_ptr = nullptr, *near_leaf = nullptr, *box_level = nullptr, *chunk_leaf = nullptr,
+      *chunk_start = nullptr;
+  int nchunk = 0;
+  long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
   double2 *T_m2l = nullptr, *T_m2m = nullptr, *T_l2l = nullptr;  // transposed [.][m][n]
   double *inv_h = nullptr;  // [L+1]
@@ -193,26 +197,32 @@ __device__ inline void eval_local(const double2 *b, int p, double2 w, double ih,
   dF = make_double2(dF.x * ih, dF.y * ih);
 }
 
+__device__ inline void eval_value(const double2 *b, int p, double2 w, double2 &F) {
+  F = b[p - 1];
+  for (int n = p - 1; n >= 1; --n) F = cfma(F, w, b[n - 1]);
+}
+
 // L2P + near field, Laplace. grid (nleaf, R); writes -(1/2pi) n.(sum_{k != i} s_k r/|r|^2).
 __global__ __launch_bounds__(64) void k_eval_laplace(
     int p, int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
     const int *__restrict__ leaf_box, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
-  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
   const double2 *b = Lexp + ((size_t)r * nbox + box) * p;
   const double2 *q = Q + (size_t)r * M;
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  for (int base = j0; base < j1; base += 64) {
-    const int j = base + threadIdx.x;
+  {
+    const int j = chunk_start[blockIdx.x] + threadIdx.x;
     const bool valid = j < j1;
     const int jj = valid ? j : j0;
     const double2 z = xs[jj], nv = nrm[jj];
-    double2 F, dF;
-    eval_local(b, p, make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf), ih_leaf, F, dF);
+    double2 F;
+    eval_value(b, p, make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf), F);
     double gx = 0.0, gy = 0.0;
     for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
       const int nl = near_leaf[e];
@@ -238,8 +248,9 @@ __global__ __launch_bounds__(64) void k_eval_stokes(
     const int *__restrict__ leaf_box, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
-  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
   const double2 *bA = Lexp + ((size_t)(3 * r) * nbox + box) * p;
@@ -247,15 +258,15 @@ __global__ __launch_bounds__(64) void k_eval_stokes(
   const double2 *bC = Lexp + ((size_t)(3 * r + 2) * nbox + box) * p;
   const double2 *q = Q + (size_t)(3 * r) * M;  // rho in sorted order
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  for (int base = j0; base < j1; base += 64) {
-    const int j = base + threadIdx.x;
+  {
+    const int j = chunk_start[blockIdx.x] + threadIdx.x;
     const bool valid = j < j1;
     const int jj = valid ? j : j0;
     const double2 z = xs[jj], nv = nrm[jj];
     const double2 w = make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf);
-    double2 A, dA, B, dB, C, dC;
+    double2 A, dA, B, C, dC;
     eval_local(bA, p, w, ih_leaf, A, dA);
-    eval_local(bB, p, w, ih_leaf, B, dB);
+    eval_value(bB, p, w, B);
     eval_local(bC, p, w, ih_leaf, C, dC);
     // t1 = conj(nu) conj(C' - conj(z) A'); t2 = conj(nu) conj(B); t3 = nu conj(A) + nu A
     const double2 zA = cmul(make_double2(z.x, -z.y), dA);
@@ -314,60 +325,79 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.size = std::max(x1 - x0, y1 - y0) * (1.0 + 1e-9) + 1e-300;
   t.ox = 0.5 * (x0 + x1);
   t.oy = 0.5 * (y0 + y1);
-  auto cell = [&](double v, double o, int n) {
-    long long i = (long long)std::floor((v - o + 0.5 * t.size) / t.size * n);
-    return (int)std::min<long long>(std::max<long long>(i, 0), n - 1);
+  // cells at the finest level (14) and their Morton keys (x bits even, y bits odd); one sort
+  // makes every box of every level a contiguous run of nodes
+  constexpr int kTop = 14;
+  const int nTop = 1 << kTop;
+  auto cell = [&](double v, double o) {
+    long long i = (long long)std::floor((v - o + 0.5 * t.size) / t.size * nTop);
+    return (unsigned)std::min<long long>(std::max<long long>(i, 0), nTop - 1);
   };
-  // depth: refine until no leaf holds more than leaf_cap nodes (at most 14 levels)
+  auto spread = [](unsigned v) {
+    v &= 0xffff;
+    v = (v | (v << 8)) & 0x00ff00ff;
+    v = (v | (v << 4)) & 0x0f0f0f0f;
+    v = (v | (v << 2)) & 0x33333333;
+    v = (v | (v << 1)) & 0x55555555;
+    return v;
+  };
+  std::vector<unsigned long long> kv(M);  // (morton << 32) | index
+  for (int k = 0; k < M; ++k) {
+    const unsigned mk = spread(cell(x[k], t.ox)) | (spread(cell(y[k], t.oy)) << 1);
+    kv[k] = ((unsigned long long)mk << 32) | (unsigned)k;
+  }
+  std::sort(kv.begin(), kv.end());
+  std::vector<int> perm(M);
+  std::vector<unsigned> mort(M);
+  for (int j = 0; j < M; ++j) {
+    perm[j] = (int)(kv[j] & 0xffffffffu);
+    mort[j] = (unsigned)(kv[j] >> 32);
+  }
+  // depth: mean population of non-empty leaves closest (in log) to leaf_cap; at least 2 levels
   int L = 2;
-  for (; L < 14; ++L) {
-    const int n = 1 << L;
-    std::unordered_map<long long, int> cnt;
-    cnt.reserve(M / 8 + 16);
-    int mx = 0;
-    for (int k = 0; k < M; ++k) {
-      long long key = (long long)cell(y[k], t.oy, n) * n + cell(x[k], t.ox, n);
-      mx = std::max(mx, ++cnt[key]);
+  double best = 1e300;
+  for (int l = 2; l <= 12; ++l) {
+    const int sh = 2 * (kTop - l);
+    long long runs = 1;
+    for (int j = 1; j < M; ++j) runs += (mort[j] >> sh) != (mort[j - 1] >> sh);
+    const double mean = (double)M / (double)runs;
+    const double d = std::fabs(std::log(mean / (double)leaf_cap));
+    if (d < best) {
+      best = d;
+      L = l;
     }
-    if (mx <= leaf_cap) break;
+    if (mean < 0.5 * leaf_cap) break;
   }
   t.L = L;
   const int nL = 1 << L;
-  std::vector<long long> key(M);
-  std::vector<int> perm(M);
-  for (int k = 0; k < M; ++k) {
-    key[k] = (long long)cell(y[k], t.oy, nL) * nL + cell(x[k], t.ox, nL);
-    perm[k] = k;
-  }
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
-  // boxes per level: sorted unique keys
+  auto decode = [](unsigned v) {  // compact even bits
+    v &= 0x55555555;
+    v = (v | (v >> 1)) & 0x33333333;
+    v = (v | (v >> 2)) & 0x0f0f0f0f;
+    v = (v | (v >> 4)) & 0x00ff00ff;
+    v = (v | (v >> 8)) & 0x0000ffff;
+    return v;
+  };
+  // boxes per level: sorted unique Morton keys (at level l a key has 2l bits)
   std::vector<std::vector<long long>> keys(L + 1);
   std::vector<int> leaf_start;
+  const int shL = 2 * (kTop - L);
   for (int j = 0; j < M; ++j) {
-    const long long kk = key[perm[j]];
+    const long long kk = mort[j] >> shL;
     if (keys[L].empty() || keys[L].back() != kk) {
       keys[L].push_back(kk);
       leaf_start.push_back(j);
     }
   }
   leaf_start.push_back(M);
-  for (int l = L - 1; l >= 0; --l) {
-    const int nch = 1 << (l + 1), n = 1 << l;
-    for (long long kk : keys[l + 1]) {
-      const long long iy = kk / nch, ix = kk % nch;
-      const long long pk = (iy >> 1) * n + (ix >> 1);
-      if (keys[l].empty() || keys[l].back() != pk) {
-        // children of one parent are not contiguous in row-major order: insert sorted later
-        keys[l].push_back(pk);
-      }
-    }
-    std::sort(keys[l].begin(), keys[l].end());
-    keys[l].erase(std::unique(keys[l].begin(), keys[l].end()), keys[l].end());
-  }
+  for (int l = L - 1; l >= 0; --l)
+    for (long long kk : keys[l + 1])
+      if (keys[l].empty() || keys[l].back() != (kk >> 2)) keys[l].push_back(kk >> 2);
   t.level_off.assign(L + 2, 0);
   for (int l = 0; l <= L; ++l) t.level_off[l + 1] = t.level_off[l] + (int)keys[l].size();
   t.nbox = t.level_off[L + 1];
   t.nleaf = (int)keys[L].size();
+  auto enc = [&](int ix, int iy) { return (long long)(spread((unsigned)ix) | (spread((unsigned)iy) << 1)); };
   auto find = [&](int l, long long kk) -> int {
     auto it = std::lower_bound(keys[l].begin(), keys[l].end(), kk);
     if (it == keys[l].end() || *it != kk) return -1;
@@ -380,17 +410,18 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     const double h = t.size / n;
     for (size_t b = 0; b < keys[l].size(); ++b) {
       const long long kk = keys[l][b];
-      const long long iy = kk / n, ix = kk % n;
+      const long long ix = decode((unsigned)kk), iy = decode((unsigned)(kk >> 1));
       const int gb = t.level_off[l] + (int)b;
       box_level[gb] = l;
       center[gb] = make_double2(-0.5 * t.size + (ix + 0.5) * h, -0.5 * t.size + (iy + 0.5) * h);
       if (l > 0) {
-        const int pb = find(l - 1, (iy >> 1) * (n >> 1) + (ix >> 1));
+        const int pb = find(l - 1, kk >> 2);
         const int cpos = (int)((iy & 1) * 2 + (ix & 1));
         child[4 * pb + cpos] = gb;
         parent[gb] = pb * 4 + cpos;
       }
     }
+    (void)n;
   }
   // M2L lists (levels >= 2) and near lists (leaves)
   std::vector<int> m2l_ptr(1, 0), m2l_src, m2l_off;
@@ -398,7 +429,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   for (int l = 2; l <= L; ++l) {
     const int n = 1 << l;
     for (long long kk : keys[l]) {
-      const int iy = (int)(kk / n), ix = (int)(kk % n);
+      const int ix = (int)decode((unsigned)kk), iy = (int)decode((unsigned)(kk >> 1));
       const int py = iy >> 1, px = ix >> 1, np = n >> 1;
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
@@ -408,7 +439,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
             for (int cx = 0; cx < 2; ++cx) {
               const int sy = 2 * qy + cy, sx = 2 * qx + cx;
               if (std::max(std::abs(sx - ix), std::abs(sy - iy)) < 2) continue;
-              const int sb = find(l, (long long)sy * n + sx);
+              const int sb = find(l, enc(sx, sy));
               if (sb < 0) continue;
               m2l_src.push_back(sb);
               m2l_off.push_back((ix - sx + 3) * 7 + (iy - sy + 3));
@@ -417,17 +448,28 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       m2l_ptr.push_back((int)m2l_src.size());
     }
   }
+  t.m2l_entries = (long long)m2l_src.size();
   std::vector<int> near_ptr(1, 0), near_leaf, leaf_box(t.nleaf);
+  std::vector<int> chunk_leaf, chunk_start;
   for (int b = 0; b < t.nleaf; ++b) {
     const long long kk = keys[L][b];
-    const int iy = (int)(kk / nL), ix = (int)(kk % nL);
+    const int ix = (int)decode((unsigned)kk), iy = (int)decode((unsigned)(kk >> 1));
     leaf_box[b] = t.level_off[L] + b;
+    for (int j = leaf_start[b]; j < leaf_start[b + 1]; j += 64) {
+      chunk_leaf.push_back(b);
+      chunk_start.push_back(j);
+    }
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         const int qy = iy + dy, qx = ix + dx;
         if (qy < 0 || qx < 0 || qy >= nL || qx >= nL) continue;
-        const int nb = find(L, (long long)qy * nL + qx);
-        if (nb >= 0) near_leaf.push_back(nb - t.level_off[L]);
+        const int nb = find(L, enc(qx, qy));
+        if (nb >= 0) {
+          near_leaf.push_back(nb - t.level_off[L]);
+          const int nl = nb - t.level_off[L];
+          t.near_pairs += (long long)(leaf_start[b + 1] - leaf_start[b]) *
+                          (leaf_start[nl + 1] - leaf_start[nl]);
+        }
       }
     near_ptr.push_back((int)near_leaf.size());
   }
@@ -475,7 +517,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   // upload (one arena)
   const size_t nm2l = std::max<size_t>(m2l_src.size(), 1), nnear = std::max<size_t>(near_leaf.size(), 1);
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
-                      m2l_ptr.size() + 2 * nm2l + near_ptr.size() + nnear + t.nbox;
+                      m2l_ptr.size() + 2 * nm2l + near_ptr.size() + nnear + t.nbox +
+                      2 * chunk_leaf.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)57 * p * p;
   const size_t bytes = d2 * 16 + (L + 1) * 8 + ints * 4 + 32 * 256;
   BIE_TRY(t.buf.reserve(bytes));
@@ -503,6 +546,9 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.m2l_off = (int *)take(nm2l * 4);
   t.near_ptr = (int *)take(near_ptr.size() * 4);
   t.near_leaf = (int *)take(nnear * 4);
+  t.nchunk = (int)chunk_leaf.size();
+  t.chunk_leaf = (int *)take(chunk_leaf.size() * 4);
+  t.chunk_start = (int *)take(chunk_start.size() * 4);
   if ((size_t)(q - t.buf.as<char>()) > t.buf.bytes) {
     set_error("fmm: arena overflow");
     return BIE_EINVAL;
@@ -530,6 +576,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.m2l_off, m2l_off.data(), m2l_off.size() * 4));
   BIE_TRY(up(t.near_ptr, near_ptr.data(), near_ptr.size() * 4));
   BIE_TRY(up(t.near_leaf, near_leaf.data(), near_leaf.size() * 4));
+  BIE_TRY(up(t.chunk_leaf, chunk_leaf.data(), chunk_leaf.size() * 4));
+  BIE_TRY(up(t.chunk_start, chunk_start.data(), chunk_start.size() * 4));
   BIE_HIP_CHECK(hipStreamSynchronize(s));  // host vectors go out of scope
   (void)off2;
   return BIE_OK;
@@ -578,22 +626,25 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   }
   const int off2 = t.level_off[2];
   const int n2 = t.nbox - off2;
-  if (n2 > 0)
+  if (n2 > 0) {
+    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)p * p);
     hipLaunchKernelGGL(k_m2l, dim3(n2, nsets), dim3(64), 0, s, p, t.nbox, off2, t.m2l_ptr,
                        t.m2l_src, t.m2l_off, t.box_level, t.inv_h, t.T_m2l, Mexp, Lexp);
+  }
   for (int l = 2; l < t.L; ++l) {
     const int nb = t.level_off[l + 2] - t.level_off[l + 1];
     hipLaunchKernelGGL(k_l2l, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l + 1],
                        t.parent, t.T_l2l, Lexp);
   }
+  ProfScope pe(BIE_K_FMM_EVAL, s, (t.near_pairs - M) * R);
   if (kind == 0)
-    hipLaunchKernelGGL(k_eval_laplace, dim3(t.nleaf, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
+    hipLaunchKernelGGL(k_eval_laplace, dim3(t.nchunk, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
                        t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
-                       t.near_leaf, Q, Lexp, partial);
+                       t.near_leaf, t.chunk_leaf, t.chunk_start, Q, Lexp, partial);
   else
-    hipLaunchKernelGGL(k_eval_stokes, dim3(t.nleaf, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
+    hipLaunchKernelGGL(k_eval_stokes, dim3(t.nchunk, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
                        t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
-                       t.near_leaf, Q, Lexp, partial);
+                       t.near_leaf, t.chunk_leaf, t.chunk_start, Q, Lexp, partial);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
