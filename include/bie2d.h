@@ -84,7 +84,8 @@ const char *bie_last_error(void);
 /* Fills *o with the defaults: BIE_FP64, BIE_DIRECT, tol 1e-12, restart 100, max_iter 500,
  * inner_tol 1e-6, max_refine 10, fmm_order 40, fmm_leaf 64. With BIE_FMM and BIE_MIXED the inner
  * applies use order ceil(0.55 fmm_order) (about the square root of the accuracy); all FMM
- * arithmetic is float64. fmm_order must lie in [4, 64]. */
+ * arithmetic is float64. fmm_order must lie in [4, 64]; the library rounds the order up to a
+ * multiple of 8. */
 int bie_default_opts(bie_opts *o);
 
 /* ---- a1: geometry and quadrature (elastance section; eq. rho for W; centroid of the mobility

@@ -45,7 +45,8 @@ struct FmmTree {
   int nchunk = 0;
   long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
-  double2 *T_m2l = nullptr, *T_m2m = nullptr, *T_l2l = nullptr;  // transposed [.][m][n]
+  double2 *T_m2l = nullptr, *T_m2m = nullptr, *T_l2l = nullptr;  // T_m2l: Hankel vectors [40][2p]
+  double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n / n!  and  1/n!
   double *inv_h = nullptr;  // [L+1]
   DevBuf work;              // charges + expansions
 };
@@ -116,6 +117,7 @@ __global__ __launch_bounds__(64) void k_p2m(int p, int M, int nbox, double inv_h
                                            const double2 *__restrict__ center,
                                            const double2 *__restrict__ xs,
                                            const double2 *__restrict__ Q,
+                                           const double *__restrict__ fact_in,
                                            double2 *__restrict__ Mexp) {
   const int leaf = blockIdx.x, set = blockIdx.y, n = threadIdx.x;
   const int box = leaf_box[leaf];
@@ -128,7 +130,10 @@ __global__ __launch_bounds__(64) void k_p2m(int p, int M, int nbox, double inv_h
     const double2 w = make_double2((z.x - c.x) * inv_h, (z.y - c.y) * inv_h);
     a = cfma(q[j], cpow(w, n), a);
   }
-  if (n < p) Mexp[((size_t)set * nbox + box) * p + n] = a;
+  if (n < p) {
+    const double f = fact_in[n];
+    Mexp[((size_t)set * nbox + box) * p + n] = make_double2(a.x * f, a.y * f);
+  }
 }
 
 // M2M for one level: grid (boxes of the level, nsets).
@@ -147,24 +152,55 @@ __global__ __launch_bounds__(64) void k_m2m(int p, int nbox, int off, const int 
   if (threadIdx.x < p) Mexp[((size_t)set * nbox + b) * p + n] = acc;
 }
 
-// M2L for all boxes of levels >= 2: grid (nbox - off2, nsets). Writes (initialises) Lexp.
-__global__ __launch_bounds__(64) void k_m2l(int p, int nbox, int off2, const int *__restrict__ ptr,
-                                           const int *__restrict__ src, const int *__restrict__ offs,
-                                           const int *__restrict__ box_level,
-                                           const double *__restrict__ inv_h,
-                                           const double2 *__restrict__ Tt,
-                                           const double2 *__restrict__ Mexp,
-                                           double2 *__restrict__ Lexp) {
-  const int t = off2 + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
-  double2 acc = make_double2(0.0, 0.0);
-  const int e0 = ptr[t - off2], e1 = ptr[t - off2 + 1];
-  for (int e = e0; e < e1; ++e) {
-    const double2 *a = Mexp + ((size_t)set * nbox + src[e]) * p;
-    const double2 *T = Tt + (size_t)offs[e] * p * p;
-    for (int m = 0; m < p; ++m) acc = cfma(T[(size_t)m * p + n], a[m], acc);
+// M2L for all boxes of levels >= 2, written into Lexp. Multipoles are stored as u_m = a_m / m!,
+// which turns the operator into a Hankel product:
+//   b_n = (1/h) ((-1)^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / d^(k+1),
+// for the box offset d. The 40 vectors V_d (2p entries each) sit in LDS; lane n reads V_d[m + n]
+// (consecutive lanes, consecutive addresses) and u_m is wave-uniform (scalar loads). Each wave
+// walks target boxes with a grid stride, so the table is loaded once per workgroup.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l(int p_unused, int nbox, int off2, int n2, int nsets,
+                                            const int *__restrict__ ptr,
+                                            const int *__restrict__ src,
+                                            const int *__restrict__ offs,
+                                            const int *__restrict__ box_level,
+                                            const double *__restrict__ inv_h,
+                                            const double *__restrict__ fact_out,
+                                            const double2 *__restrict__ Vtab,
+                                            const double2 *__restrict__ Mexp,
+                                            double2 *__restrict__ Lexp) {
+  constexpr int p = P;
+  extern __shared__ double2 V[];
+  const int tlen = 40 * 2 * p;
+  for (int i = threadIdx.x; i < tlen; i += blockDim.x) V[i] = Vtab[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane < p ? lane : p - 1;
+  const int waves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const long long total = (long long)n2 * nsets;
+  for (long long item = (long long)blockIdx.x * waves + wave; item < total;
+       item += (long long)gridDim.x * waves) {
+    const int set = (int)(item / n2);
+    const int t = off2 + (int)(item % n2);
+    // four partial sums (m mod 4) break the dependent multiply-add chain
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+    const int e0 = ptr[t - off2], e1 = ptr[t - off2 + 1];
+    for (int e = e0; e < e1; ++e) {
+      const double2 *u = Mexp + ((size_t)set * nbox + src[e]) * p;
+      const double2 *Vo = V + offs[e] * 2 * p + n;
+#pragma unroll
+      for (int m = 0; m < p; m += 4) {
+        a0 = cfma(u[m], Vo[m], a0);
+        a1 = cfma(u[m + 1], Vo[m + 1], a1);
+        a2 = cfma(u[m + 2], Vo[m + 2], a2);
+        a3 = cfma(u[m + 3], Vo[m + 3], a3);
+      }
+    }
+    const double2 acc = make_double2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
+    const double sc = inv_h[box_level[t]] * fact_out[n];
+    if (lane < p) Lexp[((size_t)set * nbox + t) * p + n] = make_double2(acc.x * sc, acc.y * sc);
   }
-  const double s = inv_h[box_level[t]];
-  if (threadIdx.x < p) Lexp[((size_t)set * nbox + t) * p + n] = make_double2(acc.x * s, acc.y * s);
 }
 
 // L2L from level l to l+1: grid (boxes of level l+1, nsets); accumulates into Lexp.
@@ -473,23 +509,36 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       }
     near_ptr.push_back((int)near_leaf.size());
   }
-  // translation operators, transposed to [m][n]
-  std::vector<double2> Tm2l((size_t)49 * p * p, make_double2(0, 0)), Tm2m((size_t)4 * p * p),
-      Tl2l((size_t)4 * p * p);
+  // translation operators. M2L: Hankel vectors V_d[k] = k!/d^(k+1), k < 2p, for the 40 offsets
+  // (compact index). M2M on u-form multipoles: u0_n = sum_{m<=n} 2^-m delta^(n-m)/(n-m)! u1_m.
+  // L2L on locals: b1_n = sum_{m>=n} C(m,n) 2^-n delta^(m-n) b0_m. Both stored as [pos][m][n].
+  std::vector<int> ocompact(49, -1);
+  int nc = 0;
+  for (int dx = -3; dx <= 3; ++dx)
+    for (int dy = -3; dy <= 3; ++dy)
+      if (std::max(std::abs(dx), std::abs(dy)) >= 2) ocompact[(dx + 3) * 7 + (dy + 3)] = nc++;
+  for (auto &o : m2l_off) o = ocompact[o];
+  std::vector<double2> Tm2l((size_t)40 * 2 * p), Tm2m((size_t)4 * p * p), Tl2l((size_t)4 * p * p);
   for (int dx = -3; dx <= 3; ++dx)
     for (int dy = -3; dy <= 3; ++dy) {
-      if (std::max(std::abs(dx), std::abs(dy)) < 2) continue;
-      const cd d(dx, dy), dinv = 1.0 / d;
-      std::vector<cd> dp(2 * p + 2);
-      dp[0] = 1.0;
-      for (int i = 1; i < 2 * p + 2; ++i) dp[i] = dp[i - 1] * dinv;
-      const int o = (dx + 3) * 7 + (dy + 3);
-      for (int n = 0; n < p; ++n)
-        for (int m = 0; m < p; ++m) {
-          const cd v = ((n & 1) ? -1.0 : 1.0) * binom(m + n, n) * dp[m + n + 1];
-          Tm2l[((size_t)o * p + m) * p + n] = make_double2(v.real(), v.imag());
-        }
+      const int o = ocompact[(dx + 3) * 7 + (dy + 3)];
+      if (o < 0) continue;
+      const cd dinv = 1.0 / cd(dx, dy);
+      cd v = dinv;  // k = 0: 0!/d
+      for (int k = 0; k < 2 * p; ++k) {
+        Tm2l[(size_t)o * 2 * p + k] = make_double2(v.real(), v.imag());
+        v = v * dinv * (double)(k + 1);
+      }
     }
+  std::vector<double> fact_out(p), fact_in(p);
+  {
+    double f = 1.0;
+    for (int n = 0; n < p; ++n) {
+      if (n > 0) f *= n;
+      fact_in[n] = 1.0 / f;
+      fact_out[n] = ((n & 1) ? -1.0 : 1.0) / f;
+    }
+  }
   for (int cpos = 0; cpos < 4; ++cpos) {
     const cd delta(((cpos & 1) ? 0.25 : -0.25), ((cpos & 2) ? 0.25 : -0.25));
     std::vector<cd> dp(p + 1);
@@ -498,7 +547,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     for (int n = 0; n < p; ++n)
       for (int m = 0; m < p; ++m) {
         cd mm = 0.0, ll = 0.0;
-        if (m <= n) mm = binom(n, m) * std::pow(0.5, m) * dp[n - m];
+        if (m <= n) mm = std::pow(0.5, m) * dp[n - m] * fact_in[n - m];
         if (m >= n) ll = binom(m, n) * std::pow(0.5, n) * dp[m - n];
         Tm2m[((size_t)cpos * p + m) * p + n] = make_double2(mm.real(), mm.imag());
         Tl2l[((size_t)cpos * p + m) * p + n] = make_double2(ll.real(), ll.imag());
@@ -519,8 +568,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
                       m2l_ptr.size() + 2 * nm2l + near_ptr.size() + nnear + t.nbox +
                       2 * chunk_leaf.size();
-  const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)57 * p * p;
-  const size_t bytes = d2 * 16 + (L + 1) * 8 + ints * 4 + 32 * 256;
+  const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p;
+  const size_t bytes = d2 * 16 + (L + 1 + 2 * p) * 8 + ints * 4 + 32 * 256;
   BIE_TRY(t.buf.reserve(bytes));
   char *q = t.buf.as<char>();
   auto take = [&](size_t nbytes) {
@@ -531,7 +580,9 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.xs = (double2 *)take(M * 16);
   t.nrm = (double2 *)take(M * 16);
   t.center = (double2 *)take(t.nbox * 16);
-  t.T_m2l = (double2 *)take((size_t)49 * p * p * 16);
+  t.T_m2l = (double2 *)take((size_t)80 * p * 16);
+  t.fact_out = (double *)take(p * 8);
+  t.fact_in = (double *)take(p * 8);
   t.T_m2m = (double2 *)take((size_t)4 * p * p * 16);
   t.T_l2l = (double2 *)take((size_t)4 * p * p * 16);
   t.inv_h = (double *)take((L + 1) * 8);
@@ -563,6 +614,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.center, center.data(), t.nbox * 16));
   BIE_TRY(up(t.T_m2l, Tm2l.data(), Tm2l.size() * 16));
   BIE_TRY(up(t.T_m2m, Tm2m.data(), Tm2m.size() * 16));
+  BIE_TRY(up(t.fact_out, fact_out.data(), p * 8));
+  BIE_TRY(up(t.fact_in, fact_in.data(), p * 8));
   BIE_TRY(up(t.T_l2l, Tl2l.data(), Tl2l.size() * 16));
   BIE_TRY(up(t.inv_h, inv_h.data(), (L + 1) * 8));
   BIE_TRY(up(t.perm, perm_i.data(), M * 4));
@@ -583,6 +636,51 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   return BIE_OK;
 }
 
+template <int P>
+bool m2l_lds_raised(size_t bytes) {
+  static size_t done = 0;
+  if (bytes <= 65536 || bytes <= done) return true;
+  if (hipFuncSetAttribute((const void *)k_m2l<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes) != hipSuccess)
+    return false;
+  done = bytes;
+  return true;
+}
+
+template <int P>
+int launch_m2l(const FmmTree &t, int nsets, int n2, const double2 *Mexp, double2 *Lexp,
+               hipStream_t s) {
+  const size_t lds = (size_t)80 * P * sizeof(double2);
+  if (!m2l_lds_raised<P>(lds)) {
+    set_error("fmm: M2L table does not fit in LDS for this order");
+    return BIE_EINVAL;
+  }
+  const long long items = (long long)n2 * nsets;
+  const int blocks = (int)std::min<long long>((items + 3) / 4, 1024);
+  hipLaunchKernelGGL(k_m2l<P>, dim3(blocks), dim3(256), lds, s, P, t.nbox, t.level_off[2], n2,
+                     nsets, t.m2l_ptr, t.m2l_src, t.m2l_off, t.box_level, t.inv_h, t.fact_out,
+                     t.T_m2l, Mexp, Lexp);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int m2l_dispatch(int p, const FmmTree &t, int nsets, int n2, const double2 *Mexp, double2 *Lexp,
+                 hipStream_t s) {
+  switch (p) {
+    case 8: return launch_m2l<8>(t, nsets, n2, Mexp, Lexp, s);
+    case 16: return launch_m2l<16>(t, nsets, n2, Mexp, Lexp, s);
+    case 24: return launch_m2l<24>(t, nsets, n2, Mexp, Lexp, s);
+    case 32: return launch_m2l<32>(t, nsets, n2, Mexp, Lexp, s);
+    case 40: return launch_m2l<40>(t, nsets, n2, Mexp, Lexp, s);
+    case 48: return launch_m2l<48>(t, nsets, n2, Mexp, Lexp, s);
+    case 56: return launch_m2l<56>(t, nsets, n2, Mexp, Lexp, s);
+    case 64: return launch_m2l<64>(t, nsets, n2, Mexp, Lexp, s);
+    default:
+      set_error("fmm: internal order not a multiple of 8");
+      return BIE_EINVAL;
+  }
+}
+
 }  // namespace
 
 int fmm_current_order() { return 0; }
@@ -592,7 +690,7 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
                   hipStream_t s, int order, int leaf) {
   int p = order > 0 ? order : 40;
   if (precision == BIE_MIXED) p = std::max(8, (p * 11 + 19) / 20);  // about sqrt of the accuracy
-  p = std::min(p, kMaxP);
+  p = std::min((p + 7) / 8 * 8, kMaxP);  // expansions use a multiple of 8 terms (rounded up)
   if (leaf <= 0) leaf = 64;
   if (!g->fmm) g->fmm = new FmmPlan();
   FmmTree *&tp = g->fmm->trees[p];
@@ -618,7 +716,7 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q);
   const double ih_leaf = (double)(1 << t.L) / t.size;
   hipLaunchKernelGGL(k_p2m, dim3(t.nleaf, nsets), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
-                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, Mexp);
+                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
   for (int l = t.L - 1; l >= 2; --l) {
     const int nb = t.level_off[l + 1] - t.level_off[l];
     hipLaunchKernelGGL(k_m2m, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l], t.child,
@@ -628,8 +726,7 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   const int n2 = t.nbox - off2;
   if (n2 > 0) {
     ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)p * p);
-    hipLaunchKernelGGL(k_m2l, dim3(n2, nsets), dim3(64), 0, s, p, t.nbox, off2, t.m2l_ptr,
-                       t.m2l_src, t.m2l_off, t.box_level, t.inv_h, t.T_m2l, Mexp, Lexp);
+    BIE_TRY(m2l_dispatch(p, t, nsets, n2, Mexp, Lexp, s));
   }
   for (int l = 2; l < t.L; ++l) {
     const int nb = t.level_off[l + 2] - t.level_off[l + 1];
