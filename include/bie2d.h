@@ -164,6 +164,28 @@ int bie_elastance_matrix(bie_geom *g, double *P, int max_rhs_per_pass, const bie
 int bie_mobility_matrix(bie_geom *g, double *Mmat, int max_rhs_per_pass, const bie_opts *opts,
                         bie_info *info, void *stream);
 
+/* ---- batched solves over several geometries (many systems in one lock-step GMRES) ---------
+ * Every right-hand side of every item is one system; all systems advance together, one batched
+ * operator apply per Arnoldi step, each with its own Hessenberg matrix and convergence test, so
+ * a system's iterates do not depend on the other members of the batch (reductions are per
+ * system and deterministic). Used for P and M of many geometries at once and by the server.
+ * kind: 0 = elastance (in [nrhs][N] charges, out [nrhs][N] potentials), 1 = mobility (in
+ * [nrhs][3N] (F, T), out [nrhs][3N] (v, omega)). in == NULL means the identity block: nrhs must
+ * equal N (kind 0) or 3N (kind 1) and out receives P or M column by column (column-major).
+ * rel_residual (host [nitems] or NULL) receives each item's worst final relative residual. */
+typedef struct bie_batch bie_batch; /* solver workspace reused across calls (opaque) */
+typedef struct {
+  bie_geom *g;
+  int kind;
+  int nrhs;
+  const double *in; /* (device) or NULL */
+  double *out;      /* (device) */
+} bie_batch_item;
+int bie_batch_create(bie_batch **out);
+int bie_batch_destroy(bie_batch *b);
+int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const bie_opts *opts,
+                    bie_info *info, double *rel_residual, void *stream);
+
 /* ---- instrumentation (not a step of the method) ---------------------------------------------
  * When enabled, the library records a pair of HIP events on the launch stream around every
  * launch of the kernel classes below and accumulates, per class, the number of launches, their

@@ -35,6 +35,11 @@ class bie_opts(ctypes.Structure):
                 ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int)]
 
 
+class bie_batch_item(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("kind", ctypes.c_int), ("nrhs", ctypes.c_int),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 class bie_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
@@ -68,6 +73,9 @@ _SIGS = {
                             ctypes.POINTER(bie_info), _P], _I),
     "bie_elastance_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
     "bie_mobility_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
+    "bie_batch_create": ([ctypes.POINTER(_P)], _I),
+    "bie_batch_destroy": ([_P], _I),
+    "bie_batch_solve": ([_P, _I, _P, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P, _P], _I),
     "bie_profile_enable": ([_I], _I),
     "bie_profile_read": ([_I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_longlong)], _I),
@@ -305,3 +313,52 @@ def bie_elastance_matrix(g, max_rhs=0, opts=None):
 
 def bie_mobility_matrix(g, max_rhs=0, opts=None):
     return _matrix(lib().bie_mobility_matrix, g, 3 * g.N, max_rhs, opts)
+
+
+class Batch:
+    """Owns a bie_batch (solver workspace reused across batched solves)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().bie_batch_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bie_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bie_batch_solve(batch, items, opts=None, allow_noconv=False):
+    """items: list of (Geometry, kind, input tensor [nrhs, width] or None for the identity
+    block). Returns (outputs, info, per-item worst relative residual); for identity items the
+    output is the matrix P (kind 0) or M (kind 1)."""
+    torch = _torch()
+    arr = (bie_batch_item * len(items))()
+    outs = []
+    for k, (g, kind, inp) in enumerate(items):
+        width = g.N if kind == 0 else 3 * g.N
+        nrhs = width if inp is None else _rows(inp, width)
+        out = torch.empty(nrhs, width, dtype=torch.float64, device=g.device)
+        outs.append(out)
+        arr[k].g = g.handle
+        arr[k].kind = kind
+        arr[k].nrhs = nrhs
+        arr[k].in_ = None if inp is None else _dptr(inp, width, "input").value
+        arr[k].out = _dptr(out).value
+    info = bie_info()
+    rel = np.zeros(len(items))
+    o = opts if opts is not None else default_opts()
+    code = lib().bie_batch_solve(batch.handle, len(items), ctypes.cast(arr, ctypes.c_void_p),
+                                 ctypes.byref(o), ctypes.byref(info),
+                                 rel.ctypes.data_as(ctypes.c_void_p), _stream())
+    if not (code == BIE_OK or (allow_noconv and code == BIE_ENOCONV)):
+        _check(code)
+    res = [o_.t().contiguous() if it[2] is None else o_ for o_, it in zip(outs, items)]
+    return res, info.as_dict(), rel

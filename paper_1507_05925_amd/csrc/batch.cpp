@@ -1,0 +1,147 @@
+// Batched solves over several geometries: each (item, rhs) is one system of the segmented GMRES
+// (gmres.cpp); one Arnoldi step applies the operator of every geometry to its systems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct bie_batch {
+  bie::SolverMem sm;
+  bie::Segments seg;
+  bie::DevBuf flat;  // incident densities, rhs, solutions [Ntot] each
+  bie::DevBuf ident; // identity blocks
+};
+
+namespace bie {
+namespace {
+
+__global__ void k_identity(int n, int cols, int col0, double *out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);  // row r of the block = rhs r
+  out[t] = (c == col0 + r) ? 1.0 : 0.0;
+}
+
+}  // namespace
+}  // namespace bie
+
+using namespace bie;
+
+extern "C" {
+
+int bie_batch_create(bie_batch **out) {
+  if (!out) {
+    set_error("bie_batch_create: NULL out");
+    return BIE_EINVAL;
+  }
+  *out = new (std::nothrow) bie_batch();
+  if (!*out) {
+    set_error("host allocation failed");
+    return BIE_ENOMEM;
+  }
+  return BIE_OK;
+}
+
+int bie_batch_destroy(bie_batch *b) {
+  if (!b) return BIE_OK;
+  (void)hipDeviceSynchronize();
+  b->sm.release();
+  b->seg.buf.release();
+  b->flat.release();
+  b->ident.release();
+  delete b;
+  return BIE_OK;
+}
+
+int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const bie_opts *opts,
+                    bie_info *info, double *rel_residual, void *stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!b || nitems < 1 || !items) {
+    set_error("bie_batch_solve: need a batch, nitems >= 1 and items");
+    return BIE_EINVAL;
+  }
+  bie_opts o;
+  if (opts) o = *opts; else bie_default_opts(&o);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<long long> lens, item_off(nitems + 1, 0), in_off(nitems + 1, 0);
+  long long pairs = 0;
+  for (int i = 0; i < nitems; ++i) {
+    const bie_batch_item &it = items[i];
+    if (!it.g || (it.kind != 0 && it.kind != 1) || it.nrhs < 1 || !it.out) {
+      set_error("bie_batch_solve: item " + std::to_string(i) + " is invalid");
+      return BIE_EINVAL;
+    }
+    const int cols = it.kind == 0 ? it.g->N : 3 * it.g->N;
+    if (!it.in && it.nrhs != cols) {
+      set_error("bie_batch_solve: identity block of item " + std::to_string(i) +
+                " needs nrhs = " + std::to_string(cols));
+      return BIE_EINVAL;
+    }
+    const long long n = it.kind == 0 ? it.g->M : 2LL * it.g->M;
+    for (int r = 0; r < it.nrhs; ++r) lens.push_back(n);
+    item_off[i + 1] = item_off[i] + n * it.nrhs;
+    in_off[i + 1] = in_off[i] + (long long)cols * (it.in ? 0 : it.nrhs);
+    pairs += (long long)it.nrhs * it.g->M * (long long)it.g->M;
+    it.g->fmm_order = o.fmm_order;
+    it.g->fmm_leaf = o.fmm_leaf;
+  }
+  const long long Ntot = item_off[nitems];
+  BIE_TRY(b->seg.build(lens, s));
+  BIE_TRY(b->flat.reserve(3 * (size_t)Ntot * sizeof(double)));
+  double *dens = b->flat.as<double>(), *f = dens + Ntot, *mu = f + Ntot;
+  if (in_off[nitems] > 0) BIE_TRY(b->ident.reserve((size_t)in_off[nitems] * sizeof(double)));
+  // incident densities and right-hand sides, per item
+  for (int i = 0; i < nitems; ++i) {
+    const bie_batch_item &it = items[i];
+    const double *in = it.in;
+    if (!in) {
+      const int cols = it.kind == 0 ? it.g->N : 3 * it.g->N;
+      double *id = b->ident.as<double>() + in_off[i];
+      const long long tot = (long long)cols * it.nrhs;
+      hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                         it.nrhs, cols, 0, id);
+      BIE_HIP_CHECK(hipGetLastError());
+      in = id;
+    }
+    BIE_TRY(incident_density(it.g, it.kind, it.nrhs, in, dens + item_off[i], s));
+    BIE_TRY(apply_operator(it.g, it.kind, BIE_FP64, o.method, 0, -1.0, it.nrhs, dens + item_off[i],
+                           f + item_off[i], s));
+  }
+  SysSet ss;
+  ss.seg = &b->seg;
+  ss.mem = &b->sm;
+  ss.pairs_per_apply = pairs;
+  const int method = o.method;
+  std::vector<bie_batch_item> its(items, items + nitems);
+  ss.apply = [its, item_off, method](int precision, const double *in, double *out, hipStream_t st) {
+    for (size_t i = 0; i < its.size(); ++i)
+      BIE_TRY(apply_operator(its[i].g, its[i].kind, precision, method, 1, 1.0, its[i].nrhs,
+                             in + item_off[i], out + item_off[i], st));
+    return BIE_OK;
+  };
+  std::vector<double> rel;
+  bie_info inf{};
+  int rc = solve_systems(ss, o, f, mu, rel, &inf, s);
+  if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+  BIE_TRY(vec_axpby(Ntot, 1.0, mu, 1.0, dens, s));
+  for (int i = 0; i < nitems; ++i)
+    BIE_TRY(read_off(items[i].g, items[i].kind, items[i].nrhs, dens + item_off[i], items[i].out, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  if (rel_residual) {
+    size_t k = 0;
+    for (int i = 0; i < nitems; ++i) {
+      double w = 0.0;
+      for (int r = 0; r < items[i].nrhs; ++r) w = std::max(w, rel[k++]);
+      rel_residual[i] = w;
+    }
+  }
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,14 +1,14 @@
-// float64 vector kernels for the Arnoldi process (classical Gram-Schmidt, twice).
-// All reductions are two-stage with a fixed summation order, so results are bitwise
-// reproducible run to run. Batched over nrhs independent vectors.
+// float64 vector kernels for the Arnoldi process over a set of independent systems ("segments")
+// of possibly different lengths, stored back to back in flat vectors of Ntot entries. Work is
+// cut into chunks that never straddle two systems; reductions are two-stage (per chunk, then per
+// system in chunk order), so every result is bitwise reproducible run to run and independent of
+// which other systems share the batch.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
 
 namespace bie {
 namespace {
-
-constexpr int kDotBlocks = 128;  // first-stage blocks per rhs (upper bound)
 
 __device__ inline double block_sum(double v, double *sh) {
 #pragma unroll
@@ -22,64 +22,63 @@ __device__ inline double block_sum(double v, double *sh) {
   return t;
 }
 
-// scratch[(r * nvec + l) * nblk + blk] = partial of <V_l, w> over this block's range
-__global__ __launch_bounds__(kBlock) void k_dots_stage1(int n, int nvec, int nblk,
-                                                       const double *__restrict__ V,
-                                                       long long vs_r, long long vs_v,
-                                                       const double *__restrict__ w, long long ws,
-                                                       double *__restrict__ scratch) {
+// partial[l * C + c] = <V_l, w> over chunk c (V_l = V + l * vstride)
+__global__ __launch_bounds__(kBlock) void k_dots_stage1(int nvec, int C, const long long *__restrict__ c0,
+                                                       const long long *__restrict__ c1,
+                                                       const double *__restrict__ V, long long vstride,
+                                                       const double *__restrict__ w,
+                                                       double *__restrict__ partial) {
   __shared__ double sh[4];
-  const int blk = blockIdx.x, r = blockIdx.y;
-  const long long chunk = ((long long)n + nblk - 1) / nblk;
-  const long long i0 = blk * chunk;
-  const long long i1 = i0 + chunk < n ? i0 + chunk : n;
-  const double *wr = w + r * ws;
+  const int c = blockIdx.x;
+  const long long i0 = c0[c], i1 = c1[c];
   for (int l = 0; l < nvec; ++l) {
-    const double *v = V + r * vs_r + l * vs_v;
+    const double *v = V + l * vstride;
     double acc = 0.0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) acc = fma(v[i], wr[i], acc);
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) acc = fma(v[i], w[i], acc);
     const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) scratch[((long long)r * nvec + l) * nblk + blk] = t;
+    if (threadIdx.x == 0) partial[(long long)l * C + c] = t;
   }
 }
 
-__global__ __launch_bounds__(64) void k_dots_stage2(int nvec, int nblk,
-                                                   const double *__restrict__ scratch,
-                                                   double *__restrict__ h, long long hs,
-                                                   int do_sqrt) {
-  const int l = blockIdx.x, r = blockIdx.y;
-  const double *p = scratch + ((long long)r * nvec + l) * nblk;
+// h[s * hs + l] = sum over the chunks of system s (in order); sqrt for norms
+__global__ __launch_bounds__(64) void k_dots_stage2(int C, const int *__restrict__ sys_chunk,
+                                                   const double *__restrict__ partial,
+                                                   double *__restrict__ h, long long hs, int do_sqrt) {
+  const int l = blockIdx.x, s = blockIdx.y;
+  const int a = sys_chunk[s], b = sys_chunk[s + 1];
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) acc += p[b];
+  for (int c = a + threadIdx.x; c < b; c += 64) acc += partial[(long long)l * C + c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (threadIdx.x == 0) h[r * hs + l] = do_sqrt ? sqrt(acc) : acc;
+  if (threadIdx.x == 0) h[s * hs + l] = do_sqrt ? sqrt(acc) : acc;
 }
 
-// w_r += sign * sum_l V_{r,l} h_{r,l}
-__global__ __launch_bounds__(kBlock) void k_combination(int n, int nvec,
-                                                       const double *__restrict__ V,
-                                                       long long vs_r, long long vs_v,
+// w += sign * sum_l V_l h[s][l] on each chunk (s = system of the chunk)
+__global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__restrict__ csys,
+                                                       const long long *__restrict__ c0,
+                                                       const long long *__restrict__ c1,
+                                                       const double *__restrict__ V, long long vstride,
                                                        const double *__restrict__ h, long long hs,
-                                                       double *__restrict__ w, long long ws,
-                                                       double sign) {
-  const int r = blockIdx.y;
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double *hr = h + r * hs;
-  const double *v = V + r * vs_r + i;
-  double acc = 0.0;
-  for (int l = 0; l < nvec; ++l) acc = fma(v[l * vs_v], hr[l], acc);
-  w[r * ws + i] += sign * acc;
+                                                       double *__restrict__ w, double sign) {
+  const int c = blockIdx.x;
+  const int s = csys[c];
+  const double *hr = h + s * hs;
+  for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) {
+    double acc = 0.0;
+    for (int l = 0; l < nvec; ++l) acc = fma(V[l * vstride + i], hr[l], acc);
+    w[i] += sign * acc;
+  }
 }
 
-__global__ void k_scale_to(int n, const double *__restrict__ w, long long ws,
-                           const double *__restrict__ den, double *__restrict__ v, long long vs) {
-  const int r = blockIdx.y;
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double d = den[r];
-  v[r * vs + i] = d > 0.0 ? w[r * ws + i] / d : 0.0;
+__global__ __launch_bounds__(kBlock) void k_scale_to(const int *__restrict__ csys,
+                                                    const long long *__restrict__ c0,
+                                                    const long long *__restrict__ c1,
+                                                    const double *__restrict__ w,
+                                                    const double *__restrict__ den,
+                                                    double *__restrict__ v) {
+  const int c = blockIdx.x;
+  const double d = den[csys[c]];
+  for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) v[i] = d > 0.0 ? w[i] / d : 0.0;
 }
 
 __global__ void k_axpby(long long total, double a, const double *__restrict__ x, double b,
@@ -89,67 +88,96 @@ __global__ void k_axpby(long long total, double a, const double *__restrict__ x,
 }
 
 __global__ void k_add_h(int cnt, long long hs, const double *__restrict__ h1, double *__restrict__ h2) {
-  const int r = blockIdx.x;
-  for (int l = threadIdx.x; l < cnt; l += blockDim.x) h2[r * hs + l] += h1[r * hs + l];
-}
-
-int dot_blocks(int n) {
-  int b = (n + 4 * kBlock - 1) / (4 * kBlock);
-  return b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b);
+  const int s = blockIdx.x;
+  for (int l = threadIdx.x; l < cnt; l += blockDim.x) h2[s * hs + l] += h1[s * hs + l];
 }
 
 }  // namespace
 
-int vec_dots(int nrhs, int n, int nvec, const double *V, long long vs_r, long long vs_v,
-             const double *w, long long ws, double *h, long long hs, double *scratch,
-             hipStream_t s) {
-  const int nblk = dot_blocks(n);
-  hipLaunchKernelGGL(k_dots_stage1, dim3(nblk, nrhs), dim3(kBlock), 0, s, n, nvec, nblk, V, vs_r,
-                     vs_v, w, ws, scratch);
-  hipLaunchKernelGGL(k_dots_stage2, dim3(nvec, nrhs), dim3(64), 0, s, nvec, nblk, scratch, h, hs, 0);
+int seg_dots(const Segments &sg, int nvec, const double *V, long long vstride, const double *w,
+             double *h, long long hs, double *scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.C, sg.c0, sg.c1, V,
+                     vstride, w, scratch);
+  hipLaunchKernelGGL(k_dots_stage2, dim3(nvec, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk, scratch,
+                     h, hs, 0);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
-int vec_sub_combination(int nrhs, int n, int nvec, const double *V, long long vs_r, long long vs_v,
-                        const double *h, long long hs, double *w, long long ws, double sign,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_combination, dim3((n + kBlock - 1) / kBlock, nrhs), dim3(kBlock), 0, s, n,
-                     nvec, V, vs_r, vs_v, h, hs, w, ws, sign);
+int seg_combination(const Segments &sg, int nvec, const double *V, long long vstride,
+                    const double *h, long long hs, double *w, double sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_combination, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0, sg.c1, V,
+                     vstride, h, hs, w, sign);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
-int vec_nrm2(int nrhs, int n, const double *w, long long ws, double *out, double *scratch,
-             hipStream_t s) {
-  const int nblk = dot_blocks(n);
-  hipLaunchKernelGGL(k_dots_stage1, dim3(nblk, nrhs), dim3(kBlock), 0, s, n, 1, nblk, w, ws, 0LL,
-                     w, ws, scratch);
-  hipLaunchKernelGGL(k_dots_stage2, dim3(1, nrhs), dim3(64), 0, s, 1, nblk, scratch, out, 1LL, 1);
+int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C), dim3(kBlock), 0, s, 1, sg.C, sg.c0, sg.c1, w, 0LL,
+                     w, scratch);
+  hipLaunchKernelGGL(k_dots_stage2, dim3(1, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk, scratch, out,
+                     1LL, 1);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
-int vec_scale_to(int nrhs, int n, const double *w, long long ws, const double *den, double *v,
-                 long long vs, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_to, dim3((n + kBlock - 1) / kBlock, nrhs), dim3(kBlock), 0, s, n, w,
-                     ws, den, v, vs);
+int seg_scale_to(const Segments &sg, const double *w, const double *den, double *v, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_to, dim3(sg.C), dim3(kBlock), 0, s, sg.csys, sg.c0, sg.c1, w, den, v);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
-int vec_axpby(int nrhs, int n, double a, const double *x, double b, double *y, hipStream_t s) {
-  const long long tot = (long long)nrhs * n;
-  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     tot, a, x, b, y);
+int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     total, a, x, b, y);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
-int vec_add_h(int nrhs, int n, const double *h1, double *h2, int cnt, long long hs, hipStream_t s) {
-  (void)n;
-  hipLaunchKernelGGL(k_add_h, dim3(nrhs), dim3(64), 0, s, cnt, hs, h1, h2);
+int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_h, dim3(S), dim3(64), 0, s, cnt, hs, h1, h2);
   BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+// Chunk list of systems with the given lengths (flat, back to back).
+int Segments::build(const std::vector<long long> &lens, hipStream_t s) {
+  S = (int)lens.size();
+  std::vector<long long> a, b;
+  std::vector<int> cs, sc(1, 0);
+  long long off = 0;
+  h_off.assign(S + 1, 0);
+  for (int k = 0; k < S; ++k) {
+    const long long n = lens[k];
+    const long long per = n > 64 * 1024 ? 4096 : 1024;  // chunk length
+    for (long long i = 0; i < n; i += per) {
+      a.push_back(off + i);
+      b.push_back(off + std::min(n, i + per));
+      cs.push_back(k);
+    }
+    if (n == 0) {  // keep one empty chunk so stage 2 sees the system
+      a.push_back(off);
+      b.push_back(off);
+      cs.push_back(k);
+    }
+    sc.push_back((int)cs.size());
+    off += n;
+    h_off[k + 1] = off;
+  }
+  C = (int)cs.size();
+  Ntot = off;
+  const size_t bytes = (size_t)C * (8 + 8 + 4) + (S + 1) * 4 + 256;
+  BIE_TRY(buf.reserve(bytes));
+  char *q = buf.as<char>();
+  c0 = (long long *)q;
+  c1 = c0 + C;
+  csys = (int *)(c1 + C);
+  sys_chunk = csys + C;
+  BIE_HIP_CHECK(hipMemcpyAsync(c0, a.data(), C * 8, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(c1, b.data(), C * 8, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(csys, cs.data(), C * 4, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(sys_chunk, sc.data(), (S + 1) * 4, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
   return BIE_OK;
 }
 

@@ -226,10 +226,9 @@ int bie_geom_destroy(bie_geom *g) {
   hipDeviceSynchronize();
   g->arena.release();
   g->ws_apply.release();
-  g->ws_solve.release();
-  g->ws_small.release();
+  g->sm.release();
+  g->seg.buf.release();
   g->ws_out.release();
-  if (g->h_pinned) hipHostFree(g->h_pinned);
   if (g->fmm) fmm_destroy(g->fmm);
   delete g;
   return BIE_OK;
@@ -244,7 +243,7 @@ int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M) {
 
 long long bie_geom_device_bytes(const bie_geom *g) {
   if (!g) return 0;
-  return (long long)(g->arena.bytes + g->ws_apply.bytes + g->ws_solve.bytes + g->ws_small.bytes +
+  return (long long)(g->arena.bytes + g->ws_apply.bytes + g->sm.big.bytes + g->sm.small.bytes +
                      g->ws_out.bytes);
 }
 
@@ -368,7 +367,7 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   BIE_TRY(apply_operator(g, kind, BIE_FP64, o.method, 0, -1.0, nrhs, dens, f, s));
   int rc = solve_system(g, kind, o, nrhs, f, mu, info, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
-  BIE_TRY(vec_axpby(nrhs, (int)len, 1.0, mu, 1.0, dens, s));  // dens = mu + incident
+  BIE_TRY(vec_axpby((long long)nrhs * len, 1.0, mu, 1.0, dens, s));  // dens = mu + incident
   BIE_TRY(read_off(g, kind, nrhs, dens, res, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   if (info) {

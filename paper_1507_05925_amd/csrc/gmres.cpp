@@ -1,12 +1,12 @@
-// Restarted GMRES in float64 (classical Gram-Schmidt applied twice), batched over nrhs
-// independent right-hand sides that share one operator apply per Arnoldi step, and float64
-// iterative refinement around a float32 far-field apply (BIE_MIXED).
+// Restarted GMRES in float64 (classical Gram-Schmidt applied twice) over a set of independent
+// systems that advance in lock step and share one batched operator apply per Arnoldi step, and
+// float64 iterative refinement around a float32 far-field apply (BIE_MIXED).
 //
-// Device: Krylov basis V [m+1][nrhs][n], operator applies, dot products, updates. Host: the
-// (m+1) x m Hessenberg columns (read back once per step), Givens rotations, the triangular
-// solve; the true residual ||f - A x|| / ||f|| with the float64 operator decides convergence
-// at the end of every cycle. The paper iterates GMRES to a relative residual of 1e-6 with
-// unstated restart details; x0 = 0 and CGS2 here are this library's choices.
+// Device: Krylov basis V [m+1][Ntot] (all systems back to back), applies, dot products, updates.
+// Host: one (m+1) x m Hessenberg matrix per system (its new column is read back once per step),
+// Givens rotations, triangular solves. The true residual ||f - A x|| / ||f|| with the float64
+// operator decides convergence at the end of every cycle. The paper iterates GMRES to a
+// relative residual of 1e-6 with unstated restart details; x0 = 0 and CGS2 are choices made here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,10 +22,6 @@
 namespace bie {
 namespace {
 
-struct Op {
-  int kind, precision, method;
-};
-
 // BIE_VERBOSE=1: one line per GMRES cycle and refinement step; =2: also every Arnoldi step.
 int verbosity() {
   static int v = [] {
@@ -40,137 +36,131 @@ struct Stats {
   long long pairs = 0;
 };
 
-int apply(bie_geom *g, const Op &op, int nrhs, const double *in, double *out, Stats &st,
-          hipStream_t s) {
-  BIE_TRY(apply_operator(g, op.kind, op.precision, op.method, 1, 1.0, nrhs, in, out, s));
-  if (op.precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;
-  st.pairs += (long long)nrhs * g->M * (long long)g->M;
+int apply(SysSet &ss, int precision, const double *in, double *out, Stats &st, hipStream_t s) {
+  BIE_TRY(ss.apply(precision, in, out, s));
+  if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;
+  st.pairs += ss.pairs_per_apply;
   return BIE_OK;
 }
 
-// Host read of `count` doubles from device (stream-ordered).
-int read_host(bie_geom *g, const double *dev, size_t count, std::vector<double> &dst, hipStream_t s) {
-  BIE_TRY(ensure_pinned(g, count * sizeof(double)));
-  BIE_HIP_CHECK(hipMemcpyAsync(g->h_pinned, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+int read_host(SolverMem &mem, const double *dev, size_t count, std::vector<double> &dst,
+              hipStream_t s) {
+  BIE_TRY(mem.ensure_pinned(count * sizeof(double)));
+  BIE_HIP_CHECK(hipMemcpyAsync(mem.pinned, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
-  dst.assign(g->h_pinned, g->h_pinned + count);
+  dst.assign(mem.pinned, mem.pinned + count);
   return BIE_OK;
 }
 
-int write_dev(bie_geom *g, double *dev, const std::vector<double> &src, hipStream_t s) {
-  BIE_TRY(ensure_pinned(g, src.size() * sizeof(double)));
-  BIE_HIP_CHECK(hipStreamSynchronize(s));  // pinned buffer may still feed an earlier copy
-  std::memcpy(g->h_pinned, src.data(), src.size() * sizeof(double));
-  BIE_HIP_CHECK(hipMemcpyAsync(dev, g->h_pinned, src.size() * sizeof(double), hipMemcpyHostToDevice, s));
+int write_dev(SolverMem &mem, double *dev, const std::vector<double> &src, hipStream_t s) {
+  BIE_TRY(mem.ensure_pinned(src.size() * sizeof(double)));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));  // the pinned buffer may still feed an earlier copy
+  std::memcpy(mem.pinned, src.data(), src.size() * sizeof(double));
+  BIE_HIP_CHECK(hipMemcpyAsync(dev, mem.pinned, src.size() * sizeof(double), hipMemcpyHostToDevice, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   return BIE_OK;
 }
 
-// Workspace carved from g->ws_solve / g->ws_small.
 struct Work {
-  double *V, *w, *r, *t;       // V [(m+1)][nrhs][n]; w, r, t [nrhs][n]
-  double *h1, *h2, *nrm, *y;   // [nrhs][m+2], [nrhs][m+2], [nrhs], [nrhs][m+1]
-  double *scratch;             // dot partials [nrhs][m+2][128]
+  double *V, *w, *r;          // V [(m+1)][Ntot]; w, r [Ntot]
+  double *h1, *h2, *nrm, *y;  // [S][m+2] x3, [S]
+  double *scratch;            // dot partials [(m+2)][C]
 };
 
-int make_work(bie_geom *g, int nrhs, int n, int m, Work &wk, int extra_vectors, double **extra) {
-  const size_t nv = (size_t)nrhs * n;
-  const size_t big = ((size_t)(m + 1) + 3 + extra_vectors) * nv * sizeof(double);
-  BIE_TRY(g->ws_solve.reserve(big));
-  double *p = g->ws_solve.as<double>();
+int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
+  const size_t N = (size_t)ss.seg->Ntot;
+  const int S = ss.seg->S;
+  BIE_TRY(ss.mem->big.reserve(((size_t)(m + 1) + 2 + extra_vectors) * N * sizeof(double) + 64));
+  double *p = ss.mem->big.as<double>();
   wk.V = p;
-  p += (size_t)(m + 1) * nv;
+  p += (size_t)(m + 1) * N;
   wk.w = p;
-  p += nv;
+  p += N;
   wk.r = p;
-  p += nv;
-  wk.t = p;
-  p += nv;
+  p += N;
   for (int e = 0; e < extra_vectors; ++e) {
     extra[e] = p;
-    p += nv;
+    p += N;
   }
   const size_t hs = (size_t)m + 2;
-  const size_t small = (3 * hs * nrhs + nrhs + (size_t)nrhs * (m + 2) * 128) * sizeof(double);
-  BIE_TRY(g->ws_small.reserve(small));
-  double *q = g->ws_small.as<double>();
+  BIE_TRY(ss.mem->small.reserve((3 * hs * S + S + hs * (size_t)ss.seg->C) * sizeof(double) + 64));
+  double *q = ss.mem->small.as<double>();
   wk.h1 = q;
-  q += hs * nrhs;
+  q += hs * S;
   wk.h2 = q;
-  q += hs * nrhs;
+  q += hs * S;
   wk.y = q;
-  q += hs * nrhs;
+  q += hs * S;
   wk.nrm = q;
-  q += nrhs;
+  q += S;
   wk.scratch = q;
   return BIE_OK;
 }
 
-// GMRES(m) on A x = f for nrhs systems. x [nrhs][n] holds the initial guess on entry (x0 = 0 if
-// x_is_zero) and the iterate on exit. conv[r] reports whether rhs r reached tol.
-int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x, bool x_is_zero,
-          double tol, int m, int max_iter, Work &wk, Stats &st, std::vector<double> &relres,
-          std::vector<int> &conv, hipStream_t s) {
-  const long long vs_v = (long long)nrhs * n;  // stride between Krylov vectors
-  const long long vs_r = n;                    // stride between rhs inside one Krylov vector
+// GMRES(m) on A x = f for every system. x holds the iterate on exit (x0 = 0 if x_is_zero).
+int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
+          const std::vector<double> &tol, int m, int max_iter, Work &wk, Stats &st,
+          std::vector<double> &relres, std::vector<int> &conv, hipStream_t s) {
+  const Segments &sg = *ss.seg;
+  SolverMem &mem = *ss.mem;
+  const int S = sg.S;
+  const long long N = sg.Ntot;
   const long long hs = m + 2;
-  std::vector<double> fnorm, beta, hh1, hh2, hn;
-  if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * nrhs * n, s));
-  BIE_TRY(vec_nrm2(nrhs, n, f, n, wk.nrm, wk.scratch, s));
-  BIE_TRY(read_host(g, wk.nrm, nrhs, fnorm, s));
-  relres.assign(nrhs, 0.0);
-  conv.assign(nrhs, 0);
+  std::vector<double> fnorm, beta, hh2, hn;
+  if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+  BIE_TRY(seg_nrm2(sg, f, wk.nrm, wk.scratch, s));
+  BIE_TRY(read_host(mem, wk.nrm, S, fnorm, s));
+  relres.assign(S, 0.0);
+  conv.assign(S, 0);
   bool first = true;
-  std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
-      gv((size_t)nrhs * (m + 1));
+  std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m),
+      gv((size_t)S * (m + 1));
   while (true) {
-    // r = f - A x
     if (first && x_is_zero) {
-      BIE_HIP_CHECK(hipMemcpyAsync(wk.r, f, sizeof(double) * nrhs * n, hipMemcpyDeviceToDevice, s));
+      BIE_HIP_CHECK(hipMemcpyAsync(wk.r, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     } else {
-      BIE_TRY(apply(g, op, nrhs, x, wk.r, st, s));
-      BIE_TRY(vec_axpby(nrhs, n, 1.0, f, -1.0, wk.r, s));
+      BIE_TRY(apply(ss, precision, x, wk.r, st, s));
+      BIE_TRY(vec_axpby(N, 1.0, f, -1.0, wk.r, s));
     }
     first = false;
-    BIE_TRY(vec_nrm2(nrhs, n, wk.r, n, wk.nrm, wk.scratch, s));
-    BIE_TRY(read_host(g, wk.nrm, nrhs, beta, s));
-    std::vector<int> active(nrhs, 0);
+    BIE_TRY(seg_nrm2(sg, wk.r, wk.nrm, wk.scratch, s));
+    BIE_TRY(read_host(mem, wk.nrm, S, beta, s));
+    std::vector<int> active(S, 0);
     int nact = 0;
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < S; ++r) {
       relres[r] = fnorm[r] > 0.0 ? beta[r] / fnorm[r] : 0.0;
-      conv[r] = relres[r] <= tol;
+      conv[r] = relres[r] <= tol[r];
       active[r] = !conv[r];
       nact += active[r];
     }
     if (verbosity() >= 1)
-      std::fprintf(stderr, "[bie] gmres prec=%d cycle start: iters=%d true rel res[0]=%.3e\n",
-                   op.precision, st.iters, relres[0]);
+      std::fprintf(stderr, "[bie] gmres prec=%d cycle start: iters=%d active=%d true rel res[0]=%.3e\n",
+                   precision, st.iters, nact, relres[0]);
     if (nact == 0 || st.iters >= max_iter) break;
-    // V_0 = r / beta (inactive rhs: zero vector)
-    for (int r = 0; r < nrhs; ++r)
+    for (int r = 0; r < S; ++r)
       if (!active[r]) beta[r] = 0.0;
-    BIE_TRY(write_dev(g, wk.nrm, beta, s));
-    BIE_TRY(vec_scale_to(nrhs, n, wk.r, n, wk.nrm, wk.V, n, s));
+    BIE_TRY(write_dev(mem, wk.nrm, beta, s));
+    BIE_TRY(seg_scale_to(sg, wk.r, wk.nrm, wk.V, s));
     std::fill(gv.begin(), gv.end(), 0.0);
-    for (int r = 0; r < nrhs; ++r) gv[(size_t)r * (m + 1)] = beta[r];
-    std::vector<int> jdone(nrhs, -1);
+    for (int r = 0; r < S; ++r) gv[(size_t)r * (m + 1)] = beta[r];
+    std::vector<int> jdone(S, -1);
     int jend = -1;
     for (int j = 0; j < m; ++j) {
-      double *Vj = wk.V + (size_t)j * vs_v;
-      double *Vj1 = wk.V + (size_t)(j + 1) * vs_v;
-      BIE_TRY(apply(g, op, nrhs, Vj, wk.w, st, s));
+      double *Vj = wk.V + (size_t)j * N;
+      double *Vj1 = wk.V + (size_t)(j + 1) * N;
+      BIE_TRY(apply(ss, precision, Vj, wk.w, st, s));
       st.iters += 1;
-      BIE_TRY(vec_dots(nrhs, n, j + 1, wk.V, vs_r, vs_v, wk.w, n, wk.h1, hs, wk.scratch, s));
-      BIE_TRY(vec_sub_combination(nrhs, n, j + 1, wk.V, vs_r, vs_v, wk.h1, hs, wk.w, n, -1.0, s));
-      BIE_TRY(vec_dots(nrhs, n, j + 1, wk.V, vs_r, vs_v, wk.w, n, wk.h2, hs, wk.scratch, s));
-      BIE_TRY(vec_sub_combination(nrhs, n, j + 1, wk.V, vs_r, vs_v, wk.h2, hs, wk.w, n, -1.0, s));
-      BIE_TRY(vec_nrm2(nrhs, n, wk.w, n, wk.nrm, wk.scratch, s));
-      BIE_TRY(vec_scale_to(nrhs, n, wk.w, n, wk.nrm, Vj1, n, s));
-      BIE_TRY(vec_add_h(nrhs, n, wk.h1, wk.h2, j + 1, hs, s));
-      BIE_TRY(read_host(g, wk.h2, (size_t)nrhs * hs, hh2, s));
-      BIE_TRY(read_host(g, wk.nrm, nrhs, hn, s));
+      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
+      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
+      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h2, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_nrm2(sg, wk.w, wk.nrm, wk.scratch, s));
+      BIE_TRY(seg_scale_to(sg, wk.w, wk.nrm, Vj1, s));
+      BIE_TRY(seg_add_h(S, wk.h1, wk.h2, j + 1, hs, s));
+      BIE_TRY(read_host(mem, wk.h2, (size_t)S * hs, hh2, s));
+      BIE_TRY(read_host(mem, wk.nrm, S, hn, s));
       bool all_done = true;
-      for (int r = 0; r < nrhs; ++r) {
+      for (int r = 0; r < S; ++r) {
         if (!active[r] || jdone[r] >= 0) continue;
         double *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
         double *col = Hc + (size_t)j * (m + 1);
@@ -193,7 +183,7 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
         const double res = std::fabs(gg[j + 1]) / fnorm[r];
         if (verbosity() >= 2 && r == 0)
           std::fprintf(stderr, "[bie]   j=%d est rel res=%.3e hn=%.3e\n", j, res, hn[r]);
-        if (res <= tol || hn[r] == 0.0) jdone[r] = j;
+        if (res <= tol[r] || hn[r] == 0.0) jdone[r] = j;
         else all_done = false;
       }
       jend = j;
@@ -201,8 +191,8 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
     }
     // y = H^{-1} g (upper triangular), x += V y
     const int nv = jend + 1;
-    std::vector<double> yv((size_t)nrhs * hs, 0.0);
-    for (int r = 0; r < nrhs; ++r) {
+    std::vector<double> yv((size_t)S * hs, 0.0);
+    for (int r = 0; r < S; ++r) {
       if (!active[r]) continue;
       const int k = (jdone[r] >= 0 ? jdone[r] : jend) + 1;
       const double *Hc = &H[((size_t)r * (m + 1)) * m];
@@ -215,96 +205,108 @@ int gmres(bie_geom *g, const Op &op, int nrhs, int n, const double *f, double *x
         yr[i] = d != 0.0 ? acc / d : 0.0;
       }
     }
-    BIE_TRY(write_dev(g, wk.y, yv, s));
-    BIE_TRY(vec_sub_combination(nrhs, n, nv, wk.V, vs_r, vs_v, wk.y, hs, x, n, 1.0, s));
+    BIE_TRY(write_dev(mem, wk.y, yv, s));
+    BIE_TRY(seg_combination(sg, nv, wk.V, N, wk.y, hs, x, 1.0, s));
   }
   return BIE_OK;
 }
 
 }  // namespace
 
-int ensure_pinned(bie_geom *g, size_t bytes) {
-  if (g->h_pinned_bytes >= bytes) return BIE_OK;
-  if (g->h_pinned) {
-    BIE_HIP_CHECK(hipHostFree(g->h_pinned));
-    g->h_pinned = nullptr;
-    g->h_pinned_bytes = 0;
+int SolverMem::ensure_pinned(size_t bytes) {
+  if (pinned_bytes >= bytes) return BIE_OK;
+  if (pinned) {
+    BIE_HIP_CHECK(hipHostFree(pinned));
+    pinned = nullptr;
+    pinned_bytes = 0;
   }
   size_t want = std::max<size_t>(bytes, 1 << 16);
-  if (hipHostMalloc((void **)&g->h_pinned, want, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&pinned, want, hipHostMallocDefault) != hipSuccess) {
     set_error("pinned host allocation failed");
     return BIE_ENOMEM;
   }
-  g->h_pinned_bytes = want;
+  pinned_bytes = want;
   return BIE_OK;
 }
 
-// Solves (1/2 I + K + L) x = f (kind 0, n = M) or the Stokes system (kind 1, n = 2M).
-int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const double *f, double *x,
-                 bie_info *info, hipStream_t s) {
-  const int n = kind == 0 ? g->M : 2 * g->M;
+void SolverMem::release() {
+  big.release();
+  small.release();
+  if (pinned) (void)hipHostFree(pinned);
+  pinned = nullptr;
+  pinned_bytes = 0;
+}
+
+// Solves every system of ss to o.tol (relative, float64 operator). relres_out gets the final true
+// relative residual per system.
+int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
+                  std::vector<double> &relres_out, bie_info *info, hipStream_t s) {
   const int m = std::max(1, std::min(o.restart, 1000));
+  const int S = ss.seg->S;
+  const long long N = ss.seg->Ntot;
   Stats st;
   std::vector<double> relres;
   std::vector<int> conv;
   Work wk;
-  double *extra[3] = {nullptr, nullptr, nullptr};
+  double *extra[2] = {nullptr, nullptr};
   const bool mixed = o.precision == BIE_MIXED;
-  BIE_TRY(make_work(g, nrhs, n, m, wk, mixed ? 3 : 0, extra));
-  BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * nrhs * n, s));
-  const Op op64{kind, BIE_FP64, o.method};
+  BIE_TRY(make_work(ss, m, wk, mixed ? 2 : 0, extra));
   int refinements = 0;
   if (!mixed) {
-    BIE_TRY(gmres(g, op64, nrhs, n, f, x, true, o.tol, m, o.max_iter, wk, st, relres, conv, s));
+    BIE_TRY(gmres(ss, BIE_FP64, f, x, true, std::vector<double>(S, o.tol), m, o.max_iter, wk, st,
+                  relres, conv, s));
   } else {
-    // x = 0, r = f; repeat: solve A32 d = r to inner_tol; x += d; r = f - A64 x
-    const Op op32{kind, BIE_MIXED, o.method};
+    // x = 0, r = f; repeat: solve A32 d = r to what the outer tolerance needs; x += d; r = f - A64 x
     double *rr = extra[0], *d = extra[1];
     std::vector<double> fnorm, rn;
-    BIE_TRY(vec_nrm2(nrhs, n, f, n, wk.nrm, wk.scratch, s));
-    BIE_TRY(read_host(g, wk.nrm, nrhs, fnorm, s));
-    BIE_HIP_CHECK(hipMemcpyAsync(rr, f, sizeof(double) * nrhs * n, hipMemcpyDeviceToDevice, s));
-    relres.assign(nrhs, 1.0);
-    conv.assign(nrhs, 0);
+    BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    BIE_TRY(seg_nrm2(*ss.seg, f, wk.nrm, wk.scratch, s));
+    BIE_TRY(read_host(*ss.mem, wk.nrm, S, fnorm, s));
+    BIE_HIP_CHECK(hipMemcpyAsync(rr, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    relres.assign(S, 1.0);
+    conv.assign(S, 0);
     for (int it = 0;; ++it) {
-      BIE_TRY(vec_nrm2(nrhs, n, rr, n, wk.nrm, wk.scratch, s));
-      BIE_TRY(read_host(g, wk.nrm, nrhs, rn, s));
+      BIE_TRY(seg_nrm2(*ss.seg, rr, wk.nrm, wk.scratch, s));
+      BIE_TRY(read_host(*ss.mem, wk.nrm, S, rn, s));
       bool all = true;
-      for (int r = 0; r < nrhs; ++r) {
+      double worst = 0.0;
+      for (int r = 0; r < S; ++r) {
         relres[r] = fnorm[r] > 0.0 ? rn[r] / fnorm[r] : 0.0;
         conv[r] = relres[r] <= o.tol;
         all = all && conv[r];
+        if (!conv[r]) worst = std::max(worst, relres[r]);
       }
       if (verbosity() >= 1)
-        std::fprintf(stderr, "[bie] refinement %d: true rel res[0]=%.3e iters=%d\n", it,
-                     relres[0], st.iters);
+        std::fprintf(stderr, "[bie] refinement %d: worst true rel res=%.3e iters=%d\n", it, worst,
+                     st.iters);
       if (all || it >= o.max_refine || st.iters >= o.max_iter) break;
-      // converged rhs get a zero residual so the inner solve leaves them untouched
-      double worst = 0.0;
-      for (int r = 0; r < nrhs; ++r) {
+      // converged systems get a zero residual so the inner solve leaves them untouched
+      for (int r = 0; r < S; ++r)
         if (conv[r])
-          BIE_HIP_CHECK(hipMemsetAsync(rr + (size_t)r * n, 0, sizeof(double) * n, s));
-        else
-          worst = std::max(worst, relres[r]);
-      }
-      // the inner solve only has to bring the residual to what the outer tolerance needs
-      // (with a margin of 3), never tighter than inner_tol
-      const double itol = std::max(o.inner_tol, o.tol / (3.0 * worst));
+          BIE_HIP_CHECK(hipMemsetAsync(rr + ss.seg->h_off[r], 0,
+                                       sizeof(double) * (ss.seg->h_off[r + 1] - ss.seg->h_off[r]), s));
+      // each inner solve only has to bring its residual to what the outer tolerance needs
+      // (with a margin of 3), never tighter than inner_tol; per system, so that a system's
+      // iterates do not depend on the rest of the batch
+      std::vector<double> itol(S);
+      for (int r = 0; r < S; ++r)
+        itol[r] = conv[r] ? 1.0 : std::max(o.inner_tol, o.tol / (3.0 * relres[r]));
       std::vector<double> irel;
       std::vector<int> iconv;
-      BIE_TRY(gmres(g, op32, nrhs, n, rr, d, true, itol, m, o.max_iter, wk, st, irel, iconv, s));
-      BIE_TRY(vec_axpby(nrhs, n, 1.0, d, 1.0, x, s));
-      BIE_TRY(apply(g, op64, nrhs, x, rr, st, s));
-      BIE_TRY(vec_axpby(nrhs, n, 1.0, f, -1.0, rr, s));
+      BIE_TRY(gmres(ss, BIE_MIXED, rr, d, true, itol, m, o.max_iter, wk, st, irel, iconv, s));
+      BIE_TRY(vec_axpby(N, 1.0, d, 1.0, x, s));
+      BIE_TRY(apply(ss, BIE_FP64, x, rr, st, s));
+      BIE_TRY(vec_axpby(N, 1.0, f, -1.0, rr, s));
       ++refinements;
     }
   }
   bool ok = true;
   double worst = 0.0;
-  for (int r = 0; r < nrhs; ++r) {
+  for (int r = 0; r < S; ++r) {
     ok = ok && conv[r];
     worst = std::max(worst, relres[r]);
   }
+  relres_out = relres;
   if (info) {
     info->iters = st.iters;
     info->refinements = refinements;
@@ -318,6 +320,27 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
     return BIE_ENOCONV;
   }
   return BIE_OK;
+}
+
+// One geometry, nrhs systems of length n = M (kind 0) or 2M (kind 1).
+int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const double *f, double *x,
+                 bie_info *info, hipStream_t s) {
+  const long long n = kind == 0 ? g->M : 2LL * g->M;
+  if (g->seg_nrhs != nrhs || g->seg_len != n) {
+    BIE_TRY(g->seg.build(std::vector<long long>(nrhs, n), s));
+    g->seg_nrhs = nrhs;
+    g->seg_len = n;
+  }
+  SysSet ss;
+  ss.seg = &g->seg;
+  ss.mem = &g->sm;
+  ss.pairs_per_apply = (long long)nrhs * g->M * (long long)g->M;
+  const int method = o.method;
+  ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out, hipStream_t st) {
+    return apply_operator(g, kind, precision, method, 1, 1.0, nrhs, in, out, st);
+  };
+  std::vector<double> rel;
+  return solve_systems(ss, o, f, x, rel, info, s);
 }
 
 }  // namespace bie

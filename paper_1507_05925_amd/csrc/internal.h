@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,34 @@ struct DevBuf {
 
 struct FmmPlan;  // far-field FMM state (fmm.hip)
 
+// Independent systems stored back to back in flat vectors; chunks never straddle two systems.
+struct Segments {
+  int S = 0, C = 0;
+  long long Ntot = 0;
+  std::vector<long long> h_off;  // [S+1] host offsets
+  DevBuf buf;
+  long long *c0 = nullptr, *c1 = nullptr;  // [C] flat chunk ranges
+  int *csys = nullptr, *sys_chunk = nullptr;  // [C] system of chunk, [S+1] chunks of a system
+  int build(const std::vector<long long> &lens, hipStream_t s);
+};
+
+// Krylov workspace and pinned staging of a solver owner (a geometry or a batch).
+struct SolverMem {
+  DevBuf big, small;
+  double *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  int ensure_pinned(size_t bytes);
+  void release();
+};
+
+// A set of systems with one batched apply: out = A in (flat layout of seg).
+struct SysSet {
+  Segments *seg = nullptr;
+  SolverMem *mem = nullptr;
+  long long pairs_per_apply = 0;
+  std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
+};
+
 }  // namespace bie
 
 struct bie_geom {
@@ -67,11 +96,11 @@ struct bie_geom {
   long long far_pairs = 0;    // pairs with distinct bodies: M^2 - sum n_b^2
   // workspaces
   bie::DevBuf ws_apply;   // strengths + far-field partials
-  bie::DevBuf ws_solve;   // Krylov basis and vectors
-  bie::DevBuf ws_small;   // reductions, Hessenberg columns
+  bie::SolverMem sm;      // Krylov basis, vectors, reductions, pinned staging
+  bie::Segments seg;      // chunk list of the current nrhs systems
+  int seg_nrhs = -1;
+  long long seg_len = -1;
   bie::DevBuf ws_out;     // solver outputs (densities, rhs) for solve entry points
-  double *h_pinned = nullptr;  // pinned host staging for small reads
-  size_t h_pinned_bytes = 0;
   bie::FmmPlan *fmm = nullptr;
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box
@@ -88,25 +117,21 @@ int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double
 int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t s);
 int geometry_build(bie_geom *g, const double *curve, const double *interior, hipStream_t s);
 
-// ---- blas.hip: float64 vector kernels used by GMRES ------------------------------------------
-// Batched over nrhs vectors of length n with the given strides (in doubles).
-int vec_dots(int nrhs, int n, int nvec, const double *V, long long vstride_rhs, long long vstride_vec,
-             const double *w, long long wstride, double *h, long long hstride, double *scratch,
-             hipStream_t s);
-int vec_sub_combination(int nrhs, int n, int nvec, const double *V, long long vstride_rhs,
-                        long long vstride_vec, const double *h, long long hstride, double *w,
-                        long long wstride, double sign, hipStream_t s);
-int vec_nrm2(int nrhs, int n, const double *w, long long wstride, double *out, double *scratch,
-             hipStream_t s);
-int vec_scale_to(int nrhs, int n, const double *w, long long wstride, const double *den,
-                 double *v, long long vstride, hipStream_t s);
-int vec_axpby(int nrhs, int n, double a, const double *x, double b, double *y, hipStream_t s);
-int vec_add_h(int nrhs, int n, const double *h1, double *h2, int cnt, long long hstride,
-              hipStream_t s);
+// ---- blas.hip: segmented float64 vector kernels used by GMRES -------------------------------
+int seg_dots(const Segments &sg, int nvec, const double *V, long long vstride, const double *w,
+             double *h, long long hs, double *scratch, hipStream_t s);
+int seg_combination(const Segments &sg, int nvec, const double *V, long long vstride,
+                    const double *h, long long hs, double *w, double sign, hipStream_t s);
+int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, hipStream_t s);
+int seg_scale_to(const Segments &sg, const double *w, const double *den, double *v, hipStream_t s);
+int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
+int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
 
 // ---- gmres.cpp ----------------------------------------------------------------------------
 int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const double *f,
                  double *x, bie_info *info, hipStream_t s);
+int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
+                  std::vector<double> &relres, bie_info *info, hipStream_t s);
 
 // ---- fmm.hip ------------------------------------------------------------------------------
 int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *s64,
@@ -114,7 +139,6 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *
 void fmm_destroy(FmmPlan *p);
 int fmm_current_order();
 
-int ensure_pinned(bie_geom *g, size_t bytes);
 
 // ---- profile.cpp: optional per-class launch timing ------------------------------------------
 struct ProfScope {

@@ -5,6 +5,7 @@ paper_1507_05925_amd.workloads; nothing here comes from the HIP path.
 
   python tests/golden/make_golden.py starfish   # 1000 starfish x 256 nodes, q ~ N(0,1) -> phi
   python tests/golden/make_golden.py ellipses   # 200 ellipses x 512 nodes, (F, T) -> (v, omega)
+  python tests/golden/make_golden.py batched    # columns of P / M of the largest batched geometries
 """
 import json
 import os
@@ -67,7 +68,37 @@ def ellipses():
     })
 
 
+def batched():
+    """Columns of P (largest elastance geometry) and M (largest mobility geometry) of the
+    32-geometry ensemble: unit charge on body 0; unit force (x) on body 0; unit torque on body 0."""
+    geoms = wl.batched_geometries()
+    out = {"workload": "32 geometries, 8-128 bodies, 64-512 nodes per body (batched ensemble)",
+           "generator": "paper_1507_05925_amd.workloads.batched_geometries()",
+           "seed": wl.SEEDS["batched"], "oracle": "oracle.matfree (float64, GMRES rtol 1e-13)",
+           "columns": []}
+    t = time.time()
+    ie = max((i for i, (k, c) in enumerate(geoms) if k == "elastance"), key=lambda i: geoms[i][1].M)
+    c = geoms[ie][1]
+    geo = ny.geometry_of(c)
+    q = np.zeros(c.nbodies)
+    q[0] = 1.0
+    r = mf.elastance_solve(geo, q, tol=1e-13, restart=100, maxiter=10)
+    out["columns"].append({"geometry": ie, "kind": "elastance", "column": 0, "M": geo["M"],
+                           "values": [float(v) for v in r["phi"]], "gmres_iters": r["iters"]})
+    im = max((i for i, (k, c) in enumerate(geoms) if k == "mobility"), key=lambda i: geoms[i][1].M)
+    c = geoms[im][1]
+    geo = ny.geometry_of(c)
+    for col in (0, 2):
+        FT = np.zeros(3 * c.nbodies)
+        FT[col] = 1.0
+        r = mf.mobility_solve(geo, FT, tol=1e-13, restart=150, maxiter=10)
+        out["columns"].append({"geometry": im, "kind": "mobility", "column": col, "M": geo["M"],
+                               "values": [float(v) for v in r["VW"]], "gmres_iters": r["iters"]})
+    out["seconds"] = time.time() - t
+    _dump("batched_columns.json", out)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["starfish", "ellipses"]
+    which = sys.argv[1:] or ["starfish", "ellipses", "batched"]
     for w in which:
-        {"starfish": starfish, "ellipses": ellipses}[w]()
+        {"starfish": starfish, "ellipses": ellipses, "batched": batched}[w]()
