@@ -186,6 +186,47 @@ int bie_batch_destroy(bie_batch *b);
 int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const bie_opts *opts,
                     bie_info *info, double *rel_residual, void *stream);
 
+/* ---- serving: continuous batching of elastance and mobility requests ------------------------
+ * A worker thread (own HIP stream, default priority) keeps a set of requests in flight. At every
+ * GMRES-cycle boundary it (1) computes each active request's true residual f - A x with the
+ * float64 operator, (2) retires the requests whose systems all reached opts.tol (potentials or
+ * rigid motions read off inside the bodies, copied to the caller's host buffer), (3) admits
+ * queued requests in arrival order while their solver state fits in hbm_budget_bytes, and
+ * (4) runs one Arnoldi cycle of at most `restart` steps over all remaining systems with the
+ * opts.precision operator (with BIE_MIXED each cycle is one float64 refinement step around a
+ * float32 far field). Requests that arrive while others are on the GPU join at the next cycle
+ * boundary; a request's arithmetic does not depend on the other requests in flight.
+ * Geometries (and their FMM trees) stay resident with their bie_geom and must outlive the
+ * requests that use them; several requests may share one geometry.
+ * Callers: any host thread; submit copies the input; out must stay valid until wait returns. */
+typedef struct bie_server bie_server;
+typedef struct {
+  long long hbm_budget_bytes; /* device bytes for solver state of requests in flight (0 = none) */
+  int max_systems;            /* cap on systems (rhs) in flight, 0 = no cap                     */
+  int max_cycles;             /* a request still above tol after this many cycles fails         */
+  bie_opts opts;              /* precision, method, tol, inner_tol, restart (cycle length), fmm */
+} bie_server_config;
+typedef struct {
+  int status;          /* BIE_OK, BIE_ENOCONV, or an error code                              */
+  int cycles;          /* GMRES cycles the request took part in                             */
+  double queue_s;      /* submit -> admitted                                                 */
+  double latency_s;    /* submit -> result in the caller's buffer                           */
+  double rel_residual; /* worst final relative residual over the request's rhs               */
+} bie_request_info;
+int bie_server_create(const bie_server_config *cfg, bie_server **out);
+/* kind 0: in [nrhs][N] charges -> out [nrhs][N] potentials; kind 1: in [nrhs][3N] (F, T) ->
+ * out [nrhs][3N] (v, omega); in and out are host pointers. *ticket identifies the request. */
+int bie_server_submit(bie_server *srv, bie_geom *g, int kind, int nrhs, const double *in,
+                      double *out, long long *ticket);
+/* Blocks until the request is done (timeout_s < 0: no timeout); BIE_EINVAL on timeout or an
+ * unknown ticket. */
+int bie_server_wait(bie_server *srv, long long ticket, double timeout_s, bie_request_info *info);
+/* Totals since creation: requests completed, rhs solved, cycles run, peak bytes in flight. */
+int bie_server_stats(bie_server *srv, long long *requests, long long *solves, long long *cycles,
+                     long long *peak_bytes);
+/* Drains the queue and in-flight work, stops the worker and frees the server. */
+int bie_server_destroy(bie_server *srv);
+
 /* ---- instrumentation (not a step of the method) ---------------------------------------------
  * When enabled, the library records a pair of HIP events on the launch stream around every
  * launch of the kernel classes below and accumulates, per class, the number of launches, their

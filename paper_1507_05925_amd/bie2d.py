@@ -76,6 +76,12 @@ _SIGS = {
     "bie_batch_create": ([ctypes.POINTER(_P)], _I),
     "bie_batch_destroy": ([_P], _I),
     "bie_batch_solve": ([_P, _I, _P, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P, _P], _I),
+    "bie_server_create": ([_P, ctypes.POINTER(_P)], _I),
+    "bie_server_submit": ([_P, _P, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
+    "bie_server_wait": ([_P, ctypes.c_longlong, ctypes.c_double, _P], _I),
+    "bie_server_stats": ([_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                          ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], _I),
+    "bie_server_destroy": ([_P], _I),
     "bie_profile_enable": ([_I], _I),
     "bie_profile_read": ([_I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_longlong)], _I),
@@ -362,3 +368,70 @@ def bie_batch_solve(batch, items, opts=None, allow_noconv=False):
         _check(code)
     res = [o_.t().contiguous() if it[2] is None else o_ for o_, it in zip(outs, items)]
     return res, info.as_dict(), rel
+
+
+class bie_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_longlong), ("max_systems", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("opts", bie_opts)]
+
+
+class bie_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int), ("queue_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """Owns a bie_server (worker thread with continuous batching). Inputs and outputs are host
+    numpy arrays; geometries must stay alive while their requests are in flight."""
+
+    def __init__(self, opts=None, hbm_budget_bytes=0, max_systems=0, max_cycles=200):
+        cfg = bie_server_config()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_systems = int(max_systems)
+        cfg.max_cycles = int(max_cycles)
+        cfg.opts = opts if opts is not None else default_opts()
+        h = ctypes.c_void_p()
+        _check(lib().bie_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._bufs = {}
+
+    def submit(self, g, kind, inp):
+        """inp: [nrhs, N] charges (kind 0) or [nrhs, 3N] (F, T) (kind 1) -> ticket."""
+        width = g.N if kind == 0 else 3 * g.N
+        a = np.ascontiguousarray(np.atleast_2d(inp), dtype=np.float64)
+        if a.shape[-1] != width:
+            raise ValueError(f"input width {a.shape[-1]} != {width}")
+        out = np.empty_like(a)
+        t = ctypes.c_longlong()
+        _check(lib().bie_server_submit(self.handle, g.handle, int(kind), a.shape[0],
+                                       a.ctypes.data_as(ctypes.c_void_p),
+                                       out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
+        self._bufs[t.value] = (a, out)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """-> (output array, info dict); raises on failure other than non-convergence."""
+        info = bie_request_info()
+        _check(lib().bie_server_wait(self.handle, ctypes.c_longlong(ticket), float(timeout),
+                                     ctypes.byref(info)))
+        a, out = self._bufs.pop(ticket)
+        return out, info.as_dict()
+
+    def stats(self):
+        v = [ctypes.c_longlong() for _ in range(4)]
+        _check(lib().bie_server_stats(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("requests", "solves", "cycles", "peak_bytes"), [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bie_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbie2d.so")
-SOURCES = ["kernels.hip", "blas.hip", "fmm.hip", "gmres.cpp", "capi.cpp", "profile.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "blas.hip", "fmm.hip", "gmres.cpp", "capi.cpp", "profile.cpp", "batch.cpp", "server.cpp"]
 
 # Packed-FP32 instructions are disabled for every device compile (the backend must not form
 # v_pk_* f32 operations); hipcc's host pass ignores the feature with a warning.
@@ -52,7 +52,7 @@ def build(verbose=False, jobs=8):
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join(f"--- {s}\n{t}" for s, t in failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -100,7 +100,8 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
 // GMRES(m) on A x = f for every system. x holds the iterate on exit (x0 = 0 if x_is_zero).
 int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
           const std::vector<double> &tol, int m, int max_iter, Work &wk, Stats &st,
-          std::vector<double> &relres, std::vector<int> &conv, hipStream_t s) {
+          std::vector<double> &relres, std::vector<int> &conv, hipStream_t s,
+          int max_cycles = 1 << 30) {
   const Segments &sg = *ss.seg;
   SolverMem &mem = *ss.mem;
   const int S = sg.S;
@@ -113,9 +114,11 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   relres.assign(S, 0.0);
   conv.assign(S, 0);
   bool first = true;
+  int cycles = 0;
   std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m),
       gv((size_t)S * (m + 1));
-  while (true) {
+  while (cycles < max_cycles) {
+    ++cycles;
     if (first && x_is_zero) {
       BIE_HIP_CHECK(hipMemcpyAsync(wk.r, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     } else {
@@ -212,6 +215,21 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
 }
 
 }  // namespace
+
+// One Arnoldi cycle (at most m steps, x0 = 0) on A d = r for every system, each system stopping
+// at its own relative tolerance; d receives the correction. Used by the serving loop.
+int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
+                const std::vector<double> &tol, int m, int &iters, int &applies, hipStream_t s) {
+  Work wk;
+  BIE_TRY(make_work(ss, m, wk, 0, nullptr));
+  Stats st;
+  std::vector<double> relres;
+  std::vector<int> conv;
+  BIE_TRY(gmres(ss, precision, r, d, true, tol, m, 1 << 30, wk, st, relres, conv, s, 1));
+  iters += st.iters;
+  applies += st.applies32 + st.applies64;
+  return BIE_OK;
+}
 
 int SolverMem::ensure_pinned(size_t bytes) {
   if (pinned_bytes >= bytes) return BIE_OK;

@@ -132,6 +132,8 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
                  double *x, bie_info *info, hipStream_t s);
 int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
                   std::vector<double> &relres, bie_info *info, hipStream_t s);
+int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
+                const std::vector<double> &tol, int m, int &iters, int &applies, hipStream_t s);
 
 // ---- fmm.hip ------------------------------------------------------------------------------
 int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *s64,

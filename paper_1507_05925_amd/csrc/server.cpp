@@ -1,0 +1,394 @@
+// Serving loop: continuous batching of elastance and mobility requests at GMRES-cycle
+// granularity, with admission by device-memory footprint (declared in include/bie2d.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace bie {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  long long id = 0;
+  bie_geom *g = nullptr;
+  int kind = 0, nrhs = 0;
+  long long n = 0;                 // unknowns per rhs
+  std::vector<double> in;          // host copy of the input
+  double *out = nullptr;           // caller's host buffer
+  DevBuf dev;                      // inc, f, x, result  [nrhs][n] x 3 + [nrhs][width]
+  double *inc = nullptr, *f = nullptr, *x = nullptr, *res = nullptr;
+  std::vector<double> relres;      // per rhs, from the last residual
+  long long bytes = 0;             // admission footprint
+  int cycles = 0;
+  Clock::time_point t_submit, t_admit;
+  bie_request_info info{};
+  bool done = false;
+};
+
+}  // namespace
+}  // namespace bie
+
+struct bie_server {
+  bie_server_config cfg;
+  int device = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<bie::Request>> queue;
+  std::map<long long, std::shared_ptr<bie::Request>> all;  // until waited for
+  long long next_id = 1;
+  bool stopping = false;
+  // worker-side state
+  std::vector<std::shared_ptr<bie::Request>> active;
+  long long bytes_in_flight = 0, peak_bytes = 0;
+  long long n_requests = 0, n_solves = 0, n_cycles = 0;
+  bie::Segments seg;
+  bie::SolverMem sm;
+  bie::DevBuf flat;  // F, X, R, D [Ntot] each
+  void run();
+};
+
+namespace bie {
+namespace {
+
+long long footprint(const bie_server_config &c, bie_geom *g, int kind, int nrhs) {
+  const long long n = kind == 0 ? g->M : 2LL * g->M;
+  const int width = kind == 0 ? g->N : 3 * g->N;
+  // request buffers (inc, f, x, result) + its share of the flat vectors and Krylov basis
+  return 8LL * nrhs * (3 * n + width) + 8LL * nrhs * n * (c.opts.restart + 1 + 4 + 3);
+}
+
+int prepare(Request &r, const bie_opts &o, hipStream_t s) {
+  const int width = r.kind == 0 ? r.g->N : 3 * r.g->N;
+  const size_t cnt = (size_t)r.nrhs * (3 * r.n + width);
+  BIE_TRY(r.dev.reserve(cnt * sizeof(double)));
+  r.inc = r.dev.as<double>();
+  r.f = r.inc + (size_t)r.nrhs * r.n;
+  r.x = r.f + (size_t)r.nrhs * r.n;
+  r.res = r.x + (size_t)r.nrhs * r.n;
+  // stage the input in the result buffer, then incident density and rhs f = -(1/2 I + K) inc
+  BIE_HIP_CHECK(hipMemcpyAsync(r.res, r.in.data(), r.in.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+  BIE_TRY(incident_density(r.g, r.kind, r.nrhs, r.res, r.inc, s));
+  BIE_TRY(apply_operator(r.g, r.kind, BIE_FP64, o.method, 0, -1.0, r.nrhs, r.inc, r.f, s));
+  BIE_HIP_CHECK(hipMemsetAsync(r.x, 0, sizeof(double) * r.nrhs * r.n, s));
+  r.relres.assign(r.nrhs, 1.0);
+  return BIE_OK;
+}
+
+int finish(Request &r, hipStream_t s) {
+  const int width = r.kind == 0 ? r.g->N : 3 * r.g->N;
+  BIE_TRY(vec_axpby((long long)r.nrhs * r.n, 1.0, r.x, 1.0, r.inc, s));  // inc = mu + incident
+  BIE_TRY(read_off(r.g, r.kind, r.nrhs, r.inc, r.res, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(r.out, r.res, sizeof(double) * r.nrhs * width,
+                               hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  return BIE_OK;
+}
+
+}  // namespace
+}  // namespace bie
+
+using namespace bie;
+
+void bie_server::run() {
+  (void)hipSetDevice(device);
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&s) != hipSuccess) return;
+  const bie_opts &o = cfg.opts;
+  const int m = std::max(1, o.restart);
+  for (;;) {
+    // ---- admission (arrival order, HBM footprint, system cap) ---------------------------------
+    std::vector<std::shared_ptr<Request>> admitted;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stopping || !queue.empty() || !active.empty(); });
+      if (stopping && queue.empty() && active.empty()) break;
+      long long systems = 0;
+      for (auto &r : active) systems += r->nrhs;
+      while (!queue.empty()) {
+        auto &r = queue.front();
+        const bool fits_mem = cfg.hbm_budget_bytes <= 0 ||
+                              bytes_in_flight + r->bytes <= cfg.hbm_budget_bytes ||
+                              (active.empty() && admitted.empty());
+        const bool fits_sys = cfg.max_systems <= 0 || systems + r->nrhs <= cfg.max_systems ||
+                              (active.empty() && admitted.empty());
+        if (!fits_mem || !fits_sys) break;
+        bytes_in_flight += r->bytes;
+        systems += r->nrhs;
+        r->t_admit = Clock::now();
+        admitted.push_back(r);
+        queue.pop_front();
+      }
+      peak_bytes = std::max(peak_bytes, bytes_in_flight);
+    }
+    for (auto &r : admitted) {
+      const int rc = prepare(*r, o, s);
+      r->info.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+      if (rc != BIE_OK) {
+        r->info.status = rc;
+        r->done = true;
+        r->dev.release();
+        std::lock_guard<std::mutex> lk(mu);
+        bytes_in_flight -= r->bytes;
+        cv_done.notify_all();
+        continue;
+      }
+      active.push_back(r);
+    }
+    if (active.empty()) continue;
+    // ---- flat layout of the active systems ------------------------------------------------------
+    std::vector<long long> lens, off(active.size() + 1, 0);
+    for (size_t i = 0; i < active.size(); ++i) {
+      for (int k = 0; k < active[i]->nrhs; ++k) lens.push_back(active[i]->n);
+      off[i + 1] = off[i] + (long long)active[i]->nrhs * active[i]->n;
+    }
+    const long long N = off.back();
+    int rc = seg.build(lens, s);
+    if (rc == BIE_OK) rc = flat.reserve(4 * (size_t)N * sizeof(double));
+    if (rc != BIE_OK) break;
+    double *F = flat.as<double>(), *X = F + N, *R = X + N, *D = R + N;
+    for (size_t i = 0; i < active.size(); ++i) {
+      const size_t bytes = sizeof(double) * active[i]->nrhs * active[i]->n;
+      (void)hipMemcpyAsync(F + off[i], active[i]->f, bytes, hipMemcpyDeviceToDevice, s);
+      (void)hipMemcpyAsync(X + off[i], active[i]->x, bytes, hipMemcpyDeviceToDevice, s);
+    }
+    SysSet ss;
+    ss.seg = &seg;
+    ss.mem = &sm;
+    std::vector<std::shared_ptr<Request>> act = active;
+    ss.apply = [act, off, &o](int precision, const double *in, double *out, hipStream_t st) {
+      for (size_t i = 0; i < act.size(); ++i)
+        BIE_TRY(apply_operator(act[i]->g, act[i]->kind, precision, o.method, 1, 1.0, act[i]->nrhs,
+                               in + off[i], out + off[i], st));
+      return BIE_OK;
+    };
+    // ---- true residual with the float64 operator; retire converged requests -------------------
+    ss.apply(BIE_FP64, X, R, s);
+    vec_axpby(N, 1.0, F, -1.0, R, s);
+    std::vector<double> rn, fn;
+    {
+      double *tmp = nullptr;
+      if (sm.small.reserve((size_t)(2 * seg.S + seg.C) * sizeof(double) + 64) != BIE_OK) break;
+      tmp = sm.small.as<double>();
+      seg_nrm2(seg, R, tmp, tmp + 2 * seg.S, s);
+      seg_nrm2(seg, F, tmp + seg.S, tmp + 2 * seg.S, s);
+      if (sm.ensure_pinned(2 * seg.S * sizeof(double)) != BIE_OK) break;
+      (void)hipMemcpyAsync(sm.pinned, tmp, 2 * seg.S * sizeof(double), hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+      rn.assign(sm.pinned, sm.pinned + seg.S);
+      fn.assign(sm.pinned + seg.S, sm.pinned + 2 * seg.S);
+    }
+    std::vector<double> itol_all(seg.S, 1.0);
+    std::vector<char> retire(active.size(), 0);
+    size_t k = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+      Request &r = *active[i];
+      bool all = true;
+      for (int j = 0; j < r.nrhs; ++j, ++k) {
+        r.relres[j] = fn[k] > 0.0 ? rn[k] / fn[k] : 0.0;
+        const bool c = r.relres[j] <= o.tol;
+        all = all && c;
+        // each cycle only has to bring the residual to what the outer tolerance needs
+        // (margin 3); with float32 far fields never tighter than inner_tol
+        itol_all[k] = c ? 1.0 : std::max(o.precision == BIE_MIXED ? o.inner_tol : 0.0,
+                                         o.tol / (3.0 * r.relres[j]));
+        if (c) (void)hipMemsetAsync(R + seg.h_off[k], 0, sizeof(double) * r.n, s);
+      }
+      if (all || r.cycles >= cfg.max_cycles) retire[i] = 1;
+    }
+    // ---- retire: results of converged requests go out before the next cycle --------------------
+    std::vector<std::shared_ptr<Request>> keep;
+    std::vector<long long> keep_old_off;
+    std::vector<double> itol;
+    k = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+      auto &r = active[i];
+      if (!retire[i]) {
+        keep.push_back(r);
+        keep_old_off.push_back(off[i]);
+        for (int j = 0; j < r->nrhs; ++j) itol.push_back(itol_all[k + j]);
+        k += r->nrhs;
+        continue;
+      }
+      k += r->nrhs;
+      int st = finish(*r, s);
+      double worst = 0.0;
+      for (double v : r->relres) worst = std::max(worst, v);
+      r->info.status = st != BIE_OK ? st : (worst <= o.tol ? BIE_OK : BIE_ENOCONV);
+      r->info.cycles = r->cycles;
+      r->info.rel_residual = worst;
+      r->info.latency_s = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
+      r->dev.release();
+      std::lock_guard<std::mutex> lk(mu);
+      bytes_in_flight -= r->bytes;
+      n_requests += 1;
+      n_solves += r->nrhs;
+      r->done = true;
+      cv_done.notify_all();
+    }
+    active.swap(keep);
+    if (active.empty()) continue;
+    // ---- one Arnoldi cycle on the residual of every remaining system ---------------------------
+    std::vector<long long> lens2, off2(active.size() + 1, 0);
+    for (size_t i = 0; i < active.size(); ++i) {
+      for (int j = 0; j < active[i]->nrhs; ++j) lens2.push_back(active[i]->n);
+      off2[i + 1] = off2[i] + (long long)active[i]->nrhs * active[i]->n;
+    }
+    double *T = X;  // X is no longer needed this cycle: it holds the re-laid-out residual
+    for (size_t i = 0; i < active.size(); ++i)
+      (void)hipMemcpyAsync(T + off2[i], R + keep_old_off[i],
+                           sizeof(double) * active[i]->nrhs * active[i]->n,
+                           hipMemcpyDeviceToDevice, s);
+    if (seg.build(lens2, s) != BIE_OK) break;
+    std::vector<std::shared_ptr<Request>> act2 = active;
+    ss.apply = [act2, off2, &o](int precision, const double *in, double *out, hipStream_t st) {
+      for (size_t i = 0; i < act2.size(); ++i)
+        BIE_TRY(apply_operator(act2[i]->g, act2[i]->kind, precision, o.method, 1, 1.0,
+                               act2[i]->nrhs, in + off2[i], out + off2[i], st));
+      return BIE_OK;
+    };
+    int iters = 0, applies = 0;
+    if (gmres_cycle(ss, o.precision, T, D, itol, m, iters, applies, s) != BIE_OK) break;
+    for (size_t i = 0; i < active.size(); ++i) {
+      vec_axpby((long long)active[i]->nrhs * active[i]->n, 1.0, D + off2[i], 1.0, active[i]->x, s);
+      active[i]->cycles += 1;
+    }
+    ++n_cycles;
+  }
+  // fail whatever is left (only after an internal error)
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto &r : active) {
+    r->info.status = BIE_EDEVICE;
+    r->done = true;
+  }
+  for (auto &r : queue) {
+    r->info.status = BIE_EDEVICE;
+    r->done = true;
+  }
+  active.clear();
+  queue.clear();
+  cv_done.notify_all();
+  (void)hipStreamDestroy(s);
+}
+
+extern "C" {
+
+int bie_server_create(const bie_server_config *cfg, bie_server **out) {
+  if (!cfg || !out) {
+    set_error("bie_server_create: NULL argument");
+    return BIE_EINVAL;
+  }
+  if (cfg->max_cycles < 1 || cfg->opts.restart < 1 || !(cfg->opts.tol > 0.0)) {
+    set_error("bie_server_create: invalid configuration");
+    return BIE_EINVAL;
+  }
+  bie_server *srv = new (std::nothrow) bie_server();
+  if (!srv) {
+    set_error("host allocation failed");
+    return BIE_ENOMEM;
+  }
+  srv->cfg = *cfg;
+  (void)hipGetDevice(&srv->device);
+  srv->worker = std::thread([srv] { srv->run(); });
+  *out = srv;
+  return BIE_OK;
+}
+
+int bie_server_submit(bie_server *srv, bie_geom *g, int kind, int nrhs, const double *in,
+                      double *out, long long *ticket) {
+  if (!srv || !g || (kind != 0 && kind != 1) || nrhs < 1 || !in || !out || !ticket) {
+    set_error("bie_server_submit: invalid argument");
+    return BIE_EINVAL;
+  }
+  auto r = std::make_shared<Request>();
+  r->g = g;
+  r->kind = kind;
+  r->nrhs = nrhs;
+  r->n = kind == 0 ? g->M : 2LL * g->M;
+  const int width = kind == 0 ? g->N : 3 * g->N;
+  r->in.assign(in, in + (size_t)nrhs * width);
+  r->out = out;
+  r->bytes = footprint(srv->cfg, g, kind, nrhs);
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stopping) {
+      set_error("bie_server_submit: server is stopping");
+      return BIE_EINVAL;
+    }
+    r->id = srv->next_id++;
+    srv->queue.push_back(r);
+    srv->all[r->id] = r;
+  }
+  srv->cv_work.notify_one();
+  *ticket = r->id;
+  return BIE_OK;
+}
+
+int bie_server_wait(bie_server *srv, long long ticket, double timeout_s, bie_request_info *info) {
+  if (!srv) {
+    set_error("bie_server_wait: NULL server");
+    return BIE_EINVAL;
+  }
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) {
+    set_error("bie_server_wait: unknown ticket");
+    return BIE_EINVAL;
+  }
+  auto r = it->second;
+  auto pred = [&] { return r->done; };
+  if (timeout_s < 0) {
+    srv->cv_done.wait(lk, pred);
+  } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
+    set_error("bie_server_wait: timed out");
+    return BIE_EINVAL;
+  }
+  if (info) *info = r->info;
+  srv->all.erase(it);
+  return r->info.status == BIE_ENOCONV ? BIE_OK : r->info.status;
+}
+
+int bie_server_stats(bie_server *srv, long long *requests, long long *solves, long long *cycles,
+                     long long *peak_bytes) {
+  if (!srv) {
+    set_error("bie_server_stats: NULL server");
+    return BIE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (requests) *requests = srv->n_requests;
+  if (solves) *solves = srv->n_solves;
+  if (cycles) *cycles = srv->n_cycles;
+  if (peak_bytes) *peak_bytes = srv->peak_bytes;
+  return BIE_OK;
+}
+
+int bie_server_destroy(bie_server *srv) {
+  if (!srv) return BIE_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  srv->seg.buf.release();
+  srv->sm.release();
+  srv->flat.release();
+  delete srv;
+  return BIE_OK;
+}
+
+}  // extern "C"
