@@ -53,12 +53,13 @@ extern "C" {
 
 #define BIE_DIRECT 0 /* all-pairs direct summation */
 #define BIE_FMM 1    /* 2D fast multipole method for the far field */
+#define BIE_AUTO 2   /* FMM for geometries with more than 32768 nodes, else direct */
 
 typedef struct bie_geom bie_geom; /* device-resident geometry + workspace (opaque) */
 
 typedef struct {
   int precision;    /* BIE_FP64 | BIE_MIXED                                            */
-  int method;       /* BIE_DIRECT | BIE_FMM                                            */
+  int method;       /* BIE_DIRECT | BIE_FMM | BIE_AUTO                                 */
   double tol;       /* target relative residual ||f - A mu|| / ||f|| (float64 apply)    */
   int restart;      /* GMRES restart length m (Krylov vectors per cycle)               */
   int max_iter;     /* cap on GMRES iterations summed over cycles and refinements      */

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bie2d.h")
 
 BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE = 0, -1, -2, -3, -4
 BIE_FP64, BIE_MIXED = 0, 1
-BIE_DIRECT, BIE_FMM = 0, 1
+BIE_DIRECT, BIE_FMM, BIE_AUTO = 0, 1, 2
 
 
 class BieError(RuntimeError):

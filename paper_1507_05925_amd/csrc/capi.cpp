@@ -86,7 +86,8 @@ static void fill_defaults(bie_opts *o) {
 
 static int check_opts(const bie_opts &o) {
   if ((o.precision != BIE_FP64 && o.precision != BIE_MIXED) ||
-      (o.method != BIE_DIRECT && o.method != BIE_FMM) || !(o.tol > 0.0) || o.restart < 1 ||
+      (o.method != BIE_DIRECT && o.method != BIE_FMM && o.method != BIE_AUTO) ||
+      !(o.tol > 0.0) || o.restart < 1 ||
       o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
       o.fmm_order > 64 || o.fmm_leaf < 1) {
     set_error("invalid bie_opts");

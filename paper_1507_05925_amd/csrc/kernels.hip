@@ -580,8 +580,9 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
     set_error("precision must be BIE_FP64 or BIE_MIXED");
     return BIE_EINVAL;
   }
+  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
   if (method != BIE_DIRECT && method != BIE_FMM) {
-    set_error("method must be BIE_DIRECT or BIE_FMM");
+    set_error("method must be BIE_DIRECT, BIE_FMM or BIE_AUTO");
     return BIE_EINVAL;
   }
   if (nrhs < 1 || !mu || !out) {

@@ -312,3 +312,25 @@ def random_forces(rng, N, nrhs=1, zero_total=True):
 
 def min_gap(g: Curves) -> float:
     return _min_gap(g.centers, g.radii)
+
+
+def serving_sessions(n_requests, seed=SEEDS["serving"]):
+    """Query sessions for the serving workload: each session is one geometry with
+    N = round(exp U[ln 2, ln 500]) bodies of 32*k nodes (64..256), shapes 50/50 starfish/ellipse,
+    kind 60/40 elastance/mobility, and 1-16 queries (one rhs each: q ~ N(0,1), or F ~ N(0,1)^2
+    with zero total and T ~ N(0,1)). Sessions are added until n_requests queries exist."""
+    rng = np.random.default_rng(seed)
+    out, total = [], 0
+    while total < n_requests:
+        N = int(round(math.exp(rng.uniform(math.log(2), math.log(500)))))
+        nodes = 32 * rng.integers(2, 9, size=N)
+        c = mixed_grid(rng, N, nodes)
+        kind = 0 if rng.uniform() < 0.6 else 1
+        nq = int(min(rng.integers(1, 17), n_requests - total))
+        if kind == 0:
+            qs = [random_charges(rng, N) for _ in range(nq)]
+        else:
+            qs = [random_forces(rng, N) for _ in range(nq)]
+        out.append((kind, c, qs))
+        total += nq
+    return out
