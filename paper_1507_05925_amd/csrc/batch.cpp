@@ -14,6 +14,7 @@ struct bie_batch {
   bie::Segments seg;
   bie::DevBuf flat;  // incident densities, rhs, solutions [Ntot] each
   bie::DevBuf ident; // identity blocks
+  bie::MultiPlan *plan = nullptr;
 };
 
 namespace bie {
@@ -53,6 +54,7 @@ int bie_batch_destroy(bie_batch *b) {
   b->seg.buf.release();
   b->flat.release();
   b->ident.release();
+  bie::multi_destroy(b->plan);
   delete b;
   return BIE_OK;
 }
@@ -67,7 +69,7 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   bie_opts o;
   if (opts) o = *opts; else bie_default_opts(&o);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  std::vector<long long> lens, item_off(nitems + 1, 0), in_off(nitems + 1, 0);
+  std::vector<long long> lens, starts, item_off(nitems + 1, 0), in_off(nitems + 1, 0);
   long long pairs = 0;
   for (int i = 0; i < nitems; ++i) {
     const bie_batch_item &it = items[i];
@@ -82,15 +84,18 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
       return BIE_EINVAL;
     }
     const long long n = it.kind == 0 ? it.g->M : 2LL * it.g->M;
-    for (int r = 0; r < it.nrhs; ++r) lens.push_back(n);
-    item_off[i + 1] = item_off[i] + n * it.nrhs;
+    for (int r = 0; r < it.nrhs; ++r) {
+      lens.push_back(n);
+      starts.push_back(item_off[i] + r * n);
+    }
+    item_off[i + 1] = align8(item_off[i] + n * it.nrhs);  // 64-byte aligned item blocks
     in_off[i + 1] = in_off[i] + (long long)cols * (it.in ? 0 : it.nrhs);
     pairs += (long long)it.nrhs * it.g->M * (long long)it.g->M;
     it.g->fmm_order = o.fmm_order;
     it.g->fmm_leaf = o.fmm_leaf;
   }
   const long long Ntot = item_off[nitems];
-  BIE_TRY(b->seg.build(lens, s));
+  BIE_TRY(b->seg.build(lens, s, &starts));
   BIE_TRY(b->flat.reserve(3 * (size_t)Ntot * sizeof(double)));
   double *dens = b->flat.as<double>(), *f = dens + Ntot, *mu = f + Ntot;
   if (in_off[nitems] > 0) BIE_TRY(b->ident.reserve((size_t)in_off[nitems] * sizeof(double)));
@@ -115,13 +120,27 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   ss.seg = &b->seg;
   ss.mem = &b->sm;
   ss.pairs_per_apply = pairs;
-  const int method = o.method;
-  std::vector<bie_batch_item> its(items, items + nitems);
-  ss.apply = [its, item_off, method](int precision, const double *in, double *out, hipStream_t st) {
-    for (size_t i = 0; i < its.size(); ++i)
-      BIE_TRY(apply_operator(its[i].g, its[i].kind, precision, method, 1, 1.0, its[i].nrhs,
-                             in + item_off[i], out + item_off[i], st));
-    return BIE_OK;
+  std::vector<MultiItem> mitems(nitems);
+  std::vector<int> first_sys(nitems + 1, 0);
+  for (int i = 0; i < nitems; ++i) {
+    bie_geom *g = items[i].g;
+    mitems[i] = {g, items[i].kind, items[i].nrhs, item_off[i],
+                 o.method == BIE_FMM || (o.method == BIE_AUTO && g->M > 32768)};
+    first_sys[i + 1] = first_sys[i] + items[i].nrhs;
+  }
+  SysSet *ssp = &ss;
+  MultiPlan **plan = &b->plan;
+  ss.apply = [ssp, plan, mitems, first_sys, Ntot](int precision, const double *in, double *out,
+                                                  hipStream_t st) {
+    // an item is applied when any of its systems is still active
+    std::vector<char> act(mitems.size(), 1);
+    if (!ssp->active.empty())
+      for (size_t i = 0; i < mitems.size(); ++i) {
+        char a = 0;
+        for (int k = first_sys[i]; k < first_sys[i + 1]; ++k) a |= ssp->active[k];
+        act[i] = a;
+      }
+    return multi_apply(*plan, mitems, act, precision, in, out, Ntot, st);
   };
   std::vector<double> rel;
   bie_info inf{};

@@ -141,7 +141,8 @@ int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStr
 }
 
 // Chunk list of systems with the given lengths (flat, back to back).
-int Segments::build(const std::vector<long long> &lens, hipStream_t s) {
+int Segments::build(const std::vector<long long> &lens, hipStream_t s,
+                    const std::vector<long long> *starts) {
   S = (int)lens.size();
   std::vector<long long> a, b;
   std::vector<int> cs, sc(1, 0);
@@ -149,6 +150,8 @@ int Segments::build(const std::vector<long long> &lens, hipStream_t s) {
   h_off.assign(S + 1, 0);
   for (int k = 0; k < S; ++k) {
     const long long n = lens[k];
+    if (starts) off = (*starts)[k];
+    h_off[k] = off;
     const long long per = n > 64 * 1024 ? 4096 : 1024;  // chunk length
     for (long long i = 0; i < n; i += per) {
       a.push_back(off + i);
@@ -164,6 +167,7 @@ int Segments::build(const std::vector<long long> &lens, hipStream_t s) {
     off += n;
     h_off[k + 1] = off;
   }
+  // h_off[k] is the start of system k; h_off[S] the end of the last one
   C = (int)cs.size();
   Ntot = off;
   const size_t bytes = (size_t)C * (8 + 8 + 4) + (S + 1) * 4 + 256;

@@ -113,6 +113,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   BIE_TRY(read_host(mem, wk.nrm, S, fnorm, s));
   relres.assign(S, 0.0);
   conv.assign(S, 0);
+  std::vector<char> done(S, 0);  // converged systems stay converged (their x no longer changes)
   bool first = true;
   int cycles = 0;
   std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m),
@@ -131,11 +132,13 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     std::vector<int> active(S, 0);
     int nact = 0;
     for (int r = 0; r < S; ++r) {
-      relres[r] = fnorm[r] > 0.0 ? beta[r] / fnorm[r] : 0.0;
-      conv[r] = relres[r] <= tol[r];
+      if (!done[r]) relres[r] = fnorm[r] > 0.0 ? beta[r] / fnorm[r] : 0.0;
+      conv[r] = done[r] || relres[r] <= tol[r];
+      done[r] = conv[r];
       active[r] = !conv[r];
       nact += active[r];
     }
+    ss.active.assign(active.begin(), active.end());  // later applies skip converged systems
     if (verbosity() >= 1)
       std::fprintf(stderr, "[bie] gmres prec=%d cycle start: iters=%d active=%d true rel res[0]=%.3e\n",
                    precision, st.iters, nact, relres[0]);
@@ -283,14 +286,15 @@ int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
     BIE_HIP_CHECK(hipMemcpyAsync(rr, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     relres.assign(S, 1.0);
     conv.assign(S, 0);
+    ss.active.assign(S, 1);
     for (int it = 0;; ++it) {
       BIE_TRY(seg_nrm2(*ss.seg, rr, wk.nrm, wk.scratch, s));
       BIE_TRY(read_host(*ss.mem, wk.nrm, S, rn, s));
       bool all = true;
       double worst = 0.0;
       for (int r = 0; r < S; ++r) {
-        relres[r] = fnorm[r] > 0.0 ? rn[r] / fnorm[r] : 0.0;
-        conv[r] = relres[r] <= o.tol;
+        if (!conv[r]) relres[r] = fnorm[r] > 0.0 ? rn[r] / fnorm[r] : 0.0;
+        conv[r] = conv[r] || relres[r] <= o.tol;
         all = all && conv[r];
         if (!conv[r]) worst = std::max(worst, relres[r]);
       }
@@ -313,6 +317,8 @@ int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
       std::vector<int> iconv;
       BIE_TRY(gmres(ss, BIE_MIXED, rr, d, true, itol, m, o.max_iter, wk, st, irel, iconv, s));
       BIE_TRY(vec_axpby(N, 1.0, d, 1.0, x, s));
+      ss.active.resize(S);
+      for (int r = 0; r < S; ++r) ss.active[r] = !conv[r];
       BIE_TRY(apply(ss, BIE_FP64, x, rr, st, s));
       BIE_TRY(vec_axpby(N, 1.0, f, -1.0, rr, s));
       ++refinements;

@@ -53,7 +53,10 @@ struct Segments {
   DevBuf buf;
   long long *c0 = nullptr, *c1 = nullptr;  // [C] flat chunk ranges
   int *csys = nullptr, *sys_chunk = nullptr;  // [C] system of chunk, [S+1] chunks of a system
-  int build(const std::vector<long long> &lens, hipStream_t s);
+  // systems back to back, or at the given start offsets (gaps between systems are never read
+  // by the segmented kernels)
+  int build(const std::vector<long long> &lens, hipStream_t s,
+            const std::vector<long long> *starts = nullptr);
 };
 
 // Krylov workspace and pinned staging of a solver owner (a geometry or a batch).
@@ -70,6 +73,7 @@ struct SysSet {
   Segments *seg = nullptr;
   SolverMem *mem = nullptr;
   long long pairs_per_apply = 0;
+  std::vector<char> active;  // per system; set by the solver before each apply (empty = all)
   std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
 };
 
@@ -141,6 +145,20 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *
 void fmm_destroy(FmmPlan *p);
 int fmm_current_order();
 
+
+// ---- multi.hip: one apply for many geometries ------------------------------------------------
+struct MultiItem {
+  bie_geom *g;
+  int kind, nrhs;
+  long long io;  // start of the item's rhs block in the flat vectors (64-byte aligned)
+  bool fmm;      // applied by the single-geometry FMM path
+};
+struct MultiPlan;
+int multi_apply(MultiPlan *&plan, const std::vector<MultiItem> &items,
+                const std::vector<char> &active, int precision, const double *in, double *out,
+                long long Ntot, hipStream_t s);
+void multi_destroy(MultiPlan *p);
+inline long long align8(long long v) { return (v + 7) / 8 * 8; }
 
 // ---- profile.cpp: optional per-class launch timing ------------------------------------------
 struct ProfScope {

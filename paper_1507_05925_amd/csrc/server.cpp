@@ -57,6 +57,7 @@ struct bie_server {
   bie::Segments seg;
   bie::SolverMem sm;
   bie::DevBuf flat;  // F, X, R, D [Ntot] each
+  bie::MultiPlan *plan = nullptr;
   void run();
 };
 
@@ -150,13 +151,16 @@ void bie_server::run() {
     }
     if (active.empty()) continue;
     // ---- flat layout of the active systems ------------------------------------------------------
-    std::vector<long long> lens, off(active.size() + 1, 0);
+    std::vector<long long> lens, starts, off(active.size() + 1, 0);
     for (size_t i = 0; i < active.size(); ++i) {
-      for (int k = 0; k < active[i]->nrhs; ++k) lens.push_back(active[i]->n);
-      off[i + 1] = off[i] + (long long)active[i]->nrhs * active[i]->n;
+      for (int k = 0; k < active[i]->nrhs; ++k) {
+        lens.push_back(active[i]->n);
+        starts.push_back(off[i] + k * active[i]->n);
+      }
+      off[i + 1] = align8(off[i] + (long long)active[i]->nrhs * active[i]->n);
     }
     const long long N = off.back();
-    int rc = seg.build(lens, s);
+    int rc = seg.build(lens, s, &starts);
     if (rc == BIE_OK) rc = flat.reserve(4 * (size_t)N * sizeof(double));
     if (rc != BIE_OK) break;
     double *F = flat.as<double>(), *X = F + N, *R = X + N, *D = R + N;
@@ -168,13 +172,21 @@ void bie_server::run() {
     SysSet ss;
     ss.seg = &seg;
     ss.mem = &sm;
-    std::vector<std::shared_ptr<Request>> act = active;
-    ss.apply = [act, off, &o](int precision, const double *in, double *out, hipStream_t st) {
-      for (size_t i = 0; i < act.size(); ++i)
-        BIE_TRY(apply_operator(act[i]->g, act[i]->kind, precision, o.method, 1, 1.0, act[i]->nrhs,
-                               in + off[i], out + off[i], st));
-      return BIE_OK;
+    auto items_of = [&o](const std::vector<std::shared_ptr<Request>> &reqs,
+                         const std::vector<long long> &offs) {
+      std::vector<MultiItem> v(reqs.size());
+      for (size_t i = 0; i < reqs.size(); ++i)
+        v[i] = {reqs[i]->g, reqs[i]->kind, reqs[i]->nrhs, offs[i],
+                o.method == BIE_FMM || (o.method == BIE_AUTO && reqs[i]->g->M > 32768)};
+      return v;
     };
+    MultiPlan **planp = &plan;
+    {
+      std::vector<MultiItem> mi = items_of(active, off);
+      ss.apply = [mi, planp, N](int precision, const double *in, double *out, hipStream_t st) {
+        return multi_apply(*planp, mi, std::vector<char>(mi.size(), 1), precision, in, out, N, st);
+      };
+    }
     // ---- true residual with the float64 operator; retire converged requests -------------------
     ss.apply(BIE_FP64, X, R, s);
     vec_axpby(N, 1.0, F, -1.0, R, s);
@@ -242,24 +254,38 @@ void bie_server::run() {
     active.swap(keep);
     if (active.empty()) continue;
     // ---- one Arnoldi cycle on the residual of every remaining system ---------------------------
-    std::vector<long long> lens2, off2(active.size() + 1, 0);
+    std::vector<long long> lens2, starts2, off2(active.size() + 1, 0);
     for (size_t i = 0; i < active.size(); ++i) {
-      for (int j = 0; j < active[i]->nrhs; ++j) lens2.push_back(active[i]->n);
-      off2[i + 1] = off2[i] + (long long)active[i]->nrhs * active[i]->n;
+      for (int j = 0; j < active[i]->nrhs; ++j) {
+        lens2.push_back(active[i]->n);
+        starts2.push_back(off2[i] + j * active[i]->n);
+      }
+      off2[i + 1] = align8(off2[i] + (long long)active[i]->nrhs * active[i]->n);
     }
     double *T = X;  // X is no longer needed this cycle: it holds the re-laid-out residual
     for (size_t i = 0; i < active.size(); ++i)
       (void)hipMemcpyAsync(T + off2[i], R + keep_old_off[i],
                            sizeof(double) * active[i]->nrhs * active[i]->n,
                            hipMemcpyDeviceToDevice, s);
-    if (seg.build(lens2, s) != BIE_OK) break;
-    std::vector<std::shared_ptr<Request>> act2 = active;
-    ss.apply = [act2, off2, &o](int precision, const double *in, double *out, hipStream_t st) {
-      for (size_t i = 0; i < act2.size(); ++i)
-        BIE_TRY(apply_operator(act2[i]->g, act2[i]->kind, precision, o.method, 1, 1.0,
-                               act2[i]->nrhs, in + off2[i], out + off2[i], st));
-      return BIE_OK;
-    };
+    if (seg.build(lens2, s, &starts2) != BIE_OK) break;
+    {
+      std::vector<MultiItem> mi = items_of(active, off2);
+      std::vector<int> first(active.size() + 1, 0);
+      for (size_t i = 0; i < active.size(); ++i) first[i + 1] = first[i] + active[i]->nrhs;
+      SysSet *ssp = &ss;
+      const long long N2 = off2.back();
+      ss.apply = [mi, planp, N2, first, ssp](int precision, const double *in, double *out,
+                                             hipStream_t st) {
+        std::vector<char> act(mi.size(), 1);
+        if (!ssp->active.empty())
+          for (size_t i = 0; i < mi.size(); ++i) {
+            char a = 0;
+            for (int k = first[i]; k < first[i + 1]; ++k) a |= ssp->active[k];
+            act[i] = a;
+          }
+        return multi_apply(*planp, mi, act, precision, in, out, N2, st);
+      };
+    }
     int iters = 0, applies = 0;
     if (gmres_cycle(ss, o.precision, T, D, itol, m, iters, applies, s) != BIE_OK) break;
     for (size_t i = 0; i < active.size(); ++i) {
@@ -387,6 +413,7 @@ int bie_server_destroy(bie_server *srv) {
   srv->seg.buf.release();
   srv->sm.release();
   srv->flat.release();
+  bie::multi_destroy(srv->plan);
   delete srv;
   return BIE_OK;
 }
