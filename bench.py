@@ -22,6 +22,8 @@ Other workloads (not the default line):
                      latency and solves/s next to the plain float64 GPU path (one solve at a
                      time, FIFO, same arrival times).
   --workload batched 32 geometries of 8-128 bodies: every P and M in one batched solve.
+  --workload copy    a plain 256 MiB device copy kernel (y = -x), 6 times: the known-size reference that
+                     scales the FETCH_SIZE / WRITE_SIZE counters into HBM bytes.
 """
 import argparse
 import json
@@ -47,7 +49,8 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--workload", choices=["starfish", "serve", "batched"], default="starfish")
+    p.add_argument("--workload", choices=["starfish", "serve", "batched", "copy"],
+                   default="starfish")
     p.add_argument("--requests", type=int, default=2000)
     return p.parse_args()
 
@@ -208,6 +211,25 @@ def batched_bench(a):
         "max_rel_residual": float(rel.max())}))
 
 
+def copy_bench(a):
+    import torch
+
+    n = 1 << 25  # 2^25 doubles = 256 MiB read + 256 MiB written per copy
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    # an elementwise kernel (not a DMA blit), so the counters see an ordinary dispatch
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 5
+    print(json.dumps({"metric": "device copy bandwidth", "value": 2 * 8 * n / dt / 1e9,
+                      "unit": "GB/s", "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
+                      "copies": 6}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -218,6 +240,8 @@ def main():
         return serve_bench(a)
     if a.workload == "batched":
         return batched_bench(a)
+    if a.workload == "copy":
+        return copy_bench(a)
     import numpy as np
     import torch
 

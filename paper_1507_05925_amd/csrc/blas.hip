@@ -22,22 +22,20 @@ __device__ inline double block_sum(double v, double *sh) {
   return t;
 }
 
-// partial[l * C + c] = <V_l, w> over chunk c (V_l = V + l * vstride)
-__global__ __launch_bounds__(kBlock) void k_dots_stage1(int nvec, int C, const long long *__restrict__ c0,
+// partial[l * C + c] = <V_l, w> over chunk c; grid (C, nvec), one workgroup per (chunk, vector)
+__global__ __launch_bounds__(kBlock) void k_dots_stage1(int C, const long long *__restrict__ c0,
                                                        const long long *__restrict__ c1,
                                                        const double *__restrict__ V, long long vstride,
                                                        const double *__restrict__ w,
                                                        double *__restrict__ partial) {
   __shared__ double sh[4];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, l = blockIdx.y;
   const long long i0 = c0[c], i1 = c1[c];
-  for (int l = 0; l < nvec; ++l) {
-    const double *v = V + l * vstride;
-    double acc = 0.0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) acc = fma(v[i], w[i], acc);
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(long long)l * C + c] = t;
-  }
+  const double *v = V + l * vstride;
+  double acc = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) acc = fma(v[i], w[i], acc);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[(long long)l * C + c] = t;
 }
 
 // h[s * hs + l] = sum over the chunks of system s (in order); sqrt for norms
@@ -53,7 +51,9 @@ __global__ __launch_bounds__(64) void k_dots_stage2(int C, const int *__restrict
   if (threadIdx.x == 0) h[s * hs + l] = do_sqrt ? sqrt(acc) : acc;
 }
 
-// w += sign * sum_l V_l h[s][l] on each chunk (s = system of the chunk)
+// w += sign * sum_l V_l h[s][l] on each chunk (s = system of the chunk); grid (C, kSub), each
+// workgroup takes every kSub-th block of 256 entries of its chunk
+constexpr int kSub = 4;
 __global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__restrict__ csys,
                                                        const long long *__restrict__ c0,
                                                        const long long *__restrict__ c1,
@@ -63,10 +63,21 @@ __global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__r
   const int c = blockIdx.x;
   const int s = csys[c];
   const double *hr = h + s * hs;
-  for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) {
-    double acc = 0.0;
-    for (int l = 0; l < nvec; ++l) acc = fma(V[l * vstride + i], hr[l], acc);
-    w[i] += sign * acc;
+  for (long long i = c0[c] + blockIdx.y * kBlock + threadIdx.x; i < c1[c]; i += kSub * kBlock) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = 0;
+    for (; l + 4 <= nvec; l += 4) {
+      a0 = fma(V[l * vstride + i], hr[l], a0);
+      a1 = fma(V[(l + 1) * vstride + i], hr[l + 1], a1);
+      a2 = fma(V[(l + 2) * vstride + i], hr[l + 2], a2);
+      a3 = fma(V[(l + 3) * vstride + i], hr[l + 3], a3);
+    }
+    // term l always goes to accumulator l mod 4, so trailing zero coefficients (a system frozen
+    // inside a longer batch cycle) leave every sum unchanged
+    if (l < nvec) a0 = fma(V[l * vstride + i], hr[l], a0);
+    if (l + 1 < nvec) a1 = fma(V[(l + 1) * vstride + i], hr[l + 1], a1);
+    if (l + 2 < nvec) a2 = fma(V[(l + 2) * vstride + i], hr[l + 2], a2);
+    w[i] += sign * ((a0 + a1) + (a2 + a3));
   }
 }
 
@@ -96,7 +107,8 @@ __global__ void k_add_h(int cnt, long long hs, const double *__restrict__ h1, do
 
 int seg_dots(const Segments &sg, int nvec, const double *V, long long vstride, const double *w,
              double *h, long long hs, double *scratch, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.C, sg.c0, sg.c1, V,
+  if (nvec <= 0) return BIE_OK;
+  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C, nvec), dim3(kBlock), 0, s, sg.C, sg.c0, sg.c1, V,
                      vstride, w, scratch);
   hipLaunchKernelGGL(k_dots_stage2, dim3(nvec, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk, scratch,
                      h, hs, 0);
@@ -106,14 +118,15 @@ int seg_dots(const Segments &sg, int nvec, const double *V, long long vstride, c
 
 int seg_combination(const Segments &sg, int nvec, const double *V, long long vstride,
                     const double *h, long long hs, double *w, double sign, hipStream_t s) {
-  hipLaunchKernelGGL(k_combination, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0, sg.c1, V,
-                     vstride, h, hs, w, sign);
+  if (nvec <= 0) return BIE_OK;
+  hipLaunchKernelGGL(k_combination, dim3(sg.C, kSub), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0,
+                     sg.c1, V, vstride, h, hs, w, sign);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
 
 int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C), dim3(kBlock), 0, s, 1, sg.C, sg.c0, sg.c1, w, 0LL,
+  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C, 1), dim3(kBlock), 0, s, sg.C, sg.c0, sg.c1, w, 0LL,
                      w, scratch);
   hipLaunchKernelGGL(k_dots_stage2, dim3(1, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk, scratch, out,
                      1LL, 1);
@@ -152,7 +165,7 @@ int Segments::build(const std::vector<long long> &lens, hipStream_t s,
     const long long n = lens[k];
     if (starts) off = (*starts)[k];
     h_off[k] = off;
-    const long long per = n > 64 * 1024 ? 4096 : 1024;  // chunk length
+    const long long per = 1024;  // chunk length
     for (long long i = 0; i < n; i += per) {
       a.push_back(off + i);
       b.push_back(off + std::min(n, i + per));

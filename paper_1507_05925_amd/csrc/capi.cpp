@@ -230,6 +230,7 @@ int bie_geom_destroy(bie_geom *g) {
   g->sm.release();
   g->seg.buf.release();
   g->ws_out.release();
+  g->ws_read.release();
   if (g->fmm) fmm_destroy(g->fmm);
   delete g;
   return BIE_OK;
@@ -245,7 +246,7 @@ int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M) {
 long long bie_geom_device_bytes(const bie_geom *g) {
   if (!g) return 0;
   return (long long)(g->arena.bytes + g->ws_apply.bytes + g->sm.big.bytes + g->sm.small.bytes +
-                     g->ws_out.bytes);
+                     g->ws_out.bytes + g->ws_read.bytes);
 }
 
 int bie_geom_set_fmm(bie_geom *g, int order, int leaf) {

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -45,7 +46,8 @@ struct FmmTree {
   int nchunk = 0;
   long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
-  double2 *T_m2l = nullptr, *T_m2m = nullptr, *T_l2l = nullptr;  // T_m2l: Hankel vectors [40][2p]
+  double2 *T_m2l = nullptr;  // Hankel vectors [40][2p]
+  double2 *T_tau = nullptr;  // M2M / L2L Toeplitz vectors [4][2p] (p zeros, then tau)
   double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n / n!  and  1/n!
   double *inv_h = nullptr;  // [L+1]
   DevBuf work;              // charges + expansions
@@ -73,15 +75,6 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cfma(double2 a, double2 b, double2 c) {  // a*b + c
   return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
-}
-__device__ inline double2 cpow(double2 w, int n) {
-  double2 r = make_double2(1.0, 0.0);
-  while (n) {
-    if (n & 1) r = cmul(r, w);
-    w = cmul(w, w);
-    n >>= 1;
-  }
-  return r;
 }
 
 __device__ inline double rcp64(double a) {
@@ -111,7 +104,20 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
 }
 
 // P2M at the leaves: grid (nleaf, nsets), one lane per coefficient.
-__global__ __launch_bounds__(64) void k_p2m(int p, int M, int nbox, double inv_h,
+// Wave-uniform read of lane l's double (l a compile-time or uniform index).
+__device__ __forceinline__ double rl64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
+// u_n = (1/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h. Lanes take 64 sources at a time and
+// raise their powers incrementally; eight coefficients at a time go through LDS, where lane
+// (b, g) = (lane / 8, lane % 8) sums sources g, g+8, ..., g+56 of coefficient b, and the eight
+// partials of b are combined across lanes. Fixed order: the result is reproducible.
+template <int P>
+__global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const int *__restrict__ leaf_start,
                                            const int *__restrict__ leaf_box,
                                            const double2 *__restrict__ center,
@@ -119,37 +125,101 @@ __global__ __launch_bounds__(64) void k_p2m(int p, int M, int nbox, double inv_h
                                            const double2 *__restrict__ Q,
                                            const double *__restrict__ fact_in,
                                            double2 *__restrict__ Mexp) {
-  const int leaf = blockIdx.x, set = blockIdx.y, n = threadIdx.x;
+  __shared__ double2 sh[8 * 64];
+  const int leaf = blockIdx.x, set = blockIdx.y, lane = threadIdx.x;
+  const int g = lane & 7, bb = lane >> 3;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
   const double2 *q = Q + (size_t)set * M;
-  double2 a = make_double2(0.0, 0.0);
+  double2 acc[P / 8];
+#pragma unroll
+  for (int k = 0; k < P / 8; ++k) acc[k] = make_double2(0.0, 0.0);
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  for (int j = j0; j < j1; ++j) {
-    const double2 z = xs[j];
-    const double2 w = make_double2((z.x - c.x) * inv_h, (z.y - c.y) * inv_h);
-    a = cfma(q[j], cpow(w, n), a);
+  for (int jb = j0; jb < j1; jb += 64) {
+    const int j = jb + lane;
+    double2 w = make_double2(0.0, 0.0), t = w;
+    if (j < j1) {
+      const double2 z = xs[j];
+      w = make_double2((z.x - c.x) * inv_h, (z.y - c.y) * inv_h);
+      t = q[j];
+    }
+#pragma unroll
+    for (int k = 0; k < P / 8; ++k) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        sh[b * 64 + lane] = t;
+        t = cmul(t, w);
+      }
+      __syncthreads();
+      double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const double2 v = sh[bb * 64 + r * 8 + g];
+        sum.x += v.x;
+        sum.y += v.y;
+      }
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        sum.x += __shfl_xor(sum.x, off, 64);
+        sum.y += __shfl_xor(sum.y, off, 64);
+      }
+      acc[k].x += sum.x;
+      acc[k].y += sum.y;
+      __syncthreads();
+    }
   }
-  if (n < p) {
-    const double f = fact_in[n];
-    Mexp[((size_t)set * nbox + box) * p + n] = make_double2(a.x * f, a.y * f);
+  if (g == 0) {
+    double2 *o = Mexp + ((size_t)set * nbox + box) * P;
+#pragma unroll
+    for (int k = 0; k < P / 8; ++k) {
+      const int n = 8 * k + bb;
+      const double f = fact_in[n];
+      o[n] = make_double2(acc[k].x * f, acc[k].y * f);
+    }
   }
 }
 
-// M2M for one level: grid (boxes of the level, nsets).
-__global__ __launch_bounds__(64) void k_m2m(int p, int nbox, int off, const int *__restrict__ child,
-                                           const double2 *__restrict__ Tt,
-                                           double2 *__restrict__ Mexp) {
-  const int b = off + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int cpos = 0; cpos < 4; ++cpos) {
-    const int ch = child[4 * b + cpos];
-    if (ch < 0) continue;
-    const double2 *a = Mexp + ((size_t)set * nbox + ch) * p;
-    const double2 *T = Tt + (size_t)cpos * p * p;
-    for (int m = 0; m <= n && m < p; ++m) acc = cfma(T[(size_t)m * p + n], a[m], acc);
+// The translations between a box and its children are Toeplitz products with one vector per
+// child position: with d = (child centre - parent centre) / parent size = (+-1/4, +-1/4) and
+// tau[k] = d^k / k!,
+//   M2M (stored u_n = a_n / n!):  u_parent[n] = sum_{m <= n} 2^-m u_child[m] tau[n - m]
+//   L2L (plain coefficients b):   b_child[n] = (2^-n / n!) sum_{m >= n} m! b_parent[m] tau[m - n]
+// The table holds, per position, p zeros followed by tau[0..p-1], so that both sums read
+// tau at a lane-dependent offset without a bound test. It sits in LDS; the source coefficient
+// of step m is read from lane m (readlane, wave-uniform).
+
+// M2M for one level: waves walk (parent box, set) items with a grid stride.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nsets,
+                                            const int *__restrict__ child,
+                                            const double2 *__restrict__ tau,
+                                            double2 *Mexp) {
+  __shared__ double2 tp[8 * P];
+  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = tau[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane < P ? lane : P - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long total = (long long)nb * nsets;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total;
+       item += (long long)gridDim.x * 4) {
+    const int set = (int)(item / nb);
+    const int b = off + (int)(item % nb);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+    for (int cpos = 0; cpos < 4; ++cpos) {
+      const int ch = child[4 * b + cpos];
+      if (ch < 0) continue;
+      const double2 u = Mexp[((size_t)set * nbox + ch) * P + n];
+      const double2 v = make_double2(ldexp(u.x, -n), ldexp(u.y, -n));
+      const double2 *tc = tp + cpos * 2 * P + P + n;  // tc[-m] = tau[n - m], zero for m > n
+#pragma unroll
+      for (int m = 0; m < P; m += 2) {
+        a0 = cfma(make_double2(rl64(v.x, m), rl64(v.y, m)), tc[-m], a0);
+        a1 = cfma(make_double2(rl64(v.x, m + 1), rl64(v.y, m + 1)), tc[-m - 1], a1);
+      }
+    }
+    if (lane < P) Mexp[((size_t)set * nbox + b) * P + n] = make_double2(a0.x + a1.x, a0.y + a1.y);
   }
-  if (threadIdx.x < p) Mexp[((size_t)set * nbox + b) * p + n] = acc;
 }
 
 // M2L for all boxes of levels >= 2, written into Lexp. Multipoles are stored as u_m = a_m / m!,
@@ -203,21 +273,41 @@ __global__ __launch_bounds__(256) void k_m2l(int p_unused, int nbox, int off2, i
   }
 }
 
-// L2L from level l to l+1: grid (boxes of level l+1, nsets); accumulates into Lexp.
-__global__ __launch_bounds__(64) void k_l2l(int p, int nbox, int off, const int *__restrict__ parent,
-                                           const double2 *__restrict__ Tt,
-                                           double2 *__restrict__ Lexp) {
-  const int c = off + blockIdx.x, set = blockIdx.y, n = threadIdx.x < p ? threadIdx.x : p - 1;
-  const int pc = parent[c];
-  const int cpos = pc & 3, pb = pc >> 2;
-  const double2 *b = Lexp + ((size_t)set * nbox + pb) * p;
-  const double2 *T = Tt + (size_t)cpos * p * p;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int m = 0; m < p; ++m)
-    if (m >= n) acc = cfma(T[(size_t)m * p + n], b[m], acc);
-  if (threadIdx.x < p) {
-    double2 *o = Lexp + ((size_t)set * nbox + c) * p + n;
-    *o = make_double2(o->x + acc.x, o->y + acc.y);
+// L2L from level l to l+1 (children of level l+1 boxes' parents), accumulated into Lexp; waves
+// walk (child box, set) items with a grid stride.
+template <int P>
+__global__ __launch_bounds__(256) void k_l2l(int nb, int off, int nbox, int nsets,
+                                            const int *__restrict__ parent,
+                                            const double2 *__restrict__ tau,
+                                            const double *__restrict__ fact_in, double2 *Lexp) {
+  __shared__ double2 tp[8 * P];
+  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = tau[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane < P ? lane : P - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double fi = fact_in[n];
+  const double sc = ldexp(fi, -n);
+  const long long total = (long long)nb * nsets;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total;
+       item += (long long)gridDim.x * 4) {
+    const int set = (int)(item / nb);
+    const int c = off + (int)(item % nb);
+    const int pc = parent[c];
+    const int cpos = pc & 3, pb = pc >> 2;
+    const double2 bp = Lexp[((size_t)set * nbox + pb) * P + n];
+    const double2 beta = make_double2(bp.x / fi, bp.y / fi);  // m! b_m on lane m
+    const double2 *tc = tp + cpos * 2 * P + P - n;           // tc[m] = tau[m - n], zero for m < n
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+#pragma unroll
+    for (int m = 0; m < P; m += 2) {
+      a0 = cfma(make_double2(rl64(beta.x, m), rl64(beta.y, m)), tc[m], a0);
+      a1 = cfma(make_double2(rl64(beta.x, m + 1), rl64(beta.y, m + 1)), tc[m + 1], a1);
+    }
+    if (lane < P) {
+      double2 *o = Lexp + ((size_t)set * nbox + c) * P + n;
+      *o = make_double2(o->x + (a0.x + a1.x) * sc, o->y + (a0.y + a1.y) * sc);
+    }
   }
 }
 
@@ -518,7 +608,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     for (int dy = -3; dy <= 3; ++dy)
       if (std::max(std::abs(dx), std::abs(dy)) >= 2) ocompact[(dx + 3) * 7 + (dy + 3)] = nc++;
   for (auto &o : m2l_off) o = ocompact[o];
-  std::vector<double2> Tm2l((size_t)40 * 2 * p), Tm2m((size_t)4 * p * p), Tl2l((size_t)4 * p * p);
+  std::vector<double2> Tm2l((size_t)40 * 2 * p);
   for (int dx = -3; dx <= 3; ++dx)
     for (int dy = -3; dy <= 3; ++dy) {
       const int o = ocompact[(dx + 3) * 7 + (dy + 3)];
@@ -539,19 +629,15 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       fact_out[n] = ((n & 1) ? -1.0 : 1.0) / f;
     }
   }
+  // translation vectors: per child position, p zeros then tau[k] = d^k / k!
+  std::vector<double2> Ttau((size_t)8 * p, make_double2(0.0, 0.0));
   for (int cpos = 0; cpos < 4; ++cpos) {
     const cd delta(((cpos & 1) ? 0.25 : -0.25), ((cpos & 2) ? 0.25 : -0.25));
-    std::vector<cd> dp(p + 1);
-    dp[0] = 1.0;
-    for (int i = 1; i <= p; ++i) dp[i] = dp[i - 1] * delta;
-    for (int n = 0; n < p; ++n)
-      for (int m = 0; m < p; ++m) {
-        cd mm = 0.0, ll = 0.0;
-        if (m <= n) mm = std::pow(0.5, m) * dp[n - m] * fact_in[n - m];
-        if (m >= n) ll = binom(m, n) * std::pow(0.5, n) * dp[m - n];
-        Tm2m[((size_t)cpos * p + m) * p + n] = make_double2(mm.real(), mm.imag());
-        Tl2l[((size_t)cpos * p + m) * p + n] = make_double2(ll.real(), ll.imag());
-      }
+    cd v = 1.0;
+    for (int k = 0; k < p; ++k) {
+      Ttau[(size_t)cpos * 2 * p + p + k] = make_double2(v.real(), v.imag());
+      v = v * delta / (double)(k + 1);
+    }
   }
   std::vector<double> inv_h(L + 1);
   for (int l = 0; l <= L; ++l) inv_h[l] = (double)(1 << l) / t.size;
@@ -583,8 +669,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.T_m2l = (double2 *)take((size_t)80 * p * 16);
   t.fact_out = (double *)take(p * 8);
   t.fact_in = (double *)take(p * 8);
-  t.T_m2m = (double2 *)take((size_t)4 * p * p * 16);
-  t.T_l2l = (double2 *)take((size_t)4 * p * p * 16);
+  t.T_tau = (double2 *)take((size_t)8 * p * 16);
   t.inv_h = (double *)take((L + 1) * 8);
   t.perm = (int *)take(M * 4);
   t.leaf_start = (int *)take((t.nleaf + 1) * 4);
@@ -613,10 +698,9 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.nrm, nrm.data(), M * 16));
   BIE_TRY(up(t.center, center.data(), t.nbox * 16));
   BIE_TRY(up(t.T_m2l, Tm2l.data(), Tm2l.size() * 16));
-  BIE_TRY(up(t.T_m2m, Tm2m.data(), Tm2m.size() * 16));
+  BIE_TRY(up(t.T_tau, Ttau.data(), Ttau.size() * 16));
   BIE_TRY(up(t.fact_out, fact_out.data(), p * 8));
   BIE_TRY(up(t.fact_in, fact_in.data(), p * 8));
-  BIE_TRY(up(t.T_l2l, Tl2l.data(), Tl2l.size() * 16));
   BIE_TRY(up(t.inv_h, inv_h.data(), (L + 1) * 8));
   BIE_TRY(up(t.perm, perm_i.data(), M * 4));
   BIE_TRY(up(t.leaf_start, leaf_start.data(), leaf_start.size() * 4));
@@ -664,22 +748,26 @@ int launch_m2l(const FmmTree &t, int nsets, int n2, const double2 *Mexp, double2
   return BIE_OK;
 }
 
-int m2l_dispatch(int p, const FmmTree &t, int nsets, int n2, const double2 *Mexp, double2 *Lexp,
-                 hipStream_t s) {
+// Calls f(std::integral_constant<int, P>) for the expansion length p (a multiple of 8).
+template <class F>
+int with_order(int p, F &&f) {
   switch (p) {
-    case 8: return launch_m2l<8>(t, nsets, n2, Mexp, Lexp, s);
-    case 16: return launch_m2l<16>(t, nsets, n2, Mexp, Lexp, s);
-    case 24: return launch_m2l<24>(t, nsets, n2, Mexp, Lexp, s);
-    case 32: return launch_m2l<32>(t, nsets, n2, Mexp, Lexp, s);
-    case 40: return launch_m2l<40>(t, nsets, n2, Mexp, Lexp, s);
-    case 48: return launch_m2l<48>(t, nsets, n2, Mexp, Lexp, s);
-    case 56: return launch_m2l<56>(t, nsets, n2, Mexp, Lexp, s);
-    case 64: return launch_m2l<64>(t, nsets, n2, Mexp, Lexp, s);
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 24: return f(std::integral_constant<int, 24>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 40: return f(std::integral_constant<int, 40>{});
+    case 48: return f(std::integral_constant<int, 48>{});
+    case 56: return f(std::integral_constant<int, 56>{});
+    case 64: return f(std::integral_constant<int, 64>{});
     default:
       set_error("fmm: internal order not a multiple of 8");
       return BIE_EINVAL;
   }
 }
+
+// Grid for the grid-stride translation kernels (four waves per workgroup).
+int translation_blocks(long long items) { return (int)std::min<long long>((items + 3) / 4, 2048); }
 
 }  // namespace
 
@@ -715,24 +803,32 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
   hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q);
   const double ih_leaf = (double)(1 << t.L) / t.size;
-  hipLaunchKernelGGL(k_p2m, dim3(t.nleaf, nsets), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
-                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
-  for (int l = t.L - 1; l >= 2; --l) {
-    const int nb = t.level_off[l + 1] - t.level_off[l];
-    hipLaunchKernelGGL(k_m2m, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l], t.child,
-                       t.T_m2m, Mexp);
-  }
-  const int off2 = t.level_off[2];
-  const int n2 = t.nbox - off2;
-  if (n2 > 0) {
-    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)p * p);
-    BIE_TRY(m2l_dispatch(p, t, nsets, n2, Mexp, Lexp, s));
-  }
-  for (int l = 2; l < t.L; ++l) {
-    const int nb = t.level_off[l + 2] - t.level_off[l + 1];
-    hipLaunchKernelGGL(k_l2l, dim3(nb, nsets), dim3(64), 0, s, p, t.nbox, t.level_off[l + 1],
-                       t.parent, t.T_l2l, Lexp);
-  }
+  BIE_TRY(with_order(p, [&](auto order) -> int {
+    constexpr int P = decltype(order)::value;
+    hipLaunchKernelGGL((k_p2m<P>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
+                       t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
+    for (int l = t.L - 1; l >= 2; --l) {
+      const int nb = t.level_off[l + 1] - t.level_off[l];
+      if (nb > 0)
+        hipLaunchKernelGGL((k_m2m<P>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
+                           0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
+    }
+    const int off2 = t.level_off[2];
+    const int n2 = t.nbox - off2;
+    if (n2 > 0) {
+      ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
+      BIE_TRY(launch_m2l<P>(t, nsets, n2, Mexp, Lexp, s));
+    }
+    for (int l = 2; l < t.L; ++l) {
+      const int nb = t.level_off[l + 2] - t.level_off[l + 1];
+      if (nb > 0)
+        hipLaunchKernelGGL((k_l2l<P>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
+                           0, s, nb, t.level_off[l + 1], t.nbox, nsets, t.parent, t.T_tau,
+                           t.fact_in, Lexp);
+    }
+    BIE_HIP_CHECK(hipGetLastError());
+    return BIE_OK;
+  }));
   ProfScope pe(BIE_K_FMM_EVAL, s, (t.near_pairs - M) * R);
   if (kind == 0)
     hipLaunchKernelGGL(k_eval_laplace, dim3(t.nchunk, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,

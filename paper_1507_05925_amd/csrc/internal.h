@@ -105,6 +105,7 @@ struct bie_geom {
   int seg_nrhs = -1;
   long long seg_len = -1;
   bie::DevBuf ws_out;     // solver outputs (densities, rhs) for solve entry points
+  bie::DevBuf ws_read;    // read-off partial sums [split][rhs][body][comp]
   bie::FmmPlan *fmm = nullptr;
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box

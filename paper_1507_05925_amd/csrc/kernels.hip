@@ -479,59 +479,149 @@ __global__ void k_rho(int M, int N, int R, const int *__restrict__ body_of,
 // ------------------------------------------------------------------------------------------
 // a7: read-off inside the bodies. grid = (N targets, nrhs); block sums over all M sources.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_potential(int M, int N, const double2 *__restrict__ xy,
+// Read-off kernels: a workgroup takes kTJ interior points (targets) against one range of
+// sources (grid: target groups x rhs x source splits), so each source record is loaded once per
+// kTJ targets. Raw sums go to part[split][rhs][target][comp]; a second kernel adds the splits in
+// order and applies the constants.
+constexpr int kTJ = 8;
+
+// Sums v[0..n) over the workgroup; the totals land in every thread's v.
+template <int n>
+__device__ inline void block_sums(double *v, double (*sh)[n]) {
+#pragma unroll
+  for (int t = 0; t < n; ++t)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[t] += __shfl_down(v[t], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int t = 0; t < n; ++t) sh[wid][t] = v[t];
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < n; ++t) v[t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+// sum_k w_k d_k log |p_j - x_k|^2 over the split's sources
+__global__ __launch_bounds__(kBlock) void k_potential(int M, int N, int nrhs,
+                                                     const double2 *__restrict__ xy,
                                                      const double *__restrict__ w,
                                                      const double *__restrict__ pint,
                                                      const double *__restrict__ dens,
-                                                     double *__restrict__ phi) {
-  __shared__ double sh[4];
-  const int j = blockIdx.x, r = blockIdx.y;
-  const double p1 = pint[2 * j], p2 = pint[2 * j + 1];
-  const double *d = dens + (size_t)r * M;
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < M; k += kBlock) {
-    const double2 q = xy[k];
-    const double dx = p1 - q.x, dy = p2 - q.y;
-    acc += w[k] * d[k] * log(fma(dx, dx, dy * dy));
+                                                     double *__restrict__ part) {
+  __shared__ double sh[4][kTJ];
+  const int j0 = blockIdx.x * kTJ, r = blockIdx.y, sp = blockIdx.z, S = gridDim.z;
+  double p1[kTJ], p2[kTJ], acc[kTJ];
+#pragma unroll
+  for (int t = 0; t < kTJ; ++t) {
+    const int j = min(j0 + t, N - 1);
+    p1[t] = pint[2 * j];
+    p2[t] = pint[2 * j + 1];
+    acc[t] = 0.0;
   }
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) phi[(size_t)r * N + j] = -t / (4.0 * kPi);  // log|r| = log(r^2)/2
+  const double *d = dens + (size_t)r * M;
+  const int k0 = (int)((long long)M * sp / S), k1 = (int)((long long)M * (sp + 1) / S);
+  for (int k = k0 + threadIdx.x; k < k1; k += kBlock) {
+    const double2 q = xy[k];
+    const double c = w[k] * d[k];
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+      const double dx = p1[t] - q.x, dy = p2[t] - q.y;
+      acc[t] = fma(c, log(fma(dx, dx, dy * dy)), acc[t]);
+    }
+  }
+  block_sums<kTJ>(acc, sh);
+  if (threadIdx.x < kTJ && j0 + (int)threadIdx.x < N) {
+    double v = acc[0];
+#pragma unroll
+    for (int t = 1; t < kTJ; ++t) v = (int)threadIdx.x == t ? acc[t] : v;
+    part[((size_t)sp * nrhs + r) * N + j0 + threadIdx.x] = v;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rigid(int M, int N, const double2 *__restrict__ xy,
+// phi_j = -(1/4 pi) sum (log |r|^2 = 2 log |r|, so S mu = -(1/2 pi) sum w mu log |r|)
+__global__ void k_potential_fin(int N, int nrhs, int S, const double *__restrict__ part,
+                                double *__restrict__ phi) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (long long)N * nrhs) return;
+  double v = 0.0;
+  for (int sp = 0; sp < S; ++sp) v += part[(size_t)sp * N * nrhs + i];
+  phi[i] = -v / (4.0 * kPi);
+}
+
+// Stokeslet velocity and the vorticity sum over the split's sources (raw sums u1, u2, om)
+__global__ __launch_bounds__(kBlock) void k_rigid(int M, int N, int nrhs,
+                                                 const double2 *__restrict__ xy,
                                                  const double *__restrict__ w,
                                                  const double *__restrict__ pint,
-                                                 const double *__restrict__ xc,
-                                                 const double *__restrict__ yc,
                                                  const double *__restrict__ dens,
-                                                 double *__restrict__ VW) {
-  __shared__ double sh[4];
-  const int j = blockIdx.x, r = blockIdx.y;
-  const double p1 = pint[2 * j], p2 = pint[2 * j + 1];
-  const double *d = dens + (size_t)r * 2 * M;
-  double u1 = 0.0, u2 = 0.0, om = 0.0;
-  for (int k = threadIdx.x; k < M; k += kBlock) {
-    const double2 q = xy[k];
-    const double dx = p1 - q.x, dy = p2 - q.y;
-    const double rr = fma(dx, dx, dy * dy);
-    const double t1 = w[k] * d[2 * k], t2 = w[k] * d[2 * k + 1];
-    const double lg = 0.5 * log(rr);
-    const double inv = 1.0 / rr;
-    const double rt = fma(dx, t1, dy * t2) * inv;
-    u1 += -lg * t1 + dx * rt;
-    u2 += -lg * t2 + dy * rt;
-    om += (dx * t2 - dy * t1) * inv;
+                                                 double *__restrict__ part) {
+  __shared__ double sh[4][3 * kTJ];
+  const int j0 = blockIdx.x * kTJ, r = blockIdx.y, sp = blockIdx.z, S = gridDim.z;
+  double p1[kTJ], p2[kTJ], acc[3 * kTJ];
+#pragma unroll
+  for (int t = 0; t < kTJ; ++t) {
+    const int j = min(j0 + t, N - 1);
+    p1[t] = pint[2 * j];
+    p2[t] = pint[2 * j + 1];
+    acc[3 * t] = acc[3 * t + 1] = acc[3 * t + 2] = 0.0;
   }
-  const double U1 = block_sum(u1, sh) / (4.0 * kPi);
-  const double U2 = block_sum(u2, sh) / (4.0 * kPi);
-  const double OM = -block_sum(om, sh) / (4.0 * kPi);
-  if (threadIdx.x == 0) {
-    const double e1 = p1 - xc[j], e2 = p2 - yc[j];
-    double *o = VW + (size_t)r * 3 * N + 3 * j;
-    o[0] = U1 + OM * e2;  // u - omega (p - x^c)^perp, (a)^perp = (-a2, a1)
-    o[1] = U2 - OM * e1;
+  const double *d = dens + (size_t)r * 2 * M;
+  const int k0 = (int)((long long)M * sp / S), k1 = (int)((long long)M * (sp + 1) / S);
+  for (int k = k0 + threadIdx.x; k < k1; k += kBlock) {
+    const double2 q = xy[k];
+    const double t1 = w[k] * d[2 * k], t2 = w[k] * d[2 * k + 1];
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+      const double dx = p1[t] - q.x, dy = p2[t] - q.y;
+      const double rr = fma(dx, dx, dy * dy);
+      const double lg = 0.5 * log(rr);
+      const double inv = 1.0 / rr;
+      const double rt = fma(dx, t1, dy * t2) * inv;
+      acc[3 * t] += -lg * t1 + dx * rt;
+      acc[3 * t + 1] += -lg * t2 + dy * rt;
+      acc[3 * t + 2] += (dx * t2 - dy * t1) * inv;
+    }
+  }
+  block_sums<3 * kTJ>(acc, sh);
+  if (threadIdx.x < kTJ && j0 + (int)threadIdx.x < N) {
+    const int t0 = threadIdx.x;
+    double U1 = acc[0], U2 = acc[1], OM = acc[2];
+#pragma unroll
+    for (int t = 1; t < kTJ; ++t) {
+      U1 = t0 == t ? acc[3 * t] : U1;
+      U2 = t0 == t ? acc[3 * t + 1] : U2;
+      OM = t0 == t ? acc[3 * t + 2] : OM;
+    }
+    double *o = part + (((size_t)sp * nrhs + r) * N + j0 + t0) * 3;
+    o[0] = U1;
+    o[1] = U2;
     o[2] = OM;
   }
+}
+
+// u = (1/4 pi) sums, omega = -(1/4 pi) om; v = u(p) - omega (p - x^c)^perp, a^perp = (-a2, a1)
+__global__ void k_rigid_fin(int N, int nrhs, int S, const double *__restrict__ pint,
+                            const double *__restrict__ xc, const double *__restrict__ yc,
+                            const double *__restrict__ part, double *__restrict__ VW) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (long long)N * nrhs) return;
+  const int j = (int)(i % N);
+  double U1 = 0.0, U2 = 0.0, OM = 0.0;
+  for (int sp = 0; sp < S; ++sp) {
+    const double *o = part + ((size_t)sp * N * nrhs + i) * 3;
+    U1 += o[0];
+    U2 += o[1];
+    OM += o[2];
+  }
+  U1 /= 4.0 * kPi;
+  U2 /= 4.0 * kPi;
+  OM = -OM / (4.0 * kPi);
+  const double e1 = pint[2 * j] - xc[j], e2 = pint[2 * j + 1] - yc[j];
+  double *o = VW + 3 * i;
+  o[0] = U1 + OM * e2;
+  o[1] = U2 - OM * e1;
+  o[2] = OM;
 }
 
 inline unsigned nblocks(long long n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }
@@ -651,13 +741,26 @@ int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double
 }
 
 int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t st) {
-  dim3 grid(g->N, nrhs);
-  if (kind == 0)
-    hipLaunchKernelGGL(k_potential, grid, dim3(kBlock), 0, st, g->M, g->N, g->xy, g->w, g->pint,
-                       dens, res);
-  else
-    hipLaunchKernelGGL(k_rigid, grid, dim3(kBlock), 0, st, g->M, g->N, g->xy, g->w, g->pint, g->xc,
-                       g->yc, dens, res);
+  if (nrhs <= 0 || g->N <= 0) return BIE_OK;
+  // source splits: about 2048 workgroups in all, at most 32 splits, at least 2048 sources each
+  const long long groups = (long long)((g->N + kTJ - 1) / kTJ) * nrhs;
+  int S = (int)std::max<long long>(1, std::min<long long>(32, (2048 + groups - 1) / groups));
+  S = std::max(1, std::min(S, g->M / 2048));
+  const int comps = kind == 0 ? 1 : 3;
+  BIE_TRY(g->ws_read.reserve((size_t)S * nrhs * g->N * comps * 8));
+  double *part = g->ws_read.as<double>();
+  dim3 grid((g->N + kTJ - 1) / kTJ, nrhs, S);
+  const unsigned fin = nblocks((long long)g->N * nrhs);
+  if (kind == 0) {
+    hipLaunchKernelGGL(k_potential, grid, dim3(kBlock), 0, st, g->M, g->N, nrhs, g->xy, g->w,
+                       g->pint, dens, part);
+    hipLaunchKernelGGL(k_potential_fin, dim3(fin), dim3(kBlock), 0, st, g->N, nrhs, S, part, res);
+  } else {
+    hipLaunchKernelGGL(k_rigid, grid, dim3(kBlock), 0, st, g->M, g->N, nrhs, g->xy, g->w, g->pint,
+                       dens, part);
+    hipLaunchKernelGGL(k_rigid_fin, dim3(fin), dim3(kBlock), 0, st, g->N, nrhs, S, g->pint, g->xc,
+                       g->yc, part, res);
+  }
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
