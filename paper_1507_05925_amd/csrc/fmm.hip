@@ -40,10 +40,15 @@ struct FmmTree {
   // device
   DevBuf buf;
   int *perm = nullptr, *leaf_start = nullptr, *leaf_box = nullptr, *child = nullptr,
-      *parent = nullptr, *m2l_ptr = nullptr, *m2l_src = nullptr, *m2l_off = nullptr,
-      *near_ptr = nullptr, *near_leaf = nullptr, *box_level = nullptr, *chunk_leaf = nullptr,
+      *parent = nullptr, *near_ptr = nullptr, *near_leaf = nullptr, *chunk_leaf = nullptr,
       *chunk_start = nullptr;
   int nchunk = 0;
+  // M2L groups: 16 target boxes each (grp_tgt, -1 = unused column), their level, and per group
+  // the offsets it uses (item_off, increasing) with the 16 source boxes of each (item_src, -1 =
+  // none)
+  int ngroup = 0, nitem = 0;
+  int *grp_ptr = nullptr, *grp_tgt = nullptr, *grp_lvl = nullptr, *item_off = nullptr,
+      *item_src = nullptr;
   long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
   double2 *T_m2l = nullptr;  // Hankel vectors [40][2p]
@@ -55,7 +60,15 @@ struct FmmTree {
 
 struct FmmPlan {
   std::map<int, FmmTree *> trees;  // by order p
+  hipStream_t side = nullptr;      // near field, concurrent with the expansion passes
+  hipEvent_t fork = nullptr, join = nullptr;
   ~FmmPlan() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     for (auto &kv : trees) {
       kv.second->buf.release();
       kv.second->work.release();
@@ -222,55 +235,94 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
   }
 }
 
-// M2L for all boxes of levels >= 2, written into Lexp. Multipoles are stored as u_m = a_m / m!,
-// which turns the operator into a Hankel product:
-//   b_n = (1/h) ((-1)^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / d^(k+1),
-// for the box offset d. The 40 vectors V_d (2p entries each) sit in LDS; lane n reads V_d[m + n]
-// (consecutive lanes, consecutive addresses) and u_m is wave-uniform (scalar loads). Each wave
-// walks target boxes with a grid stride, so the table is loaded once per workgroup.
+// M2L for all boxes of levels >= 2, written into Lexp, on the matrix cores. Multipoles are stored
+// as u_m = a_m / m!, which turns the operator for a box offset d into a Hankel product
+//   b_n = (1/h) ((-1)^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / d^(k+1).
+// Target boxes are grouped 16 at a time (same level, same position within the parent, so their
+// interaction lists share most offsets). For each offset d used by a group, the 16 multipoles
+// (one per target; zero where a target has no source at that offset) form the columns of U, and
+// the group's locals accumulate H_d U, with H_d the Hankel matrix of V_d written as a real
+// 2p x 2p matrix (rows and columns interleave real and imaginary parts), in 16x16x4 float64
+// MFMA tiles: lane (j, q) = (lane % 16, lane / 16) holds A[j][q] and B[q][j] of a k-step and
+// rows q + 4r of column j of an accumulator tile.
+// One workgroup per (group, set): its four waves split the k-steps (each loads a quarter of U
+// and keeps every row tile), then the four partial tiles are added in wave order through LDS.
+// A is read from the offset table in LDS (real and imaginary planes), B from the multipoles.
+// Offsets are taken in increasing order: each target's sum has a fixed order.
+typedef double m2l_d4 __attribute__((ext_vector_type(4)));
+
 template <int P>
-__global__ __launch_bounds__(256) void k_m2l(int p_unused, int nbox, int off2, int n2, int nsets,
-                                            const int *__restrict__ ptr,
-                                            const int *__restrict__ src,
-                                            const int *__restrict__ offs,
-                                            const int *__restrict__ box_level,
+__global__ __launch_bounds__(256) void k_m2l(int nbox, const int *__restrict__ grp_ptr,
+                                            const int *__restrict__ grp_tgt,
+                                            const int *__restrict__ grp_lvl,
+                                            const int *__restrict__ item_off,
+                                            const int *__restrict__ item_src,
                                             const double *__restrict__ inv_h,
                                             const double *__restrict__ fact_out,
                                             const double2 *__restrict__ Vtab,
                                             const double2 *__restrict__ Mexp,
                                             double2 *__restrict__ Lexp) {
-  constexpr int p = P;
-  extern __shared__ double2 V[];
-  const int tlen = 40 * 2 * p;
-  for (int i = threadIdx.x; i < tlen; i += blockDim.x) V[i] = Vtab[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int n = lane < p ? lane : p - 1;
-  const int waves = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const long long total = (long long)n2 * nsets;
-  for (long long item = (long long)blockIdx.x * waves + wave; item < total;
-       item += (long long)gridDim.x * waves) {
-    const int set = (int)(item / n2);
-    const int t = off2 + (int)(item % n2);
-    // four partial sums (m mod 4) break the dependent multiply-add chain
-    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
-    const int e0 = ptr[t - off2], e1 = ptr[t - off2 + 1];
-    for (int e = e0; e < e1; ++e) {
-      const double2 *u = Mexp + ((size_t)set * nbox + src[e]) * p;
-      const double2 *Vo = V + offs[e] * 2 * p + n;
-#pragma unroll
-      for (int m = 0; m < p; m += 4) {
-        a0 = cfma(u[m], Vo[m], a0);
-        a1 = cfma(u[m + 1], Vo[m + 1], a1);
-        a2 = cfma(u[m + 2], Vo[m + 2], a2);
-        a3 = cfma(u[m + 3], Vo[m + 3], a3);
-      }
-    }
-    const double2 acc = make_double2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
-    const double sc = inv_h[box_level[t]] * fact_out[n];
-    if (lane < p) Lexp[((size_t)set * nbox + t) * p + n] = make_double2(acc.x * sc, acc.y * sc);
+  constexpr int RT = 2 * P / 16;  // accumulator row tiles
+  constexpr int KW = P / 8;       // k-steps per wave (2p / 4 in all, over four waves)
+  extern __shared__ double lds_v[];
+  double *VR = lds_v, *VI = lds_v + 40 * 2 * P;
+  for (int i = threadIdx.x; i < 40 * 2 * P; i += blockDim.x) {
+    const double2 v = Vtab[i];
+    VR[i] = v.x;
+    VI[i] = v.y;
   }
+  __syncthreads();
+  const int g = blockIdx.x, set = blockIdx.y;
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // A[i][k] with i = 2n + ci, k = 2m + ck: Re V[n+m] if ci == ck, Im V[n+m] if (1, 0),
+  // -Im V[n+m] if (0, 1). This lane: ci = j & 1, ck = q & 1, n + m = 8 rt + 2 kk + abase.
+  const int ci = j & 1, ck = q & 1;
+  const double *plane = ci == ck ? VR : VI;
+  const double sgn = (ci == 0 && ck == 1) ? -1.0 : 1.0;
+  const int abase = (j >> 1) + (q >> 1) + 2 * KW * w;
+  m2l_d4 acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = m2l_d4{0.0, 0.0, 0.0, 0.0};
+  const double *Ms = reinterpret_cast<const double *>(Mexp + (size_t)set * nbox * P);
+  const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
+  for (int it = i0; it < i1; ++it) {
+    const int o = item_off[it];
+    const int src = item_src[it * 16 + j];
+    // B[k][j] = component ck of u_src[m]: k = 4 kk + q, m = 2 kk + q / 2, kk = KW w + kl
+    double b[KW];
+    const double *u = Ms + (size_t)(src < 0 ? 0 : src) * 2 * P + 2 * (q >> 1) + ck + 4 * KW * w;
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = src < 0 ? 0.0 : u[4 * kl];
+    const double *Ap = plane + o * 2 * P + abase;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int kl = 0; kl < KW; ++kl)
+        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * rt + 2 * kl], b[kl], acc[rt], 0,
+                                                       0, 0);
+  }
+  // partial tiles of the four waves through LDS (the table is no longer needed)
+  __syncthreads();
+  double *red = lds_v;  // [wave][rt][r][lane]
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[((w * RT + rt) * 4 + r) * 64 + lane] = acc[rt][r];
+  __syncthreads();
+  const int t = grp_tgt[g * 16 + j];
+  if (t < 0) return;
+  const double sc = inv_h[grp_lvl[g]];
+  double *out = reinterpret_cast<double *>(Lexp + ((size_t)set * nbox + t) * P) + (q & 1);
+  for (int rt = w; rt < RT; rt += 4)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) v += red[((ww * RT + rt) * 4 + r) * 64 + lane];
+      const int n = 8 * rt + 2 * r + (q >> 1);
+      out[2 * n] = v * sc * fact_out[n];
+    }
 }
 
 // L2L from level l to l+1 (children of level l+1 boxes' parents), accumulated into Lexp; waves
@@ -311,118 +363,217 @@ __global__ __launch_bounds__(256) void k_l2l(int nb, int off, int nbox, int nset
   }
 }
 
-// Local expansion value F and derivative F' at w = (z - c)/h (Horner); F' includes 1/h.
-__device__ inline void eval_local(const double2 *b, int p, double2 w, double ih, double2 &F,
-                                  double2 &dF) {
-  F = b[p - 1];
+// Local expansion value F and derivative F' at w = (z - c)/h (Horner); F' includes 1/h. The
+// coefficients are wave-uniform (one box per wave) and P is a compile-time constant, so the
+// loads batch into a few scalar loads.
+template <int P>
+__device__ inline void eval_local(const double2 *b, double2 w, double ih, double2 &F, double2 &dF) {
+  F = b[P - 1];
   dF = make_double2(0.0, 0.0);
-  for (int n = p - 1; n >= 1; --n) {
-    dF = cfma(dF, w, make_double2(F.x * 1.0, F.y * 1.0));
+#pragma unroll
+  for (int n = P - 1; n >= 1; --n) {
+    dF = cfma(dF, w, F);
     F = cfma(F, w, b[n - 1]);
   }
   dF = make_double2(dF.x * ih, dF.y * ih);
 }
 
-__device__ inline void eval_value(const double2 *b, int p, double2 w, double2 &F) {
-  F = b[p - 1];
-  for (int n = p - 1; n >= 1; --n) F = cfma(F, w, b[n - 1]);
+template <int P>
+__device__ inline double2 eval_value(const double2 *b, double2 w) {
+  double2 F = b[P - 1];
+#pragma unroll
+  for (int n = P - 1; n >= 1; --n) F = cfma(F, w, b[n - 1]);
+  return F;
 }
 
-// L2P + near field, Laplace. grid (nleaf, R); writes -(1/2pi) n.(sum_{k != i} s_k r/|r|^2).
-__global__ __launch_bounds__(64) void k_eval_laplace(
-    int p, int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
-    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
-    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
-  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int box = leaf_box[leaf];
-  const double2 c = center[box];
-  const double2 *b = Lexp + ((size_t)r * nbox + box) * p;
-  const double2 *q = Q + (size_t)r * M;
-  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  {
-    const int j = chunk_start[blockIdx.x] + threadIdx.x;
-    const bool valid = j < j1;
-    const int jj = valid ? j : j0;
-    const double2 z = xs[jj], nv = nrm[jj];
-    double2 F;
-    eval_value(b, p, make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf), F);
-    double gx = 0.0, gy = 0.0;
-    for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
-      const int nl = near_leaf[e];
-      for (int k = leaf_start[nl]; k < leaf_start[nl + 1]; ++k) {
-        const double2 y = xs[k];
-        const double dx = z.x - y.x, dy = z.y - y.y;
-        const bool same = (k == jj);
-        const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
-        const double t = same ? 0.0 : q[k].x * inv;
-        gx = fma(dx, t, gx);
-        gy = fma(dy, t, gy);
-      }
+// Near-field sums over the sources [k0, k1) of one neighbour leaf, four sources per step with
+// their loads issued together. SELF: the leaf holds the target itself (node `self`), whose pair
+// is masked without a branch.
+template <bool SELF>
+__device__ __forceinline__ void near_laplace(int k0, int k1, int self, double2 z,
+                                             const double2 *__restrict__ xs,
+                                             const double *__restrict__ qx, double &gx,
+                                             double &gy) {
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    double2 y[4];
+    double c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      y[u] = xs[k + u];
+      c[u] = qx[2 * (k + u)];
     }
-    const double far = nv.x * F.x - nv.y * F.y;  // Re(nu F)
-    const double v = -(far + nv.x * gx + nv.y * gy) / (2.0 * kPi);
-    if (valid) out[(size_t)r * M + perm[j]] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double dx = z.x - y[u].x, dy = z.y - y[u].y;
+      double rr = fma(dx, dx, dy * dy);
+      if (SELF) rr = (k + u == self) ? 1.0 : rr;
+      double t = c[u] * rcp64(rr);
+      if (SELF) t = (k + u == self) ? 0.0 : t;
+      gx = fma(dx, t, gx);
+      gy = fma(dy, t, gy);
+    }
+  }
+  for (; k < k1; ++k) {
+    const double2 y = xs[k];
+    const double c = qx[2 * k];
+    const double dx = z.x - y.x, dy = z.y - y.y;
+    double rr = fma(dx, dx, dy * dy);
+    if (SELF) rr = (k == self) ? 1.0 : rr;
+    double t = c * rcp64(rr);
+    if (SELF) t = (k == self) ? 0.0 : t;
+    gx = fma(dx, t, gx);
+    gy = fma(dy, t, gy);
   }
 }
 
-// L2P + near field, Stokes. grid (nleaf, R); sets 3r, 3r+1, 3r+2 are A, B, C.
-__global__ __launch_bounds__(64) void k_eval_stokes(
-    int p, int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
-    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+template <bool SELF>
+__device__ __forceinline__ void near_stokes(int k0, int k1, int self, double2 z, double2 nv,
+                                            const double2 *__restrict__ xs,
+                                            const double2 *__restrict__ q, double &gx,
+                                            double &gy) {
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    double2 y[4], sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      y[u] = xs[k + u];
+      sv[u] = q[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double dx = z.x - y[u].x, dy = z.y - y[u].y;
+      double rr = fma(dx, dx, dy * dy);
+      if (SELF) rr = (k + u == self) ? 1.0 : rr;
+      const double inv = rcp64(rr);
+      const double rn = fma(dx, nv.x, dy * nv.y);
+      double cc = fma(dx, sv[u].x, dy * sv[u].y) * rn * (inv * inv);
+      if (SELF) cc = (k + u == self) ? 0.0 : cc;
+      gx = fma(cc, dx, gx);
+      gy = fma(cc, dy, gy);
+    }
+  }
+  for (; k < k1; ++k) {
+    const double2 y = xs[k], sv = q[k];
+    const double dx = z.x - y.x, dy = z.y - y.y;
+    double rr = fma(dx, dx, dy * dy);
+    if (SELF) rr = (k == self) ? 1.0 : rr;
+    const double inv = rcp64(rr);
+    const double rn = fma(dx, nv.x, dy * nv.y);
+    double cc = fma(dx, sv.x, dy * sv.y) * rn * (inv * inv);
+    if (SELF) cc = (k == self) ? 0.0 : cc;
+    gx = fma(cc, dx, gx);
+    gy = fma(cc, dy, gy);
+  }
+}
+
+// Near field, Laplace: grid (target chunks, R), one wave per chunk of up to 64 nodes of a leaf;
+// writes -(1/2pi) n.(sum over the neighbour leaves, k != i, of s_k r/|r|^2).
+__global__ __launch_bounds__(64) void k_near_laplace(
+    int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
+    const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double2 *__restrict__ Q, const double2 *__restrict__ Lexp, double *__restrict__ out) {
+    const double2 *__restrict__ Q, double *__restrict__ out) {
+  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
+  const int j = chunk_start[blockIdx.x] + threadIdx.x;
+  const bool valid = j < j1;
+  const int jj = valid ? j : j0;
+  const double2 z = xs[jj], nv = nrm[jj];
+  const double *qx = reinterpret_cast<const double *>(Q + (size_t)r * M);
+  double gx = 0.0, gy = 0.0;
+  for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
+    const int nl = near_leaf[e];
+    const int k0 = leaf_start[nl], k1 = leaf_start[nl + 1];
+    if (nl == leaf)
+      near_laplace<true>(k0, k1, jj, z, xs, qx, gx, gy);
+    else
+      near_laplace<false>(k0, k1, jj, z, xs, qx, gx, gy);
+  }
+  if (valid) out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+}
+
+// L2P, Laplace: adds -(1/2pi) Re(nu F(z)) for the local expansion F of the target's leaf.
+template <int P>
+__global__ __launch_bounds__(64) void k_l2p_laplace(
+    int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const double2 *__restrict__ Lexp, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
-  const double2 *bA = Lexp + ((size_t)(3 * r) * nbox + box) * p;
-  const double2 *bB = Lexp + ((size_t)(3 * r + 1) * nbox + box) * p;
-  const double2 *bC = Lexp + ((size_t)(3 * r + 2) * nbox + box) * p;
-  const double2 *q = Q + (size_t)(3 * r) * M;  // rho in sorted order
+  const int j = chunk_start[blockIdx.x] + threadIdx.x;
+  if (j >= leaf_start[leaf + 1]) return;
+  const double2 z = xs[j], nv = nrm[j];
+  const double2 F = eval_value<P>(Lexp + ((size_t)r * nbox + box) * P,
+                                  make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf));
+  double *o = out + (size_t)r * M + perm[j];
+  *o -= (nv.x * F.x - nv.y * F.y) / (2.0 * kPi);  // Re(nu F)
+}
+
+// Near field, Stokes: grid (target chunks, R); rho of rhs r is charge set 3r (sorted order).
+__global__ __launch_bounds__(64) void k_near_stokes(
+    int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
+    const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const double2 *__restrict__ Q, double *__restrict__ out) {
+  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  {
-    const int j = chunk_start[blockIdx.x] + threadIdx.x;
-    const bool valid = j < j1;
-    const int jj = valid ? j : j0;
-    const double2 z = xs[jj], nv = nrm[jj];
-    const double2 w = make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf);
-    double2 A, dA, B, C, dC;
-    eval_local(bA, p, w, ih_leaf, A, dA);
-    eval_value(bB, p, w, B);
-    eval_local(bC, p, w, ih_leaf, C, dC);
-    // t1 = conj(nu) conj(C' - conj(z) A'); t2 = conj(nu) conj(B); t3 = nu conj(A) + nu A
-    const double2 zA = cmul(make_double2(z.x, -z.y), dA);
-    const double2 u = make_double2(dC.x - zA.x, -(dC.y - zA.y));  // conj(C' - conj(z) A')
-    const double2 nc = make_double2(nv.x, -nv.y);
-    const double2 t1 = cmul(nc, u);
-    const double2 t2 = cmul(nc, make_double2(B.x, -B.y));
-    const double2 t3 = cmul(nv, make_double2(2.0 * A.x, 0.0));  // conj(A) + A = 2 Re A
-    const double fx = 0.25 * (t1.x + t2.x + t3.x), fy = 0.25 * (t1.y + t2.y + t3.y);
-    double gx = 0.0, gy = 0.0;
-    for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
-      const int nl = near_leaf[e];
-      for (int k = leaf_start[nl]; k < leaf_start[nl + 1]; ++k) {
-        const double2 y = xs[k];
-        const double2 sv = q[k];
-        const double dx = z.x - y.x, dy = z.y - y.y;
-        const bool same = (k == jj);
-        const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
-        const double rn = fma(dx, nv.x, dy * nv.y);
-        const double cc = same ? 0.0 : fma(dx, sv.x, dy * sv.y) * rn * (inv * inv);
-        gx = fma(cc, dx, gx);
-        gy = fma(cc, dy, gy);
-      }
-    }
-    if (valid) {
-      const int i = perm[j];
-      out[(size_t)r * 2 * M + 2 * i] = -(fx + gx) / kPi;
-      out[(size_t)r * 2 * M + 2 * i + 1] = -(fy + gy) / kPi;
-    }
+  const int j = chunk_start[blockIdx.x] + threadIdx.x;
+  const bool valid = j < j1;
+  const int jj = valid ? j : j0;
+  const double2 z = xs[jj], nv = nrm[jj];
+  const double2 *q = Q + (size_t)(3 * r) * M;
+  double gx = 0.0, gy = 0.0;
+  for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
+    const int nl = near_leaf[e];
+    const int k0 = leaf_start[nl], k1 = leaf_start[nl + 1];
+    if (nl == leaf)
+      near_stokes<true>(k0, k1, jj, z, nv, xs, q, gx, gy);
+    else
+      near_stokes<false>(k0, k1, jj, z, nv, xs, q, gx, gy);
   }
+  if (valid) {
+    const int i = perm[j];
+    out[(size_t)r * 2 * M + 2 * i] = -gx / kPi;
+    out[(size_t)r * 2 * M + 2 * i + 1] = -gy / kPi;
+  }
+}
+
+// L2P, Stokes: sets 3r, 3r+1, 3r+2 are the expansions of A, B, C; adds -(1/pi) of
+// (1/4)[conj(nu) conj(C' - conj(z) A') + conj(nu) conj(B) + nu (conj(A) + A)].
+template <int P>
+__global__ __launch_bounds__(64) void k_l2p_stokes(
+    int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const double2 *__restrict__ Lexp, double *__restrict__ out) {
+  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  const int box = leaf_box[leaf];
+  const double2 c = center[box];
+  const int j = chunk_start[blockIdx.x] + threadIdx.x;
+  if (j >= leaf_start[leaf + 1]) return;
+  const double2 z = xs[j], nv = nrm[j];
+  const double2 w = make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf);
+  double2 A, dA, C, dC;
+  eval_local<P>(Lexp + ((size_t)(3 * r) * nbox + box) * P, w, ih_leaf, A, dA);
+  const double2 B = eval_value<P>(Lexp + ((size_t)(3 * r + 1) * nbox + box) * P, w);
+  eval_local<P>(Lexp + ((size_t)(3 * r + 2) * nbox + box) * P, w, ih_leaf, C, dC);
+  const double2 zA = cmul(make_double2(z.x, -z.y), dA);
+  const double2 u = make_double2(dC.x - zA.x, -(dC.y - zA.y));  // conj(C' - conj(z) A')
+  const double2 nc = make_double2(nv.x, -nv.y);
+  const double2 t1 = cmul(nc, u);
+  const double2 t2 = cmul(nc, make_double2(B.x, -B.y));
+  const double2 t3 = cmul(nv, make_double2(2.0 * A.x, 0.0));  // conj(A) + A = 2 Re A
+  const double fx = 0.25 * (t1.x + t2.x + t3.x), fy = 0.25 * (t1.y + t2.y + t3.y);
+  const int i = perm[j];
+  out[(size_t)r * 2 * M + 2 * i] -= fx / kPi;
+  out[(size_t)r * 2 * M + 2 * i + 1] -= fy / kPi;
 }
 
 // ---- host: tree and translation operators ---------------------------------------------------
@@ -608,6 +759,40 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     for (int dy = -3; dy <= 3; ++dy)
       if (std::max(std::abs(dx), std::abs(dy)) >= 2) ocompact[(dx + 3) * 7 + (dy + 3)] = nc++;
   for (auto &o : m2l_off) o = ocompact[o];
+  // M2L groups (k_m2l): per level and position within the parent, 16 boxes at a time in Morton
+  // order; per group the offsets its boxes use, in increasing order, with one source per box
+  std::vector<int> grp_ptr(1, 0), grp_tgt, grp_lvl, item_off, item_src;
+  for (int l = 2; l <= L; ++l) {
+    std::vector<int> cls[4];
+    for (size_t b = 0; b < keys[l].size(); ++b) {
+      const long long kk = keys[l][b];
+      const int ix = (int)decode((unsigned)kk), iy = (int)decode((unsigned)(kk >> 1));
+      cls[(ix & 1) | ((iy & 1) << 1)].push_back(t.level_off[l] + (int)b);
+    }
+    for (int c = 0; c < 4; ++c)
+      for (size_t g0 = 0; g0 < cls[c].size(); g0 += 16) {
+        std::vector<int> src_of(40 * 16, -1);
+        std::vector<char> used(40, 0);
+        for (int col = 0; col < 16; ++col) {
+          const int tb = g0 + col < cls[c].size() ? cls[c][g0 + col] : -1;
+          grp_tgt.push_back(tb);
+          if (tb < 0) continue;
+          for (int e = m2l_ptr[tb - off2]; e < m2l_ptr[tb - off2 + 1]; ++e) {
+            src_of[m2l_off[e] * 16 + col] = m2l_src[e];
+            used[m2l_off[e]] = 1;
+          }
+        }
+        for (int o = 0; o < 40; ++o)
+          if (used[o]) {
+            item_off.push_back(o);
+            for (int col = 0; col < 16; ++col) item_src.push_back(src_of[o * 16 + col]);
+          }
+        grp_lvl.push_back(l);
+        grp_ptr.push_back((int)item_off.size());
+      }
+  }
+  t.ngroup = (int)grp_lvl.size();
+  t.nitem = (int)item_off.size();
   std::vector<double2> Tm2l((size_t)40 * 2 * p);
   for (int dx = -3; dx <= 3; ++dx)
     for (int dy = -3; dy <= 3; ++dy) {
@@ -650,10 +835,10 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     perm_i[j] = k;
   }
   // upload (one arena)
-  const size_t nm2l = std::max<size_t>(m2l_src.size(), 1), nnear = std::max<size_t>(near_leaf.size(), 1);
+  const size_t nitem = std::max<size_t>(item_off.size(), 1), nnear = std::max<size_t>(near_leaf.size(), 1);
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
-                      m2l_ptr.size() + 2 * nm2l + near_ptr.size() + nnear + t.nbox +
-                      2 * chunk_leaf.size();
+                      grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + near_ptr.size() +
+                      nnear + 2 * chunk_leaf.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p;
   const size_t bytes = d2 * 16 + (L + 1 + 2 * p) * 8 + ints * 4 + 32 * 256;
   BIE_TRY(t.buf.reserve(bytes));
@@ -676,10 +861,11 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.leaf_box = (int *)take(t.nleaf * 4);
   t.child = (int *)take(4 * (size_t)t.nbox * 4);
   t.parent = (int *)take(t.nbox * 4);
-  t.box_level = (int *)take(t.nbox * 4);
-  t.m2l_ptr = (int *)take(m2l_ptr.size() * 4);
-  t.m2l_src = (int *)take(nm2l * 4);
-  t.m2l_off = (int *)take(nm2l * 4);
+  t.grp_ptr = (int *)take(grp_ptr.size() * 4);
+  t.grp_tgt = (int *)take(std::max<size_t>(grp_tgt.size(), 1) * 4);
+  t.grp_lvl = (int *)take(std::max<size_t>(grp_lvl.size(), 1) * 4);
+  t.item_off = (int *)take(nitem * 4);
+  t.item_src = (int *)take(nitem * 16 * 4);
   t.near_ptr = (int *)take(near_ptr.size() * 4);
   t.near_leaf = (int *)take(nnear * 4);
   t.nchunk = (int)chunk_leaf.size();
@@ -707,10 +893,11 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.leaf_box, leaf_box.data(), t.nleaf * 4));
   BIE_TRY(up(t.child, child.data(), child.size() * 4));
   BIE_TRY(up(t.parent, parent.data(), t.nbox * 4));
-  BIE_TRY(up(t.box_level, box_level.data(), t.nbox * 4));
-  BIE_TRY(up(t.m2l_ptr, m2l_ptr.data(), m2l_ptr.size() * 4));
-  BIE_TRY(up(t.m2l_src, m2l_src.data(), m2l_src.size() * 4));
-  BIE_TRY(up(t.m2l_off, m2l_off.data(), m2l_off.size() * 4));
+  BIE_TRY(up(t.grp_ptr, grp_ptr.data(), grp_ptr.size() * 4));
+  BIE_TRY(up(t.grp_tgt, grp_tgt.data(), grp_tgt.size() * 4));
+  BIE_TRY(up(t.grp_lvl, grp_lvl.data(), grp_lvl.size() * 4));
+  BIE_TRY(up(t.item_off, item_off.data(), item_off.size() * 4));
+  BIE_TRY(up(t.item_src, item_src.data(), item_src.size() * 4));
   BIE_TRY(up(t.near_ptr, near_ptr.data(), near_ptr.size() * 4));
   BIE_TRY(up(t.near_leaf, near_leaf.data(), near_leaf.size() * 4));
   BIE_TRY(up(t.chunk_leaf, chunk_leaf.data(), chunk_leaf.size() * 4));
@@ -732,18 +919,17 @@ bool m2l_lds_raised(size_t bytes) {
 }
 
 template <int P>
-int launch_m2l(const FmmTree &t, int nsets, int n2, const double2 *Mexp, double2 *Lexp,
-               hipStream_t s) {
-  const size_t lds = (size_t)80 * P * sizeof(double2);
+int launch_m2l(const FmmTree &t, int nsets, const double2 *Mexp, double2 *Lexp, hipStream_t s) {
+  const size_t lds = (size_t)2 * 40 * 2 * P * sizeof(double);
   if (!m2l_lds_raised<P>(lds)) {
     set_error("fmm: M2L table does not fit in LDS for this order");
     return BIE_EINVAL;
   }
-  const long long items = (long long)n2 * nsets;
-  const int blocks = (int)std::min<long long>((items + 3) / 4, 1024);
-  hipLaunchKernelGGL(k_m2l<P>, dim3(blocks), dim3(256), lds, s, P, t.nbox, t.level_off[2], n2,
-                     nsets, t.m2l_ptr, t.m2l_src, t.m2l_off, t.box_level, t.inv_h, t.fact_out,
-                     t.T_m2l, Mexp, Lexp);
+  // the reduction of the four partial tiles reuses the table's LDS (1024 P <= 1280 P bytes)
+  static_assert(4 * (2 * P / 16) * 4 * 64 <= 2 * 40 * 2 * P, "M2L reduction exceeds the table");
+  hipLaunchKernelGGL(k_m2l<P>, dim3(t.ngroup, nsets), dim3(256), lds, s, t.nbox, t.grp_ptr,
+                     t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_m2l,
+                     Mexp, Lexp);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
@@ -800,8 +986,31 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   double2 *Q = t.work.as<double2>();
   double2 *Mexp = Q + (size_t)nsets * M;
   double2 *Lexp = Mexp + (size_t)nsets * t.nbox * p;
+  FmmPlan &plan = *g->fmm;
+  if (!plan.side) {  // side stream for the near field (default priority) and its fork/join events
+    BIE_HIP_CHECK(hipStreamCreateWithFlags(&plan.side, hipStreamNonBlocking));
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.fork, hipEventDisableTiming));
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, hipEventDisableTiming));
+  }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
   hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q);
+  // the near field needs only the charges: it runs on the side stream while the expansions are
+  // built, and writes `partial`; the L2P kernels add the far part after the join
+  BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
+  BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
+  {
+    ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
+    if (kind == 0)
+      hipLaunchKernelGGL(k_near_laplace, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+                         t.leaf_start, t.xs, t.nrm, t.perm, t.near_ptr, t.near_leaf, t.chunk_leaf,
+                         t.chunk_start, Q, partial);
+    else
+      hipLaunchKernelGGL(k_near_stokes, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+                         t.leaf_start, t.xs, t.nrm, t.perm, t.near_ptr, t.near_leaf, t.chunk_leaf,
+                         t.chunk_start, Q, partial);
+    BIE_HIP_CHECK(hipGetLastError());
+  }
+  BIE_HIP_CHECK(hipEventRecord(plan.join, plan.side));
   const double ih_leaf = (double)(1 << t.L) / t.size;
   BIE_TRY(with_order(p, [&](auto order) -> int {
     constexpr int P = decltype(order)::value;
@@ -813,11 +1022,9 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
         hipLaunchKernelGGL((k_m2m<P>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
                            0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
     }
-    const int off2 = t.level_off[2];
-    const int n2 = t.nbox - off2;
-    if (n2 > 0) {
+    if (t.ngroup > 0) {
       ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
-      BIE_TRY(launch_m2l<P>(t, nsets, n2, Mexp, Lexp, s));
+      BIE_TRY(launch_m2l<P>(t, nsets, Mexp, Lexp, s));
     }
     for (int l = 2; l < t.L; ++l) {
       const int nb = t.level_off[l + 2] - t.level_off[l + 1];
@@ -826,18 +1033,18 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
                            0, s, nb, t.level_off[l + 1], t.nbox, nsets, t.parent, t.T_tau,
                            t.fact_in, Lexp);
     }
+    BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
+    if (kind == 0)
+      hipLaunchKernelGGL((k_l2p_laplace<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
+                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
+                         t.chunk_leaf, t.chunk_start, Lexp, partial);
+    else
+      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
+                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
+                         t.chunk_leaf, t.chunk_start, Lexp, partial);
     BIE_HIP_CHECK(hipGetLastError());
     return BIE_OK;
   }));
-  ProfScope pe(BIE_K_FMM_EVAL, s, (t.near_pairs - M) * R);
-  if (kind == 0)
-    hipLaunchKernelGGL(k_eval_laplace, dim3(t.nchunk, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
-                       t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
-                       t.near_leaf, t.chunk_leaf, t.chunk_start, Q, Lexp, partial);
-  else
-    hipLaunchKernelGGL(k_eval_stokes, dim3(t.nchunk, R), dim3(64), 0, s, p, M, t.nbox, ih_leaf,
-                       t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm, t.near_ptr,
-                       t.near_leaf, t.chunk_leaf, t.chunk_start, Q, Lexp, partial);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
