@@ -34,7 +34,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X vector TFLOP/s
+PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X vector TFLOP/s (float64 MFMA: also 78.6)
 FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), scale (1), 2 fma (4)
 FLOPS_PER_CMAC = 8   # complex multiply-add
 
@@ -82,13 +82,32 @@ def cpu_baseline(curves, target_seconds):
                       f"{dt:.1f} s wall"}
 
 
-def roofline(prof, kc, units_flops, dtype):
+def roofline(prof, kc, units_flops, dtype, bound="alu", kernel=None):
+    """Achieved algorithmic FLOP/s of one kernel class from its live HIP-event launch timings."""
     ms = prof["ms_total"] / max(prof["launches"], 1)
     units = prof["pairs"] / max(prof["launches"], 1)
     ach = units_flops * units / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    return {"bound": "alu", "achieved": ach, "peak": PEAK[dtype], "unit": "TFLOP/s",
-            "frac": ach / PEAK[dtype], "traffic": None, "avg_launch_ms": ms,
+    peak = PEAK[dtype]
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": traffic_bytes(kernel), "avg_launch_ms": ms,
             "launches": prof["launches"], "units_per_launch": units, "flops_per_unit": units_flops}
+
+
+def traffic_bytes(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (profiles/traffic.json:
+    FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy-kernel calibration), or None when
+    there is none or the kernel's source file has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if kernel is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def pct(v, q):
@@ -281,19 +300,23 @@ def main():
         pairs += info["pairs"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    classes = {
-        "k_lap_far_f32": (bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32"),
-        "k_lap_far_f64": (bie2d.BIE_K_FAR_LAPLACE_F64, FLOPS_PER_PAIR, "f64"),
-        "k_m2l": (bie2d.BIE_K_FMM_M2L, FLOPS_PER_CMAC, "f64"),
-        "k_eval_laplace": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64"),
-        "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64"),
+    order = (opts.fmm_order + 7) // 8 * 8
+    classes = {  # class, algorithmic flops per unit, dtype, bound, kernel name in the profiles
+        "k_lap_far_f32": (bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32", "alu",
+                          "k_lap_far_f32<1>"),
+        "k_lap_far_f64": (bie2d.BIE_K_FAR_LAPLACE_F64, FLOPS_PER_PAIR, "f64", "alu",
+                          "k_lap_far_f64<1>"),
+        "k_m2l": (bie2d.BIE_K_FMM_M2L, FLOPS_PER_CMAC, "f64", "mfma", f"k_m2l<{order}>"),
+        "k_near_laplace": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near_laplace"),
+        "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64", "alu", "k_lap_epilogue"),
     }
     profs = {k: bie2d.bie_profile_read(v[0]) for k, v in classes.items()}
     fmm_total = bie2d.bie_profile_read(bie2d.BIE_K_FMM)
     bie2d.bie_profile_enable(False)
     dom = max((k for k in classes if classes[k][1] > 0), key=lambda k: profs[k]["ms_total"])
-    rl = roofline(profs[dom], classes[dom][0], classes[dom][1], classes[dom][2])
-    rl["kernel"] = dom
+    c = classes[dom]
+    rl = roofline(profs[dom], c[0], c[1], c[2], bound=c[3], kernel=c[4])
+    rl["kernel"] = c[4]
 
     # the direct float32 far-field sweep on the same workload (survey row a3), 5 applies
     mu = torch.randn(1, g.M, dtype=torch.float64, device=dev)
@@ -305,7 +328,8 @@ def main():
     torch.cuda.synchronize()
     p32 = bie2d.bie_profile_read(bie2d.BIE_K_FAR_LAPLACE_F32)
     bie2d.bie_profile_enable(False)
-    rl_direct = roofline(p32, bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32")
+    rl_direct = roofline(p32, bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32",
+                         kernel="k_lap_far_f32<1>")
     rl_direct["kernel"] = "k_lap_far_f32<1>"
 
     acc = {}

@@ -40,7 +40,7 @@ struct FmmTree {
   // device
   DevBuf buf;
   int *perm = nullptr, *leaf_start = nullptr, *leaf_box = nullptr, *child = nullptr,
-      *parent = nullptr, *near_ptr = nullptr, *near_leaf = nullptr, *chunk_leaf = nullptr,
+      *parent = nullptr, *run_ptr = nullptr, *chunk_leaf = nullptr,
       *chunk_start = nullptr;
   int nchunk = 0;
   // M2L groups: 16 target boxes each (grp_tgt, -1 = unused column), their level, and per group
@@ -50,6 +50,7 @@ struct FmmTree {
   int *grp_ptr = nullptr, *grp_tgt = nullptr, *grp_lvl = nullptr, *item_off = nullptr,
       *item_src = nullptr;
   long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
+  int2 *run = nullptr;  // near field: per leaf, runs [k0, k1) of sorted nodes in neighbour leaves
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
   double2 *T_m2l = nullptr;  // Hankel vectors [40][2p]
   double2 *T_tau = nullptr;  // M2M / L2L Toeplitz vectors [4][2p] (p zeros, then tau)
@@ -96,22 +97,27 @@ __device__ inline double rcp64(double a) {
   return fma(y, e, y);
 }
 
-// Complex charges in sorted order. Laplace: one set per rhs; Stokes: A, B, C per rhs.
+// Charges in sorted order: Laplace set r is (s, 0); Stokes sets 3r, 3r+1, 3r+2 are rho,
+// conj(rho), rho conj(z). Also the near-field source records S4[r][j] = (x, y, s, 0), resp.
+// (x, y, rho).
 __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
                          const double2 *__restrict__ xs, const double *__restrict__ s64,
-                         double2 *__restrict__ Q) {
+                         double2 *__restrict__ Q, double4 *__restrict__ S4) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const int k = perm[j];
+  const double2 z = xs[j];
   for (int r = 0; r < R; ++r) {
     if (kind == 0) {
-      Q[(size_t)r * M + j] = make_double2(s64[(size_t)r * M + k], 0.0);
+      const double v = s64[(size_t)r * M + k];
+      Q[(size_t)r * M + j] = make_double2(v, 0.0);
+      S4[(size_t)r * M + j] = make_double4(z.x, z.y, v, 0.0);
     } else {
       const double2 rho = make_double2(s64[(size_t)r * 2 * M + 2 * k], s64[(size_t)r * 2 * M + 2 * k + 1]);
-      const double2 z = xs[j];
       Q[(size_t)(3 * r) * M + j] = rho;
       Q[(size_t)(3 * r + 1) * M + j] = make_double2(rho.x, -rho.y);
       Q[(size_t)(3 * r + 2) * M + j] = cmul(rho, make_double2(z.x, -z.y));
+      S4[(size_t)r * M + j] = make_double4(z.x, z.y, rho.x, rho.y);
     }
   }
 }
@@ -386,84 +392,52 @@ __device__ inline double2 eval_value(const double2 *b, double2 w) {
   return F;
 }
 
-// Near-field sums over the sources [k0, k1) of one neighbour leaf, four sources per step with
-// their loads issued together. SELF: the leaf holds the target itself (node `self`), whose pair
-// is masked without a branch.
-template <bool SELF>
-__device__ __forceinline__ void near_laplace(int k0, int k1, int self, double2 z,
-                                             const double2 *__restrict__ xs,
-                                             const double *__restrict__ qx, double &gx,
-                                             double &gy) {
-  int k = k0;
-  for (; k + 4 <= k1; k += 4) {
-    double2 y[4];
-    double c[4];
+// Near field. The neighbour leaves of a leaf (itself included) form a few runs of consecutive
+// sorted nodes. Source records (x, y, s, 0) or (x, y, rho) are wave-uniform and are read eight
+// per step with the scalar loads issued together; a run's tail is one step more over clamped
+// indices with zero strength. SELF: the run holds the target's own leaf, and the pair of a target
+// with itself is masked without a branch.
+template <bool STOKES, bool SELF, bool TAIL>
+__device__ __forceinline__ void near_step(const double4 *rec, int k, int k1, int self, double2 z,
+                                          double2 nv, double &gx, double &gy) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      y[u] = xs[k + u];
-      c[u] = qx[2 * (k + u)];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double dx = z.x - y[u].x, dy = z.y - y[u].y;
-      double rr = fma(dx, dx, dy * dy);
-      if (SELF) rr = (k + u == self) ? 1.0 : rr;
-      double t = c[u] * rcp64(rr);
-      if (SELF) t = (k + u == self) ? 0.0 : t;
-      gx = fma(dx, t, gx);
-      gy = fma(dy, t, gy);
-    }
-  }
-  for (; k < k1; ++k) {
-    const double2 y = xs[k];
-    const double c = qx[2 * k];
-    const double dx = z.x - y.x, dy = z.y - y.y;
+  for (int u = 0; u < 8; ++u) {
+    const bool in = !TAIL || k + u < k1;  // wave-uniform
+    const double dx = z.x - rec[u].x, dy = z.y - rec[u].y;
     double rr = fma(dx, dx, dy * dy);
-    if (SELF) rr = (k == self) ? 1.0 : rr;
-    double t = c * rcp64(rr);
-    if (SELF) t = (k == self) ? 0.0 : t;
+    const bool same = SELF && (k + u == self);
+    if (SELF) rr = same ? 1.0 : rr;
+    if (TAIL) rr = in ? rr : 1.0;  // padded slots repeat record k1 - 1, which may be the target
+    const double inv = rcp64(rr);
+    double t;
+    if (STOKES) {
+      const double rn = fma(dx, nv.x, dy * nv.y);
+      t = fma(dx, in ? rec[u].z : 0.0, dy * (in ? rec[u].w : 0.0)) * rn * (inv * inv);
+    } else {
+      t = (in ? rec[u].z : 0.0) * inv;
+    }
+    if (SELF) t = same ? 0.0 : t;
     gx = fma(dx, t, gx);
     gy = fma(dy, t, gy);
   }
 }
 
-template <bool SELF>
-__device__ __forceinline__ void near_stokes(int k0, int k1, int self, double2 z, double2 nv,
-                                            const double2 *__restrict__ xs,
-                                            const double2 *__restrict__ q, double &gx,
-                                            double &gy) {
+template <bool STOKES, bool SELF>
+__device__ __forceinline__ void near_run(int k0, int k1, int self, double2 z, double2 nv,
+                                         const double4 *__restrict__ S4, double &gx, double &gy) {
   int k = k0;
-  for (; k + 4 <= k1; k += 4) {
-    double2 y[4], sv[4];
+  for (; k + 8 <= k1; k += 8) {
+    const double4 *p = S4 + k;  // eight consecutive records: the loads merge
+    double4 rec[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      y[u] = xs[k + u];
-      sv[u] = q[k + u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double dx = z.x - y[u].x, dy = z.y - y[u].y;
-      double rr = fma(dx, dx, dy * dy);
-      if (SELF) rr = (k + u == self) ? 1.0 : rr;
-      const double inv = rcp64(rr);
-      const double rn = fma(dx, nv.x, dy * nv.y);
-      double cc = fma(dx, sv[u].x, dy * sv[u].y) * rn * (inv * inv);
-      if (SELF) cc = (k + u == self) ? 0.0 : cc;
-      gx = fma(cc, dx, gx);
-      gy = fma(cc, dy, gy);
-    }
+    for (int u = 0; u < 8; ++u) rec[u] = p[u];
+    near_step<STOKES, SELF, false>(rec, k, k1, self, z, nv, gx, gy);
   }
-  for (; k < k1; ++k) {
-    const double2 y = xs[k], sv = q[k];
-    const double dx = z.x - y.x, dy = z.y - y.y;
-    double rr = fma(dx, dx, dy * dy);
-    if (SELF) rr = (k == self) ? 1.0 : rr;
-    const double inv = rcp64(rr);
-    const double rn = fma(dx, nv.x, dy * nv.y);
-    double cc = fma(dx, sv.x, dy * sv.y) * rn * (inv * inv);
-    if (SELF) cc = (k == self) ? 0.0 : cc;
-    gx = fma(cc, dx, gx);
-    gy = fma(cc, dy, gy);
+  if (k < k1) {
+    double4 rec[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rec[u] = S4[min(k + u, k1 - 1)];
+    near_step<STOKES, SELF, true>(rec, k, k1, self, z, nv, gx, gy);
   }
 }
 
@@ -472,24 +446,23 @@ __device__ __forceinline__ void near_stokes(int k0, int k1, int self, double2 z,
 __global__ __launch_bounds__(64) void k_near_laplace(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
     const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const int *__restrict__ run_ptr, const int2 *__restrict__ run,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double2 *__restrict__ Q, double *__restrict__ out) {
+    const double4 *__restrict__ S4, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   const bool valid = j < j1;
   const int jj = valid ? j : j0;
   const double2 z = xs[jj], nv = nrm[jj];
-  const double *qx = reinterpret_cast<const double *>(Q + (size_t)r * M);
+  const double4 *src = S4 + (size_t)r * M;
   double gx = 0.0, gy = 0.0;
-  for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
-    const int nl = near_leaf[e];
-    const int k0 = leaf_start[nl], k1 = leaf_start[nl + 1];
-    if (nl == leaf)
-      near_laplace<true>(k0, k1, jj, z, xs, qx, gx, gy);
+  for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
+    const int2 kr = run[e];
+    if (kr.x <= j0 && j1 <= kr.y)
+      near_run<false, true>(kr.x, kr.y, jj, z, nv, src, gx, gy);
     else
-      near_laplace<false>(k0, k1, jj, z, xs, qx, gx, gy);
+      near_run<false, false>(kr.x, kr.y, jj, z, nv, src, gx, gy);
   }
   if (valid) out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
 }
@@ -514,28 +487,28 @@ __global__ __launch_bounds__(64) void k_l2p_laplace(
   *o -= (nv.x * F.x - nv.y * F.y) / (2.0 * kPi);  // Re(nu F)
 }
 
-// Near field, Stokes: grid (target chunks, R); rho of rhs r is charge set 3r (sorted order).
+// Near field, Stokes: grid (target chunks, R); writes -(1/pi) sum over the neighbour leaves,
+// k != i, of (r.n)(r.rho_k) r/|r|^4.
 __global__ __launch_bounds__(64) void k_near_stokes(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
     const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ near_ptr, const int *__restrict__ near_leaf,
+    const int *__restrict__ run_ptr, const int2 *__restrict__ run,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double2 *__restrict__ Q, double *__restrict__ out) {
+    const double4 *__restrict__ S4, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   const bool valid = j < j1;
   const int jj = valid ? j : j0;
   const double2 z = xs[jj], nv = nrm[jj];
-  const double2 *q = Q + (size_t)(3 * r) * M;
+  const double4 *src = S4 + (size_t)r * M;
   double gx = 0.0, gy = 0.0;
-  for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
-    const int nl = near_leaf[e];
-    const int k0 = leaf_start[nl], k1 = leaf_start[nl + 1];
-    if (nl == leaf)
-      near_stokes<true>(k0, k1, jj, z, nv, xs, q, gx, gy);
+  for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
+    const int2 kr = run[e];
+    if (kr.x <= j0 && j1 <= kr.y)
+      near_run<true, true>(kr.x, kr.y, jj, z, nv, src, gx, gy);
     else
-      near_stokes<false>(k0, k1, jj, z, nv, xs, q, gx, gy);
+      near_run<true, false>(kr.x, kr.y, jj, z, nv, src, gx, gy);
   }
   if (valid) {
     const int i = perm[j];
@@ -835,9 +808,24 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     perm_i[j] = k;
   }
   // upload (one arena)
-  const size_t nitem = std::max<size_t>(item_off.size(), 1), nnear = std::max<size_t>(near_leaf.size(), 1);
+  // near runs: the neighbour leaves of a leaf in increasing order, consecutive ones merged
+  std::vector<int> run_ptr(1, 0), run_kk;
+  for (int b = 0; b < t.nleaf; ++b) {
+    std::vector<int> nb(near_leaf.begin() + near_ptr[b], near_leaf.begin() + near_ptr[b + 1]);
+    std::sort(nb.begin(), nb.end());
+    for (size_t i = 0; i < nb.size(); ++i) {
+      if (i > 0 && nb[i] == nb[i - 1] + 1) {
+        run_kk.back() = leaf_start[nb[i] + 1];
+      } else {
+        run_kk.push_back(leaf_start[nb[i]]);
+        run_kk.push_back(leaf_start[nb[i] + 1]);
+      }
+    }
+    run_ptr.push_back((int)run_kk.size() / 2);
+  }
+  const size_t nitem = std::max<size_t>(item_off.size(), 1), nnear = std::max<size_t>(run_kk.size(), 2);
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
-                      grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + near_ptr.size() +
+                      grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + run_ptr.size() +
                       nnear + 2 * chunk_leaf.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p;
   const size_t bytes = d2 * 16 + (L + 1 + 2 * p) * 8 + ints * 4 + 32 * 256;
@@ -866,8 +854,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.grp_lvl = (int *)take(std::max<size_t>(grp_lvl.size(), 1) * 4);
   t.item_off = (int *)take(nitem * 4);
   t.item_src = (int *)take(nitem * 16 * 4);
-  t.near_ptr = (int *)take(near_ptr.size() * 4);
-  t.near_leaf = (int *)take(nnear * 4);
+  t.run_ptr = (int *)take(run_ptr.size() * 4);
+  t.run = (int2 *)take(nnear * 4);
   t.nchunk = (int)chunk_leaf.size();
   t.chunk_leaf = (int *)take(chunk_leaf.size() * 4);
   t.chunk_start = (int *)take(chunk_start.size() * 4);
@@ -898,8 +886,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.grp_lvl, grp_lvl.data(), grp_lvl.size() * 4));
   BIE_TRY(up(t.item_off, item_off.data(), item_off.size() * 4));
   BIE_TRY(up(t.item_src, item_src.data(), item_src.size() * 4));
-  BIE_TRY(up(t.near_ptr, near_ptr.data(), near_ptr.size() * 4));
-  BIE_TRY(up(t.near_leaf, near_leaf.data(), near_leaf.size() * 4));
+  BIE_TRY(up(t.run_ptr, run_ptr.data(), run_ptr.size() * 4));
+  BIE_TRY(up(t.run, run_kk.data(), run_kk.size() * 4));
   BIE_TRY(up(t.chunk_leaf, chunk_leaf.data(), chunk_leaf.size() * 4));
   BIE_TRY(up(t.chunk_start, chunk_start.data(), chunk_start.size() * 4));
   BIE_HIP_CHECK(hipStreamSynchronize(s));  // host vectors go out of scope
@@ -981,9 +969,12 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   FmmTree &t = *tp;
   const int M = t.M;
   const int nsets = kind == 0 ? R : 3 * R;
-  const size_t need = ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * 16 + 512;
+  // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
+  // locals [nsets][nbox][p]
+  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * 16 + 512;
   BIE_TRY(t.work.reserve(need));
-  double2 *Q = t.work.as<double2>();
+  double4 *S4 = t.work.as<double4>();
+  double2 *Q = reinterpret_cast<double2 *>(S4 + (size_t)R * M);
   double2 *Mexp = Q + (size_t)nsets * M;
   double2 *Lexp = Mexp + (size_t)nsets * t.nbox * p;
   FmmPlan &plan = *g->fmm;
@@ -993,7 +984,8 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
     BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, hipEventDisableTiming));
   }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
-  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q);
+  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q,
+                     S4);
   // the near field needs only the charges: it runs on the side stream while the expansions are
   // built, and writes `partial`; the L2P kernels add the far part after the join
   BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
@@ -1002,12 +994,12 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
     ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
     if (kind == 0)
       hipLaunchKernelGGL(k_near_laplace, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
-                         t.leaf_start, t.xs, t.nrm, t.perm, t.near_ptr, t.near_leaf, t.chunk_leaf,
-                         t.chunk_start, Q, partial);
+                         t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                         t.chunk_start, S4, partial);
     else
       hipLaunchKernelGGL(k_near_stokes, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
-                         t.leaf_start, t.xs, t.nrm, t.perm, t.near_ptr, t.near_leaf, t.chunk_leaf,
-                         t.chunk_start, Q, partial);
+                         t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                         t.chunk_start, S4, partial);
     BIE_HIP_CHECK(hipGetLastError());
   }
   BIE_HIP_CHECK(hipEventRecord(plan.join, plan.side));
