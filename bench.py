@@ -52,6 +52,7 @@ def parse():
     p.add_argument("--workload", choices=["starfish", "serve", "batched", "copy"],
                    default="starfish")
     p.add_argument("--requests", type=int, default=2000)
+    p.add_argument("--serve-restart", type=int, default=20)
     return p.parse_args()
 
 
@@ -119,6 +120,7 @@ def serve_bench(a):
     import threading
 
     import numpy as np
+    import torch
 
     from paper_1507_05925_amd import bie2d
     from paper_1507_05925_amd import workloads as wl
@@ -128,47 +130,70 @@ def serve_bench(a):
     geoms = [bie2d.Geometry.from_curves(c) for _, c, _ in sessions]
     queries = [(si, kind, q) for si, (kind, c, qs) in enumerate(sessions) for q in qs]
     opts = bie2d.default_opts(precision=bie2d.BIE_MIXED, method=bie2d.BIE_AUTO, tol=1e-10,
-                              restart=30)
+                              restart=a.serve_restart)
+    # geometries are resident: quadrature data, and FMM trees for both precisions, built once
+    for (kind, _, _), g in zip(sessions, geoms):
+        width = g.M if kind == 0 else 2 * g.M
+        mu = torch.zeros(1, width, dtype=torch.float64, device="cuda")
+        f = bie2d.bie_laplace_apply if kind == 0 else bie2d.bie_stokes_apply
+        for prec in (bie2d.BIE_FP64, bie2d.BIE_MIXED):
+            f(g, mu, prec, bie2d.BIE_AUTO)
+    torch.cuda.synchronize()
     srv = bie2d.Server(opts, hbm_budget_bytes=64 << 30, max_cycles=400)
-    # saturation: the warm-up queries all at once
-    t = time.perf_counter()
-    tk = [srv.submit(geoms[si], kind, q) for si, kind, q in queries[:warm]]
-    for x in tk:
+    for x in [srv.submit(geoms[si], kind, q) for si, kind, q in queries[:warm]]:
         srv.wait(x)
-    sat = warm / (time.perf_counter() - t)
-    rate = 0.7 * sat
-    rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=a.requests))
     run = queries[warm:]
-    tickets = [None] * len(run)
+    # saturation: a backlog of queries drawn from the run's own mix, all submitted at once
+    rng = np.random.default_rng(11)
+    sample = rng.choice(len(run), size=min(300, len(run)), replace=False)
+    t = time.perf_counter()
+    for x in [srv.submit(geoms[run[i][0]], run[i][1], run[i][2]) for i in sample]:
+        srv.wait(x)
+    sat = len(sample) / (time.perf_counter() - t)
 
-    def client():
+    def stream(rate, reqs, seed):
+        arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=len(reqs)))
+        tickets = [None] * len(reqs)
+
+        def client():
+            t0 = time.perf_counter()
+            for i, (si, kind, q) in enumerate(reqs):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(geoms[si], kind, q)
+
         t0 = time.perf_counter()
-        for i, (si, kind, q) in enumerate(run):
-            dt = arrivals[i] - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets[i] = srv.submit(geoms[si], kind, q)
+        th = threading.Thread(target=client)
+        th.start()
+        lat, outs, statuses = [], [], []
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            out, info = srv.wait(tickets[i])
+            lat.append(info["latency_s"])
+            outs.append(out)
+            statuses.append(info["status"])
+        th.join()
+        wall = time.perf_counter() - t0
+        return arrivals, lat, outs, statuses, wall
 
-    t0 = time.perf_counter()
-    th = threading.Thread(target=client)
-    th.start()
-    lat, outs, statuses = [], [], []
-    for i in range(len(run)):
-        while tickets[i] is None:
-            time.sleep(0.0005)
-        out, info = srv.wait(tickets[i])
-        lat.append(info["latency_s"])
-        outs.append(out)
-        statuses.append(info["status"])
-    th.join()
-    wall = time.perf_counter() - t0
+    rate = 0.7 * sat
+    c0 = srv.stats()["cycles"]
+    arrivals, lat, outs, statuses, wall = stream(rate, run, 7)
     st = srv.stats()
+    st["cycles_in_run"] = st["cycles"] - c0
+    sweep = []
+    for frac in (0.4, 0.9):
+        part = run[: max(1, len(run) // 2)]
+        _, l2, _, s2, w2 = stream(frac * sat, part, 8)
+        sweep.append({"offered_fraction_of_saturation": frac, "offered_rate_per_s": frac * sat,
+                      "solves_per_s": len(part) / w2, "p50": pct(l2, 0.5), "p99": pct(l2, 0.99),
+                      "all_ok": all(x == 0 for x in s2)})
     srv.close()
     # the plain float64 GPU path: one solve at a time; FIFO queue with the same arrivals
     o64 = bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_AUTO, tol=1e-10,
-                             restart=30)
-    import torch
+                             restart=a.serve_restart)
     service, errs = [], []
     for i, (si, kind, q) in enumerate(run):
         qd = torch.as_tensor(q, device="cuda")
@@ -192,8 +217,10 @@ def serve_bench(a):
                                "x 64-256 nodes, 1-16 queries per resident geometry, method auto "
                                "(FMM above 32768 nodes), mixed precision, tol 1e-10",
                    "offered_rate_per_s": rate, "saturation_rate_per_s": sat,
-                   "geometries": len(sessions)},
+                   "saturation_backlog": len(sample), "geometries": len(sessions),
+                   "restart": a.serve_restart},
         "latency_s": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99), "mean": float(np.mean(lat))},
+        "sweep": sweep,
         "plain_fp64_gpu": {"service_s_mean": float(np.mean(service)),
                            "throughput_solves_per_s": len(run) / float(np.sum(service)),
                            "latency_s": {"p50": pct(lat64, 0.5), "p99": pct(lat64, 0.99)}},

@@ -29,8 +29,14 @@ struct ItemDesc {
   const float2 *xr;
 };
 
+constexpr int kFmmStreams = 4;
+
 struct MultiPlan {
   DevBuf desc_buf, task_buf, ws;
+  // items applied by the FMM run on a small pool of streams (one per geometry, by first
+  // appearance), forked from and joined back to the caller's stream
+  hipStream_t pool[kFmmStreams] = {};
+  hipEvent_t fork = nullptr, join[kFmmStreams] = {};
   std::vector<int> split_host;
   int nfar[2] = {0, 0}, nepi[2] = {0, 0}, npack = 0;
   int *far_task[2] = {nullptr, nullptr}, *epi_task[2] = {nullptr, nullptr}, *pack_task = nullptr;
@@ -44,6 +50,14 @@ struct MultiPlan {
 
 void multi_destroy(MultiPlan *p) {
   if (!p) return;
+  for (int i = 0; i < kFmmStreams; ++i) {
+    if (p->pool[i]) {
+      (void)hipStreamSynchronize(p->pool[i]);
+      (void)hipStreamDestroy(p->pool[i]);
+    }
+    if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
   p->desc_buf.release();
   p->task_buf.release();
   p->ws.release();
@@ -436,10 +450,11 @@ int build_plan(MultiPlan &P, const std::vector<MultiItem> &items, const std::vec
     d.body_of = g->body_of;
     d.x = g->x; d.y = g->y; d.nx = g->nx; d.ny = g->ny; d.w = g->w; d.kappa = g->kappa;
     d.px = g->px; d.py = g->py; d.xc = g->xc; d.yc = g->yc; d.xy = g->xy; d.xr = g->xr;
-    // source splits from the item alone (about 8k workgroups for the item by itself), so an
-    // item's summation order never depends on the rest of the batch
-    const long long base = (long long)d.nchunk * d.ntile;
-    const long long want = base >= 8192 ? 1 : (8192 + base - 1) / base;
+    // source splits from the geometry alone (about 4k workgroups for one rhs chunk, at most 16
+    // splits, which bounds the partial sums of items with many rhs), so a system's summation
+    // order depends neither on the rest of the batch nor on how many rhs share its item
+    const long long base = d.ntile;
+    const long long want = std::min<long long>(16, (4096 + base - 1) / base);
     split_bodies(g, (int)std::min<long long>(want, std::min(g->N, 64)), item_splits[i]);
     d.nsplit = (int)item_splits[i].size() - 1;
     d.slot = slots[m.kind];
@@ -576,11 +591,37 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
                          P->epi_task[1], P->desc, in, s64, part_stk, out);
   }
   BIE_HIP_CHECK(hipGetLastError());
-  for (int i = 0; i < n; ++i)
-    if (active[i] && items[i].fmm)
-      BIE_TRY(apply_operator(items[i].g, items[i].kind, precision, BIE_FMM, 1, 1.0, items[i].nrhs,
-                             in + items[i].io, out + items[i].io, s));
-  return BIE_OK;
+  // FMM items: independent geometries overlap on the stream pool; items of one geometry share
+  // its workspace and stay on one stream, in item order
+  std::vector<const bie_geom *> gseen;
+  std::vector<int> on(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (!active[i] || !items[i].fmm) continue;
+    size_t gi = std::find(gseen.begin(), gseen.end(), items[i].g) - gseen.begin();
+    if (gi == gseen.size()) gseen.push_back(items[i].g);
+    on[i] = (int)(gi % kFmmStreams);
+  }
+  if (gseen.empty()) return BIE_OK;
+  if (!P->fork) {
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
+    for (int k = 0; k < kFmmStreams; ++k) {
+      BIE_HIP_CHECK(hipStreamCreateWithFlags(&P->pool[k], hipStreamNonBlocking));
+      BIE_HIP_CHECK(hipEventCreateWithFlags(&P->join[k], hipEventDisableTiming));
+    }
+  }
+  const int used = (int)std::min<size_t>(gseen.size(), kFmmStreams);
+  BIE_HIP_CHECK(hipEventRecord(P->fork, s));
+  for (int k = 0; k < used; ++k) BIE_HIP_CHECK(hipStreamWaitEvent(P->pool[k], P->fork, 0));
+  int rc = BIE_OK;
+  for (int i = 0; i < n && rc == BIE_OK; ++i)
+    if (on[i] >= 0)
+      rc = apply_operator(items[i].g, items[i].kind, precision, BIE_FMM, 1, 1.0, items[i].nrhs,
+                          in + items[i].io, out + items[i].io, P->pool[on[i]]);
+  for (int k = 0; k < used; ++k) {
+    BIE_HIP_CHECK(hipEventRecord(P->join[k], P->pool[k]));
+    BIE_HIP_CHECK(hipStreamWaitEvent(s, P->join[k], 0));
+  }
+  return rc;
 }
 
 }  // namespace bie

@@ -99,6 +99,40 @@ int finish(Request &r, hipStream_t s) {
   return BIE_OK;
 }
 
+// Flat layout of the active requests: requests of one geometry and kind are adjacent (the
+// active list is kept sorted that way) and packed back to back, so each such group is one item
+// of the multi-geometry apply; groups start at 64-byte boundaries. off[i] is the start of
+// request i; items[k] covers requests first[k] .. first[k+1]-1.
+struct Layout {
+  std::vector<long long> off;
+  std::vector<MultiItem> items;
+  std::vector<size_t> first;
+  long long total = 0;
+};
+
+Layout layout(const std::vector<std::shared_ptr<Request>> &reqs, const bie_opts &o) {
+  Layout L;
+  L.off.assign(reqs.size() + 1, 0);
+  long long cur = 0;
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    const Request &r = *reqs[i];
+    const bool new_group = i == 0 || reqs[i - 1]->g != r.g || reqs[i - 1]->kind != r.kind;
+    if (new_group) {
+      cur = align8(cur);
+      L.first.push_back(i);
+      L.items.push_back({r.g, r.kind, 0, cur,
+                         o.method == BIE_FMM || (o.method == BIE_AUTO && r.g->M > 32768)});
+    }
+    L.off[i] = cur;
+    L.items.back().nrhs += r.nrhs;
+    cur += (long long)r.nrhs * r.n;
+  }
+  L.first.push_back(reqs.size());
+  L.total = align8(cur);
+  L.off[reqs.size()] = L.total;
+  return L;
+}
+
 }  // namespace
 }  // namespace bie
 
@@ -150,16 +184,20 @@ void bie_server::run() {
       active.push_back(r);
     }
     if (active.empty()) continue;
+    std::stable_sort(active.begin(), active.end(),
+                     [](const std::shared_ptr<Request> &a, const std::shared_ptr<Request> &b) {
+                       return a->g != b->g ? a->g < b->g : a->kind < b->kind;
+                     });
     // ---- flat layout of the active systems ------------------------------------------------------
-    std::vector<long long> lens, starts, off(active.size() + 1, 0);
-    for (size_t i = 0; i < active.size(); ++i) {
+    const Layout L1 = layout(active, o);
+    const std::vector<long long> &off = L1.off;
+    std::vector<long long> lens, starts;
+    for (size_t i = 0; i < active.size(); ++i)
       for (int k = 0; k < active[i]->nrhs; ++k) {
         lens.push_back(active[i]->n);
         starts.push_back(off[i] + k * active[i]->n);
       }
-      off[i + 1] = align8(off[i] + (long long)active[i]->nrhs * active[i]->n);
-    }
-    const long long N = off.back();
+    const long long N = L1.total;
     int rc = seg.build(lens, s, &starts);
     if (rc == BIE_OK) rc = flat.reserve(4 * (size_t)N * sizeof(double));
     if (rc != BIE_OK) break;
@@ -172,17 +210,9 @@ void bie_server::run() {
     SysSet ss;
     ss.seg = &seg;
     ss.mem = &sm;
-    auto items_of = [&o](const std::vector<std::shared_ptr<Request>> &reqs,
-                         const std::vector<long long> &offs) {
-      std::vector<MultiItem> v(reqs.size());
-      for (size_t i = 0; i < reqs.size(); ++i)
-        v[i] = {reqs[i]->g, reqs[i]->kind, reqs[i]->nrhs, offs[i],
-                o.method == BIE_FMM || (o.method == BIE_AUTO && reqs[i]->g->M > 32768)};
-      return v;
-    };
     MultiPlan **planp = &plan;
     {
-      std::vector<MultiItem> mi = items_of(active, off);
+      const std::vector<MultiItem> mi = L1.items;
       ss.apply = [mi, planp, N](int precision, const double *in, double *out, hipStream_t st) {
         return multi_apply(*planp, mi, std::vector<char>(mi.size(), 1), precision, in, out, N, st);
       };
@@ -254,14 +284,14 @@ void bie_server::run() {
     active.swap(keep);
     if (active.empty()) continue;
     // ---- one Arnoldi cycle on the residual of every remaining system ---------------------------
-    std::vector<long long> lens2, starts2, off2(active.size() + 1, 0);
-    for (size_t i = 0; i < active.size(); ++i) {
+    const Layout L2 = layout(active, o);
+    const std::vector<long long> &off2 = L2.off;
+    std::vector<long long> lens2, starts2;
+    for (size_t i = 0; i < active.size(); ++i)
       for (int j = 0; j < active[i]->nrhs; ++j) {
         lens2.push_back(active[i]->n);
         starts2.push_back(off2[i] + j * active[i]->n);
       }
-      off2[i + 1] = align8(off2[i] + (long long)active[i]->nrhs * active[i]->n);
-    }
     double *T = X;  // X is no longer needed this cycle: it holds the re-laid-out residual
     for (size_t i = 0; i < active.size(); ++i)
       (void)hipMemcpyAsync(T + off2[i], R + keep_old_off[i],
@@ -269,11 +299,14 @@ void bie_server::run() {
                            hipMemcpyDeviceToDevice, s);
     if (seg.build(lens2, s, &starts2) != BIE_OK) break;
     {
-      std::vector<MultiItem> mi = items_of(active, off2);
-      std::vector<int> first(active.size() + 1, 0);
-      for (size_t i = 0; i < active.size(); ++i) first[i + 1] = first[i] + active[i]->nrhs;
+      const std::vector<MultiItem> mi = L2.items;
+      // systems of item k: those of requests L2.first[k] .. L2.first[k+1]-1
+      std::vector<int> sys0(active.size() + 1, 0);
+      for (size_t i = 0; i < active.size(); ++i) sys0[i + 1] = sys0[i] + active[i]->nrhs;
+      std::vector<int> first(mi.size() + 1, 0);
+      for (size_t k = 0; k <= mi.size(); ++k) first[k] = sys0[L2.first[k]];
       SysSet *ssp = &ss;
-      const long long N2 = off2.back();
+      const long long N2 = L2.total;
       ss.apply = [mi, planp, N2, first, ssp](int precision, const double *in, double *out,
                                              hipStream_t st) {
         std::vector<char> act(mi.size(), 1);
