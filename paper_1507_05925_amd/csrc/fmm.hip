@@ -251,14 +251,15 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
 // 2p x 2p matrix (rows and columns interleave real and imaginary parts), in 16x16x4 float64
 // MFMA tiles: lane (j, q) = (lane % 16, lane / 16) holds A[j][q] and B[q][j] of a k-step and
 // rows q + 4r of column j of an accumulator tile.
-// One workgroup per (group, set): its four waves split the k-steps (each loads a quarter of U
-// and keeps every row tile), then the four partial tiles are added in wave order through LDS.
+// One workgroup of eight waves per (group, set): waves 0-3 take the first ceil(RT/2) row tiles and
+// waves 4-7 the rest, and within each half the four waves split the k-steps (each loads a quarter
+// of U); the four partial tiles of every row tile are then added in wave order through LDS.
 // A is read from the offset table in LDS (real and imaginary planes), B from the multipoles.
 // Offsets are taken in increasing order: each target's sum has a fixed order.
 typedef double m2l_d4 __attribute__((ext_vector_type(4)));
 
 template <int P>
-__global__ __launch_bounds__(256) void k_m2l(int nbox, const int *__restrict__ grp_ptr,
+__global__ __launch_bounds__(512) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
                                             const int *__restrict__ grp_tgt,
                                             const int *__restrict__ grp_lvl,
                                             const int *__restrict__ item_off,
@@ -268,8 +269,9 @@ __global__ __launch_bounds__(256) void k_m2l(int nbox, const int *__restrict__ g
                                             const double2 *__restrict__ Vtab,
                                             const double2 *__restrict__ Mexp,
                                             double2 *__restrict__ Lexp) {
-  constexpr int RT = 2 * P / 16;  // accumulator row tiles
-  constexpr int KW = P / 8;       // k-steps per wave (2p / 4 in all, over four waves)
+  constexpr int RT = 2 * P / 16;      // accumulator row tiles
+  constexpr int RH = (RT + 1) / 2;    // row tiles of the first half
+  constexpr int KW = P / 8;           // k-steps per wave (2p / 4 in all, over four waves)
   extern __shared__ double lds_v[];
   double *VR = lds_v, *VI = lds_v + 40 * 2 * P;
   for (int i = threadIdx.x; i < 40 * 2 * P; i += blockDim.x) {
@@ -278,49 +280,77 @@ __global__ __launch_bounds__(256) void k_m2l(int nbox, const int *__restrict__ g
     VI[i] = v.y;
   }
   __syncthreads();
-  const int g = blockIdx.x, set = blockIdx.y;
+  const int g = g0 + blockIdx.x, set = blockIdx.y;
   const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wv & 3, half = wv >> 2;
+  const int rt0 = half ? RH : 0;
   // A[i][k] with i = 2n + ci, k = 2m + ck: Re V[n+m] if ci == ck, Im V[n+m] if (1, 0),
   // -Im V[n+m] if (0, 1). This lane: ci = j & 1, ck = q & 1, n + m = 8 rt + 2 kk + abase.
   const int ci = j & 1, ck = q & 1;
   const double *plane = ci == ck ? VR : VI;
   const double sgn = (ci == 0 && ck == 1) ? -1.0 : 1.0;
   const int abase = (j >> 1) + (q >> 1) + 2 * KW * w;
-  m2l_d4 acc[RT];
+  m2l_d4 acc[RH];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) acc[rt] = m2l_d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < RH; ++t) acc[t] = m2l_d4{0.0, 0.0, 0.0, 0.0};
   const double *Ms = reinterpret_cast<const double *>(Mexp + (size_t)set * nbox * P);
   const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
+  // B[k][j] = component ck of u_src[m]: k = 4 kk + q, m = 2 kk + q / 2, kk = KW w + kl.
+  // Software pipeline: the loads of item it+1's B and of item it+2's source index are issued
+  // before item it's MFMAs.
+  const int lofs = 2 * (q >> 1) + ck + 4 * KW * w;
+  // loads are unconditional (a missing source reads box 0) and zeroed afterwards, so no branch
+  // separates the prefetch from the MFMAs
+  auto load_b = [&](double *b, int src) {
+    const double *u = Ms + (size_t)max(src, 0) * 2 * P + lofs;
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = u[4 * kl];
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = src < 0 ? 0.0 : b[kl];
+  };
+  double bn[KW];
+  load_b(bn, i0 < i1 ? item_src[i0 * 16 + j] : -1);
+  int src_nn = i0 + 1 < i1 ? item_src[(i0 + 1) * 16 + j] : -1;
   for (int it = i0; it < i1; ++it) {
     const int o = item_off[it];
-    const int src = item_src[it * 16 + j];
-    // B[k][j] = component ck of u_src[m]: k = 4 kk + q, m = 2 kk + q / 2, kk = KW w + kl
     double b[KW];
-    const double *u = Ms + (size_t)(src < 0 ? 0 : src) * 2 * P + 2 * (q >> 1) + ck + 4 * KW * w;
 #pragma unroll
-    for (int kl = 0; kl < KW; ++kl) b[kl] = src < 0 ? 0.0 : u[4 * kl];
-    const double *Ap = plane + o * 2 * P + abase;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int kl = 0; kl < KW; ++kl) b[kl] = bn[kl];
+    load_b(bn, it + 1 < i1 ? src_nn : -1);
+    src_nn = it + 2 < i1 ? item_src[(it + 2) * 16 + j] : -1;
+    const double *Ap = plane + o * 2 * P + abase + 8 * rt0;
+    // k-step outer, row tile inner: consecutive MFMAs write different accumulators
+    if (rt0 + RH <= RT) {
 #pragma unroll
       for (int kl = 0; kl < KW; ++kl)
-        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * rt + 2 * kl], b[kl], acc[rt], 0,
-                                                       0, 0);
+#pragma unroll
+        for (int t = 0; t < RH; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
+                                                        0, 0, 0);
+    } else {  // the second half holds one tile fewer
+#pragma unroll
+      for (int kl = 0; kl < KW; ++kl)
+#pragma unroll
+        for (int t = 0; t < RH - 1; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
+                                                        0, 0, 0);
+    }
   }
-  // partial tiles of the four waves through LDS (the table is no longer needed)
+  // partial tiles through LDS (the table is no longer needed): red[w][rt][r][lane]
   __syncthreads();
-  double *red = lds_v;  // [wave][rt][r][lane]
+  double *red = lds_v;
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+  for (int t = 0; t < RH; ++t)
+    if (rt0 + t < RT)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[((w * RT + rt) * 4 + r) * 64 + lane] = acc[rt][r];
+      for (int r = 0; r < 4; ++r) red[((w * RT + rt0 + t) * 4 + r) * 64 + lane] = acc[t][r];
   __syncthreads();
-  const int t = grp_tgt[g * 16 + j];
-  if (t < 0) return;
+  const int tb = grp_tgt[g * 16 + j];
+  if (tb < 0) return;
   const double sc = inv_h[grp_lvl[g]];
-  double *out = reinterpret_cast<double *>(Lexp + ((size_t)set * nbox + t) * P) + (q & 1);
-  for (int rt = w; rt < RT; rt += 4)
+  double *out = reinterpret_cast<double *>(Lexp + ((size_t)set * nbox + tb) * P) + (q & 1);
+  for (int rt = wv; rt < RT; rt += 8)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double v = 0.0;
@@ -906,8 +936,11 @@ bool m2l_lds_raised(size_t bytes) {
   return true;
 }
 
+// M2L for groups [ga, gb) (groups are ordered by level, so a level is one range)
 template <int P>
-int launch_m2l(const FmmTree &t, int nsets, const double2 *Mexp, double2 *Lexp, hipStream_t s) {
+int launch_m2l(const FmmTree &t, int ga, int gb, int nsets, const double2 *Mexp, double2 *Lexp,
+               hipStream_t s) {
+  if (gb <= ga) return BIE_OK;
   const size_t lds = (size_t)2 * 40 * 2 * P * sizeof(double);
   if (!m2l_lds_raised<P>(lds)) {
     set_error("fmm: M2L table does not fit in LDS for this order");
@@ -915,7 +948,7 @@ int launch_m2l(const FmmTree &t, int nsets, const double2 *Mexp, double2 *Lexp, 
   }
   // the reduction of the four partial tiles reuses the table's LDS (1024 P <= 1280 P bytes)
   static_assert(4 * (2 * P / 16) * 4 * 64 <= 2 * 40 * 2 * P, "M2L reduction exceeds the table");
-  hipLaunchKernelGGL(k_m2l<P>, dim3(t.ngroup, nsets), dim3(256), lds, s, t.nbox, t.grp_ptr,
+  hipLaunchKernelGGL(k_m2l<P>, dim3(gb - ga, nsets), dim3(512), lds, s, ga, t.nbox, t.grp_ptr,
                      t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_m2l,
                      Mexp, Lexp);
   BIE_HIP_CHECK(hipGetLastError());
@@ -1016,7 +1049,7 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
     }
     if (t.ngroup > 0) {
       ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
-      BIE_TRY(launch_m2l<P>(t, nsets, Mexp, Lexp, s));
+      BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
     }
     for (int l = 2; l < t.L; ++l) {
       const int nb = t.level_off[l + 2] - t.level_off[l + 1];
