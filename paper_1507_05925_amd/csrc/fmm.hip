@@ -54,7 +54,7 @@ struct FmmTree {
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
   double2 *T_m2l = nullptr;  // Hankel vectors [40][2p]
   double2 *T_tau = nullptr;  // M2M / L2L Toeplitz vectors [4][2p] (p zeros, then tau)
-  double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n / n!  and  1/n!
+  double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n c^n / n!  and  c^n / n!
   double *inv_h = nullptr;  // [L+1]
   DevBuf work;              // charges + expansions
 };
@@ -131,7 +131,8 @@ __device__ __forceinline__ double rl64(double v, int l) {
 }
 
 // P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
-// u_n = (1/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h. Lanes take 64 sources at a time and
+// u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in). Lanes
+// take 64 sources at a time and
 // raise their powers incrementally; eight coefficients at a time go through LDS, where lane
 // (b, g) = (lane / 8, lane % 8) sums sources g, g+8, ..., g+56 of coefficient b, and the eight
 // partials of b are combined across lanes. Fixed order: the result is reproducible.
@@ -199,10 +200,11 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
 }
 
 // The translations between a box and its children are Toeplitz products with one vector per
-// child position: with d = (child centre - parent centre) / parent size = (+-1/4, +-1/4) and
-// tau[k] = d^k / k!,
-//   M2M (stored u_n = a_n / n!):  u_parent[n] = sum_{m <= n} 2^-m u_child[m] tau[n - m]
-//   L2L (plain coefficients b):   b_child[n] = (2^-n / n!) sum_{m >= n} m! b_parent[m] tau[m - n]
+// child position: with d = (child centre - parent centre) / parent size = (+-1/4, +-1/4), the
+// table scale s and tau[k] = (s d)^k / k!,
+//   M2M (stored u_n = a_n s^n / n!):  u_parent[n] = sum_{m <= n} 2^-m u_child[m] tau[n - m]
+//   L2L (plain coefficients b):  b_child[n] = 2^-n (s^n/n!) sum_{m >= n} (m!/s^m) b_parent[m]
+//                                                                          tau[m - n]
 // The table holds, per position, p zeros followed by tau[0..p-1], so that both sums read
 // tau at a lane-dependent offset without a bound test. It sits in LDS; the source coefficient
 // of step m is read from lane m (readlane, wave-uniform).
@@ -242,8 +244,9 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
 }
 
 // M2L for all boxes of levels >= 2, written into Lexp, on the matrix cores. Multipoles are stored
-// as u_m = a_m / m!, which turns the operator for a box offset d into a Hankel product
-//   b_n = (1/h) ((-1)^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / d^(k+1).
+// as u_m = a_m s^m / m! (s: the table scale), which turns the operator for a box offset d into a
+// Hankel product
+//   b_n = (1/h) ((-1)^n s^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / (s^k d^(k+1)).
 // Target boxes are grouped 16 at a time (same level, same position within the parent, so their
 // interaction lists share most offsets). For each offset d used by a group, the 16 multipoles
 // (one per target; zero where a target has no source at that offset) form the columns of U, and
@@ -796,35 +799,40 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   }
   t.ngroup = (int)grp_lvl.size();
   t.nitem = (int)item_off.size();
+  // All tables carry a scale s = max(1, 2p/e): multipoles are stored as u_m = a_m s^m / m!, so
+  // the M2L Hankel vectors become V_d[k] = k! / (s^k d^(k+1)), the output factor
+  // (-1)^n s^n / n!, and the child-parent Toeplitz vectors tau[k] = (s d)^k / k!. The products
+  // are unchanged; every table entry stays of moderate size (float32 range included).
+  const double csc = std::max(1.0, 2.0 * p / 2.718281828459045);
   std::vector<double2> Tm2l((size_t)40 * 2 * p);
   for (int dx = -3; dx <= 3; ++dx)
     for (int dy = -3; dy <= 3; ++dy) {
       const int o = ocompact[(dx + 3) * 7 + (dy + 3)];
       if (o < 0) continue;
       const cd dinv = 1.0 / cd(dx, dy);
-      cd v = dinv;  // k = 0: 0!/d
+      cd v = dinv;  // k = 0: 0! / (c^0 d)
       for (int k = 0; k < 2 * p; ++k) {
         Tm2l[(size_t)o * 2 * p + k] = make_double2(v.real(), v.imag());
-        v = v * dinv * (double)(k + 1);
+        v = v * dinv * ((double)(k + 1) / csc);
       }
     }
   std::vector<double> fact_out(p), fact_in(p);
   {
-    double f = 1.0;
+    double f = 1.0;  // s^n / n!
     for (int n = 0; n < p; ++n) {
-      if (n > 0) f *= n;
-      fact_in[n] = 1.0 / f;
-      fact_out[n] = ((n & 1) ? -1.0 : 1.0) / f;
+      if (n > 0) f *= csc / n;
+      fact_in[n] = f;
+      fact_out[n] = (n & 1) ? -f : f;
     }
   }
-  // translation vectors: per child position, p zeros then tau[k] = d^k / k!
+  // translation vectors: per child position, p zeros then tau[k] = (s d)^k / k!
   std::vector<double2> Ttau((size_t)8 * p, make_double2(0.0, 0.0));
   for (int cpos = 0; cpos < 4; ++cpos) {
     const cd delta(((cpos & 1) ? 0.25 : -0.25), ((cpos & 2) ? 0.25 : -0.25));
     cd v = 1.0;
     for (int k = 0; k < p; ++k) {
       Ttau[(size_t)cpos * 2 * p + p + k] = make_double2(v.real(), v.imag());
-      v = v * delta / (double)(k + 1);
+      v = v * delta * (csc / (double)(k + 1));
     }
   }
   std::vector<double> inv_h(L + 1);

@@ -3,8 +3,8 @@
 // float64 iterative refinement around a float32 far-field apply (BIE_MIXED).
 //
 // Device: Krylov basis V [m+1][Ntot] (all systems back to back), applies, dot products, updates.
-// Host: one (m+1) x m Hessenberg matrix per system (its new column is read back once per step),
-// Givens rotations, triangular solves. The true residual ||f - A x|| / ||f|| with the float64
+// Host: one (m+1) x m Hessenberg matrix per system (its new column is read back once per step,
+// while the next step already runs on the device), Givens rotations, triangular solves. The true residual ||f - A x|| / ||f|| with the float64
 // operator decides convergence at the end of every cycle. The paper iterates GMRES to a
 // relative residual of 1e-6 with unstated restart details; x0 = 0 and CGS2 are choices made here.
 #include <hip/hip_runtime.h>
@@ -107,7 +107,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   const int S = sg.S;
   const long long N = sg.Ntot;
   const long long hs = m + 2;
-  std::vector<double> fnorm, beta, hh2, hn;
+  std::vector<double> fnorm, beta;
   if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
   BIE_TRY(seg_nrm2(sg, f, wk.nrm, wk.scratch, s));
   BIE_TRY(read_host(mem, wk.nrm, S, fnorm, s));
@@ -151,20 +151,37 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     for (int r = 0; r < S; ++r) gv[(size_t)r * (m + 1)] = beta[r];
     std::vector<int> jdone(S, -1);
     int jend = -1;
-    for (int j = 0; j < m; ++j) {
+    // Arnoldi step j: apply, CGS2 against V_0..V_j, V_{j+1} = w / ||w||, and an asynchronous copy
+    // of the new Hessenberg column into pinned slot j % 2. Steps run one ahead of the host: step
+    // j+1 is queued before the host waits for step j's column (a cycle that stops at step j
+    // leaves step j+1's work unused).
+    const size_t slot = (size_t)S * hs + S;
+    BIE_TRY(mem.ensure_pinned(2 * slot * sizeof(double)));
+    auto step = [&](int j) -> int {
       double *Vj = wk.V + (size_t)j * N;
       double *Vj1 = wk.V + (size_t)(j + 1) * N;
       BIE_TRY(apply(ss, precision, Vj, wk.w, st, s));
+      // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||
+      BIE_TRY(seg_dots_partial(sg, j + 1, wk.V, N, wk.w, wk.scratch, s));
+      BIE_TRY(seg_comb_partial(sg, j + 1, wk.V, N, wk.scratch, nullptr, wk.h1, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_dots_partial(sg, j + 1, wk.V, N, wk.w, wk.scratch, s));
+      BIE_TRY(seg_comb_partial(sg, j + 1, wk.V, N, wk.scratch, wk.h1, wk.h2, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_dots_partial(sg, 1, wk.w, 0, wk.w, wk.scratch, s));
+      BIE_TRY(seg_scale_partial(sg, wk.scratch, wk.w, wk.nrm, Vj1, s));
+      double *dst = mem.pinned + (j & 1) * slot;
+      BIE_HIP_CHECK(hipMemcpyAsync(dst, wk.h2, (size_t)S * hs * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+      BIE_HIP_CHECK(hipMemcpyAsync(dst + (size_t)S * hs, wk.nrm, S * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+      BIE_HIP_CHECK(hipEventRecord(mem.ev[j & 1], s));
+      return BIE_OK;
+    };
+    BIE_TRY(step(0));
+    for (int j = 0; j < m; ++j) {
       st.iters += 1;
-      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
-      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h2, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_nrm2(sg, wk.w, wk.nrm, wk.scratch, s));
-      BIE_TRY(seg_scale_to(sg, wk.w, wk.nrm, Vj1, s));
-      BIE_TRY(seg_add_h(S, wk.h1, wk.h2, j + 1, hs, s));
-      BIE_TRY(read_host(mem, wk.h2, (size_t)S * hs, hh2, s));
-      BIE_TRY(read_host(mem, wk.nrm, S, hn, s));
+      if (j + 1 < m && st.iters < max_iter) BIE_TRY(step(j + 1));
+      BIE_HIP_CHECK(hipEventSynchronize(mem.ev[j & 1]));
+      const double *hh2 = mem.pinned + (j & 1) * slot, *hn = hh2 + (size_t)S * hs;
       bool all_done = true;
       for (int r = 0; r < S; ++r) {
         if (!active[r] || jdone[r] >= 0) continue;
@@ -195,6 +212,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       jend = j;
       if (all_done || st.iters >= max_iter) break;
     }
+    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the step queued ahead, if any, is complete
     // y = H^{-1} g (upper triangular), x += V y
     const int nv = jend + 1;
     std::vector<double> yv((size_t)S * hs, 0.0);
@@ -235,6 +253,8 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
 }
 
 int SolverMem::ensure_pinned(size_t bytes) {
+  for (auto &e : ev)
+    if (!e) BIE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (pinned_bytes >= bytes) return BIE_OK;
   if (pinned) {
     BIE_HIP_CHECK(hipHostFree(pinned));
@@ -256,6 +276,10 @@ void SolverMem::release() {
   if (pinned) (void)hipHostFree(pinned);
   pinned = nullptr;
   pinned_bytes = 0;
+  for (auto &e : ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
 }
 
 // Solves every system of ss to o.tol (relative, float64 operator). relres_out gets the final true
