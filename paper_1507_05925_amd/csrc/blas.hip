@@ -81,81 +81,6 @@ __global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__r
   }
 }
 
-// Sum over the chunks of system sy of partial[l * C + .] for l = 0..nvec-1 into hl[l] (LDS),
-// every workgroup redundantly; each value is added exactly as the two-stage reduction adds it
-// (64 lanes over the chunks in order, then a shuffle tree), so results are bitwise the same.
-__device__ inline void system_sums(int nvec, int C, int a, int b, const double *__restrict__ partial,
-                                   double *hl, int do_sqrt) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int l = wid; l < nvec; l += kBlock / 64) {
-    double acc = 0.0;
-    for (int c = a + lane; c < b; c += 64) acc += partial[(long long)l * C + c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) hl[l] = do_sqrt ? sqrt(acc) : acc;
-  }
-  __syncthreads();
-}
-
-// Fused second stage + combination: h = the system's sums of partial (from k_dots_stage1), then
-// w += sign * sum_l V_l h_l on the chunk. The first workgroup of each system writes h to
-// hout[s * hs + l], plus hadd[s * hs + l] when hadd is given. Grid (C, kSub).
-constexpr int kSubF = 4;
-__global__ __launch_bounds__(kBlock) void k_comb_partial(int nvec, int C,
-                                                        const int *__restrict__ csys,
-                                                        const int *__restrict__ sys_chunk,
-                                                        const long long *__restrict__ c0,
-                                                        const long long *__restrict__ c1,
-                                                        const double *__restrict__ V,
-                                                        long long vstride,
-                                                        const double *__restrict__ partial,
-                                                        const double *__restrict__ hadd,
-                                                        double *__restrict__ hout, long long hs,
-                                                        double *__restrict__ w, double sign) {
-  extern __shared__ double hl[];
-  const int c = blockIdx.x;
-  const int s = csys[c];
-  const int a = sys_chunk[s], b = sys_chunk[s + 1];
-  system_sums(nvec, C, a, b, partial, hl, 0);
-  if (c == a && blockIdx.y == 0)
-    for (int l = threadIdx.x; l < nvec; l += kBlock)
-      hout[s * hs + l] = hadd ? hadd[s * hs + l] + hl[l] : hl[l];
-  for (long long i = c0[c] + blockIdx.y * kBlock + threadIdx.x; i < c1[c]; i += kSubF * kBlock) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = 0;
-    for (; l + 4 <= nvec; l += 4) {
-      a0 = fma(V[l * vstride + i], hl[l], a0);
-      a1 = fma(V[(l + 1) * vstride + i], hl[l + 1], a1);
-      a2 = fma(V[(l + 2) * vstride + i], hl[l + 2], a2);
-      a3 = fma(V[(l + 3) * vstride + i], hl[l + 3], a3);
-    }
-    if (l < nvec) a0 = fma(V[l * vstride + i], hl[l], a0);
-    if (l + 1 < nvec) a1 = fma(V[(l + 1) * vstride + i], hl[l + 1], a1);
-    if (l + 2 < nvec) a2 = fma(V[(l + 2) * vstride + i], hl[l + 2], a2);
-    w[i] += sign * ((a0 + a1) + (a2 + a3));
-  }
-}
-
-// Fused norm second stage + scaling: d = sqrt(the system's sum of partial), v = w / d; the first
-// workgroup of each system writes d to nrm[s].
-__global__ __launch_bounds__(kBlock) void k_scale_partial(int C, const int *__restrict__ csys,
-                                                         const int *__restrict__ sys_chunk,
-                                                         const long long *__restrict__ c0,
-                                                         const long long *__restrict__ c1,
-                                                         const double *__restrict__ partial,
-                                                         const double *__restrict__ w,
-                                                         double *__restrict__ nrm,
-                                                         double *__restrict__ v) {
-  __shared__ double hl[1];
-  const int c = blockIdx.x;
-  const int s = csys[c];
-  const int a = sys_chunk[s], b = sys_chunk[s + 1];
-  system_sums(1, C, a, b, partial, hl, 1);
-  const double d = hl[0];
-  if (c == a && threadIdx.x == 0) nrm[s] = d;
-  for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) v[i] = d > 0.0 ? w[i] / d : 0.0;
-}
-
 __global__ __launch_bounds__(kBlock) void k_scale_to(const int *__restrict__ csys,
                                                     const long long *__restrict__ c0,
                                                     const long long *__restrict__ c1,
@@ -218,34 +143,6 @@ int seg_scale_to(const Segments &sg, const double *w, const double *den, double 
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                      total, a, x, b, y);
-  BIE_HIP_CHECK(hipGetLastError());
-  return BIE_OK;
-}
-
-int seg_dots_partial(const Segments &sg, int nvec, const double *V, long long vstride,
-                     const double *w, double *partial, hipStream_t s) {
-  if (nvec <= 0) return BIE_OK;
-  hipLaunchKernelGGL(k_dots_stage1, dim3(sg.C, nvec), dim3(kBlock), 0, s, sg.C, sg.c0, sg.c1, V,
-                     vstride, w, partial);
-  BIE_HIP_CHECK(hipGetLastError());
-  return BIE_OK;
-}
-
-int seg_comb_partial(const Segments &sg, int nvec, const double *V, long long vstride,
-                     const double *partial, const double *hadd, double *hout, long long hs,
-                     double *w, double sign, hipStream_t s) {
-  if (nvec <= 0) return BIE_OK;
-  hipLaunchKernelGGL(k_comb_partial, dim3(sg.C, kSubF), dim3(kBlock), nvec * sizeof(double), s,
-                     nvec, sg.C, sg.csys, sg.sys_chunk, sg.c0, sg.c1, V, vstride, partial, hadd,
-                     hout, hs, w, sign);
-  BIE_HIP_CHECK(hipGetLastError());
-  return BIE_OK;
-}
-
-int seg_scale_partial(const Segments &sg, const double *partial, const double *w, double *nrm,
-                      double *v, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_partial, dim3(sg.C), dim3(kBlock), 0, s, sg.C, sg.csys,
-                     sg.sys_chunk, sg.c0, sg.c1, partial, w, nrm, v);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

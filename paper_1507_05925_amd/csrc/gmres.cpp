@@ -162,12 +162,13 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       double *Vj1 = wk.V + (size_t)(j + 1) * N;
       BIE_TRY(apply(ss, precision, Vj, wk.w, st, s));
       // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||
-      BIE_TRY(seg_dots_partial(sg, j + 1, wk.V, N, wk.w, wk.scratch, s));
-      BIE_TRY(seg_comb_partial(sg, j + 1, wk.V, N, wk.scratch, nullptr, wk.h1, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_dots_partial(sg, j + 1, wk.V, N, wk.w, wk.scratch, s));
-      BIE_TRY(seg_comb_partial(sg, j + 1, wk.V, N, wk.scratch, wk.h1, wk.h2, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_dots_partial(sg, 1, wk.w, 0, wk.w, wk.scratch, s));
-      BIE_TRY(seg_scale_partial(sg, wk.scratch, wk.w, wk.nrm, Vj1, s));
+      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
+      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
+      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h2, hs, wk.w, -1.0, s));
+      BIE_TRY(seg_nrm2(sg, wk.w, wk.nrm, wk.scratch, s));
+      BIE_TRY(seg_scale_to(sg, wk.w, wk.nrm, Vj1, s));
+      BIE_TRY(seg_add_h(S, wk.h1, wk.h2, j + 1, hs, s));
       double *dst = mem.pinned + (j & 1) * slot;
       BIE_HIP_CHECK(hipMemcpyAsync(dst, wk.h2, (size_t)S * hs * sizeof(double),
                                    hipMemcpyDeviceToHost, s));

@@ -132,16 +132,6 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
 int seg_scale_to(const Segments &sg, const double *w, const double *den, double *v, hipStream_t s);
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
 int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
-// Fused forms for one Arnoldi step: first stage only (partials per chunk and vector); second
-// stage inside the combination (w += sign V h, h written to hout, plus hadd if given) and inside
-// the scaling (v = w / ||w||, norms written to nrm). Same sums as seg_dots / seg_nrm2.
-int seg_dots_partial(const Segments &sg, int nvec, const double *V, long long vstride,
-                     const double *w, double *partial, hipStream_t s);
-int seg_comb_partial(const Segments &sg, int nvec, const double *V, long long vstride,
-                     const double *partial, const double *hadd, double *hout, long long hs,
-                     double *w, double sign, hipStream_t s);
-int seg_scale_partial(const Segments &sg, const double *partial, const double *w, double *nrm,
-                      double *v, hipStream_t s);
 
 // ---- gmres.cpp ----------------------------------------------------------------------------
 int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const double *f,
