@@ -84,11 +84,34 @@ namespace {
 
 using cd = std::complex<double>;
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex numbers as float2 / double2; the expansions of the mixed-precision Laplace apply are
+// float, everything else double.
+template <class T> struct cx_of;
+template <> struct cx_of<double> { using type = double2; };
+template <> struct cx_of<float> { using type = float2; };
+template <class T>
+using cx = typename cx_of<T>::type;
+
+template <class T>
+__device__ inline cx<T> mkc(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
 }
-__device__ inline double2 cfma(double2 a, double2 b, double2 c) {  // a*b + c
-  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+template <class V>
+__device__ inline V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class V>
+__device__ inline V cfma(V a, V b, V c) {  // a*b + c
+  V r;
+  r.x = fma(a.x, b.x, fma(-a.y, b.y, c.x));
+  r.y = fma(a.x, b.y, fma(a.y, b.x, c.y));
+  return r;
 }
 
 __device__ inline double rcp64(double a) {
@@ -97,12 +120,13 @@ __device__ inline double rcp64(double a) {
   return fma(y, e, y);
 }
 
-// Charges in sorted order: Laplace set r is (s, 0); Stokes sets 3r, 3r+1, 3r+2 are rho,
-// conj(rho), rho conj(z). Also the near-field source records S4[r][j] = (x, y, s, 0), resp.
-// (x, y, rho).
+// Charges in sorted order: Laplace set r is (s, 0) (in float when Qf is given); Stokes sets 3r,
+// 3r+1, 3r+2 are rho, conj(rho), rho conj(z). Also the near-field source records
+// S4[r][j] = (x, y, s, 0), resp. (x, y, rho), always in float64.
 __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
                          const double2 *__restrict__ xs, const double *__restrict__ s64,
-                         double2 *__restrict__ Q, double4 *__restrict__ S4) {
+                         double2 *__restrict__ Q, float2 *__restrict__ Qf,
+                         double4 *__restrict__ S4) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const int k = perm[j];
@@ -110,7 +134,10 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
   for (int r = 0; r < R; ++r) {
     if (kind == 0) {
       const double v = s64[(size_t)r * M + k];
-      Q[(size_t)r * M + j] = make_double2(v, 0.0);
+      if (Qf)
+        Qf[(size_t)r * M + j] = make_float2((float)v, 0.0f);
+      else
+        Q[(size_t)r * M + j] = make_double2(v, 0.0);
       S4[(size_t)r * M + j] = make_double4(z.x, z.y, v, 0.0);
     } else {
       const double2 rho = make_double2(s64[(size_t)r * 2 * M + 2 * k], s64[(size_t)r * 2 * M + 2 * k + 1]);
@@ -123,11 +150,14 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
 }
 
 // P2M at the leaves: grid (nleaf, nsets), one lane per coefficient.
-// Wave-uniform read of lane l's double (l a compile-time or uniform index).
-__device__ __forceinline__ double rl64(double v, int l) {
+// Wave-uniform read of lane l's value (l a compile-time or uniform index).
+__device__ __forceinline__ double rl(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
   return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float rl(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
@@ -136,31 +166,31 @@ __device__ __forceinline__ double rl64(double v, int l) {
 // raise their powers incrementally; eight coefficients at a time go through LDS, where lane
 // (b, g) = (lane / 8, lane % 8) sums sources g, g+8, ..., g+56 of coefficient b, and the eight
 // partials of b are combined across lanes. Fixed order: the result is reproducible.
-template <int P>
+template <int P, class T>
 __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const int *__restrict__ leaf_start,
                                            const int *__restrict__ leaf_box,
                                            const double2 *__restrict__ center,
                                            const double2 *__restrict__ xs,
-                                           const double2 *__restrict__ Q,
+                                           const cx<T> *__restrict__ Q,
                                            const double *__restrict__ fact_in,
-                                           double2 *__restrict__ Mexp) {
-  __shared__ double2 sh[8 * 64];
+                                           cx<T> *__restrict__ Mexp) {
+  __shared__ cx<T> sh[8 * 64];
   const int leaf = blockIdx.x, set = blockIdx.y, lane = threadIdx.x;
   const int g = lane & 7, bb = lane >> 3;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
-  const double2 *q = Q + (size_t)set * M;
-  double2 acc[P / 8];
+  const cx<T> *q = Q + (size_t)set * M;
+  cx<T> acc[P / 8];
 #pragma unroll
-  for (int k = 0; k < P / 8; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int k = 0; k < P / 8; ++k) acc[k] = mkc<T>(0, 0);
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
   for (int jb = j0; jb < j1; jb += 64) {
     const int j = jb + lane;
-    double2 w = make_double2(0.0, 0.0), t = w;
+    cx<T> w = mkc<T>(0, 0), t = w;
     if (j < j1) {
-      const double2 z = xs[j];
-      w = make_double2((z.x - c.x) * inv_h, (z.y - c.y) * inv_h);
+      const double2 z = xs[j];  // leaf-relative coordinates formed in float64
+      w = mkc<T>((T)((z.x - c.x) * inv_h), (T)((z.y - c.y) * inv_h));
       t = q[j];
     }
 #pragma unroll
@@ -171,10 +201,10 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
         t = cmul(t, w);
       }
       __syncthreads();
-      double2 sum = make_double2(0.0, 0.0);
+      cx<T> sum = mkc<T>(0, 0);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const double2 v = sh[bb * 64 + r * 8 + g];
+        const cx<T> v = sh[bb * 64 + r * 8 + g];
         sum.x += v.x;
         sum.y += v.y;
       }
@@ -189,12 +219,12 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
     }
   }
   if (g == 0) {
-    double2 *o = Mexp + ((size_t)set * nbox + box) * P;
+    cx<T> *o = Mexp + ((size_t)set * nbox + box) * P;
 #pragma unroll
     for (int k = 0; k < P / 8; ++k) {
       const int n = 8 * k + bb;
-      const double f = fact_in[n];
-      o[n] = make_double2(acc[k].x * f, acc[k].y * f);
+      const T f = (T)fact_in[n];
+      o[n] = mkc<T>(acc[k].x * f, acc[k].y * f);
     }
   }
 }
@@ -210,13 +240,12 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
 // of step m is read from lane m (readlane, wave-uniform).
 
 // M2M for one level: waves walk (parent box, set) items with a grid stride.
-template <int P>
+template <int P, class T>
 __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nsets,
                                             const int *__restrict__ child,
-                                            const double2 *__restrict__ tau,
-                                            double2 *Mexp) {
-  __shared__ double2 tp[8 * P];
-  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = tau[i];
+                                            const double2 *__restrict__ tau, cx<T> *Mexp) {
+  __shared__ cx<T> tp[8 * P];
+  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = mkc<T>((T)tau[i].x, (T)tau[i].y);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int n = lane < P ? lane : P - 1;
@@ -226,20 +255,20 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
        item += (long long)gridDim.x * 4) {
     const int set = (int)(item / nb);
     const int b = off + (int)(item % nb);
-    double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+    cx<T> a0 = mkc<T>(0, 0), a1 = a0;
     for (int cpos = 0; cpos < 4; ++cpos) {
       const int ch = child[4 * b + cpos];
       if (ch < 0) continue;
-      const double2 u = Mexp[((size_t)set * nbox + ch) * P + n];
-      const double2 v = make_double2(ldexp(u.x, -n), ldexp(u.y, -n));
-      const double2 *tc = tp + cpos * 2 * P + P + n;  // tc[-m] = tau[n - m], zero for m > n
+      const cx<T> u = Mexp[((size_t)set * nbox + ch) * P + n];
+      const cx<T> v = mkc<T>(ldexp(u.x, -n), ldexp(u.y, -n));
+      const cx<T> *tc = tp + cpos * 2 * P + P + n;  // tc[-m] = tau[n - m], zero for m > n
 #pragma unroll
       for (int m = 0; m < P; m += 2) {
-        a0 = cfma(make_double2(rl64(v.x, m), rl64(v.y, m)), tc[-m], a0);
-        a1 = cfma(make_double2(rl64(v.x, m + 1), rl64(v.y, m + 1)), tc[-m - 1], a1);
+        a0 = cfma(mkc<T>(rl(v.x, m), rl(v.y, m)), tc[-m], a0);
+        a1 = cfma(mkc<T>(rl(v.x, m + 1), rl(v.y, m + 1)), tc[-m - 1], a1);
       }
     }
-    if (lane < P) Mexp[((size_t)set * nbox + b) * P + n] = make_double2(a0.x + a1.x, a0.y + a1.y);
+    if (lane < P) Mexp[((size_t)set * nbox + b) * P + n] = mkc<T>(a0.x + a1.x, a0.y + a1.y);
   }
 }
 
@@ -364,21 +393,125 @@ __global__ __launch_bounds__(512) void k_m2l(int g0, int nbox, const int *__rest
     }
 }
 
+// The same M2L in float32 for the mixed-precision Laplace apply, on 16x16x4 float32 MFMA tiles.
+// Operand layout as above; the accumulator layout differs: lane (j, q) holds rows 4q + r of
+// column j, that is, real and imaginary parts of b_n and b_{n+1} for n = 8 rt + 2q.
+typedef float m2l_f4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__global__ __launch_bounds__(512) void k_m2l_f32(int nbox, const int *__restrict__ grp_ptr,
+                                                const int *__restrict__ grp_tgt,
+                                                const int *__restrict__ grp_lvl,
+                                                const int *__restrict__ item_off,
+                                                const int *__restrict__ item_src,
+                                                const double *__restrict__ inv_h,
+                                                const double *__restrict__ fact_out,
+                                                const double2 *__restrict__ Vtab,
+                                                const float2 *__restrict__ Mexp,
+                                                float2 *__restrict__ Lexp) {
+  constexpr int RT = 2 * P / 16;
+  constexpr int RH = (RT + 1) / 2;
+  constexpr int KW = P / 8;
+  extern __shared__ float lds_f[];
+  float *VR = lds_f, *VI = lds_f + 40 * 2 * P;
+  for (int i = threadIdx.x; i < 40 * 2 * P; i += blockDim.x) {
+    const double2 v = Vtab[i];
+    VR[i] = (float)v.x;
+    VI[i] = (float)v.y;
+  }
+  __syncthreads();
+  const int g = blockIdx.x, set = blockIdx.y;
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wv & 3, half = wv >> 2;
+  const int rt0 = half ? RH : 0;
+  const int ci = j & 1, ck = q & 1;
+  const float *plane = ci == ck ? VR : VI;
+  const float sgn = (ci == 0 && ck == 1) ? -1.0f : 1.0f;
+  const int abase = (j >> 1) + (q >> 1) + 2 * KW * w;
+  m2l_f4 acc[RH];
+#pragma unroll
+  for (int t = 0; t < RH; ++t) acc[t] = m2l_f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float *Ms = reinterpret_cast<const float *>(Mexp + (size_t)set * nbox * P);
+  const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
+  const int lofs = 2 * (q >> 1) + ck + 4 * KW * w;
+  auto load_b = [&](float *b, int src) {
+    const float *u = Ms + (size_t)max(src, 0) * 2 * P + lofs;
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = u[4 * kl];
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = src < 0 ? 0.0f : b[kl];
+  };
+  float bn[KW];
+  load_b(bn, i0 < i1 ? item_src[i0 * 16 + j] : -1);
+  int src_nn = i0 + 1 < i1 ? item_src[(i0 + 1) * 16 + j] : -1;
+  for (int it = i0; it < i1; ++it) {
+    const int o = item_off[it];
+    float b[KW];
+#pragma unroll
+    for (int kl = 0; kl < KW; ++kl) b[kl] = bn[kl];
+    load_b(bn, it + 1 < i1 ? src_nn : -1);
+    src_nn = it + 2 < i1 ? item_src[(it + 2) * 16 + j] : -1;
+    const float *Ap = plane + o * 2 * P + abase + 8 * rt0;
+    if (rt0 + RH <= RT) {
+#pragma unroll
+      for (int kl = 0; kl < KW; ++kl)
+#pragma unroll
+        for (int t = 0; t < RH; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
+                                                        0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kl = 0; kl < KW; ++kl)
+#pragma unroll
+        for (int t = 0; t < RH - 1; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
+                                                        0, 0, 0);
+    }
+  }
+  __syncthreads();
+  float *red = lds_f;  // [w][rt][r][lane]
+#pragma unroll
+  for (int t = 0; t < RH; ++t)
+    if (rt0 + t < RT)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((w * RT + rt0 + t) * 4 + r) * 64 + lane] = acc[t][r];
+  __syncthreads();
+  const int tb = grp_tgt[g * 16 + j];
+  if (tb < 0) return;
+  const double sc = inv_h[grp_lvl[g]];
+  float2 *out = Lexp + ((size_t)set * nbox + tb) * P;
+  for (int rt = wv; rt < RT; rt += 8) {
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float x = 0.0f;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) x += red[((ww * RT + rt) * 4 + r) * 64 + lane];
+      v[r] = x;
+    }
+    const int n = 8 * rt + 2 * q;
+    const float f0 = (float)(sc * fact_out[n]), f1 = (float)(sc * fact_out[n + 1]);
+    out[n] = make_float2(v[0] * f0, v[1] * f0);
+    out[n + 1] = make_float2(v[2] * f1, v[3] * f1);
+  }
+}
+
 // L2L from level l to l+1 (children of level l+1 boxes' parents), accumulated into Lexp; waves
 // walk (child box, set) items with a grid stride.
-template <int P>
+template <int P, class T>
 __global__ __launch_bounds__(256) void k_l2l(int nb, int off, int nbox, int nsets,
                                             const int *__restrict__ parent,
                                             const double2 *__restrict__ tau,
-                                            const double *__restrict__ fact_in, double2 *Lexp) {
-  __shared__ double2 tp[8 * P];
-  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = tau[i];
+                                            const double *__restrict__ fact_in, cx<T> *Lexp) {
+  __shared__ cx<T> tp[8 * P];
+  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = mkc<T>((T)tau[i].x, (T)tau[i].y);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int n = lane < P ? lane : P - 1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const double fi = fact_in[n];
-  const double sc = ldexp(fi, -n);
+  const T fi = (T)fact_in[n];
+  const T sc = ldexp(fi, -n);
   const long long total = (long long)nb * nsets;
   for (long long item = (long long)blockIdx.x * 4 + wave; item < total;
        item += (long long)gridDim.x * 4) {
@@ -386,18 +519,18 @@ __global__ __launch_bounds__(256) void k_l2l(int nb, int off, int nbox, int nset
     const int c = off + (int)(item % nb);
     const int pc = parent[c];
     const int cpos = pc & 3, pb = pc >> 2;
-    const double2 bp = Lexp[((size_t)set * nbox + pb) * P + n];
-    const double2 beta = make_double2(bp.x / fi, bp.y / fi);  // m! b_m on lane m
-    const double2 *tc = tp + cpos * 2 * P + P - n;           // tc[m] = tau[m - n], zero for m < n
-    double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+    const cx<T> bp = Lexp[((size_t)set * nbox + pb) * P + n];
+    const cx<T> beta = mkc<T>(bp.x / fi, bp.y / fi);  // m! b_m / s^m on lane m
+    const cx<T> *tc = tp + cpos * 2 * P + P - n;      // tc[m] = tau[m - n], zero for m < n
+    cx<T> a0 = mkc<T>(0, 0), a1 = a0;
 #pragma unroll
     for (int m = 0; m < P; m += 2) {
-      a0 = cfma(make_double2(rl64(beta.x, m), rl64(beta.y, m)), tc[m], a0);
-      a1 = cfma(make_double2(rl64(beta.x, m + 1), rl64(beta.y, m + 1)), tc[m + 1], a1);
+      a0 = cfma(mkc<T>(rl(beta.x, m), rl(beta.y, m)), tc[m], a0);
+      a1 = cfma(mkc<T>(rl(beta.x, m + 1), rl(beta.y, m + 1)), tc[m + 1], a1);
     }
     if (lane < P) {
-      double2 *o = Lexp + ((size_t)set * nbox + c) * P + n;
-      *o = make_double2(o->x + (a0.x + a1.x) * sc, o->y + (a0.y + a1.y) * sc);
+      cx<T> *o = Lexp + ((size_t)set * nbox + c) * P + n;
+      *o = mkc<T>(o->x + (a0.x + a1.x) * sc, o->y + (a0.y + a1.y) * sc);
     }
   }
 }
@@ -417,9 +550,9 @@ __device__ inline void eval_local(const double2 *b, double2 w, double ih, double
   dF = make_double2(dF.x * ih, dF.y * ih);
 }
 
-template <int P>
-__device__ inline double2 eval_value(const double2 *b, double2 w) {
-  double2 F = b[P - 1];
+template <int P, class V>
+__device__ inline V eval_value(const V *b, V w) {
+  V F = b[P - 1];
 #pragma unroll
   for (int n = P - 1; n >= 1; --n) F = cfma(F, w, b[n - 1]);
   return F;
@@ -501,23 +634,23 @@ __global__ __launch_bounds__(64) void k_near_laplace(
 }
 
 // L2P, Laplace: adds -(1/2pi) Re(nu F(z)) for the local expansion F of the target's leaf.
-template <int P>
+template <int P, class T>
 __global__ __launch_bounds__(64) void k_l2p_laplace(
     int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
     const int *__restrict__ leaf_box, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double2 *__restrict__ Lexp, double *__restrict__ out) {
+    const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   if (j >= leaf_start[leaf + 1]) return;
   const double2 z = xs[j], nv = nrm[j];
-  const double2 F = eval_value<P>(Lexp + ((size_t)r * nbox + box) * P,
-                                  make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf));
+  const cx<T> F = eval_value<P>(Lexp + ((size_t)r * nbox + box) * P,
+                                mkc<T>((T)((z.x - c.x) * ih_leaf), (T)((z.y - c.y) * ih_leaf)));
   double *o = out + (size_t)r * M + perm[j];
-  *o -= (nv.x * F.x - nv.y * F.y) / (2.0 * kPi);  // Re(nu F)
+  *o -= (nv.x * (double)F.x - nv.y * (double)F.y) / (2.0 * kPi);  // Re(nu F)
 }
 
 // Near field, Stokes: grid (target chunks, R); writes -(1/pi) sum over the neighbour leaves,
@@ -963,6 +1096,64 @@ int launch_m2l(const FmmTree &t, int ga, int gb, int nsets, const double2 *Mexp,
   return BIE_OK;
 }
 
+// Grid for the grid-stride translation kernels (four waves per workgroup).
+int translation_blocks(long long items) { return (int)std::min<long long>((items + 3) / 4, 2048); }
+
+template <int P>
+int launch_m2l_f32(const FmmTree &t, int nsets, const float2 *Mexp, float2 *Lexp, hipStream_t s) {
+  if (t.ngroup <= 0) return BIE_OK;
+  const size_t lds = (size_t)2 * 40 * 2 * P * sizeof(float);  // at most 40 KiB
+  static_assert(4 * (2 * P / 16) * 4 * 64 <= 2 * 40 * 2 * P, "M2L reduction exceeds the table");
+  hipLaunchKernelGGL(k_m2l_f32<P>, dim3(t.ngroup, nsets), dim3(512), lds, s, t.nbox, t.grp_ptr,
+                     t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_m2l,
+                     Mexp, Lexp);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+// Upward pass, M2L, downward pass, then (after the near field's join) L2P into `partial`, with
+// expansions in T. float is used for the mixed-precision Laplace apply only.
+template <int P, class T>
+int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
+                     const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s) {
+  const int M = t.M;
+  hipLaunchKernelGGL((k_p2m<P, T>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
+                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
+  for (int l = t.L - 1; l >= 2; --l) {
+    const int nb = t.level_off[l + 1] - t.level_off[l];
+    if (nb > 0)
+      hipLaunchKernelGGL((k_m2m<P, T>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
+                         0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
+  }
+  if (t.ngroup > 0) {
+    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
+    if constexpr (std::is_same<T, float>::value)
+      BIE_TRY(launch_m2l_f32<P>(t, nsets, Mexp, Lexp, s));
+    else
+      BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
+  }
+  for (int l = 2; l < t.L; ++l) {
+    const int nb = t.level_off[l + 2] - t.level_off[l + 1];
+    if (nb > 0)
+      hipLaunchKernelGGL((k_l2l<P, T>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
+                         0, s, nb, t.level_off[l + 1], t.nbox, nsets, t.parent, t.T_tau,
+                         t.fact_in, Lexp);
+  }
+  BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
+  if (kind == 0) {
+    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
+                       ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
+                       t.chunk_leaf, t.chunk_start, Lexp, partial);
+  } else {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
+                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
+                         t.chunk_leaf, t.chunk_start, Lexp, partial);
+  }
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
 // Calls f(std::integral_constant<int, P>) for the expansion length p (a multiple of 8).
 template <class F>
 int with_order(int p, F &&f) {
@@ -980,9 +1171,6 @@ int with_order(int p, F &&f) {
       return BIE_EINVAL;
   }
 }
-
-// Grid for the grid-stride translation kernels (four waves per workgroup).
-int translation_blocks(long long items) { return (int)std::min<long long>((items + 3) / 4, 2048); }
 
 }  // namespace
 
@@ -1010,14 +1198,17 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   FmmTree &t = *tp;
   const int M = t.M;
   const int nsets = kind == 0 ? R : 3 * R;
+  // float expansions for the mixed-precision Laplace apply (the near field stays float64)
+  const bool f32 = precision == BIE_MIXED && kind == 0;
+  const size_t csz = f32 ? sizeof(float2) : sizeof(double2);
   // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
   // locals [nsets][nbox][p]
-  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * 16 + 512;
+  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * csz + 512;
   BIE_TRY(t.work.reserve(need));
   double4 *S4 = t.work.as<double4>();
-  double2 *Q = reinterpret_cast<double2 *>(S4 + (size_t)R * M);
-  double2 *Mexp = Q + (size_t)nsets * M;
-  double2 *Lexp = Mexp + (size_t)nsets * t.nbox * p;
+  char *wq = reinterpret_cast<char *>(S4 + (size_t)R * M);
+  char *wm = wq + (size_t)nsets * M * csz;
+  char *wl = wm + (size_t)nsets * t.nbox * p * csz;
   FmmPlan &plan = *g->fmm;
   if (!plan.side) {  // side stream for the near field (default priority) and its fork/join events
     BIE_HIP_CHECK(hipStreamCreateWithFlags(&plan.side, hipStreamNonBlocking));
@@ -1025,8 +1216,9 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
     BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, hipEventDisableTiming));
   }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
-  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64, Q,
-                     S4);
+  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64,
+                     f32 ? nullptr : reinterpret_cast<double2 *>(wq),
+                     f32 ? reinterpret_cast<float2 *>(wq) : nullptr, S4);
   // the near field needs only the charges: it runs on the side stream while the expansions are
   // built, and writes `partial`; the L2P kernels add the far part after the join
   BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
@@ -1047,36 +1239,15 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   const double ih_leaf = (double)(1 << t.L) / t.size;
   BIE_TRY(with_order(p, [&](auto order) -> int {
     constexpr int P = decltype(order)::value;
-    hipLaunchKernelGGL((k_p2m<P>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
-                       t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
-    for (int l = t.L - 1; l >= 2; --l) {
-      const int nb = t.level_off[l + 1] - t.level_off[l];
-      if (nb > 0)
-        hipLaunchKernelGGL((k_m2m<P>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
-                           0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
-    }
-    if (t.ngroup > 0) {
-      ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
-      BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
-    }
-    for (int l = 2; l < t.L; ++l) {
-      const int nb = t.level_off[l + 2] - t.level_off[l + 1];
-      if (nb > 0)
-        hipLaunchKernelGGL((k_l2l<P>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
-                           0, s, nb, t.level_off[l + 1], t.nbox, nsets, t.parent, t.T_tau,
-                           t.fact_in, Lexp);
-    }
-    BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
-    if (kind == 0)
-      hipLaunchKernelGGL((k_l2p_laplace<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
-                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
-                         t.chunk_leaf, t.chunk_start, Lexp, partial);
-    else
-      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
-                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
-                         t.chunk_leaf, t.chunk_start, Lexp, partial);
-    BIE_HIP_CHECK(hipGetLastError());
-    return BIE_OK;
+    if (f32)
+      return expansion_passes<P, float>(t, plan, kind, R, nsets, ih_leaf,
+                                        reinterpret_cast<const float2 *>(wq),
+                                        reinterpret_cast<float2 *>(wm),
+                                        reinterpret_cast<float2 *>(wl), partial, s);
+    return expansion_passes<P, double>(t, plan, kind, R, nsets, ih_leaf,
+                                       reinterpret_cast<const double2 *>(wq),
+                                       reinterpret_cast<double2 *>(wm),
+                                       reinterpret_cast<double2 *>(wl), partial, s);
   }));
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;

@@ -107,3 +107,35 @@ def test_fmm_full_size_elastance(precision, tol):
     phi, info = bie2d.bie_elastance_solve(g, dev(q[None]), o)
     err = float(np.abs(phi.cpu().numpy()[0] - np.asarray(gold["phi"])).max() / np.abs(gold["phi"]).max())
     assert err < tol, (err, info)
+
+
+@pytest.mark.parametrize("kind", ["laplace", "stokes"])
+def test_fmm_mixed_apply_accuracy(kind):
+    """The inner apply of mixed-precision refinement: float32 expansions (Laplace) or a
+    half-length float64 FMM (Stokes), the near field in float64. Its error against the float64
+    direct apply sits at the float32 / truncation level that the refinement removes."""
+    rng = np.random.default_rng(4)
+    for name, c in _cases().items():
+        g = bie2d.Geometry.from_curves(c)
+        n = g.M if kind == "laplace" else 2 * g.M
+        mu = dev(rng.standard_normal((2, n)))
+        f = bie2d.bie_laplace_apply if kind == "laplace" else bie2d.bie_stokes_apply
+        ref = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_DIRECT)
+        out = f(g, mu, bie2d.BIE_MIXED, bie2d.BIE_FMM)
+        err = float((out - ref).abs().max() / ref.abs().max())
+        assert err < 2e-5, (name, err)
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_fmm_full_size_mobility(precision, tol):
+    """200 ellipses x 512 nodes (204,800 unknowns) through the Stokes FMM, against the stored
+    float64 oracle (v, omega) of every body."""
+    gold = json.load(open(os.path.join(GOLDEN, "ellipses_200x512_vw.json")))
+    c, FT = wl.mobility_ellipses()
+    g = bie2d.Geometry.from_curves(c)
+    o = bie2d.default_opts(precision=precision, method=bie2d.BIE_FMM, tol=1e-12, restart=100)
+    VW, info = bie2d.bie_mobility_solve(g, dev(FT[None]), o)
+    VW = VW.cpu().numpy()[0].reshape(-1, 3)
+    ref = np.asarray(gold["VW"]).reshape(-1, 3)
+    for a, b in ((VW[:, :2], ref[:, :2]), (VW[:, 2], ref[:, 2])):
+        assert float(np.abs(a - b).max() / np.abs(b).max()) < tol, info
