@@ -298,6 +298,61 @@ def batched_geometries(count=32, seed=SEEDS["batched"], nb_range=(8, 128), nodes
     return out
 
 
+def plate_samples(n, shift):
+    """Capacitor plate of the nanocomposite application: a rounded bar of length 2.2 and
+    thickness 0.2, centred at (0, shift), sampled at s_k = -pi/2 + pi (k - 1/2) / (n/2),
+    k = 1..n (a full period of the parameter, so the trapezoidal rule applies). On
+    s in [-pi/2, pi/2]: x = 1.1 (1 - (2/pi) a(s)), y = 0.1 erf(7 s), with the smoothed |s|
+    a(s) = s erf(10 s) + exp(-100 s^2) / (10 sqrt(pi)) (so a' = erf(10 s)); the other half
+    mirrors it, x(s) = -x(pi - s), y(s) = y(pi - s). Counterclockwise."""
+    from scipy.special import erf
+    half = n // 2
+    s = -0.5 * math.pi + math.pi * (np.arange(1, n + 1) - 0.5) / half
+    right = s <= 0.5 * math.pi
+    u = np.where(right, s, math.pi - s)  # parameter on the right half
+    k = 2.2 / math.pi
+    a = u * erf(10 * u) + np.exp(-100 * u * u) / (10 * math.sqrt(math.pi))
+    x = 1.1 * (1 - (2 / math.pi) * a)
+    dx = -k * erf(10 * u)
+    ddx = -k * (20 / math.sqrt(math.pi)) * np.exp(-100 * u * u)
+    y = 0.1 * erf(7 * u)
+    dy = 0.1 * (14 / math.sqrt(math.pi)) * np.exp(-49 * u * u)
+    ddy = dy * (-98 * u)
+    # mirrored half: x(s) = -x(pi - s) so x' = x'(u), x'' = -x''(u); y(s) = y(pi - s) so
+    # y' = -y'(u), y'' = y''(u)
+    x = np.where(right, x, -x)
+    ddx = np.where(right, ddx, -ddx)
+    dy = np.where(right, dy, -dy)
+    return x, y + shift, dx, dy, ddx, ddy
+
+
+def nanocomposite(m, A, plate_nodes=800, particle_nodes=600):
+    """The nanocomposite capacitance workload: two plates (shifted copies of plate_samples at
+    y = +1.1 and -1.1, conductors 0 and 1) and an m x 10 lattice of ellipses of area 0.002/m and
+    aspect ratio A (x semi-axis over y semi-axis) centred at (-0.9 + 1.8 (k-1)/10, y_j), each
+    sampled at 600 equispaced parameter values. Charges +1 and -1 on
+    the plates, 0 elsewhere. Returns (curves, q).
+    Row centres: the printed -0.9 + 1.8 (j-1)/m puts a single row 0.075 from the lower plate and
+    reproduces none of the printed capacitances for m = 1; the centred rows
+    -0.9 + 1.8 (j - 1/2)/m reproduce them (to the printed digits for A = 1), and are used."""
+    samples = [plate_samples(plate_nodes, 1.1), plate_samples(plate_nodes, -1.1)]
+    centers = [[0.0, 1.1], [0.0, -1.1]]
+    radii = [1.1, 1.1]
+    if m > 0:
+        b = math.sqrt(0.002 / (m * math.pi * A))
+        a = A * b
+        for j in range(1, m + 1):
+            for kk in range(1, 11):
+                cx = -0.9 + 1.8 * (kk - 1) / 10
+                cy = -0.9 + 1.8 * (j - 0.5) / m
+                samples.append(ellipse_samples(particle_nodes, cx, cy, a, b, 0.0))
+                centers.append([cx, cy])
+                radii.append(max(a, b))
+    q = np.zeros(len(samples))
+    q[0], q[1] = 1.0, -1.0
+    return assemble(samples, centers, radii), q
+
+
 def random_charges(rng, N, nrhs=1):
     return rng.standard_normal((nrhs, N))
 

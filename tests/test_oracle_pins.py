@@ -465,3 +465,28 @@ def _fourier_at(t, coeffs, beta):
         dr = dr + a * k * np.cos(k * t)
         ddr = ddr - a * k * k * np.sin(k * t)
     return wl._radial(t, 0.0, 0.0, r, dr, ddr, beta)
+
+
+def _capacitance(m, A):
+    c, q = wl.nanocomposite(m, A if A is not None else 1.0)
+    phi = ny.elastance_solve(ny.geometry_of(c), q[None])["phi"][0]
+    return 1.0 / (phi[0] - phi[1])
+
+
+def test_nanocomposite_table3_capacitance():
+    """Table 3 (nanocomposite capacitance, section 6.1.3): the oracle's C = 1 / (V1 - V2) for the
+    plates alone (m = 0) and one row of particles at three aspect ratios matches the printed
+    values to within 1.5e-4 (the paper iterates only to a residual of 1e-6 with a different
+    quadrature). This pins the readings of the garbled plate and lattice formulas: the smoothed
+    |s| with its exp(-100 s^2)/(10 sqrt pi) term, centred rows, A = x semi-axis / y semi-axis;
+    the printed row formula (the row 0.075 from a plate) misses the m = 1 values by 3e-3."""
+    rows = json.load(open(os.path.join(GOLDEN, "nanocomposite_table3.json")))["rows"]
+    for r in rows:
+        if r["m"] > 1 or r["A"] not in (None, 0.25, 1.0, 4.0):
+            continue
+        assert abs(_capacitance(r["m"], r["A"]) - r["C"]) < 1.5e-4, r
+    # the plates alone reach the printed digits and are converged in the plate resolution
+    c, q = wl.nanocomposite(0, 1.0, plate_nodes=400)
+    phi = ny.elastance_solve(ny.geometry_of(c), q[None])["phi"][0]
+    assert abs(1.0 / (phi[0] - phi[1]) - 2.2949) < 5e-5
+    assert abs(1.0 / (phi[0] - phi[1]) - _capacitance(0, None)) < 1e-12
