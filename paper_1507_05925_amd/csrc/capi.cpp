@@ -145,7 +145,10 @@ int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *cu
   hipGetDevice(&g->device);
   g->h_body_ptr.resize(nbodies + 1);
   g->h_body_ptr[0] = 0;
-  for (int b = 0; b < nbodies; ++b) g->h_body_ptr[b + 1] = g->h_body_ptr[b] + nodes_per_body[b];
+  for (int b = 0; b < nbodies; ++b) {
+    g->h_body_ptr[b + 1] = g->h_body_ptr[b] + nodes_per_body[b];
+    g->max_nb = std::max(g->max_nb, nodes_per_body[b]);
+  }
   plan_splits(g);
   g->far_pairs = (long long)M * M;
   for (int b = 0; b < nbodies; ++b) g->far_pairs -= (long long)nodes_per_body[b] * nodes_per_body[b];

@@ -83,6 +83,7 @@ struct SysSet {
 struct bie_geom {
   int N = 0, M = 0, device = 0;
   std::vector<int> h_body_ptr;  // host copy [N+1]
+  int max_nb = 0;               // nodes of the largest body
   int max_nodes = 0;            // largest n_b
   // device arrays (one arena)
   bie::DevBuf arena;

@@ -358,51 +358,75 @@ __global__ __launch_bounds__(kBlock) void k_stk_far_f64(
 // k != i of body b), the smooth diagonal limit, 1/2 mu, the completion L (with_L), and the
 // far-field partials (nsplit of them, summed in split order); out = alpha * total.
 // ------------------------------------------------------------------------------------------
+// Epilogues: grid (body x target tile, rhs), tiles of kBlock targets (ntile per body, the
+// largest body's count; tiles past a body's end exit at once). Each workgroup forms its body's
+// completion sums itself, then the self-body block (sources read four per step), the diagonal
+// limit, the identity and the far-field partials for its targets.
 __global__ __launch_bounds__(kBlock) void k_lap_epilogue(
-    int M, int nsplit, int R, const int *__restrict__ body_ptr, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ nx, const double *__restrict__ ny,
-    const double *__restrict__ w, const double *__restrict__ kappa, const double *__restrict__ mu,
-    const double *__restrict__ s64, const double *__restrict__ partial, int with_L, int self_block,
-    double alpha, double *__restrict__ out) {
+    int M, int nsplit, int R, int ntile, const int *__restrict__ body_ptr,
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ nx,
+    const double *__restrict__ ny, const double *__restrict__ w, const double *__restrict__ kappa,
+    const double *__restrict__ mu, const double *__restrict__ s64, const double *__restrict__ partial,
+    int with_L, int self_block, double alpha, double *__restrict__ out) {
   __shared__ double sh[4];
-  const int b = blockIdx.x, r = blockIdx.y;
+  const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile, r = blockIdx.y;
   const int k0 = body_ptr[b], k1 = body_ptr[b + 1];
+  if (k0 + tile * kBlock >= k1) return;  // whole workgroup
   const int kend = self_block ? k1 : k0;  // the FMM far field already holds same-body pairs
   const double *s = s64 + (size_t)r * M;
   const double *m = mu + (size_t)r * M;
   double part = 0.0;
   for (int k = k0 + threadIdx.x; k < k1; k += kBlock) part += s[k];
   const double charge = block_sum(part, sh);  // int_{Gamma_b} mu ds
-  for (int base = k0; base < k1; base += kBlock) {
-    const int i = base + threadIdx.x;
-    const bool valid = i < k1;
-    const int ii = valid ? i : k0;
-    const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
-    double gx = 0.0, gy = 0.0;
-    for (int k = k0; k < kend; ++k) {
-      const double dx = xi - x[k], dy = yi - y[k];
-      const bool same = (k == ii);
+  const int i = k0 + tile * kBlock + threadIdx.x;
+  const bool valid = i < k1;
+  const int ii = valid ? i : k0;
+  const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
+  double gx = 0.0, gy = 0.0;
+  int k = k0;
+  for (; k + 4 <= kend; k += 4) {
+    double xs[4], ys[4], ss[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xs[u] = x[k + u];
+      ys[u] = y[k + u];
+      ss[u] = s[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double dx = xi - xs[u], dy = yi - ys[u];
+      const bool same = (k + u == ii);
       const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
-      const double t = same ? 0.0 : s[k] * inv;
+      const double t = same ? 0.0 : ss[u] * inv;
       gx = fma(dx, t, gx);
       gy = fma(dy, t, gy);
     }
-    double v = 0.5 * m[ii] - (a * gx + bb * gy) / (2.0 * kPi) - s[ii] * kappa[ii] / (4.0 * kPi);
-    if (with_L) v += charge;
-    for (int sp = 0; sp < nsplit; ++sp) v += partial[((size_t)sp * R + r) * M + ii];
-    if (valid) out[(size_t)r * M + i] = alpha * v;
   }
+  for (; k < kend; ++k) {
+    const double dx = xi - x[k], dy = yi - y[k];
+    const bool same = (k == ii);
+    const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
+    const double t = same ? 0.0 : s[k] * inv;
+    gx = fma(dx, t, gx);
+    gy = fma(dy, t, gy);
+  }
+  double v = 0.5 * m[ii] - (a * gx + bb * gy) / (2.0 * kPi) - s[ii] * kappa[ii] / (4.0 * kPi);
+  if (with_L) v += charge;
+  for (int sp = 0; sp < nsplit; ++sp) v += partial[((size_t)sp * R + r) * M + ii];
+  if (valid) out[(size_t)r * M + i] = alpha * v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_stk_epilogue(
-    int M, int nsplit, int R, const int *__restrict__ body_ptr, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ nx, const double *__restrict__ ny,
-    const double *__restrict__ kappa, const double *__restrict__ px, const double *__restrict__ py,
-    const double *__restrict__ mu, const double *__restrict__ s64, const double *__restrict__ partial,
-    int with_L, int self_block, double alpha, double *__restrict__ out) {
+    int M, int nsplit, int R, int ntile, const int *__restrict__ body_ptr,
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ nx,
+    const double *__restrict__ ny, const double *__restrict__ kappa, const double *__restrict__ px,
+    const double *__restrict__ py, const double *__restrict__ mu, const double *__restrict__ s64,
+    const double *__restrict__ partial, int with_L, int self_block, double alpha,
+    double *__restrict__ out) {
   __shared__ double sh[4];
-  const int b = blockIdx.x, r = blockIdx.y;
+  const int b = blockIdx.x / ntile, tile = blockIdx.x % ntile, r = blockIdx.y;
   const int k0 = body_ptr[b], k1 = body_ptr[b + 1];
+  if (k0 + tile * kBlock >= k1) return;  // whole workgroup
   const int kend = self_block ? k1 : k0;
   const double *s = s64 + (size_t)r * 2 * M;
   const double *m = mu + (size_t)r * 2 * M;
@@ -413,40 +437,59 @@ __global__ __launch_bounds__(kBlock) void k_stk_epilogue(
     tq += px[k] * s[2 * k] + py[k] * s[2 * k + 1];
   }
   const double F1 = block_sum(f1, sh), F2 = block_sum(f2, sh), TQ = block_sum(tq, sh);
-  for (int base = k0; base < k1; base += kBlock) {
-    const int i = base + threadIdx.x;
-    const bool valid = i < k1;
-    const int ii = valid ? i : k0;
-    const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
-    double gx = 0.0, gy = 0.0;
-    for (int k = k0; k < kend; ++k) {
-      const double dx = xi - x[k], dy = yi - y[k];
-      const bool same = (k == ii);
+  const int i = k0 + tile * kBlock + threadIdx.x;
+  const bool valid = i < k1;
+  const int ii = valid ? i : k0;
+  const double xi = x[ii], yi = y[ii], a = nx[ii], bb = ny[ii];
+  double gx = 0.0, gy = 0.0;
+  int k = k0;
+  for (; k + 4 <= kend; k += 4) {
+    double xs[4], ys[4], s1[4], s2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xs[u] = x[k + u];
+      ys[u] = y[k + u];
+      s1[u] = s[2 * (k + u)];
+      s2[u] = s[2 * (k + u) + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double dx = xi - xs[u], dy = yi - ys[u];
+      const bool same = (k + u == ii);
       const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
       const double rn = fma(dx, a, dy * bb);
-      const double cc = same ? 0.0 : fma(dx, s[2 * k], dy * s[2 * k + 1]) * rn * (inv * inv);
+      const double cc = same ? 0.0 : fma(dx, s1[u], dy * s2[u]) * rn * (inv * inv);
       gx = fma(cc, dx, gx);
       gy = fma(cc, dy, gy);
     }
-    // tangent tau = (-n_y, n_x); diagonal -(kappa/2pi) w tau (tau . mu)
-    const double t1 = -bb, t2 = a;
-    const double ts = t1 * s[2 * ii] + t2 * s[2 * ii + 1];
-    const double d = -kappa[ii] / (2.0 * kPi);
-    double v1 = 0.5 * m[2 * ii] - gx / kPi + d * t1 * ts;
-    double v2 = 0.5 * m[2 * ii + 1] - gy / kPi + d * t2 * ts;
-    if (with_L) {
-      v1 += F1 + px[ii] * TQ;
-      v2 += F2 + py[ii] * TQ;
-    }
-    for (int sp = 0; sp < nsplit; ++sp) {
-      const double *o = partial + ((size_t)sp * R + r) * 2 * M;
-      v1 += o[2 * ii];
-      v2 += o[2 * ii + 1];
-    }
-    if (valid) {
-      out[(size_t)r * 2 * M + 2 * i] = alpha * v1;
-      out[(size_t)r * 2 * M + 2 * i + 1] = alpha * v2;
-    }
+  }
+  for (; k < kend; ++k) {
+    const double dx = xi - x[k], dy = yi - y[k];
+    const bool same = (k == ii);
+    const double inv = rcp64(same ? 1.0 : fma(dx, dx, dy * dy));
+    const double rn = fma(dx, a, dy * bb);
+    const double cc = same ? 0.0 : fma(dx, s[2 * k], dy * s[2 * k + 1]) * rn * (inv * inv);
+    gx = fma(cc, dx, gx);
+    gy = fma(cc, dy, gy);
+  }
+  // tangent tau = (-n_y, n_x); diagonal -(kappa/2pi) w tau (tau . mu)
+  const double t1 = -bb, t2 = a;
+  const double ts = t1 * s[2 * ii] + t2 * s[2 * ii + 1];
+  const double d = -kappa[ii] / (2.0 * kPi);
+  double v1 = 0.5 * m[2 * ii] - gx / kPi + d * t1 * ts;
+  double v2 = 0.5 * m[2 * ii + 1] - gy / kPi + d * t2 * ts;
+  if (with_L) {
+    v1 += F1 + px[ii] * TQ;
+    v2 += F2 + py[ii] * TQ;
+  }
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double *o = partial + ((size_t)sp * R + r) * 2 * M;
+    v1 += o[2 * ii];
+    v2 += o[2 * ii + 1];
+  }
+  if (valid) {
+    out[(size_t)r * 2 * M + 2 * i] = alpha * v1;
+    out[(size_t)r * 2 * M + 2 * i + 1] = alpha * v2;
   }
 }
 
@@ -711,16 +754,17 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
       }
       BIE_HIP_CHECK(hipGetLastError());
     }
-    dim3 eg(g->N, R);
+    const int ntile = std::max(1, (g->max_nb + kBlock - 1) / kBlock);
+    dim3 eg(g->N * ntile, R);
     ProfScope prof(BIE_K_EPILOGUE, st, 0);
     if (kind == 0)
-      hipLaunchKernelGGL(k_lap_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, g->body_ptr,
-                         g->x, g->y, g->nx, g->ny, g->w, g->kappa, mu + off, s64 + off, partial,
-                         with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
+      hipLaunchKernelGGL(k_lap_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, ntile,
+                         g->body_ptr, g->x, g->y, g->nx, g->ny, g->w, g->kappa, mu + off,
+                         s64 + off, partial, with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
     else
-      hipLaunchKernelGGL(k_stk_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, g->body_ptr,
-                         g->x, g->y, g->nx, g->ny, g->kappa, g->px, g->py, mu + off, s64 + off,
-                         partial, with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
+      hipLaunchKernelGGL(k_stk_epilogue, eg, dim3(kBlock), 0, st, g->M, nsplit, R, ntile,
+                         g->body_ptr, g->x, g->y, g->nx, g->ny, g->kappa, g->px, g->py, mu + off,
+                         s64 + off, partial, with_L, method == BIE_FMM ? 0 : 1, alpha, out + off);
     BIE_HIP_CHECK(hipGetLastError());
     r0 += R;
   }
