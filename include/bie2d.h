@@ -165,6 +165,22 @@ int bie_elastance_matrix(bie_geom *g, double *P, int max_rhs_per_pass, const bie
 int bie_mobility_matrix(bie_geom *g, double *Mmat, int max_rhs_per_pass, const bie_opts *opts,
                         bie_info *info, void *stream);
 
+/* ---- off-surface evaluation: the field everywhere (the representation formulas) ------------
+ * The solution is a layer potential of the total density everywhere, not only on the curves:
+ * u = S[mu + sigma] for the elastance problem (eq. TotRepresentation; constant, = phi_j, inside
+ * conductor j) and u = Scal[mu + rho] for the mobility problem (eq. TotRepresentationStokes;
+ * the rigid motion of body j inside it), the fields the paper draws as contours and velocity
+ * plots. Given the solve's input (q [nrhs][N], resp. (F, T) [nrhs][3N]) and its density mu
+ * (mu_out of the solve: [nrhs][M], resp. [nrhs][2M] node-major), these evaluate that field at
+ * npts points pts [2*npts] (x0, y0, x1, ...): u [nrhs][npts], resp. velocities [nrhs][npts][2]
+ * (viscosity 1). All buffers are device memory. The trapezoidal rule is spectrally accurate for
+ * points a few node spacings away from every curve; closer points get no near-singular
+ * correction (the paper uses QBX there) and lose accuracy. npts = 0 is a no-op. */
+int bie_elastance_field(bie_geom *g, int nrhs, const double *q, const double *mu, int npts,
+                        const double *pts, double *u, void *stream);
+int bie_mobility_field(bie_geom *g, int nrhs, const double *FT, const double *mu, int npts,
+                       const double *pts, double *u, void *stream);
+
 /* ---- batched solves over several geometries (many systems in one lock-step GMRES) ---------
  * Every right-hand side of every item is one system; all systems advance together, one batched
  * operator apply per Arnoldi step, each with its own Hessenberg matrix and convergence test, so

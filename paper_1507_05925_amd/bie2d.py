@@ -67,6 +67,8 @@ _SIGS = {
     "bie_mobility_rhs": ([_P, _I, _P, _P, _P, _P], _I),
     "bie_laplace_potential": ([_P, _I, _P, _P, _P], _I),
     "bie_stokes_rigid_motion": ([_P, _I, _P, _P, _P], _I),
+    "bie_elastance_field": ([_P, _I, _P, _P, _I, _P, _P, _P], _I),
+    "bie_mobility_field": ([_P, _I, _P, _P, _I, _P, _P, _P], _I),
     "bie_elastance_solve": ([_P, _I, _P, _P, _P, ctypes.POINTER(bie_opts),
                              ctypes.POINTER(bie_info), _P], _I),
     "bie_mobility_solve": ([_P, _I, _P, _P, _P, ctypes.POINTER(bie_opts),
@@ -302,6 +304,26 @@ def bie_elastance_solve(g, q, opts=None, want_mu=False, allow_noconv=False):
 def bie_mobility_solve(g, FT, opts=None, want_mu=False, allow_noconv=False):
     """FT [.., 3N] -> (VW [.., 3N], info[, mu [.., 2M]])."""
     return _solve(lib().bie_mobility_solve, g, FT, 3 * g.N, 2 * g.M, opts, want_mu, allow_noconv)
+
+
+def _field(fn, g, inp, width, mu, mlen, pts, comps):
+    torch = _torch()
+    R = _rows(inp, width)
+    P = pts.reshape(-1, 2).shape[0]
+    out = torch.empty((R, P, comps) if comps > 1 else (R, P), dtype=torch.float64, device=g.device)
+    _check(fn(g.handle, R, _dptr(inp, width, "input"), _dptr(mu, mlen, "mu"), int(P),
+              _dptr(pts.reshape(-1), None, "pts"), _dptr(out), _stream()))
+    return out
+
+
+def bie_elastance_field(g, q, mu, pts):
+    """Potential u = S[mu + sigma(q)] at points pts [P, 2]: q [R, N], mu [R, M] -> [R, P]."""
+    return _field(lib().bie_elastance_field, g, q, g.N, mu, g.M, pts, 1)
+
+
+def bie_mobility_field(g, FT, mu, pts):
+    """Velocity Scal[mu + rho(F, T)] at points pts [P, 2]: FT [R, 3N], mu [R, 2M] -> [R, P, 2]."""
+    return _field(lib().bie_mobility_field, g, FT, 3 * g.N, mu, 2 * g.M, pts, 2)
 
 
 def _matrix(fn, g, n, max_rhs, opts):

@@ -329,6 +329,25 @@ int bie_mobility_rhs(bie_geom *g, int nrhs, const double *FT, double *rho, doubl
   return rhs_entry(g, 1, BIE_DIRECT, nrhs, FT, rho, f, stream);
 }
 
+// Off-surface evaluation: total density = mu + incident density of `in`, then its layer
+// potential at the given points.
+static int field_entry(bie_geom *g, int kind, int nrhs, const double *in, const double *mu,
+                       int npts, const double *pts, double *u, void *stream) {
+  BIE_TRY(check_geom(g));
+  if (nrhs < 1 || npts < 0 || !in || !mu || (npts > 0 && (!pts || !u))) {
+    set_error("field: nrhs >= 1, npts >= 0 and non-NULL buffers required");
+    return BIE_EINVAL;
+  }
+  if (npts == 0) return BIE_OK;
+  hipStream_t s = as_stream(stream);
+  const long long len = kind == 0 ? g->M : 2LL * g->M;
+  BIE_TRY(g->ws_out.reserve((size_t)len * nrhs * 8));
+  double *dens = g->ws_out.as<double>();
+  BIE_TRY(incident_density(g, kind, nrhs, in, dens, s));
+  BIE_TRY(vec_axpby(len * nrhs, 1.0, mu, 1.0, dens, s));
+  return eval_points(g, kind, nrhs, dens, npts, pts, false, u, s);
+}
+
 int bie_laplace_potential(bie_geom *g, int nrhs, const double *dens, double *phi, void *stream) {
   BIE_TRY(check_geom(g));
   if (nrhs < 1 || !dens || !phi) {
@@ -336,6 +355,16 @@ int bie_laplace_potential(bie_geom *g, int nrhs, const double *dens, double *phi
     return BIE_EINVAL;
   }
   return read_off(g, 0, nrhs, dens, phi, as_stream(stream));
+}
+
+int bie_elastance_field(bie_geom *g, int nrhs, const double *q, const double *mu, int npts,
+                        const double *pts, double *u, void *stream) {
+  return field_entry(g, 0, nrhs, q, mu, npts, pts, u, stream);
+}
+
+int bie_mobility_field(bie_geom *g, int nrhs, const double *FT, const double *mu, int npts,
+                       const double *pts, double *u, void *stream) {
+  return field_entry(g, 1, nrhs, FT, mu, npts, pts, u, stream);
 }
 
 int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *VW, void *stream) {

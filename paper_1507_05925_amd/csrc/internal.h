@@ -122,6 +122,8 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
 int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double *dens,
                      hipStream_t s);
 int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t s);
+int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
+                bool rigid, double *res, hipStream_t st);
 int geometry_build(bie_geom *g, const double *curve, const double *interior, hipStream_t s);
 
 // ---- blas.hip: segmented float64 vector kernels used by GMRES -------------------------------

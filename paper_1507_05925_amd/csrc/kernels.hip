@@ -784,29 +784,54 @@ int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double
   return BIE_OK;
 }
 
-int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t st) {
-  if (nrhs <= 0 || g->N <= 0) return BIE_OK;
+// Layer potentials of a total density at arbitrary points: Laplace u = S[dens], one value per
+// point; Stokes the velocity of the Stokeslet sum (two values per point) or, with rigid (the
+// interior read-off at the geometry's interior points), (v, omega) per body.
+__global__ void k_velocity_fin(int N, int nrhs, int S, const double *__restrict__ part,
+                               double *__restrict__ U) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (long long)N * nrhs) return;
+  double U1 = 0.0, U2 = 0.0;
+  for (int sp = 0; sp < S; ++sp) {
+    const double *o = part + ((size_t)sp * N * nrhs + i) * 3;
+    U1 += o[0];
+    U2 += o[1];
+  }
+  U[2 * i] = U1 / (4.0 * kPi);
+  U[2 * i + 1] = U2 / (4.0 * kPi);
+}
+
+int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
+                bool rigid, double *res, hipStream_t st) {
+  if (nrhs <= 0 || npts <= 0) return BIE_OK;
   // source splits: about 2048 workgroups in all, at most 32 splits, at least 2048 sources each
-  const long long groups = (long long)((g->N + kTJ - 1) / kTJ) * nrhs;
+  const long long groups = (long long)((npts + kTJ - 1) / kTJ) * nrhs;
   int S = (int)std::max<long long>(1, std::min<long long>(32, (2048 + groups - 1) / groups));
   S = std::max(1, std::min(S, g->M / 2048));
   const int comps = kind == 0 ? 1 : 3;
-  BIE_TRY(g->ws_read.reserve((size_t)S * nrhs * g->N * comps * 8));
+  BIE_TRY(g->ws_read.reserve((size_t)S * nrhs * npts * comps * 8));
   double *part = g->ws_read.as<double>();
-  dim3 grid((g->N + kTJ - 1) / kTJ, nrhs, S);
-  const unsigned fin = nblocks((long long)g->N * nrhs);
+  dim3 grid((npts + kTJ - 1) / kTJ, nrhs, S);
+  const unsigned fin = nblocks((long long)npts * nrhs);
   if (kind == 0) {
-    hipLaunchKernelGGL(k_potential, grid, dim3(kBlock), 0, st, g->M, g->N, nrhs, g->xy, g->w,
-                       g->pint, dens, part);
-    hipLaunchKernelGGL(k_potential_fin, dim3(fin), dim3(kBlock), 0, st, g->N, nrhs, S, part, res);
-  } else {
-    hipLaunchKernelGGL(k_rigid, grid, dim3(kBlock), 0, st, g->M, g->N, nrhs, g->xy, g->w, g->pint,
+    hipLaunchKernelGGL(k_potential, grid, dim3(kBlock), 0, st, g->M, npts, nrhs, g->xy, g->w, pts,
                        dens, part);
-    hipLaunchKernelGGL(k_rigid_fin, dim3(fin), dim3(kBlock), 0, st, g->N, nrhs, S, g->pint, g->xc,
-                       g->yc, part, res);
+    hipLaunchKernelGGL(k_potential_fin, dim3(fin), dim3(kBlock), 0, st, npts, nrhs, S, part, res);
+  } else {
+    hipLaunchKernelGGL(k_rigid, grid, dim3(kBlock), 0, st, g->M, npts, nrhs, g->xy, g->w, pts,
+                       dens, part);
+    if (rigid)
+      hipLaunchKernelGGL(k_rigid_fin, dim3(fin), dim3(kBlock), 0, st, npts, nrhs, S, pts, g->xc,
+                         g->yc, part, res);
+    else
+      hipLaunchKernelGGL(k_velocity_fin, dim3(fin), dim3(kBlock), 0, st, npts, nrhs, S, part, res);
   }
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
+}
+
+int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t st) {
+  return eval_points(g, kind, nrhs, dens, g->N, g->pint, true, res, st);
 }
 
 }  // namespace bie
