@@ -12,6 +12,9 @@ Contents
             sides, LU solve, outputs, elastance matrix P and mobility matrix M.
   matfree   the same operators applied matrix-free by plain C loops (for node counts where the
             dense matrix does not fit), GMRES via scipy, sampled-row applies.
+  dirichlet the capacitance and resistance problems (the inverse problems of the paper's
+            cross-tests) by completed double layers: dense operators, LU solves, the bounded
+            solution with its charges / forces and torques and u_inf, the matrices C and R.
 
 Parity status: every function is pinned by tests/test_oracle_*.py against closed forms, the
 paper's tables, discrete Gauss-law identities, invariants or brute force (no function is
