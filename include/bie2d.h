@@ -181,6 +181,50 @@ int bie_elastance_field(bie_geom *g, int nrhs, const double *q, const double *mu
 int bie_mobility_field(bie_geom *g, int nrhs, const double *FT, const double *mu, int npts,
                        const double *pts, double *u, void *stream);
 
+/* ---- the inverse problems: capacitance and resistance (the paper's cross-tests) -------------
+ * The numerical section checks the elastance (mobility) solver by first solving the capacitance
+ * (resistance) problem for prescribed potentials phi_j (rigid motions v_j + omega_j
+ * (x - x^c_j)^perp), which gives the charges q_j (forces F_j and torques T_j about x^c_j) and the
+ * value at infinity u_inf, then feeding those to the elastance (mobility) solver; the prescribed
+ * data come back up to u_inf (introduction: the Dirichlet problem with u bounded at infinity; the
+ * cross-test protocol of the numerical section). The paper cites the standard equations for
+ * these problems; the ones used here are the completed double layers:
+ *   Laplace: u = D[mu] + sum_j G_R(x, z_j) int_{Gamma_j} mu,
+ *            D[mu](x) = int dG/dn_y(x, y) mu(y) ds_y, G = -(1/2pi) log|x - y|,
+ *            G_R(x, z) = -(1/2pi) log(|x - z| / R);   (1/2 I + D + C) mu = f on the curves.
+ *   Stokes:  u = Dcal[mu] + sum_j [Gcal_R(x, z_j) a_j + t_j (x - z_j)^perp / (4 pi |x - z_j|^2)],
+ *            Dcal[mu](x) = (1/pi) int (r.n_y)(r.mu) r / |r|^4 ds_y (r = x - y),
+ *            Gcal_R(x, z) = (1/4pi)(-log(|d| / R) I + d d^T / |d|^2), d = x - z,
+ *            a_j = int_{Gamma_j} mu, t_j = int_{Gamma_j} ((y - z_j)^perp, mu);  viscosity 1.
+ * z_j is body j's interior point (bie_geom_create; default its centroid), which must lie inside
+ * the body; R is twice the diagonal of the nodes' bounding box. Nystrom discretisation on the
+ * trapezoidal nodes, diagonal by the smooth kernel limits (-kappa/4pi; -(kappa/2pi) tau tau^T).
+ * All applies and solves are float64 with direct summation (opts.precision and opts.method are
+ * ignored).
+ *
+ * bie_laplace_dl_apply / bie_stokes_dl_apply: out = (1/2 I + D + C) mu (with_completion = 0 drops
+ * C), mu and out (device) [nrhs][M], resp. [nrhs][2M] node-major; mu and out must not alias.
+ *
+ * bie_capacitance_solve: phi (device) [nrhs][N] -> q (device) [nrhs][N] (sum_j q_j = 0,
+ * q_j = -int_{Gamma_j} du/dn, the charge of the elastance problem) and u_inf (device) [nrhs].
+ * bie_resistance_solve: VW (device) [nrhs][3N] (v_1x, v_1y, omega_1, ...) -> FT (device)
+ * [nrhs][3N] (F_1x, F_1y, T_1, ...; sum_j F_j = 0, the force and torque of the mobility problem)
+ * and u_inf (device) [nrhs][2].
+ * Each solves nrhs + 1 (Laplace) or nrhs + 2 (Stokes) systems in one multi-rhs GMRES: the data
+ * and the uniform boundary values 1, resp. e_x and e_y, whose combination is the bounded
+ * solution. mu_out (device) [nrhs][M], resp. [nrhs][2M], or NULL receives that solution's
+ * density; then u = D[mu_out] + sum_j q_j G(x, z_j) + u_inf (Stokes: Dcal[mu_out] plus the
+ * Stokeslet F_j and the rotlet of t_j = T_j - (z_j - x^c_j) x F_j at z_j, plus u_inf).
+ * opts NULL = defaults; info may be NULL; BIE_ENOCONV: outputs from the last iterate. */
+int bie_laplace_dl_apply(bie_geom *g, int with_completion, int nrhs, const double *mu, double *out,
+                         void *stream);
+int bie_stokes_dl_apply(bie_geom *g, int with_completion, int nrhs, const double *mu, double *out,
+                        void *stream);
+int bie_capacitance_solve(bie_geom *g, int nrhs, const double *phi, double *q, double *u_inf,
+                          double *mu_out, const bie_opts *opts, bie_info *info, void *stream);
+int bie_resistance_solve(bie_geom *g, int nrhs, const double *VW, double *FT, double *u_inf,
+                         double *mu_out, const bie_opts *opts, bie_info *info, void *stream);
+
 /* ---- batched solves over several geometries (many systems in one lock-step GMRES) ---------
  * Every right-hand side of every item is one system; all systems advance together, one batched
  * operator apply per Arnoldi step, each with its own Hessenberg matrix and convergence test, so
@@ -259,7 +303,8 @@ int bie_server_destroy(bie_server *srv);
 #define BIE_K_FMM 5             /* FMM far field, all its kernels; units: M^2 per rhs (equivalent pairs) */
 #define BIE_K_FMM_M2L 6         /* FMM multipole-to-local; units: complex multiply-adds */
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
-#define BIE_K_COUNT 8
+#define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
+#define BIE_K_COUNT 9
 int bie_profile_enable(int on);
 int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs);
 

@@ -73,6 +73,12 @@ _SIGS = {
                              ctypes.POINTER(bie_info), _P], _I),
     "bie_mobility_solve": ([_P, _I, _P, _P, _P, ctypes.POINTER(bie_opts),
                             ctypes.POINTER(bie_info), _P], _I),
+    "bie_laplace_dl_apply": ([_P, _I, _I, _P, _P, _P], _I),
+    "bie_stokes_dl_apply": ([_P, _I, _I, _P, _P, _P], _I),
+    "bie_capacitance_solve": ([_P, _I, _P, _P, _P, _P, ctypes.POINTER(bie_opts),
+                               ctypes.POINTER(bie_info), _P], _I),
+    "bie_resistance_solve": ([_P, _I, _P, _P, _P, _P, ctypes.POINTER(bie_opts),
+                              ctypes.POINTER(bie_info), _P], _I),
     "bie_elastance_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
     "bie_mobility_matrix": ([_P, _P, _I, ctypes.POINTER(bie_opts), ctypes.POINTER(bie_info), _P], _I),
     "bie_batch_create": ([ctypes.POINTER(_P)], _I),
@@ -90,7 +96,8 @@ _SIGS = {
 }
 
 BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
-BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL, BIE_K_COUNT = 4, 5, 6, 7, 8
+BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL = 4, 5, 6, 7
+BIE_K_DOUBLE_LAYER, BIE_K_COUNT = 8, 9
 
 
 def bie_profile_enable(on=True):
@@ -324,6 +331,57 @@ def bie_elastance_field(g, q, mu, pts):
 def bie_mobility_field(g, FT, mu, pts):
     """Velocity Scal[mu + rho(F, T)] at points pts [P, 2]: FT [R, 3N], mu [R, 2M] -> [R, P, 2]."""
     return _field(lib().bie_mobility_field, g, FT, 3 * g.N, mu, 2 * g.M, pts, 2)
+
+
+def bie_laplace_dl_apply(g, mu, with_completion=True, out=None):
+    """(1/2 I + D + C) mu for mu [.., M] (capacitance operator)."""
+    torch = _torch()
+    out = torch.empty_like(mu) if out is None else out
+    _check(lib().bie_laplace_dl_apply(g.handle, int(with_completion), _rows(mu, g.M),
+                                      _dptr(mu, g.M, "mu"), _dptr(out, g.M, "out"), _stream()))
+    return out
+
+
+def bie_stokes_dl_apply(g, mu, with_completion=True, out=None):
+    """(1/2 I + Dcal + C) mu for mu [.., 2M] node-major (resistance operator)."""
+    torch = _torch()
+    out = torch.empty_like(mu) if out is None else out
+    _check(lib().bie_stokes_dl_apply(g.handle, int(with_completion), _rows(mu, 2 * g.M),
+                                     _dptr(mu, 2 * g.M, "mu"), _dptr(out, 2 * g.M, "out"),
+                                     _stream()))
+    return out
+
+
+def _dl_solve(fn, g, data, width_in, width_mu, width_inf, opts, want_mu, allow_noconv):
+    torch = _torch()
+    R = _rows(data, width_in)
+    res = torch.empty(R, width_in, dtype=torch.float64, device=data.device)
+    uinf = torch.empty(R, width_inf, dtype=torch.float64, device=data.device)
+    mu = torch.empty(R, width_mu, dtype=torch.float64, device=data.device) if want_mu else None
+    info = bie_info()
+    o = opts if opts is not None else default_opts()
+    code = fn(g.handle, R, _dptr(data, width_in, "input"), _dptr(res), _dptr(uinf),
+              _dptr(mu) if want_mu else None, ctypes.byref(o), ctypes.byref(info), _stream())
+    if not (code == BIE_OK or (allow_noconv and code == BIE_ENOCONV)):
+        _check(code)
+    shape = data.shape[:-1]
+    uinf = uinf.reshape(shape + ((width_inf,) if width_inf > 1 else ()))
+    out = (res.reshape(shape + (width_in,)), uinf, info.as_dict())
+    if want_mu:
+        out = out + (mu.reshape(shape + (width_mu,)),)
+    return out
+
+
+def bie_capacitance_solve(g, phi, opts=None, want_mu=False, allow_noconv=False):
+    """Conductor potentials phi [.., N] -> (q [.., N], u_inf [..], info[, mu [.., M]])."""
+    return _dl_solve(lib().bie_capacitance_solve, g, phi, g.N, g.M, 1, opts, want_mu,
+                     allow_noconv)
+
+
+def bie_resistance_solve(g, VW, opts=None, want_mu=False, allow_noconv=False):
+    """Rigid motions VW [.., 3N] -> (FT [.., 3N], u_inf [.., 2], info[, mu [.., 2M]])."""
+    return _dl_solve(lib().bie_resistance_solve, g, VW, 3 * g.N, 2 * g.M, 2, opts, want_mu,
+                     allow_noconv)
 
 
 def _matrix(fn, g, n, max_rhs, opts):

@@ -153,8 +153,9 @@ int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *cu
   g->far_pairs = (long long)M * M;
   for (int b = 0; b < nbodies; ++b) g->far_pairs -= (long long)nodes_per_body[b] * nodes_per_body[b];
   const size_t Md = (size_t)M, Nd = (size_t)nbodies;
-  // arena: doubles first (8 node arrays, xy (2M), 4 body arrays, pint (2N), area), then floats, ints
-  const size_t nd = 8 * Md + 2 * Md + 4 * Nd + 2 * Nd + Nd;
+  // arena: doubles first (8 node arrays, xy (2M), 4 body arrays, pint (2N), area, the
+  // double-layer length scale), then floats, ints
+  const size_t nd = 8 * Md + 2 * Md + 4 * Nd + 2 * Nd + Nd + 1;
   const size_t bytes = nd * 8 + Md * 8 /*xr*/ + (Nd + 1 + Md + g->h_split_body.size()) * 4 + 256;
   int rc = g->arena.reserve(bytes);
   if (rc != BIE_OK) {
@@ -182,6 +183,7 @@ int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *cu
   g->W = take(Nd);
   g->pint = take(2 * Nd);
   g->area = take(Nd);
+  g->dl_scale = take(1);
   g->xr = reinterpret_cast<float2 *>(p);
   int *ip = reinterpret_cast<int *>(g->xr + Md);
   g->body_ptr = ip;
@@ -419,6 +421,60 @@ int bie_elastance_solve(bie_geom *g, int nrhs, const double *q, double *phi, dou
 int bie_mobility_solve(bie_geom *g, int nrhs, const double *FT, double *VW, double *mu_out,
                        const bie_opts *opts, bie_info *info, void *stream) {
   return solve_entry(g, 1, nrhs, FT, VW, mu_out, opts, info, stream);
+}
+
+// Capacitance and resistance: completed double layers, bounded solution (dirichlet.hip).
+static int dl_apply_entry(bie_geom *g, int stokes, int with_C, int nrhs, const double *mu,
+                          double *out, void *stream) {
+  BIE_TRY(check_geom(g));
+  if (nrhs < 1 || !mu || !out || mu == out) {
+    set_error("double-layer apply: nrhs >= 1, non-NULL and distinct mu, out required");
+    return BIE_EINVAL;
+  }
+  return dl_apply(g, stokes, with_C ? 1 : 0, 1.0, nrhs, mu, out, as_stream(stream));
+}
+
+int bie_laplace_dl_apply(bie_geom *g, int with_completion, int nrhs, const double *mu, double *out,
+                         void *stream) {
+  return dl_apply_entry(g, 0, with_completion, nrhs, mu, out, stream);
+}
+
+int bie_stokes_dl_apply(bie_geom *g, int with_completion, int nrhs, const double *mu, double *out,
+                        void *stream) {
+  return dl_apply_entry(g, 1, with_completion, nrhs, mu, out, stream);
+}
+
+static int dl_solve_entry(bie_geom *g, int stokes, int nrhs, const double *data, double *res,
+                          double *u_inf, double *mu_out, const bie_opts *opts, bie_info *info,
+                          void *stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  BIE_TRY(check_geom(g));
+  if (nrhs < 1 || !data || !res || !u_inf) {
+    set_error("capacitance/resistance solve: nrhs >= 1 and non-NULL input and outputs required");
+    return BIE_EINVAL;
+  }
+  bie_opts o;
+  if (opts) o = *opts; else fill_defaults(&o);
+  BIE_TRY(check_opts(o));
+  hipStream_t s = as_stream(stream);
+  int rc = dl_solve(g, stokes, nrhs, data, res, u_inf, mu_out, o, info, s);
+  if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  if (info) {
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc == BIE_OK && !(info->rel_residual <= o.tol)) rc = BIE_ENOCONV;
+  }
+  return rc;
+}
+
+int bie_capacitance_solve(bie_geom *g, int nrhs, const double *phi, double *q, double *u_inf,
+                          double *mu_out, const bie_opts *opts, bie_info *info, void *stream) {
+  return dl_solve_entry(g, 0, nrhs, phi, q, u_inf, mu_out, opts, info, stream);
+}
+
+int bie_resistance_solve(bie_geom *g, int nrhs, const double *VW, double *FT, double *u_inf,
+                         double *mu_out, const bie_opts *opts, bie_info *info, void *stream) {
+  return dl_solve_entry(g, 1, nrhs, VW, FT, u_inf, mu_out, opts, info, stream);
 }
 
 // Identity right-hand-side block, solved in passes of <= max_rhs columns; column j of the

@@ -371,10 +371,10 @@ int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
   return BIE_OK;
 }
 
-// One geometry, nrhs systems of length n = M (kind 0) or 2M (kind 1).
+// One geometry, nrhs systems of length n = M (kinds 0, 2) or 2M (kinds 1, 3).
 int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const double *f, double *x,
                  bie_info *info, hipStream_t s) {
-  const long long n = kind == 0 ? g->M : 2LL * g->M;
+  const long long n = (kind & 1) ? 2LL * g->M : g->M;
   if (g->seg_nrhs != nrhs || g->seg_len != n) {
     BIE_TRY(g->seg.build(std::vector<long long>(nrhs, n), s));
     g->seg_nrhs = nrhs;

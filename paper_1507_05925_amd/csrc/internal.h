@@ -93,6 +93,7 @@ struct bie_geom {
   double *len = nullptr, *xc = nullptr, *yc = nullptr, *W = nullptr;  // [N]
   double *pint = nullptr;   // [N][2] interior read-off points
   double *area = nullptr;   // [N] signed area (validation)
+  double *dl_scale = nullptr;  // [1] length scale R of the completed double layers
   double2 *xy = nullptr;    // [M] float64 source coordinates
   float2 *xr = nullptr;     // [M] float32 coordinates relative to the body centroid
   // source-body splits of the far-field sweep
@@ -116,7 +117,8 @@ struct bie_geom {
 namespace bie {
 
 // ---- kernels.hip: operator pieces -------------------------------------------------------
-// kind: 0 = Laplace (len = M per rhs), 1 = Stokes (len = 2M per rhs)
+// kind: 0 = Laplace (len = M per rhs), 1 = Stokes (len = 2M per rhs); 2 and 3 are the
+// completed double layers of the capacitance and resistance problems (Laplace, Stokes)
 int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L, double alpha,
                    int nrhs, const double *mu, double *out, hipStream_t s);
 int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double *dens,
@@ -125,6 +127,13 @@ int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, h
 int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
                 bool rigid, double *res, hipStream_t st);
 int geometry_build(bie_geom *g, const double *curve, const double *interior, hipStream_t s);
+
+// ---- dirichlet.hip: capacitance and resistance problems (completed double layers) --------
+// kind 2 (Laplace) and 3 (Stokes) of apply_operator / solve_system
+int dl_apply(bie_geom *g, int stokes, int with_C, double alpha, int nrhs, const double *mu,
+             double *out, hipStream_t s);
+int dl_solve(bie_geom *g, int stokes, int nrhs, const double *data, double *res, double *u_inf,
+             double *mu_out, const bie_opts &opts, bie_info *info, hipStream_t s);
 
 // ---- blas.hip: segmented float64 vector kernels used by GMRES -------------------------------
 int seg_dots(const Segments &sg, int nvec, const double *V, long long vstride, const double *w,

@@ -105,6 +105,38 @@ __global__ __launch_bounds__(kBlock) void k_geometry(
   }
 }
 
+// Length scale R of the completed double layers (capacitance and resistance problems): twice the
+// diagonal of the nodes' bounding box, which exceeds the logarithmic capacity of the curves.
+// One workgroup.
+__global__ __launch_bounds__(kBlock) void k_scale_length(int M, const double *__restrict__ x,
+                                                         const double *__restrict__ y,
+                                                         double *__restrict__ R) {
+  __shared__ double sh[4][4];
+  double v[4] = {x[0], -x[0], y[0], -y[0]};  // min x, -max x, min y, -max y
+  for (int k = threadIdx.x; k < M; k += kBlock) {
+    v[0] = fmin(v[0], x[k]);
+    v[1] = fmin(v[1], -x[k]);
+    v[2] = fmin(v[2], y[k]);
+    v[3] = fmin(v[3], -y[k]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[a] = fmin(v[a], __shfl_down(v[a], off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) sh[wid][a] = v[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) m[a] = fmin(fmin(sh[0][a], sh[1][a]), fmin(sh[2][a], sh[3][a]));
+    const double dx = -m[1] - m[0], dy = -m[3] - m[2];
+    R[0] = 2.0 * sqrt(dx * dx + dy * dy);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Source strengths s = w * mu (float64 and float32 copies); len = M (Laplace) or 2M (Stokes).
 // ------------------------------------------------------------------------------------------
@@ -701,6 +733,7 @@ int geometry_build(bie_geom *g, const double *curve, const double *interior, hip
   hipLaunchKernelGGL(k_geometry, dim3(g->N), dim3(kBlock), 0, st, g->M, g->body_ptr, curve,
                      interior, g->x, g->y, g->nx, g->ny, g->w, g->kappa, g->px, g->py, g->len,
                      g->xc, g->yc, g->W, g->pint, g->area, g->xy, g->xr, g->body_of);
+  hipLaunchKernelGGL(k_scale_length, dim3(1), dim3(kBlock), 0, st, g->M, g->x, g->y, g->dl_scale);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
@@ -709,6 +742,7 @@ int geometry_build(bie_geom *g, const double *curve, const double *interior, hip
 // share each pair's geometry work.
 int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L, double alpha,
                    int nrhs, const double *mu, double *out, hipStream_t st) {
+  if (kind == 2 || kind == 3) return dl_apply(g, kind - 2, with_L, alpha, nrhs, mu, out, st);
   if (precision != BIE_FP64 && precision != BIE_MIXED) {
     set_error("precision must be BIE_FP64 or BIE_MIXED");
     return BIE_EINVAL;
