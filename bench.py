@@ -25,6 +25,8 @@ Other workloads (not the default line):
   --workload nanocomposite  every configuration of the paper's nanocomposite capacitance table
                      (two plates and m x 10 particles, m = 0, 1, 4, 16, five aspect ratios): the
                      capacitance and the solve time beside the printed ones.
+  --workload crosstest  the paper's cross-tests (capacitance then elastance, resistance then
+                     mobility) on two discs at three gaps and the splash curves.
   --workload copy    a plain 256 MiB device copy kernel (y = -x), 6 times: the known-size reference that
                      scales the FETCH_SIZE / WRITE_SIZE counters into HBM bytes.
 """
@@ -52,7 +54,8 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--workload", choices=["starfish", "serve", "batched", "nanocomposite", "copy"],
+    p.add_argument("--workload", choices=["starfish", "serve", "batched", "nanocomposite", "crosstest",
+                                          "copy"],
                    default="starfish")
     p.add_argument("--requests", type=int, default=2000)
     p.add_argument("--serve-restart", type=int, default=20)
@@ -305,6 +308,80 @@ def nanocomposite_bench(a):
         "max_abs_diff_vs_paper_C": max(x["abs_diff"] for x in out), "rows": out}))
 
 
+def crosstest_bench(a):
+    """The paper's cross-tests on the GPU: prescribed potentials (rigid motions) -> capacitance
+    (resistance) solve -> elastance (mobility) solve with the resulting charges (forces, torques)
+    -> the prescribed data up to u_inf. Cases: two discs at gaps 0.5, 0.05, 0.005 (256, 1024,
+    6144 nodes per disc) and the five splash curves (1024 nodes each), float64 direct, GMRES tol
+    1e-12. One untimed round, then the median of 5 timed rounds per case."""
+    import numpy as np
+    import torch
+
+    from paper_1507_05925_amd import bie2d
+    from paper_1507_05925_amd import workloads as wl
+
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "two_disc_tables.json")))
+    spl = json.load(open(os.path.join(ROOT, "tests", "golden", "splash_prescribed.json")))
+    cases = [(f"two discs d={d}", wl.two_discs(d, n), [tab["elastance"]["phi1"], tab["elastance"]["phi2"]],
+              [*tab["mobility"]["v_body1"], tab["mobility"]["omega1"], *tab["mobility"]["v_body2"],
+               tab["mobility"]["omega2"]]) for d, n in ((0.5, 256), (0.05, 1024), (0.005, 6144))]
+    cases.append(("splash", wl.splash(1024), spl["phi"],
+                  list(np.stack([spl["v1"], spl["v2"], spl["omega"]], 1).reshape(-1))))
+    o = bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_DIRECT, tol=1e-12,
+                           restart=300, max_iter=3000)
+    bie2d.bie_profile_enable(True)
+    out, total_t, nsolves = [], 0.0, 0
+    for name, c, phi, VW in cases:
+        g = bie2d.Geometry.from_curves(c)
+        phid = torch.as_tensor(np.array(phi)[None], device="cuda")
+        vwd = torch.as_tensor(np.array(VW)[None], device="cuda")
+
+        def rounds():
+            q, ui, i1 = bie2d.bie_capacitance_solve(g, phid, o, allow_noconv=True)
+            back, i2 = bie2d.bie_elastance_solve(g, q, o, allow_noconv=True)
+            FT, uv, i3 = bie2d.bie_resistance_solve(g, vwd, o, allow_noconv=True)
+            bm, i4 = bie2d.bie_mobility_solve(g, FT, o, allow_noconv=True)
+            return q, ui, back, FT, uv, bm, (i1, i2, i3, i4)
+
+        rounds()
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            q, ui, back, FT, uv, bm, infos = rounds()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        t = float(np.median(ts))
+        total_t += t
+        nsolves += 4
+        e_phi = float(np.abs(back.cpu().numpy()[0] + float(ui.cpu().numpy()[0]) - np.array(phi)).max())
+        want = np.array(VW).reshape(-1, 3).copy()
+        want[:, 0:2] -= uv.cpu().numpy()[0][None, :]
+        e_vw = float(np.abs(bm.cpu().numpy()[0].reshape(-1, 3) - want).max())
+        out.append({"case": name, "M": int(c.M), "seconds_per_round": t,
+                    "iters": [i["iters"] for i in infos],
+                    "rel_residual": [i["rel_residual"] for i in infos],
+                    "max_err_potential": e_phi, "max_err_rigid_motion": e_vw,
+                    "u_inf_laplace": float(ui.cpu().numpy()[0]),
+                    "u_inf_stokes": [float(v) for v in uv.cpu().numpy()[0]]})
+        g.close()
+    pr = bie2d.bie_profile_read(bie2d.BIE_K_DOUBLE_LAYER)
+    n, ms, pairs = pr["launches"], pr["ms_total"], pr["pairs"]
+    print(json.dumps({
+        "metric": "solves/s of the paper's cross-tests (capacitance + elastance, resistance + "
+                  "mobility; two discs at three gaps and the splash curves)",
+        "value": nsolves / total_t, "unit": "solves/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "the paper's geometries and prescribed data",
+        "config": {"workload": "cross-tests: two discs d = 0.5, 0.05, 0.005 (256, 1024, 6144 "
+                               "nodes per disc), splash (5 x 1024), float64 direct, tol 1e-12"},
+        "double_layer_applies": {"launches": n, "ms_total": ms, "pairs": pairs,
+                                 "pairs_per_s": pairs / (ms * 1e-3) if ms > 0 else None},
+        "max_err_potential": max(x["max_err_potential"] for x in out),
+        "max_err_rigid_motion": max(x["max_err_rigid_motion"] for x in out),
+        "cases": out}))
+
+
 def copy_bench(a):
     import torch
 
@@ -336,6 +413,8 @@ def main():
         return batched_bench(a)
     if a.workload == "copy":
         return copy_bench(a)
+    if a.workload == "crosstest":
+        return crosstest_bench(a)
     if a.workload == "nanocomposite":
         return nanocomposite_bench(a)
     import numpy as np
