@@ -18,6 +18,6 @@ Contents
 
 Parity status: every function is pinned by tests/test_oracle_*.py against closed forms, the
 paper's tables, discrete Gauss-law identities, invariants or brute force (no function is
-"parity unpinned"); the splash-test and nanocomposite values have no printed potentials, so
-those geometries are used only as inputs.
+"parity unpinned"). The splash geometry is pinned through the paper's cross-tests with its printed
+potentials and rigid motions; the nanocomposite geometry through the printed capacitances.
 """
