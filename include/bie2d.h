@@ -294,7 +294,9 @@ int bie_server_destroy(bie_server *srv);
  * summed durations and the work units they process (target-source pairs times rhs unless the
  * class says otherwise).
  * bie_profile_enable(1) clears the counters; bie_profile_read() waits for the recorded events
- * of that class and returns the totals. Process-wide; not thread safe. */
+ * of that class and returns the totals. bie_profile_select(mask) limits the recording to the
+ * classes whose bit (1 << class) is set (default: all), so that timing one class adds no events
+ * around the others. Process-wide; not thread safe. */
 #define BIE_K_FAR_LAPLACE_F32 0 /* float32 far-field sweep, Laplace            */
 #define BIE_K_FAR_LAPLACE_F64 1 /* float64 far-field sweep, Laplace            */
 #define BIE_K_FAR_STOKES_F32 2  /* float32 far-field sweep, Stokes             */
@@ -306,6 +308,7 @@ int bie_server_destroy(bie_server *srv);
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_COUNT 9
 int bie_profile_enable(int on);
+int bie_profile_select(unsigned mask);
 int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs);
 
 #ifdef __cplusplus

@@ -21,6 +21,7 @@ struct ClassStats {
 };
 
 bool g_on = false;
+unsigned g_mask = ~0u;
 ClassStats g_stats[BIE_K_COUNT];
 std::vector<hipEvent_t> g_pool;
 
@@ -52,7 +53,8 @@ int drain(ClassStats &c) {
 
 }  // namespace
 
-ProfScope::ProfScope(int k, hipStream_t st, long long p) : kclass(k), s(st), pairs(p), on(g_on) {
+ProfScope::ProfScope(int k, hipStream_t st, long long p)
+    : kclass(k), s(st), pairs(p), on(g_on && ((g_mask >> k) & 1u)) {
   if (!on) return;
   hipEvent_t a = get_event();
   if (!a) {
@@ -88,6 +90,11 @@ int bie_profile_enable(int on) {
     c = ClassStats();
   }
   g_on = on != 0;
+  return BIE_OK;
+}
+
+int bie_profile_select(unsigned mask) {
+  g_mask = mask;
   return BIE_OK;
 }
 
