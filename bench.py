@@ -44,6 +44,14 @@ FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), 
 FLOPS_PER_CMAC = 8   # complex multiply-add
 
 
+def m2l_flops_per_entry(p):
+    """One M2L interaction-list entry as the kernel computes it: the source scaled by d^-m
+    (p complex products, 6 flops each), the real Hankel matrix C (p x p) applied to its real and
+    imaginary parts (2 p^2 multiply-adds, 4 p^2 flops), and the product scaled by d^-(n+1) and
+    added (p complex multiply-adds, 8 flops each)."""
+    return 4 * p * p + 14 * p
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -452,7 +460,7 @@ def main():
                           "k_lap_far_f32<1>"),
         "k_lap_far_f64": (bie2d.BIE_K_FAR_LAPLACE_F64, FLOPS_PER_PAIR, "f64", "alu",
                           "k_lap_far_f64<1>"),
-        "k_m2l": (bie2d.BIE_K_FMM_M2L, FLOPS_PER_CMAC, "f64", "mfma", f"k_m2l<{order}>"),
+        "k_m2l": (bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(order), "f64", "mfma", f"k_m2l<{order}>"),
         "k_near_laplace": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near_laplace"),
         "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64", "alu", "k_lap_epilogue"),
     }

@@ -303,7 +303,7 @@ int bie_server_destroy(bie_server *srv);
 #define BIE_K_FAR_STOKES_F64 3  /* float64 far-field sweep, Stokes             */
 #define BIE_K_EPILOGUE 4        /* self blocks + diagonal + completion + sum   */
 #define BIE_K_FMM 5             /* FMM far field, all its kernels; units: M^2 per rhs (equivalent pairs) */
-#define BIE_K_FMM_M2L 6         /* FMM multipole-to-local; units: complex multiply-adds */
+#define BIE_K_FMM_M2L 6         /* FMM multipole-to-local; units: interaction-list entries (box pairs) per set */
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_COUNT 9

@@ -52,7 +52,9 @@ struct FmmTree {
   long long m2l_entries = 0, near_pairs = 0;  // work units for instrumentation
   int2 *run = nullptr;  // near field: per leaf, runs [k0, k1) of sorted nodes in neighbour leaves
   double2 *xs = nullptr, *center = nullptr, *nrm = nullptr;  // sorted coords (rel. root), centres
-  double2 *T_m2l = nullptr;  // Hankel vectors [40][2p]
+  double2 *T_m2l = nullptr;  // Hankel vectors [40][2p] (float32 M2L)
+  double *T_c = nullptr;      // real Hankel vector C[k] = k! / s^k, [2p] (float64 M2L)
+  double2 *T_dpow = nullptr;  // powers d^-k, k = 0 .. 16 ceil(p / 16), per offset [40][.]
   double2 *T_tau = nullptr;  // M2M / L2L Toeplitz vectors [4][2p] (p zeros, then tau)
   double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n c^n / n!  and  c^n / n!
   double *inv_h = nullptr;  // [L+1]
@@ -273,123 +275,127 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
 }
 
 // M2L for all boxes of levels >= 2, written into Lexp, on the matrix cores. Multipoles are stored
-// as u_m = a_m s^m / m! (s: the table scale), which turns the operator for a box offset d into a
-// Hankel product
-//   b_n = (1/h) ((-1)^n s^n / n!) sum_m u_m V_d[m + n],   V_d[k] = k! / (s^k d^(k+1)).
-// Target boxes are grouped 16 at a time (same level, same position within the parent, so their
-// interaction lists share most offsets). For each offset d used by a group, the 16 multipoles
-// (one per target; zero where a target has no source at that offset) form the columns of U, and
-// the group's locals accumulate H_d U, with H_d the Hankel matrix of V_d written as a real
-// 2p x 2p matrix (rows and columns interleave real and imaginary parts), in 16x16x4 float64
-// MFMA tiles: lane (j, q) = (lane % 16, lane / 16) holds A[j][q] and B[q][j] of a k-step and
-// rows q + 4r of column j of an accumulator tile.
-// One workgroup of eight waves per (group, set): waves 0-3 take the first ceil(RT/2) row tiles and
-// waves 4-7 the rest, and within each half the four waves split the k-steps (each loads a quarter
-// of U); the four partial tiles of every row tile are then added in wave order through LDS.
-// A is read from the offset table in LDS (real and imaginary planes), B from the multipoles.
-// Offsets are taken in increasing order: each target's sum has a fixed order.
+// as u_m = a_m s^m / m! (s: the table scale). For a box offset d (in units of the box size) the
+// operator is the Hankel product b_n = (1/h) f_n sum_m u_m V_d[m + n] with f_n = (-1)^n s^n / n!
+// and V_d[k] = k! / (s^k d^(k+1)) = C[k] d^-(k+1), where C[k] = k! / s^k is real. So
+//   b_n = (1/h) f_n d^-(n+1) sum_m C[m + n] (u_m d^-m):
+// a complex scaling of the source, one real Hankel matrix C shared by every offset, and a complex
+// scaling of the product. Target boxes are grouped 16 at a time (same level, same position in the
+// parent, so their interaction lists share most offsets); an item is one offset d of a group with
+// the 16 sources at that offset (zero columns where a target has none). Per item, the real and
+// imaginary parts of the 16 scaled sources form two 16-column B operands, C's row tiles (in
+// registers for the whole kernel) the A operands of 16x16x4 float64 MFMAs, and the lane scales
+// the two results (the real and imaginary parts of C u~) by d^-(n+1) into its complex
+// accumulators. MFMA lane layout: lane (j, q) = (lane % 16, lane / 16) holds A[j][q] and B[q][j]
+// of a k-step and rows q + 4r of column j of an accumulator tile.
+// One workgroup of four waves per (group, set): wave w takes items w, w + 4, ... in order, and
+// the four partial sums are added in wave order through LDS at the end (a fixed order).
 typedef double m2l_d4 __attribute__((ext_vector_type(4)));
 
 template <int P>
-__global__ __launch_bounds__(512) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
-                                            const int *__restrict__ grp_tgt,
-                                            const int *__restrict__ grp_lvl,
-                                            const int *__restrict__ item_off,
-                                            const int *__restrict__ item_src,
-                                            const double *__restrict__ inv_h,
-                                            const double *__restrict__ fact_out,
-                                            const double2 *__restrict__ Vtab,
-                                            const double2 *__restrict__ Mexp,
-                                            double2 *__restrict__ Lexp) {
-  constexpr int RT = 2 * P / 16;      // accumulator row tiles
-  constexpr int RH = (RT + 1) / 2;    // row tiles of the first half
-  constexpr int KW = P / 8;           // k-steps per wave (2p / 4 in all, over four waves)
-  extern __shared__ double lds_v[];
-  double *VR = lds_v, *VI = lds_v + 40 * 2 * P;
-  for (int i = threadIdx.x; i < 40 * 2 * P; i += blockDim.x) {
-    const double2 v = Vtab[i];
-    VR[i] = v.x;
-    VI[i] = v.y;
-  }
-  __syncthreads();
+struct M2lShape {
+  static constexpr int RT = (P + 15) / 16;   // row tiles of C (rows >= P are zero)
+  static constexpr int KS = P / 4;           // k-steps
+  static constexpr int DP = 16 * RT + 1;     // powers d^-k, k = 0 .. 16 RT, per offset
+  static constexpr int CN = 16 * RT + P;     // C[k] for k < CN (zeros from 2p - 1 on)
+  static constexpr int TABLE = 40 * DP * 2 + CN;  // doubles
+  static constexpr int RED = 4 * RT * 4 * 2 * 64;
+  static constexpr int LDS = TABLE > RED ? TABLE : RED;
+};
+
+template <int P>
+__global__ __launch_bounds__(256, 3) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
+                                               const int *__restrict__ grp_tgt,
+                                               const int *__restrict__ grp_lvl,
+                                               const int *__restrict__ item_off,
+                                               const int *__restrict__ item_src,
+                                               const double *__restrict__ inv_h,
+                                               const double *__restrict__ fact_out,
+                                               const double *__restrict__ Ctab,
+                                               const double2 *__restrict__ Dpow,
+                                               const double2 *__restrict__ Mexp,
+                                               double2 *__restrict__ Lexp) {
+  using S = M2lShape<P>;
+  constexpr int RT = S::RT, KS = S::KS, DP = S::DP;
+  __shared__ double lds[S::LDS];
+  double2 *dps = reinterpret_cast<double2 *>(lds);
+  double *cs = lds + 40 * DP * 2;
+  for (int i = threadIdx.x; i < 40 * DP; i += blockDim.x) dps[i] = Dpow[i];
+  for (int i = threadIdx.x; i < S::CN; i += blockDim.x) cs[i] = i < 2 * P - 1 ? Ctab[i] : 0.0;
   const int g = g0 + blockIdx.x, set = blockIdx.y;
   const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = wv & 3, half = wv >> 2;
-  const int rt0 = half ? RH : 0;
-  // A[i][k] with i = 2n + ci, k = 2m + ck: Re V[n+m] if ci == ck, Im V[n+m] if (1, 0),
-  // -Im V[n+m] if (0, 1). This lane: ci = j & 1, ck = q & 1, n + m = 8 rt + 2 kk + abase.
-  const int ci = j & 1, ck = q & 1;
-  const double *plane = ci == ck ? VR : VI;
-  const double sgn = (ci == 0 && ck == 1) ? -1.0 : 1.0;
-  const int abase = (j >> 1) + (q >> 1) + 2 * KW * w;
-  m2l_d4 acc[RH];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double br[RT][4], bi[RT][4];
 #pragma unroll
-  for (int t = 0; t < RH; ++t) acc[t] = m2l_d4{0.0, 0.0, 0.0, 0.0};
-  const double *Ms = reinterpret_cast<const double *>(Mexp + (size_t)set * nbox * P);
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) br[t][r] = bi[t][r] = 0.0;
+  const double2 *Ms = Mexp + (size_t)set * nbox * P;
   const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
-  // B[k][j] = component ck of u_src[m]: k = 4 kk + q, m = 2 kk + q / 2, kk = KW w + kl.
-  // Software pipeline: the loads of item it+1's B and of item it+2's source index are issued
-  // before item it's MFMAs.
-  const int lofs = 2 * (q >> 1) + ck + 4 * KW * w;
-  // loads are unconditional (a missing source reads box 0) and zeroed afterwards, so no branch
-  // separates the prefetch from the MFMAs
-  auto load_b = [&](double *b, int src) {
-    const double *u = Ms + (size_t)max(src, 0) * 2 * P + lofs;
-#pragma unroll
-    for (int kl = 0; kl < KW; ++kl) b[kl] = u[4 * kl];
-#pragma unroll
-    for (int kl = 0; kl < KW; ++kl) b[kl] = src < 0 ? 0.0 : b[kl];
-  };
-  double bn[KW];
-  load_b(bn, i0 < i1 ? item_src[i0 * 16 + j] : -1);
-  int src_nn = i0 + 1 < i1 ? item_src[(i0 + 1) * 16 + j] : -1;
-  for (int it = i0; it < i1; ++it) {
+  __syncthreads();
+  for (int it = i0 + w; it < i1; it += 4) {
+    // this lane's sources u_src[m], m = 4 kk + q; a missing source reads box 0, then zeros
+    const int src = item_src[it * 16 + j];
     const int o = item_off[it];
-    double b[KW];
+    const double2 *up = Ms + (size_t)max(src, 0) * P + q;
+    const double2 *dp = dps + o * DP;
+    double bre[KS], bim[KS];
 #pragma unroll
-    for (int kl = 0; kl < KW; ++kl) b[kl] = bn[kl];
-    load_b(bn, it + 1 < i1 ? src_nn : -1);
-    src_nn = it + 2 < i1 ? item_src[(it + 2) * 16 + j] : -1;
-    const double *Ap = plane + o * 2 * P + abase + 8 * rt0;
-    // k-step outer, row tile inner: consecutive MFMAs write different accumulators
-    if (rt0 + RH <= RT) {
+    for (int kk = 0; kk < KS; ++kk) {
+      const double2 u = up[4 * kk];
+      const double2 pw = dp[4 * kk + q];  // d^-m
+      const double ur = src < 0 ? 0.0 : u.x, ui = src < 0 ? 0.0 : u.y;
+      bre[kk] = fma(ur, pw.x, -ui * pw.y);
+      bim[kk] = fma(ur, pw.y, ui * pw.x);
+    }
+    // one row tile at a time: the real and imaginary products, then the scaling by d^-(n+1).
+    // A[n][m] = C[n + m]; rows n >= P (the last tile's padding) hold finite values that are
+    // never written out
 #pragma unroll
-      for (int kl = 0; kl < KW; ++kl)
+    for (int t = 0; t < RT; ++t) {
+      const double *ca = cs + 16 * t + j + q;
+      m2l_d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < RH; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
-                                                        0, 0, 0);
-    } else {  // the second half holds one tile fewer
+      for (int kk = 0; kk < KS; ++kk) {
+        const double a = ca[4 * kk];
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bre[kk], yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bim[kk], yi, 0, 0, 0);
+      }
 #pragma unroll
-      for (int kl = 0; kl < KW; ++kl)
-#pragma unroll
-        for (int t = 0; t < RH - 1; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sgn * Ap[8 * t + 2 * kl], b[kl], acc[t],
-                                                        0, 0, 0);
+      for (int r = 0; r < 4; ++r) {
+        const double2 pw = dp[16 * t + q + 4 * r + 1];  // d^-(n+1)
+        br[t][r] = fma(yr[r], pw.x, fma(-yi[r], pw.y, br[t][r]));
+        bi[t][r] = fma(yr[r], pw.y, fma(yi[r], pw.x, bi[t][r]));
+      }
     }
   }
-  // partial tiles through LDS (the table is no longer needed): red[w][rt][r][lane]
-  __syncthreads();
-  double *red = lds_v;
+  __syncthreads();  // the tables are no longer read: their LDS holds the partial sums
+  double *red = lds;
 #pragma unroll
-  for (int t = 0; t < RH; ++t)
-    if (rt0 + t < RT)
+  for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[((w * RT + rt0 + t) * 4 + r) * 64 + lane] = acc[t][r];
+    for (int r = 0; r < 4; ++r) {
+      red[(((w * RT + t) * 4 + r) * 2) * 64 + lane] = br[t][r];
+      red[(((w * RT + t) * 4 + r) * 2 + 1) * 64 + lane] = bi[t][r];
+    }
   __syncthreads();
   const int tb = grp_tgt[g * 16 + j];
   if (tb < 0) return;
   const double sc = inv_h[grp_lvl[g]];
-  double *out = reinterpret_cast<double *>(Lexp + ((size_t)set * nbox + tb) * P) + (q & 1);
-  for (int rt = wv; rt < RT; rt += 8)
+  double2 *out = Lexp + ((size_t)set * nbox + tb) * P;
+  for (int t = w; t < RT; t += 4)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double v = 0.0;
+      const int n = 16 * t + q + 4 * r;
+      if (n >= P) continue;
+      double vr = 0.0, vi = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) v += red[((ww * RT + rt) * 4 + r) * 64 + lane];
-      const int n = 8 * rt + 2 * r + (q >> 1);
-      out[2 * n] = v * sc * fact_out[n];
+      for (int ww = 0; ww < 4; ++ww) {
+        vr += red[(((ww * RT + t) * 4 + r) * 2) * 64 + lane];
+        vi += red[(((ww * RT + t) * 4 + r) * 2 + 1) * 64 + lane];
+      }
+      const double f = sc * fact_out[n];
+      out[n] = make_double2(vr * f, vi * f);
     }
 }
 
@@ -949,6 +955,28 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
         v = v * dinv * ((double)(k + 1) / csc);
       }
     }
+  // float64 M2L: C[k] = k! / s^k and the powers d^-k of the 40 offsets
+  const int dpn = 16 * ((p + 15) / 16) + 1;
+  std::vector<double> Tc(2 * p);
+  {
+    double v = 1.0;
+    for (int k = 0; k < 2 * p; ++k) {
+      Tc[k] = v;
+      v *= (double)(k + 1) / csc;
+    }
+  }
+  std::vector<double2> Tdpow((size_t)40 * dpn);
+  for (int dx = -3; dx <= 3; ++dx)
+    for (int dy = -3; dy <= 3; ++dy) {
+      const int o = ocompact[(dx + 3) * 7 + (dy + 3)];
+      if (o < 0) continue;
+      const cd dinv = 1.0 / cd(dx, dy);
+      cd v = 1.0;
+      for (int k = 0; k < dpn; ++k) {
+        Tdpow[(size_t)o * dpn + k] = make_double2(v.real(), v.imag());
+        v *= dinv;
+      }
+    }
   std::vector<double> fact_out(p), fact_in(p);
   {
     double f = 1.0;  // s^n / n!
@@ -998,8 +1026,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
                       grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + run_ptr.size() +
                       nnear + 2 * chunk_leaf.size();
-  const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p;
-  const size_t bytes = d2 * 16 + (L + 1 + 2 * p) * 8 + ints * 4 + 32 * 256;
+  const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p + Tdpow.size();
+  const size_t bytes = d2 * 16 + (L + 1 + 4 * p) * 8 + ints * 4 + 34 * 256;
   BIE_TRY(t.buf.reserve(bytes));
   char *q = t.buf.as<char>();
   auto take = [&](size_t nbytes) {
@@ -1011,6 +1039,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.nrm = (double2 *)take(M * 16);
   t.center = (double2 *)take(t.nbox * 16);
   t.T_m2l = (double2 *)take((size_t)80 * p * 16);
+  t.T_c = (double *)take(Tc.size() * 8);
+  t.T_dpow = (double2 *)take(Tdpow.size() * 16);
   t.fact_out = (double *)take(p * 8);
   t.fact_in = (double *)take(p * 8);
   t.T_tau = (double2 *)take((size_t)8 * p * 16);
@@ -1043,6 +1073,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.nrm, nrm.data(), M * 16));
   BIE_TRY(up(t.center, center.data(), t.nbox * 16));
   BIE_TRY(up(t.T_m2l, Tm2l.data(), Tm2l.size() * 16));
+  BIE_TRY(up(t.T_c, Tc.data(), Tc.size() * 8));
+  BIE_TRY(up(t.T_dpow, Tdpow.data(), Tdpow.size() * 16));
   BIE_TRY(up(t.T_tau, Ttau.data(), Ttau.size() * 16));
   BIE_TRY(up(t.fact_out, fact_out.data(), p * 8));
   BIE_TRY(up(t.fact_in, fact_in.data(), p * 8));
@@ -1066,32 +1098,15 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   return BIE_OK;
 }
 
-template <int P>
-bool m2l_lds_raised(size_t bytes) {
-  static size_t done = 0;
-  if (bytes <= 65536 || bytes <= done) return true;
-  if (hipFuncSetAttribute((const void *)k_m2l<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)bytes) != hipSuccess)
-    return false;
-  done = bytes;
-  return true;
-}
-
 // M2L for groups [ga, gb) (groups are ordered by level, so a level is one range)
 template <int P>
 int launch_m2l(const FmmTree &t, int ga, int gb, int nsets, const double2 *Mexp, double2 *Lexp,
                hipStream_t s) {
   if (gb <= ga) return BIE_OK;
-  const size_t lds = (size_t)2 * 40 * 2 * P * sizeof(double);
-  if (!m2l_lds_raised<P>(lds)) {
-    set_error("fmm: M2L table does not fit in LDS for this order");
-    return BIE_EINVAL;
-  }
-  // the reduction of the four partial tiles reuses the table's LDS (1024 P <= 1280 P bytes)
-  static_assert(4 * (2 * P / 16) * 4 * 64 <= 2 * 40 * 2 * P, "M2L reduction exceeds the table");
-  hipLaunchKernelGGL(k_m2l<P>, dim3(gb - ga, nsets), dim3(512), lds, s, ga, t.nbox, t.grp_ptr,
-                     t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_m2l,
-                     Mexp, Lexp);
+  static_assert(M2lShape<P>::LDS * sizeof(double) <= 65536, "M2L LDS exceeds 64 KiB");
+  hipLaunchKernelGGL(k_m2l<P>, dim3(gb - ga, nsets), dim3(256), 0, s, ga, t.nbox, t.grp_ptr,
+                     t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_c,
+                     t.T_dpow, Mexp, Lexp);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
@@ -1126,7 +1141,7 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
                          0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
   }
   if (t.ngroup > 0) {
-    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets * (long long)P * P);
+    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets);
     if constexpr (std::is_same<T, float>::value)
       BIE_TRY(launch_m2l_f32<P>(t, nsets, Mexp, Lexp, s));
     else
