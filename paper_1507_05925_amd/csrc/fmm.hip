@@ -12,8 +12,9 @@
 // non-empty boxes are stored, in Morton order, so each box is a contiguous run of sorted nodes. Expansions are scaled by the box size h:
 //   multipole a_m = sum_k Q_k ((zeta_k - c)/h)^m,   F(z) = sum_m a_m h^m / (z - c)^{m+1}
 //   local     F(z) = sum_n b_n ((z - c)/h)^n
-// so the 40 M2L operators (offsets d with max(|dx|,|dy|) in {2,3}) and the 4 M2M / 4 L2L operators
-// are the same at every level (M2L carries one 1/h factor). Near field: the 3 x 3 neighbouring
+// so the 40 M2L operators (offsets d with max(|dx|,|dy|) in {2,3}) and the 4 M2M operators are
+// the same at every level (M2L carries one 1/h factor). There is no L2L pass: each target sums
+// the local expansions of all its ancestors directly. Near field: the 3 x 3 neighbouring
 // leaves, summed directly in float64 for every pair k != i, including pairs on the same body, so
 // the epilogue adds only the diagonal limit, identity and completion. Deterministic: one wave per
 // box with one lane per coefficient; fixed list orders.
@@ -55,7 +56,7 @@ struct FmmTree {
   double2 *T_m2l = nullptr;  // Hankel vectors [40][2p] (float32 M2L)
   double *T_c = nullptr;      // real Hankel vector C[k] = k! / s^k, [2p] (float64 M2L)
   double2 *T_dpow = nullptr;  // powers d^-k, k = 0 .. 16 ceil(p / 16), per offset [40][.]
-  double2 *T_tau = nullptr;  // M2M / L2L Toeplitz vectors [4][2p] (p zeros, then tau)
+  double2 *T_tau = nullptr;  // M2M Toeplitz vectors [4][2p] (p zeros, then tau)
   double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n c^n / n!  and  c^n / n!
   double *inv_h = nullptr;  // [L+1]
   DevBuf work;              // charges + expansions
@@ -231,15 +232,12 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
   }
 }
 
-// The translations between a box and its children are Toeplitz products with one vector per
-// child position: with d = (child centre - parent centre) / parent size = (+-1/4, +-1/4), the
-// table scale s and tau[k] = (s d)^k / k!,
-//   M2M (stored u_n = a_n s^n / n!):  u_parent[n] = sum_{m <= n} 2^-m u_child[m] tau[n - m]
-//   L2L (plain coefficients b):  b_child[n] = 2^-n (s^n/n!) sum_{m >= n} (m!/s^m) b_parent[m]
-//                                                                          tau[m - n]
-// The table holds, per position, p zeros followed by tau[0..p-1], so that both sums read
-// tau at a lane-dependent offset without a bound test. It sits in LDS; the source coefficient
-// of step m is read from lane m (readlane, wave-uniform).
+// M2M is a Toeplitz product with one vector per child position: with d = (child centre - parent
+// centre) / parent size = (+-1/4, +-1/4), the table scale s and tau[k] = (s d)^k / k!,
+//   u_parent[n] = sum_{m <= n} 2^-m u_child[m] tau[n - m]   (stored u_n = a_n s^n / n!).
+// The table holds, per position, p zeros followed by tau[0..p-1], so that the sum reads tau at a
+// lane-dependent offset without a bound test. It sits in LDS; the source coefficient of step m
+// is read from lane m (readlane, wave-uniform).
 
 // M2M for one level: waves walk (parent box, set) items with a grid stride.
 template <int P, class T>
@@ -503,44 +501,6 @@ __global__ __launch_bounds__(512) void k_m2l_f32(int nbox, const int *__restrict
   }
 }
 
-// L2L from level l to l+1 (children of level l+1 boxes' parents), accumulated into Lexp; waves
-// walk (child box, set) items with a grid stride.
-template <int P, class T>
-__global__ __launch_bounds__(256) void k_l2l(int nb, int off, int nbox, int nsets,
-                                            const int *__restrict__ parent,
-                                            const double2 *__restrict__ tau,
-                                            const double *__restrict__ fact_in, cx<T> *Lexp) {
-  __shared__ cx<T> tp[8 * P];
-  for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = mkc<T>((T)tau[i].x, (T)tau[i].y);
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int n = lane < P ? lane : P - 1;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const T fi = (T)fact_in[n];
-  const T sc = ldexp(fi, -n);
-  const long long total = (long long)nb * nsets;
-  for (long long item = (long long)blockIdx.x * 4 + wave; item < total;
-       item += (long long)gridDim.x * 4) {
-    const int set = (int)(item / nb);
-    const int c = off + (int)(item % nb);
-    const int pc = parent[c];
-    const int cpos = pc & 3, pb = pc >> 2;
-    const cx<T> bp = Lexp[((size_t)set * nbox + pb) * P + n];
-    const cx<T> beta = mkc<T>(bp.x / fi, bp.y / fi);  // m! b_m / s^m on lane m
-    const cx<T> *tc = tp + cpos * 2 * P + P - n;      // tc[m] = tau[m - n], zero for m < n
-    cx<T> a0 = mkc<T>(0, 0), a1 = a0;
-#pragma unroll
-    for (int m = 0; m < P; m += 2) {
-      a0 = cfma(mkc<T>(rl(beta.x, m), rl(beta.y, m)), tc[m], a0);
-      a1 = cfma(mkc<T>(rl(beta.x, m + 1), rl(beta.y, m + 1)), tc[m + 1], a1);
-    }
-    if (lane < P) {
-      cx<T> *o = Lexp + ((size_t)set * nbox + c) * P + n;
-      *o = mkc<T>(o->x + (a0.x + a1.x) * sc, o->y + (a0.y + a1.y) * sc);
-    }
-  }
-}
-
 // Local expansion value F and derivative F' at w = (z - c)/h (Horner); F' includes 1/h. The
 // coefficients are wave-uniform (one box per wave) and P is a compile-time constant, so the
 // loads batch into a few scalar loads.
@@ -639,22 +599,37 @@ __global__ __launch_bounds__(64) void k_near_laplace(
   if (valid) out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
 }
 
-// L2P, Laplace: adds -(1/2pi) Re(nu F(z)) for the local expansion F of the target's leaf.
+// Downward pass and evaluation in one: the local expansion of a leaf is the sum over its
+// ancestors A (levels 2 to L, the leaf included) of A's M2L part re-expanded about the leaf, and
+// re-expanding a polynomial about another centre is exact (L2L has no truncation). So each target
+// evaluates the M2L part of every ancestor directly at its own scaled coordinate
+// w_A = (z - c_A)/h_A and sums the values (levels in decreasing order), which replaces the
+// level-by-level L2L passes. The ancestors are wave-uniform (one leaf per wave), so their
+// coefficients come in by scalar loads.
+// L2P, Laplace: adds -(1/2pi) Re(nu F(z)).
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_l2p_laplace(
-    int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
-    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const int *__restrict__ parent,
+    const double2 *__restrict__ center, const double2 *__restrict__ xs,
+    const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int box = leaf_box[leaf];
-  const double2 c = center[box];
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   if (j >= leaf_start[leaf + 1]) return;
   const double2 z = xs[j], nv = nrm[j];
-  const cx<T> F = eval_value<P>(Lexp + ((size_t)r * nbox + box) * P,
-                                mkc<T>((T)((z.x - c.x) * ih_leaf), (T)((z.y - c.y) * ih_leaf)));
+  cx<T> F = mkc<T>(0, 0);
+  int b = leaf_box[leaf];
+  double ih = ih_leaf;
+  for (int l = L; l >= 2; --l) {
+    const double2 c = center[b];
+    const cx<T> Fl = eval_value<P>(Lexp + ((size_t)r * nbox + b) * P,
+                                   mkc<T>((T)((z.x - c.x) * ih), (T)((z.y - c.y) * ih)));
+    F = mkc<T>(F.x + Fl.x, F.y + Fl.y);
+    b = parent[b] >> 2;
+    ih *= 0.5;
+  }
   double *o = out + (size_t)r * M + perm[j];
   *o -= (nv.x * (double)F.x - nv.y * (double)F.y) / (2.0 * kPi);  // Re(nu F)
 }
@@ -693,22 +668,34 @@ __global__ __launch_bounds__(64) void k_near_stokes(
 // (1/4)[conj(nu) conj(C' - conj(z) A') + conj(nu) conj(B) + nu (conj(A) + A)].
 template <int P>
 __global__ __launch_bounds__(64) void k_l2p_stokes(
-    int M, int nbox, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const double2 *__restrict__ center,
-    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
+    const int *__restrict__ leaf_box, const int *__restrict__ parent,
+    const double2 *__restrict__ center, const double2 *__restrict__ xs,
+    const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double2 *__restrict__ Lexp, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int box = leaf_box[leaf];
-  const double2 c = center[box];
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   if (j >= leaf_start[leaf + 1]) return;
   const double2 z = xs[j], nv = nrm[j];
-  const double2 w = make_double2((z.x - c.x) * ih_leaf, (z.y - c.y) * ih_leaf);
-  double2 A, dA, C, dC;
-  eval_local<P>(Lexp + ((size_t)(3 * r) * nbox + box) * P, w, ih_leaf, A, dA);
-  const double2 B = eval_value<P>(Lexp + ((size_t)(3 * r + 1) * nbox + box) * P, w);
-  eval_local<P>(Lexp + ((size_t)(3 * r + 2) * nbox + box) * P, w, ih_leaf, C, dC);
+  double2 A = make_double2(0.0, 0.0), dA = A, B = A, C = A, dC = A;
+  int b = leaf_box[leaf];
+  double ih = ih_leaf;
+  for (int l = L; l >= 2; --l) {  // ancestors, as in the Laplace evaluation
+    const double2 c = center[b];
+    const double2 w = make_double2((z.x - c.x) * ih, (z.y - c.y) * ih);
+    double2 Al, dAl, Cl, dCl;
+    eval_local<P>(Lexp + ((size_t)(3 * r) * nbox + b) * P, w, ih, Al, dAl);
+    const double2 Bl = eval_value<P>(Lexp + ((size_t)(3 * r + 1) * nbox + b) * P, w);
+    eval_local<P>(Lexp + ((size_t)(3 * r + 2) * nbox + b) * P, w, ih, Cl, dCl);
+    A = make_double2(A.x + Al.x, A.y + Al.y);
+    dA = make_double2(dA.x + dAl.x, dA.y + dAl.y);
+    B = make_double2(B.x + Bl.x, B.y + Bl.y);
+    C = make_double2(C.x + Cl.x, C.y + Cl.y);
+    dC = make_double2(dC.x + dCl.x, dC.y + dCl.y);
+    b = parent[b] >> 2;
+    ih *= 0.5;
+  }
   const double2 zA = cmul(make_double2(z.x, -z.y), dA);
   const double2 u = make_double2(dC.x - zA.x, -(dC.y - zA.y));  // conj(C' - conj(z) A')
   const double2 nc = make_double2(nv.x, -nv.y);
@@ -895,9 +882,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       }
     near_ptr.push_back((int)near_leaf.size());
   }
-  // translation operators. M2L: Hankel vectors V_d[k] = k!/d^(k+1), k < 2p, for the 40 offsets
-  // (compact index). M2M on u-form multipoles: u0_n = sum_{m<=n} 2^-m delta^(n-m)/(n-m)! u1_m.
-  // L2L on locals: b1_n = sum_{m>=n} C(m,n) 2^-n delta^(m-n) b0_m. Both stored as [pos][m][n].
+  // translation operators: the 40 M2L offsets (compact index) and, below, the M2L and M2M
+  // tables
   std::vector<int> ocompact(49, -1);
   int nc = 0;
   for (int dx = -3; dx <= 3; ++dx)
@@ -1126,14 +1112,18 @@ int launch_m2l_f32(const FmmTree &t, int nsets, const float2 *Mexp, float2 *Lexp
   return BIE_OK;
 }
 
-// Upward pass, M2L, downward pass, then (after the near field's join) L2P into `partial`, with
-// expansions in T. float is used for the mixed-precision Laplace apply only.
-template <int P, class T>
+// Upward pass (P2M, M2M), M2L, then (after the near field's join) the evaluation of every
+// ancestor's local expansion at the targets into `partial`, with expansions in T. float is used for the mixed-precision Laplace apply only.
+template <int P, class T, class Near>
 int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
-                     const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s) {
+                     const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
+                     Near &&launch_near) {
   const int M = t.M;
   hipLaunchKernelGGL((k_p2m<P, T>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
                      t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
+  // the near field is submitted after P2M (it depends only on the gather): P2M, which heads the
+  // chain of expansion passes, reaches the compute units first
+  BIE_TRY(launch_near());
   for (int l = t.L - 1; l >= 2; --l) {
     const int nb = t.level_off[l + 1] - t.level_off[l];
     if (nb > 0)
@@ -1147,23 +1137,16 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
     else
       BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
   }
-  for (int l = 2; l < t.L; ++l) {
-    const int nb = t.level_off[l + 2] - t.level_off[l + 1];
-    if (nb > 0)
-      hipLaunchKernelGGL((k_l2l<P, T>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
-                         0, s, nb, t.level_off[l + 1], t.nbox, nsets, t.parent, t.T_tau,
-                         t.fact_in, Lexp);
-  }
   BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
   if (kind == 0) {
-    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
-                       ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
+    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox, t.L,
+                       ih_leaf, t.leaf_start, t.leaf_box, t.parent, t.center, t.xs, t.nrm, t.perm,
                        t.chunk_leaf, t.chunk_start, Lexp, partial);
   } else {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox,
-                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, t.nrm, t.perm,
-                         t.chunk_leaf, t.chunk_start, Lexp, partial);
+      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox, t.L,
+                         ih_leaf, t.leaf_start, t.leaf_box, t.parent, t.center, t.xs, t.nrm,
+                         t.perm, t.chunk_leaf, t.chunk_start, Lexp, partial);
   }
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
@@ -1234,23 +1217,26 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
   hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64,
                      f32 ? nullptr : reinterpret_cast<double2 *>(wq),
                      f32 ? reinterpret_cast<float2 *>(wq) : nullptr, S4);
-  // the near field needs only the charges: it runs on the side stream while the expansions are
-  // built, and writes `partial`; the L2P kernels add the far part after the join
+  // the near field needs only the source records: it runs on the side stream while the
+  // expansions are built, and writes `partial`; the L2P kernels add the far part after the join
   BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
-  BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
-  {
-    ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
-    if (kind == 0)
-      hipLaunchKernelGGL(k_near_laplace, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
-                         t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
-                         t.chunk_start, S4, partial);
-    else
-      hipLaunchKernelGGL(k_near_stokes, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
-                         t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
-                         t.chunk_start, S4, partial);
-    BIE_HIP_CHECK(hipGetLastError());
-  }
-  BIE_HIP_CHECK(hipEventRecord(plan.join, plan.side));
+  auto launch_near = [&]() -> int {
+    BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
+    {
+      ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
+      if (kind == 0)
+        hipLaunchKernelGGL(k_near_laplace, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+                           t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                           t.chunk_start, S4, partial);
+      else
+        hipLaunchKernelGGL(k_near_stokes, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+                           t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                           t.chunk_start, S4, partial);
+      BIE_HIP_CHECK(hipGetLastError());
+    }
+    BIE_HIP_CHECK(hipEventRecord(plan.join, plan.side));
+    return BIE_OK;
+  };
   const double ih_leaf = (double)(1 << t.L) / t.size;
   BIE_TRY(with_order(p, [&](auto order) -> int {
     constexpr int P = decltype(order)::value;
@@ -1258,11 +1244,11 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
       return expansion_passes<P, float>(t, plan, kind, R, nsets, ih_leaf,
                                         reinterpret_cast<const float2 *>(wq),
                                         reinterpret_cast<float2 *>(wm),
-                                        reinterpret_cast<float2 *>(wl), partial, s);
+                                        reinterpret_cast<float2 *>(wl), partial, s, launch_near);
     return expansion_passes<P, double>(t, plan, kind, R, nsets, ih_leaf,
                                        reinterpret_cast<const double2 *>(wq),
                                        reinterpret_cast<double2 *>(wm),
-                                       reinterpret_cast<double2 *>(wl), partial, s);
+                                       reinterpret_cast<double2 *>(wl), partial, s, launch_near);
   }));
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
