@@ -40,6 +40,7 @@ struct FmmTree {
   std::vector<int> level_off;  // [L+2]
   // device
   DevBuf buf;
+  int *leaf_anc = nullptr;  // per leaf its boxes at levels L, L - 1, ..., 2 [nleaf][L - 1]
   int *perm = nullptr, *leaf_start = nullptr, *leaf_box = nullptr, *child = nullptr,
       *parent = nullptr, *run_ptr = nullptr, *chunk_leaf = nullptr,
       *chunk_start = nullptr;
@@ -604,30 +605,46 @@ __global__ __launch_bounds__(64) void k_near_laplace(
 // re-expanding a polynomial about another centre is exact (L2L has no truncation). So each target
 // evaluates the M2L part of every ancestor directly at its own scaled coordinate
 // w_A = (z - c_A)/h_A and sums the values (levels in decreasing order), which replaces the
-// level-by-level L2L passes. The ancestors are wave-uniform (one leaf per wave), so their
-// coefficients come in by scalar loads.
-// L2P, Laplace: adds -(1/2pi) Re(nu F(z)).
+// level-by-level L2L passes. One wave per chunk of a leaf: the ancestors (a table per leaf) are
+// the same for the whole wave, so the wave first copies their coefficients into LDS with
+// coalesced vector loads (one wait), and the Horner steps then read them by LDS broadcast.
+// Copies the coefficient sets `sets` (nsets_here of them) of the nlev ancestors into cf:
+// cf[(k * nlev + i) * P + n] = Lexp[set k][anc[i]][n].
+template <int P, class T>
+__device__ __forceinline__ void stage_ancestors(const int *anc, int nlev, int nbox, int set0,
+                                                int nsets_here, const cx<T> *__restrict__ Lexp,
+                                                cx<T> *cf) {
+  const int total = nsets_here * nlev * P;
+  for (int e = threadIdx.x; e < total; e += 64) {
+    const int n = e % P, ki = e / P, i = ki % nlev, k = ki / nlev;
+    cf[e] = Lexp[((size_t)(set0 + k) * nbox + anc[i]) * P + n];
+  }
+  __syncthreads();
+}
+
+// L2P, Laplace: adds -(1/2pi) Re(nu F(z)). Dynamic LDS: (L - 1) P coefficients.
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_l2p_laplace(
     int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const int *__restrict__ parent,
-    const double2 *__restrict__ center, const double2 *__restrict__ xs,
-    const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ leaf_anc, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
+  extern __shared__ char l2p_lds[];
+  cx<T> *cf = reinterpret_cast<cx<T> *>(l2p_lds);
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  const int nlev = L - 1;
+  const int *anc = leaf_anc + (size_t)leaf * nlev;  // levels L, L - 1, ..., 2
+  stage_ancestors<P, T>(anc, nlev, nbox, r, 1, Lexp, cf);
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   if (j >= leaf_start[leaf + 1]) return;
   const double2 z = xs[j], nv = nrm[j];
   cx<T> F = mkc<T>(0, 0);
-  int b = leaf_box[leaf];
   double ih = ih_leaf;
-  for (int l = L; l >= 2; --l) {
-    const double2 c = center[b];
-    const cx<T> Fl = eval_value<P>(Lexp + ((size_t)r * nbox + b) * P,
-                                   mkc<T>((T)((z.x - c.x) * ih), (T)((z.y - c.y) * ih)));
+  for (int i = 0; i < nlev; ++i) {
+    const double2 c = center[anc[i]];
+    const cx<T> Fl = eval_value<P>(cf + i * P, mkc<T>((T)((z.x - c.x) * ih), (T)((z.y - c.y) * ih)));
     F = mkc<T>(F.x + Fl.x, F.y + Fl.y);
-    b = parent[b] >> 2;
     ih *= 0.5;
   }
   double *o = out + (size_t)r * M + perm[j];
@@ -669,31 +686,33 @@ __global__ __launch_bounds__(64) void k_near_stokes(
 template <int P>
 __global__ __launch_bounds__(64) void k_l2p_stokes(
     int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
-    const int *__restrict__ leaf_box, const int *__restrict__ parent,
-    const double2 *__restrict__ center, const double2 *__restrict__ xs,
-    const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ leaf_anc, const double2 *__restrict__ center,
+    const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double2 *__restrict__ Lexp, double *__restrict__ out) {
+  extern __shared__ char l2p_lds[];
+  double2 *cf = reinterpret_cast<double2 *>(l2p_lds);  // sets A, B, C of every ancestor
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  const int nlev = L - 1;
+  const int *anc = leaf_anc + (size_t)leaf * nlev;
+  stage_ancestors<P, double>(anc, nlev, nbox, 3 * r, 3, Lexp, cf);
   const int j = chunk_start[blockIdx.x] + threadIdx.x;
   if (j >= leaf_start[leaf + 1]) return;
   const double2 z = xs[j], nv = nrm[j];
   double2 A = make_double2(0.0, 0.0), dA = A, B = A, C = A, dC = A;
-  int b = leaf_box[leaf];
   double ih = ih_leaf;
-  for (int l = L; l >= 2; --l) {  // ancestors, as in the Laplace evaluation
-    const double2 c = center[b];
+  for (int i = 0; i < nlev; ++i) {  // ancestors, as in the Laplace evaluation
+    const double2 c = center[anc[i]];
     const double2 w = make_double2((z.x - c.x) * ih, (z.y - c.y) * ih);
     double2 Al, dAl, Cl, dCl;
-    eval_local<P>(Lexp + ((size_t)(3 * r) * nbox + b) * P, w, ih, Al, dAl);
-    const double2 Bl = eval_value<P>(Lexp + ((size_t)(3 * r + 1) * nbox + b) * P, w);
-    eval_local<P>(Lexp + ((size_t)(3 * r + 2) * nbox + b) * P, w, ih, Cl, dCl);
+    eval_local<P>(cf + (size_t)(0 * nlev + i) * P, w, ih, Al, dAl);
+    const double2 Bl = eval_value<P>(cf + (size_t)(1 * nlev + i) * P, w);
+    eval_local<P>(cf + (size_t)(2 * nlev + i) * P, w, ih, Cl, dCl);
     A = make_double2(A.x + Al.x, A.y + Al.y);
     dA = make_double2(dA.x + dAl.x, dA.y + dAl.y);
     B = make_double2(B.x + Bl.x, B.y + Bl.y);
     C = make_double2(C.x + Cl.x, C.y + Cl.y);
     dC = make_double2(dC.x + dCl.x, dC.y + dCl.y);
-    b = parent[b] >> 2;
     ih *= 0.5;
   }
   const double2 zA = cmul(make_double2(z.x, -z.y), dA);
@@ -858,12 +877,13 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     }
   }
   t.m2l_entries = (long long)m2l_src.size();
-  std::vector<int> near_ptr(1, 0), near_leaf, leaf_box(t.nleaf);
+  std::vector<int> near_ptr(1, 0), near_leaf, leaf_box(t.nleaf), leaf_anc((size_t)t.nleaf * (L - 1));
   std::vector<int> chunk_leaf, chunk_start;
   for (int b = 0; b < t.nleaf; ++b) {
     const long long kk = keys[L][b];
     const int ix = (int)decode((unsigned)kk), iy = (int)decode((unsigned)(kk >> 1));
     leaf_box[b] = t.level_off[L] + b;
+    for (int i = 0, a = leaf_box[b]; i < L - 1; ++i, a = parent[a] >> 2) leaf_anc[(size_t)b * (L - 1) + i] = a;
     for (int j = leaf_start[b]; j < leaf_start[b + 1]; j += 64) {
       chunk_leaf.push_back(b);
       chunk_start.push_back(j);
@@ -1011,7 +1031,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   const size_t nitem = std::max<size_t>(item_off.size(), 1), nnear = std::max<size_t>(run_kk.size(), 2);
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
                       grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + run_ptr.size() +
-                      nnear + 2 * chunk_leaf.size();
+                      nnear + 2 * chunk_leaf.size() + leaf_anc.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p + Tdpow.size();
   const size_t bytes = d2 * 16 + (L + 1 + 4 * p) * 8 + ints * 4 + 34 * 256;
   BIE_TRY(t.buf.reserve(bytes));
@@ -1034,6 +1054,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.perm = (int *)take(M * 4);
   t.leaf_start = (int *)take((t.nleaf + 1) * 4);
   t.leaf_box = (int *)take(t.nleaf * 4);
+  t.leaf_anc = (int *)take(leaf_anc.size() * 4);
   t.child = (int *)take(4 * (size_t)t.nbox * 4);
   t.parent = (int *)take(t.nbox * 4);
   t.grp_ptr = (int *)take(grp_ptr.size() * 4);
@@ -1068,6 +1089,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.perm, perm_i.data(), M * 4));
   BIE_TRY(up(t.leaf_start, leaf_start.data(), leaf_start.size() * 4));
   BIE_TRY(up(t.leaf_box, leaf_box.data(), t.nleaf * 4));
+  BIE_TRY(up(t.leaf_anc, leaf_anc.data(), leaf_anc.size() * 4));
   BIE_TRY(up(t.child, child.data(), child.size() * 4));
   BIE_TRY(up(t.parent, parent.data(), t.nbox * 4));
   BIE_TRY(up(t.grp_ptr, grp_ptr.data(), grp_ptr.size() * 4));
@@ -1139,14 +1161,16 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   }
   BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
   if (kind == 0) {
-    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox, t.L,
-                       ih_leaf, t.leaf_start, t.leaf_box, t.parent, t.center, t.xs, t.nrm, t.perm,
-                       t.chunk_leaf, t.chunk_start, Lexp, partial);
+    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64),
+                       (size_t)(t.L - 1) * P * sizeof(cx<T>), s, M, t.nbox, t.L, ih_leaf,
+                       t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.chunk_leaf,
+                       t.chunk_start, Lexp, partial);
   } else {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64), 0, s, M, t.nbox, t.L,
-                         ih_leaf, t.leaf_start, t.leaf_box, t.parent, t.center, t.xs, t.nrm,
-                         t.perm, t.chunk_leaf, t.chunk_start, Lexp, partial);
+      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64),
+                         (size_t)3 * (t.L - 1) * P * sizeof(double2), s, M, t.nbox, t.L, ih_leaf,
+                         t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.chunk_leaf,
+                         t.chunk_start, Lexp, partial);
   }
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
