@@ -81,6 +81,60 @@ __global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__r
   }
 }
 
+// The second Gram-Schmidt update fused with the norm of its result: as k_combination, and each
+// workgroup (chunk c, part sub) writes the sum of squares of the entries it wrote to
+// partial[c * kSub + sub].
+__global__ __launch_bounds__(kBlock) void k_combination_nrm(
+    int nvec, const int *__restrict__ csys, const long long *__restrict__ c0,
+    const long long *__restrict__ c1, const double *__restrict__ V, long long vstride,
+    const double *__restrict__ h, long long hs, double *__restrict__ w, double sign,
+    double *__restrict__ partial) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  const int s = csys[c];
+  const double *hr = h + s * hs;
+  double sq = 0.0;
+  for (long long i = c0[c] + blockIdx.y * kBlock + threadIdx.x; i < c1[c]; i += kSub * kBlock) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = 0;
+    for (; l + 4 <= nvec; l += 4) {
+      a0 = fma(V[l * vstride + i], hr[l], a0);
+      a1 = fma(V[(l + 1) * vstride + i], hr[l + 1], a1);
+      a2 = fma(V[(l + 2) * vstride + i], hr[l + 2], a2);
+      a3 = fma(V[(l + 3) * vstride + i], hr[l + 3], a3);
+    }
+    if (l < nvec) a0 = fma(V[l * vstride + i], hr[l], a0);
+    if (l + 1 < nvec) a1 = fma(V[(l + 1) * vstride + i], hr[l + 1], a1);
+    if (l + 2 < nvec) a2 = fma(V[(l + 2) * vstride + i], hr[l + 2], a2);
+    const double v = w[i] + sign * ((a0 + a1) + (a2 + a3));
+    w[i] = v;
+    sq = fma(v, v, sq);
+  }
+  const double t = block_sum(sq, sh);
+  if (threadIdx.x == 0) partial[(long long)c * kSub + blockIdx.y] = t;
+}
+
+// Per system s (one workgroup): nrm[s] = sqrt of the sum of its chunks' partials (in order); the
+// Hessenberg column h2[s][0..cnt-1] += h1[s][...] and h2[s][cnt] = nrm[s].
+__global__ __launch_bounds__(64) void k_nrm_column(int cnt, const int *__restrict__ sys_chunk,
+                                                  const double *__restrict__ partial,
+                                                  const double *__restrict__ h1,
+                                                  double *__restrict__ h2, long long hs,
+                                                  double *__restrict__ nrm) {
+  const int s = blockIdx.x;
+  const int a = sys_chunk[s] * kSub, b = sys_chunk[s + 1] * kSub;
+  double acc = 0.0;
+  for (int e = a + threadIdx.x; e < b; e += 64) acc += partial[e];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  for (int l = threadIdx.x; l < cnt; l += 64) h2[s * hs + l] += h1[s * hs + l];
+  if (threadIdx.x == 0) {
+    const double n = sqrt(acc);
+    nrm[s] = n;
+    h2[s * hs + cnt] = n;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_scale_to(const int *__restrict__ csys,
                                                     const long long *__restrict__ c0,
                                                     const long long *__restrict__ c1,
@@ -130,6 +184,18 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
                      w, scratch);
   hipLaunchKernelGGL(k_dots_stage2, dim3(1, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk, scratch, out,
                      1LL, 1);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
+                           const double *h1, double *h2, long long hs, double *w, double *nrm,
+                           double *scratch, hipStream_t s) {
+  if (nvec <= 0) return BIE_OK;
+  hipLaunchKernelGGL(k_combination_nrm, dim3(sg.C, kSub), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0,
+                     sg.c1, V, vstride, h2, hs, w, -1.0, scratch);
+  hipLaunchKernelGGL(k_nrm_column, dim3(sg.S), dim3(64), 0, s, nvec, sg.sys_chunk, scratch, h1, h2,
+                     hs, nrm);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

@@ -64,7 +64,7 @@ int write_dev(SolverMem &mem, double *dev, const std::vector<double> &src, hipSt
 struct Work {
   double *V, *w, *r;          // V [(m+1)][Ntot]; w, r [Ntot]
   double *h1, *h2, *nrm, *y;  // [S][m+2] x3, [S]
-  double *scratch;            // dot partials [(m+2)][C]
+  double *scratch;            // dot partials [max(m+2, 4)][C]
 };
 
 int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
@@ -83,7 +83,9 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
     p += N;
   }
   const size_t hs = (size_t)m + 2;
-  BIE_TRY(ss.mem->small.reserve((3 * hs * S + S + hs * (size_t)ss.seg->C) * sizeof(double) + 64));
+  // scratch: dot partials [(m+2)][C], or four per chunk for the fused update and norm
+  const size_t np = std::max<size_t>(hs, 4) * (size_t)ss.seg->C;
+  BIE_TRY(ss.mem->small.reserve((3 * hs * S + S + np) * sizeof(double) + 64));
   double *q = ss.mem->small.as<double>();
   wk.h1 = q;
   q += hs * S;
@@ -165,14 +167,12 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
       BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h2, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_nrm2(sg, wk.w, wk.nrm, wk.scratch, s));
+      // second update fused with ||w||; the column h1 + h2 with ||w|| as entry j + 1
+      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm,
+                                     wk.scratch, s));
       BIE_TRY(seg_scale_to(sg, wk.w, wk.nrm, Vj1, s));
-      BIE_TRY(seg_add_h(S, wk.h1, wk.h2, j + 1, hs, s));
       double *dst = mem.pinned + (j & 1) * slot;
       BIE_HIP_CHECK(hipMemcpyAsync(dst, wk.h2, (size_t)S * hs * sizeof(double),
-                                   hipMemcpyDeviceToHost, s));
-      BIE_HIP_CHECK(hipMemcpyAsync(dst + (size_t)S * hs, wk.nrm, S * sizeof(double),
                                    hipMemcpyDeviceToHost, s));
       BIE_HIP_CHECK(hipEventRecord(mem.ev[j & 1], s));
       return BIE_OK;
@@ -182,14 +182,14 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       st.iters += 1;
       if (j + 1 < m && st.iters < max_iter) BIE_TRY(step(j + 1));
       BIE_HIP_CHECK(hipEventSynchronize(mem.ev[j & 1]));
-      const double *hh2 = mem.pinned + (j & 1) * slot, *hn = hh2 + (size_t)S * hs;
+      const double *hh2 = mem.pinned + (j & 1) * slot;
       bool all_done = true;
       for (int r = 0; r < S; ++r) {
         if (!active[r] || jdone[r] >= 0) continue;
         double *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
         double *col = Hc + (size_t)j * (m + 1);
-        for (int i = 0; i <= j; ++i) col[i] = hh2[(size_t)r * hs + i];
-        col[j + 1] = hn[r];
+        for (int i = 0; i <= j + 1; ++i) col[i] = hh2[(size_t)r * hs + i];
+        const double hn = col[j + 1];
         double *c = &cs[(size_t)r * m], *sv = &sn[(size_t)r * m], *gg = &gv[(size_t)r * (m + 1)];
         for (int i = 0; i < j; ++i) {
           const double a = col[i], b = col[i + 1];
@@ -206,8 +206,8 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
         gg[j] = c[j] * gg[j];
         const double res = std::fabs(gg[j + 1]) / fnorm[r];
         if (verbosity() >= 2 && r == 0)
-          std::fprintf(stderr, "[bie]   j=%d est rel res=%.3e hn=%.3e\n", j, res, hn[r]);
-        if (res <= tol[r] || hn[r] == 0.0) jdone[r] = j;
+          std::fprintf(stderr, "[bie]   j=%d est rel res=%.3e hn=%.3e\n", j, res, hn);
+        if (res <= tol[r] || hn == 0.0) jdone[r] = j;
         else all_done = false;
       }
       jend = j;
