@@ -124,27 +124,34 @@ __device__ inline double rcp64(double a) {
   return fma(y, e, y);
 }
 
-// Charges in sorted order: Laplace set r is (s, 0) (in float when Qf is given); Stokes sets 3r,
+// Source strengths s = w mu (written to s64 in node order, as the epilogue reads them) and, in
+// sorted order, the charges: Laplace set r is (s, 0) (in float when Qf is given); Stokes sets 3r,
 // 3r+1, 3r+2 are rho, conj(rho), rho conj(z). Also the near-field source records
 // S4[r][j] = (x, y, s, 0), resp. (x, y, rho), always in float64.
 __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
-                         const double2 *__restrict__ xs, const double *__restrict__ s64,
+                         const double2 *__restrict__ xs, const double *__restrict__ wq,
+                         const double *__restrict__ mu, double *__restrict__ s64,
                          double2 *__restrict__ Q, float2 *__restrict__ Qf,
                          double4 *__restrict__ S4) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const int k = perm[j];
   const double2 z = xs[j];
+  const double wk = wq[k];
   for (int r = 0; r < R; ++r) {
     if (kind == 0) {
-      const double v = s64[(size_t)r * M + k];
+      const double v = wk * mu[(size_t)r * M + k];
+      s64[(size_t)r * M + k] = v;
       if (Qf)
         Qf[(size_t)r * M + j] = make_float2((float)v, 0.0f);
       else
         Q[(size_t)r * M + j] = make_double2(v, 0.0);
       S4[(size_t)r * M + j] = make_double4(z.x, z.y, v, 0.0);
     } else {
-      const double2 rho = make_double2(s64[(size_t)r * 2 * M + 2 * k], s64[(size_t)r * 2 * M + 2 * k + 1]);
+      const double2 rho = make_double2(wk * mu[(size_t)r * 2 * M + 2 * k],
+                                       wk * mu[(size_t)r * 2 * M + 2 * k + 1]);
+      s64[(size_t)r * 2 * M + 2 * k] = rho.x;
+      s64[(size_t)r * 2 * M + 2 * k + 1] = rho.y;
       Q[(size_t)(3 * r) * M + j] = rho;
       Q[(size_t)(3 * r + 1) * M + j] = make_double2(rho.x, -rho.y);
       Q[(size_t)(3 * r + 2) * M + j] = cmul(rho, make_double2(z.x, -z.y));
@@ -1199,7 +1206,8 @@ int with_order(int p, F &&f) {
 int fmm_current_order() { return 0; }
 
 // Far field of all pairs k != i (sets: Laplace R, Stokes 3R) into partial [R][len] (nsplit 1).
-int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64, double *partial,
+int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu, double *s64,
+                  double *partial,
                   hipStream_t s, int order, int leaf) {
   int p = order > 0 ? order : 40;
   if (precision == BIE_MIXED) p = std::max(8, (p * 11 + 19) / 20);  // about sqrt of the accuracy
@@ -1238,7 +1246,8 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *s64
     BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, hipEventDisableTiming));
   }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
-  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, s64,
+  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, g->w,
+                     mu, s64,
                      f32 ? nullptr : reinterpret_cast<double2 *>(wq),
                      f32 ? reinterpret_cast<float2 *>(wq) : nullptr, S4);
   // the near field needs only the source records: it runs on the side stream while the

@@ -159,7 +159,8 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
                 const std::vector<double> &tol, int m, int &iters, int &applies, hipStream_t s);
 
 // ---- fmm.hip ------------------------------------------------------------------------------
-int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *s64,
+// mu [nrhs][len] in; s64 [nrhs][len] out (the strengths w mu, for the epilogue)
+int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *mu, double *s64,
                   double *partial, hipStream_t s, int order, int leaf);
 void fmm_destroy(FmmPlan *p);
 int fmm_current_order();

@@ -769,15 +769,17 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
   double *partial = reinterpret_cast<double *>(
       (reinterpret_cast<uintptr_t>(s32 + (size_t)nrhs * len) + 63) & ~uintptr_t(63));
   const long long tot = (long long)nrhs * len;
-  hipLaunchKernelGGL(k_pack, dim3(nblocks(tot)), dim3(kBlock), 0, st, tot, g->M, comps, g->w, mu,
-                     s64, precision == BIE_MIXED ? s32 : nullptr);
-  BIE_HIP_CHECK(hipGetLastError());
+  if (method != BIE_FMM) {  // the FMM gather forms the strengths itself
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(tot)), dim3(kBlock), 0, st, tot, g->M, comps, g->w, mu,
+                       s64, precision == BIE_MIXED ? s32 : nullptr);
+    BIE_HIP_CHECK(hipGetLastError());
+  }
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     const int R = left >= maxR ? maxR : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
     const size_t off = (size_t)r0 * len;
     if (method == BIE_FMM) {
-      BIE_TRY(fmm_far_field(g, kind, precision, R, s64 + off, partial, st, g->fmm_order,
+      BIE_TRY(fmm_far_field(g, kind, precision, R, mu + off, s64 + off, partial, st, g->fmm_order,
                             g->fmm_leaf));
     } else {
       switch (R) {
