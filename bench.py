@@ -490,6 +490,14 @@ def main():
     rl = roofline(bie2d.bie_profile_read(c[0]), c[0], c[1], c[2], bound=c[3], kernel=c[4])
     rl["kernel"] = c[4]
     bie2d.bie_profile_enable(False)
+    # the matrix-core kernel (M2L) on its own, from one more solve that times only that class
+    cm = classes["k_m2l"]
+    bie2d.bie_profile_select([cm[0]])
+    bie2d.bie_profile_enable(True)
+    bie2d.bie_elastance_solve(g, q_d, opts)
+    rl_m2l = roofline(bie2d.bie_profile_read(cm[0]), cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
+    rl_m2l["kernel"] = cm[4]
+    bie2d.bie_profile_enable(False)
     bie2d.bie_profile_select(None)
 
     # the direct float32 far-field sweep on the same workload (survey row a3), 5 applies
@@ -541,6 +549,7 @@ def main():
                                        "rel_residual")},
         "accuracy": acc,
         "roofline": rl,
+        "roofline_m2l": rl_m2l,
         "roofline_direct_p2p": rl_direct,
         "kernel_ms_per_solve_untimed": {k: v["ms_total"] for k, v in profs.items()},
         "fmm_ms_per_apply": fmm_total["ms_total"] / max(fmm_total["launches"], 1),
