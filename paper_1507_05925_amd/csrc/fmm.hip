@@ -533,10 +533,9 @@ __device__ inline V eval_value(const V *b, V w) {
 }
 
 // Near field. The neighbour leaves of a leaf (itself included) form a few runs of consecutive
-// sorted nodes. Source records (x, y, s, 0) or (x, y, rho) are wave-uniform and are read eight
-// per step with the scalar loads issued together; a run's tail is one step more over clamped
-// indices with zero strength. SELF: the run holds the target's own leaf, and the pair of a target
-// with itself is masked without a branch.
+// sorted nodes, whose source records (x, y, s, 0) or (x, y, rho) are the same for the whole wave.
+// SELF: the run holds the target's own leaf, and the pair of a target with itself is masked
+// without a branch.
 template <bool STOKES, bool SELF, bool TAIL>
 __device__ __forceinline__ void near_step(const double4 *rec, int k, int k1, int self, double2 z,
                                           double2 nv, double &gx, double &gy) {
@@ -562,22 +561,34 @@ __device__ __forceinline__ void near_step(const double4 *rec, int k, int k1, int
   }
 }
 
+// A run is read in blocks of kNearBuf records: the wave copies a block into LDS with coalesced
+// vector loads (one wait per block) and then reads the records by LDS broadcast, eight per step
+// (LDS reads complete in order, so they overlap with the arithmetic; scalar loads, which complete
+// out of order, cannot). A block's tail is one step more over repeated indices with zero weight.
+constexpr int kNearBuf = 128;
+
 template <bool STOKES, bool SELF>
 __device__ __forceinline__ void near_run(int k0, int k1, int self, double2 z, double2 nv,
-                                         const double4 *__restrict__ S4, double &gx, double &gy) {
-  int k = k0;
-  for (; k + 8 <= k1; k += 8) {
-    const double4 *p = S4 + k;  // eight consecutive records: the loads merge
-    double4 rec[8];
+                                         const double4 *__restrict__ S4, double4 *buf,
+                                         double &gx, double &gy) {
+  for (int base = k0; base < k1; base += kNearBuf) {
+    const int n = min(kNearBuf, k1 - base);
+    __syncthreads();  // the previous block is no longer read
+    for (int t = threadIdx.x; t < n; t += 64) buf[t] = S4[base + t];
+    __syncthreads();
+    int k = 0;
+    for (; k + 8 <= n; k += 8) {
+      double4 rec[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) rec[u] = p[u];
-    near_step<STOKES, SELF, false>(rec, k, k1, self, z, nv, gx, gy);
-  }
-  if (k < k1) {
-    double4 rec[8];
+      for (int u = 0; u < 8; ++u) rec[u] = buf[k + u];
+      near_step<STOKES, SELF, false>(rec, base + k, base + n, self, z, nv, gx, gy);
+    }
+    if (k < n) {
+      double4 rec[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) rec[u] = S4[min(k + u, k1 - 1)];
-    near_step<STOKES, SELF, true>(rec, k, k1, self, z, nv, gx, gy);
+      for (int u = 0; u < 8; ++u) rec[u] = buf[min(k + u, n - 1)];
+      near_step<STOKES, SELF, true>(rec, base + k, base + n, self, z, nv, gx, gy);
+    }
   }
 }
 
@@ -596,13 +607,14 @@ __global__ __launch_bounds__(64) void k_near_laplace(
   const int jj = valid ? j : j0;
   const double2 z = xs[jj], nv = nrm[jj];
   const double4 *src = S4 + (size_t)r * M;
+  __shared__ double4 buf[kNearBuf];
   double gx = 0.0, gy = 0.0;
   for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
     const int2 kr = run[e];
     if (kr.x <= j0 && j1 <= kr.y)
-      near_run<false, true>(kr.x, kr.y, jj, z, nv, src, gx, gy);
+      near_run<false, true>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
     else
-      near_run<false, false>(kr.x, kr.y, jj, z, nv, src, gx, gy);
+      near_run<false, false>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
   }
   if (valid) out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
 }
@@ -673,13 +685,14 @@ __global__ __launch_bounds__(64) void k_near_stokes(
   const int jj = valid ? j : j0;
   const double2 z = xs[jj], nv = nrm[jj];
   const double4 *src = S4 + (size_t)r * M;
+  __shared__ double4 buf[kNearBuf];
   double gx = 0.0, gy = 0.0;
   for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
     const int2 kr = run[e];
     if (kr.x <= j0 && j1 <= kr.y)
-      near_run<true, true>(kr.x, kr.y, jj, z, nv, src, gx, gy);
+      near_run<true, true>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
     else
-      near_run<true, false>(kr.x, kr.y, jj, z, nv, src, gx, gy);
+      near_run<true, false>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
   }
   if (valid) {
     const int i = perm[j];
