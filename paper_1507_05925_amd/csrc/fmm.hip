@@ -247,26 +247,26 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
 // lane-dependent offset without a bound test. It sits in LDS; the source coefficient of step m
 // is read from lane m (readlane, wave-uniform).
 
-// M2M for one level: waves walk (parent box, set) items with a grid stride.
+// M2M for one level: one workgroup per (parent box, set) with a grid stride; wave c translates
+// the child at position c, and the four contributions are added through LDS in position order.
 template <int P, class T>
 __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nsets,
                                             const int *__restrict__ child,
                                             const double2 *__restrict__ tau, cx<T> *Mexp) {
   __shared__ cx<T> tp[8 * P];
+  __shared__ cx<T> part[4 * 64];
   for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = mkc<T>((T)tau[i].x, (T)tau[i].y);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int n = lane < P ? lane : P - 1;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cpos = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long total = (long long)nb * nsets;
-  for (long long item = (long long)blockIdx.x * 4 + wave; item < total;
-       item += (long long)gridDim.x * 4) {
+  for (long long item = blockIdx.x; item < total; item += gridDim.x) {
     const int set = (int)(item / nb);
     const int b = off + (int)(item % nb);
     cx<T> a0 = mkc<T>(0, 0), a1 = a0;
-    for (int cpos = 0; cpos < 4; ++cpos) {
-      const int ch = child[4 * b + cpos];
-      if (ch < 0) continue;
+    const int ch = child[4 * b + cpos];
+    if (ch >= 0) {
       const cx<T> u = Mexp[((size_t)set * nbox + ch) * P + n];
       const cx<T> v = mkc<T>(ldexp(u.x, -n), ldexp(u.y, -n));
       const cx<T> *tc = tp + cpos * 2 * P + P + n;  // tc[-m] = tau[n - m], zero for m > n
@@ -276,7 +276,14 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
         a1 = cfma(mkc<T>(rl(v.x, m + 1), rl(v.y, m + 1)), tc[-m - 1], a1);
       }
     }
-    if (lane < P) Mexp[((size_t)set * nbox + b) * P + n] = mkc<T>(a0.x + a1.x, a0.y + a1.y);
+    part[cpos * 64 + lane] = mkc<T>(a0.x + a1.x, a0.y + a1.y);
+    __syncthreads();
+    if (cpos == 0 && lane < P) {
+      const cx<T> r0 = part[lane], r1 = part[64 + lane], r2 = part[128 + lane], r3 = part[192 + lane];
+      Mexp[((size_t)set * nbox + b) * P + n] =
+          mkc<T>((r0.x + r1.x) + (r2.x + r3.x), (r0.y + r1.y) + (r2.y + r3.y));
+    }
+    __syncthreads();
   }
 }
 
@@ -1139,8 +1146,6 @@ int launch_m2l(const FmmTree &t, int ga, int gb, int nsets, const double2 *Mexp,
   return BIE_OK;
 }
 
-// Grid for the grid-stride translation kernels (four waves per workgroup).
-int translation_blocks(long long items) { return (int)std::min<long long>((items + 3) / 4, 2048); }
 
 template <int P>
 int launch_m2l_f32(const FmmTree &t, int nsets, const float2 *Mexp, float2 *Lexp, hipStream_t s) {
@@ -1169,8 +1174,8 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   for (int l = t.L - 1; l >= 2; --l) {
     const int nb = t.level_off[l + 1] - t.level_off[l];
     if (nb > 0)
-      hipLaunchKernelGGL((k_m2m<P, T>), dim3(translation_blocks((long long)nb * nsets)), dim3(256),
-                         0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
+      hipLaunchKernelGGL((k_m2m<P, T>), dim3((unsigned)std::min<long long>((long long)nb * nsets, 4096)),
+                         dim3(256), 0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
   }
   if (t.ngroup > 0) {
     ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets);
