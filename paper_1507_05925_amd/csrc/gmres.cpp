@@ -167,10 +167,10 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
       BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      // second update fused with ||w||; the column h1 + h2 with ||w|| as entry j + 1
-      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm,
+      // second update fused with ||w||; V_{j+1} = w / ||w||; the column h1 + h2 with ||w|| as
+      // entry j + 1
+      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1,
                                      wk.scratch, s));
-      BIE_TRY(seg_scale_to(sg, wk.w, wk.nrm, Vj1, s));
       double *dst = mem.pinned + (j & 1) * slot;
       BIE_HIP_CHECK(hipMemcpyAsync(dst, wk.h2, (size_t)S * hs * sizeof(double),
                                    hipMemcpyDeviceToHost, s));
