@@ -117,13 +117,14 @@ __global__ __launch_bounds__(kBlock) void k_combination_nrm(
 // Normalisation of the new Krylov vector, one workgroup per chunk c (system s): every workgroup
 // of s sums s's partials in the same fixed order, so all of them form the same ||w||, and writes
 // v = w / ||w|| over its chunk; the first workgroup of s also completes the Hessenberg column,
-// h2[s][0..cnt-1] += h1[s][...] and h2[s][cnt] = ||w||, and stores ||w|| in nrm[s].
+// h2[s][0..cnt-1] += h1[s][...] and h2[s][cnt] = ||w||, stores ||w|| in nrm[s] and, when col_out
+// is given (mapped host memory), writes the column there too.
 __global__ __launch_bounds__(kBlock) void k_normalize_column(
     int cnt, const int *__restrict__ csys, const int *__restrict__ sys_chunk,
     const long long *__restrict__ c0, const long long *__restrict__ c1,
     const double *__restrict__ partial, const double *__restrict__ w, double *__restrict__ v,
     const double *__restrict__ h1, double *__restrict__ h2, long long hs,
-    double *__restrict__ nrm) {
+    double *__restrict__ nrm, double *__restrict__ col_out) {
   __shared__ double sh[4];
   const int c = blockIdx.x, s = csys[c];
   const int a = sys_chunk[s] * kSub, b = sys_chunk[s + 1] * kSub;
@@ -132,10 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_normalize_column(
   const double n = sqrt(block_sum(acc, sh));
   for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) v[i] = n > 0.0 ? w[i] / n : 0.0;
   if (c == sys_chunk[s]) {
-    for (int l = threadIdx.x; l < cnt; l += kBlock) h2[s * hs + l] += h1[s * hs + l];
+    for (int l = threadIdx.x; l < cnt; l += kBlock) {
+      const double hv = h2[s * hs + l] + h1[s * hs + l];
+      h2[s * hs + l] = hv;
+      if (col_out) col_out[s * hs + l] = hv;
+    }
     if (threadIdx.x == 0) {
       nrm[s] = n;
       h2[s * hs + cnt] = n;
+      if (col_out) col_out[s * hs + cnt] = n;
     }
   }
 }
@@ -195,12 +201,12 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
 
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
-                           double *vnext, double *scratch, hipStream_t s) {
+                           double *vnext, double *col_out, double *scratch, hipStream_t s) {
   if (nvec <= 0) return BIE_OK;
   hipLaunchKernelGGL(k_combination_nrm, dim3(sg.C, kSub), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0,
                      sg.c1, V, vstride, h2, hs, w, -1.0, scratch);
   hipLaunchKernelGGL(k_normalize_column, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys,
-                     sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm);
+                     sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm, col_out);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

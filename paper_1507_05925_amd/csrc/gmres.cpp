@@ -169,11 +169,9 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
       // second update fused with ||w||; V_{j+1} = w / ||w||; the column h1 + h2 with ||w|| as
       // entry j + 1
+      // the column goes straight to pinned slot j % 2 (mapped host memory)
       BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1,
-                                     wk.scratch, s));
-      double *dst = mem.pinned + (j & 1) * slot;
-      BIE_HIP_CHECK(hipMemcpyAsync(dst, wk.h2, (size_t)S * hs * sizeof(double),
-                                   hipMemcpyDeviceToHost, s));
+                                     mem.pinned_dev + (j & 1) * slot, wk.scratch, s));
       BIE_HIP_CHECK(hipEventRecord(mem.ev[j & 1], s));
       return BIE_OK;
     };
@@ -258,15 +256,21 @@ int SolverMem::ensure_pinned(size_t bytes) {
     if (!e) BIE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (pinned_bytes >= bytes) return BIE_OK;
   if (pinned) {
+    BIE_HIP_CHECK(hipDeviceSynchronize());  // no kernel or copy may still use the old buffer
     BIE_HIP_CHECK(hipHostFree(pinned));
     pinned = nullptr;
+    pinned_dev = nullptr;
     pinned_bytes = 0;
   }
   size_t want = std::max<size_t>(bytes, 1 << 16);
-  if (hipHostMalloc((void **)&pinned, want, hipHostMallocDefault) != hipSuccess) {
+  // mapped and coherent: kernels write Hessenberg columns into it directly, visible to the host
+  // once the event recorded after them has completed
+  if (hipHostMalloc((void **)&pinned, want, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
     set_error("pinned host allocation failed");
     return BIE_ENOMEM;
   }
+  BIE_HIP_CHECK(hipHostGetDevicePointer((void **)&pinned_dev, pinned, 0));
   pinned_bytes = want;
   return BIE_OK;
 }
@@ -276,6 +280,7 @@ void SolverMem::release() {
   small.release();
   if (pinned) (void)hipHostFree(pinned);
   pinned = nullptr;
+  pinned_dev = nullptr;
   pinned_bytes = 0;
   for (auto &e : ev) {
     if (e) (void)hipEventDestroy(e);

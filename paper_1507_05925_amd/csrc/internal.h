@@ -62,7 +62,8 @@ struct Segments {
 // Krylov workspace and pinned staging of a solver owner (a geometry or a batch).
 struct SolverMem {
   DevBuf big, small;
-  double *pinned = nullptr;
+  double *pinned = nullptr;      // mapped, coherent host memory
+  double *pinned_dev = nullptr;  // its device address (kernels write Hessenberg columns there)
   size_t pinned_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};  // completion of the two pinned read-back slots
   int ensure_pinned(size_t bytes);
@@ -143,11 +144,11 @@ int seg_combination(const Segments &sg, int nvec, const double *V, long long vst
 int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, hipStream_t s);
 int seg_scale_to(const Segments &sg, const double *w, const double *den, double *v, hipStream_t s);
 // w -= V h2 (nvec vectors), then nrm = ||w|| per system, vnext = w / ||w||,
-// h2[s][0..nvec-1] += h1[s][...] and h2[s][nvec] = nrm[s] (the new Hessenberg column); scratch
-// holds C * 4 partials
+// h2[s][0..nvec-1] += h1[s][...] and h2[s][nvec] = nrm[s] (the new Hessenberg column, also written to
+// col_out [S][hs] when not NULL); scratch holds C * 4 partials
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
-                           double *vnext, double *scratch, hipStream_t s);
+                           double *vnext, double *col_out, double *scratch, hipStream_t s);
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
 int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
 
