@@ -53,7 +53,6 @@ __global__ __launch_bounds__(64) void k_dots_stage2(int C, const int *__restrict
 
 // w += sign * sum_l V_l h[s][l] on each chunk (s = system of the chunk); grid (C, kSub), each
 // workgroup takes every kSub-th block of 256 entries of its chunk
-constexpr int kSub = 4;
 __global__ __launch_bounds__(kBlock) void k_combination(int nvec, const int *__restrict__ csys,
                                                        const long long *__restrict__ c0,
                                                        const long long *__restrict__ c1,
@@ -118,13 +117,15 @@ __global__ __launch_bounds__(kBlock) void k_combination_nrm(
 // of s sums s's partials in the same fixed order, so all of them form the same ||w||, and writes
 // v = w / ||w|| over its chunk; the first workgroup of s also completes the Hessenberg column,
 // h2[s][0..cnt-1] += h1[s][...] and h2[s][cnt] = ||w||, stores ||w|| in nrm[s] and, when col_out
-// is given (mapped host memory), writes the column there too.
+// is given (mapped host memory), writes the column there too, then (when flag is given) stores
+// seq in flag[s] once the column is visible to the host.
 __global__ __launch_bounds__(kBlock) void k_normalize_column(
     int cnt, const int *__restrict__ csys, const int *__restrict__ sys_chunk,
     const long long *__restrict__ c0, const long long *__restrict__ c1,
     const double *__restrict__ partial, const double *__restrict__ w, double *__restrict__ v,
     const double *__restrict__ h1, double *__restrict__ h2, long long hs,
-    double *__restrict__ nrm, double *__restrict__ col_out) {
+    double *__restrict__ nrm, double *__restrict__ col_out, unsigned long long *flag,
+    unsigned long long seq) {
   __shared__ double sh[4];
   const int c = blockIdx.x, s = csys[c];
   const int a = sys_chunk[s] * kSub, b = sys_chunk[s + 1] * kSub;
@@ -142,6 +143,12 @@ __global__ __launch_bounds__(kBlock) void k_normalize_column(
       nrm[s] = n;
       h2[s * hs + cnt] = n;
       if (col_out) col_out[s * hs + cnt] = n;
+    }
+    if (flag) {  // (uniform over the workgroup)
+      __threadfence_system();  // this thread's column entries reach host memory first
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(flag + s, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -201,12 +208,14 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
 
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
-                           double *vnext, double *col_out, double *scratch, hipStream_t s) {
+                           double *vnext, double *col_out, unsigned long long *flag,
+                           unsigned long long seq, double *scratch, hipStream_t s) {
   if (nvec <= 0) return BIE_OK;
   hipLaunchKernelGGL(k_combination_nrm, dim3(sg.C, kSub), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0,
                      sg.c1, V, vstride, h2, hs, w, -1.0, scratch);
   hipLaunchKernelGGL(k_normalize_column, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys,
-                     sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm, col_out);
+                     sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm, col_out, flag,
+                     seq);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
@@ -242,7 +251,7 @@ int Segments::build(const std::vector<long long> &lens, hipStream_t s,
     const long long n = lens[k];
     if (starts) off = (*starts)[k];
     h_off[k] = off;
-    const long long per = 1024;  // chunk length
+    const long long per = kChunk;  // chunk length
     for (long long i = 0; i < n; i += per) {
       a.push_back(off + i);
       b.push_back(off + std::min(n, i + per));

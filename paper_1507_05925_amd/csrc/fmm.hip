@@ -296,8 +296,8 @@ __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nset
 // scaling of the product. Target boxes are grouped 16 at a time (same level, same position in the
 // parent, so their interaction lists share most offsets); an item is one offset d of a group with
 // the 16 sources at that offset (zero columns where a target has none). Per item, the real and
-// imaginary parts of the 16 scaled sources form two 16-column B operands, C's row tiles (in
-// registers for the whole kernel) the A operands of 16x16x4 float64 MFMAs, and the lane scales
+// imaginary parts of the 16 scaled sources form two 16-column B operands, C's row tiles (read
+// from LDS per item) the A operands of 16x16x4 float64 MFMAs, and the lane scales
 // the two results (the real and imaginary parts of C u~) by d^-(n+1) into its complex
 // accumulators. MFMA lane layout: lane (j, q) = (lane % 16, lane / 16) holds A[j][q] and B[q][j]
 // of a k-step and rows q + 4r of column j of an accumulator tile.
@@ -315,9 +315,13 @@ struct M2lShape {
   static constexpr int RED = 4 * RT * 4 * 2 * 64;
   static constexpr int LDS = TABLE > RED ? TABLE : RED;
 };
+// whether an item's sources are loaded during the previous item's products (two waves per SIMD
+// hold the extra registers up to order 48)
+template <int P>
+constexpr bool kM2lPrefetch = P <= 48;
 
 template <int P>
-__global__ __launch_bounds__(256, 3) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
+__global__ __launch_bounds__(256, 2) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
                                                const int *__restrict__ grp_tgt,
                                                const int *__restrict__ grp_lvl,
                                                const int *__restrict__ item_off,
@@ -345,28 +349,51 @@ __global__ __launch_bounds__(256, 3) void k_m2l(int g0, int nbox, const int *__r
     for (int r = 0; r < 4; ++r) br[t][r] = bi[t][r] = 0.0;
   const double2 *Ms = Mexp + (size_t)set * nbox * P;
   const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
+  // software pipeline over the wave's items it = i0 + w, i0 + w + 4, ...: the sources of the
+  // next item are loaded before this item's products (up to order 48; above, the registers do
+  // not allow it and they are loaded after) and pre-scaled after them; the indices run one item
+  // further ahead. This lane's sources are u_src[m], m = 4 kk + q; a missing source reads box 0,
+  // then zeros.
+  int it = i0 + w;
+  int s1 = -1, o1 = 0, s2 = -1, o2 = 0;  // (source, offset) of items it, it + 4
+  if (it < i1) { s1 = item_src[it * 16 + j]; o1 = item_off[it]; }
+  if (it + 4 < i1) { s2 = item_src[(it + 4) * 16 + j]; o2 = item_off[it + 4]; }
+  double bre[KS], bim[KS];
+  double2 un[KS];
   __syncthreads();
-  for (int it = i0 + w; it < i1; it += 4) {
-    // this lane's sources u_src[m], m = 4 kk + q; a missing source reads box 0, then zeros
-    const int src = item_src[it * 16 + j];
-    const int o = item_off[it];
-    const double2 *up = Ms + (size_t)max(src, 0) * P + q;
-    const double2 *dp = dps + o * DP;
-    double bre[KS], bim[KS];
+  if (it < i1) {
+    const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
+    const double2 *dp = dps + o1 * DP;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const double2 u = up[4 * kk];
       const double2 pw = dp[4 * kk + q];  // d^-m
-      const double ur = src < 0 ? 0.0 : u.x, ui = src < 0 ? 0.0 : u.y;
+      const double ur = s1 < 0 ? 0.0 : u.x, ui = s1 < 0 ? 0.0 : u.y;
       bre[kk] = fma(ur, pw.x, -ui * pw.y);
       bim[kk] = fma(ur, pw.y, ui * pw.x);
     }
+  }
+  for (; it < i1; it += 4) {
+    const int o = o1;
+    const double2 *dp = dps + o * DP;
+    s1 = s2; o1 = o2;  // item it + 4
+    const bool more = it + 4 < i1;
+    if constexpr (kM2lPrefetch<P>)
+      if (more) {
+        const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) un[kk] = up[4 * kk];
+      }
+    if (it + 8 < i1) { s2 = item_src[(it + 8) * 16 + j]; o2 = item_off[it + 8]; }
     // one row tile at a time: the real and imaginary products, then the scaling by d^-(n+1).
     // A[n][m] = C[n + m]; rows n >= P (the last tile's padding) hold finite values that are
-    // never written out
+    // never written out. The entries are read from LDS per item (an opaque zero keeps the
+    // compiler from holding all of them in registers across items).
+    int zoff = 0;
+    asm volatile("" : "+v"(zoff));
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      const double *ca = cs + 16 * t + j + q;
+      const double *ca = cs + 16 * t + j + q + zoff;
       m2l_d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
@@ -379,6 +406,21 @@ __global__ __launch_bounds__(256, 3) void k_m2l(int g0, int nbox, const int *__r
         const double2 pw = dp[16 * t + q + 4 * r + 1];  // d^-(n+1)
         br[t][r] = fma(yr[r], pw.x, fma(-yi[r], pw.y, br[t][r]));
         bi[t][r] = fma(yr[r], pw.y, fma(yi[r], pw.x, bi[t][r]));
+      }
+    }
+    if (more) {
+      if constexpr (!kM2lPrefetch<P>) {
+        const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) un[kk] = up[4 * kk];
+      }
+      const double2 *dq = dps + o1 * DP;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const double2 pw = dq[4 * kk + q];  // d^-m
+        const double ur = s1 < 0 ? 0.0 : un[kk].x, ui = s1 < 0 ? 0.0 : un[kk].y;
+        bre[kk] = fma(ur, pw.x, -ui * pw.y);
+        bim[kk] = fma(ur, pw.y, ui * pw.x);
       }
     }
   }
@@ -1168,15 +1210,16 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   const int M = t.M;
   hipLaunchKernelGGL((k_p2m<P, T>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
                      t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
-  // the near field is submitted after P2M (it depends only on the gather): P2M, which heads the
-  // chain of expansion passes, reaches the compute units first
-  BIE_TRY(launch_near());
   for (int l = t.L - 1; l >= 2; --l) {
     const int nb = t.level_off[l + 1] - t.level_off[l];
     if (nb > 0)
       hipLaunchKernelGGL((k_m2m<P, T>), dim3((unsigned)std::min<long long>((long long)nb * nsets, 4096)),
                          dim3(256), 0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
   }
+  // the near field (it depends only on the gather) is submitted after the multipole passes: it
+  // then runs beside the M2L, whose products are on the matrix cores, rather than slowing the
+  // M2M passes
+  BIE_TRY(launch_near());
   if (t.ngroup > 0) {
     ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets);
     if constexpr (std::is_same<T, float>::value)

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -58,6 +59,42 @@ int write_dev(SolverMem &mem, double *dev, const std::vector<double> &src, hipSt
   std::memcpy(mem.pinned, src.data(), src.size() * sizeof(double));
   BIE_HIP_CHECK(hipMemcpyAsync(dev, mem.pinned, src.size() * sizeof(double), hipMemcpyHostToDevice, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
+  return BIE_OK;
+}
+
+// Tag stored in a column's flag word: a NaN bit pattern with the step number in its payload, a
+// value that the doubles staged through the same pinned buffer never take.
+unsigned long long column_tag(unsigned long long seq) {
+  return 0x7FF5A00000000000ULL | (seq & 0x00000FFFFFFFFFFFULL);
+}
+
+// Waits until the kernel of an Arnoldi step has stored `tag` in all S flag words (mapped host
+// memory, written after the column). After every 2 ms without them the stream is queried (a
+// step normally takes far less): an error is returned as such, and a stream that is idle while
+// a flag is still missing is an error too.
+int wait_column(const double *flags, int S, unsigned long long tag, hipStream_t s) {
+  const volatile unsigned long long *f = reinterpret_cast<const volatile unsigned long long *>(flags);
+  auto ready = [&]() {
+    for (int r = 0; r < S; ++r)
+      if (f[r] != tag) return false;
+    return true;
+  };
+  using clk = std::chrono::steady_clock;
+  auto last = clk::now();
+  for (unsigned spin = 1;; ++spin) {
+    if (ready()) break;
+    if ((spin & 1023) == 0 && clk::now() - last > std::chrono::milliseconds(2)) {
+      last = clk::now();
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (ready()) break;
+        set_error("Arnoldi step finished without its Hessenberg column");
+        return BIE_EDEVICE;
+      }
+      if (e != hipErrorNotReady) BIE_HIP_CHECK(e);
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return BIE_OK;
 }
 
@@ -153,33 +190,36 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     for (int r = 0; r < S; ++r) gv[(size_t)r * (m + 1)] = beta[r];
     std::vector<int> jdone(S, -1);
     int jend = -1;
-    // Arnoldi step j: apply, CGS2 against V_0..V_j, V_{j+1} = w / ||w||, and an asynchronous copy
-    // of the new Hessenberg column into pinned slot j % 2. Steps run one ahead of the host: step
-    // j+1 is queued before the host waits for step j's column (a cycle that stops at step j
-    // leaves step j+1's work unused).
+    // Arnoldi step j: apply, CGS2 against V_0..V_j, V_{j+1} = w / ||w||, and the new Hessenberg
+    // column, written by the last kernel into pinned slot j % 2. Steps run one ahead of the
+    // host: step j+1 is queued before the host waits for step j's column (a cycle that stops at
+    // step j leaves step j+1's work unused).
+    // slot: the S columns, then one flag word per system
     const size_t slot = (size_t)S * hs + S;
     BIE_TRY(mem.ensure_pinned(2 * slot * sizeof(double)));
+    unsigned long long seqv[2] = {0, 0};
     auto step = [&](int j) -> int {
       double *Vj = wk.V + (size_t)j * N;
       double *Vj1 = wk.V + (size_t)(j + 1) * N;
       BIE_TRY(apply(ss, precision, Vj, wk.w, st, s));
-      // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||
+      // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||.
+      // The second update is fused with ||w||; the column (h1 + h2 with ||w|| as entry j + 1)
+      // goes straight to pinned slot j % 2 (mapped host memory), followed by its flag word
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
       BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      // second update fused with ||w||; V_{j+1} = w / ||w||; the column h1 + h2 with ||w|| as
-      // entry j + 1
-      // the column goes straight to pinned slot j % 2 (mapped host memory)
-      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1,
-                                     mem.pinned_dev + (j & 1) * slot, wk.scratch, s));
-      BIE_HIP_CHECK(hipEventRecord(mem.ev[j & 1], s));
+      double *col = mem.pinned_dev + (j & 1) * slot;
+      seqv[j & 1] = column_tag(++mem.seq);
+      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1, col,
+                                     reinterpret_cast<unsigned long long *>(col + (size_t)S * hs),
+                                     seqv[j & 1], wk.scratch, s));
       return BIE_OK;
     };
     BIE_TRY(step(0));
     for (int j = 0; j < m; ++j) {
       st.iters += 1;
       if (j + 1 < m && st.iters < max_iter) BIE_TRY(step(j + 1));
-      BIE_HIP_CHECK(hipEventSynchronize(mem.ev[j & 1]));
+      BIE_TRY(wait_column(mem.pinned + (j & 1) * slot + (size_t)S * hs, S, seqv[j & 1], s));
       const double *hh2 = mem.pinned + (j & 1) * slot;
       bool all_done = true;
       for (int r = 0; r < S; ++r) {
@@ -252,8 +292,6 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
 }
 
 int SolverMem::ensure_pinned(size_t bytes) {
-  for (auto &e : ev)
-    if (!e) BIE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (pinned_bytes >= bytes) return BIE_OK;
   if (pinned) {
     BIE_HIP_CHECK(hipDeviceSynchronize());  // no kernel or copy may still use the old buffer
@@ -263,8 +301,8 @@ int SolverMem::ensure_pinned(size_t bytes) {
     pinned_bytes = 0;
   }
   size_t want = std::max<size_t>(bytes, 1 << 16);
-  // mapped and coherent: kernels write Hessenberg columns into it directly, visible to the host
-  // once the event recorded after them has completed
+  // mapped and coherent: kernels write Hessenberg columns into it directly, each followed by a
+  // flag word that tells the host the column is complete
   if (hipHostMalloc((void **)&pinned, want, hipHostMallocMapped | hipHostMallocCoherent) !=
       hipSuccess) {
     set_error("pinned host allocation failed");
@@ -282,10 +320,6 @@ void SolverMem::release() {
   pinned = nullptr;
   pinned_dev = nullptr;
   pinned_bytes = 0;
-  for (auto &e : ev) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
 }
 
 // Solves every system of ss to o.tol (relative, float64 operator). relres_out gets the final true

@@ -15,6 +15,8 @@ namespace bie {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kBlock = 256;  // threads per workgroup for every kernel (4 wave64)
+constexpr int kSub = 4;                // workgroups per chunk in the segmented update kernels
+constexpr int kChunk = kSub * kBlock;  // entries per chunk of a segmented vector
 
 void set_error(const std::string &msg);
 
@@ -65,7 +67,7 @@ struct SolverMem {
   double *pinned = nullptr;      // mapped, coherent host memory
   double *pinned_dev = nullptr;  // its device address (kernels write Hessenberg columns there)
   size_t pinned_bytes = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};  // completion of the two pinned read-back slots
+  unsigned long long seq = 0;  // last Arnoldi step number handed out (column flags)
   int ensure_pinned(size_t bytes);
   void release();
 };
@@ -145,10 +147,12 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
 int seg_scale_to(const Segments &sg, const double *w, const double *den, double *v, hipStream_t s);
 // w -= V h2 (nvec vectors), then nrm = ||w|| per system, vnext = w / ||w||,
 // h2[s][0..nvec-1] += h1[s][...] and h2[s][nvec] = nrm[s] (the new Hessenberg column, also written to
-// col_out [S][hs] when not NULL); scratch holds C * 4 partials
+// col_out [S][hs] when not NULL, and then seq to flag[s] when flag is not NULL: both in mapped
+// host memory); scratch holds C * 4 partials
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
-                           double *vnext, double *col_out, double *scratch, hipStream_t s);
+                           double *vnext, double *col_out, unsigned long long *flag,
+                           unsigned long long seq, double *scratch, hipStream_t s);
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
 int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
 
