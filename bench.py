@@ -461,7 +461,7 @@ def main():
         "k_lap_far_f64": (bie2d.BIE_K_FAR_LAPLACE_F64, FLOPS_PER_PAIR, "f64", "alu",
                           "k_lap_far_f64<1>"),
         "k_m2l": (bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(order), "f64", "mfma", f"k_m2l<{order}>"),
-        "k_near_laplace": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near_laplace"),
+        "k_near": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near<false>"),
         "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64", "alu", "k_lap_epilogue"),
     }
     # one untimed solve with every class recorded picks the dominant kernel class; the timed

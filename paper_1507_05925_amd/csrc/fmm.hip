@@ -45,6 +45,11 @@ struct FmmTree {
       *parent = nullptr, *run_ptr = nullptr, *chunk_leaf = nullptr,
       *chunk_start = nullptr;
   int nchunk = 0;
+  // evaluation chunks (L2P): up to 64 consecutive sorted targets of at most kEvalLeaves
+  // consecutive leaves; ev_start [nev + 1], ev_leaf [nev] (first leaf); ev_maxslot = most
+  // ancestor expansions one chunk stages
+  int *ev_start = nullptr, *ev_leaf = nullptr;
+  int nev = 0, ev_maxslot = 0;
   // M2L groups: 16 target boxes each (grp_tgt, -1 = unused column), their level, and per group
   // the offsets it uses (item_off, increasing) with the 16 source boxes of each (item_src, -1 =
   // none)
@@ -582,90 +587,130 @@ __device__ inline V eval_value(const V *b, V w) {
 }
 
 // Near field. The neighbour leaves of a leaf (itself included) form a few runs of consecutive
-// sorted nodes, whose source records (x, y, s, 0) or (x, y, rho) are the same for the whole wave.
-// SELF: the run holds the target's own leaf, and the pair of a target with itself is masked
-// without a branch.
-template <bool STOKES, bool SELF, bool TAIL>
-__device__ __forceinline__ void near_step(const double4 *rec, int k, int k1, int self, double2 z,
-                                          double2 nv, double &gx, double &gy) {
+// sorted nodes, whose source records (x, y, s, 0) or (x, y, rho) are the same for all targets of
+// the leaf. A workgroup of four waves takes a chunk of up to 64 targets of one leaf: wave w holds
+// targets 16 w .. 16 w + 15 of the chunk (lane % 16), and lane group g = lane / 16 takes the
+// records g, g + 4, g + 8, ... of the staged records, so a leaf of n targets keeps ceil(n / 16)
+// waves busy with 16 lanes per target row instead of one wave with n of 64 lanes. The four
+// groups' sums are added at the end in a fixed order.
+//
+// No pair is masked. The pair of a target with itself has r = 0 exactly (its record holds the
+// same coordinates): |r|^2 is raised to kSelfFloor, far below the square of any distance between
+// two nodes, so the factor stays finite and the pair adds r times it, i.e. zero. Staged segments
+// are padded to a multiple of 32 records with zero-weight records far away, which add zero too.
+constexpr double kSelfFloor = 1e-100;
+constexpr double kNearPad = 1e50;  // coordinates of a padding record
+
+// One step over the eight records rec (this lane's group).
+template <bool STOKES>
+__device__ __forceinline__ void near_step(const double4 *rec, double2 z, double2 nv, double &gx,
+                                          double &gy) {
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const bool in = !TAIL || k + u < k1;  // wave-uniform
     const double dx = z.x - rec[u].x, dy = z.y - rec[u].y;
-    double rr = fma(dx, dx, dy * dy);
-    const bool same = SELF && (k + u == self);
-    if (SELF) rr = same ? 1.0 : rr;
-    if (TAIL) rr = in ? rr : 1.0;  // padded slots repeat record k1 - 1, which may be the target
-    const double inv = rcp64(rr);
+    const double inv = rcp64(fmax(fma(dx, dx, dy * dy), kSelfFloor));
     double t;
     if (STOKES) {
       const double rn = fma(dx, nv.x, dy * nv.y);
-      t = fma(dx, in ? rec[u].z : 0.0, dy * (in ? rec[u].w : 0.0)) * rn * (inv * inv);
+      t = fma(dx, rec[u].z, dy * rec[u].w) * rn * (inv * inv);
     } else {
-      t = (in ? rec[u].z : 0.0) * inv;
+      t = rec[u].z * inv;
     }
-    if (SELF) t = same ? 0.0 : t;
     gx = fma(dx, t, gx);
     gy = fma(dy, t, gy);
   }
 }
 
-// A run is read in blocks of kNearBuf records: the wave copies a block into LDS with coalesced
-// vector loads (one wait per block) and then reads the records by LDS broadcast, eight per step
-// (LDS reads complete in order, so they overlap with the arithmetic; scalar loads, which complete
-// out of order, cannot). A block's tail is one step more over repeated indices with zero weight.
-constexpr int kNearBuf = 128;
-
-template <bool STOKES, bool SELF>
-__device__ __forceinline__ void near_run(int k0, int k1, int self, double2 z, double2 nv,
-                                         const double4 *__restrict__ S4, double4 *buf,
+// Sum over the staged records at LDS positions [0, n) (n a multiple of 32): this lane's group
+// reads positions g, g + 4, ... by LDS broadcast (four addresses per read, one per group), eight
+// per step.
+template <bool STOKES>
+__device__ __forceinline__ void near_seg(const double4 *buf, int n, int g, double2 z, double2 nv,
                                          double &gx, double &gy) {
-  for (int base = k0; base < k1; base += kNearBuf) {
-    const int n = min(kNearBuf, k1 - base);
-    __syncthreads();  // the previous block is no longer read
-    for (int t = threadIdx.x; t < n; t += 64) buf[t] = S4[base + t];
-    __syncthreads();
-    int k = 0;
-    for (; k + 8 <= n; k += 8) {
-      double4 rec[8];
+  for (int k = 0; k < n; k += 32) {
+    double4 rec[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) rec[u] = buf[k + u];
-      near_step<STOKES, SELF, false>(rec, base + k, base + n, self, z, nv, gx, gy);
-    }
-    if (k < n) {
-      double4 rec[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) rec[u] = buf[min(k + u, n - 1)];
-      near_step<STOKES, SELF, true>(rec, base + k, base + n, self, z, nv, gx, gy);
-    }
+    for (int u = 0; u < 8; ++u) rec[u] = buf[k + 4 * u + g];
+    near_step<STOKES>(rec, z, nv, gx, gy);
   }
 }
 
-// Near field, Laplace: grid (target chunks, R), one wave per chunk of up to 64 nodes of a leaf;
-// writes -(1/2pi) n.(sum over the neighbour leaves, k != i, of s_k r/|r|^2).
-__global__ __launch_bounds__(64) void k_near_laplace(
+// LDS records per workgroup (a multiple of 32). A leaf whose runs hold at most this many records
+// (after padding) has them all staged at once, back to back: one load latency and one barrier.
+// Larger neighbourhoods are read run by run in blocks of this size.
+constexpr int kNearCap = 1024;
+
+// Copies n records src[0 .. n) to buf[at ..], then zero-weight padding up to a multiple of 32
+// records; returns the padded count.
+__device__ __forceinline__ int near_stage(const double4 *__restrict__ src, int n, double4 *buf,
+                                          int at) {
+  const int np = (n + 31) & ~31;
+  for (int t = threadIdx.x; t < np; t += blockDim.x)
+    buf[at + t] = t < n ? src[t] : make_double4(kNearPad, kNearPad, 0.0, 0.0);
+  return np;
+}
+
+// Near field: grid (target chunks, R), 256 threads. Laplace writes -(1/2pi) n.(sum over the
+// neighbour leaves, k != i, of s_k r/|r|^2); Stokes writes -(1/pi) sum over the neighbour leaves,
+// k != i, of (r.n)(r.rho_k) r/|r|^4 (two components per node). Waves without targets (busy false,
+// uniform over the wave) take part in the copies and barriers only.
+template <bool STOKES>
+__global__ __launch_bounds__(256) void k_near(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
     const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ run_ptr, const int2 *__restrict__ run,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double4 *__restrict__ S4, double *__restrict__ out) {
   const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  const int j = chunk_start[blockIdx.x] + threadIdx.x;
-  const bool valid = j < j1;
-  const int jj = valid ? j : j0;
-  const double2 z = xs[jj], nv = nrm[jj];
+  const int j1 = leaf_start[leaf + 1];
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int t0 = chunk_start[blockIdx.x] + 16 * (threadIdx.x >> 6);  // the wave's first target
+  const int j = t0 + (lane & 15);
+  const bool valid = j < j1, busy = t0 < j1;
+  const int jj = valid ? j : t0;
+  const double2 z = xs[min(jj, M - 1)], nv = nrm[min(jj, M - 1)];
   const double4 *src = S4 + (size_t)r * M;
-  __shared__ double4 buf[kNearBuf];
+  __shared__ double4 buf[kNearCap];
   double gx = 0.0, gy = 0.0;
-  for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
-    const int2 kr = run[e];
-    if (kr.x <= j0 && j1 <= kr.y)
-      near_run<false, true>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
-    else
-      near_run<false, false>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
+  const int e0 = run_ptr[leaf], e1 = run_ptr[leaf + 1];
+  int total = 0;
+  for (int e = e0; e < e1; ++e) total += run[e].y - run[e].x;
+  const int padded = (total + 31) & ~31;
+  if (padded <= kNearCap) {  // the runs back to back, one padding at the end
+    int at = 0;
+    for (int e = e0; e < e1; ++e) {
+      const int2 kr = run[e];
+      const int n = kr.y - kr.x;
+      for (int t = threadIdx.x; t < n; t += blockDim.x) buf[at + t] = src[kr.x + t];
+      at += n;
+    }
+    for (int t = total + threadIdx.x; t < padded; t += blockDim.x)
+      buf[t] = make_double4(kNearPad, kNearPad, 0.0, 0.0);
+    __syncthreads();
+    if (busy) near_seg<STOKES>(buf, padded, g, z, nv, gx, gy);
+  } else {
+    for (int e = e0; e < e1; ++e) {
+      const int2 kr = run[e];
+      for (int base = kr.x; base < kr.y; base += kNearCap) {
+        __syncthreads();  // the previous block is no longer read
+        const int n = near_stage(src + base, min(kNearCap, kr.y - base), buf, 0);
+        __syncthreads();
+        if (busy) near_seg<STOKES>(buf, n, g, z, nv, gx, gy);
+      }
+    }
   }
-  if (valid) out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+  gx += __shfl_xor(gx, 16, 64);
+  gy += __shfl_xor(gy, 16, 64);
+  gx += __shfl_xor(gx, 32, 64);
+  gy += __shfl_xor(gy, 32, 64);
+  if (!valid || g != 0) return;
+  const int i = perm[j];
+  if (STOKES) {
+    out[(size_t)r * 2 * M + 2 * i] = -gx / kPi;
+    out[(size_t)r * 2 * M + 2 * i + 1] = -gy / kPi;
+  } else {
+    out[(size_t)r * M + i] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+  }
 }
 
 // Downward pass and evaluation in one: the local expansion of a leaf is the sum over its
@@ -673,81 +718,85 @@ __global__ __launch_bounds__(64) void k_near_laplace(
 // re-expanding a polynomial about another centre is exact (L2L has no truncation). So each target
 // evaluates the M2L part of every ancestor directly at its own scaled coordinate
 // w_A = (z - c_A)/h_A and sums the values (levels in decreasing order), which replaces the
-// level-by-level L2L passes. One wave per chunk of a leaf: the ancestors (a table per leaf) are
-// the same for the whole wave, so the wave first copies their coefficients into LDS with
-// coalesced vector loads (one wait), and the Horner steps then read them by LDS broadcast.
-// Copies the coefficient sets `sets` (nsets_here of them) of the nlev ancestors into cf:
-// cf[(k * nlev + i) * P + n] = Lexp[set k][anc[i]][n].
+// level-by-level L2L passes. One wave per evaluation chunk: up to 64 consecutive sorted targets of
+// at most kEvalLeaves consecutive leaves, so that nearly every lane has a target. At each level
+// the ancestors of consecutive leaves are consecutive boxes (boxes of a level are numbered in
+// Morton order and none is empty), so the chunk's ancestors at level index i (0 = leaf level)
+// are the boxes lo_i .. hi_i. The wave first copies their coefficients into LDS with coalesced
+// vector loads (one wait), at slots off_i .. off_i + hi_i - lo_i (levels in order), and the Horner
+// steps then read them by LDS broadcast (one address per leaf of the chunk).
+constexpr int kEvalLeaves = 4;
+
+// Copies the ancestor coefficients of a chunk whose first and last leaves have the ancestor lists
+// a0 and a1 ([nlev] each): per set k < nsets_here (from set0),
+// cf[(k * nslot + off_i + b) * P + n] = Lexp[set0 + k][lo_i + b][n].
 template <int P, class T>
-__device__ __forceinline__ void stage_ancestors(const int *anc, int nlev, int nbox, int set0,
-                                                int nsets_here, const cx<T> *__restrict__ Lexp,
-                                                cx<T> *cf) {
-  const int total = nsets_here * nlev * P;
-  for (int e = threadIdx.x; e < total; e += 64) {
-    const int n = e % P, ki = e / P, i = ki % nlev, k = ki / nlev;
-    cf[e] = Lexp[((size_t)(set0 + k) * nbox + anc[i]) * P + n];
+__device__ __forceinline__ void stage_levels(const int *a0, const int *a1, int nlev, int nbox,
+                                             int set0, int nsets_here, int nslot,
+                                             const cx<T> *__restrict__ Lexp, cx<T> *cf) {
+  int off = 0;
+  for (int i = 0; i < nlev; ++i) {
+    const int lo = a0[i], cnt = a1[i] - lo + 1;
+    for (int k = 0; k < nsets_here; ++k) {
+      const cx<T> *src = Lexp + ((size_t)(set0 + k) * nbox + lo) * P;
+      cx<T> *dst = cf + ((size_t)k * nslot + off) * P;
+      for (int e = threadIdx.x; e < cnt * P; e += 64) dst[e] = src[e];
+    }
+    off += cnt;
   }
   __syncthreads();
 }
 
-// L2P, Laplace: adds -(1/2pi) Re(nu F(z)). Dynamic LDS: (L - 1) P coefficients.
+// The chunk's leaves: first lf0, last lf1 (the leaf of its last target), and the number of
+// ancestor slots.
+__device__ __forceinline__ int chunk_leaves(const int *__restrict__ leaf_start,
+                                            const int *__restrict__ leaf_anc, int nlev, int lf0,
+                                            int j1, int &lf1) {
+  lf1 = lf0;
+  while (leaf_start[lf1 + 1] < j1) ++lf1;
+  const int *a0 = leaf_anc + (size_t)lf0 * nlev, *a1 = leaf_anc + (size_t)lf1 * nlev;
+  int nslot = 0;
+  for (int i = 0; i < nlev; ++i) nslot += a1[i] - a0[i] + 1;
+  return nslot;
+}
+
+// L2P, Laplace: adds -(1/2pi) Re(nu F(z)). Grid (evaluation chunks, R); dynamic LDS:
+// ev_maxslot P coefficients.
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_l2p_laplace(
     int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
     const int *__restrict__ leaf_anc, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const int *__restrict__ ev_start, const int *__restrict__ ev_leaf,
     const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
   extern __shared__ char l2p_lds[];
   cx<T> *cf = reinterpret_cast<cx<T> *>(l2p_lds);
-  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int nlev = L - 1;
-  const int *anc = leaf_anc + (size_t)leaf * nlev;  // levels L, L - 1, ..., 2
-  stage_ancestors<P, T>(anc, nlev, nbox, r, 1, Lexp, cf);
-  const int j = chunk_start[blockIdx.x] + threadIdx.x;
-  if (j >= leaf_start[leaf + 1]) return;
+  const int c = blockIdx.x, r = blockIdx.y;
+  const int j0 = ev_start[c], j1 = ev_start[c + 1], lf0 = ev_leaf[c];
+  const int nlev = L - 1;  // ancestor lists: levels L, L - 1, ..., 2
+  int lf1;
+  const int nslot = chunk_leaves(leaf_start, leaf_anc, nlev, lf0, j1, lf1);
+  const int *a0 = leaf_anc + (size_t)lf0 * nlev, *a1 = leaf_anc + (size_t)lf1 * nlev;
+  stage_levels<P, T>(a0, a1, nlev, nbox, r, 1, nslot, Lexp, cf);
+  const int j = j0 + threadIdx.x;
+  if (j >= j1) return;
+  int lf = lf0;
+  while (leaf_start[lf + 1] <= j) ++lf;
+  const int *anc = leaf_anc + (size_t)lf * nlev;
   const double2 z = xs[j], nv = nrm[j];
   cx<T> F = mkc<T>(0, 0);
   double ih = ih_leaf;
-  for (int i = 0; i < nlev; ++i) {
-    const double2 c = center[anc[i]];
-    const cx<T> Fl = eval_value<P>(cf + i * P, mkc<T>((T)((z.x - c.x) * ih), (T)((z.y - c.y) * ih)));
+  for (int i = 0, off = 0; i < nlev; ++i) {
+    const int b = anc[i];
+    const double2 cc = center[b];
+    const cx<T> Fl = eval_value<P>(cf + (size_t)(off + b - a0[i]) * P,
+                                   mkc<T>((T)((z.x - cc.x) * ih), (T)((z.y - cc.y) * ih)));
     F = mkc<T>(F.x + Fl.x, F.y + Fl.y);
+    off += a1[i] - a0[i] + 1;
     ih *= 0.5;
   }
   double *o = out + (size_t)r * M + perm[j];
   *o -= (nv.x * (double)F.x - nv.y * (double)F.y) / (2.0 * kPi);  // Re(nu F)
-}
-
-// Near field, Stokes: grid (target chunks, R); writes -(1/pi) sum over the neighbour leaves,
-// k != i, of (r.n)(r.rho_k) r/|r|^4.
-__global__ __launch_bounds__(64) void k_near_stokes(
-    int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
-    const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ run_ptr, const int2 *__restrict__ run,
-    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
-    const double4 *__restrict__ S4, double *__restrict__ out) {
-  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
-  const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  const int j = chunk_start[blockIdx.x] + threadIdx.x;
-  const bool valid = j < j1;
-  const int jj = valid ? j : j0;
-  const double2 z = xs[jj], nv = nrm[jj];
-  const double4 *src = S4 + (size_t)r * M;
-  __shared__ double4 buf[kNearBuf];
-  double gx = 0.0, gy = 0.0;
-  for (int e = run_ptr[leaf]; e < run_ptr[leaf + 1]; ++e) {
-    const int2 kr = run[e];
-    if (kr.x <= j0 && j1 <= kr.y)
-      near_run<true, true>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
-    else
-      near_run<true, false>(kr.x, kr.y, jj, z, nv, src, buf, gx, gy);
-  }
-  if (valid) {
-    const int i = perm[j];
-    out[(size_t)r * 2 * M + 2 * i] = -gx / kPi;
-    out[(size_t)r * 2 * M + 2 * i + 1] = -gy / kPi;
-  }
 }
 
 // L2P, Stokes: sets 3r, 3r+1, 3r+2 are the expansions of A, B, C; adds -(1/pi) of
@@ -757,26 +806,35 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
     int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
     const int *__restrict__ leaf_anc, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
-    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const int *__restrict__ ev_start, const int *__restrict__ ev_leaf,
     const double2 *__restrict__ Lexp, double *__restrict__ out) {
   extern __shared__ char l2p_lds[];
-  double2 *cf = reinterpret_cast<double2 *>(l2p_lds);  // sets A, B, C of every ancestor
-  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  double2 *cf = reinterpret_cast<double2 *>(l2p_lds);  // sets A, B, C of every staged ancestor
+  const int c = blockIdx.x, r = blockIdx.y;
+  const int j0 = ev_start[c], j1 = ev_start[c + 1], lf0 = ev_leaf[c];
   const int nlev = L - 1;
-  const int *anc = leaf_anc + (size_t)leaf * nlev;
-  stage_ancestors<P, double>(anc, nlev, nbox, 3 * r, 3, Lexp, cf);
-  const int j = chunk_start[blockIdx.x] + threadIdx.x;
-  if (j >= leaf_start[leaf + 1]) return;
+  int lf1;
+  const int nslot = chunk_leaves(leaf_start, leaf_anc, nlev, lf0, j1, lf1);
+  const int *a0 = leaf_anc + (size_t)lf0 * nlev, *a1 = leaf_anc + (size_t)lf1 * nlev;
+  stage_levels<P, double>(a0, a1, nlev, nbox, 3 * r, 3, nslot, Lexp, cf);
+  const int j = j0 + threadIdx.x;
+  if (j >= j1) return;
+  int lf = lf0;
+  while (leaf_start[lf + 1] <= j) ++lf;
+  const int *anc = leaf_anc + (size_t)lf * nlev;
   const double2 z = xs[j], nv = nrm[j];
   double2 A = make_double2(0.0, 0.0), dA = A, B = A, C = A, dC = A;
   double ih = ih_leaf;
-  for (int i = 0; i < nlev; ++i) {  // ancestors, as in the Laplace evaluation
-    const double2 c = center[anc[i]];
-    const double2 w = make_double2((z.x - c.x) * ih, (z.y - c.y) * ih);
+  for (int i = 0, off = 0; i < nlev; ++i) {  // ancestors, as in the Laplace evaluation
+    const int b = anc[i];
+    const double2 cc = center[b];
+    const double2 w = make_double2((z.x - cc.x) * ih, (z.y - cc.y) * ih);
+    const size_t sl = (size_t)(off + b - a0[i]);
+    off += a1[i] - a0[i] + 1;
     double2 Al, dAl, Cl, dCl;
-    eval_local<P>(cf + (size_t)(0 * nlev + i) * P, w, ih, Al, dAl);
-    const double2 Bl = eval_value<P>(cf + (size_t)(1 * nlev + i) * P, w);
-    eval_local<P>(cf + (size_t)(2 * nlev + i) * P, w, ih, Cl, dCl);
+    eval_local<P>(cf + (0 * (size_t)nslot + sl) * P, w, ih, Al, dAl);
+    const double2 Bl = eval_value<P>(cf + (1 * (size_t)nslot + sl) * P, w);
+    eval_local<P>(cf + (2 * (size_t)nslot + sl) * P, w, ih, Cl, dCl);
     A = make_double2(A.x + Al.x, A.y + Al.y);
     dA = make_double2(dA.x + dAl.x, dA.y + dAl.y);
     B = make_double2(B.x + Bl.x, B.y + Bl.y);
@@ -971,6 +1029,35 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       }
     near_ptr.push_back((int)near_leaf.size());
   }
+  // evaluation chunks: from target j, up to 64 targets, adding whole or partial leaves while
+  // the chunk spans at most kEvalLeaves leaves and `cap` ancestor slots (2 (L - 1), and at most
+  // what keeps the Stokes evaluation's three sets within 64 KiB of LDS; one leaf: L - 1)
+  std::vector<int> ev_start, ev_leaf;
+  int ev_maxslot = 0;
+  {
+    const int nlev = L - 1;
+    const int cap = std::min(2 * nlev, 65536 / (3 * 16 * p));
+    auto slots = [&](int b0, int b1) {
+      int n = 0;
+      for (int i = 0; i < nlev; ++i)
+        n += leaf_anc[(size_t)b1 * nlev + i] - leaf_anc[(size_t)b0 * nlev + i] + 1;
+      return n;
+    };
+    int b = 0;
+    for (int j = 0; j < M;) {
+      while (leaf_start[b + 1] <= j) ++b;
+      const int end = std::min(M, j + 64);
+      int last = b;
+      while (last + 1 < t.nleaf && leaf_start[last + 1] < end && last + 2 - b <= kEvalLeaves &&
+             slots(b, last + 1) <= cap)
+        ++last;
+      ev_start.push_back(j);
+      ev_leaf.push_back(b);
+      ev_maxslot = std::max(ev_maxslot, slots(b, last));
+      j = std::min(end, leaf_start[last + 1]);
+    }
+    ev_start.push_back(M);
+  }
   // translation operators: the 40 M2L offsets (compact index) and, below, the M2L and M2M
   // tables
   std::vector<int> ocompact(49, -1);
@@ -1100,9 +1187,9 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   const size_t nitem = std::max<size_t>(item_off.size(), 1), nnear = std::max<size_t>(run_kk.size(), 2);
   const size_t ints = (size_t)M + (t.nleaf + 1) + t.nleaf + 4 * (size_t)t.nbox + t.nbox +
                       grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + run_ptr.size() +
-                      nnear + 2 * chunk_leaf.size() + leaf_anc.size();
+                      nnear + 2 * chunk_leaf.size() + leaf_anc.size() + 2 * ev_start.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p + Tdpow.size();
-  const size_t bytes = d2 * 16 + (L + 1 + 4 * p) * 8 + ints * 4 + 34 * 256;
+  const size_t bytes = d2 * 16 + (L + 1 + 4 * p) * 8 + ints * 4 + 36 * 256;
   BIE_TRY(t.buf.reserve(bytes));
   char *q = t.buf.as<char>();
   auto take = [&](size_t nbytes) {
@@ -1136,6 +1223,10 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.nchunk = (int)chunk_leaf.size();
   t.chunk_leaf = (int *)take(chunk_leaf.size() * 4);
   t.chunk_start = (int *)take(chunk_start.size() * 4);
+  t.nev = (int)ev_leaf.size();
+  t.ev_maxslot = ev_maxslot;
+  t.ev_start = (int *)take(ev_start.size() * 4);
+  t.ev_leaf = (int *)take(ev_leaf.size() * 4);
   if ((size_t)(q - t.buf.as<char>()) > t.buf.bytes) {
     set_error("fmm: arena overflow");
     return BIE_EINVAL;
@@ -1170,6 +1261,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.run, run_kk.data(), run_kk.size() * 4));
   BIE_TRY(up(t.chunk_leaf, chunk_leaf.data(), chunk_leaf.size() * 4));
   BIE_TRY(up(t.chunk_start, chunk_start.data(), chunk_start.size() * 4));
+  BIE_TRY(up(t.ev_start, ev_start.data(), ev_start.size() * 4));
+  BIE_TRY(up(t.ev_leaf, ev_leaf.data(), ev_leaf.size() * 4));
   BIE_HIP_CHECK(hipStreamSynchronize(s));  // host vectors go out of scope
   (void)off2;
   return BIE_OK;
@@ -1229,16 +1322,16 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   }
   BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
   if (kind == 0) {
-    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nchunk, R), dim3(64),
-                       (size_t)(t.L - 1) * P * sizeof(cx<T>), s, M, t.nbox, t.L, ih_leaf,
-                       t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.chunk_leaf,
-                       t.chunk_start, Lexp, partial);
+    hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nev, R), dim3(64),
+                       (size_t)t.ev_maxslot * P * sizeof(cx<T>), s, M, t.nbox, t.L, ih_leaf,
+                       t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.ev_start,
+                       t.ev_leaf, Lexp, partial);
   } else {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nchunk, R), dim3(64),
-                         (size_t)3 * (t.L - 1) * P * sizeof(double2), s, M, t.nbox, t.L, ih_leaf,
-                         t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.chunk_leaf,
-                         t.chunk_start, Lexp, partial);
+      hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nev, R), dim3(64),
+                         (size_t)3 * t.ev_maxslot * P * sizeof(double2), s, M, t.nbox, t.L,
+                         ih_leaf, t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm,
+                         t.ev_start, t.ev_leaf, Lexp, partial);
   }
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
@@ -1319,11 +1412,11 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
     {
       ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
       if (kind == 0)
-        hipLaunchKernelGGL(k_near_laplace, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+        hipLaunchKernelGGL(k_near<false>, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
                            t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
                            t.chunk_start, S4, partial);
       else
-        hipLaunchKernelGGL(k_near_stokes, dim3(t.nchunk, R), dim3(64), 0, plan.side, M,
+        hipLaunchKernelGGL(k_near<true>, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
                            t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
                            t.chunk_start, S4, partial);
       BIE_HIP_CHECK(hipGetLastError());
