@@ -177,11 +177,12 @@ __device__ __forceinline__ float rl(float v, int l) {
 }
 
 // P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
-// u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in). Lanes
-// take 64 sources at a time and
-// raise their powers incrementally; eight coefficients at a time go through LDS, where lane
-// (b, g) = (lane / 8, lane % 8) sums sources g, g+8, ..., g+56 of coefficient b, and the eight
-// partials of b are combined across lanes. Fixed order: the result is reproducible.
+// u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in). Lane
+// (g, b) = (lane % 8, lane / 8) takes the sources j = j0 + g, j0 + g + 8, ... and the P/8
+// coefficients n = b P/8 .. (b + 1) P/8 - 1: per source it forms w^(b P/8) (w^(P/8) raised to b by
+// squaring) and the following powers by running products, accumulating in registers. The eight
+// lanes of each coefficient block are then added by three shuffle steps. Fixed order: the result
+// is reproducible.
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const int *__restrict__ leaf_start,
@@ -191,54 +192,50 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const cx<T> *__restrict__ Q,
                                            const double *__restrict__ fact_in,
                                            cx<T> *__restrict__ Mexp) {
-  __shared__ cx<T> sh[8 * 64];
+  constexpr int NB = P / 8;  // coefficients per lane
   const int leaf = blockIdx.x, set = blockIdx.y, lane = threadIdx.x;
-  const int g = lane & 7, bb = lane >> 3;
+  const int g = lane & 7, b = lane >> 3;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
   const cx<T> *q = Q + (size_t)set * M;
-  cx<T> acc[P / 8];
+  cx<T> acc[NB];
 #pragma unroll
-  for (int k = 0; k < P / 8; ++k) acc[k] = mkc<T>(0, 0);
+  for (int k = 0; k < NB; ++k) acc[k] = mkc<T>(0, 0);
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  for (int jb = j0; jb < j1; jb += 64) {
-    const int j = jb + lane;
-    cx<T> w = mkc<T>(0, 0), t = w;
-    if (j < j1) {
-      const double2 z = xs[j];  // leaf-relative coordinates formed in float64
-      w = mkc<T>((T)((z.x - c.x) * inv_h), (T)((z.y - c.y) * inv_h));
-      t = q[j];
+  for (int j = j0 + g; j < j1; j += 8) {
+    const double2 z = xs[j];  // leaf-relative coordinates formed in float64
+    const cx<T> w = mkc<T>((T)((z.x - c.x) * inv_h), (T)((z.y - c.y) * inv_h));
+    cx<T> wb = w;  // w^NB
+#pragma unroll
+    for (int k = 1; k < NB; ++k) wb = cmul(wb, w);
+    cx<T> t = q[j];  // q w^(b NB), by squaring over the three bits of b
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+      const cx<T> tw = cmul(t, wb);
+      const bool use = (b >> bit) & 1;  // per component (a select of the pair is not)
+      t.x = use ? tw.x : t.x;
+      t.y = use ? tw.y : t.y;
+      wb = cmul(wb, wb);
     }
 #pragma unroll
-    for (int k = 0; k < P / 8; ++k) {
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        sh[b * 64 + lane] = t;
-        t = cmul(t, w);
-      }
-      __syncthreads();
-      cx<T> sum = mkc<T>(0, 0);
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const cx<T> v = sh[bb * 64 + r * 8 + g];
-        sum.x += v.x;
-        sum.y += v.y;
-      }
-#pragma unroll
-      for (int off = 1; off < 8; off <<= 1) {
-        sum.x += __shfl_xor(sum.x, off, 64);
-        sum.y += __shfl_xor(sum.y, off, 64);
-      }
-      acc[k].x += sum.x;
-      acc[k].y += sum.y;
-      __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+      acc[k].x += t.x;
+      acc[k].y += t.y;
+      t = cmul(t, w);
     }
   }
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      acc[k].x += __shfl_xor(acc[k].x, off, 64);
+      acc[k].y += __shfl_xor(acc[k].y, off, 64);
+    }
   if (g == 0) {
     cx<T> *o = Mexp + ((size_t)set * nbox + box) * P;
 #pragma unroll
-    for (int k = 0; k < P / 8; ++k) {
-      const int n = 8 * k + bb;
+    for (int k = 0; k < NB; ++k) {
+      const int n = NB * b + k;
       const T f = (T)fact_in[n];
       o[n] = mkc<T>(acc[k].x * f, acc[k].y * f);
     }
