@@ -176,6 +176,12 @@ __device__ __forceinline__ float rl(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Wave priority of the expansion chain (P2M, M2M, M2L, evaluation). The near field runs on a
+// second stream beside the chain and shares its compute units; at equal priority it slows the
+// chain's latency-bound kernels. Raised, the chain's waves issue first where both are resident
+// and the near field takes the remaining issue slots (it stays at the default, 0).
+constexpr int kChainPrio = 3;
+
 // P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
 // u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in). Lane
 // (g, b) = (lane % 8, lane / 8) takes the sources j = j0 + g, j0 + g + 8, ... and the P/8
@@ -192,6 +198,7 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const cx<T> *__restrict__ Q,
                                            const double *__restrict__ fact_in,
                                            cx<T> *__restrict__ Mexp) {
+  __builtin_amdgcn_s_setprio(kChainPrio);
   constexpr int NB = P / 8;  // coefficients per lane
   const int leaf = blockIdx.x, set = blockIdx.y, lane = threadIdx.x;
   const int g = lane & 7, b = lane >> 3;
@@ -255,6 +262,7 @@ template <int P, class T>
 __global__ __launch_bounds__(256) void k_m2m(int nb, int off, int nbox, int nsets,
                                             const int *__restrict__ child,
                                             const double2 *__restrict__ tau, cx<T> *Mexp) {
+  __builtin_amdgcn_s_setprio(kChainPrio);
   __shared__ cx<T> tp[8 * P];
   __shared__ cx<T> part[4 * 64];
   for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) tp[i] = mkc<T>((T)tau[i].x, (T)tau[i].y);
@@ -334,6 +342,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l(int g0, int nbox, const int *__r
                                                const double2 *__restrict__ Dpow,
                                                const double2 *__restrict__ Mexp,
                                                double2 *__restrict__ Lexp) {
+  __builtin_amdgcn_s_setprio(kChainPrio);
   using S = M2lShape<P>;
   constexpr int RT = S::RT, KS = S::KS, DP = S::DP;
   __shared__ double lds[S::LDS];
@@ -766,6 +775,7 @@ __global__ __launch_bounds__(64) void k_l2p_laplace(
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ ev_start, const int *__restrict__ ev_leaf,
     const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
+  __builtin_amdgcn_s_setprio(kChainPrio);
   extern __shared__ char l2p_lds[];
   cx<T> *cf = reinterpret_cast<cx<T> *>(l2p_lds);
   const int c = blockIdx.x, r = blockIdx.y;
@@ -805,6 +815,7 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ ev_start, const int *__restrict__ ev_leaf,
     const double2 *__restrict__ Lexp, double *__restrict__ out) {
+  __builtin_amdgcn_s_setprio(kChainPrio);
   extern __shared__ char l2p_lds[];
   double2 *cf = reinterpret_cast<double2 *>(l2p_lds);  // sets A, B, C of every staged ancestor
   const int c = blockIdx.x, r = blockIdx.y;
