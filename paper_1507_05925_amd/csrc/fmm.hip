@@ -325,13 +325,14 @@ struct M2lShape {
   static constexpr int RED = 4 * RT * 4 * 2 * 64;
   static constexpr int LDS = TABLE > RED ? TABLE : RED;
 };
-// whether an item's sources are loaded during the previous item's products (two waves per SIMD
-// hold the extra registers up to order 48)
+// whether an item's sources are loaded during the previous item's products: the extra registers
+// leave two workgroups per CU (up to order 40); otherwise items run one after another in fewer
+// registers, three workgroups per CU
 template <int P>
-constexpr bool kM2lPrefetch = P <= 48;
+constexpr bool kM2lPrefetch = P <= 40;
 
 template <int P>
-__global__ __launch_bounds__(256, 2) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
+__global__ __launch_bounds__(256, kM2lPrefetch<P> ? 2 : 3) void k_m2l(int g0, int nbox, const int *__restrict__ grp_ptr,
                                                const int *__restrict__ grp_tgt,
                                                const int *__restrict__ grp_lvl,
                                                const int *__restrict__ item_off,
@@ -360,48 +361,10 @@ __global__ __launch_bounds__(256, 2) void k_m2l(int g0, int nbox, const int *__r
     for (int r = 0; r < 4; ++r) br[t][r] = bi[t][r] = 0.0;
   const double2 *Ms = Mexp + (size_t)set * nbox * P;
   const int i0 = grp_ptr[g], i1 = grp_ptr[g + 1];
-  // software pipeline over the wave's items it = i0 + w, i0 + w + 4, ...: the sources of the
-  // next item are loaded before this item's products (up to order 48; above, the registers do
-  // not allow it and they are loaded after) and pre-scaled after them; the indices run one item
-  // further ahead. This lane's sources are u_src[m], m = 4 kk + q; a missing source reads box 0,
-  // then zeros.
-  int it = i0 + w;
-  int s1 = -1, o1 = 0, s2 = -1, o2 = 0;  // (source, offset) of items it, it + 4
-  if (it < i1) { s1 = item_src[it * 16 + j]; o1 = item_off[it]; }
-  if (it + 4 < i1) { s2 = item_src[(it + 4) * 16 + j]; o2 = item_off[it + 4]; }
-  double bre[KS], bim[KS];
-  double2 un[KS];
-  __syncthreads();
-  if (it < i1) {
-    const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
-    const double2 *dp = dps + o1 * DP;
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const double2 u = up[4 * kk];
-      const double2 pw = dp[4 * kk + q];  // d^-m
-      const double ur = s1 < 0 ? 0.0 : u.x, ui = s1 < 0 ? 0.0 : u.y;
-      bre[kk] = fma(ur, pw.x, -ui * pw.y);
-      bim[kk] = fma(ur, pw.y, ui * pw.x);
-    }
-  }
-  for (; it < i1; it += 4) {
-    const int o = o1;
-    const double2 *dp = dps + o * DP;
-    s1 = s2; o1 = o2;  // item it + 4
-    const bool more = it + 4 < i1;
-    if constexpr (kM2lPrefetch<P>)
-      if (more) {
-        const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
-#pragma unroll
-        for (int kk = 0; kk < KS; ++kk) un[kk] = up[4 * kk];
-      }
-    if (it + 8 < i1) { s2 = item_src[(it + 8) * 16 + j]; o2 = item_off[it + 8]; }
-    // one row tile at a time: the real and imaginary products, then the scaling by d^-(n+1).
-    // A[n][m] = C[n + m]; rows n >= P (the last tile's padding) hold finite values that are
-    // never written out. The entries are read from LDS per item (an opaque zero keeps the
-    // compiler from holding all of them in registers across items).
-    int zoff = 0;
-    asm volatile("" : "+v"(zoff));
+  // one item's products: one row tile at a time, the real and imaginary products, then the
+  // scaling by d^-(n+1) into the accumulators. A[n][m] = C[n + m]; rows n >= P (the last
+  // tile's padding) hold finite values that are never written out.
+  auto products = [&](const double *bre, const double *bim, const double2 *dp, int zoff) {
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const double *ca = cs + 16 * t + j + q + zoff;
@@ -419,20 +382,64 @@ __global__ __launch_bounds__(256, 2) void k_m2l(int g0, int nbox, const int *__r
         bi[t][r] = fma(yr[r], pw.y, fma(yi[r], pw.x, bi[t][r]));
       }
     }
-    if (more) {
-      if constexpr (!kM2lPrefetch<P>) {
+  };
+  // this lane's sources u_src[m], m = 4 kk + q, scaled by d^-m; a missing source (src < 0)
+  // reads box 0, then zeros
+  auto prescale = [&](const double2 *u, int src, const double2 *dp, double *bre, double *bim) {
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const double2 pw = dp[4 * kk + q];  // d^-m
+      const double ur = src < 0 ? 0.0 : u[kk].x, ui = src < 0 ? 0.0 : u[kk].y;
+      bre[kk] = fma(ur, pw.x, -ui * pw.y);
+      bim[kk] = fma(ur, pw.y, ui * pw.x);
+    }
+  };
+  __syncthreads();
+  if constexpr (kM2lPrefetch<P>) {
+    // software pipeline over the wave's items it = i0 + w, i0 + w + 4, ...: the sources of the
+    // next item are loaded before this item's products and pre-scaled after them; the indices
+    // run one item further ahead
+    int it = i0 + w;
+    int s1 = -1, o1 = 0, s2 = -1, o2 = 0;  // (source, offset) of items it, it + 4
+    if (it < i1) { s1 = item_src[it * 16 + j]; o1 = item_off[it]; }
+    if (it + 4 < i1) { s2 = item_src[(it + 4) * 16 + j]; o2 = item_off[it + 4]; }
+    double bre[KS], bim[KS];
+    double2 un[KS];
+    if (it < i1) {
+      const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) un[kk] = up[4 * kk];
+      prescale(un, s1, dps + o1 * DP, bre, bim);
+    }
+    for (; it < i1; it += 4) {
+      const double2 *dp = dps + o1 * DP;
+      s1 = s2; o1 = o2;  // item it + 4
+      const bool more = it + 4 < i1;
+      if (more) {
         const double2 *up = Ms + (size_t)max(s1, 0) * P + q;
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) un[kk] = up[4 * kk];
       }
-      const double2 *dq = dps + o1 * DP;
+      if (it + 8 < i1) { s2 = item_src[(it + 8) * 16 + j]; o2 = item_off[it + 8]; }
+      // the C entries are read from LDS per item (an opaque zero keeps the compiler from
+      // holding all of them in registers across items)
+      int zoff = 0;
+      asm volatile("" : "+v"(zoff));
+      products(bre, bim, dp, zoff);
+      if (more) prescale(un, s1, dps + o1 * DP, bre, bim);
+    }
+  } else {
+    // one item after another: its sources, their scaling, the products
+    for (int it = i0 + w; it < i1; it += 4) {
+      const int src = item_src[it * 16 + j];
+      const double2 *dp = dps + item_off[it] * DP;
+      const double2 *up = Ms + (size_t)max(src, 0) * P + q;
+      double2 u[KS];
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        const double2 pw = dq[4 * kk + q];  // d^-m
-        const double ur = s1 < 0 ? 0.0 : un[kk].x, ui = s1 < 0 ? 0.0 : un[kk].y;
-        bre[kk] = fma(ur, pw.x, -ui * pw.y);
-        bim[kk] = fma(ur, pw.y, ui * pw.x);
-      }
+      for (int kk = 0; kk < KS; ++kk) u[kk] = up[4 * kk];
+      double bre[KS], bim[KS];
+      prescale(u, src, dp, bre, bim);
+      products(bre, bim, dp, 0);
     }
   }
   __syncthreads();  // the tables are no longer read: their LDS holds the partial sums
