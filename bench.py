@@ -44,6 +44,8 @@ FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), 
 FLOPS_PER_CMAC = 8   # complex multiply-add
 
 
+PROFILE_EVERY = 8  # launches per timed launch of the roofline kernel in the timed solves
+
 def m2l_flops_per_entry(p):
     """One M2L interaction-list entry as the kernel computes it: the source scaled by d^-m
     (p complex products, 6 flops each), the real Hankel matrix C (p x p) applied to its real and
@@ -476,7 +478,10 @@ def main():
     c = classes[dom]
     torch.cuda.synchronize()
 
+    # events around every 8th launch of that class only: each event marker leaves the stream idle
+    # for a few microseconds, which would otherwise lengthen the timed solves
     bie2d.bie_profile_select([c[0]])
+    bie2d.bie_profile_sample(PROFILE_EVERY)
     bie2d.bie_profile_enable(True)
     lat, pairs, info = [], 0, None
     t0 = time.perf_counter()
@@ -489,7 +494,9 @@ def main():
     elapsed = time.perf_counter() - t0
     rl = roofline(bie2d.bie_profile_read(c[0]), c[0], c[1], c[2], bound=c[3], kernel=c[4])
     rl["kernel"] = c[4]
+    rl["sampled_every"] = PROFILE_EVERY
     bie2d.bie_profile_enable(False)
+    bie2d.bie_profile_sample(1)
     # the matrix-core kernel (M2L) on its own, from one more solve that times only that class
     cm = classes["k_m2l"]
     bie2d.bie_profile_select([cm[0]])

@@ -296,7 +296,10 @@ int bie_server_destroy(bie_server *srv);
  * bie_profile_enable(1) clears the counters; bie_profile_read() waits for the recorded events
  * of that class and returns the totals. bie_profile_select(mask) limits the recording to the
  * classes whose bit (1 << class) is set (default: all), so that timing one class adds no events
- * around the others. Process-wide; not thread safe. */
+ * around the others. bie_profile_sample(every) records only every every-th launch of each class
+ * (default 1, every launch; every < 1 is BIE_EINVAL): an event marker on a stream leaves the GPU
+ * idle for a few microseconds, so sampling keeps the timed work close to an unprofiled run; the
+ * launch count and the totals then cover the sampled launches. Process-wide; not thread safe. */
 #define BIE_K_FAR_LAPLACE_F32 0 /* float32 far-field sweep, Laplace            */
 #define BIE_K_FAR_LAPLACE_F64 1 /* float64 far-field sweep, Laplace            */
 #define BIE_K_FAR_STOKES_F32 2  /* float32 far-field sweep, Stokes             */
@@ -309,6 +312,7 @@ int bie_server_destroy(bie_server *srv);
 #define BIE_K_COUNT 9
 int bie_profile_enable(int on);
 int bie_profile_select(unsigned mask);
+int bie_profile_sample(int every);
 int bie_profile_read(int kclass, long long *launches, double *ms_total, long long *pairs);
 
 #ifdef __cplusplus

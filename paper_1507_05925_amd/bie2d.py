@@ -91,6 +91,7 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_server_destroy": ([_P], _I),
     "bie_profile_enable": ([_I], _I),
+    "bie_profile_sample": ([ctypes.c_int], _I),
     "bie_profile_select": ([ctypes.c_uint], _I),
     "bie_profile_read": ([_I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_longlong)], _I),
@@ -109,6 +110,11 @@ def bie_profile_select(classes=None):
     """Record only the given kernel classes (None: all)."""
     mask = 0xFFFFFFFF if classes is None else sum(1 << int(k) for k in classes)
     _check(lib().bie_profile_select(mask))
+
+
+def bie_profile_sample(every=1):
+    """Record events around every `every`-th launch of each class only."""
+    _check(lib().bie_profile_sample(int(every)))
 
 
 def bie_profile_read(kclass):

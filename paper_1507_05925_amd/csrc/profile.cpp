@@ -22,6 +22,8 @@ struct ClassStats {
 
 bool g_on = false;
 unsigned g_mask = ~0u;
+int g_every = 1;                        // record every g_every-th launch of a class
+long long g_seen[BIE_K_COUNT] = {};      // launches of each class while enabled
 ClassStats g_stats[BIE_K_COUNT];
 std::vector<hipEvent_t> g_pool;
 
@@ -55,6 +57,8 @@ int drain(ClassStats &c) {
 
 ProfScope::ProfScope(int k, hipStream_t st, long long p)
     : kclass(k), s(st), pairs(p), on(g_on && ((g_mask >> k) & 1u)) {
+  if (!on) return;
+  on = g_seen[k]++ % g_every == 0;
   if (!on) return;
   hipEvent_t a = get_event();
   if (!a) {
@@ -90,11 +94,21 @@ int bie_profile_enable(int on) {
     c = ClassStats();
   }
   g_on = on != 0;
+  for (auto &n : g_seen) n = 0;
   return BIE_OK;
 }
 
 int bie_profile_select(unsigned mask) {
   g_mask = mask;
+  return BIE_OK;
+}
+
+int bie_profile_sample(int every) {
+  if (every < 1) {
+    set_error("bie_profile_sample: every must be at least 1");
+    return BIE_EINVAL;
+  }
+  g_every = every;
   return BIE_OK;
 }
 
