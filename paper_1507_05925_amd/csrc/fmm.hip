@@ -651,7 +651,7 @@ __device__ __forceinline__ void near_seg(const double4 *buf, int n, int g, doubl
 // LDS records per workgroup (a multiple of 32). A leaf whose runs hold at most this many records
 // (after padding) has them all staged at once, back to back: one load latency and one barrier.
 // Larger neighbourhoods are read run by run in blocks of this size.
-constexpr int kNearCap = 1024;
+constexpr int kNearCap = 512;
 
 // Copies n records src[0 .. n) to buf[at ..], then zero-weight padding up to a multiple of 32
 // records; returns the padded count.
