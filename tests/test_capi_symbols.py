@@ -29,3 +29,10 @@ def test_default_opts_and_errors_without_gpu():
     rc = L.bie_geom_create(1, npb.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(8), None, None,
                            ctypes.byref(h))
     assert rc == bie2d.BIE_EINVAL and b"fewer than 3" in L.bie_last_error()
+
+
+def test_profile_sample_argument_check_without_gpu():
+    L = bie2d.lib()
+    assert L.bie_profile_sample(0) == bie2d.BIE_EINVAL
+    assert b"at least 1" in L.bie_last_error()
+    assert L.bie_profile_sample(1) == bie2d.BIE_OK

@@ -43,13 +43,50 @@ def test_fmm_error_decays_with_order(kind):
         f = bie2d.bie_laplace_apply if kind == "laplace" else bie2d.bie_stokes_apply
         ref = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_DIRECT)
         errs = []
-        for p in (12, 20, 28, 40, 52):
+        for p in (12, 20, 28, 40, 52, 64):  # expansion lengths 16 .. 64 (every M2L code path)
             g.set_fmm(p, 48)
             out = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
             errs.append(float((out - ref).abs().max() / ref.abs().max()))
-        assert errs[-1] < 1e-12, (name, errs)
+        assert errs[-1] < 1e-12 and errs[-2] < 1e-12, (name, errs)
         assert errs[3] < 1e-10, (name, errs)
         assert errs[0] > 10 * errs[2], (name, errs)  # converging, not accidentally exact
+
+
+@pytest.mark.parametrize("kind", ["laplace", "stokes"])
+def test_fmm_large_leaves(kind):
+    """Leaves of about 200 nodes: neighbourhoods of more than 512 source records, which the near
+    field reads run by run in blocks (the path the default leaf size rarely takes)."""
+    rng = np.random.default_rng(7)
+    c = _cases()["starfish100"]
+    g = bie2d.Geometry.from_curves(c)
+    n = g.M if kind == "laplace" else 2 * g.M
+    mu = dev(rng.standard_normal((2, n)))
+    f = bie2d.bie_laplace_apply if kind == "laplace" else bie2d.bie_stokes_apply
+    ref = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_DIRECT)
+    g.set_fmm(40, 200)
+    out = f(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
+    assert float((out - ref).abs().max() / ref.abs().max()) < 1e-10
+
+
+def test_profile_sampling():
+    """bie_profile_sample(3): events around launches 0, 3, 6 of a class only."""
+    c = _cases()["starfish100"]
+    g = bie2d.Geometry.from_curves(c)
+    g.set_fmm(40, 48)
+    mu = dev(np.random.default_rng(8).standard_normal((1, g.M)))
+    bie2d.bie_laplace_apply(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
+    try:
+        bie2d.bie_profile_select([bie2d.BIE_K_FMM_M2L])
+        bie2d.bie_profile_sample(3)
+        bie2d.bie_profile_enable(True)
+        for _ in range(7):
+            bie2d.bie_laplace_apply(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
+        r = bie2d.bie_profile_read(bie2d.BIE_K_FMM_M2L)
+        assert r["launches"] == 3 and r["ms_total"] > 0, r
+    finally:
+        bie2d.bie_profile_enable(False)
+        bie2d.bie_profile_sample(1)
+        bie2d.bie_profile_select(None)
 
 
 @pytest.mark.parametrize("kind", ["laplace", "stokes"])
