@@ -666,9 +666,11 @@ __device__ __forceinline__ int near_stage(const double4 *__restrict__ src, int n
 // Near field: grid (target chunks, R), 256 threads. Laplace writes -(1/2pi) n.(sum over the
 // neighbour leaves, k != i, of s_k r/|r|^2); Stokes writes -(1/pi) sum over the neighbour leaves,
 // k != i, of (r.n)(r.rho_k) r/|r|^4 (two components per node). Waves without targets (busy false,
-// uniform over the wave) take part in the copies and barriers only.
+// uniform over the wave) take part in the copies and barriers only. At least five waves per
+// SIMD (at most 102 VGPRs instead of 104): the kernel shares the compute units with the
+// expansion chain, and its smaller register footprint leaves room for the chain's waves.
 template <bool STOKES>
-__global__ __launch_bounds__(256) void k_near(
+__global__ __launch_bounds__(256, 5) void k_near(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
     const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ run_ptr, const int2 *__restrict__ run,
