@@ -209,26 +209,41 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
 #pragma unroll
   for (int k = 0; k < NB; ++k) acc[k] = mkc<T>(0, 0);
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  for (int j = j0 + g; j < j1; j += 8) {
-    const double2 z = xs[j];  // leaf-relative coordinates formed in float64
-    const cx<T> w = mkc<T>((T)((z.x - c.x) * inv_h), (T)((z.y - c.y) * inv_h));
-    cx<T> wb = w;  // w^NB
+  // 64 sources at a time: every load of the batch is issued before the first product (lanes past
+  // the leaf's end take the leaf's first coordinate and a zero charge, so they add zero)
+  for (int jb = j0; jb < j1; jb += 64) {
+    double2 zz[8];
+    cx<T> qq[8];
 #pragma unroll
-    for (int k = 1; k < NB; ++k) wb = cmul(wb, w);
-    cx<T> t = q[j];  // q w^(b NB), by squaring over the three bits of b
-#pragma unroll
-    for (int bit = 0; bit < 3; ++bit) {
-      const cx<T> tw = cmul(t, wb);
-      const bool use = (b >> bit) & 1;  // per component (a select of the pair is not)
-      t.x = use ? tw.x : t.x;
-      t.y = use ? tw.y : t.y;
-      wb = cmul(wb, wb);
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + g + 8 * u;
+      const bool ok = j < j1;
+      zz[u] = xs[ok ? j : j0];
+      qq[u] = ok ? q[j] : mkc<T>(0, 0);
     }
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      acc[k].x += t.x;
-      acc[k].y += t.y;
-      t = cmul(t, w);
+    for (int u = 0; u < 8; ++u) {
+      if (jb + 8 * u >= j1) break;  // uniform over the wave
+      // leaf-relative coordinates formed in float64
+      const cx<T> w = mkc<T>((T)((zz[u].x - c.x) * inv_h), (T)((zz[u].y - c.y) * inv_h));
+      cx<T> wb = w;  // w^NB
+#pragma unroll
+      for (int k = 1; k < NB; ++k) wb = cmul(wb, w);
+      cx<T> t = qq[u];  // q w^(b NB), by squaring over the three bits of b
+#pragma unroll
+      for (int bit = 0; bit < 3; ++bit) {
+        const cx<T> tw = cmul(t, wb);
+        const bool use = (b >> bit) & 1;  // per component (a select of the pair is not)
+        t.x = use ? tw.x : t.x;
+        t.y = use ? tw.y : t.y;
+        wb = cmul(wb, wb);
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        acc[k].x += t.x;
+        acc[k].y += t.y;
+        t = cmul(t, w);
+      }
     }
   }
 #pragma unroll
@@ -744,8 +759,9 @@ constexpr int kEvalLeaves = 4;
 
 // Copies the ancestor coefficients of a chunk whose first and last leaves have the ancestor lists
 // a0 and a1 ([nlev] each): per set k < nsets_here (from set0),
-// cf[(k * nslot + off_i + b) * P + n] = Lexp[set0 + k][lo_i + b][n].
-template <int P, class T>
+// cf[(k * nslot + off_i + b) * P + n] = Lexp[set0 + k][lo_i + b][n]. With DERIV_LAST the last set
+// is staged as the coefficients of its derivative in w, (n + 1) Lexp[..][n + 1] (0 for n = P - 1).
+template <int P, class T, bool DERIV_LAST = false>
 __device__ __forceinline__ void stage_levels(const int *a0, const int *a1, int nlev, int nbox,
                                              int set0, int nsets_here, int nslot,
                                              const cx<T> *__restrict__ Lexp, cx<T> *cf) {
@@ -755,7 +771,15 @@ __device__ __forceinline__ void stage_levels(const int *a0, const int *a1, int n
     for (int k = 0; k < nsets_here; ++k) {
       const cx<T> *src = Lexp + ((size_t)(set0 + k) * nbox + lo) * P;
       cx<T> *dst = cf + ((size_t)k * nslot + off) * P;
-      for (int e = threadIdx.x; e < cnt * P; e += 64) dst[e] = src[e];
+      if (DERIV_LAST && k == nsets_here - 1) {
+        for (int e = threadIdx.x; e < cnt * P; e += 64) {
+          const int n = e % P;
+          const T f = (T)(n + 1);
+          dst[e] = n < P - 1 ? mkc<T>(f * src[e + 1].x, f * src[e + 1].y) : mkc<T>(0, 0);
+        }
+      } else {
+        for (int e = threadIdx.x; e < cnt * P; e += 64) dst[e] = src[e];
+      }
     }
     off += cnt;
   }
@@ -833,14 +857,14 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
   int lf1;
   const int nslot = chunk_leaves(leaf_start, leaf_anc, nlev, lf0, j1, lf1);
   const int *a0 = leaf_anc + (size_t)lf0 * nlev, *a1 = leaf_anc + (size_t)lf1 * nlev;
-  stage_levels<P, double>(a0, a1, nlev, nbox, 3 * r, 3, nslot, Lexp, cf);
+  stage_levels<P, double, true>(a0, a1, nlev, nbox, 3 * r, 3, nslot, Lexp, cf);
   const int j = j0 + threadIdx.x;
   if (j >= j1) return;
   int lf = lf0;
   while (leaf_start[lf + 1] <= j) ++lf;
   const int *anc = leaf_anc + (size_t)lf * nlev;
   const double2 z = xs[j], nv = nrm[j];
-  double2 A = make_double2(0.0, 0.0), dA = A, B = A, C = A, dC = A;
+  double2 A = make_double2(0.0, 0.0), dA = A, B = A, dC = A;
   double ih = ih_leaf;
   for (int i = 0, off = 0; i < nlev; ++i) {  // ancestors, as in the Laplace evaluation
     const int b = anc[i];
@@ -848,14 +872,15 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
     const double2 w = make_double2((z.x - cc.x) * ih, (z.y - cc.y) * ih);
     const size_t sl = (size_t)(off + b - a0[i]);
     off += a1[i] - a0[i] + 1;
-    double2 Al, dAl, Cl, dCl;
+    double2 Al, dAl;
     eval_local<P>(cf + (0 * (size_t)nslot + sl) * P, w, ih, Al, dAl);
     const double2 Bl = eval_value<P>(cf + (1 * (size_t)nslot + sl) * P, w);
-    eval_local<P>(cf + (2 * (size_t)nslot + sl) * P, w, ih, Cl, dCl);
+    // C enters through its derivative only: staged as derivative coefficients (P - 1 terms)
+    const double2 dCw = eval_value<P - 1>(cf + (2 * (size_t)nslot + sl) * P, w);
+    const double2 dCl = make_double2(dCw.x * ih, dCw.y * ih);
     A = make_double2(A.x + Al.x, A.y + Al.y);
     dA = make_double2(dA.x + dAl.x, dA.y + dAl.y);
     B = make_double2(B.x + Bl.x, B.y + Bl.y);
-    C = make_double2(C.x + Cl.x, C.y + Cl.y);
     dC = make_double2(dC.x + dCl.x, dC.y + dCl.y);
     ih *= 0.5;
   }
@@ -1461,8 +1486,12 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   FmmPlan &plan = *g->fmm;
   if (!plan.side) {  // side stream for the near field (default priority) and its fork/join events
     BIE_HIP_CHECK(hipStreamCreateWithFlags(&plan.side, hipStreamNonBlocking));
-    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.fork, hipEventDisableTiming));
-    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, hipEventDisableTiming));
+    // both streams are on one device: a device-scope release suffices, and the default
+    // system-scope fence of the event marker (a cache write-back and invalidation) would leave
+    // the stream idle for several microseconds at every fork and join
+    constexpr unsigned kFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.fork, kFlags));
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, kFlags));
   }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
   hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, g->w,

@@ -603,10 +603,12 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
   }
   if (gseen.empty()) return BIE_OK;
   if (!P->fork) {
-    BIE_HIP_CHECK(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
+    // all streams are on one device: no system-scope fence at the event markers
+    constexpr unsigned kFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+    BIE_HIP_CHECK(hipEventCreateWithFlags(&P->fork, kFlags));
     for (int k = 0; k < kFmmStreams; ++k) {
       BIE_HIP_CHECK(hipStreamCreateWithFlags(&P->pool[k], hipStreamNonBlocking));
-      BIE_HIP_CHECK(hipEventCreateWithFlags(&P->join[k], hipEventDisableTiming));
+      BIE_HIP_CHECK(hipEventCreateWithFlags(&P->join[k], kFlags));
     }
   }
   const int used = (int)std::min<size_t>(gseen.size(), kFmmStreams);

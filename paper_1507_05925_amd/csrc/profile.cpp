@@ -34,7 +34,9 @@ hipEvent_t get_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing only: no system-scope fence (a cache write-back) at the markers, which would add its
+  // own cost to the measured launches and to the work after them
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
