@@ -182,14 +182,15 @@ __device__ __forceinline__ float rl(float v, int l) {
 // and the near field takes the remaining issue slots (it stays at the default, 0).
 constexpr int kChainPrio = 3;
 
-// P2M: grid (leaves, nsets), one wave per leaf. Multipole coefficients of the leaf,
-// u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in). Lane
-// (g, b) = (lane % 8, lane / 8) takes the sources j = j0 + g, j0 + g + 8, ... and the P/8
+// P2M: grid (leaves, nsets / NS), one wave per leaf and NS charge sets. Multipole coefficients of
+// the leaf, u_n = (s^n/n!) sum_j q_j w_j^n with w_j = (z_j - c)/h and the table scale s (fact_in).
+// Lane (g, b) = (lane % 8, lane / 8) takes the sources j = j0 + g, j0 + g + 8, ... and the P/8
 // coefficients n = b P/8 .. (b + 1) P/8 - 1: per source it forms w^(b P/8) (w^(P/8) raised to b by
 // squaring) and the following powers by running products, accumulating in registers. The eight
 // lanes of each coefficient block are then added by three shuffle steps. Fixed order: the result
-// is reproducible.
-template <int P, class T>
+// is reproducible. With NS > 1 (the three charge sets of a Stokes right-hand side) the powers of
+// w are formed once per source for all NS sets.
+template <int P, class T, int NS>
 __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const int *__restrict__ leaf_start,
                                            const int *__restrict__ leaf_box,
@@ -199,67 +200,96 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const double *__restrict__ fact_in,
                                            cx<T> *__restrict__ Mexp) {
   __builtin_amdgcn_s_setprio(kChainPrio);
-  constexpr int NB = P / 8;  // coefficients per lane
-  const int leaf = blockIdx.x, set = blockIdx.y, lane = threadIdx.x;
+  constexpr int NB = P / 8;          // coefficients per lane
+  constexpr int U = NS == 1 ? 8 : 4;  // sources per lane in one batch of loads
+  const int leaf = blockIdx.x, set0 = blockIdx.y * NS, lane = threadIdx.x;
   const int g = lane & 7, b = lane >> 3;
   const int box = leaf_box[leaf];
   const double2 c = center[box];
-  const cx<T> *q = Q + (size_t)set * M;
-  cx<T> acc[NB];
+  cx<T> acc[NS][NB];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) acc[k] = mkc<T>(0, 0);
+  for (int e = 0; e < NS; ++e)
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[e][k] = mkc<T>(0, 0);
   const int j0 = leaf_start[leaf], j1 = leaf_start[leaf + 1];
-  // 64 sources at a time: every load of the batch is issued before the first product (lanes past
-  // the leaf's end take the leaf's first coordinate and a zero charge, so they add zero)
-  for (int jb = j0; jb < j1; jb += 64) {
-    double2 zz[8];
-    cx<T> qq[8];
+  // 8 U sources at a time: every load of the batch is issued before the first product (lanes
+  // past the leaf's end take the leaf's first coordinate and zero charges, so they add zero)
+  for (int jb = j0; jb < j1; jb += 8 * U) {
+    double2 zz[U];
+    cx<T> qq[U][NS];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int j = jb + g + 8 * u;
       const bool ok = j < j1;
       zz[u] = xs[ok ? j : j0];
-      qq[u] = ok ? q[j] : mkc<T>(0, 0);
+#pragma unroll
+      for (int e = 0; e < NS; ++e) qq[u][e] = ok ? Q[(size_t)(set0 + e) * M + j] : mkc<T>(0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (jb + 8 * u >= j1) break;  // uniform over the wave
       // leaf-relative coordinates formed in float64
       const cx<T> w = mkc<T>((T)((zz[u].x - c.x) * inv_h), (T)((zz[u].y - c.y) * inv_h));
       cx<T> wb = w;  // w^NB
 #pragma unroll
       for (int k = 1; k < NB; ++k) wb = cmul(wb, w);
-      cx<T> t = qq[u];  // q w^(b NB), by squaring over the three bits of b
+      cx<T> t[NS];
+      if constexpr (NS == 1) {
+        t[0] = qq[u][0];  // q w^(b NB), by squaring over the three bits of b
 #pragma unroll
-      for (int bit = 0; bit < 3; ++bit) {
-        const cx<T> tw = cmul(t, wb);
-        const bool use = (b >> bit) & 1;  // per component (a select of the pair is not)
-        t.x = use ? tw.x : t.x;
-        t.y = use ? tw.y : t.y;
-        wb = cmul(wb, wb);
+        for (int bit = 0; bit < 3; ++bit) {
+          const cx<T> tw = cmul(t[0], wb);
+          const bool use = (b >> bit) & 1;  // per component (a select of the pair is not)
+          t[0].x = use ? tw.x : t[0].x;
+          t[0].y = use ? tw.y : t[0].y;
+          wb = cmul(wb, wb);
+        }
+      } else {
+        cx<T> pw = mkc<T>(1, 0);  // w^(b NB), by squaring over the three bits of b
+#pragma unroll
+        for (int bit = 0; bit < 3; ++bit) {
+          const cx<T> tw = cmul(pw, wb);
+          const bool use = (b >> bit) & 1;
+          pw.x = use ? tw.x : pw.x;
+          pw.y = use ? tw.y : pw.y;
+          if (bit < 2) wb = cmul(wb, wb);
+        }
+#pragma unroll
+        for (int e = 0; e < NS; ++e) t[e] = cmul(qq[u][e], pw);
       }
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
-        acc[k].x += t.x;
-        acc[k].y += t.y;
-        t = cmul(t, w);
+#pragma unroll
+        for (int e = 0; e < NS; ++e) {
+          acc[e][k].x += t[e].x;
+          acc[e][k].y += t[e].y;
+        }
+        if (k + 1 < NB) {
+#pragma unroll
+          for (int e = 0; e < NS; ++e) t[e] = cmul(t[e], w);
+        }
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
+  for (int e = 0; e < NS; ++e)
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-      acc[k].x += __shfl_xor(acc[k].x, off, 64);
-      acc[k].y += __shfl_xor(acc[k].y, off, 64);
-    }
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        acc[e][k].x += __shfl_xor(acc[e][k].x, off, 64);
+        acc[e][k].y += __shfl_xor(acc[e][k].y, off, 64);
+      }
   if (g == 0) {
-    cx<T> *o = Mexp + ((size_t)set * nbox + box) * P;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int n = NB * b + k;
-      const T f = (T)fact_in[n];
-      o[n] = mkc<T>(acc[k].x * f, acc[k].y * f);
+    for (int e = 0; e < NS; ++e) {
+      cx<T> *o = Mexp + ((size_t)(set0 + e) * nbox + box) * P;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int n = NB * b + k;
+        const T f = (T)fact_in[n];
+        o[n] = mkc<T>(acc[e][k].x * f, acc[e][k].y * f);
+      }
     }
   }
 }
@@ -1391,8 +1421,17 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
                      const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
                      Near &&launch_near) {
   const int M = t.M;
-  hipLaunchKernelGGL((k_p2m<P, T>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox, ih_leaf,
-                     t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
+  bool p2m_done = false;
+  if constexpr (std::is_same<T, double>::value) {
+    if (kind != 0 && nsets % 3 == 0) {  // Stokes: the three sets of a right-hand side in one wave
+      hipLaunchKernelGGL((k_p2m<P, T, 3>), dim3(t.nleaf, nsets / 3), dim3(64), 0, s, M, t.nbox,
+                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
+      p2m_done = true;
+    }
+  }
+  if (!p2m_done)
+    hipLaunchKernelGGL((k_p2m<P, T, 1>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox,
+                       ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
   for (int l = t.L - 1; l >= 2; --l) {
     const int nb = t.level_off[l + 1] - t.level_off[l];
     if (nb > 0)
