@@ -165,7 +165,6 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
   }
 }
 
-// P2M at the leaves: grid (nleaf, nsets), one lane per coefficient.
 // Wave-uniform read of lane l's value (l a compile-time or uniform index).
 __device__ __forceinline__ double rl(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
