@@ -176,3 +176,22 @@ def test_fmm_full_size_mobility(precision, tol):
     ref = np.asarray(gold["VW"]).reshape(-1, 3)
     for a, b in ((VW[:, :2], ref[:, :2]), (VW[:, 2], ref[:, 2])):
         assert float(np.abs(a - b).max() / np.abs(b).max()) < tol, info
+
+
+@pytest.mark.parametrize("kind", ["laplace", "stokes"])
+def test_fmm_back_to_back_applies_repeat(kind):
+    """The near field runs on a second stream joined to the expansion chain by events: applies
+    queued back to back, with alternating inputs and no host synchronisation between them, must
+    reproduce each other bit for bit (a missing dependency would let the evaluation or the next
+    apply's gather overlap the near field)."""
+    c = wl.elastance_starfish()[0] if kind == "laplace" else wl.mobility_ellipses()[0]
+    g = bie2d.Geometry.from_curves(c)
+    n = g.M if kind == "laplace" else 2 * g.M
+    apply = bie2d.bie_laplace_apply if kind == "laplace" else bie2d.bie_stokes_apply
+    rng = np.random.default_rng(21)
+    mu = [dev(rng.standard_normal((1, n))) for _ in range(2)]
+    outs = [apply(g, mu[k % 2], bie2d.BIE_FP64, bie2d.BIE_FMM) for k in range(6)]
+    torch.cuda.synchronize()
+    for k in range(2, 6):
+        assert torch.equal(outs[k], outs[k % 2]), k
+    assert not torch.equal(outs[0], outs[1])
