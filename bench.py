@@ -21,6 +21,8 @@ Other workloads (not the default line):
                      continuous batching at 0.7 x the measured saturation rate; p50/p99
                      latency and solves/s next to the plain float64 GPU path (one solve at a
                      time, FIFO, same arrival times).
+  --workload mobility 200 rigid ellipses x 512 nodes (204,800 unknowns), FMM: solves in float64
+                     and in the mixed mode, (v, omega) against the stored float64 oracle solution.
   --workload batched 32 geometries of 8-128 bodies: every P and M in one batched solve.
   --workload nanocomposite  every configuration of the paper's nanocomposite capacitance table
                      (two plates and m x 10 particles, m = 0, 1, 4, 16, five aspect ratios): the
@@ -45,6 +47,7 @@ FLOPS_PER_CMAC = 8   # complex multiply-add
 
 
 PROFILE_EVERY = 8  # launches per timed launch of the roofline kernel in the timed solves
+
 
 def m2l_flops_per_entry(p):
     """One M2L interaction-list entry as the kernel computes it: the source scaled by d^-m
