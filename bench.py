@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X vector TFLOP/s (float64 MFMA: also 78.6)
 FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), scale (1), 2 fma (4)
 FLOPS_PER_CMAC = 8   # complex multiply-add
+FLOPS_PER_PAIR_STOKES = 19  # stresslet kernel per node pair (two components)
 
 
 PROFILE_EVERY = 8  # launches per timed launch of the roofline kernel in the timed solves
@@ -365,6 +366,24 @@ def mobility_bench(a):
             r["rel_err_omega_vs_fp64_oracle"] = float(np.abs(v[:, 2] - ref[:, 2]).max()
                                                       / np.abs(ref[:, 2]).max())
         runs[name] = r
+    # the float64 order-40 kernels timed with HIP events over one more solve, each class in a
+    # solve of its own: the M2L (three charge sets per right-hand side) and the Stokes near field
+    o = bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
+                           max_iter=2000)
+    rls = {}
+    for key, kc, flops, bound, kern in (
+            ("roofline_m2l", bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(40), "mfma", "k_m2l<40>"),
+            ("roofline_near", bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR_STOKES, "alu", "k_near<true>")):
+        bie2d.bie_profile_select([kc])
+        bie2d.bie_profile_enable(True)
+        bie2d.bie_mobility_solve(g, ft, o)
+        torch.cuda.synchronize()
+        # (kernel=None: the committed traffic counters were taken on the elastance workload)
+        rl = roofline(bie2d.bie_profile_read(kc), kc, flops, "f64", bound=bound, kernel=None)
+        rl["kernel"] = kern
+        rls[key] = rl
+        bie2d.bie_profile_enable(False)
+    bie2d.bie_profile_select(None)
     g.close()
     best = max(runs, key=lambda k: runs[k]["solves_per_s"])
     print(json.dumps({
@@ -378,7 +397,7 @@ def mobility_bench(a):
         "config": {"workload": "mobility, 200 ellipses (aspect 1..3, gaps >= 0.2) x 512 nodes "
                                "(204,800 unknowns), FMM, GMRES tol %g" % a.tol,
                    "fastest": best},
-        "runs": runs}))
+        "runs": runs, **rls}))
 
 
 def crosstest_bench(a):
