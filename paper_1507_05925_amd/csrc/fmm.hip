@@ -175,6 +175,16 @@ __device__ __forceinline__ float rl(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Launch order to XCD-contiguous work: consecutive workgroups go round-robin to the eight XCDs,
+// each with its own L2. Workgroup i (of n along x) takes item (i % 8) * q + min(i % 8, r) + i / 8
+// (q = n / 8, r = n % 8), so each XCD works through one contiguous range of items, and items
+// that share inputs (neighbouring leaves and boxes in Morton order) share its L2. A bijection
+// on [0, n).
+__device__ __forceinline__ int xcd_item(int i, int n) {
+  const int q = n >> 3, r = n & 7, x = i & 7;
+  return x * q + min(x, r) + (i >> 3);
+}
+
 // Wave priority of the expansion chain (P2M, M2M, M2L, evaluation). The near field runs on a
 // second stream beside the chain and shares its compute units; at equal priority it slows the
 // chain's latency-bound kernels. Raised, the chain's waves issue first where both are resident
@@ -713,6 +723,8 @@ __device__ __forceinline__ int near_stage(const double4 *__restrict__ src, int n
 // uniform over the wave) take part in the copies and barriers only. At least five waves per
 // SIMD (at most 102 VGPRs instead of 104): the kernel shares the compute units with the
 // expansion chain, and its smaller register footprint leaves room for the chain's waves.
+// Chunks are taken in XCD-contiguous order (xcd_item): neighbouring leaves, which stage mostly
+// the same source records, then run on one XCD and share its L2.
 template <bool STOKES>
 __global__ __launch_bounds__(256, 5) void k_near(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
@@ -720,10 +732,11 @@ __global__ __launch_bounds__(256, 5) void k_near(
     const int *__restrict__ run_ptr, const int2 *__restrict__ run,
     const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
     const double4 *__restrict__ S4, double *__restrict__ out) {
-  const int leaf = chunk_leaf[blockIdx.x], r = blockIdx.y;
+  const int cb = xcd_item(blockIdx.x, gridDim.x);
+  const int leaf = chunk_leaf[cb], r = blockIdx.y;
   const int j1 = leaf_start[leaf + 1];
   const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int t0 = chunk_start[blockIdx.x] + 16 * (threadIdx.x >> 6);  // the wave's first target
+  const int t0 = chunk_start[cb] + 16 * (threadIdx.x >> 6);  // the wave's first target
   const int j = t0 + (lane & 15);
   const bool valid = j < j1, busy = t0 < j1;
   const int jj = valid ? j : t0;
