@@ -841,6 +841,8 @@ __device__ __forceinline__ int chunk_leaves(const int *__restrict__ leaf_start,
   return nslot;
 }
 
+// Both evaluation kernels take their chunks in XCD-contiguous order (xcd_item): sibling leaves,
+// which stage the same ancestors, then share one XCD's L2.
 // L2P, Laplace: adds -(1/2pi) Re(nu F(z)). Grid (evaluation chunks, R); dynamic LDS:
 // ev_maxslot P coefficients.
 template <int P, class T>
@@ -853,7 +855,7 @@ __global__ __launch_bounds__(64) void k_l2p_laplace(
   __builtin_amdgcn_s_setprio(kChainPrio);
   extern __shared__ char l2p_lds[];
   cx<T> *cf = reinterpret_cast<cx<T> *>(l2p_lds);
-  const int c = blockIdx.x, r = blockIdx.y;
+  const int c = xcd_item(blockIdx.x, gridDim.x), r = blockIdx.y;
   const int j0 = ev_start[c], j1 = ev_start[c + 1], lf0 = ev_leaf[c];
   const int nlev = L - 1;  // ancestor lists: levels L, L - 1, ..., 2
   int lf1;
@@ -893,7 +895,7 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
   __builtin_amdgcn_s_setprio(kChainPrio);
   extern __shared__ char l2p_lds[];
   double2 *cf = reinterpret_cast<double2 *>(l2p_lds);  // sets A, B, C of every staged ancestor
-  const int c = blockIdx.x, r = blockIdx.y;
+  const int c = xcd_item(blockIdx.x, gridDim.x), r = blockIdx.y;
   const int j0 = ev_start[c], j1 = ev_start[c + 1], lf0 = ev_leaf[c];
   const int nlev = L - 1;
   int lf1;
