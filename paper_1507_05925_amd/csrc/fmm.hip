@@ -1232,6 +1232,57 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
       }
     }
   }
+  {
+    // Dispatch order. Workgroup i of the M2L launch runs on XCD i % 8, each XCD with its own L2:
+    // the groups of every level are cut into eight contiguous parts of about equal work (items),
+    // and XCD x takes part x of every level, so neighbouring groups, which read mostly the same
+    // source multipoles, share one L2 while the work stays balanced over the XCDs. Only the order
+    // of the groups changes (each group writes its own boxes' locals).
+    const int G = (int)grp_lvl.size();
+    std::vector<std::vector<int>> share(8);
+    for (int a = 0; a < G;) {
+      int b = a;
+      while (b < G && grp_lvl[b] == grp_lvl[a]) ++b;
+      const int i0 = grp_ptr[a], i1 = grp_ptr[b];  // grp_ptr[g] .. grp_ptr[g + 1]: group g's items
+      int x = 0;
+      for (int g = a; g < b; ++g) {
+        const int mid = grp_ptr[g] + (grp_ptr[g + 1] - grp_ptr[g]) / 2;
+        while (x < 7 && (long long)(mid - i0) * 8 >= (long long)(i1 - i0) * (x + 1)) ++x;
+        share[x].push_back(g);
+      }
+      a = b;
+    }
+    std::vector<int> order;
+    order.reserve(G);
+    std::vector<size_t> next(8, 0);
+    for (int i = 0; i < G; ++i) {
+      int x = i & 7;
+      if (next[x] == share[x].size()) {  // this XCD's share is used up: take from the largest rest
+        size_t best = 0;
+        for (int y = 0; y < 8; ++y)
+          if (share[y].size() - next[y] > best) best = share[y].size() - next[y], x = y;
+      }
+      order.push_back(share[x][next[x]++]);
+    }
+    std::vector<int> tgt2, lvl2, ptr2(1, 0), off2v, src2;
+    tgt2.reserve(grp_tgt.size());
+    src2.reserve(item_src.size());
+    for (int g : order) {
+      const int e0 = grp_ptr[g], e1 = grp_ptr[g + 1];
+      tgt2.insert(tgt2.end(), grp_tgt.begin() + 16 * (size_t)g, grp_tgt.begin() + 16 * (size_t)g + 16);
+      for (int e = e0; e < e1; ++e) {
+        off2v.push_back(item_off[e]);
+        src2.insert(src2.end(), item_src.begin() + 16 * (size_t)e, item_src.begin() + 16 * (size_t)e + 16);
+      }
+      lvl2.push_back(grp_lvl[g]);
+      ptr2.push_back((int)off2v.size());
+    }
+    grp_tgt.swap(tgt2);
+    grp_lvl.swap(lvl2);
+    grp_ptr.swap(ptr2);
+    item_off.swap(off2v);
+    item_src.swap(src2);
+  }
   t.ngroup = (int)grp_lvl.size();
   t.nitem = (int)item_off.size();
   // All tables carry a scale s = max(1, 2p/e): multipoles are stored as u_m = a_m s^m / m!, so
