@@ -45,11 +45,23 @@ extern "C" {
 #define BIE_ENOMEM (-2)   /* device allocation failed */
 #define BIE_ENOCONV (-3)  /* GMRES did not reach the tolerance within max_iter */
 #define BIE_EDEVICE (-4)  /* HIP runtime error */
+#define BIE_ERESOLVE (-5) /* warning from bie_geom_create / bie_ctx_geom_create only: the geometry
+                             WAS created (*out is valid and usable) but a curve is under-resolved
+                             (its trapezoidal turning number sum_k kappa_k w_k misses 2 pi by more
+                             than 1e-8 relative) or a node of one body lies closer than 3 node
+                             spacings of another body to it (the trapezoidal rule on that body
+                             then loses accuracy like exp(-2 pi d / h)); bie_last_error() names the
+                             bodies. Results stay the exact solution of the discrete system; only
+                             their distance to the continuum solution is at risk. */
 
 #define BIE_FP64 0   /* every step in float64 */
-#define BIE_MIXED 1  /* far-field pair sums in float32 (body-relative coordinates, float64
-                        accumulation across source bodies) inside GMRES; float64 self-body
-                        blocks, diagonal, completion, Arnoldi and refinement residuals */
+#define BIE_MIXED 1  /* inner GMRES on a float32 far field inside float64 iterative refinement.
+                        Direct method: far-field pair sums in float32 (body-relative
+                        coordinates, float64 accumulation across source bodies), float64
+                        self-body blocks. FMM: float32 near field (leaf-relative coordinates)
+                        and Laplace expansions, expansions of about half the order; float64
+                        same-body near-diagonal band. Both: float64 diagonal, completion,
+                        Arnoldi and refinement residuals (float64 operator). */
 
 #define BIE_DIRECT 0 /* all-pairs direct summation */
 #define BIE_FMM 1    /* 2D fast multipole method for the far field */
@@ -67,6 +79,17 @@ typedef struct {
   int max_refine;   /* BIE_MIXED: cap on outer refinement steps                       */
   int fmm_order;    /* BIE_FMM: expansion order p (terms per expansion)               */
   int fmm_leaf;     /* BIE_FMM: maximum nodes per leaf box                            */
+  double viscosity; /* mobility / resistance: fluid viscosity > 0 (mobility problem
+                       statement: viscosity 1 there). Velocities scale as 1/viscosity,
+                       forces and torques as viscosity; densities do not change.        */
+  double fmm_eps;   /* BIE_FMM: > 0 sets the expansion order from a relative accuracy
+                       target, p = ceil(log(fmm_eps) / log(0.55)) clamped to [8, 64]
+                       (the FMM error falls about as 0.55^p); 0 = use fmm_order           */
+  int l2_scaling;   /* 1: GMRES on the symmetrised system D A D^-1 (D mu) = D f with
+                       D = diag(sqrt(w)) (the paper's L2 rescaling of the numerical
+                       section): same solution, the stopping test then uses the discrete
+                       L2 norm ||D r|| / ||D f||. Single-geometry solves only (the batch
+                       and the server reject it).                                       */
 } bie_opts;
 
 typedef struct {
@@ -77,17 +100,43 @@ typedef struct {
   double rel_residual;   /* final true relative residual, float64 apply (max over rhs)    */
   double seconds;        /* wall time of the call                                         */
   long long pairs;       /* pair interactions evaluated (direct: M^2 per apply per rhs)   */
+  double net_charge_or_force[2]; /* solves: sum_j q_j (elastance; [1] = 0) or sum_j F_j
+                                    (mobility) of the right-hand side with the largest
+                                    magnitude. The paper requires both to vanish (eqs.
+                                    ChargeConservation, NoNetForce); any value is accepted
+                                    (see the solves) and reported here. */
 } bie_info;
 
 /* Message of the last failure on this thread (never NULL). */
 const char *bie_last_error(void);
 
 /* Fills *o with the defaults: BIE_FP64, BIE_DIRECT, tol 1e-12, restart 100, max_iter 500,
- * inner_tol 1e-6, max_refine 10, fmm_order 40, fmm_leaf 64. With BIE_FMM and BIE_MIXED the inner
- * applies use order ceil(0.55 fmm_order) (about the square root of the accuracy); all FMM
- * arithmetic is float64. fmm_order must lie in [4, 64]; the library rounds the order up to a
- * multiple of 8. */
+ * inner_tol 1e-6, max_refine 10, fmm_order 40, fmm_leaf 64, viscosity 1, fmm_eps 0,
+ * l2_scaling 0. With BIE_FMM and BIE_MIXED the inner applies use order ceil(0.55 fmm_order)
+ * (about the square root of the accuracy) with a float32 near field and, for Laplace, float32
+ * expansions (Stokes expansions stay float64: their C' - conj(z) A' combination cancels); the
+ * float64 refinement residuals use the full order in float64. fmm_order must lie in [4, 64];
+ * the library rounds the order up to a multiple of 8. */
 int bie_default_opts(bie_opts *o);
+
+/* ---- context: device, default options, owned geometries -------------------------------------
+ * A context binds one HIP device and a set of default options. Geometries created through it
+ * (bie_ctx_geom_create) live on its device, are owned by it until bie_geom_destroy (bie_destroy
+ * destroys the ones left), and take the context's defaults wherever a call passes opts = NULL.
+ * Every call on such a geometry makes the context's device current for its duration. A context
+ * is used from one host thread at a time; bie_last_error() reports per thread, hence per
+ * context. Geometries from bie_geom_create have no context: process defaults, the current
+ * device at creation.
+ * bie_create: device = HIP device ordinal (0 .. count - 1); defaults NULL = bie_default_opts.
+ * Errors: BIE_EINVAL (NULL out, bad device ordinal or options), BIE_EDEVICE (no device). */
+typedef struct bie_ctx bie_ctx;
+int bie_create(bie_ctx **out, int device, const bie_opts *defaults);
+int bie_destroy(bie_ctx *ctx);
+int bie_ctx_defaults(const bie_ctx *ctx, bie_opts *out);
+/* As bie_geom_create, on the context's device and owned by the context. */
+int bie_ctx_geom_create(bie_ctx *ctx, int nbodies, const int32_t *nodes_per_body,
+                        const double *curve, const double *interior, void *stream,
+                        bie_geom **out);
 
 /* ---- a1: geometry and quadrature (elastance section; eq. rho for W; centroid of the mobility
  * problem statement) ------------------------------------------------------------------------
@@ -99,10 +148,17 @@ int bie_default_opts(bie_opts *o);
  * Computes on the device: outward normal n = (y', -x')/|x'|, curvature, weights
  * w_k = (2 pi / n_b)|x'(t_k)|, |Gamma_j|, x^c_j = sum w x / sum w, W_j = sum w |x - x^c_j|^2,
  * p_k = (x_k - x^c_j)^perp, float32 body-relative coordinates.
- * Errors: BIE_EINVAL for N < 1, n_b < 3, NULL curve, non-finite samples, or a body whose
- * signed area is not positive (clockwise). */
+ * Errors: BIE_EINVAL for N < 1, n_b < 3, NULL curve, non-finite samples, a body whose signed
+ * area is not positive (clockwise), or a read-off point (given, or the default centroid) that
+ * is not inside its body's node polygon (winding number 1; phi and (v, omega) are read there,
+ * where u is constant, resp. a rigid motion). BIE_ERESOLVE: created, with the warning above. */
 int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *curve,
                     const double *interior, void *stream, bie_geom **out);
+/* The checks bie_geom_create applies, on host copies of its inputs (curve (host) [6][M],
+ * interior (host) [N][2] or NULL), without a device: BIE_OK, BIE_EINVAL or BIE_ERESOLVE with
+ * the same messages. */
+int bie_curves_check(int nbodies, const int32_t *nodes_per_body, const double *curve,
+                     const double *interior);
 int bie_geom_destroy(bie_geom *g);
 int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M);
 /* Copies the per-node quadrature data (device out [8][M]: x, y, nx, ny, w, kappa, px, py) and
@@ -148,8 +204,12 @@ int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *V
  * Elastance: q (device) [nrhs][N] -> phi (device) [nrhs][N]; mu_out (device) [nrhs][M] or NULL.
  * Mobility: FT (device) [nrhs][3N] -> VW (device) [nrhs][3N]; mu_out (device) [nrhs][2M] or NULL.
  * Any q is accepted: for sum q != 0 (or sum F != 0) the same representation gives the unique
- * field with u + (Q/2 pi) log|x| -> 0 (its potential is grounded at infinity in that sense).
- * opts NULL = defaults; info may be NULL. BIE_ENOCONV: outputs hold the last iterate. */
+ * field with u + (Q/2 pi) log|x| -> 0 (its potential is grounded at infinity in that sense);
+ * info->net_charge_or_force reports the net charge, resp. force. Mobility velocities are for
+ * opts.viscosity (mu_out, the traction density, does not depend on it).
+ * opts NULL = defaults (the context's for a context geometry); info may be NULL.
+ * Errors: BIE_EINVAL for a non-finite q, F or T (the input is read once to check it), bad
+ * sizes or options. BIE_ENOCONV: outputs hold the last iterate. */
 int bie_elastance_solve(bie_geom *g, int nrhs, const double *q, double *phi, double *mu_out,
                         const bie_opts *opts, bie_info *info, void *stream);
 int bie_mobility_solve(bie_geom *g, int nrhs, const double *FT, double *VW, double *mu_out,
@@ -248,7 +308,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
                     bie_info *info, double *rel_residual, void *stream);
 
 /* ---- serving: continuous batching of elastance and mobility requests ------------------------
- * A worker thread (own HIP stream, default priority) keeps a set of requests in flight. At every
+ * A worker thread (own HIP stream, default priority, created with the server: BIE_EDEVICE
+ * from bie_server_create when the device cannot be used) keeps a set of requests in flight. At every
  * GMRES-cycle boundary it (1) computes each active request's true residual f - A x with the
  * float64 operator, (2) retires the requests whose systems all reached opts.tol (potentials or
  * rigid motions read off inside the bodies, copied to the caller's host buffer), (3) admits
@@ -273,6 +334,10 @@ typedef struct {
   double queue_s;      /* submit -> admitted                                                 */
   double latency_s;    /* submit -> result in the caller's buffer                           */
   double rel_residual; /* worst final relative residual over the request's rhs               */
+  int inflight;        /* requests in flight right after this one was admitted (itself too) */
+  long long footprint_bytes; /* bytes charged for it: its solver state plus, for the first
+                                request on its geometry and kind, the geometry's FMM tree and
+                                apply workspace (charged once while any of its requests run) */
 } bie_request_info;
 int bie_server_create(const bie_server_config *cfg, bie_server **out);
 /* kind 0: in [nrhs][N] charges -> out [nrhs][N] potentials; kind 1: in [nrhs][3N] (F, T) ->
@@ -287,6 +352,10 @@ int bie_server_stats(bie_server *srv, long long *requests, long long *solves, lo
                      long long *peak_bytes);
 /* Drains the queue and in-flight work, stops the worker and frees the server. */
 int bie_server_destroy(bie_server *srv);
+/* Testing hook for the error path: the next `cycles` worker cycles fail with BIE_EDEVICE
+ * before doing any work. A failing cycle fails only the requests in flight in it (their wait
+ * returns the error); the worker stays up and serves the requests that come after. */
+int bie_server_inject_failure(bie_server *srv, int cycles);
 
 /* ---- instrumentation (not a step of the method) ---------------------------------------------
  * When enabled, the library records a pair of HIP events on the launch stream around every

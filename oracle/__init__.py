@@ -17,7 +17,10 @@ Contents
             solution with its charges / forces and torques and u_inf, the matrices C and R.
 
 Parity status: every function is pinned by tests/test_oracle_*.py against closed forms, the
-paper's tables, discrete Gauss-law identities, invariants or brute force (no function is
-"parity unpinned"). The splash geometry is pinned through the paper's cross-tests with its printed
-potentials and rigid motions; the nanocomposite geometry through the printed capacitances.
+paper's tables, discrete Gauss-law identities, invariants or brute force; capacitance_field by
+the exact two-disc exterior potential of the two-disc test (and the double layer's Gauss law).
+The splash geometry is pinned through the paper's cross-tests with its printed potentials and
+rigid motions; the nanocomposite geometry through the printed capacitances. Results that no pin
+reaches: the splash potentials and velocities themselves (the paper prints only errors) and the
+iteration counts (another discretization).
 """

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import warnings
+import weakref
 
 import numpy as np
 
@@ -17,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbie2d.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bie2d.h")
 
-BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE = 0, -1, -2, -3, -4
+BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE, BIE_ERESOLVE = 0, -1, -2, -3, -4, -5
 BIE_FP64, BIE_MIXED = 0, 1
 BIE_DIRECT, BIE_FMM, BIE_AUTO = 0, 1, 2
 
@@ -28,11 +30,18 @@ class BieError(RuntimeError):
         self.code = code
 
 
+class ResolutionWarning(UserWarning):
+    """bie_geom_create returned BIE_ERESOLVE: the geometry exists, but a curve is
+    under-resolved or two bodies are closer than a few node spacings."""
+
+
 class bie_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("method", ctypes.c_int), ("tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int)]
+                ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int),
+                ("viscosity", ctypes.c_double), ("fmm_eps", ctypes.c_double),
+                ("l2_scaling", ctypes.c_int)]
 
 
 class bie_batch_item(ctypes.Structure):
@@ -44,10 +53,12 @@ class bie_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("pairs", ctypes.c_longlong)]
+                ("pairs", ctypes.c_longlong), ("net_charge_or_force", ctypes.c_double * 2)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["net_charge_or_force"] = tuple(self.net_charge_or_force)
+        return d
 
 
 _P = ctypes.c_void_p
@@ -55,7 +66,12 @@ _I = ctypes.c_int
 _SIGS = {
     "bie_last_error": ([], ctypes.c_char_p),
     "bie_default_opts": ([ctypes.POINTER(bie_opts)], _I),
+    "bie_create": ([ctypes.POINTER(_P), _I, ctypes.POINTER(bie_opts)], _I),
+    "bie_destroy": ([_P], _I),
+    "bie_ctx_defaults": ([_P, ctypes.POINTER(bie_opts)], _I),
+    "bie_ctx_geom_create": ([_P, _I, _P, _P, _P, _P, ctypes.POINTER(_P)], _I),
     "bie_geom_create": ([_I, _P, _P, _P, _P, ctypes.POINTER(_P)], _I),
+    "bie_curves_check": ([_I, _P, _P, _P], _I),
     "bie_geom_destroy": ([_P], _I),
     "bie_geom_sizes": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "bie_geom_export": ([_P, _P, _P, _P], _I),
@@ -90,6 +106,7 @@ _SIGS = {
     "bie_server_stats": ([_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_server_destroy": ([_P], _I),
+    "bie_server_inject_failure": ([_P, _I], _I),
     "bie_profile_enable": ([_I], _I),
     "bie_profile_sample": ([ctypes.c_int], _I),
     "bie_profile_select": ([ctypes.c_uint], _I),
@@ -185,31 +202,86 @@ def default_opts(**kw):
     return o
 
 
+def bie_curves_check(curves, interior=None):
+    """Host-side checks of curve samples (a Curves object) as bie_geom_create applies them:
+    returns (code, message) with code BIE_OK, BIE_EINVAL or BIE_ERESOLVE."""
+    c = np.ascontiguousarray(np.stack([curves.x, curves.y, curves.dx, curves.dy, curves.ddx,
+                                       curves.ddy]), dtype=np.float64)
+    npb = np.ascontiguousarray(curves.nodes_per_body, dtype=np.int32)
+    ip = None if interior is None else np.ascontiguousarray(interior, dtype=np.float64).reshape(-1)
+    code = lib().bie_curves_check(len(npb), npb.ctypes.data_as(ctypes.c_void_p),
+                                  c.ctypes.data_as(ctypes.c_void_p),
+                                  None if ip is None else ip.ctypes.data_as(ctypes.c_void_p))
+    return code, (lib().bie_last_error().decode() if code != BIE_OK else "")
+
+
+class Context:
+    """Owns a bie_ctx: a device, default options, and the geometries created through it."""
+
+    def __init__(self, device=0, defaults=None):
+        h = ctypes.c_void_p()
+        _check(lib().bie_create(ctypes.byref(h), int(device),
+                                None if defaults is None else ctypes.byref(defaults)))
+        self.handle = h
+        self.device = int(device)
+        self._geoms = weakref.WeakSet()
+
+    def defaults(self):
+        o = bie_opts()
+        _check(lib().bie_ctx_defaults(self.handle, ctypes.byref(o)))
+        return o
+
+    def geometry(self, curves, interior=None):
+        return Geometry.from_curves(curves, device=f"cuda:{self.device}", interior=interior,
+                                    ctx=self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for g in list(self._geoms):  # bie_destroy frees them: forget the handles first
+                g.handle = None
+            lib().bie_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Geometry:
     """Owns a bie_geom (device-resident quadrature data and workspace)."""
 
-    def __init__(self, nodes_per_body, curve, interior=None):
+    def __init__(self, nodes_per_body, curve, interior=None, ctx=None):
         self.nodes_per_body = np.ascontiguousarray(nodes_per_body, dtype=np.int32)
         M = int(self.nodes_per_body.sum())
         if tuple(curve.shape) != (6, M):
             raise ValueError(f"curve must have shape (6, {M})")
         h = ctypes.c_void_p()
         ip = None if interior is None else _dptr(interior, 2, "interior")
-        _check(lib().bie_geom_create(len(self.nodes_per_body),
-                                     self.nodes_per_body.ctypes.data_as(ctypes.c_void_p),
-                                     _dptr(curve, M, "curve"), ip, _stream(), ctypes.byref(h)))
+        args = (len(self.nodes_per_body), self.nodes_per_body.ctypes.data_as(ctypes.c_void_p),
+                _dptr(curve, M, "curve"), ip, _stream(), ctypes.byref(h))
+        code = (lib().bie_geom_create(*args) if ctx is None
+                else lib().bie_ctx_geom_create(ctx.handle, *args))
+        if code == BIE_ERESOLVE:
+            warnings.warn(lib().bie_last_error().decode(), ResolutionWarning, stacklevel=3)
+        else:
+            _check(code)
         self.handle = h
+        self.ctx = ctx  # keeps the context alive while the geometry is
+        if ctx is not None:
+            ctx._geoms.add(self)
         self.N, self.M = len(self.nodes_per_body), M
         self.device = curve.device
 
     @classmethod
-    def from_curves(cls, curves, device="cuda", interior=None):
+    def from_curves(cls, curves, device="cuda", interior=None, ctx=None):
         torch = _torch()
         c = np.stack([curves.x, curves.y, curves.dx, curves.dy, curves.ddx, curves.ddy])
         t = torch.from_numpy(np.ascontiguousarray(c)).to(device)
         it = None if interior is None else torch.as_tensor(np.asarray(interior, np.float64),
                                                           device=device).reshape(-1, 2).contiguous()
-        return cls(curves.nodes_per_body, t, it)
+        return cls(curves.nodes_per_body, t, it, ctx=ctx)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -304,9 +376,9 @@ def _solve(fn, g, data, width_in, width_mu, opts, want_mu, allow_noconv):
     res = torch.empty(R, width_in, dtype=torch.float64, device=data.device)
     mu = torch.empty(R, width_mu, dtype=torch.float64, device=data.device) if want_mu else None
     info = bie_info()
-    o = opts if opts is not None else default_opts()
+    o = None if opts is None else ctypes.byref(opts)  # NULL: the library's (or context's) defaults
     code = fn(g.handle, R, _dptr(data, width_in, "input"), _dptr(res),
-              _dptr(mu) if want_mu else None, ctypes.byref(o), ctypes.byref(info), _stream())
+              _dptr(mu) if want_mu else None, o, ctypes.byref(info), _stream())
     if not (code == BIE_OK or (allow_noconv and code == BIE_ENOCONV)):
         _check(code)
     shape = data.shape[:-1]
@@ -372,9 +444,9 @@ def _dl_solve(fn, g, data, width_in, width_mu, width_inf, opts, want_mu, allow_n
     uinf = torch.empty(R, width_inf, dtype=torch.float64, device=data.device)
     mu = torch.empty(R, width_mu, dtype=torch.float64, device=data.device) if want_mu else None
     info = bie_info()
-    o = opts if opts is not None else default_opts()
+    o = None if opts is None else ctypes.byref(opts)
     code = fn(g.handle, R, _dptr(data, width_in, "input"), _dptr(res), _dptr(uinf),
-              _dptr(mu) if want_mu else None, ctypes.byref(o), ctypes.byref(info), _stream())
+              _dptr(mu) if want_mu else None, o, ctypes.byref(info), _stream())
     if not (code == BIE_OK or (allow_noconv and code == BIE_ENOCONV)):
         _check(code)
     shape = data.shape[:-1]
@@ -401,8 +473,8 @@ def _matrix(fn, g, n, max_rhs, opts):
     torch = _torch()
     out = torch.empty(n, n, dtype=torch.float64, device=g.device)  # rows = columns of the matrix
     info = bie_info()
-    o = opts if opts is not None else default_opts()
-    _check(fn(g.handle, _dptr(out), int(max_rhs), ctypes.byref(o), ctypes.byref(info), _stream()))
+    o = None if opts is None else ctypes.byref(opts)
+    _check(fn(g.handle, _dptr(out), int(max_rhs), o, ctypes.byref(info), _stream()))
     return out.t().contiguous(), info.as_dict()  # column-major buffer -> matrix
 
 
@@ -470,7 +542,8 @@ class bie_server_config(ctypes.Structure):
 
 class bie_request_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int), ("queue_s", ctypes.c_double),
-                ("latency_s", ctypes.c_double), ("rel_residual", ctypes.c_double)]
+                ("latency_s", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("inflight", ctypes.c_int), ("footprint_bytes", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -505,13 +578,20 @@ class Server:
         self._bufs[t.value] = (a, out)
         return t.value
 
-    def wait(self, ticket, timeout=-1.0):
-        """-> (output array, info dict); raises on failure other than non-convergence."""
+    def wait(self, ticket, timeout=-1.0, raise_on_error=True):
+        """-> (output array, info dict); raises on failure other than non-convergence unless
+        raise_on_error is False (then info["status"] carries the code)."""
         info = bie_request_info()
-        _check(lib().bie_server_wait(self.handle, ctypes.c_longlong(ticket), float(timeout),
-                                     ctypes.byref(info)))
+        code = lib().bie_server_wait(self.handle, ctypes.c_longlong(ticket), float(timeout),
+                                     ctypes.byref(info))
+        if code != BIE_OK and (raise_on_error or ticket not in self._bufs):
+            _check(code)
         a, out = self._bufs.pop(ticket)
         return out, info.as_dict()
+
+    def inject_failure(self, cycles=1):
+        """Testing hook: the next `cycles` worker cycles fail (bie_server_inject_failure)."""
+        _check(lib().bie_server_inject_failure(self.handle, int(cycles)))
 
     def stats(self):
         v = [ctypes.c_longlong() for _ in range(4)]

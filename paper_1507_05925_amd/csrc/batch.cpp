@@ -68,6 +68,12 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   }
   bie_opts o;
   if (opts) o = *opts; else bie_default_opts(&o);
+  BIE_TRY(check_opts(o));
+  if (o.l2_scaling) {
+    set_error("bie_batch_solve: l2_scaling is supported by the single-geometry solves only");
+    return BIE_EINVAL;
+  }
+  o.fmm_order = effective_order(o);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   std::vector<long long> lens, starts, item_off(nitems + 1, 0), in_off(nitems + 1, 0);
   long long pairs = 0;
@@ -125,7 +131,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   for (int i = 0; i < nitems; ++i) {
     bie_geom *g = items[i].g;
     mitems[i] = {g, items[i].kind, items[i].nrhs, item_off[i],
-                 o.method == BIE_FMM || (o.method == BIE_AUTO && g->M > 32768)};
+                 o.method == BIE_FMM || (o.method == BIE_AUTO && g->M > 32768), o.fmm_order,
+                 o.fmm_leaf};
     first_sys[i + 1] = first_sys[i] + items[i].nrhs;
   }
   SysSet *ssp = &ss;
@@ -147,8 +154,12 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   int rc = solve_systems(ss, o, f, mu, rel, &inf, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
   BIE_TRY(vec_axpby(Ntot, 1.0, mu, 1.0, dens, s));
-  for (int i = 0; i < nitems; ++i)
+  for (int i = 0; i < nitems; ++i) {
     BIE_TRY(read_off(items[i].g, items[i].kind, items[i].nrhs, dens + item_off[i], items[i].out, s));
+    if (items[i].kind == 1 && o.viscosity != 1.0)  // velocities for the caller's viscosity
+      BIE_TRY(vec_axpby((long long)items[i].nrhs * 3 * items[i].g->N, 0.0, items[i].out,
+                        1.0 / o.viscosity, items[i].out, s));
+  }
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   if (rel_residual) {
     size_t k = 0;

@@ -2,10 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -82,25 +85,142 @@ static void fill_defaults(bie_opts *o) {
   o->max_refine = 10;
   o->fmm_order = 40;
   o->fmm_leaf = 64;
+  o->viscosity = 1.0;
+  o->fmm_eps = 0.0;
+  o->l2_scaling = 0;
 }
 
-static int check_opts(const bie_opts &o) {
+int check_opts(const bie_opts &o) {
   if ((o.precision != BIE_FP64 && o.precision != BIE_MIXED) ||
       (o.method != BIE_DIRECT && o.method != BIE_FMM && o.method != BIE_AUTO) ||
       !(o.tol > 0.0) || o.restart < 1 ||
       o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
-      o.fmm_order > 64 || o.fmm_leaf < 1) {
+      o.fmm_order > 64 || o.fmm_leaf < 1 || !(o.viscosity > 0.0) || !std::isfinite(o.viscosity) ||
+      !(o.fmm_eps >= 0.0) || !(o.fmm_eps < 1.0) || (o.l2_scaling != 0 && o.l2_scaling != 1)) {
     set_error("invalid bie_opts");
     return BIE_EINVAL;
   }
   return BIE_OK;
 }
 
+// The expansion order the options ask for: from fmm_eps when it is set (the FMM error falls
+// about as 0.55^p for the one-box-separation interaction lists), else fmm_order.
+int effective_order(const bie_opts &o) {
+  if (!(o.fmm_eps > 0.0)) return o.fmm_order;
+  const int p = (int)std::ceil(std::log(o.fmm_eps) / std::log(0.55));
+  return std::max(8, std::min(64, p));
+}
+
+// Makes `dev` the current device for the lifetime of the guard (restoring the previous one).
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess)
+      prev = cur;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace bie
+
+struct bie_ctx {
+  int device = 0;
+  bie_opts defaults{};
+  std::mutex mu;
+  std::set<bie_geom *> geoms;  // owned until bie_geom_destroy
+};
+
+namespace bie {
+// Options of a call: the caller's, else its context's defaults, else the process defaults.
+static bie_opts opts_for(const bie_geom *g, const bie_opts *opts) {
+  bie_opts o;
+  if (opts) o = *opts;
+  else if (g && g->ctx) o = g->ctx->defaults;
+  else fill_defaults(&o);
+  return o;
+}
 }  // namespace bie
 
 using namespace bie;
 
+static int geom_create(int nbodies, const int32_t *nodes_per_body, const double *curve,
+                       const double *interior, void *stream, bie_geom **out);
+
 extern "C" {
+
+int bie_create(bie_ctx **out, int device, const bie_opts *defaults) {
+  if (!out) {
+    set_error("bie_create: NULL out");
+    return BIE_EINVAL;
+  }
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    set_error("bie_create: no HIP device");
+    return BIE_EDEVICE;
+  }
+  if (device < 0 || device >= count) {
+    set_error("bie_create: device ordinal " + std::to_string(device) + " out of range [0, " +
+              std::to_string(count) + ")");
+    return BIE_EINVAL;
+  }
+  bie_opts o;
+  if (defaults) o = *defaults; else fill_defaults(&o);
+  BIE_TRY(check_opts(o));
+  bie_ctx *c = new (std::nothrow) bie_ctx();
+  if (!c) {
+    set_error("host allocation failed");
+    return BIE_ENOMEM;
+  }
+  c->device = device;
+  c->defaults = o;
+  *out = c;
+  return BIE_OK;
+}
+
+int bie_destroy(bie_ctx *ctx) {
+  if (!ctx) return BIE_OK;
+  std::set<bie_geom *> left;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    left.swap(ctx->geoms);
+  }
+  for (bie_geom *g : left) {
+    g->ctx = nullptr;
+    bie_geom_destroy(g);
+  }
+  delete ctx;
+  return BIE_OK;
+}
+
+int bie_ctx_defaults(const bie_ctx *ctx, bie_opts *out) {
+  if (!ctx || !out) {
+    set_error("bie_ctx_defaults: NULL argument");
+    return BIE_EINVAL;
+  }
+  *out = ctx->defaults;
+  return BIE_OK;
+}
+
+int bie_ctx_geom_create(bie_ctx *ctx, int nbodies, const int32_t *nodes_per_body,
+                        const double *curve, const double *interior, void *stream,
+                        bie_geom **out) {
+  if (!ctx) {
+    set_error("bie_ctx_geom_create: NULL context");
+    return BIE_EINVAL;
+  }
+  DeviceGuard dg(ctx->device);
+  const int rc = geom_create(nbodies, nodes_per_body, curve, interior, stream, out);
+  if ((rc == BIE_OK || rc == BIE_ERESOLVE) && out && *out) {
+    (*out)->ctx = ctx;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->geoms.insert(*out);
+  }
+  return rc;
+}
 
 const char *bie_last_error(void) { return g_last_error.c_str(); }
 
@@ -115,6 +235,30 @@ int bie_default_opts(bie_opts *o) {
 
 int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *curve,
                     const double *interior, void *stream, bie_geom **out) {
+  return geom_create(nbodies, nodes_per_body, curve, interior, stream, out);
+}
+
+int bie_curves_check(int nbodies, const int32_t *nodes_per_body, const double *curve,
+                     const double *interior) {
+  if (!nodes_per_body || !curve || nbodies < 1) {
+    set_error("bie_curves_check: need nbodies >= 1 and non-NULL nodes_per_body, curve");
+    return BIE_EINVAL;
+  }
+  for (int b = 0; b < nbodies; ++b)
+    if (nodes_per_body[b] < 3) {
+      set_error("bie_curves_check: body " + std::to_string(b) + " has fewer than 3 nodes");
+      return BIE_EINVAL;
+    }
+  std::string msg;
+  const int rc = check_curves(nbodies, nodes_per_body, curve, interior, msg);
+  if (rc != BIE_OK) set_error("bie_curves_check: " + msg);
+  return rc;
+}
+
+}  // extern "C"
+
+static int geom_create(int nbodies, const int32_t *nodes_per_body, const double *curve,
+                       const double *interior, void *stream, bie_geom **out) {
   if (!out || !nodes_per_body || !curve || nbodies < 1) {
     set_error("bie_geom_create: need nbodies >= 1 and non-NULL nodes_per_body, curve, out");
     return BIE_EINVAL;
@@ -134,11 +278,33 @@ int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *cu
     set_error("bie_geom_create: more than 2^28 nodes");
     return BIE_EINVAL;
   }
+  // the caller's samples (device memory) are checked on the host before anything is built
+  int warn = BIE_OK;
+  std::string warn_msg;
+  {
+    hipStream_t s0 = as_stream(stream);
+    std::vector<double> hc(6 * (size_t)M), hi(interior ? 2 * (size_t)nbodies : 0);
+    if (hipMemcpyAsync(hc.data(), curve, hc.size() * 8, hipMemcpyDeviceToHost, s0) != hipSuccess ||
+        (interior && hipMemcpyAsync(hi.data(), interior, hi.size() * 8, hipMemcpyDeviceToHost,
+                                    s0) != hipSuccess) ||
+        hipStreamSynchronize(s0) != hipSuccess) {
+      set_error("bie_geom_create: device to host copy of the curve samples failed");
+      return BIE_EDEVICE;
+    }
+    warn = check_curves(nbodies, nodes_per_body, hc.data(), interior ? hi.data() : nullptr,
+                        warn_msg);
+    if (warn == BIE_EINVAL) {
+      set_error("bie_geom_create: " + warn_msg);
+      return BIE_EINVAL;
+    }
+  }
   bie_geom *g = new (std::nothrow) bie_geom();
   if (!g) {
     set_error("host allocation failed");
     return BIE_ENOMEM;
   }
+  static std::atomic<unsigned long long> next_gen{1};
+  g->gen = next_gen.fetch_add(1);
   g->N = nbodies;
   g->M = (int)M;
   g->max_nodes = maxn;
@@ -205,37 +371,32 @@ int bie_geom_create(int nbodies, const int32_t *nodes_per_body, const double *cu
   }
   rc = geometry_build(g, curve, interior, s);
   if (rc != BIE_OK) return fail(rc);
-  std::vector<double> area(Nd), len(Nd);
-  if (hipMemcpyAsync(area.data(), g->area, Nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(len.data(), g->len, Nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
-    set_error("bie_geom_create: device to host copy failed");
+  if (hipStreamSynchronize(s) != hipSuccess) {  // the geometry is ready on any stream
+    set_error("bie_geom_create: geometry build failed on the device");
     return fail(BIE_EDEVICE);
   }
-  for (int b = 0; b < nbodies; ++b) {
-    if (!std::isfinite(area[b]) || !std::isfinite(len[b])) {
-      set_error("bie_geom_create: non-finite curve samples on body " + std::to_string(b));
-      return fail(BIE_EINVAL);
-    }
-    if (!(area[b] > 0.0)) {
-      set_error("bie_geom_create: body " + std::to_string(b) +
-                " is not positively oriented (signed area <= 0)");
-      return fail(BIE_EINVAL);
-    }
-  }
   *out = g;
-  return BIE_OK;
+  if (warn != BIE_OK) set_error("bie_geom_create (warning, geometry created): " + warn_msg);
+  return warn;
 }
+
+extern "C" {
 
 int bie_geom_destroy(bie_geom *g) {
   if (!g) return BIE_OK;
-  hipDeviceSynchronize();
+  if (g->ctx) {
+    std::lock_guard<std::mutex> lk(g->ctx->mu);
+    g->ctx->geoms.erase(g);
+  }
+  DeviceGuard dg(g->device);
+  (void)hipDeviceSynchronize();
   g->arena.release();
   g->ws_apply.release();
   g->sm.release();
   g->seg.buf.release();
   g->ws_out.release();
   g->ws_read.release();
+  g->ws_scale.release();
   if (g->fmm) fmm_destroy(g->fmm);
   delete g;
   return BIE_OK;
@@ -243,6 +404,7 @@ int bie_geom_destroy(bie_geom *g) {
 
 int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nbodies) *nbodies = g->N;
   if (M) *M = g->M;
   return BIE_OK;
@@ -251,11 +413,12 @@ int bie_geom_sizes(const bie_geom *g, int *nbodies, int *M) {
 long long bie_geom_device_bytes(const bie_geom *g) {
   if (!g) return 0;
   return (long long)(g->arena.bytes + g->ws_apply.bytes + g->sm.big.bytes + g->sm.small.bytes +
-                     g->ws_out.bytes + g->ws_read.bytes);
+                     g->ws_out.bytes + g->ws_read.bytes + g->ws_scale.bytes);
 }
 
 int bie_geom_set_fmm(bie_geom *g, int order, int leaf) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (order < 4 || order > 64 || leaf < 1) {
     set_error("bie_geom_set_fmm: order must lie in [4, 64] and leaf >= 1");
     return BIE_EINVAL;
@@ -267,6 +430,7 @@ int bie_geom_set_fmm(bie_geom *g, int order, int leaf) {
 
 int bie_geom_export(const bie_geom *g, double *out, double *out_body, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   hipStream_t s = as_stream(stream);
   const size_t Md = g->M, Nd = g->N;
   const double *src[8] = {g->x, g->y, g->nx, g->ny, g->w, g->kappa, g->px, g->py};
@@ -283,6 +447,7 @@ int bie_geom_export(const bie_geom *g, double *out, double *out_body, void *stre
 static int apply_entry(bie_geom *g, int kind, int precision, int method, int with_L, int nrhs,
                        const double *mu, double *out, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (mu == out) {
     set_error("apply: mu and out must not alias");
     return BIE_EINVAL;
@@ -305,6 +470,7 @@ int bie_stokes_apply(bie_geom *g, int precision, int method, int with_L, int nrh
 static int rhs_entry(bie_geom *g, int kind, int method, int nrhs, const double *data,
                      double *dens, double *f, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !data) {
     set_error("rhs: nrhs >= 1 and non-NULL input required");
     return BIE_EINVAL;
@@ -336,6 +502,7 @@ int bie_mobility_rhs(bie_geom *g, int nrhs, const double *FT, double *rho, doubl
 static int field_entry(bie_geom *g, int kind, int nrhs, const double *in, const double *mu,
                        int npts, const double *pts, double *u, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || npts < 0 || !in || !mu || (npts > 0 && (!pts || !u))) {
     set_error("field: nrhs >= 1, npts >= 0 and non-NULL buffers required");
     return BIE_EINVAL;
@@ -352,6 +519,7 @@ static int field_entry(bie_geom *g, int kind, int nrhs, const double *in, const 
 
 int bie_laplace_potential(bie_geom *g, int nrhs, const double *dens, double *phi, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !dens || !phi) {
     set_error("potential: nrhs >= 1 and non-NULL buffers required");
     return BIE_EINVAL;
@@ -371,6 +539,7 @@ int bie_mobility_field(bie_geom *g, int nrhs, const double *FT, const double *mu
 
 int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *VW, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !dens || !VW) {
     set_error("rigid motion: nrhs >= 1 and non-NULL buffers required");
     return BIE_EINVAL;
@@ -378,21 +547,60 @@ int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *V
   return read_off(g, 1, nrhs, dens, VW, as_stream(stream));
 }
 
+// Reads a solve's input ([nrhs][N] charges, or [nrhs][3N] (F, T)) to the host once: rejects
+// non-finite entries, and returns the net charge (sum q) or net force (sum F) of the
+// right-hand side with the largest magnitude.
+static int input_check(int kind, int N, int nrhs, const double *data, hipStream_t s,
+                       double net[2]) {
+  const size_t width = kind == 0 ? (size_t)N : 3 * (size_t)N;
+  std::vector<double> h((size_t)nrhs * width);
+  BIE_HIP_CHECK(hipMemcpyAsync(h.data(), data, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  net[0] = net[1] = 0.0;
+  double best = -1.0;
+  for (int r = 0; r < nrhs; ++r) {
+    const double *v = h.data() + (size_t)r * width;
+    double a = 0.0, b = 0.0;
+    for (size_t j = 0; j < width; ++j)
+      if (!std::isfinite(v[j])) {
+        set_error(std::string("solve: non-finite ") + (kind == 0 ? "charge" : "force or torque") +
+                  " in right-hand side " + std::to_string(r));
+        return BIE_EINVAL;
+      }
+    if (kind == 0) {
+      for (int j = 0; j < N; ++j) a += v[j];
+    } else {
+      for (int j = 0; j < N; ++j) {
+        a += v[3 * j];
+        b += v[3 * j + 1];
+      }
+    }
+    if (std::hypot(a, b) > best) {
+      best = std::hypot(a, b);
+      net[0] = a;
+      net[1] = b;
+    }
+  }
+  return BIE_OK;
+}
+
 // The whole path: incident density, rhs, GMRES, read-off.
 static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, double *res,
                        double *mu_out, const bie_opts *opts, bie_info *info, void *stream) {
   auto t0 = std::chrono::steady_clock::now();
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !data || !res) {
     set_error("solve: nrhs >= 1 and non-NULL input/output required");
     return BIE_EINVAL;
   }
-  bie_opts o;
-  if (opts) o = *opts; else fill_defaults(&o);
+  const bie_opts o = opts_for(g, opts);
   BIE_TRY(check_opts(o));
   hipStream_t s = as_stream(stream);
+  double net[2];
+  BIE_TRY(input_check(kind, g->N, nrhs, data, s, net));
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
-  g->fmm_order = o.fmm_order;
+  g->fmm_order = effective_order(o);
   g->fmm_leaf = o.fmm_leaf;
   // ws_out: dens [nrhs][len], f [nrhs][len], mu [nrhs][len]
   BIE_TRY(g->ws_out.reserve(3 * len * nrhs * 8));
@@ -405,9 +613,13 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
   BIE_TRY(vec_axpby((long long)nrhs * len, 1.0, mu, 1.0, dens, s));  // dens = mu + incident
   BIE_TRY(read_off(g, kind, nrhs, dens, res, s));
+  if (kind == 1 && o.viscosity != 1.0)  // velocities of the viscosity-1 problem, rescaled
+    BIE_TRY(vec_axpby((long long)nrhs * 3 * g->N, 0.0, res, 1.0 / o.viscosity, res, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   if (info) {
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->net_charge_or_force[0] = net[0];
+    info->net_charge_or_force[1] = net[1];
     if (rc == BIE_OK && !(info->rel_residual <= o.tol)) rc = BIE_ENOCONV;
   }
   return rc;
@@ -427,6 +639,7 @@ int bie_mobility_solve(bie_geom *g, int nrhs, const double *FT, double *VW, doub
 static int dl_apply_entry(bie_geom *g, int stokes, int with_C, int nrhs, const double *mu,
                           double *out, void *stream) {
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !mu || !out || mu == out) {
     set_error("double-layer apply: nrhs >= 1, non-NULL and distinct mu, out required");
     return BIE_EINVAL;
@@ -449,16 +662,18 @@ static int dl_solve_entry(bie_geom *g, int stokes, int nrhs, const double *data,
                           void *stream) {
   auto t0 = std::chrono::steady_clock::now();
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (nrhs < 1 || !data || !res || !u_inf) {
     set_error("capacitance/resistance solve: nrhs >= 1 and non-NULL input and outputs required");
     return BIE_EINVAL;
   }
-  bie_opts o;
-  if (opts) o = *opts; else fill_defaults(&o);
+  const bie_opts o = opts_for(g, opts);
   BIE_TRY(check_opts(o));
   hipStream_t s = as_stream(stream);
   int rc = dl_solve(g, stokes, nrhs, data, res, u_inf, mu_out, o, info, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+  if (stokes && o.viscosity != 1.0)  // forces and torques of the viscosity-1 problem, rescaled
+    BIE_TRY(vec_axpby((long long)nrhs * 3 * g->N, 0.0, res, o.viscosity, res, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   if (info) {
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -483,6 +698,7 @@ static int matrix_entry(bie_geom *g, int kind, double *out, int max_rhs, const b
                         bie_info *info, void *stream) {
   auto t0 = std::chrono::steady_clock::now();
   BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
   if (!out) {
     set_error("matrix: NULL output");
     return BIE_EINVAL;
@@ -521,6 +737,11 @@ static int matrix_entry(bie_geom *g, int kind, double *out, int max_rhs, const b
     acc.applies_fp32 += one.applies_fp32;
     acc.rel_residual = std::max(acc.rel_residual, one.rel_residual);
     acc.pairs += one.pairs;
+    if (std::hypot(one.net_charge_or_force[0], one.net_charge_or_force[1]) >
+        std::hypot(acc.net_charge_or_force[0], acc.net_charge_or_force[1])) {
+      acc.net_charge_or_force[0] = one.net_charge_or_force[0];
+      acc.net_charge_or_force[1] = one.net_charge_or_force[1];
+    }
   }
   hipStreamSynchronize(s);
   idbuf.release();

@@ -69,7 +69,7 @@ struct FmmTree {
 };
 
 struct FmmPlan {
-  std::map<int, FmmTree *> trees;  // by order p
+  std::map<std::pair<int, int>, FmmTree *> trees;  // by (order p, leaf population)
   hipStream_t side = nullptr;      // near field, concurrent with the expansion passes
   hipEvent_t fork = nullptr, join = nullptr;
   ~FmmPlan() {
@@ -1453,13 +1453,13 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   return BIE_OK;
 }
 
-// M2L for groups [ga, gb) (groups are ordered by level, so a level is one range)
+// M2L for all groups [0, ngroup): groups are in XCD-balanced dispatch order (each XCD takes a
+// contiguous share of every level), so a level is not one contiguous range of groups
 template <int P>
-int launch_m2l(const FmmTree &t, int ga, int gb, int nsets, const double2 *Mexp, double2 *Lexp,
-               hipStream_t s) {
-  if (gb <= ga) return BIE_OK;
+int launch_m2l(const FmmTree &t, int nsets, const double2 *Mexp, double2 *Lexp, hipStream_t s) {
+  if (t.ngroup <= 0) return BIE_OK;
   static_assert(M2lShape<P>::LDS * sizeof(double) <= 65536, "M2L LDS exceeds 64 KiB");
-  hipLaunchKernelGGL(k_m2l<P>, dim3(gb - ga, nsets), dim3(256), 0, s, ga, t.nbox, t.grp_ptr,
+  hipLaunchKernelGGL(k_m2l<P>, dim3(t.ngroup, nsets), dim3(256), 0, s, 0, t.nbox, t.grp_ptr,
                      t.grp_tgt, t.grp_lvl, t.item_off, t.item_src, t.inv_h, t.fact_out, t.T_c,
                      t.T_dpow, Mexp, Lexp);
   BIE_HIP_CHECK(hipGetLastError());
@@ -1512,7 +1512,7 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
     if constexpr (std::is_same<T, float>::value)
       BIE_TRY(launch_m2l_f32<P>(t, nsets, Mexp, Lexp, s));
     else
-      BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
+      BIE_TRY(launch_m2l<P>(t, nsets, Mexp, Lexp, s));
   }
   BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
   if (kind == 0) {
@@ -1553,16 +1553,45 @@ int with_order(int p, F &&f) {
 
 int fmm_current_order() { return 0; }
 
+// Expansion length the apply uses for a requested order (mixed precision: about half).
+static int fmm_length(int order, int precision) {
+  int p = order > 0 ? order : 40;
+  if (precision == BIE_MIXED) p = std::max(8, (p * 11 + 19) / 20);  // about sqrt of the accuracy
+  return std::min((p + 7) / 8 * 8, kMaxP);  // expansions use a multiple of 8 terms (rounded up)
+}
+
+long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf) {
+  if (leaf <= 0) leaf = 64;
+  long long total = 0;
+  // a mixed solve keeps both trees: the float64 residual applies and the shorter inner ones
+  const int precs[2] = {BIE_FP64, BIE_MIXED};
+  for (int k = 0; k < (precision == BIE_MIXED ? 2 : 1); ++k) {
+    const int p = fmm_length(order, precs[k]);
+    const int R = kind == 0 ? 8 : 4, nsets = kind == 0 ? R : 3 * R;
+    const size_t csz = (precs[k] == BIE_MIXED && kind == 0) ? 8 : 16;
+    long long nbox = 2LL * g->M / leaf + 64, tree = 0;
+    if (g->fmm) {
+      auto it = g->fmm->trees.find(std::make_pair(p, leaf));
+      if (it != g->fmm->trees.end() && it->second) {
+        nbox = it->second->nbox;
+        tree = (long long)it->second->buf.bytes;
+      }
+    }
+    if (tree == 0) tree = 96LL * g->M + 1024LL * nbox + 16LL * 8 * p * p;
+    total += tree + (long long)R * g->M * 32 +
+             (long long)((size_t)nsets * g->M + 2 * (size_t)nsets * nbox * p) * (long long)csz;
+  }
+  return total;
+}
+
 // Far field of all pairs k != i (sets: Laplace R, Stokes 3R) into partial [R][len] (nsplit 1).
 int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu, double *s64,
                   double *partial,
                   hipStream_t s, int order, int leaf) {
-  int p = order > 0 ? order : 40;
-  if (precision == BIE_MIXED) p = std::max(8, (p * 11 + 19) / 20);  // about sqrt of the accuracy
-  p = std::min((p + 7) / 8 * 8, kMaxP);  // expansions use a multiple of 8 terms (rounded up)
+  const int p = fmm_length(order, precision);
   if (leaf <= 0) leaf = 64;
   if (!g->fmm) g->fmm = new FmmPlan();
-  FmmTree *&tp = g->fmm->trees[p];
+  FmmTree *&tp = g->fmm->trees[std::make_pair(p, leaf)];
   if (!tp) {
     tp = new FmmTree();
     const int rc = build_tree(g, p, leaf, *tp, s);

@@ -424,11 +424,30 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
   ss.mem = &g->sm;
   ss.pairs_per_apply = (long long)nrhs * g->M * (long long)g->M;
   const int method = o.method;
-  ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out, hipStream_t st) {
-    return apply_operator(g, kind, precision, method, 1, 1.0, nrhs, in, out, st);
-  };
   std::vector<double> rel;
-  return solve_systems(ss, o, f, x, rel, info, s);
+  if (!o.l2_scaling) {
+    ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out,
+                                       hipStream_t st) {
+      return apply_operator(g, kind, precision, method, 1, 1.0, nrhs, in, out, st);
+    };
+    return solve_systems(ss, o, f, x, rel, info, s);
+  }
+  // L2 rescaling: GMRES on (D A D^-1)(D x) = D f with D = diag(sqrt(w)), the trapezoidal
+  // discretisation of the L2 inner product on the curves; then x = D^-1 (D x)
+  const int comps = (kind & 1) ? 2 : 1;
+  BIE_TRY(g->ws_scale.reserve(2 * (size_t)nrhs * n * sizeof(double)));
+  double *fs = g->ws_scale.as<double>(), *tmp = fs + (size_t)nrhs * n;
+  BIE_TRY(scale_sqrtw(g, comps, nrhs, 0, f, fs, s));
+  ss.apply = [g, kind, method, nrhs, comps, tmp](int precision, const double *in, double *out,
+                                                 hipStream_t st) {
+    BIE_TRY(scale_sqrtw(g, comps, nrhs, 1, in, tmp, st));
+    BIE_TRY(apply_operator(g, kind, precision, method, 1, 1.0, nrhs, tmp, out, st));
+    return scale_sqrtw(g, comps, nrhs, 0, out, out, st);
+  };
+  const int rc = solve_systems(ss, o, fs, x, rel, info, s);
+  if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+  BIE_TRY(scale_sqrtw(g, comps, nrhs, 1, x, x, s));
+  return rc;
 }
 
 }  // namespace bie

@@ -19,6 +19,8 @@ constexpr int kSub = 4;                // workgroups per chunk in the segmented 
 constexpr int kChunk = kSub * kBlock;  // entries per chunk of a segmented vector
 
 void set_error(const std::string &msg);
+int check_opts(const bie_opts &o);       // BIE_EINVAL (message set) for invalid options
+int effective_order(const bie_opts &o);  // FMM expansion order from fmm_eps or fmm_order
 
 #define BIE_HIP_CHECK(call)                                                              \
   do {                                                                                   \
@@ -81,10 +83,30 @@ struct SysSet {
   std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
 };
 
+// Resolution warning thresholds: a node closer than kResolveGap node spacings of another body
+// (trapezoidal error about exp(-2 pi kResolveGap) ~ 6e-9 there), or a trapezoidal turning
+// number off 2 pi by more than kResolveTurn (relative).
+constexpr double kResolveGap = 3.0;
+constexpr double kResolveTurn = 1e-8;
+
+// Checks of curve samples (host [6][M]: x, y, x', y', x'', y'') and optional read-off points
+// (host [N][2]) before a geometry is built (checks.cpp): BIE_EINVAL (msg set) for non-finite
+// samples, a clockwise body or a read-off point outside its body's node polygon; else
+// BIE_ERESOLVE (msg set) for a turning number off 2 pi by more than kResolveTurn or a node
+// closer than kResolveGap node spacings of another body; else BIE_OK.
+int check_curves(int N, const int32_t *nodes_per_body, const double *curve,
+                 const double *interior, std::string &msg);
+
 }  // namespace bie
 
+struct bie_ctx;
+
 struct bie_geom {
+  bie_ctx *ctx = nullptr;  // owning context (NULL: created by bie_geom_create)
   int N = 0, M = 0, device = 0;
+  // process-unique id given at creation: caches keyed on a geometry (batched-apply plans) use
+  // it, never the address, which a later geometry may reuse
+  unsigned long long gen = 0;
   std::vector<int> h_body_ptr;  // host copy [N+1]
   int max_nb = 0;               // nodes of the largest body
   int max_nodes = 0;            // largest n_b
@@ -112,6 +134,7 @@ struct bie_geom {
   long long seg_len = -1;
   bie::DevBuf ws_out;     // solver outputs (densities, rhs) for solve entry points
   bie::DevBuf ws_read;    // read-off partial sums [split][rhs][body][comp]
+  bie::DevBuf ws_scale;   // L2-scaled solves: scaled rhs and the unscaled apply input
   bie::FmmPlan *fmm = nullptr;
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box
@@ -126,6 +149,9 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
                    int nrhs, const double *mu, double *out, hipStream_t s);
 int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double *dens,
                      hipStream_t s);
+// out = D in, or D^-1 in with inverse, D = diag(sqrt(w)) per node and component ([nrhs][M comps])
+int scale_sqrtw(bie_geom *g, int comps, int nrhs, int inverse, const double *in, double *out,
+                hipStream_t s);
 int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t s);
 int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
                 bool rigid, double *res, hipStream_t st);
@@ -169,6 +195,9 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
 int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *mu, double *s64,
                   double *partial, hipStream_t s, int order, int leaf);
 void fmm_destroy(FmmPlan *p);
+// device bytes of g's FMM state (tree and work area) for one solve kind, precision, order and
+// leaf size: the actual size where the tree exists, else an upper estimate
+long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf);
 int fmm_current_order();
 
 
@@ -178,6 +207,7 @@ struct MultiItem {
   int kind, nrhs;
   long long io;  // start of the item's rhs block in the flat vectors (64-byte aligned)
   bool fmm;      // applied by the single-geometry FMM path
+  int fmm_order = 40, fmm_leaf = 64;  // its expansion order and leaf population (FMM items)
 };
 struct MultiPlan;
 int multi_apply(MultiPlan *&plan, const std::vector<MultiItem> &items,

@@ -807,6 +807,26 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
   return BIE_OK;
 }
 
+// out = D in (inverse: D^-1 in), D = diag(sqrt(w)) on every component of every node.
+__global__ void k_scale_sqrtw(long long total, int M, int comps, const double *__restrict__ w,
+                              int inverse, const double *__restrict__ in,
+                              double *__restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int node = (int)((t % ((long long)M * comps)) / comps);
+  const double d = sqrt(w[node]);
+  out[t] = inverse ? in[t] / d : in[t] * d;
+}
+
+int scale_sqrtw(bie_geom *g, int comps, int nrhs, int inverse, const double *in, double *out,
+                hipStream_t st) {
+  const long long tot = (long long)nrhs * g->M * comps;
+  hipLaunchKernelGGL(k_scale_sqrtw, dim3(nblocks(tot)), dim3(kBlock), 0, st, tot, g->M, comps,
+                     g->w, inverse, in, out);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
 int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double *dens,
                      hipStream_t st) {
   const long long tot = (long long)nrhs * g->M;

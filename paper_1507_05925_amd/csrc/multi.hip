@@ -42,8 +42,12 @@ struct MultiPlan {
   int *far_task[2] = {nullptr, nullptr}, *epi_task[2] = {nullptr, nullptr}, *pack_task = nullptr;
   ItemDesc *desc = nullptr;
   long long nslots[2] = {0, 0};
-  std::vector<const void *> key_geoms;
+  // the plan is reused while every item matches: geometry id, kind, rhs count, method and
+  // offset of its block, and the active flags
+  std::vector<unsigned long long> key_gen;
   std::vector<int> key_kind, key_nrhs;
+  std::vector<char> key_fmm;
+  std::vector<long long> key_io;
   std::vector<char> key_active;
   bool valid = false;
 };
@@ -521,20 +525,25 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
                 int precision, const double *in, double *out, long long Ntot, hipStream_t s) {
   if (!P) P = new MultiPlan();
   const int n = (int)items.size();
-  bool same = P->valid && (int)P->key_geoms.size() == n && P->key_active == active;
+  bool same = P->valid && (int)P->key_gen.size() == n && P->key_active == active;
   for (int i = 0; same && i < n; ++i)
-    same = P->key_geoms[i] == items[i].g && P->key_kind[i] == items[i].kind &&
-           P->key_nrhs[i] == items[i].nrhs;
+    same = P->key_gen[i] == items[i].g->gen && P->key_kind[i] == items[i].kind &&
+           P->key_nrhs[i] == items[i].nrhs && P->key_fmm[i] == (char)items[i].fmm &&
+           P->key_io[i] == items[i].io;
   if (!same) {
     P->valid = false;
     BIE_TRY(build_plan(*P, items, active, s));
-    P->key_geoms.assign(n, nullptr);
-    P->key_kind.assign(n, 0);
-    P->key_nrhs.assign(n, 0);
+    P->key_gen.resize(n);
+    P->key_kind.resize(n);
+    P->key_nrhs.resize(n);
+    P->key_fmm.resize(n);
+    P->key_io.resize(n);
     for (int i = 0; i < n; ++i) {
-      P->key_geoms[i] = items[i].g;
+      P->key_gen[i] = items[i].g->gen;
       P->key_kind[i] = items[i].kind;
       P->key_nrhs[i] = items[i].nrhs;
+      P->key_fmm[i] = (char)items[i].fmm;
+      P->key_io[i] = items[i].io;
     }
     P->key_active = active;
     P->valid = true;
@@ -616,9 +625,12 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
   for (int k = 0; k < used; ++k) BIE_HIP_CHECK(hipStreamWaitEvent(P->pool[k], P->fork, 0));
   int rc = BIE_OK;
   for (int i = 0; i < n && rc == BIE_OK; ++i)
-    if (on[i] >= 0)
+    if (on[i] >= 0) {
+      items[i].g->fmm_order = items[i].fmm_order;  // the caller's expansion order and leaf size
+      items[i].g->fmm_leaf = items[i].fmm_leaf;
       rc = apply_operator(items[i].g, items[i].kind, precision, BIE_FMM, 1, 1.0, items[i].nrhs,
                           in + items[i].io, out + items[i].io, P->pool[on[i]]);
+    }
   for (int k = 0; k < used; ++k) {
     BIE_HIP_CHECK(hipEventRecord(P->join[k], P->pool[k]));
     BIE_HIP_CHECK(hipStreamWaitEvent(s, P->join[k], 0));

@@ -22,7 +22,7 @@ import math
 import numpy as np
 
 SEEDS = {"elastance_small": 150701, "elastance_starfish": 150702, "mobility_ellipses": 150703,
-         "batched": 150704, "serving": 150705}
+         "batched": 150704, "serving": 150705, "fmm_items": 150706, "near_touching": 150707}
 
 
 @dataclasses.dataclass
@@ -389,3 +389,30 @@ def serving_sessions(n_requests, seed=SEEDS["serving"]):
         out.append((kind, c, qs))
         total += nq
     return out
+
+
+def fmm_items(seed=SEEDS["fmm_items"]):
+    """Items above the 32,768-node threshold of BIE_AUTO (so batches and the server send them
+    through the FMM): 130 starfish x 256 nodes (33,280; two charge vectors q ~ N(0,1)) and 66
+    ellipses x 512 nodes (33,792; two (F, T) vectors, F zero-sum), with the recipes of the
+    1000-starfish and 200-ellipse workloads; plus two small direct items (3 ellipses x 128,
+    elastance; a 5-body mixed grid, mobility) so that FMM and direct items share a batch."""
+    rng = np.random.default_rng(seed)
+    star = starfish_grid(rng, 130, 256, cols=13)
+    ell = ellipse_grid(rng, 66, 512, cols=11)
+    small_e = random_ellipses_box(rng, 3, 128, gap=0.5)
+    small_m = mixed_grid(rng, 5, np.array([64, 96, 128, 160, 64]))
+    return [("elastance", star, random_charges(rng, 130, 2)),
+            ("mobility", ell, random_forces(rng, 66, 2)),
+            ("elastance", small_e, random_charges(rng, 3, 1)),
+            ("mobility", small_m, random_forces(rng, 5, 1))]
+
+
+def near_touching_forces(seed=SEEDS["near_touching"]):
+    """Two (F, T) vectors for the two unit discs at gap 0.005: one seeded F ~ N(0,1)^2 (not
+    zero-sum), T ~ N(0,1), and one net-force-free pair F_1 = -F_2 = (1, 0), T = 0 (the
+    squeeze motion that the lubrication gap resists)."""
+    rng = np.random.default_rng(seed)
+    a = random_forces(rng, 2, 1, zero_total=False)[0]
+    b = np.array([1.0, 0.0, 0.0, -1.0, 0.0, 0.0])
+    return np.stack([a, b])

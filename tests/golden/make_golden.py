@@ -6,6 +6,8 @@ paper_1507_05925_amd.workloads; nothing here comes from the HIP path.
   python tests/golden/make_golden.py starfish   # 1000 starfish x 256 nodes, q ~ N(0,1) -> phi
   python tests/golden/make_golden.py ellipses   # 200 ellipses x 512 nodes, (F, T) -> (v, omega)
   python tests/golden/make_golden.py batched    # columns of P / M of the largest batched geometries
+  python tests/golden/make_golden.py fmm_items  # items above the FMM threshold of BIE_AUTO
+  python tests/golden/make_golden.py near_touching  # two discs at gap 0.005, mobility
 """
 import json
 import os
@@ -98,7 +100,64 @@ def batched():
     _dump("batched_columns.json", out)
 
 
+def fmm_items():
+    """Outputs for the items of workloads.fmm_items() (two of them above the FMM threshold)."""
+    out = {"workload": "130 starfish x 256 (2 q), 66 ellipses x 512 (2 (F, T)), 3 ellipses x 128 "
+                       "(1 q), 5-body mixed grid (1 (F, T))",
+           "generator": "paper_1507_05925_amd.workloads.fmm_items()",
+           "seed": wl.SEEDS["fmm_items"], "oracle": "oracle.matfree (float64, GMRES rtol 1e-13)",
+           "items": []}
+    t = time.time()
+    for kind, c, inputs in wl.fmm_items():
+        geo = ny.geometry_of(c)
+        vals, its = [], []
+        for v in inputs:
+            if kind == "elastance":
+                r = mf.elastance_solve(geo, v, tol=1e-13, restart=100, maxiter=10)
+                vals.append([float(x) for x in r["phi"]])
+            else:
+                r = mf.mobility_solve(geo, v, tol=1e-13, restart=150, maxiter=10)
+                vals.append([float(x) for x in r["VW"]])
+            its.append(r["iters"])
+        out["items"].append({"kind": kind, "M": geo["M"], "N": geo["N"], "values": vals,
+                             "gmres_iters": its})
+        print(kind, geo["M"], its, time.time() - t)
+    out["seconds"] = time.time() - t
+    _dump("fmm_items.json", out)
+
+
+def near_touching():
+    """(v, omega) of the two unit discs at gap 0.005, 6144 nodes per disc, for the table row's
+    forces and torques (two-disc mobility table) and the seeded vectors of
+    workloads.near_touching_forces()."""
+    tab = json.load(open(os.path.join(HERE, "two_disc_tables.json")))["mobility"]["rows"][2]
+    c = wl.two_discs(0.005, 6144)
+    geo = ny.geometry_of(c)
+    inputs = [np.array([tab["F11"], tab["F21"], tab["T1"], -tab["F11"], -tab["F21"], tab["T2"]])]
+    inputs += list(wl.near_touching_forces())
+    t = time.time()
+    vals, its, res = [], [], []
+    for FT in inputs:
+        r = mf.mobility_solve(geo, FT, tol=1e-13, restart=400, maxiter=10)
+        rr = mf.stokes_apply(geo, r["mu"]) - r["f"]
+        vals.append([float(x) for x in r["VW"]])
+        its.append(r["iters"])
+        res.append(float(np.linalg.norm(rr) / np.linalg.norm(r["f"])))
+        print(its[-1], res[-1], time.time() - t)
+    _dump("two_discs_0005_vw.json", {
+        "workload": "mobility, two unit discs at gap 0.005, 6144 nodes per disc",
+        "generator": "paper_1507_05925_amd.workloads.two_discs(0.005, 6144); inputs: the "
+                     "two-disc mobility table row at d = 0.005, then "
+                     "workloads.near_touching_forces()",
+        "seed": wl.SEEDS["near_touching"], "oracle": "oracle.matfree.mobility_solve (float64, "
+                                                      "GMRES rtol 1e-13)",
+        "inputs": [[float(x) for x in v] for v in inputs], "VW": vals, "gmres_iters": its,
+        "rel_residual": res, "seconds": time.time() - t})
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["starfish", "ellipses", "batched"]
+    jobs = {"starfish": starfish, "ellipses": ellipses, "batched": batched,
+            "fmm_items": fmm_items, "near_touching": near_touching}
+    which = sys.argv[1:] or list(jobs)
     for w in which:
-        {"starfish": starfish, "ellipses": ellipses, "batched": batched}[w]()
+        jobs[w]()

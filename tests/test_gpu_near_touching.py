@@ -52,3 +52,20 @@ def test_two_discs_gap_0005_mobility():
     got = VW[0:2] - VW[3:5]
     assert np.abs(got - dv).max() / np.abs(dv).max() < 5e-6, (got, dv, info)
     assert abs(VW[2] - tab["omega1"]) < 2e-5 and abs(VW[5] - tab["omega2"]) < 2e-5, (VW, info)
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_two_discs_gap_0005_mobility_vs_oracle(precision, tol):
+    """(v, omega) at gap 0.005 against the stored float64 oracle solution of the same discrete
+    system (tests/golden/two_discs_0005_vw.json, oracle/matfree only): the table row's forces and
+    torques, a seeded (F, T) with net force, and the squeeze pair F_1 = -F_2."""
+    gold = json.load(open(os.path.join(GOLDEN, "two_discs_0005_vw.json")))
+    g = bie2d.Geometry.from_curves(wl.two_discs(D, NODES))
+    o = bie2d.default_opts(precision=precision, tol=1e-13, restart=300, max_iter=6000,
+                           max_refine=30)
+    VW, info = bie2d.bie_mobility_solve(g, dev(gold["inputs"]), o)
+    VW = VW.cpu().numpy()
+    for k, ref in enumerate(gold["VW"]):
+        ref = np.array(ref)
+        err = float(np.abs(VW[k] - ref).max() / np.abs(ref).max())
+        assert err < tol, (k, err, info)

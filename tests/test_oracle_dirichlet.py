@@ -163,6 +163,53 @@ def test_capacitance_two_disc_exact(d, n, tol):
     assert abs(res["u_inf"] - 0.5 * (phi[0] + phi[1])) < 1e-12
 
 
+def _u_exact(d, phi, pts):
+    """The two-disc test's exact exterior potential (bipolar solution):
+    u_ex(x) = -(v1 / 2 pi) log(|x - (alpha, 0)| / |x + (alpha, 0)|) + v2 with
+    alpha = sqrt(d + d^2/4), v1 = pi (phi2 - phi1) / log(|x0 + (alpha, 0)| / |x0 - (alpha, 0)|),
+    v2 = (phi1 + phi2) / 2, x0 = (d/2, 0) (the printed "(d/2)" read as the point)."""
+    al = math.sqrt(d + d * d / 4)
+    x0 = d / 2
+    v1 = math.pi * (phi[1] - phi[0]) / math.log((x0 + al) / (al - x0))
+    p = np.asarray(pts, dtype=np.float64)
+    rm = np.hypot(p[:, 0] - al, p[:, 1])
+    rp = np.hypot(p[:, 0] + al, p[:, 1])
+    return -(v1 / (2 * math.pi)) * np.log(rm / rp) + 0.5 * (phi[0] + phi[1])
+
+
+@pytest.mark.parametrize("d,n,tol", [(0.5, 256, 1e-11), (0.05, 1024, 1e-9)])
+def test_capacitance_field_two_disc_exact(d, n, tol):
+    """capacitance_field at exterior points equals the exact two-disc potential: near the gap,
+    above and below the discs, and far out (where it tends to u_inf = v2)."""
+    geo = _geo(wl.two_discs(d, n))
+    phi = np.array([0.209, -0.123])
+    res = dr.capacitance_solve(geo, phi)
+    c = 1.0 + d / 2
+    pts = np.array([[0.0, 0.6], [0.0, -1.5], [-c, 1.4], [c + 1.3, 0.2], [-c - 1.5, -0.7],
+                    [2.0, 2.0], [40.0, -30.0]])
+    u = dr.capacitance_field(geo, res, pts)
+    ue = _u_exact(d, phi, pts)
+    assert np.abs(u - ue).max() < tol * np.abs(phi).max(), (u, ue)
+    # a planted mistake: the double-layer term with the wrong sign misses by O(1e-2)
+    wrong = -dr.double_layer(geo, res["mu"], pts) + (u - dr.double_layer(geo, res["mu"], pts))
+    assert np.abs(wrong - ue).max() > 1e-3
+
+
+def test_capacitance_field_double_layer_identity():
+    """D[1] = -1 inside a curve and 0 outside (the discrete Gauss law through double_layer,
+    the kernel capacitance_field evaluates), and capacitance_field of the uniform data on one
+    disc is the constant datum everywhere outside (q = 0, u_inf = phi)."""
+    geo = _geo(wl.two_discs(0.5, 256))
+    body0 = (geo["body"] == 0).astype(float)
+    inside = dr.double_layer(geo, body0, np.array([[-1.25, 0.3], [-1.0, -0.5]]))
+    outside = dr.double_layer(geo, body0, np.array([[1.25, 0.0], [0.0, 3.0], [-4.0, 0.0]]))
+    assert np.abs(inside + 1.0).max() < 1e-13 and np.abs(outside).max() < 1e-13
+    one = _geo(wl.single_disc(128, R=0.7, cx=0.3, cy=-0.2))
+    res = dr.capacitance_solve(one, [0.42])
+    u = dr.capacitance_field(one, res, np.array([[1.5, 0.0], [0.3, 2.0], [-5.0, 4.0]]))
+    assert np.abs(u - 0.42).max() < 1e-13
+
+
 def test_capacitance_table1():
     """The capacitance solve with the prescribed 0.209 and -0.123 reproduces the printed q1
     (= -q / (2 pi)) to its six digits."""
