@@ -182,6 +182,22 @@ int bie_laplace_apply(bie_geom *g, int precision, int method, int with_L, int nr
 int bie_stokes_apply(bie_geom *g, int precision, int method, int with_L, int nrhs,
                      const double *mu, double *out, void *stream);
 
+/* ---- the same apply without allocation ----------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same result as bie_laplace_apply (kind 0) or
+ * bie_stokes_apply (kind 1) with method BIE_DIRECT and the same arguments (it runs the same
+ * kernels), but its workspace (strengths and far-field partial sums) is a fixed 64 MiB array in
+ * device memory that the library holds per device for the life of the process; the call
+ * allocates and frees nothing (and records no profiling events). The workspace it needs,
+ * 12 nrhs len + 8 nsplit R len bytes (len = M or 2M, R = 8 Laplace / 4 Stokes rhs per pass,
+ * nsplit <= 64 source splits of the geometry), must fit: else BIE_EINVAL, with the size in the
+ * message. All calls on one device share that array: calls that overlap on one device (any
+ * geometry, any stream) race and must be ordered by the caller. Nothing in it needs clearing
+ * between calls (every entry a call reads, it writes first). The geometry itself must already
+ * exist (bie_geom_create allocates). */
+int bie_apply_noalloc(bie_geom *g, int kind, int precision, int with_L, int nrhs,
+                      const double *mu, double *out, void *stream);
+
 /* ---- a2: incident densities and right-hand sides -------------------------------------------
  * sigma_k = q_j/|Gamma_j| (eq. sigma); f = -(1/2 I + K) sigma.  q (device) [nrhs][N];
  * sigma, f (device) [nrhs][M]; either output may be NULL.

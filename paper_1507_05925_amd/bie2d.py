@@ -79,6 +79,7 @@ _SIGS = {
     "bie_geom_set_fmm": ([_P, _I, _I], _I),
     "bie_laplace_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
     "bie_stokes_apply": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
+    "bie_apply_noalloc": ([_P, _I, _I, _I, _I, _P, _P, _P], _I),
     "bie_elastance_rhs": ([_P, _I, _P, _P, _P, _P], _I),
     "bie_mobility_rhs": ([_P, _I, _P, _P, _P, _P], _I),
     "bie_laplace_potential": ([_P, _I, _P, _P, _P], _I),
@@ -333,6 +334,16 @@ def bie_stokes_apply(g, mu, precision=BIE_FP64, method=BIE_DIRECT, with_L=True, 
     out = torch.empty_like(mu) if out is None else out
     _check(lib().bie_stokes_apply(g.handle, precision, method, int(with_L), _rows(mu, 2 * g.M),
                                   _dptr(mu, 2 * g.M, "mu"), _dptr(out, 2 * g.M, "out"), _stream()))
+    return out
+
+
+def bie_apply_noalloc(g, kind, mu, precision=BIE_FP64, with_L=True, out=None):
+    """The direct apply with the library's fixed per-device workspace (no allocation)."""
+    torch = _torch()
+    n = g.M if kind == 0 else 2 * g.M
+    out = torch.empty_like(mu) if out is None else out
+    _check(lib().bie_apply_noalloc(g.handle, int(kind), precision, int(with_L), _rows(mu, n),
+                                   _dptr(mu, n, "mu"), _dptr(out, n, "out"), _stream()))
     return out
 
 

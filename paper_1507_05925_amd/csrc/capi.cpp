@@ -111,18 +111,6 @@ int effective_order(const bie_opts &o) {
   return std::max(8, std::min(64, p));
 }
 
-// Makes `dev` the current device for the lifetime of the guard (restoring the previous one).
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess)
-      prev = cur;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 }  // namespace bie
 

@@ -19,6 +19,19 @@ constexpr int kSub = 4;                // workgroups per chunk in the segmented 
 constexpr int kChunk = kSub * kBlock;  // entries per chunk of a segmented vector
 
 void set_error(const std::string &msg);
+// Makes `dev` the current device for the lifetime of the guard (restoring the previous one).
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess)
+      prev = cur;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
 int check_opts(const bie_opts &o);       // BIE_EINVAL (message set) for invalid options
 int effective_order(const bie_opts &o);  // FMM expansion order from fmm_eps or fmm_order
 
@@ -147,6 +160,12 @@ namespace bie {
 // completed double layers of the capacitance and resistance problems (Laplace, Stokes)
 int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L, double alpha,
                    int nrhs, const double *mu, double *out, hipStream_t s);
+// the same with a caller-provided workspace of ws_bytes >= apply_workspace_bytes(...) bytes
+// (kinds 0 and 1; method BIE_DIRECT or BIE_FMM)
+int apply_operator_ws(bie_geom *g, int kind, int precision, int method, int with_L,
+                      double alpha, int nrhs, const double *mu, double *out, void *ws,
+                      size_t ws_bytes, hipStream_t s);
+size_t apply_workspace_bytes(const bie_geom *g, int kind, int method, int nrhs);
 int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double *dens,
                      hipStream_t s);
 // out = D in, or D^-1 in with inverse, D = diag(sqrt(w)) per node and component ([nrhs][M comps])
@@ -217,6 +236,11 @@ void multi_destroy(MultiPlan *p);
 inline long long align8(long long v) { return (v + 7) / 8 * 8; }
 
 // ---- profile.cpp: optional per-class launch timing ------------------------------------------
+// While a ProfSuspend lives, this thread records no profiling events (no event is created).
+struct ProfSuspend {
+  ProfSuspend();
+  ~ProfSuspend();
+};
 struct ProfScope {
   int kclass;
   hipStream_t s;

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "internal.h"
 
@@ -738,11 +740,34 @@ int geometry_build(bie_geom *g, const double *curve, const double *interior, hip
   return BIE_OK;
 }
 
+// Workspace bytes of one apply: strengths s64 [nrhs][len], s32 [nrhs][len], then (64-byte
+// aligned) the far-field partials [nsplit][maxR][len].
+size_t apply_workspace_bytes(const bie_geom *g, int kind, int method, int nrhs) {
+  const long long len = (long long)g->M * (kind == 0 ? 1 : 2);
+  const int maxR = kind == 0 ? 8 : 4;
+  const int nsplit = method == BIE_FMM ? 1 : g->nsplit;
+  return (size_t)nrhs * len * (sizeof(double) + sizeof(float)) + 64 +
+         (size_t)nsplit * maxR * len * sizeof(double);
+}
+
 // Far-field partials per rhs chunk and the epilogue. Chunks of <= 8 (Laplace) / 4 (Stokes) rhs
 // share each pair's geometry work.
 int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L, double alpha,
                    int nrhs, const double *mu, double *out, hipStream_t st) {
   if (kind == 2 || kind == 3) return dl_apply(g, kind - 2, with_L, alpha, nrhs, mu, out, st);
+  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
+  if (nrhs < 1) {
+    set_error("apply: nrhs >= 1 required");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(g->ws_apply.reserve(apply_workspace_bytes(g, kind, method, nrhs)));
+  return apply_operator_ws(g, kind, precision, method, with_L, alpha, nrhs, mu, out,
+                           g->ws_apply.ptr, g->ws_apply.bytes, st);
+}
+
+int apply_operator_ws(bie_geom *g, int kind, int precision, int method, int with_L,
+                      double alpha, int nrhs, const double *mu, double *out, void *ws,
+                      size_t ws_bytes, hipStream_t st) {
   if (precision != BIE_FP64 && precision != BIE_MIXED) {
     set_error("precision must be BIE_FP64 or BIE_MIXED");
     return BIE_EINVAL;
@@ -760,11 +785,11 @@ int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L,
   const long long len = (long long)g->M * comps;
   const int maxR = kind == 0 ? 8 : 4;
   const int nsplit = method == BIE_FMM ? 1 : g->nsplit;
-  // workspace: s64 [nrhs][len], s32 [nrhs][len], partial [nsplit][maxR][len]
-  const size_t need = (size_t)nrhs * len * (sizeof(double) + sizeof(float)) + 64 +
-                      (size_t)nsplit * maxR * len * sizeof(double);
-  BIE_TRY(g->ws_apply.reserve(need));
-  double *s64 = g->ws_apply.as<double>();
+  if (!ws || ws_bytes < apply_workspace_bytes(g, kind, method, nrhs)) {
+    set_error("apply: workspace too small");
+    return BIE_EINVAL;
+  }
+  double *s64 = static_cast<double *>(ws);
   float *s32 = reinterpret_cast<float *>(s64 + (size_t)nrhs * len);
   double *partial = reinterpret_cast<double *>(
       (reinterpret_cast<uintptr_t>(s32 + (size_t)nrhs * len) + 63) & ~uintptr_t(63));
@@ -891,3 +916,66 @@ int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, h
 }
 
 }  // namespace bie
+
+// ---- the apply without allocation ---------------------------------------------------------
+// The direct apply's workspace (strengths and far-field partials) lives in this file-scope
+// device array instead of memory the library allocates. Each device holds its own copy for the
+// life of the process; host code uses only the device address that hipGetSymbolAddress returns
+// for it (the array's name is a host-side stand-in, not a device address).
+namespace bie {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device (looked up once per device, with it current).
+int scratch_on_current_device(char **out) {
+  int dev = -1;
+  BIE_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("bie_apply_noalloc: device ordinal out of range");
+    return BIE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    BIE_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BIE_OK;
+}
+
+}  // namespace
+}  // namespace bie
+
+extern "C" int bie_apply_noalloc(bie_geom *g, int kind, int precision, int with_L, int nrhs,
+                                 const double *mu, double *out, void *stream) {
+  using namespace bie;
+  if (!g || (kind != 0 && kind != 1) || nrhs < 1 || !mu || !out || mu == out) {
+    set_error("bie_apply_noalloc: need a geometry, kind 0 or 1, nrhs >= 1 and distinct "
+              "non-NULL mu, out");
+    return BIE_EINVAL;
+  }
+  if (precision != BIE_FP64 && precision != BIE_MIXED) {
+    set_error("bie_apply_noalloc: precision must be BIE_FP64 or BIE_MIXED");
+    return BIE_EINVAL;
+  }
+  const size_t need = apply_workspace_bytes(g, kind, BIE_DIRECT, nrhs);
+  if (need > kScratchBytes) {
+    set_error("bie_apply_noalloc: this apply needs " + std::to_string(need) +
+              " bytes of scratch, more than its fixed " + std::to_string(kScratchBytes) +
+              " (use fewer right-hand sides per call or bie_laplace_apply / bie_stokes_apply)");
+    return BIE_EINVAL;
+  }
+  DeviceGuard dg(g->device);
+  char *ws = nullptr;
+  BIE_TRY(scratch_on_current_device(&ws));
+  ProfSuspend quiet;  // profiling events would be created (allocated) on first use
+  return apply_operator_ws(g, kind, precision, BIE_DIRECT, with_L ? 1 : 0, 1.0, nrhs, mu, out,
+                           ws, kScratchBytes, reinterpret_cast<hipStream_t>(stream));
+}

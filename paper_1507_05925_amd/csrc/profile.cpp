@@ -55,10 +55,15 @@ int drain(ClassStats &c) {
   return BIE_OK;
 }
 
+thread_local int g_suspend = 0;  // > 0 inside a ProfSuspend
+
 }  // namespace
 
+ProfSuspend::ProfSuspend() { ++g_suspend; }
+ProfSuspend::~ProfSuspend() { --g_suspend; }
+
 ProfScope::ProfScope(int k, hipStream_t st, long long p)
-    : kclass(k), s(st), pairs(p), on(g_on && ((g_mask >> k) & 1u)) {
+    : kclass(k), s(st), pairs(p), on(g_on && ((g_mask >> k) & 1u) && g_suspend == 0) {
   if (!on) return;
   on = g_seen[k]++ % g_every == 0;
   if (!on) return;
