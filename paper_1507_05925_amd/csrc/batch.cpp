@@ -155,7 +155,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
   BIE_TRY(vec_axpby(Ntot, 1.0, mu, 1.0, dens, s));
   for (int i = 0; i < nitems; ++i) {
-    BIE_TRY(read_off(items[i].g, items[i].kind, items[i].nrhs, dens + item_off[i], items[i].out, s));
+    BIE_TRY(read_off(items[i].g, items[i].kind, items[i].nrhs, dens + item_off[i], items[i].out, s,
+                     mitems[i].fmm ? BIE_FMM : BIE_DIRECT));
     if (items[i].kind == 1 && o.viscosity != 1.0)  // velocities for the caller's viscosity
       BIE_TRY(vec_axpby((long long)items[i].nrhs * 3 * items[i].g->N, 0.0, items[i].out,
                         1.0 / o.viscosity, items[i].out, s));

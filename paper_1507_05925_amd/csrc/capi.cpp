@@ -502,7 +502,7 @@ static int field_entry(bie_geom *g, int kind, int nrhs, const double *in, const 
   double *dens = g->ws_out.as<double>();
   BIE_TRY(incident_density(g, kind, nrhs, in, dens, s));
   BIE_TRY(vec_axpby(len * nrhs, 1.0, mu, 1.0, dens, s));
-  return eval_points(g, kind, nrhs, dens, npts, pts, false, u, s);
+  return eval_points(g, kind, nrhs, dens, npts, pts, false, u, s, BIE_AUTO);
 }
 
 int bie_laplace_potential(bie_geom *g, int nrhs, const double *dens, double *phi, void *stream) {
@@ -600,7 +600,7 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   int rc = solve_system(g, kind, o, nrhs, f, mu, info, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
   BIE_TRY(vec_axpby((long long)nrhs * len, 1.0, mu, 1.0, dens, s));  // dens = mu + incident
-  BIE_TRY(read_off(g, kind, nrhs, dens, res, s));
+  BIE_TRY(read_off(g, kind, nrhs, dens, res, s, o.method));
   if (kind == 1 && o.viscosity != 1.0)  // velocities of the viscosity-1 problem, rescaled
     BIE_TRY(vec_axpby((long long)nrhs * 3 * g->N, 0.0, res, 1.0 / o.viscosity, res, s));
   BIE_HIP_CHECK(hipStreamSynchronize(s));

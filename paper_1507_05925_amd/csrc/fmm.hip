@@ -66,6 +66,25 @@ struct FmmTree {
   double *fact_out = nullptr, *fact_in = nullptr;  // (-1)^n c^n / n!  and  c^n / n!
   double *inv_h = nullptr;  // [L+1]
   DevBuf work;              // charges + expansions
+  // evaluation at arbitrary points (treecode over this tree): per box its level, centre,
+  // children and run [lo, hi) of sorted nodes (host); the log-expansion factors
+  // T_log[m] = (m - 1)! / s^m (device); the interaction lists of the geometry's read-off points
+  std::vector<int> h_level, h_child, h_lo, h_hi;
+  std::vector<double2> h_center;
+  double *T_log = nullptr;
+  struct PointLists *rd = nullptr;
+};
+
+// Interaction lists of a set of evaluation points: boxes whose multipoles are evaluated at the
+// point (every box at level >= 2 with |z - c| >= sqrt(2) h, i.e. twice its half-diagonal, whose
+// parent is not), and the runs [k0, k1) of sorted nodes of the remaining leaves, summed directly.
+struct PointLists {
+  int npts = 0;
+  long long nbox_total = 0, direct_pairs = 0;
+  DevBuf buf;
+  int *box_ptr = nullptr, *run_ptr = nullptr;  // [npts + 1] each
+  int2 *box = nullptr;                         // (box, level)
+  int2 *run = nullptr;                         // [k0, k1)
 };
 
 struct FmmPlan {
@@ -80,6 +99,10 @@ struct FmmPlan {
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     for (auto &kv : trees) {
+      if (kv.second->rd) {
+        kv.second->rd->buf.release();
+        delete kv.second->rd;
+      }
       kv.second->buf.release();
       kv.second->work.release();
       delete kv.second;
@@ -940,6 +963,175 @@ __global__ __launch_bounds__(64) void k_l2p_stokes(
   out[(size_t)r * 2 * M + 2 * i + 1] -= fy / kPi;
 }
 
+// ---- evaluation at arbitrary points (read-off, off-surface field) ----------------------------
+// The single-layer potentials at points z off the curves, by a treecode over this tree: the
+// multipoles of the boxes in the point's list (P2M and M2M of the density's strengths, as in
+// the apply) evaluated at z, plus the nodes of the remaining leaves directly.
+//   Laplace: sum_k q_k log(z - zeta_k) = a_0 log(z - c) - sum_{m>=1} a_m (h / (z - c))^m / m,
+//   a_m = sum_k q_k ((zeta_k - c)/h)^m = u_m m! / s^m (stored u_m), so the m-th term is
+//   u_m T_log[m] t^m with t = h / (z - c), T_log[m] = (m - 1)! / s^m; the potential needs its
+//   real part (log|z - zeta|).
+//   Stokes (traction strengths t_k = w_k (dens_1 + i dens_2)_k as complex numbers f):
+//   sum_k G(z - zeta_k) f_k = (1/4pi) [ -sum f ln|r| + F/2 + (1/2) (z conj(A) - conj(C)) ],
+//   with r = z - zeta, F = sum f, A(z) = sum f / (z - zeta), C(z) = sum f conj(zeta) / (z - zeta)
+//   (the charge sets A and C of the apply), and sum f ln|r| = (L_A + conj(L_B)) / 2 with the log
+//   sums L of the sets A (f) and B (conj f); half the vorticity is -(1/4pi) Im A(z).
+//   Cauchy multipole: A(z) = (1/(z - c)) sum_m u_m (m! / s^m) t^m (T_c).
+
+// Charges in sorted order only: Laplace set r = (w dens, 0); Stokes sets 3r, 3r + 1, 3r + 2 =
+// f, conj f, f conj(z) with f = w (dens_1 + i dens_2).
+__global__ void k_gather_q(int M, int R, int kind, const int *__restrict__ perm,
+                           const double2 *__restrict__ xs, const double *__restrict__ wq,
+                           const double *__restrict__ dens, double2 *__restrict__ Q) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int k = perm[j];
+  const double wk = wq[k];
+  for (int r = 0; r < R; ++r) {
+    if (kind == 0) {
+      Q[(size_t)r * M + j] = make_double2(wk * dens[(size_t)r * M + k], 0.0);
+    } else {
+      const double2 z = xs[j];
+      const double2 f = make_double2(wk * dens[(size_t)r * 2 * M + 2 * k],
+                                     wk * dens[(size_t)r * 2 * M + 2 * k + 1]);
+      Q[(size_t)(3 * r) * M + j] = f;
+      Q[(size_t)(3 * r + 1) * M + j] = make_double2(f.x, -f.y);
+      Q[(size_t)(3 * r + 2) * M + j] = cmul(f, make_double2(z.x, -z.y));
+    }
+  }
+}
+
+__device__ __forceinline__ double2 cdiv1(double2 z) {  // 1 / z
+  const double d = 1.0 / fma(z.x, z.x, z.y * z.y);
+  return make_double2(z.x * d, -z.y * d);
+}
+
+// Wave sum in a fixed order (the same tree for every call).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Laplace: phi(z) = -(1/2pi) sum_k q_k log|z - zeta_k|. Grid (points, R), one wave each.
+template <int P>
+__global__ __launch_bounds__(64) void k_eval_lap(
+    int M, int nbox, double size, const double2 *__restrict__ pts, double ox, double oy,
+    const int *__restrict__ box_ptr, const int2 *__restrict__ boxes,
+    const int *__restrict__ run_ptr, const int2 *__restrict__ runs,
+    const double2 *__restrict__ center, const double *__restrict__ T_log,
+    const double2 *__restrict__ xs, const double2 *__restrict__ Q,
+    const double2 *__restrict__ Mexp, int npts, double *__restrict__ out) {
+  const int p = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const double2 z = make_double2(pts[p].x - ox, pts[p].y - oy);
+  double acc = 0.0;
+  for (int e = box_ptr[p] + lane; e < box_ptr[p + 1]; e += 64) {
+    const int2 bl = boxes[e];
+    const double h = size / (double)(1 << bl.y);
+    const double2 c = center[bl.x];
+    const double2 dz = make_double2(z.x - c.x, z.y - c.y);
+    const double2 id = cdiv1(dz);
+    const double2 t = make_double2(h * id.x, h * id.y);
+    const double2 *u = Mexp + ((size_t)r * nbox + bl.x) * P;
+    double2 S = make_double2(u[P - 1].x * T_log[P - 1], u[P - 1].y * T_log[P - 1]);
+#pragma unroll
+    for (int m = P - 2; m >= 1; --m)
+      S = cfma(S, t, make_double2(u[m].x * T_log[m], u[m].y * T_log[m]));
+    S = cmul(S, t);  // sum_{m>=1} u_m T_log[m] t^m
+    acc += u[0].x * 0.5 * log(fma(dz.x, dz.x, dz.y * dz.y)) - S.x;
+  }
+  const double2 *q = Q + (size_t)r * M;
+  for (int e = run_ptr[p]; e < run_ptr[p + 1]; ++e) {
+    const int2 kr = runs[e];
+    for (int k = kr.x + lane; k < kr.y; k += 64) {
+      const double2 zk = xs[k];
+      const double dx = z.x - zk.x, dy = z.y - zk.y;
+      acc = fma(q[k].x, 0.5 * log(fma(dx, dx, dy * dy)), acc);
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[(size_t)r * npts + p] = -acc / (2.0 * kPi);
+}
+
+// Stokes: u(z) (viscosity 1) and half the vorticity; with rigid, v = u - omega (p - x^c)^perp
+// and omega for body p (out [R][npts][3]), else the velocity (out [R][npts][2]).
+template <int P>
+__global__ __launch_bounds__(64) void k_eval_stk(
+    int M, int nbox, double size, const double2 *__restrict__ pts, double ox, double oy,
+    const int *__restrict__ box_ptr, const int2 *__restrict__ boxes,
+    const int *__restrict__ run_ptr, const int2 *__restrict__ runs,
+    const double2 *__restrict__ center, const double *__restrict__ T_log,
+    const double *__restrict__ T_c, const double2 *__restrict__ xs,
+    const double2 *__restrict__ Q, const double2 *__restrict__ Mexp, int npts, int rigid,
+    const double *__restrict__ xc, const double *__restrict__ yc, double *__restrict__ out) {
+  const int p = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const double2 z = make_double2(pts[p].x - ox, pts[p].y - oy);
+  double u1 = 0.0, u2 = 0.0, om = 0.0;  // raw sums: u = (1/4pi) (u1, u2), omega = -(1/4pi) om
+  for (int e = box_ptr[p] + lane; e < box_ptr[p + 1]; e += 64) {
+    const int2 bl = boxes[e];
+    const double h = size / (double)(1 << bl.y);
+    const double2 c = center[bl.x];
+    const double2 dz = make_double2(z.x - c.x, z.y - c.y);
+    const double2 id = cdiv1(dz);
+    const double2 t = make_double2(h * id.x, h * id.y);
+    const double2 *uA = Mexp + ((size_t)(3 * r) * nbox + bl.x) * P;
+    const double2 *uB = Mexp + ((size_t)(3 * r + 1) * nbox + bl.x) * P;
+    const double2 *uC = Mexp + ((size_t)(3 * r + 2) * nbox + bl.x) * P;
+    double2 SA = make_double2(uA[P - 1].x * T_log[P - 1], uA[P - 1].y * T_log[P - 1]);
+    double2 SB = make_double2(uB[P - 1].x * T_log[P - 1], uB[P - 1].y * T_log[P - 1]);
+    double2 FA = make_double2(uA[P - 1].x * T_c[P - 1], uA[P - 1].y * T_c[P - 1]);
+    double2 FC = make_double2(uC[P - 1].x * T_c[P - 1], uC[P - 1].y * T_c[P - 1]);
+#pragma unroll
+    for (int m = P - 2; m >= 0; --m) {
+      if (m >= 1) {
+        SA = cfma(SA, t, make_double2(uA[m].x * T_log[m], uA[m].y * T_log[m]));
+        SB = cfma(SB, t, make_double2(uB[m].x * T_log[m], uB[m].y * T_log[m]));
+      }
+      FA = cfma(FA, t, make_double2(uA[m].x * T_c[m], uA[m].y * T_c[m]));
+      FC = cfma(FC, t, make_double2(uC[m].x * T_c[m], uC[m].y * T_c[m]));
+    }
+    SA = cmul(SA, t);
+    SB = cmul(SB, t);
+    const double2 A = cmul(FA, id), C = cmul(FC, id);
+    const double lnr = 0.5 * log(fma(dz.x, dz.x, dz.y * dz.y));
+    // -F ln|dz| + (S_A + conj(S_B)) / 2 + F / 2 + (z conj(A) - conj(C)) / 2, F = a_0 of set A
+    const double2 zA = cmul(z, make_double2(A.x, -A.y));
+    u1 += -uA[0].x * lnr + 0.5 * (SA.x + SB.x) + 0.5 * uA[0].x + 0.5 * (zA.x - C.x);
+    u2 += -uA[0].y * lnr + 0.5 * (SA.y - SB.y) + 0.5 * uA[0].y + 0.5 * (zA.y + C.y);
+    om += A.y;
+  }
+  const double2 *f = Q + (size_t)(3 * r) * M;
+  for (int e = run_ptr[p]; e < run_ptr[p + 1]; ++e) {
+    const int2 kr = runs[e];
+    for (int k = kr.x + lane; k < kr.y; k += 64) {
+      const double2 zk = xs[k], fk = f[k];
+      const double dx = z.x - zk.x, dy = z.y - zk.y;
+      const double rr = fma(dx, dx, dy * dy);
+      const double lg = 0.5 * log(rr), inv = 1.0 / rr;
+      const double rt = fma(dx, fk.x, dy * fk.y) * inv;
+      u1 += -lg * fk.x + dx * rt;
+      u2 += -lg * fk.y + dy * rt;
+      om += (dx * fk.y - dy * fk.x) * inv;
+    }
+  }
+  u1 = wave_sum(u1);
+  u2 = wave_sum(u2);
+  om = wave_sum(om);
+  if (lane != 0) return;
+  const double U1 = u1 / (4.0 * kPi), U2 = u2 / (4.0 * kPi), OM = -om / (4.0 * kPi);
+  if (rigid) {  // v = u(p) - omega (p - x^c)^perp, a^perp = (-a2, a1)
+    const double e1 = pts[p].x - xc[p], e2 = pts[p].y - yc[p];
+    double *o = out + ((size_t)r * npts + p) * 3;
+    o[0] = U1 + OM * e2;
+    o[1] = U2 - OM * e1;
+    o[2] = OM;
+  } else {
+    double *o = out + ((size_t)r * npts + p) * 2;
+    o[0] = U1;
+    o[1] = U2;
+  }
+}
+
 // ---- host: tree and translation operators ---------------------------------------------------
 
 double binom(int n, int k) {
@@ -1064,6 +1256,24 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
     }
     (void)n;
   }
+  // host copies for the evaluation at arbitrary points: box levels, centres, children, and the
+  // run of sorted nodes of every box (leaves first, then each parent spans its children)
+  t.h_level = box_level;
+  t.h_center = center;
+  t.h_child = child;
+  t.h_lo.assign(t.nbox, M);
+  t.h_hi.assign(t.nbox, 0);
+  for (int b = 0; b < (int)keys[L].size(); ++b) {
+    t.h_lo[t.level_off[L] + b] = leaf_start[b];
+    t.h_hi[t.level_off[L] + b] = leaf_start[b + 1];
+  }
+  for (int l = L - 1; l >= 0; --l)
+    for (int b = t.level_off[l]; b < t.level_off[l + 1]; ++b)
+      for (int c = 0; c < 4; ++c)
+        if (child[4 * b + c] >= 0) {
+          t.h_lo[b] = std::min(t.h_lo[b], t.h_lo[child[4 * b + c]]);
+          t.h_hi[b] = std::max(t.h_hi[b], t.h_hi[child[4 * b + c]]);
+        }
   // M2L lists (levels >= 2) and near lists (leaves)
   std::vector<int> m2l_ptr(1, 0), m2l_src, m2l_off;
   const int off2 = t.level_off[std::min(2, L)];
@@ -1345,6 +1555,8 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   }
   std::vector<double> inv_h(L + 1);
   for (int l = 0; l <= L; ++l) inv_h[l] = (double)(1 << l) / t.size;
+  std::vector<double> Tlog(p, 0.0);  // (m - 1)! / s^m, m >= 1
+  for (int m = 1; m < p; ++m) Tlog[m] = Tc[m] / m;
   std::vector<double2> xs(M), nrm(M);
   std::vector<int> perm_i(M);
   for (int j = 0; j < M; ++j) {
@@ -1374,7 +1586,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
                       grp_ptr.size() + 18 * (size_t)t.ngroup + 17 * nitem + run_ptr.size() +
                       nnear + 2 * chunk_leaf.size() + leaf_anc.size() + 2 * ev_start.size();
   const size_t d2 = 2 * (size_t)M + t.nbox + (size_t)80 * p + (size_t)8 * p * p + Tdpow.size();
-  const size_t bytes = d2 * 16 + (L + 1 + 4 * p) * 8 + ints * 4 + 36 * 256;
+  const size_t bytes = d2 * 16 + (L + 1 + 5 * p) * 8 + ints * 4 + 37 * 256;
   BIE_TRY(t.buf.reserve(bytes));
   char *q = t.buf.as<char>();
   auto take = [&](size_t nbytes) {
@@ -1392,6 +1604,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   t.fact_in = (double *)take(p * 8);
   t.T_tau = (double2 *)take((size_t)8 * p * 16);
   t.inv_h = (double *)take((L + 1) * 8);
+  t.T_log = (double *)take(p * 8);
   t.perm = (int *)take(M * 4);
   t.leaf_start = (int *)take((t.nleaf + 1) * 4);
   t.leaf_box = (int *)take(t.nleaf * 4);
@@ -1431,6 +1644,7 @@ int build_tree(bie_geom *g, int p, int leaf_cap, FmmTree &t, hipStream_t s) {
   BIE_TRY(up(t.fact_out, fact_out.data(), p * 8));
   BIE_TRY(up(t.fact_in, fact_in.data(), p * 8));
   BIE_TRY(up(t.inv_h, inv_h.data(), (L + 1) * 8));
+  BIE_TRY(up(t.T_log, Tlog.data(), p * 8));
   BIE_TRY(up(t.perm, perm_i.data(), M * 4));
   BIE_TRY(up(t.leaf_start, leaf_start.data(), leaf_start.size() * 4));
   BIE_TRY(up(t.leaf_box, leaf_box.data(), t.nleaf * 4));
@@ -1481,10 +1695,10 @@ int launch_m2l_f32(const FmmTree &t, int nsets, const float2 *Mexp, float2 *Lexp
 
 // Upward pass (P2M, M2M), M2L, then (after the near field's join) the evaluation of every
 // ancestor's local expansion at the targets into `partial`, with expansions in T. float is used for the mixed-precision Laplace apply only.
-template <int P, class T, class Near>
-int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
-                     const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
-                     Near &&launch_near) {
+// Multipoles of every box at levels >= 2: P2M at the leaves, then M2M level by level.
+template <int P, class T>
+void upward_pass(const FmmTree &t, int kind, int nsets, double ih_leaf, const cx<T> *Q,
+                 cx<T> *Mexp, hipStream_t s) {
   const int M = t.M;
   bool p2m_done = false;
   if constexpr (std::is_same<T, double>::value) {
@@ -1503,6 +1717,14 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
       hipLaunchKernelGGL((k_m2m<P, T>), dim3((unsigned)std::min<long long>((long long)nb * nsets, 4096)),
                          dim3(256), 0, s, nb, t.level_off[l], t.nbox, nsets, t.child, t.T_tau, Mexp);
   }
+}
+
+template <int P, class T, class Near>
+int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
+                     const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
+                     Near &&launch_near) {
+  const int M = t.M;
+  upward_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);
   // the near field (it depends only on the gather) is submitted after the multipole passes: it
   // then runs beside the M2L, whose products are on the matrix cores, rather than slowing the
   // M2M passes
@@ -1560,6 +1782,169 @@ static int fmm_length(int order, int precision) {
   return std::min((p + 7) / 8 * 8, kMaxP);  // expansions use a multiple of 8 terms (rounded up)
 }
 
+namespace {
+
+// The tree of g for (order, leaf), built on first use.
+int get_tree(bie_geom *g, int p, int leaf, hipStream_t s, FmmTree **out) {
+  if (!g->fmm) g->fmm = new FmmPlan();
+  FmmTree *&tp = g->fmm->trees[std::make_pair(p, leaf)];
+  if (!tp) {
+    tp = new FmmTree();
+    const int rc = build_tree(g, p, leaf, *tp, s);
+    if (rc != BIE_OK) {
+      tp->buf.release();
+      delete tp;
+      tp = nullptr;
+      return rc;
+    }
+  }
+  *out = tp;
+  return BIE_OK;
+}
+
+// Interaction lists of the points pts (absolute coordinates, host) on tree t: a descent from
+// the level-2 boxes; a box at level l >= 2 with |z - c| >= sqrt(2) h_l (twice its half-diagonal:
+// the multipole's terms fall at least as 2^-m) is evaluated by its multipole, a leaf closer
+// than that contributes its nodes directly, any other box is replaced by its children.
+int build_point_lists(const FmmTree &t, const std::vector<double2> &pts, PointLists &pl,
+                      hipStream_t s) {
+  const int n = (int)pts.size();
+  std::vector<int> bptr(1, 0), rptr(1, 0);
+  std::vector<int2> bx, rn;
+  std::vector<int> stack;
+  long long direct = 0;
+  for (int i = 0; i < n; ++i) {
+    const double zx = pts[i].x - t.ox, zy = pts[i].y - t.oy;
+    stack.clear();
+    const int l2 = std::min(2, t.L);
+    for (int b = t.level_off[l2 + 1] - 1; b >= t.level_off[l2]; --b) stack.push_back(b);
+    std::vector<int2> myruns;
+    while (!stack.empty()) {
+      const int b = stack.back();
+      stack.pop_back();
+      const int l = t.h_level[b];
+      const double h = t.size / (double)(1 << l);
+      const double dx = zx - t.h_center[b].x, dy = zy - t.h_center[b].y;
+      if (l >= 2 && dx * dx + dy * dy >= 2.0 * h * h) {
+        bx.push_back(make_int2(b, l));
+      } else if (l == t.L) {
+        myruns.push_back(make_int2(t.h_lo[b], t.h_hi[b]));
+      } else {
+        for (int c = 3; c >= 0; --c)
+          if (t.h_child[4 * b + c] >= 0) stack.push_back(t.h_child[4 * b + c]);
+      }
+    }
+    std::sort(myruns.begin(), myruns.end(), [](int2 a, int2 b) { return a.x < b.x; });
+    for (const int2 &r : myruns) {
+      direct += r.y - r.x;
+      if (!rn.empty() && (int)rn.size() > rptr.back() && rn.back().y == r.x) rn.back().y = r.y;
+      else rn.push_back(r);
+    }
+    bptr.push_back((int)bx.size());
+    rptr.push_back((int)rn.size());
+  }
+  pl.npts = n;
+  pl.nbox_total = (long long)bx.size();
+  pl.direct_pairs = direct;
+  const size_t bytes = (size_t)(2 * (n + 1)) * 4 + (bx.size() + rn.size()) * 8 + 4 * 256;
+  BIE_TRY(pl.buf.reserve(bytes));
+  char *q = pl.buf.as<char>();
+  auto take = [&](size_t nb) {
+    char *r = q;
+    q += (nb + 255) & ~size_t(255);
+    return r;
+  };
+  pl.box_ptr = (int *)take((n + 1) * 4);
+  pl.run_ptr = (int *)take((n + 1) * 4);
+  pl.box = (int2 *)take(std::max<size_t>(bx.size(), 1) * 8);
+  pl.run = (int2 *)take(std::max<size_t>(rn.size(), 1) * 8);
+  BIE_HIP_CHECK(hipMemcpyAsync(pl.box_ptr, bptr.data(), bptr.size() * 4, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipMemcpyAsync(pl.run_ptr, rptr.data(), rptr.size() * 4, hipMemcpyHostToDevice, s));
+  if (!bx.empty())
+    BIE_HIP_CHECK(hipMemcpyAsync(pl.box, bx.data(), bx.size() * 8, hipMemcpyHostToDevice, s));
+  if (!rn.empty())
+    BIE_HIP_CHECK(hipMemcpyAsync(pl.run, rn.data(), rn.size() * 8, hipMemcpyHostToDevice, s));
+  BIE_HIP_CHECK(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return BIE_OK;
+}
+
+}  // namespace
+
+// Single-layer potentials of dens at npts points pts (device [npts][2]; the geometry's read-off
+// points when pts == g->pint, whose lists are kept with the tree) by the treecode over the
+// float64 FMM tree of the geometry's order and leaf size. Laplace: res [nrhs][npts]; Stokes:
+// rigid (read-off) res [nrhs][npts][3] = (v, omega), else velocities [nrhs][npts][2].
+int fmm_eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts,
+                    const double *pts, bool rigid, double *res, hipStream_t s) {
+  const int p = fmm_length(g->fmm_order, BIE_FP64);
+  const int leaf = g->fmm_leaf > 0 ? g->fmm_leaf : 64;
+  FmmTree *tp = nullptr;
+  BIE_TRY(get_tree(g, p, leaf, s, &tp));
+  FmmTree &t = *tp;
+  PointLists local, *pl = &local;
+  const bool cached = pts == g->pint && npts == g->N;
+  if (cached && t.rd) {
+    pl = t.rd;
+  } else {
+    std::vector<double2> hp(npts);
+    BIE_HIP_CHECK(hipMemcpyAsync(hp.data(), pts, (size_t)npts * 16, hipMemcpyDeviceToHost, s));
+    BIE_HIP_CHECK(hipStreamSynchronize(s));
+    if (cached) {
+      t.rd = new PointLists();
+      pl = t.rd;
+    }
+    const int rc = build_point_lists(t, hp, *pl, s);
+    if (rc != BIE_OK) {
+      if (cached) {
+        t.rd->buf.release();
+        delete t.rd;
+        t.rd = nullptr;
+      }
+      return rc;
+    }
+  }
+  const int M = t.M;
+  const int Rmax = kind == 0 ? 8 : 4;
+  const double ih_leaf = (double)(1 << t.L) / t.size;
+  int rc = BIE_OK;
+  for (int r0 = 0; r0 < nrhs && rc == BIE_OK; r0 += Rmax) {
+    const int R = std::min(Rmax, nrhs - r0);
+    const int nsets = kind == 0 ? R : 3 * R;
+    // work: charges Q [nsets][M], multipoles [nsets][nbox][p] (float64)
+    const size_t need = ((size_t)nsets * M + (size_t)nsets * t.nbox * p) * sizeof(double2) + 512;
+    rc = t.work.reserve(need);
+    if (rc != BIE_OK) break;
+    double2 *Q = t.work.as<double2>();
+    double2 *Mexp = Q + (size_t)nsets * M;
+    const size_t len = (size_t)M * (kind == 0 ? 1 : 2);
+    hipLaunchKernelGGL(k_gather_q, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm,
+                       t.xs, g->w, dens + (size_t)r0 * len, Q);
+    const size_t w = kind == 0 ? 1 : (rigid ? 3 : 2);
+    double *o = res + (size_t)r0 * npts * w;
+    rc = with_order(p, [&](auto order) -> int {
+      constexpr int P = decltype(order)::value;
+      upward_pass<P, double>(t, kind, nsets, ih_leaf, Q, Mexp, s);
+      if (kind == 0)
+        hipLaunchKernelGGL(k_eval_lap<P>, dim3(npts, R), dim3(64), 0, s, M, t.nbox, t.size,
+                           reinterpret_cast<const double2 *>(pts), t.ox, t.oy, pl->box_ptr, pl->box,
+                           pl->run_ptr, pl->run, t.center, t.T_log, t.xs, Q, Mexp, npts, o);
+      else
+        hipLaunchKernelGGL(k_eval_stk<P>, dim3(npts, R), dim3(64), 0, s, M, t.nbox, t.size,
+                           reinterpret_cast<const double2 *>(pts), t.ox, t.oy, pl->box_ptr, pl->box,
+                           pl->run_ptr, pl->run, t.center, t.T_log, t.T_c, t.xs, Q, Mexp, npts,
+                           rigid ? 1 : 0, g->xc, g->yc, o);
+      BIE_HIP_CHECK(hipGetLastError());
+      return BIE_OK;
+    });
+  }
+  if (pl == &local) {
+    (void)hipStreamSynchronize(s);  // the lists are freed on return
+    local.buf.release();
+  }
+  return rc;
+}
+
+
 long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf) {
   if (leaf <= 0) leaf = 64;
   long long total = 0;
@@ -1590,18 +1975,8 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
                   hipStream_t s, int order, int leaf) {
   const int p = fmm_length(order, precision);
   if (leaf <= 0) leaf = 64;
-  if (!g->fmm) g->fmm = new FmmPlan();
-  FmmTree *&tp = g->fmm->trees[std::make_pair(p, leaf)];
-  if (!tp) {
-    tp = new FmmTree();
-    const int rc = build_tree(g, p, leaf, *tp, s);
-    if (rc != BIE_OK) {
-      tp->buf.release();
-      delete tp;
-      tp = nullptr;
-      return rc;
-    }
-  }
+  FmmTree *tp = nullptr;
+  BIE_TRY(get_tree(g, p, leaf, s, &tp));
   FmmTree &t = *tp;
   const int M = t.M;
   const int nsets = kind == 0 ? R : 3 * R;

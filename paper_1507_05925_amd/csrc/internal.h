@@ -171,9 +171,12 @@ int incident_density(bie_geom *g, int kind, int nrhs, const double *data, double
 // out = D in, or D^-1 in with inverse, D = diag(sqrt(w)) per node and component ([nrhs][M comps])
 int scale_sqrtw(bie_geom *g, int comps, int nrhs, int inverse, const double *in, double *out,
                 hipStream_t s);
-int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t s);
+// method BIE_FMM (or BIE_AUTO above 32768 nodes): treecode over the float64 FMM tree of the
+// geometry's order and leaf size; else the direct sum over all nodes
+int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t s,
+             int method = BIE_DIRECT);
 int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
-                bool rigid, double *res, hipStream_t st);
+                bool rigid, double *res, hipStream_t st, int method = BIE_DIRECT);
 int geometry_build(bie_geom *g, const double *curve, const double *interior, hipStream_t s);
 
 // ---- dirichlet.hip: capacitance and resistance problems (completed double layers) --------
@@ -214,6 +217,10 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
 int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *mu, double *s64,
                   double *partial, hipStream_t s, int order, int leaf);
 void fmm_destroy(FmmPlan *p);
+// single-layer potentials at points by the treecode over the float64 FMM tree (see kernels.hip
+// eval_points for the layouts)
+int fmm_eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts,
+                    const double *pts, bool rigid, double *res, hipStream_t s);
 // device bytes of g's FMM state (tree and work area) for one solve kind, precision, order and
 // leaf size: the actual size where the tree exists, else an upper estimate
 long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf);

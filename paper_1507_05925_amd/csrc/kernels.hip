@@ -883,8 +883,10 @@ __global__ void k_velocity_fin(int N, int nrhs, int S, const double *__restrict_
 }
 
 int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
-                bool rigid, double *res, hipStream_t st) {
+                bool rigid, double *res, hipStream_t st, int method) {
   if (nrhs <= 0 || npts <= 0) return BIE_OK;
+  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
+  if (method == BIE_FMM) return fmm_eval_points(g, kind, nrhs, dens, npts, pts, rigid, res, st);
   // source splits: about 2048 workgroups in all, at most 32 splits, at least 2048 sources each
   const long long groups = (long long)((npts + kTJ - 1) / kTJ) * nrhs;
   int S = (int)std::max<long long>(1, std::min<long long>(32, (2048 + groups - 1) / groups));
@@ -911,8 +913,9 @@ int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, c
   return BIE_OK;
 }
 
-int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t st) {
-  return eval_points(g, kind, nrhs, dens, g->N, g->pint, true, res, st);
+int read_off(bie_geom *g, int kind, int nrhs, const double *dens, double *res, hipStream_t st,
+             int method) {
+  return eval_points(g, kind, nrhs, dens, g->N, g->pint, true, res, st, method);
 }
 
 }  // namespace bie

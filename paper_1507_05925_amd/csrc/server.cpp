@@ -122,7 +122,7 @@ int prepare(Request &r, const bie_opts &o, hipStream_t s) {
 int finish(Request &r, const bie_opts &o, hipStream_t s) {
   const int width = r.kind == 0 ? r.g->N : 3 * r.g->N;
   BIE_TRY(vec_axpby((long long)r.nrhs * r.n, 1.0, r.x, 1.0, r.inc, s));  // inc = mu + incident
-  BIE_TRY(read_off(r.g, r.kind, r.nrhs, r.inc, r.res, s));
+  BIE_TRY(read_off(r.g, r.kind, r.nrhs, r.inc, r.res, s, uses_fmm(o, r.g) ? BIE_FMM : BIE_DIRECT));
   if (r.kind == 1 && o.viscosity != 1.0)  // velocities for the configured viscosity
     BIE_TRY(vec_axpby((long long)r.nrhs * width, 0.0, r.res, 1.0 / o.viscosity, r.res, s));
   BIE_HIP_CHECK(hipMemcpyAsync(r.out, r.res, sizeof(double) * r.nrhs * width,

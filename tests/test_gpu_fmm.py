@@ -195,3 +195,59 @@ def test_fmm_back_to_back_applies_repeat(kind):
     for k in range(2, 6):
         assert torch.equal(outs[k], outs[k % 2]), k
     assert not torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_treecode_readoff_matches_direct(kind):
+    """With the FMM, phi and (v, omega) are read off by the treecode over the FMM tree (box
+    multipoles where |z - c| >= sqrt(2) h, nearby leaves directly); the direct read-off of the
+    same total density agrees to 1e-12."""
+    c = _cases()["starfish100"] if kind == 0 else _cases()["ellipses30"]
+    g = bie2d.Geometry.from_curves(c)
+    rng = np.random.default_rng(12)
+    o = bie2d.default_opts(method=bie2d.BIE_FMM, tol=1e-12)
+    if kind == 0:
+        q = dev(rng.standard_normal((3, g.N)))
+        phi, _, mu = bie2d.bie_elastance_solve(g, q, o, want_mu=True)
+        sigma, _ = bie2d.bie_elastance_rhs(g, q)
+        ref = bie2d.bie_laplace_potential(g, (mu + sigma).contiguous())
+        out = phi
+    else:
+        FT = dev(wl.random_forces(rng, g.N, 2))
+        out, _, mu = bie2d.bie_mobility_solve(g, FT, o, want_mu=True)
+        rho, _ = bie2d.bie_mobility_rhs(g, FT)
+        ref = bie2d.bie_stokes_rigid_motion(g, (mu + rho).contiguous())
+    assert float((out - ref).abs().max() / ref.abs().max()) < 1e-12
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_treecode_field_vs_oracle(kind):
+    """Off-surface evaluation on a geometry above the FMM threshold (BIE_AUTO: the treecode)
+    against the oracle's direct layer potentials, at points between, near (four node spacings)
+    and far from the curves."""
+    k, c, inp = wl.fmm_items()[kind]
+    g = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    rng = np.random.default_rng(13)
+    lo = np.array([c.x.min(), c.y.min()]) - 2.0
+    hi = np.array([c.x.max(), c.y.max()]) + 2.0
+    pts = rng.uniform(lo, hi, size=(300, 2))
+    b = rng.integers(0, c.nbodies, 40)
+    k0 = c.body_ptr[b] + 5
+    nrm = np.stack([geo["nx"][k0], geo["ny"][k0]], 1)
+    near = np.stack([c.x[k0], c.y[k0]], 1) + 4.0 * geo["w"][k0][:, None] * nrm
+    pts = np.concatenate([pts, near, [[500.0, -300.0]]])
+    # keep points at least four node spacings away from every curve
+    d = np.hypot(pts[:, None, 0] - c.x[None, :], pts[:, None, 1] - c.y[None, :])
+    pts = pts[(d / geo["w"][None, :]).min(1) >= 3.9]
+    mu = rng.standard_normal(g.M if kind == 0 else 2 * g.M) * 0.1
+    inp0 = inp[0]
+    if kind == 0:
+        u = bie2d.bie_elastance_field(g, dev(inp0[None]), dev(mu[None]), dev(pts)).cpu().numpy()[0]
+        dens = mu + ny.incident_charge(geo, inp0)
+        ref = mf.single_layer(geo, dens, pts)
+    else:
+        u = bie2d.bie_mobility_field(g, dev(inp0[None]), dev(mu[None]), dev(pts)).cpu().numpy()[0]
+        dens = mu + ny.incident_traction(geo, inp0)
+        ref = mf.stokes_velocity_vorticity(geo, dens, pts)[:, :2]
+    assert float(np.abs(u - ref).max() / np.abs(ref).max()) < 1e-11
