@@ -591,6 +591,24 @@ def main():
     bie2d.bie_profile_enable(False)
     bie2d.bie_profile_select(None)
 
+    # the same solves replaying captured HIP graphs of every Arnoldi step (the timed solves
+    # above launch each step's kernels on the stream, the library default)
+    bie2d.bie_set_graphs(True)
+    bie2d.bie_elastance_solve(g, q_d, opts)  # captures the steps
+    torch.cuda.synchronize()
+    t_g = time.perf_counter()
+    for _ in range(a.steps):
+        bie2d.bie_elastance_solve(g, q_d, opts)
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t_g) / a.steps
+    captured, replayed = g.graph_stats()
+    bie2d.bie_set_graphs(False)
+    ms_stream = 1e3 * elapsed / a.steps
+    graphs = {"ms_per_solve_stream_launch": ms_stream, "ms_per_solve_graph_replay": ms_graph,
+              "arnoldi_steps_per_solve": info["iters"],
+              "us_per_step_graph_minus_stream": 1e3 * (ms_graph - ms_stream) / max(info["iters"], 1),
+              "steps_captured": captured, "steps_replayed": replayed}
+
     # the direct float32 far-field sweep on the same workload (survey row a3), 5 applies
     mu = torch.randn(1, g.M, dtype=torch.float64, device=dev)
     bie2d.bie_laplace_apply(g, mu, bie2d.BIE_MIXED, bie2d.BIE_DIRECT)
@@ -644,6 +662,7 @@ def main():
         "roofline_direct_p2p": rl_direct,
         "kernel_ms_per_solve_untimed": {k: v["ms_total"] for k, v in profs.items()},
         "fmm_ms_per_apply": fmm_total["ms_total"] / max(fmm_total["launches"], 1),
+        "graphs": graphs,
     }
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(curves, a.cpu_seconds)

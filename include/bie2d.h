@@ -395,6 +395,17 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_COUNT 9
+/* Graph replay of the solves' Arnoldi steps (default off: measured slower than stream
+ * launches on the 1000-starfish solve, about 6 us more per step). A single-geometry solve runs each
+ * Arnoldi step (the operator apply, with the FMM's near field forked onto a second stream and
+ * joined back, and the Gram-Schmidt kernels) eagerly the first time, captures it as a HIP graph
+ * and replays that graph in later cycles and solves of the same configuration; a different
+ * configuration or a reallocated workspace drops the captured steps. Results are bitwise the
+ * same either way. Process-wide. Batches and the server run their steps eagerly. */
+int bie_set_graphs(int on);
+/* Graph statistics of a geometry's solver: steps captured and steps replayed since creation. */
+int bie_geom_graph_stats(const bie_geom *g, long long *captured, long long *replayed);
+
 int bie_profile_enable(int on);
 int bie_profile_select(unsigned mask);
 int bie_profile_sample(int every);

@@ -108,6 +108,9 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_server_destroy": ([_P], _I),
     "bie_server_inject_failure": ([_P, _I], _I),
+    "bie_set_graphs": ([_I], _I),
+    "bie_geom_graph_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
+                              ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_profile_enable": ([_I], _I),
     "bie_profile_sample": ([ctypes.c_int], _I),
     "bie_profile_select": ([ctypes.c_uint], _I),
@@ -118,6 +121,11 @@ _SIGS = {
 BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
 BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL = 4, 5, 6, 7
 BIE_K_DOUBLE_LAYER, BIE_K_COUNT = 8, 9
+
+
+def bie_set_graphs(on=True):
+    """Replay captured HIP graphs of the solves' Arnoldi steps (process-wide, default off)."""
+    _check(lib().bie_set_graphs(int(on)))
 
 
 def bie_profile_enable(on=True):
@@ -312,6 +320,12 @@ class Geometry:
 
     def device_bytes(self):
         return int(lib().bie_geom_device_bytes(self.handle))
+
+    def graph_stats(self):
+        """-> (Arnoldi steps captured as HIP graphs, steps replayed) of this geometry's solves."""
+        c, r = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().bie_geom_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def set_fmm(self, order, leaf=64):
         _check(lib().bie_geom_set_fmm(self.handle, int(order), int(leaf)))

@@ -118,14 +118,16 @@ __global__ __launch_bounds__(kBlock) void k_combination_nrm(
 // v = w / ||w|| over its chunk; the first workgroup of s also completes the Hessenberg column,
 // h2[s][0..cnt-1] += h1[s][...] and h2[s][cnt] = ||w||, stores ||w|| in nrm[s] and, when col_out
 // is given (mapped host memory), writes the column there too, then (when flag is given) stores
-// seq in flag[s] once the column is visible to the host.
+// the tag of step *seq_base + seq_off in flag[s] once the column is visible to the host (the
+// base is read when the kernel runs, so a captured graph of the step stays valid across
+// cycles).
 __global__ __launch_bounds__(kBlock) void k_normalize_column(
     int cnt, const int *__restrict__ csys, const int *__restrict__ sys_chunk,
     const long long *__restrict__ c0, const long long *__restrict__ c1,
     const double *__restrict__ partial, const double *__restrict__ w, double *__restrict__ v,
     const double *__restrict__ h1, double *__restrict__ h2, long long hs,
     double *__restrict__ nrm, double *__restrict__ col_out, unsigned long long *flag,
-    unsigned long long seq) {
+    const unsigned long long *seq_base, unsigned long long seq_off) {
   __shared__ double sh[4];
   const int c = blockIdx.x, s = csys[c];
   const int a = sys_chunk[s] * kSub, b = sys_chunk[s + 1] * kSub;
@@ -147,8 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_normalize_column(
     if (flag) {  // (uniform over the workgroup)
       __threadfence_system();  // this thread's column entries reach host memory first
       __syncthreads();
-      if (threadIdx.x == 0)
+      if (threadIdx.x == 0) {
+        const unsigned long long seq = column_tag(*seq_base + seq_off);
         __hip_atomic_store(flag + s, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
   }
 }
@@ -209,13 +213,14 @@ int seg_nrm2(const Segments &sg, const double *w, double *out, double *scratch, 
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
                            double *vnext, double *col_out, unsigned long long *flag,
-                           unsigned long long seq, double *scratch, hipStream_t s) {
+                           const unsigned long long *seq_base, unsigned long long seq_off,
+                           double *scratch, hipStream_t s) {
   if (nvec <= 0) return BIE_OK;
   hipLaunchKernelGGL(k_combination_nrm, dim3(sg.C, kSub), dim3(kBlock), 0, s, nvec, sg.csys, sg.c0,
                      sg.c1, V, vstride, h2, hs, w, -1.0, scratch);
   hipLaunchKernelGGL(k_normalize_column, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys,
                      sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm, col_out, flag,
-                     seq);
+                     seq_base, seq_off);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

@@ -20,8 +20,17 @@ static thread_local std::string g_last_error = "no error";
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+static std::atomic<unsigned long long> g_epoch{0};
+unsigned long long buffer_epoch() { return g_epoch.load(); }
+
+// off by default: on ROCm 7.2 a replayed step measured slower than its stream launches (about
+// 6 us more per Arnoldi step of the 1000-starfish solve)
+static std::atomic<int> g_graphs{0};
+bool graphs_enabled() { return g_graphs.load() != 0; }
+
 int DevBuf::reserve(size_t need) {
   if (need <= bytes) return BIE_OK;
+  g_epoch.fetch_add(1);
   if (ptr) {
     hipError_t e = hipDeviceSynchronize();
     (void)e;
@@ -40,6 +49,7 @@ int DevBuf::reserve(size_t need) {
 }
 
 void DevBuf::release() {
+  if (ptr) g_epoch.fetch_add(1);
   if (ptr) hipFree(ptr);
   ptr = nullptr;
   bytes = 0;
@@ -211,6 +221,11 @@ int bie_ctx_geom_create(bie_ctx *ctx, int nbodies, const int32_t *nodes_per_body
 }
 
 const char *bie_last_error(void) { return g_last_error.c_str(); }
+
+int bie_set_graphs(int on) {
+  g_graphs.store(on ? 1 : 0);
+  return BIE_OK;
+}
 
 int bie_default_opts(bie_opts *o) {
   if (!o) {
@@ -387,6 +402,13 @@ int bie_geom_destroy(bie_geom *g) {
   g->ws_scale.release();
   if (g->fmm) fmm_destroy(g->fmm);
   delete g;
+  return BIE_OK;
+}
+
+int bie_geom_graph_stats(const bie_geom *g, long long *captured, long long *replayed) {
+  BIE_TRY(check_geom(g));
+  if (captured) *captured = g->sm.graph_captures;
+  if (replayed) *replayed = g->sm.graph_replays;
   return BIE_OK;
 }
 

@@ -62,12 +62,6 @@ int write_dev(SolverMem &mem, double *dev, const std::vector<double> &src, hipSt
   return BIE_OK;
 }
 
-// Tag stored in a column's flag word: a NaN bit pattern with the step number in its payload, a
-// value that the doubles staged through the same pinned buffer never take.
-unsigned long long column_tag(unsigned long long seq) {
-  return 0x7FF5A00000000000ULL | (seq & 0x00000FFFFFFFFFFFULL);
-}
-
 // Waits until the kernel of an Arnoldi step has stored `tag` in all S flag words (mapped host
 // memory, written after the column). After every 2 ms without them the stream is queried (a
 // step normally takes far less): an error is returned as such, and a stream that is idle while
@@ -194,14 +188,25 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     // column, written by the last kernel into pinned slot j % 2. Steps run one ahead of the
     // host: step j+1 is queued before the host waits for step j's column (a cycle that stops at
     // step j leaves step j+1's work unused).
-    // slot: the S columns, then one flag word per system
+    // pinned: two slots (the S columns, then one flag word per system), then the tag base of
+    // this cycle (step j stores the tag of base + j + 1); the base is written before the
+    // cycle's first step, when no earlier step is in flight
     const size_t slot = (size_t)S * hs + S;
-    BIE_TRY(mem.ensure_pinned(2 * slot * sizeof(double)));
+    BIE_TRY(mem.ensure_pinned((2 * slot + 1) * sizeof(double)));
+    volatile unsigned long long *base_h =
+        reinterpret_cast<volatile unsigned long long *>(mem.pinned + 2 * slot);
+    const unsigned long long *base_d =
+        reinterpret_cast<const unsigned long long *>(mem.pinned_dev + 2 * slot);
+    const unsigned long long base = mem.seq;
+    *base_h = base;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    mem.seq += (unsigned long long)m + 1;
     unsigned long long seqv[2] = {0, 0};
-    auto step = [&](int j) -> int {
+    // the launches of step j (its arguments depend only on j and the solver's buffers)
+    auto step_body = [&](int j, Stats &sts, hipStream_t s) -> int {
       double *Vj = wk.V + (size_t)j * N;
       double *Vj1 = wk.V + (size_t)(j + 1) * N;
-      BIE_TRY(apply(ss, precision, Vj, wk.w, st, s));
+      BIE_TRY(apply(ss, precision, Vj, wk.w, sts, s));
       // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||.
       // The second update is fused with ||w||; the column (h1 + h2 with ||w|| as entry j + 1)
       // goes straight to pinned slot j % 2 (mapped host memory), followed by its flag word
@@ -209,10 +214,72 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
       double *col = mem.pinned_dev + (j & 1) * slot;
-      seqv[j & 1] = column_tag(++mem.seq);
       BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1, col,
                                      reinterpret_cast<unsigned long long *>(col + (size_t)S * hs),
-                                     seqv[j & 1], wk.scratch, s));
+                                     base_d, (unsigned long long)j + 1, wk.scratch, s));
+      return BIE_OK;
+    };
+    // With graphs: step j is captured (after running it once eagerly, which sizes every buffer)
+    // and replayed in later cycles and solves of the same configuration; a change of the
+    // configuration or any buffer reallocation drops the captured steps.
+    const bool use_graphs = graphs_enabled() && !ss.graph_key.empty();
+    std::string gkey;
+    if (use_graphs) {
+      char buf[256];
+      std::snprintf(buf, sizeof buf, "|m%d|S%d|N%lld|%p|%p|%p|%p|%p|%p|%p|%p", m, S, N,
+                    (void *)wk.V, (void *)wk.w, (void *)wk.h1, (void *)wk.h2, (void *)wk.nrm,
+                    (void *)wk.scratch, (void *)mem.pinned_dev, (void *)sg.c0);
+      gkey = ss.graph_key + buf;
+    }
+    auto step = [&](int j) -> int {
+      seqv[j & 1] = column_tag(base + (unsigned long long)j + 1);
+      if (!use_graphs) return step_body(j, st, s);
+      StepGraphs &gr = mem.graphs[precision == BIE_MIXED ? 1 : 0];
+      if (gr.key != gkey || gr.epoch != buffer_epoch()) {
+        gr.clear();
+        gr.key = gkey;
+        gr.epoch = buffer_epoch();
+      }
+      if (j < (int)gr.exec.size() && gr.exec[j]) {
+        BIE_HIP_CHECK(hipGraphLaunch(gr.exec[j], s));
+        if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;
+        st.pairs += ss.pairs_per_apply;
+        ++mem.graph_replays;
+        return BIE_OK;
+      }
+      BIE_TRY(step_body(j, st, s));
+      if (gr.epoch != buffer_epoch()) {  // the eager step allocated: earlier captures are stale
+        gr.clear();
+        gr.key = gkey;
+        gr.epoch = buffer_epoch();
+      }
+      if (!mem.cap) BIE_HIP_CHECK(hipStreamCreateWithFlags(&mem.cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      BIE_HIP_CHECK(hipStreamBeginCapture(mem.cap, hipStreamCaptureModeThreadLocal));
+      Stats dummy;
+      int rc;
+      {
+        ProfSuspend quiet;  // no profiling events inside a captured step
+        rc = step_body(j, dummy, mem.cap);
+      }
+      const hipError_t e = hipStreamEndCapture(mem.cap, &graph);
+      if (rc != BIE_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc == BIE_OK) set_error(std::string("graph capture of an Arnoldi step failed: ") +
+                                    hipGetErrorString(e));
+        return rc != BIE_OK ? rc : BIE_EDEVICE;
+      }
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        set_error(std::string("graph instantiation of an Arnoldi step failed: ") +
+                  hipGetErrorString(ei));
+        return BIE_EDEVICE;
+      }
+      if ((int)gr.exec.size() <= j) gr.exec.resize(j + 1, nullptr);
+      gr.exec[j] = exec;
+      ++mem.graph_captures;
       return BIE_OK;
     };
     BIE_TRY(step(0));
@@ -313,7 +380,18 @@ int SolverMem::ensure_pinned(size_t bytes) {
   return BIE_OK;
 }
 
+void StepGraphs::clear() {
+  for (hipGraphExec_t e : exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  exec.clear();
+  key.clear();
+}
+
 void SolverMem::release() {
+  graphs[0].clear();
+  graphs[1].clear();
+  if (cap) (void)hipStreamDestroy(cap);
+  cap = nullptr;
   big.release();
   small.release();
   if (pinned) (void)hipHostFree(pinned);
@@ -424,6 +502,13 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
   ss.mem = &g->sm;
   ss.pairs_per_apply = (long long)nrhs * g->M * (long long)g->M;
   const int method = o.method;
+  {
+    char key[160];
+    std::snprintf(key, sizeof key, "g%llu|k%d|m%d|r%d|o%d|l%d|s%d|%p|%p", g->gen, kind, method,
+                  nrhs, g->fmm_order, g->fmm_leaf, o.l2_scaling, (void *)g->ws_apply.ptr,
+                  (void *)g->ws_scale.ptr);
+    ss.graph_key = key;
+  }
   std::vector<double> rel;
   if (!o.l2_scaling) {
     ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out,

@@ -76,6 +76,22 @@ struct Segments {
             const std::vector<long long> *starts = nullptr);
 };
 
+// Number of device buffer (re)allocations so far: a cached HIP graph whose kernels point into
+// library buffers is valid only while this has not changed since its capture.
+unsigned long long buffer_epoch();
+
+// Whether solves replay captured HIP graphs of their Arnoldi steps (bie_set_graphs).
+bool graphs_enabled();
+
+// Instantiated graphs of the Arnoldi steps j = 0, 1, ... of one solver configuration: each
+// replays step j's operator apply and Gram-Schmidt kernels with the same buffers.
+struct StepGraphs {
+  std::string key;
+  unsigned long long epoch = 0;
+  std::vector<hipGraphExec_t> exec;
+  void clear();
+};
+
 // Krylov workspace and pinned staging of a solver owner (a geometry or a batch).
 struct SolverMem {
   DevBuf big, small;
@@ -83,6 +99,10 @@ struct SolverMem {
   double *pinned_dev = nullptr;  // its device address (kernels write Hessenberg columns there)
   size_t pinned_bytes = 0;
   unsigned long long seq = 0;  // last Arnoldi step number handed out (column flags)
+  StepGraphs graphs[2];        // by apply precision (BIE_FP64, BIE_MIXED)
+  hipStream_t cap = nullptr;   // private stream the steps are captured on (capture is not
+                               // possible on the legacy null stream); replays use the caller's
+  long long graph_replays = 0, graph_captures = 0;
   int ensure_pinned(size_t bytes);
   void release();
 };
@@ -94,6 +114,9 @@ struct SysSet {
   long long pairs_per_apply = 0;
   std::vector<char> active;  // per system; set by the solver before each apply (empty = all)
   std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
+  // identity of the apply's arguments for graph capture (empty: the steps are never captured,
+  // e.g. batches, whose applies depend on the active flags)
+  std::string graph_key;
 };
 
 // Resolution warning thresholds: a node closer than kResolveGap node spacings of another body
@@ -200,7 +223,13 @@ int seg_scale_to(const Segments &sg, const double *w, const double *den, double 
 int seg_combination_column(const Segments &sg, int nvec, const double *V, long long vstride,
                            const double *h1, double *h2, long long hs, double *w, double *nrm,
                            double *vnext, double *col_out, unsigned long long *flag,
-                           unsigned long long seq, double *scratch, hipStream_t s);
+                           const unsigned long long *seq_base, unsigned long long seq_off,
+                           double *scratch, hipStream_t s);
+// the value stored in a column's flag word for step number seq (a NaN bit pattern with seq in
+// its payload, which the doubles staged through the same pinned buffer never take)
+__host__ __device__ inline unsigned long long column_tag(unsigned long long seq) {
+  return 0x7FF5A00000000000ULL | (seq & 0x00000FFFFFFFFFFFULL);
+}
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
 int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
 
