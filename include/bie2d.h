@@ -78,7 +78,9 @@ typedef struct {
   double inner_tol; /* BIE_MIXED: relative tolerance of each inner float32-apply solve */
   int max_refine;   /* BIE_MIXED: cap on outer refinement steps                       */
   int fmm_order;    /* BIE_FMM: expansion order p (terms per expansion)               */
-  int fmm_leaf;     /* BIE_FMM: maximum nodes per leaf box                            */
+  int fmm_leaf;     /* BIE_FMM: mean nodes per leaf box the tree depth aims at; 0 = tuned:
+                       the solves take it from the autotuner (bie_autotune) for the
+                       geometry's shape class, per precision                            */
   double viscosity; /* mobility / resistance: fluid viscosity > 0 (mobility problem
                        statement: viscosity 1 there). Velocities scale as 1/viscosity,
                        forces and torques as viscosity; densities do not change.        */
@@ -395,6 +397,21 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_COUNT 9
+/* ---- autotuning of the FMM leaf size -------------------------------------------------------
+ * The leaf population trades near-field pair work against expansion work; the best value
+ * depends on the kernel, the precision and the node density. bie_autotune times the operator
+ * apply of `kind` at `precision` with nrhs right-hand sides (up to 8, resp. 4, per pass) on g
+ * for leaf sizes 24, 32, 48, 64, 96, 128 (each with its own tree; the losers' trees are
+ * freed), for the float64 apply and, with BIE_MIXED, also for the float32 inner apply, and
+ * stores the fastest per shape class (kind, precision, rhs per pass, floor(log2 M),
+ * floor(log2 M/N)) in the geometry's context (process-wide for a geometry without one). A
+ * class already in the cache is not timed again. The leaf sizes are set on g and returned.
+ * Solves with opts.fmm_leaf = 0 and the FMM call it themselves. bie_autotune_stats: classes
+ * tuned and cache hits (ctx NULL: the process cache). */
+int bie_autotune(bie_geom *g, int kind, int precision, int nrhs, int *leaf_fp64,
+                 int *leaf_mixed, void *stream);
+int bie_autotune_stats(const bie_ctx *ctx, long long *tunings, long long *hits);
+
 /* Graph replay of the solves' Arnoldi steps (default off: measured slower than stream
  * launches on the 1000-starfish solve, about 6 us more per step). A single-geometry solve runs each
  * Arnoldi step (the operator apply, with the FMM's near field forked onto a second stream and

@@ -109,6 +109,9 @@ _SIGS = {
     "bie_server_destroy": ([_P], _I),
     "bie_server_inject_failure": ([_P, _I], _I),
     "bie_set_graphs": ([_I], _I),
+    "bie_autotune": ([_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _P], _I),
+    "bie_autotune_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
+                            ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_geom_graph_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
                               ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_profile_enable": ([_I], _I),
@@ -121,6 +124,22 @@ _SIGS = {
 BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
 BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL = 4, 5, 6, 7
 BIE_K_DOUBLE_LAYER, BIE_K_COUNT = 8, 9
+
+
+def bie_autotune(g, kind, precision=BIE_FP64, nrhs=1):
+    """Tune (or look up) the FMM leaf sizes for g's shape class -> (leaf_fp64, leaf_mixed)."""
+    a, b = _I(), _I()
+    _check(lib().bie_autotune(g.handle, int(kind), precision, int(nrhs), ctypes.byref(a),
+                              ctypes.byref(b), _stream()))
+    return a.value, b.value
+
+
+def bie_autotune_stats(ctx=None):
+    """-> (shape classes tuned, cache hits) of a context's cache (None: the process cache)."""
+    t, h = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(lib().bie_autotune_stats(None if ctx is None else ctx.handle, ctypes.byref(t),
+                                    ctypes.byref(h)))
+    return t.value, h.value
 
 
 def bie_set_graphs(on=True):

@@ -105,7 +105,7 @@ int check_opts(const bie_opts &o) {
       (o.method != BIE_DIRECT && o.method != BIE_FMM && o.method != BIE_AUTO) ||
       !(o.tol > 0.0) || o.restart < 1 ||
       o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
-      o.fmm_order > 64 || o.fmm_leaf < 1 || !(o.viscosity > 0.0) || !std::isfinite(o.viscosity) ||
+      o.fmm_order > 64 || o.fmm_leaf < 0 || !(o.viscosity > 0.0) || !std::isfinite(o.viscosity) ||
       !(o.fmm_eps >= 0.0) || !(o.fmm_eps < 1.0) || (o.l2_scaling != 0 && o.l2_scaling != 1)) {
     set_error("invalid bie_opts");
     return BIE_EINVAL;
@@ -124,14 +124,22 @@ int effective_order(const bie_opts &o) {
 
 }  // namespace bie
 
+struct bie_tune_cache;
+
 struct bie_ctx {
   int device = 0;
   bie_opts defaults{};
   std::mutex mu;
   std::set<bie_geom *> geoms;  // owned until bie_geom_destroy
+  bie_tune_cache *tune = nullptr;  // autotuned FMM leaf sizes of this context's shape classes
 };
 
 namespace bie {
+bie_tune_cache *new_tune_cache();
+void delete_tune_cache(bie_tune_cache *c);
+bie_tune_cache *process_tune_cache();
+int tune_cache_stats(bie_tune_cache *c, long long *tunings, long long *hits);
+bie_tune_cache *tune_cache_of(bie_geom *g) { return g && g->ctx ? g->ctx->tune : nullptr; }
 // Options of a call: the caller's, else its context's defaults, else the process defaults.
 static bie_opts opts_for(const bie_geom *g, const bie_opts *opts) {
   bie_opts o;
@@ -175,6 +183,7 @@ int bie_create(bie_ctx **out, int device, const bie_opts *defaults) {
   }
   c->device = device;
   c->defaults = o;
+  c->tune = new_tune_cache();
   *out = c;
   return BIE_OK;
 }
@@ -190,6 +199,7 @@ int bie_destroy(bie_ctx *ctx) {
     g->ctx = nullptr;
     bie_geom_destroy(g);
   }
+  delete_tune_cache(ctx->tune);
   delete ctx;
   return BIE_OK;
 }
@@ -405,6 +415,24 @@ int bie_geom_destroy(bie_geom *g) {
   return BIE_OK;
 }
 
+int bie_autotune(bie_geom *g, int kind, int precision, int nrhs, int *leaf_fp64,
+                 int *leaf_mixed, void *stream) {
+  BIE_TRY(check_geom(g));
+  DeviceGuard dg(g->device);
+  if ((kind != 0 && kind != 1) || (precision != BIE_FP64 && precision != BIE_MIXED) || nrhs < 1) {
+    set_error("bie_autotune: kind 0 or 1, precision BIE_FP64 or BIE_MIXED, nrhs >= 1");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(autotune_leaf(g, kind, precision, nrhs, as_stream(stream)));
+  if (leaf_fp64) *leaf_fp64 = g->fmm_leaf;
+  if (leaf_mixed) *leaf_mixed = g->fmm_leaf_mixed > 0 ? g->fmm_leaf_mixed : g->fmm_leaf;
+  return BIE_OK;
+}
+
+int bie_autotune_stats(const bie_ctx *ctx, long long *tunings, long long *hits) {
+  return tune_cache_stats(ctx ? ctx->tune : process_tune_cache(), tunings, hits);
+}
+
 int bie_geom_graph_stats(const bie_geom *g, long long *captured, long long *replayed) {
   BIE_TRY(check_geom(g));
   if (captured) *captured = g->sm.graph_captures;
@@ -611,7 +639,13 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   BIE_TRY(input_check(kind, g->N, nrhs, data, s, net));
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
   g->fmm_order = effective_order(o);
-  g->fmm_leaf = o.fmm_leaf;
+  const int meth = o.method == BIE_AUTO ? (g->M > 32768 ? BIE_FMM : BIE_DIRECT) : o.method;
+  if (o.fmm_leaf == 0 && meth == BIE_FMM) {  // leaf sizes from the tuner (cached per class)
+    BIE_TRY(autotune_leaf(g, kind, o.precision, nrhs, s));
+  } else {
+    g->fmm_leaf = o.fmm_leaf > 0 ? o.fmm_leaf : 64;
+    g->fmm_leaf_mixed = 0;
+  }
   // ws_out: dens [nrhs][len], f [nrhs][len], mu [nrhs][len]
   BIE_TRY(g->ws_out.reserve(3 * len * nrhs * 8));
   double *dens = g->ws_out.as<double>();

@@ -1945,6 +1945,22 @@ int fmm_eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npt
 }
 
 
+void fmm_drop_tree(bie_geom *g, int precision, int order, int leaf) {
+  if (!g->fmm) return;
+  auto it = g->fmm->trees.find(std::make_pair(fmm_length(order, precision), leaf));
+  if (it == g->fmm->trees.end() || !it->second) return;
+  (void)hipDeviceSynchronize();  // no apply may still use it
+  FmmTree *t = it->second;
+  if (t->rd) {
+    t->rd->buf.release();
+    delete t->rd;
+  }
+  t->buf.release();
+  t->work.release();
+  delete t;
+  g->fmm->trees.erase(it);
+}
+
 long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf) {
   if (leaf <= 0) leaf = 64;
   long long total = 0;

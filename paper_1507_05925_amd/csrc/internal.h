@@ -174,6 +174,7 @@ struct bie_geom {
   bie::FmmPlan *fmm = nullptr;
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box
+  int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
 };
 
 namespace bie {
@@ -253,6 +254,14 @@ int fmm_eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npt
 // device bytes of g's FMM state (tree and work area) for one solve kind, precision, order and
 // leaf size: the actual size where the tree exists, else an upper estimate
 long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order, int leaf);
+// frees g's tree for this precision, order and leaf size (if any)
+void fmm_drop_tree(bie_geom *g, int precision, int order, int leaf);
+
+// ---- autotune.cpp: FMM leaf size per shape class ------------------------------------------
+// Sets g->fmm_leaf / g->fmm_leaf_mixed for a solve of `kind` at `precision` with nrhs right-hand
+// sides: from the cache of g's context (or the process cache) for g's shape class, else by
+// timing applies on g over the candidate leaf sizes and storing the fastest.
+int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s);
 int fmm_current_order();
 
 

@@ -804,8 +804,10 @@ int apply_operator_ws(bie_geom *g, int kind, int precision, int method, int with
     const int R = left >= maxR ? maxR : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
     const size_t off = (size_t)r0 * len;
     if (method == BIE_FMM) {
+      const int leaf = precision == BIE_MIXED && g->fmm_leaf_mixed > 0 ? g->fmm_leaf_mixed
+                                                                        : g->fmm_leaf;
       BIE_TRY(fmm_far_field(g, kind, precision, R, mu + off, s64 + off, partial, st, g->fmm_order,
-                            g->fmm_leaf));
+                            leaf));
     } else {
       switch (R) {
         case 8: launch_far<8>(g, kind, precision, s64, s32, partial, st, off); break;
