@@ -95,10 +95,22 @@ int wait_column(const double *flags, int S, unsigned long long tag, hipStream_t 
 struct Work {
   double *V, *w, *r;          // V [(m+1)][Ntot]; w, r [Ntot]
   double *h1, *h2, *nrm, *y;  // [S][m+2] x3, [S]
+  double *zero;               // [S][m+2] zeros (the absent second pass of a one-pass step)
   double *scratch;            // dot partials [max(m+2, 4)][C]
 };
 
-int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
+// Gram-Schmidt passes per Arnoldi step: two (CGS2) for the float64 operator; one for the
+// float32-apply inner solves of the mixed mode, which only reach about 1e-6 and whose result
+// the float64 refinement residual checks (BIE_INNER_CGS=2 restores two passes there).
+int gs_passes(int precision) {
+  static const int inner = [] {
+    const char *e = std::getenv("BIE_INNER_CGS");
+    return e && std::atoi(e) == 2 ? 2 : 1;
+  }();
+  return precision == BIE_MIXED ? inner : 2;
+}
+
+int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hipStream_t s) {
   const size_t N = (size_t)ss.seg->Ntot;
   const int S = ss.seg->S;
   BIE_TRY(ss.mem->big.reserve(((size_t)(m + 1) + 2 + extra_vectors) * N * sizeof(double) + 64));
@@ -116,7 +128,7 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
   const size_t hs = (size_t)m + 2;
   // scratch: dot partials [(m+2)][C], or four per chunk for the fused update and norm
   const size_t np = std::max<size_t>(hs, 4) * (size_t)ss.seg->C;
-  BIE_TRY(ss.mem->small.reserve((3 * hs * S + S + np) * sizeof(double) + 64));
+  BIE_TRY(ss.mem->small.reserve((4 * hs * S + S + np) * sizeof(double) + 64));
   double *q = ss.mem->small.as<double>();
   wk.h1 = q;
   q += hs * S;
@@ -124,9 +136,13 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra) {
   q += hs * S;
   wk.y = q;
   q += hs * S;
+  wk.zero = q;
+  q += hs * S;
   wk.nrm = q;
   q += S;
   wk.scratch = q;
+  // written once here, never by a step (kernels only read it)
+  BIE_HIP_CHECK(hipMemsetAsync(wk.zero, 0, hs * S * sizeof(double), s));
   return BIE_OK;
 }
 
@@ -211,12 +227,18 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       // The second update is fused with ||w||; the column (h1 + h2 with ||w|| as entry j + 1)
       // goes straight to pinned slot j % 2 (mapped host memory), followed by its flag word
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
+      double *col = mem.pinned_dev + (j & 1) * slot;
+      auto *flag = reinterpret_cast<unsigned long long *>(col + (size_t)S * hs);
+      if (gs_passes(precision) == 1) {  // w -= V h1, column = h1 (+ zeros), ||w||
+        BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.zero, wk.h1, hs, wk.w, wk.nrm, Vj1,
+                                       col, flag, base_d, (unsigned long long)j + 1, wk.scratch,
+                                       s));
+        return BIE_OK;
+      }
       BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
       BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      double *col = mem.pinned_dev + (j & 1) * slot;
       BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1, col,
-                                     reinterpret_cast<unsigned long long *>(col + (size_t)S * hs),
-                                     base_d, (unsigned long long)j + 1, wk.scratch, s));
+                                     flag, base_d, (unsigned long long)j + 1, wk.scratch, s));
       return BIE_OK;
     };
     // With graphs: step j is captured (after running it once eagerly, which sizes every buffer)
@@ -348,7 +370,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
 int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
                 const std::vector<double> &tol, int m, int &iters, int &applies, hipStream_t s) {
   Work wk;
-  BIE_TRY(make_work(ss, m, wk, 0, nullptr));
+  BIE_TRY(make_work(ss, m, wk, 0, nullptr, s));
   Stats st;
   std::vector<double> relres;
   std::vector<int> conv;
@@ -413,7 +435,7 @@ int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
   Work wk;
   double *extra[2] = {nullptr, nullptr};
   const bool mixed = o.precision == BIE_MIXED;
-  BIE_TRY(make_work(ss, m, wk, mixed ? 2 : 0, extra));
+  BIE_TRY(make_work(ss, m, wk, mixed ? 2 : 0, extra, s));
   int refinements = 0;
   if (!mixed) {
     BIE_TRY(gmres(ss, BIE_FP64, f, x, true, std::vector<double>(S, o.tol), m, o.max_iter, wk, st,
