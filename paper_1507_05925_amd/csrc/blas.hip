@@ -168,6 +168,157 @@ __global__ __launch_bounds__(kBlock) void k_scale_to(const int *__restrict__ csy
   for (long long i = c0[c] + threadIdx.x; i < c1[c]; i += kBlock) v[i] = d > 0.0 ? w[i] / d : 0.0;
 }
 
+// ---- DCGS2 Arnoldi (classical Gram-Schmidt with delayed reorthogonalisation) ---------------
+// Step j >= 1 works on U, the candidate for basis vector V_j after one projection, and
+// Z = A U. One pass over V_0..V_{j-1} gives s = V^T U, t = V^T Z, U.U and U.Z (one reduction);
+// from them a small per-system kernel finishes column j - 1 of the Hessenberg matrix (the first
+// projection's coefficients plus s, and nu = sqrt(U.U - s.s) below the diagonal) and forms the
+// coefficients of the next projection without another pass, using the Arnoldi relation
+// A V_i = sum_k H[k][i] V_k: with V_j = (U - V s) / nu, A V_j = (Z - V (H s)) / nu, so
+// V_k . A V_j = (t_k - (H s)_k) / nu (k < j) and ((U.Z - s.t) / nu - (H s)_j) / nu (k = j).
+// A second pass writes V_j and the next candidate U' = A V_j - sum_{k<=j} g'_k V_k
+// = Z / nu - sum_{k<=j} c_k V_k with c_k = (H s)_k / nu + g'_k.
+
+// partial rows over chunk c: 2l = V_l . U and 2l + 1 = V_l . Z (l < nv); 2 nv = U . U and
+// 2 nv + 1 = U . Z. Z NULL: the odd rows are zero. Grid (C, nv + 1).
+__global__ __launch_bounds__(kBlock) void k_dots_uz(int C, const long long *__restrict__ c0,
+                                                   const long long *__restrict__ c1, int nv,
+                                                   const double *__restrict__ V, long long vstride,
+                                                   const double *__restrict__ U,
+                                                   const double *__restrict__ Z,
+                                                   double *__restrict__ partial) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x, l = blockIdx.y;
+  const long long i0 = c0[c], i1 = c1[c];
+  const double *a = l < nv ? V + l * vstride : U;
+  double su = 0.0, sz = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    const double x = a[i];
+    su = fma(x, U[i], su);
+    if (Z) sz = fma(x, Z[i], sz);
+  }
+  su = block_sum(su, sh);
+  sz = block_sum(sz, sh);
+  if (threadIdx.x == 0) {
+    partial[(long long)(2 * l) * C + c] = su;
+    partial[(long long)(2 * l + 1) * C + c] = sz;
+  }
+}
+
+// Per system s (one workgroup): raw[s][2i], raw[s][2i + 1] = s_i, t_i (i < j), raw[s][2j],
+// raw[s][2j + 1] = U.U, U.Z. Finishes column j - 1 (H[i][j-1] = G[i] + s_i, H[j][j-1] = nu) in
+// the device copy Hd (column-major, leading dimension ldh) and in mapped host memory col_out,
+// then stores the tag of step *seq_base + seq_off in flag[s]. Unless finalize: the coefficients
+// of the update, sc = s (k < j), cc = c (k <= j), inu = 1/nu, and G = g' (the first projection's
+// coefficients of the next column). nu = 0 (breakdown) gives zero coefficients. Dynamic LDS:
+// 3 (j + 1) doubles.
+__global__ __launch_bounds__(kBlock) void k_dcgs_small(
+    int j, int finalize, const double *__restrict__ raw, long long rstride,
+    double *__restrict__ G, double *__restrict__ Hd, long long ldh, long long hstride,
+    double *__restrict__ sc, double *__restrict__ cc, double *__restrict__ inu, long long hs,
+    double *__restrict__ col_out, unsigned long long *flag,
+    const unsigned long long *seq_base, unsigned long long seq_off) {
+  extern __shared__ double sm[];
+  double *sv = sm, *tv = sm + (j + 1), *hv = sm + 2 * (j + 1);
+  __shared__ double red[2];
+  const int s = blockIdx.x;
+  const double *rw = raw + s * rstride;
+  double *H = Hd + s * hstride;
+  for (int i = threadIdx.x; i < j; i += kBlock) {
+    sv[i] = rw[2 * i];
+    tv[i] = rw[2 * i + 1];
+  }
+  __syncthreads();
+  // s.s and s.t in a fixed order (first wave: lanes stride, then the shuffle tree)
+  if (threadIdx.x < 64) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < j; i += 64) {
+      a = fma(sv[i], sv[i], a);
+      b = fma(sv[i], tv[i], b);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
+    }
+    if (threadIdx.x == 0) {
+      red[0] = a;
+      red[1] = b;
+    }
+  }
+  __syncthreads();
+  const double nu2 = rw[2 * j] - red[0];
+  const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  // column j - 1, final
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    const double v = i < j ? G[s * hs + i] + sv[i] : nu;
+    H[(long long)(j - 1) * ldh + i] = v;
+    if (col_out) col_out[s * hs + i] = v;
+  }
+  if (flag) {
+    __threadfence_system();  // the column reaches host memory before its flag
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long tag = column_tag(*seq_base + seq_off);
+      __hip_atomic_store(flag + s, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+  if (finalize) return;
+  __syncthreads();  // column j - 1 of H is written (and G read)
+  // (H s)_k = sum_{i < j} H[k][i] s_i, k = 0..j (H[k][i] = 0 for k > i + 1)
+  for (int k = threadIdx.x; k <= j; k += kBlock) {
+    double a = 0.0;
+    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) a = fma(H[(long long)i * ldh + k], sv[i], a);
+    hv[k] = a;
+  }
+  __syncthreads();
+  const double iv = nu > 0.0 ? 1.0 / nu : 0.0;
+  for (int k = threadIdx.x; k <= j; k += kBlock) {
+    const double g = k < j ? (tv[k] - hv[k]) * iv : ((rw[2 * j + 1] - red[1]) * iv - hv[k]) * iv;
+    cc[s * hs + k] = nu > 0.0 ? hv[k] * iv + g : 0.0;
+    G[s * hs + k] = nu > 0.0 ? g : 0.0;
+    if (k < j) sc[s * hs + k] = sv[k];
+  }
+  if (threadIdx.x == 0) inu[s] = iv;
+}
+
+// V_j = (U - sum_{k<j} sc_k V_k) / nu and U = Z / nu - sum_{k<j} cc_k V_k - cc_j V_j, entry by
+// entry (one pass over V_0..V_{j-1}); grid (C, kSub) as k_combination.
+__global__ __launch_bounds__(kBlock) void k_dcgs_update(
+    int j, const int *__restrict__ csys, const long long *__restrict__ c0,
+    const long long *__restrict__ c1, const double *__restrict__ V, long long vstride,
+    const double *__restrict__ sc, const double *__restrict__ cc, const double *__restrict__ inu,
+    long long hs, double *__restrict__ U, const double *__restrict__ Z, double *__restrict__ Vj) {
+  const int c = blockIdx.x, s = csys[c];
+  const double *sr = sc + s * hs, *cr = cc + s * hs;
+  const double iv = inu[s], cj = cr[j];
+  for (long long i = c0[c] + blockIdx.y * kBlock + threadIdx.x; i < c1[c]; i += kSub * kBlock) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    int l = 0;
+    for (; l + 4 <= j; l += 4) {
+      const double v0 = V[l * vstride + i], v1 = V[(l + 1) * vstride + i];
+      const double v2 = V[(l + 2) * vstride + i], v3 = V[(l + 3) * vstride + i];
+      a0 = fma(v0, sr[l], a0);
+      a1 = fma(v1, sr[l + 1], a1);
+      a2 = fma(v2, sr[l + 2], a2);
+      a3 = fma(v3, sr[l + 3], a3);
+      b0 = fma(v0, cr[l], b0);
+      b1 = fma(v1, cr[l + 1], b1);
+      b2 = fma(v2, cr[l + 2], b2);
+      b3 = fma(v3, cr[l + 3], b3);
+    }
+    for (int r = 0; l + r < j; ++r) {
+      const double v = V[(l + r) * vstride + i];
+      if (r == 0) { a0 = fma(v, sr[l], a0); b0 = fma(v, cr[l], b0); }
+      if (r == 1) { a1 = fma(v, sr[l + 1], a1); b1 = fma(v, cr[l + 1], b1); }
+      if (r == 2) { a2 = fma(v, sr[l + 2], a2); b2 = fma(v, cr[l + 2], b2); }
+    }
+    const double vj = (U[i] - ((a0 + a1) + (a2 + a3))) * iv;
+    Vj[i] = vj;
+    U[i] = Z[i] * iv - ((b0 + b1) + (b2 + b3)) - cj * vj;
+  }
+}
+
 __global__ void k_axpby(long long total, double a, const double *__restrict__ x, double b,
                         double *__restrict__ y) {
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -221,6 +372,36 @@ int seg_combination_column(const Segments &sg, int nvec, const double *V, long l
   hipLaunchKernelGGL(k_normalize_column, dim3(sg.C), dim3(kBlock), 0, s, nvec, sg.csys,
                      sg.sys_chunk, sg.c0, sg.c1, scratch, w, vnext, h1, h2, hs, nrm, col_out, flag,
                      seq_base, seq_off);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int dcgs_dots(const Segments &sg, int nv, const double *V, long long vstride, const double *U,
+              const double *Z, double *raw, long long rstride, double *scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_uz, dim3(sg.C, nv + 1), dim3(kBlock), 0, s, sg.C, sg.c0, sg.c1, nv, V,
+                     vstride, U, Z, scratch);
+  hipLaunchKernelGGL(k_dots_stage2, dim3(2 * nv + 2, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk,
+                     scratch, raw, rstride, 0);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int dcgs_small(int S, int j, bool finalize, const double *raw, long long rstride, double *G,
+               double *Hd, long long ldh, long long hstride, double *sc, double *cc, double *inu,
+               long long hs, double *col_out, unsigned long long *flag,
+               const unsigned long long *seq_base, unsigned long long seq_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_small, dim3(S), dim3(kBlock), (size_t)3 * (j + 1) * sizeof(double), s,
+                     j, finalize ? 1 : 0, raw, rstride, G, Hd, ldh, hstride, sc, cc, inu, hs,
+                     col_out, flag, seq_base, seq_off);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int dcgs_update(const Segments &sg, int j, const double *V, long long vstride, const double *sc,
+                const double *cc, const double *inu, long long hs, double *U, const double *Z,
+                double *Vj, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_update, dim3(sg.C, kSub), dim3(kBlock), 0, s, j, sg.csys, sg.c0, sg.c1,
+                     V, vstride, sc, cc, inu, hs, U, Z, Vj);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

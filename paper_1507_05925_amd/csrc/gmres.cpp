@@ -93,27 +93,26 @@ int wait_column(const double *flags, int S, unsigned long long tag, hipStream_t 
 }
 
 struct Work {
-  double *V, *w, *r;          // V [(m+1)][Ntot]; w, r [Ntot]
-  double *h1, *h2, *nrm, *y;  // [S][m+2] x3, [S]
-  double *zero;               // [S][m+2] zeros (the absent second pass of a one-pass step)
-  double *scratch;            // dot partials [max(m+2, 4)][C]
+  double *V, *w, *r, *U;      // V [(m+1)][Ntot]; w (= A U), r, U (the next candidate) [Ntot]
+  double *y, *nrm;            // [S][m+2], [S]
+  double *h1, *zero;          // one-pass steps: coefficients, and zeros (the absent second pass)
+  double *G, *sc, *cc, *inu;  // DCGS2 coefficients: [S][m+2] x3, [S]
+  double *raw;                // per-system reductions [S][2m+4]
+  double *Hd;                 // device copy of the Hessenberg matrices [S][(m+2)(m+1)]
+  double *scratch;            // partial sums [2m+4][C]
+  long long hs = 0, rstride = 0, ldh = 0, hstride = 0;
 };
 
-// Gram-Schmidt passes per Arnoldi step: two (CGS2) for the float64 operator; one for the
-// float32-apply inner solves of the mixed mode, which only reach about 1e-6 and whose result
-// the float64 refinement residual checks (BIE_INNER_CGS=2 restores two passes there).
-int gs_passes(int precision) {
-  static const int inner = [] {
-    const char *e = std::getenv("BIE_INNER_CGS");
-    return e && std::atoi(e) == 2 ? 2 : 1;
-  }();
-  return precision == BIE_MIXED ? inner : 2;
-}
+// Arnoldi steps: DCGS2 (two passes over the basis, the column finished one step late) for the
+// float64 operator; one classical Gram-Schmidt pass for the float32-apply inner solves of the
+// mixed mode, which only reach about 1e-6 and whose result the float64 refinement residual
+// checks (the late column of DCGS2 would cost them one more apply per cycle).
+bool one_pass(int precision) { return precision == BIE_MIXED; }
 
-int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hipStream_t s) {
+int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hipStream_t st) {
   const size_t N = (size_t)ss.seg->Ntot;
   const int S = ss.seg->S;
-  BIE_TRY(ss.mem->big.reserve(((size_t)(m + 1) + 2 + extra_vectors) * N * sizeof(double) + 64));
+  BIE_TRY(ss.mem->big.reserve(((size_t)(m + 1) + 3 + extra_vectors) * N * sizeof(double) + 64));
   double *p = ss.mem->big.as<double>();
   wk.V = p;
   p += (size_t)(m + 1) * N;
@@ -121,28 +120,39 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hi
   p += N;
   wk.r = p;
   p += N;
+  wk.U = p;
+  p += N;
   for (int e = 0; e < extra_vectors; ++e) {
     extra[e] = p;
     p += N;
   }
-  const size_t hs = (size_t)m + 2;
-  // scratch: dot partials [(m+2)][C], or four per chunk for the fused update and norm
-  const size_t np = std::max<size_t>(hs, 4) * (size_t)ss.seg->C;
-  BIE_TRY(ss.mem->small.reserve((4 * hs * S + S + np) * sizeof(double) + 64));
+  wk.hs = m + 2;
+  wk.rstride = 2 * (long long)m + 4;
+  wk.ldh = m + 2;
+  wk.hstride = wk.ldh * (m + 1);
+  const size_t hs = (size_t)wk.hs;
+  const size_t np = (size_t)wk.rstride * (size_t)ss.seg->C;
+  const size_t small = (6 * hs + 2) * S + (size_t)wk.rstride * S + (size_t)wk.hstride * S + np;
+  BIE_TRY(ss.mem->small.reserve(small * sizeof(double) + 64));
   double *q = ss.mem->small.as<double>();
-  wk.h1 = q;
-  q += hs * S;
-  wk.h2 = q;
-  q += hs * S;
-  wk.y = q;
-  q += hs * S;
-  wk.zero = q;
-  q += hs * S;
-  wk.nrm = q;
-  q += S;
-  wk.scratch = q;
+  auto take = [&](size_t n) {
+    double *r = q;
+    q += n;
+    return r;
+  };
+  wk.y = take(hs * S);
+  wk.G = take(hs * S);
+  wk.sc = take(hs * S);
+  wk.cc = take(hs * S);
+  wk.nrm = take(S);
+  wk.inu = take(S);
+  wk.raw = take((size_t)wk.rstride * S);
+  wk.Hd = take((size_t)wk.hstride * S);
+  wk.h1 = take(hs * S);
+  wk.zero = take(hs * S);
+  wk.scratch = take(np);
   // written once here, never by a step (kernels only read it)
-  BIE_HIP_CHECK(hipMemsetAsync(wk.zero, 0, hs * S * sizeof(double), s));
+  BIE_HIP_CHECK(hipMemsetAsync(wk.zero, 0, hs * S * sizeof(double), st));
   return BIE_OK;
 }
 
@@ -218,27 +228,43 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     std::atomic_thread_fence(std::memory_order_seq_cst);
     mem.seq += (unsigned long long)m + 1;
     unsigned long long seqv[2] = {0, 0};
-    // the launches of step j (its arguments depend only on j and the solver's buffers)
+    // The launches of Arnoldi step j (DCGS2; their arguments depend only on j and the solver's
+    // buffers). Step 0: U = A V_0 - (V_0.A V_0) V_0 (the first projection of the first
+    // candidate). Step j in 1..m-1: Z = A U; the reductions; column j - 1 finished and written
+    // to pinned slot (j - 1) % 2 with its flag; V_j and the next candidate U. Step m (the end of
+    // a full cycle) only finishes column m - 1 (no apply).
+    // One-pass steps: step j (0..m-1) applies A to V_j, projects once and writes V_{j+1} and
+    // column j. Either way column c goes to pinned slot c % 2 with the tag of base + c + 1.
+    const bool onep = one_pass(precision);
+    const int lag = onep ? 0 : 1;       // column c comes from step c + lag
+    const int last_step = onep ? m - 1 : m;
     auto step_body = [&](int j, Stats &sts, hipStream_t s) -> int {
-      double *Vj = wk.V + (size_t)j * N;
-      double *Vj1 = wk.V + (size_t)(j + 1) * N;
-      BIE_TRY(apply(ss, precision, Vj, wk.w, sts, s));
-      // CGS2: h1 = V^T w, w -= V h1; h2 = V^T w, w -= V h2; column = h1 + h2; V_{j+1} = w/||w||.
-      // The second update is fused with ||w||; the column (h1 + h2 with ||w|| as entry j + 1)
-      // goes straight to pinned slot j % 2 (mapped host memory), followed by its flag word
-      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
-      double *col = mem.pinned_dev + (j & 1) * slot;
-      auto *flag = reinterpret_cast<unsigned long long *>(col + (size_t)S * hs);
-      if (gs_passes(precision) == 1) {  // w -= V h1, column = h1 (+ zeros), ||w||
-        BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.zero, wk.h1, hs, wk.w, wk.nrm, Vj1,
-                                       col, flag, base_d, (unsigned long long)j + 1, wk.scratch,
-                                       s));
+      if (onep) {
+        BIE_TRY(apply(ss, precision, wk.V + (size_t)j * N, wk.w, sts, s));
+        BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
+        double *col = mem.pinned_dev + (j & 1) * slot;
+        auto *flag = reinterpret_cast<unsigned long long *>(col + (size_t)S * hs);
+        return seg_combination_column(sg, j + 1, wk.V, N, wk.zero, wk.h1, hs, wk.w, wk.nrm,
+                                      wk.V + (size_t)(j + 1) * N, col, flag, base_d,
+                                      (unsigned long long)j + 1, wk.scratch, s);
+      }
+      if (j == 0) {
+        BIE_TRY(apply(ss, precision, wk.V, wk.U, sts, s));
+        BIE_TRY(seg_dots(sg, 1, wk.V, N, wk.U, wk.G, hs, wk.scratch, s));
+        BIE_TRY(seg_combination(sg, 1, wk.V, N, wk.G, hs, wk.U, -1.0, s));
         return BIE_OK;
       }
-      BIE_TRY(seg_combination(sg, j + 1, wk.V, N, wk.h1, hs, wk.w, -1.0, s));
-      BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h2, hs, wk.scratch, s));
-      BIE_TRY(seg_combination_column(sg, j + 1, wk.V, N, wk.h1, wk.h2, hs, wk.w, wk.nrm, Vj1, col,
-                                     flag, base_d, (unsigned long long)j + 1, wk.scratch, s));
+      const bool fin = j == m;
+      if (!fin) BIE_TRY(apply(ss, precision, wk.U, wk.w, sts, s));
+      BIE_TRY(dcgs_dots(sg, j, wk.V, N, wk.U, fin ? nullptr : wk.w, wk.raw, wk.rstride,
+                        wk.scratch, s));
+      double *col = mem.pinned_dev + ((j - 1) & 1) * slot;
+      auto *flag = reinterpret_cast<unsigned long long *>(col + (size_t)S * hs);
+      BIE_TRY(dcgs_small(S, j, fin, wk.raw, wk.rstride, wk.G, wk.Hd, wk.ldh, wk.hstride, wk.sc,
+                         wk.cc, wk.inu, hs, col, flag, base_d, (unsigned long long)j, s));
+      if (!fin)
+        BIE_TRY(dcgs_update(sg, j, wk.V, N, wk.sc, wk.cc, wk.inu, hs, wk.U, wk.w,
+                            wk.V + (size_t)j * N, s));
       return BIE_OK;
     };
     // With graphs: step j is captured (after running it once eagerly, which sizes every buffer)
@@ -249,13 +275,14 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     if (use_graphs) {
       char buf[256];
       std::snprintf(buf, sizeof buf, "|m%d|S%d|N%lld|%p|%p|%p|%p|%p|%p|%p|%p", m, S, N,
-                    (void *)wk.V, (void *)wk.w, (void *)wk.h1, (void *)wk.h2, (void *)wk.nrm,
+                    (void *)wk.V, (void *)wk.w, (void *)wk.U, (void *)wk.G, (void *)wk.Hd,
                     (void *)wk.scratch, (void *)mem.pinned_dev, (void *)sg.c0);
       gkey = ss.graph_key + buf;
     }
     auto step = [&](int j) -> int {
-      seqv[j & 1] = column_tag(base + (unsigned long long)j + 1);
-      if (!use_graphs) return step_body(j, st, s);
+      const int c = j - lag;  // the column this step finishes (none for the first DCGS2 step)
+      if (c >= 0) seqv[c & 1] = column_tag(base + (unsigned long long)c + 1);
+      if (!use_graphs || (!onep && j == m)) return step_body(j, st, s);
       StepGraphs &gr = mem.graphs[precision == BIE_MIXED ? 1 : 0];
       if (gr.key != gkey || gr.epoch != buffer_epoch()) {
         gr.clear();
@@ -264,7 +291,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       }
       if (j < (int)gr.exec.size() && gr.exec[j]) {
         BIE_HIP_CHECK(hipGraphLaunch(gr.exec[j], s));
-        if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;
+        if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;  // (j < m)
         st.pairs += ss.pairs_per_apply;
         ++mem.graph_replays;
         return BIE_OK;
@@ -304,10 +331,11 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       ++mem.graph_captures;
       return BIE_OK;
     };
-    BIE_TRY(step(0));
+    // Column j comes from step j + lag; step j + lag + 1 is queued before the host waits for it.
+    for (int k = 0; k <= lag; ++k) BIE_TRY(step(k));
     for (int j = 0; j < m; ++j) {
       st.iters += 1;
-      if (j + 1 < m && st.iters < max_iter) BIE_TRY(step(j + 1));
+      if (j + lag + 1 <= last_step && st.iters < max_iter) BIE_TRY(step(j + lag + 1));
       BIE_TRY(wait_column(mem.pinned + (j & 1) * slot + (size_t)S * hs, S, seqv[j & 1], s));
       const double *hh2 = mem.pinned + (j & 1) * slot;
       bool all_done = true;
@@ -340,7 +368,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       jend = j;
       if (all_done || st.iters >= max_iter) break;
     }
-    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the step queued ahead, if any, is complete
+    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the steps queued ahead, if any, are complete
     // y = H^{-1} g (upper triangular), x += V y
     const int nv = jend + 1;
     std::vector<double> yv((size_t)S * hs, 0.0);

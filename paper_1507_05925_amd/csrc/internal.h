@@ -232,6 +232,17 @@ __host__ __device__ inline unsigned long long column_tag(unsigned long long seq)
   return 0x7FF5A00000000000ULL | (seq & 0x00000FFFFFFFFFFFULL);
 }
 int vec_axpby(long long total, double a, const double *x, double b, double *y, hipStream_t s);
+// DCGS2 Arnoldi step pieces (blas.hip): raw[s][0 .. 2nv+1] = (V_l.U, V_l.Z)_l, U.U, U.Z (Z may be
+// NULL); the per-system column and coefficients; the update writing V_j and the next candidate
+int dcgs_dots(const Segments &sg, int nv, const double *V, long long vstride, const double *U,
+              const double *Z, double *raw, long long rstride, double *scratch, hipStream_t s);
+int dcgs_small(int S, int j, bool finalize, const double *raw, long long rstride, double *G,
+               double *Hd, long long ldh, long long hstride, double *sc, double *cc, double *inu,
+               long long hs, double *col_out, unsigned long long *flag,
+               const unsigned long long *seq_base, unsigned long long seq_off, hipStream_t s);
+int dcgs_update(const Segments &sg, int j, const double *V, long long vstride, const double *sc,
+                const double *cc, const double *inu, long long hs, double *U, const double *Z,
+                double *Vj, hipStream_t s);
 int seg_add_h(int S, const double *h1, double *h2, int cnt, long long hs, hipStream_t s);
 
 // ---- gmres.cpp ----------------------------------------------------------------------------
