@@ -50,6 +50,9 @@ FLOPS_PER_PAIR_STOKES = 19  # stresslet kernel per node pair (two components)
 PROFILE_EVERY = 8  # launches per timed launch of the roofline kernel in the timed solves
 
 
+MIXED_STRATEGY = {"relaxed": 0, "refine": 1}  # BIE_MIXED_RELAXED, BIE_MIXED_REFINE
+
+
 def m2l_flops_per_entry(p):
     """One M2L interaction-list entry as the kernel computes it: the source scaled by d^-m
     (p complex products, 6 flops each), the real Hankel matrix C (p x p) applied to its real and
@@ -65,6 +68,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--method", choices=["fmm", "direct"], default="fmm")
     p.add_argument("--precision", choices=["fp64", "mixed"], default=None)
+    p.add_argument("--mixed-strategy", choices=["relaxed", "refine"], default="relaxed")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -342,7 +346,7 @@ def mobility_bench(a):
     runs = {}
     for name, prec in (("fp64", bie2d.BIE_FP64), ("mixed", bie2d.BIE_MIXED)):
         o = bie2d.default_opts(precision=prec, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
-                               max_iter=2000)
+                               max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy])
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_mobility_solve(g, ft, o)
         torch.cuda.synchronize()
@@ -526,7 +530,8 @@ def main():
     meth = bie2d.BIE_FMM if a.method == "fmm" else bie2d.BIE_DIRECT
     precision = a.precision or ("fp64" if a.method == "fmm" else "mixed")
     prec = bie2d.BIE_MIXED if precision == "mixed" else bie2d.BIE_FP64
-    opts = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100, max_iter=2000)
+    opts = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100, max_iter=2000,
+                              mixed_strategy=MIXED_STRATEGY[a.mixed_strategy])
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -649,6 +654,7 @@ def main():
         "config": {"workload": "elastance, 1000 starfish r0(1+0.3cos5t) x 256 nodes (M=256000), "
                                "q~N(0,1), GMRES tol 1e-10",
                    "method": a.method, "precision": precision, "fmm_order": opts.fmm_order,
+                   **({"mixed_strategy": a.mixed_strategy} if prec == bie2d.BIE_MIXED else {}),
                    "nodes": curves.M, "bodies": curves.nbodies},
         "solves_per_s": a.steps / elapsed,
         "latency_s": {"p50": lat_sorted[len(lat) // 2],

@@ -55,13 +55,28 @@ extern "C" {
                              their distance to the continuum solution is at risk. */
 
 #define BIE_FP64 0   /* every step in float64 */
-#define BIE_MIXED 1  /* inner GMRES on a float32 far field inside float64 iterative refinement.
-                        Direct method: far-field pair sums in float32 (body-relative
+#define BIE_MIXED 1  /* float32 far field in the late GMRES steps (or the inner solves of a
+                        refinement: mixed_strategy). Direct: float32 pair sums (body-relative
                         coordinates, float64 accumulation across source bodies), float64
-                        self-body blocks. FMM: float32 near field (leaf-relative coordinates)
-                        and Laplace expansions, expansions of about half the order; float64
-                        same-body near-diagonal band. Both: float64 diagonal, completion,
-                        Arnoldi and refinement residuals (float64 operator). */
+                        self-body blocks. FMM: float64 near field, expansions of about half the
+                        order, float32 for Laplace (multipoles, M2M, M2L, evaluation), float64
+                        for Stokes. Both: float64 diagonal, completion, Arnoldi and true
+                        residuals (float64 operator). */
+
+/* How BIE_MIXED wins the float64 accuracy back:
+ * BIE_MIXED_RELAXED  one float64 GMRES (float64 Arnoldi and residuals) whose steps apply the
+ *                    float32 operator once the estimated relative residual of every system it
+ *                    applies to is below tol / 1e-6 (1e-6: about the float32 apply's relative
+ *                    error): the error a step's apply may carry grows as the residual it reduces
+ *                    falls (relaxed inexact Krylov, Simoncini & Szyld 2003). The solve stops
+ *                    only on the float64 true residual of a cycle start, so a cycle that the
+ *                    float32 steps left short is followed by another. The rhs of one geometry
+ *                    share each step's precision; the items of a batch choose theirs apart (at
+ *                    most 1024 items; larger batches choose together).
+ * BIE_MIXED_REFINE   iterative refinement: inner GMRES on the float32 operator to inner_tol (one
+ *                    Gram-Schmidt pass), x += d, float64 residual, repeat (max_refine). */
+#define BIE_MIXED_RELAXED 0
+#define BIE_MIXED_REFINE 1
 
 #define BIE_DIRECT 0 /* all-pairs direct summation */
 #define BIE_FMM 1    /* 2D fast multipole method for the far field */
@@ -87,6 +102,7 @@ typedef struct {
   double fmm_eps;   /* BIE_FMM: > 0 sets the expansion order from a relative accuracy
                        target, p = ceil(log(fmm_eps) / log(0.55)) clamped to [8, 64]
                        (the FMM error falls about as 0.55^p); 0 = use fmm_order           */
+  int mixed_strategy; /* BIE_MIXED: BIE_MIXED_RELAXED (default) or BIE_MIXED_REFINE   */
   int l2_scaling;   /* 1: GMRES on the symmetrised system D A D^-1 (D mu) = D f with
                        D = diag(sqrt(w)) (the paper's L2 rescaling of the numerical
                        section): same solution, the stopping test then uses the discrete
@@ -114,11 +130,12 @@ const char *bie_last_error(void);
 
 /* Fills *o with the defaults: BIE_FP64, BIE_DIRECT, tol 1e-12, restart 100, max_iter 500,
  * inner_tol 1e-6, max_refine 10, fmm_order 40, fmm_leaf 64, viscosity 1, fmm_eps 0,
- * l2_scaling 0. With BIE_FMM and BIE_MIXED the inner applies use order ceil(0.55 fmm_order)
- * (about the square root of the accuracy) with a float32 near field and, for Laplace, float32
- * expansions (Stokes expansions stay float64: their C' - conj(z) A' combination cancels); the
- * float64 refinement residuals use the full order in float64. fmm_order must lie in [4, 64];
- * the library rounds the order up to a multiple of 8. */
+ * mixed_strategy BIE_MIXED_RELAXED, l2_scaling 0. With BIE_FMM and BIE_MIXED the float32-apply
+ * steps use order ceil(0.55 fmm_order) (about the square root of the accuracy); the near field
+ * stays float64, the Laplace expansions (multipoles, M2M, M2L, evaluation) are float32, the
+ * Stokes expansions stay float64 (their C' - conj(z) A' combination cancels). The float64
+ * applies use the full order. fmm_order must lie in [4, 64]; the library rounds the order up
+ * to a multiple of 8. */
 int bie_default_opts(bie_opts *o);
 
 /* ---- context: device, default options, owned geometries -------------------------------------
@@ -306,8 +323,9 @@ int bie_resistance_solve(bie_geom *g, int nrhs, const double *VW, double *FT, do
 /* ---- batched solves over several geometries (many systems in one lock-step GMRES) ---------
  * Every right-hand side of every item is one system; all systems advance together, one batched
  * operator apply per Arnoldi step, each with its own Hessenberg matrix and convergence test, so
- * a system's iterates do not depend on the other members of the batch (reductions are per
- * system and deterministic). Used for P and M of many geometries at once and by the server.
+ * an item's iterates do not depend on the other items of the batch (reductions are per system
+ * and deterministic; with BIE_MIXED_RELAXED the rhs of one item share each step's precision, and
+ * batches of more than 1024 items share it across items). Used for P and M of many geometries at once and by the server.
  * kind: 0 = elastance (in [nrhs][N] charges, out [nrhs][N] potentials), 1 = mobility (in
  * [nrhs][3N] (F, T), out [nrhs][3N] (v, omega)). in == NULL means the identity block: nrhs must
  * equal N (kind 0) or 3N (kind 1) and out receives P or M column by column (column-major).

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bie2d.h")
 BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE, BIE_ERESOLVE = 0, -1, -2, -3, -4, -5
 BIE_FP64, BIE_MIXED = 0, 1
 BIE_DIRECT, BIE_FMM, BIE_AUTO = 0, 1, 2
+BIE_MIXED_RELAXED, BIE_MIXED_REFINE = 0, 1
 
 
 class BieError(RuntimeError):
@@ -41,7 +42,7 @@ class bie_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int),
                 ("viscosity", ctypes.c_double), ("fmm_eps", ctypes.c_double),
-                ("l2_scaling", ctypes.c_int)]
+                ("mixed_strategy", ctypes.c_int), ("l2_scaling", ctypes.c_int)]
 
 
 class bie_batch_item(ctypes.Structure):

@@ -135,6 +135,7 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
                  o.fmm_leaf};
     first_sys[i + 1] = first_sys[i] + items[i].nrhs;
   }
+  ss.group_ptr = first_sys;  // items: a relaxed mixed solve picks precisions per item
   SysSet *ssp = &ss;
   MultiPlan **plan = &b->plan;
   ss.apply = [ssp, plan, mitems, first_sys, Ntot](int precision, const double *in, double *out,
@@ -147,6 +148,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
         for (int k = first_sys[i]; k < first_sys[i + 1]; ++k) a |= ssp->active[k];
         act[i] = a;
       }
+    if (precision == kPrecPerGroup)
+      return multi_apply(*plan, mitems, act, BIE_FP64, in, out, Ntot, st, &ssp->group_f32);
     return multi_apply(*plan, mitems, act, precision, in, out, Ntot, st);
   };
   std::vector<double> rel;

@@ -95,6 +95,7 @@ static void fill_defaults(bie_opts *o) {
   o->max_refine = 10;
   o->fmm_order = 40;
   o->fmm_leaf = 64;
+  o->mixed_strategy = BIE_MIXED_RELAXED;
   o->viscosity = 1.0;
   o->fmm_eps = 0.0;
   o->l2_scaling = 0;
@@ -106,7 +107,8 @@ int check_opts(const bie_opts &o) {
       !(o.tol > 0.0) || o.restart < 1 ||
       o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
       o.fmm_order > 64 || o.fmm_leaf < 0 || !(o.viscosity > 0.0) || !std::isfinite(o.viscosity) ||
-      !(o.fmm_eps >= 0.0) || !(o.fmm_eps < 1.0) || (o.l2_scaling != 0 && o.l2_scaling != 1)) {
+      !(o.fmm_eps >= 0.0) || !(o.fmm_eps < 1.0) || (o.l2_scaling != 0 && o.l2_scaling != 1) ||
+      (o.mixed_strategy != BIE_MIXED_RELAXED && o.mixed_strategy != BIE_MIXED_REFINE)) {
     set_error("invalid bie_opts");
     return BIE_EINVAL;
   }

@@ -39,7 +39,7 @@ struct Stats {
 
 int apply(SysSet &ss, int precision, const double *in, double *out, Stats &st, hipStream_t s) {
   BIE_TRY(ss.apply(precision, in, out, s));
-  if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;
+  if (precision != BIE_FP64) st.applies32 += 1; else st.applies64 += 1;  // (per group: some f32)
   st.pairs += ss.pairs_per_apply;
   return BIE_OK;
 }
@@ -157,10 +157,16 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hi
 }
 
 // GMRES(m) on A x = f for every system. x holds the iterate on exit (x0 = 0 if x_is_zero).
+// With relaxed (and precision BIE_MIXED): float64 GMRES whose Arnoldi steps apply the float32
+// operator once every active system's estimated relative residual is below
+// tol / kF32ApplyError (the apply error a step may carry falls with the residual it reduces,
+// Simoncini & Szyld 2003); earlier steps and every cycle's true residual use float64.
+constexpr double kF32ApplyError = 1e-6;  // about the float32 apply's relative error
+
 int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
           const std::vector<double> &tol, int m, int max_iter, Work &wk, Stats &st,
           std::vector<double> &relres, std::vector<int> &conv, hipStream_t s,
-          int max_cycles = 1 << 30) {
+          int max_cycles = 1 << 30, bool relaxed = false) {
   const Segments &sg = *ss.seg;
   SolverMem &mem = *ss.mem;
   const int S = sg.S;
@@ -177,12 +183,21 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   int cycles = 0;
   std::vector<double> H((size_t)S * (m + 1) * m), cs((size_t)S * m), sn((size_t)S * m),
       gv((size_t)S * (m + 1));
+  const int ngroups = relaxed && ss.group_ptr.size() >= 2 &&
+                              (int)ss.group_ptr.size() - 1 <= kMaxPrecGroups
+                          ? (int)ss.group_ptr.size() - 1
+                          : 1;
+  std::vector<int> group_of(S, 0);
+  if (ngroups > 1)
+    for (int q = 0; q < ngroups; ++q)
+      for (int r = ss.group_ptr[q]; r < ss.group_ptr[q + 1]; ++r) group_of[r] = q;
+  std::vector<char> gf32(ngroups, 0);
   while (cycles < max_cycles) {
     ++cycles;
     if (first && x_is_zero) {
       BIE_HIP_CHECK(hipMemcpyAsync(wk.r, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     } else {
-      BIE_TRY(apply(ss, precision, x, wk.r, st, s));
+      BIE_TRY(apply(ss, relaxed ? BIE_FP64 : precision, x, wk.r, st, s));
       BIE_TRY(vec_axpby(N, 1.0, f, -1.0, wk.r, s));
     }
     first = false;
@@ -235,12 +250,18 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     // a full cycle) only finishes column m - 1 (no apply).
     // One-pass steps: step j (0..m-1) applies A to V_j, projects once and writes V_{j+1} and
     // column j. Either way column c goes to pinned slot c % 2 with the tag of base + c + 1.
-    const bool onep = one_pass(precision);
+    const bool onep = one_pass(precision) && !relaxed;
+    // relaxed: per group of systems (batch items; else all systems), the largest estimated
+    // relative residual over tolerance of its systems still iterating (after the last column
+    // the host has seen) decides the precision of the group's apply when a step is queued
+    std::vector<double> gworst(ngroups, 0.0);
+    for (int r = 0; r < S; ++r)
+      if (active[r]) gworst[group_of[r]] = std::max(gworst[group_of[r]], relres[r] / tol[r]);
     const int lag = onep ? 0 : 1;       // column c comes from step c + lag
     const int last_step = onep ? m - 1 : m;
-    auto step_body = [&](int j, Stats &sts, hipStream_t s) -> int {
+    auto step_body = [&](int j, Stats &sts, hipStream_t s, int sp) -> int {
       if (onep) {
-        BIE_TRY(apply(ss, precision, wk.V + (size_t)j * N, wk.w, sts, s));
+        BIE_TRY(apply(ss, sp, wk.V + (size_t)j * N, wk.w, sts, s));
         BIE_TRY(seg_dots(sg, j + 1, wk.V, N, wk.w, wk.h1, hs, wk.scratch, s));
         double *col = mem.pinned_dev + (j & 1) * slot;
         auto *flag = reinterpret_cast<unsigned long long *>(col + (size_t)S * hs);
@@ -249,13 +270,13 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
                                       (unsigned long long)j + 1, wk.scratch, s);
       }
       if (j == 0) {
-        BIE_TRY(apply(ss, precision, wk.V, wk.U, sts, s));
+        BIE_TRY(apply(ss, sp, wk.V, wk.U, sts, s));
         BIE_TRY(seg_dots(sg, 1, wk.V, N, wk.U, wk.G, hs, wk.scratch, s));
         BIE_TRY(seg_combination(sg, 1, wk.V, N, wk.G, hs, wk.U, -1.0, s));
         return BIE_OK;
       }
       const bool fin = j == m;
-      if (!fin) BIE_TRY(apply(ss, precision, wk.U, wk.w, sts, s));
+      if (!fin) BIE_TRY(apply(ss, sp, wk.U, wk.w, sts, s));
       BIE_TRY(dcgs_dots(sg, j, wk.V, N, wk.U, fin ? nullptr : wk.w, wk.raw, wk.rstride,
                         wk.scratch, s));
       double *col = mem.pinned_dev + ((j - 1) & 1) * slot;
@@ -274,7 +295,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     std::string gkey;
     if (use_graphs) {
       char buf[256];
-      std::snprintf(buf, sizeof buf, "|m%d|S%d|N%lld|%p|%p|%p|%p|%p|%p|%p|%p", m, S, N,
+      std::snprintf(buf, sizeof buf, "|m%d|o%d|S%d|N%lld|%p|%p|%p|%p|%p|%p|%p|%p", m, (int)onep, S, N,
                     (void *)wk.V, (void *)wk.w, (void *)wk.U, (void *)wk.G, (void *)wk.Hd,
                     (void *)wk.scratch, (void *)mem.pinned_dev, (void *)sg.c0);
       gkey = ss.graph_key + buf;
@@ -282,8 +303,15 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     auto step = [&](int j) -> int {
       const int c = j - lag;  // the column this step finishes (none for the first DCGS2 step)
       if (c >= 0) seqv[c & 1] = column_tag(base + (unsigned long long)c + 1);
-      if (!use_graphs || (!onep && j == m)) return step_body(j, st, s);
-      StepGraphs &gr = mem.graphs[precision == BIE_MIXED ? 1 : 0];
+      int sp = precision;
+      if (relaxed) {
+        int nf = 0;
+        for (int q = 0; q < ngroups; ++q) nf += gf32[q] = gworst[q] * kF32ApplyError < 1.0;
+        sp = nf == ngroups ? BIE_MIXED : nf == 0 ? BIE_FP64 : kPrecPerGroup;
+        if (sp == kPrecPerGroup) ss.group_f32 = gf32;
+      }
+      if (!use_graphs || sp == kPrecPerGroup || (!onep && j == m)) return step_body(j, st, s, sp);
+      StepGraphs &gr = mem.graphs[sp == BIE_MIXED ? 1 : 0];
       if (gr.key != gkey || gr.epoch != buffer_epoch()) {
         gr.clear();
         gr.key = gkey;
@@ -291,12 +319,12 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       }
       if (j < (int)gr.exec.size() && gr.exec[j]) {
         BIE_HIP_CHECK(hipGraphLaunch(gr.exec[j], s));
-        if (precision == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;  // (j < m)
+        if (sp == BIE_MIXED) st.applies32 += 1; else st.applies64 += 1;  // (j < m)
         st.pairs += ss.pairs_per_apply;
         ++mem.graph_replays;
         return BIE_OK;
       }
-      BIE_TRY(step_body(j, st, s));
+      BIE_TRY(step_body(j, st, s, sp));
       if (gr.epoch != buffer_epoch()) {  // the eager step allocated: earlier captures are stale
         gr.clear();
         gr.key = gkey;
@@ -309,7 +337,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       int rc;
       {
         ProfSuspend quiet;  // no profiling events inside a captured step
-        rc = step_body(j, dummy, mem.cap);
+        rc = step_body(j, dummy, mem.cap, sp);
       }
       const hipError_t e = hipStreamEndCapture(mem.cap, &graph);
       if (rc != BIE_OK || e != hipSuccess || !graph) {
@@ -339,6 +367,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       BIE_TRY(wait_column(mem.pinned + (j & 1) * slot + (size_t)S * hs, S, seqv[j & 1], s));
       const double *hh2 = mem.pinned + (j & 1) * slot;
       bool all_done = true;
+      std::fill(gworst.begin(), gworst.end(), 0.0);
       for (int r = 0; r < S; ++r) {
         if (!active[r] || jdone[r] >= 0) continue;
         double *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
@@ -360,6 +389,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
         gg[j + 1] = -sv[j] * gg[j];
         gg[j] = c[j] * gg[j];
         const double res = std::fabs(gg[j + 1]) / fnorm[r];
+        gworst[group_of[r]] = std::max(gworst[group_of[r]], res / tol[r]);
         if (verbosity() >= 2 && r == 0)
           std::fprintf(stderr, "[bie]   j=%d est rel res=%.3e hn=%.3e\n", j, res, hn);
         if (res <= tol[r] || hn == 0.0) jdone[r] = j;
@@ -465,9 +495,9 @@ int solve_systems(SysSet &ss, const bie_opts &o, const double *f, double *x,
   const bool mixed = o.precision == BIE_MIXED;
   BIE_TRY(make_work(ss, m, wk, mixed ? 2 : 0, extra, s));
   int refinements = 0;
-  if (!mixed) {
-    BIE_TRY(gmres(ss, BIE_FP64, f, x, true, std::vector<double>(S, o.tol), m, o.max_iter, wk, st,
-                  relres, conv, s));
+  if (!mixed || o.mixed_strategy == BIE_MIXED_RELAXED) {
+    BIE_TRY(gmres(ss, mixed ? BIE_MIXED : BIE_FP64, f, x, true, std::vector<double>(S, o.tol), m,
+                  o.max_iter, wk, st, relres, conv, s, 1 << 30, mixed));
   } else {
     // x = 0, r = f; repeat: solve A32 d = r to what the outer tolerance needs; x += d; r = f - A64 x
     double *rr = extra[0], *d = extra[1];

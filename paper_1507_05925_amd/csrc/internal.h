@@ -108,11 +108,24 @@ struct SolverMem {
 };
 
 // A set of systems with one batched apply: out = A in (flat layout of seg).
+// Apply precision value meaning "per group": group g's systems use float32 where
+// SysSet::group_f32[g] is set, float64 elsewhere.
+constexpr int kPrecPerGroup = -1;
+// Most groups (batch items) whose applies can take per-group precisions; a set with more groups
+// is treated as one group.
+constexpr int kMaxPrecGroups = 1024;
+
 struct SysSet {
   Segments *seg = nullptr;
   SolverMem *mem = nullptr;
   long long pairs_per_apply = 0;
   std::vector<char> active;  // per system; set by the solver before each apply (empty = all)
+  // groups of systems whose applies are independent of each other's (batch items: system
+  // ranges group_ptr[g] .. group_ptr[g+1]-1); empty = all systems form one group. A relaxed
+  // mixed solve chooses each step's precision per group, so a group's iterates do not depend on
+  // the other groups.
+  std::vector<int> group_ptr;
+  std::vector<char> group_f32;  // per group, read by apply(kPrecPerGroup, ...)
   std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
   // identity of the apply's arguments for graph capture (empty: the steps are never captured,
   // e.g. batches, whose applies depend on the active flags)
@@ -285,9 +298,11 @@ struct MultiItem {
   int fmm_order = 40, fmm_leaf = 64;  // its expansion order and leaf population (FMM items)
 };
 struct MultiPlan;
+// item_f32 (nullptr: every item uses precision): per item, 1 = float32 far field (BIE_MIXED),
+// 0 = float64; at most kMaxPrecGroups items.
 int multi_apply(MultiPlan *&plan, const std::vector<MultiItem> &items,
                 const std::vector<char> &active, int precision, const double *in, double *out,
-                long long Ntot, hipStream_t s);
+                long long Ntot, hipStream_t s, const std::vector<char> *item_f32 = nullptr);
 void multi_destroy(MultiPlan *p);
 inline long long align8(long long v) { return (v + 7) / 8 * 8; }
 

@@ -115,6 +115,15 @@ __device__ inline double block_sum(double v, double *sh) {
 // task encoding: 4 ints per far task (item, chunk, tile, split); 3 per epilogue (item, body, rhs);
 // 2 per pack task (item, rhs)
 
+// Far-field precision of an item: MODE 0 float64, 1 float32, 2 bit `it` of the mask (per-item
+// precisions of a relaxed mixed batch; the branch is uniform over the workgroup).
+struct ItemMask {
+  unsigned long long w[kMaxPrecGroups / 64];
+};
+__device__ __forceinline__ bool item_f32(int mode, const ItemMask &m, int it) {
+  return mode == 1 || (mode == 2 && ((m.w[it >> 6] >> (it & 63)) & 1ull));
+}
+
 __global__ __launch_bounds__(kBlock) void k_multi_pack(const int *__restrict__ tasks,
                                                       const ItemDesc *__restrict__ D,
                                                       const double *__restrict__ mu,
@@ -132,14 +141,16 @@ __global__ __launch_bounds__(kBlock) void k_multi_pack(const int *__restrict__ t
   }
 }
 
-template <int R, bool F32>
+template <int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_multi_far_lap(const int *__restrict__ tasks,
                                                          const ItemDesc *__restrict__ D,
                                                          const double *__restrict__ s64,
                                                          const float *__restrict__ s32,
-                                                         double *__restrict__ partial) {
+                                                         double *__restrict__ partial,
+                                                         const ItemMask f32mask) {
   const int *tk = tasks + 4 * blockIdx.x;
   const int it = tk[0], ch = tk[1], tile = tk[2], sp = tk[3];
+  const bool F32 = item_f32(MODE, f32mask, it);
   const ItemDesc &d = D[it];
   const int M = d.M;
   const int i = tile * kT + threadIdx.x;
@@ -222,14 +233,16 @@ __global__ __launch_bounds__(kBlock) void k_multi_far_lap(const int *__restrict_
   for (int r = 0; r < R; ++r) o[r * kT + threadIdx.x] = -(a * Gx[r] + b * Gy[r]) / (2.0 * kPi);
 }
 
-template <int R, bool F32>
+template <int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_multi_far_stk(const int *__restrict__ tasks,
                                                          const ItemDesc *__restrict__ D,
                                                          const double *__restrict__ s64,
                                                          const float *__restrict__ s32,
-                                                         double *__restrict__ partial) {
+                                                         double *__restrict__ partial,
+                                                         const ItemMask f32mask) {
   const int *tk = tasks + 4 * blockIdx.x;
   const int it = tk[0], ch = tk[1], tile = tk[2], sp = tk[3];
+  const bool F32 = item_f32(MODE, f32mask, it);
   const ItemDesc &d = D[it];
   const int M = d.M;
   const int i = tile * kT + threadIdx.x;
@@ -522,9 +535,27 @@ int build_plan(MultiPlan &P, const std::vector<MultiItem> &items, const std::vec
 // out = (1/2 I + K + L) in for every active item (rhs blocks at items[i].io in flat vectors);
 // inactive items get out = 0.
 int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::vector<char> &active,
-                int precision, const double *in, double *out, long long Ntot, hipStream_t s) {
+                int precision, const double *in, double *out, long long Ntot, hipStream_t s,
+                const std::vector<char> *item_f32) {
   if (!P) P = new MultiPlan();
   const int n = (int)items.size();
+  if (item_f32 && ((int)item_f32->size() != n || n > kMaxPrecGroups)) {
+    set_error("multi_apply: per-item precisions need one flag per item and at most 1024 items");
+    return BIE_EINVAL;
+  }
+  // far-field mode: 0 float64, 1 float32, 2 per item (mask)
+  ItemMask mask{};
+  int mode = precision == BIE_MIXED ? 1 : 0;
+  if (item_f32) {
+    int nf = 0;
+    for (int i = 0; i < n; ++i)
+      if ((*item_f32)[i]) {
+        mask.w[i >> 6] |= 1ull << (i & 63);
+        ++nf;
+      }
+    mode = nf == 0 ? 0 : nf == n ? 1 : 2;
+  }
+  auto f32_of = [&](int i) { return mode == 2 ? (*item_f32)[i] != 0 : mode == 1; };
   bool same = P->valid && (int)P->key_gen.size() == n && P->key_active == active;
   for (int i = 0; same && i < n; ++i)
     same = P->key_gen[i] == items[i].g->gen && P->key_kind[i] == items[i].kind &&
@@ -548,7 +579,7 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
     P->key_active = active;
     P->valid = true;
   }
-  const bool f32 = precision == BIE_MIXED;
+  const bool f32 = mode != 0;  // some item needs the float32 strengths
   // workspace: s64 [Np], s32 [Np], partial (Laplace slots, then Stokes slots); Np pads Ntot by
   // R rhs of the longest item so that a far task's last rhs chunk can read past its item
   long long maxlen = 0;
@@ -574,21 +605,27 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
                        s64, f32 ? s32 : nullptr);
   if (P->nfar[0] > 0) {
     ProfScope prof(f32 ? BIE_K_FAR_LAPLACE_F32 : BIE_K_FAR_LAPLACE_F64, s, 0);
-    if (f32)
-      hipLaunchKernelGGL((k_multi_far_lap<kRLap, true>), dim3(P->nfar[0]), dim3(kBlock), 0, s,
-                         P->far_task[0], P->desc, s64, s32, part_lap);
+    if (mode == 2)
+      hipLaunchKernelGGL((k_multi_far_lap<kRLap, 2>), dim3(P->nfar[0]), dim3(kBlock), 0, s,
+                         P->far_task[0], P->desc, s64, s32, part_lap, mask);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_multi_far_lap<kRLap, 1>), dim3(P->nfar[0]), dim3(kBlock), 0, s,
+                         P->far_task[0], P->desc, s64, s32, part_lap, mask);
     else
-      hipLaunchKernelGGL((k_multi_far_lap<kRLap, false>), dim3(P->nfar[0]), dim3(kBlock), 0, s,
-                         P->far_task[0], P->desc, s64, s32, part_lap);
+      hipLaunchKernelGGL((k_multi_far_lap<kRLap, 0>), dim3(P->nfar[0]), dim3(kBlock), 0, s,
+                         P->far_task[0], P->desc, s64, s32, part_lap, mask);
   }
   if (P->nfar[1] > 0) {
     ProfScope prof(f32 ? BIE_K_FAR_STOKES_F32 : BIE_K_FAR_STOKES_F64, s, 0);
-    if (f32)
-      hipLaunchKernelGGL((k_multi_far_stk<kRStk, true>), dim3(P->nfar[1]), dim3(kBlock), 0, s,
-                         P->far_task[1], P->desc, s64, s32, part_stk);
+    if (mode == 2)
+      hipLaunchKernelGGL((k_multi_far_stk<kRStk, 2>), dim3(P->nfar[1]), dim3(kBlock), 0, s,
+                         P->far_task[1], P->desc, s64, s32, part_stk, mask);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_multi_far_stk<kRStk, 1>), dim3(P->nfar[1]), dim3(kBlock), 0, s,
+                         P->far_task[1], P->desc, s64, s32, part_stk, mask);
     else
-      hipLaunchKernelGGL((k_multi_far_stk<kRStk, false>), dim3(P->nfar[1]), dim3(kBlock), 0, s,
-                         P->far_task[1], P->desc, s64, s32, part_stk);
+      hipLaunchKernelGGL((k_multi_far_stk<kRStk, 0>), dim3(P->nfar[1]), dim3(kBlock), 0, s,
+                         P->far_task[1], P->desc, s64, s32, part_stk, mask);
   }
   {
     ProfScope prof(BIE_K_EPILOGUE, s, 0);
@@ -628,8 +665,8 @@ int multi_apply(MultiPlan *&P, const std::vector<MultiItem> &items, const std::v
     if (on[i] >= 0) {
       items[i].g->fmm_order = items[i].fmm_order;  // the caller's expansion order and leaf size
       items[i].g->fmm_leaf = items[i].fmm_leaf;
-      rc = apply_operator(items[i].g, items[i].kind, precision, BIE_FMM, 1, 1.0, items[i].nrhs,
-                          in + items[i].io, out + items[i].io, P->pool[on[i]]);
+      rc = apply_operator(items[i].g, items[i].kind, f32_of(i) ? BIE_MIXED : BIE_FP64, BIE_FMM, 1,
+                          1.0, items[i].nrhs, in + items[i].io, out + items[i].io, P->pool[on[i]]);
     }
   for (int k = 0; k < used; ++k) {
     BIE_HIP_CHECK(hipEventRecord(P->join[k], P->pool[k]));

@@ -83,6 +83,7 @@ def test_option_validation_before_device():
     item = bie2d.bie_batch_item()
     info = bie2d.bie_info()
     for field, value in (("viscosity", 0.0), ("viscosity", float("nan")), ("fmm_eps", -1e-3),
+                         ("mixed_strategy", 2), ("mixed_strategy", -1),
                          ("l2_scaling", 2), ("l2_scaling", 1)):
         o = bie2d.default_opts(**{field: value})
         rc = L.bie_batch_solve(b, 1, ctypes.cast(ctypes.pointer(item), ctypes.c_void_p),
@@ -92,6 +93,7 @@ def test_option_validation_before_device():
     L.bie_batch_destroy(b)
     o = bie2d.default_opts()
     assert o.viscosity == 1.0 and o.fmm_eps == 0.0 and o.l2_scaling == 0
+    assert o.mixed_strategy == bie2d.BIE_MIXED_RELAXED
 
 
 @no_gpu

@@ -43,7 +43,7 @@ def test_context_defaults_and_ownership():
     assert ctx.defaults().precision == bie2d.BIE_MIXED
     g = ctx.geometry(c)
     phi, info = bie2d.bie_elastance_solve(g, dev(q[None]))  # opts NULL: the context's
-    assert info["refinements"] >= 1 and info["applies_fp32"] > 0, info
+    assert info["applies_fp32"] > 0, info  # the context's mixed precision
     assert rel(phi[0], ref) < 1e-9
     phi2, info2 = bie2d.bie_elastance_solve(g, dev(q[None]), bie2d.default_opts(tol=1e-12))
     assert info2["refinements"] == 0 and rel(phi2[0], ref) < 1e-10
