@@ -65,9 +65,10 @@ extern "C" {
 
 /* How BIE_MIXED wins the float64 accuracy back:
  * BIE_MIXED_RELAXED  one float64 GMRES (float64 Arnoldi and residuals) whose steps apply the
- *                    float32 operator once the estimated relative residual of every system it
- *                    applies to is below tol / 1e-6 (1e-6: about the float32 apply's relative
- *                    error): the error a step's apply may carry grows as the residual it reduces
+ *                    BIE_MIXED operator once the estimated relative residual of every system it
+ *                    applies to is below tol / eta, eta that apply's relative error (1e-7
+ *                    direct, 1e-6 FMM Laplace, 1e-8 FMM Stokes; measured values rounded up):
+ *                    the error a step's apply may carry grows as the residual it reduces
  *                    falls (relaxed inexact Krylov, Simoncini & Szyld 2003). The solve stops
  *                    only on the float64 true residual of a cycle start, so a cycle that the
  *                    float32 steps left short is followed by another. The rhs of one geometry

@@ -131,11 +131,13 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   for (int i = 0; i < nitems; ++i) {
     bie_geom *g = items[i].g;
     mitems[i] = {g, items[i].kind, items[i].nrhs, item_off[i],
-                 o.method == BIE_FMM || (o.method == BIE_AUTO && g->M > 32768), o.fmm_order,
+                 method_is_fmm(o.method, g->M), o.fmm_order,
                  o.fmm_leaf};
     first_sys[i + 1] = first_sys[i] + items[i].nrhs;
   }
   ss.group_ptr = first_sys;  // items: a relaxed mixed solve picks precisions per item
+  for (int i = 0; i < nitems; ++i)
+    ss.group_eta.push_back(mixed_apply_error(items[i].g, items[i].kind, o.method));
   SysSet *ssp = &ss;
   MultiPlan **plan = &b->plan;
   ss.apply = [ssp, plan, mitems, first_sys, Ntot](int precision, const double *in, double *out,

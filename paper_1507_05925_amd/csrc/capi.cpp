@@ -641,7 +641,7 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   BIE_TRY(input_check(kind, g->N, nrhs, data, s, net));
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
   g->fmm_order = effective_order(o);
-  const int meth = o.method == BIE_AUTO ? (g->M > 32768 ? BIE_FMM : BIE_DIRECT) : o.method;
+  const int meth = o.method == BIE_AUTO ? (method_is_fmm(o.method, g->M) ? BIE_FMM : BIE_DIRECT) : o.method;
   if (o.fmm_leaf == 0 && meth == BIE_FMM) {  // leaf sizes from the tuner (cached per class)
     BIE_TRY(autotune_leaf(g, kind, o.precision, nrhs, s));
   } else {

@@ -817,6 +817,108 @@ __global__ __launch_bounds__(256, 5) void k_near(
   }
 }
 
+// Float32 near field of the mixed-precision Laplace apply: k_near<false>'s neighbour lists,
+// chunks and summation pattern, with the staged records converted to float32 coordinates
+// relative to the chunk's first target (one float64 difference, rounded once, so a target and its
+// own record still give r = 0 exactly) and float32 pair terms; each lane adds its eight-record
+// partial sums into float64 accumulators. Coordinates relative to a point of the leaf keep the
+// float32 rounding of r at eps32 times the neighbourhood size rather than the geometry's.
+constexpr float kSelfFloor32 = 1e-20f;  // |r|^2 floor (self pair): s / floor stays finite
+constexpr float kNearPad32 = 1e18f;     // padding record coordinates: |r|^2 stays finite
+
+__device__ __forceinline__ void near_seg32(const float4 *buf, int n, int g, float2 z, double &gx,
+                                           double &gy) {
+  for (int k = 0; k < n; k += 32) {
+    float4 rec[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rec[u] = buf[k + 4 * u + g];
+    float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float dx = z.x - rec[u].x, dy = z.y - rec[u].y;
+      const float inv = __builtin_amdgcn_rcpf(fmaxf(fmaf(dx, dx, dy * dy), kSelfFloor32));
+      const float t = rec[u].z * inv;
+      sx = fmaf(dx, t, sx);
+      sy = fmaf(dy, t, sy);
+    }
+    gx += (double)sx;
+    gy += (double)sy;
+  }
+}
+
+// Stages n records src[0 .. n) at buf[at ..] relative to o, then padding up to a multiple of 32.
+__device__ __forceinline__ int near_stage32(const double4 *__restrict__ src, int n, float4 *buf,
+                                            int at, double2 o) {
+  const int np = (n + 31) & ~31;
+  for (int t = threadIdx.x; t < np; t += blockDim.x) {
+    float4 v = make_float4(kNearPad32, kNearPad32, 0.0f, 0.0f);
+    if (t < n) {
+      const double4 r = src[t];
+      v = make_float4((float)(r.x - o.x), (float)(r.y - o.y), (float)r.z, 0.0f);
+    }
+    buf[at + t] = v;
+  }
+  return np;
+}
+
+__global__ __launch_bounds__(256, 6) void k_near_f32(
+    int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
+    const double2 *__restrict__ nrm, const int *__restrict__ perm,
+    const int *__restrict__ run_ptr, const int2 *__restrict__ run,
+    const int *__restrict__ chunk_leaf, const int *__restrict__ chunk_start,
+    const double4 *__restrict__ S4, double *__restrict__ out) {
+  const int cb = xcd_item(blockIdx.x, gridDim.x);
+  const int leaf = chunk_leaf[cb], r = blockIdx.y;
+  const int j1 = leaf_start[leaf + 1];
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int t0 = chunk_start[cb] + 16 * (threadIdx.x >> 6);  // the wave's first target
+  const int j = t0 + (lane & 15);
+  const bool valid = j < j1, busy = t0 < j1;
+  const int jj = valid ? j : t0;
+  const double2 o = xs[chunk_start[cb]];  // origin of the chunk's float32 coordinates
+  const double2 zd = xs[min(jj, M - 1)], nv = nrm[min(jj, M - 1)];
+  const float2 z = make_float2((float)(zd.x - o.x), (float)(zd.y - o.y));
+  const double4 *src = S4 + (size_t)r * M;
+  __shared__ float4 buf[kNearCap];
+  double gx = 0.0, gy = 0.0;
+  const int e0 = run_ptr[leaf], e1 = run_ptr[leaf + 1];
+  int total = 0;
+  for (int e = e0; e < e1; ++e) total += run[e].y - run[e].x;
+  if (((total + 31) & ~31) <= kNearCap) {  // the runs back to back, one padding at the end
+    int at = 0;
+    for (int e = e0; e < e1; ++e) {
+      const int2 kr = run[e];
+      const int n = kr.y - kr.x;
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double4 v = src[kr.x + t];
+        buf[at + t] = make_float4((float)(v.x - o.x), (float)(v.y - o.y), (float)v.z, 0.0f);
+      }
+      at += n;
+    }
+    const int padded = (total + 31) & ~31;
+    for (int t = total + threadIdx.x; t < padded; t += blockDim.x)
+      buf[t] = make_float4(kNearPad32, kNearPad32, 0.0f, 0.0f);
+    __syncthreads();
+    if (busy) near_seg32(buf, padded, g, z, gx, gy);
+  } else {
+    for (int e = e0; e < e1; ++e) {
+      const int2 kr = run[e];
+      for (int base = kr.x; base < kr.y; base += kNearCap) {
+        __syncthreads();  // the previous block is no longer read
+        const int n = near_stage32(src + base, min(kNearCap, kr.y - base), buf, 0, o);
+        __syncthreads();
+        if (busy) near_seg32(buf, n, g, z, gx, gy);
+      }
+    }
+  }
+  gx += __shfl_xor(gx, 16, 64);
+  gy += __shfl_xor(gy, 16, 64);
+  gx += __shfl_xor(gx, 32, 64);
+  gy += __shfl_xor(gy, 32, 64);
+  if (!valid || g != 0) return;
+  out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+}
+
 // Downward pass and evaluation in one: the local expansion of a leaf is the sum over its
 // ancestors A (levels 2 to L, the leaf included) of A's M2L part re-expanded about the leaf, and
 // re-expanding a polynomial about another centre is exact (L2L has no truncation). So each target
@@ -1726,17 +1828,25 @@ void upward_pass(const FmmTree &t, int kind, int nsets, double ih_leaf, const cx
   m2m_passes<P, T>(t, nsets, Mexp, s);
 }
 
+constexpr int kNearAtF32 = 0;
+
 template <int P, class T, class Near>
 int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
                      const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
                      Near &&launch_near) {
   const int M = t.M;
-  upward_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);
-  // the near field (it depends only on the gather) is submitted after the multipole passes: it
-  // then runs beside the M2L, whose products are on the matrix cores, rather than slowing the
-  // M2M passes (running the leaf level's M2L beside the M2M passes on a second stream, with the
-  // near field submitted first, measured 153 us per apply against 135 us)
-  BIE_TRY(launch_near());
+  // Where the near field (it depends only on the gather) is submitted: float64 expansions after
+  // the multipole passes, so that it runs beside the M2L, whose products are on the matrix cores,
+  // rather than slowing the M2M passes (running the leaf level's M2L beside the M2M passes on a
+  // second stream, with the near field submitted first, measured 153 us per apply against
+  // 135 us); float32 expansions at kNearAtF32 (0 before the P2M, 1 before the M2M passes, 2
+  // after them), since their M2L is shorter than the near field.
+  constexpr int near_at = std::is_same<T, float>::value ? kNearAtF32 : 2;
+  if (near_at == 0) BIE_TRY(launch_near());
+  p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);
+  if (near_at == 1) BIE_TRY(launch_near());
+  m2m_passes<P, T>(t, nsets, Mexp, s);
+  if (near_at == 2) BIE_TRY(launch_near());
   if (t.ngroup > 0) {
     ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets);
     BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
@@ -2001,7 +2111,7 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   FmmTree &t = *tp;
   const int M = t.M;
   const int nsets = kind == 0 ? R : 3 * R;
-  // float expansions for the mixed-precision Laplace apply (the near field stays float64)
+  // float32 expansions and near field for the mixed-precision Laplace apply
   const bool f32 = precision == BIE_MIXED && kind == 0;
   const size_t csz = f32 ? sizeof(float2) : sizeof(double2);
   // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
@@ -2034,7 +2144,11 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
     BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
     {
       ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
-      if (kind == 0)
+      if (kind == 0 && f32)
+        hipLaunchKernelGGL(k_near_f32, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
+                           t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                           t.chunk_start, S4, partial);
+      else if (kind == 0)
         hipLaunchKernelGGL(k_near<false>, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
                            t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
                            t.chunk_start, S4, partial);

@@ -158,10 +158,12 @@ int make_work(SysSet &ss, int m, Work &wk, int extra_vectors, double **extra, hi
 
 // GMRES(m) on A x = f for every system. x holds the iterate on exit (x0 = 0 if x_is_zero).
 // With relaxed (and precision BIE_MIXED): float64 GMRES whose Arnoldi steps apply the float32
-// operator once every active system's estimated relative residual is below
-// tol / kF32ApplyError (the apply error a step may carry falls with the residual it reduces,
-// Simoncini & Szyld 2003); earlier steps and every cycle's true residual use float64.
-constexpr double kF32ApplyError = 1e-6;  // about the float32 apply's relative error
+// operator once every active system's estimated relative residual is below tol / eta, eta the
+// relative error of that apply (the apply error a step may carry grows as the residual it
+// reduces falls, Simoncini & Szyld 2003); earlier steps and every cycle's true residual use
+// float64. Per group of systems (ss.group_ptr), with the group's eta (ss.group_eta).
+constexpr double kF32ApplyError = 1e-6;  // eta where the set gives none
+
 
 int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
           const std::vector<double> &tol, int m, int max_iter, Work &wk, Stats &st,
@@ -192,6 +194,11 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     for (int q = 0; q < ngroups; ++q)
       for (int r = ss.group_ptr[q]; r < ss.group_ptr[q + 1]; ++r) group_of[r] = q;
   std::vector<char> gf32(ngroups, 0);
+  std::vector<double> geta(ngroups, kF32ApplyError);
+  for (int q = 0; q < ngroups; ++q)
+    if (!ss.group_eta.empty())
+      geta[q] = ngroups == 1 ? *std::max_element(ss.group_eta.begin(), ss.group_eta.end())
+                             : ss.group_eta[q];
   while (cycles < max_cycles) {
     ++cycles;
     if (first && x_is_zero) {
@@ -306,7 +313,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       int sp = precision;
       if (relaxed) {
         int nf = 0;
-        for (int q = 0; q < ngroups; ++q) nf += gf32[q] = gworst[q] * kF32ApplyError < 1.0;
+        for (int q = 0; q < ngroups; ++q) nf += gf32[q] = gworst[q] * geta[q] < 1.0;
         sp = nf == ngroups ? BIE_MIXED : nf == 0 ? BIE_FP64 : kPrecPerGroup;
         if (sp == kPrecPerGroup) ss.group_f32 = gf32;
       }
@@ -422,6 +429,17 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
 }
 
 }  // namespace
+
+// The BIE_MIXED apply's relative error (2-norm, random densities, against the float64 direct
+// apply) measured on the 1000-starfish and 200-ellipse geometries, rounded up: direct float32
+// far field 2.4e-8 .. 4.4e-8; FMM Laplace (float32 expansions and near field) 2.6e-7 .. 3.1e-7;
+// FMM Stokes (float64 expansions of about half the order) 1.4e-10 .. 2.0e-10. A value set too
+// large only delays the switch; one too small can cost a further restart cycle, never accuracy
+// (the solve stops on float64 true residuals).
+double mixed_apply_error(const bie_geom *g, int kind, int method) {
+  if (!method_is_fmm(method, g->M)) return 1e-7;
+  return (kind & 1) ? 1e-8 : 1e-6;
+}
 
 // One Arnoldi cycle (at most m steps, x0 = 0) on A d = r for every system, each system stopping
 // at its own relative tolerance; d receives the correction. Used by the serving loop.
@@ -589,6 +607,7 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
                   (void *)g->ws_scale.ptr);
     ss.graph_key = key;
   }
+  ss.group_eta.assign(1, mixed_apply_error(g, kind, method));
   std::vector<double> rel;
   if (!o.l2_scaling) {
     ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out,

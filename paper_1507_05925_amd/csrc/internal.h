@@ -108,6 +108,14 @@ struct SolverMem {
 };
 
 // A set of systems with one batched apply: out = A in (flat layout of seg).
+// BIE_AUTO: the FMM for geometries with more than this many nodes, else direct summation.
+constexpr long long kAutoFmmNodes = 32768;
+inline bool method_is_fmm(int method, long long M) {
+  return method == BIE_FMM || (method == BIE_AUTO && M > kAutoFmmNodes);
+}
+// Relative error (2-norm) that the relaxed mixed strategy assumes for a BIE_MIXED apply.
+double mixed_apply_error(const bie_geom *g, int kind, int method);
+
 // Apply precision value meaning "per group": group g's systems use float32 where
 // SysSet::group_f32[g] is set, float64 elsewhere.
 constexpr int kPrecPerGroup = -1;
@@ -126,6 +134,8 @@ struct SysSet {
   // the other groups.
   std::vector<int> group_ptr;
   std::vector<char> group_f32;  // per group, read by apply(kPrecPerGroup, ...)
+  // per group (or one value for all), the relative error of its BIE_MIXED apply (empty: 1e-6)
+  std::vector<double> group_eta;
   std::function<int(int precision, const double *in, double *out, hipStream_t s)> apply;
   // identity of the apply's arguments for graph capture (empty: the steps are never captured,
   // e.g. batches, whose applies depend on the active flags)

@@ -755,7 +755,7 @@ size_t apply_workspace_bytes(const bie_geom *g, int kind, int method, int nrhs) 
 int apply_operator(bie_geom *g, int kind, int precision, int method, int with_L, double alpha,
                    int nrhs, const double *mu, double *out, hipStream_t st) {
   if (kind == 2 || kind == 3) return dl_apply(g, kind - 2, with_L, alpha, nrhs, mu, out, st);
-  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
+  if (method == BIE_AUTO) method = method_is_fmm(method, g->M) ? BIE_FMM : BIE_DIRECT;
   if (nrhs < 1) {
     set_error("apply: nrhs >= 1 required");
     return BIE_EINVAL;
@@ -772,7 +772,7 @@ int apply_operator_ws(bie_geom *g, int kind, int precision, int method, int with
     set_error("precision must be BIE_FP64 or BIE_MIXED");
     return BIE_EINVAL;
   }
-  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
+  if (method == BIE_AUTO) method = method_is_fmm(method, g->M) ? BIE_FMM : BIE_DIRECT;
   if (method != BIE_DIRECT && method != BIE_FMM) {
     set_error("method must be BIE_DIRECT, BIE_FMM or BIE_AUTO");
     return BIE_EINVAL;
@@ -887,7 +887,7 @@ __global__ void k_velocity_fin(int N, int nrhs, int S, const double *__restrict_
 int eval_points(bie_geom *g, int kind, int nrhs, const double *dens, int npts, const double *pts,
                 bool rigid, double *res, hipStream_t st, int method) {
   if (nrhs <= 0 || npts <= 0) return BIE_OK;
-  if (method == BIE_AUTO) method = g->M > 32768 ? BIE_FMM : BIE_DIRECT;
+  if (method == BIE_AUTO) method = method_is_fmm(method, g->M) ? BIE_FMM : BIE_DIRECT;
   if (method == BIE_FMM) return fmm_eval_points(g, kind, nrhs, dens, npts, pts, rigid, res, st);
   // source splits: about 2048 workgroups in all, at most 32 splits, at least 2048 sources each
   const long long groups = (long long)((npts + kTJ - 1) / kTJ) * nrhs;

@@ -74,7 +74,7 @@ namespace bie {
 namespace {
 
 bool uses_fmm(const bie_opts &o, const bie_geom *g) {
-  return o.method == BIE_FMM || (o.method == BIE_AUTO && g->M > 32768);
+  return method_is_fmm(o.method, g->M);
 }
 
 // Device bytes of one request's solver state: its buffers (incident density, rhs, iterate,
