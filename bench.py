@@ -4,7 +4,9 @@ Setup (untimed, reported): the curve samples and charges are put in HBM, the geo
 quadrature data are built on the device (bie_geom_create), and one solve builds the FMM tree.
 One timed step = one whole solve on that resident geometry: incident charge and right-hand side,
 GMRES to a relative residual of 1e-10 with the operator apply (far field by the 2D FMM, float64
-self terms, diagonal and completion), potentials read off inside every conductor.
+self terms, diagonal and completion), potentials read off inside every conductor. By default the
+solves are mixed precision (float64 GMRES whose late steps apply the float32 operator), checked
+against the stored float64 oracle potentials; `fp64_path` times the same solves in plain float64.
 
 Reported value: pair interactions per second, counted as M^2 per operator apply (for the FMM this
 is the equivalent direct count, labelled as such in `metric`), over the timed steps.
@@ -13,7 +15,8 @@ events on the launch stream; `roofline_direct_p2p` is the direct float32 far-fie
 same workload.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--method fmm|direct]
-                  [--precision fp64|mixed] [--no-cpu-baseline]
+                  [--precision fp64|mixed] [--mixed-strategy relaxed|refine]
+                  [--no-cpu-baseline]
 
 Other workloads (not the default line):
   --workload serve   Poisson stream of elastance (60%) and mobility (40%) queries on
@@ -69,6 +72,8 @@ def parse():
     p.add_argument("--method", choices=["fmm", "direct"], default="fmm")
     p.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     p.add_argument("--mixed-strategy", choices=["relaxed", "refine"], default="relaxed")
+    p.add_argument("--fmm-leaf", type=int, default=0,
+                   help="FMM mean nodes per leaf (0: the library's autotuner picks it)")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -80,16 +85,24 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(curves, target_seconds):
-    """The float64 CPU oracle's matrix-free apply (plain C loops, OpenMP over targets) on a
-    bounded sample of target rows of the same workload, scaled to pairs/s."""
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo, as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_apply_rate(geo, mu, target_seconds):
+    """Pairs/s of the float64 oracle's matrix-free apply on a strided sample of target rows
+    sized to take about target_seconds; returns (rate, rows, seconds)."""
     import numpy as np
 
     from oracle import matfree as mf
-    from oracle import nystrom as ny
 
-    geo = ny.geometry_of(curves)
-    mu = np.random.default_rng(0).standard_normal(geo["M"])
     stride = 997
     while True:
         rows = np.arange(0, geo["M"], stride, dtype=np.int32)
@@ -99,12 +112,55 @@ def cpu_baseline(curves, target_seconds):
         if dt >= 0.5 * target_seconds or stride == 1:
             break
         stride = max(1, int(stride * dt / target_seconds))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    pairs = len(rows) * geo["M"]
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"float64 oracle apply of (1/2 I + K + L) (direct sum, no FMM): {len(rows)} "
+    return len(rows) * geo["M"] / dt, len(rows), dt
+
+
+def cpu_baseline(curves, target_seconds):
+    """The float64 CPU oracle's matrix-free apply (plain C loops, OpenMP over targets) on a
+    bounded sample of target rows of the same workload, scaled to pairs/s, with all host threads
+    and with one; and the dense oracle's solve (Nystrom matrix, LU) of the small 4-ellipse case
+    next to the GPU solve of the same case."""
+    import numpy as np
+
+    from oracle import matfree as mf
+    from oracle import nystrom as ny
+    from paper_1507_05925_amd import bie2d
+    from paper_1507_05925_amd import workloads as wl
+
+    geo = ny.geometry_of(curves)
+    mu = np.random.default_rng(0).standard_normal(geo["M"])
+    threads = mf.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    rate, nrows, dt = oracle_apply_rate(geo, mu, target_seconds)
+    mf.set_threads(1)
+    rate1, nrows1, dt1 = oracle_apply_rate(geo, mu, target_seconds / 4)
+    mf.set_threads(threads)
+    # the 4-ellipse elastance case (512 unknowns): dense oracle solve vs the GPU float64 solve
+    c1, q1 = wl.elastance_small()
+    g1 = ny.geometry_of(c1)
+    t = time.perf_counter()
+    ref = ny.elastance_solve(g1, q1)
+    t_lu = time.perf_counter() - t
+    G = bie2d.Geometry.from_curves(c1)
+    qd = __import__("torch").as_tensor(q1[None], device="cuda")
+    o = bie2d.default_opts(precision=bie2d.BIE_FP64, tol=1e-12)
+    bie2d.bie_elastance_solve(G, qd, o)
+    t = time.perf_counter()
+    phi, _ = bie2d.bie_elastance_solve(G, qd, o)
+    __import__("torch").cuda.synchronize()
+    t_gpu = time.perf_counter() - t
+    G.close()
+    err = float(np.abs(phi.cpu().numpy()[0] - ref["phi"]).max() / np.abs(ref["phi"]).max())
+    pairs = nrows * geo["M"]
+    return {"value": rate, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"float64 oracle apply of (1/2 I + K + L) (direct sum, no FMM): {nrows} "
                       f"of {geo['M']} target rows x all {geo['M']} sources = {pairs:.3e} pairs in "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall on {threads} threads",
+            "one_core": {"value": rate1, "unit": "pair-interactions/s",
+                         "sample": f"{nrows1} rows x {geo['M']} sources in {dt1:.1f} s, 1 thread"},
+            "small_case_solve": {"workload": "elastance, 4 ellipses x 128 nodes (512 unknowns)",
+                                 "oracle_dense_lu_s": t_lu, "gpu_fp64_solve_s": t_gpu,
+                                 "gpu_rel_err_vs_oracle": err}}
 
 
 def roofline(prof, kc, units_flops, dtype, bound="alu", kernel=None):
@@ -328,8 +384,8 @@ def nanocomposite_bench(a):
 
 def mobility_bench(a):
     """Mobility of 200 rigid ellipses x 512 nodes (204,800 unknowns), FMM, GMRES tol 1e-10, in
-    float64 and in the mixed mode (for Stokes an FMM of about half the order, still in float64,
-    inside float64 refinement): geometry resident, warm-up solves, then `steps` timed solves per
+    float64 and in the mixed mode (for Stokes the late GMRES steps apply an FMM of about half the
+    order, still in float64): geometry resident, warm-up solves, then `steps` timed solves per
     mode; (v, omega) compared with the stored float64 oracle solution."""
     import numpy as np
     import torch
@@ -346,7 +402,8 @@ def mobility_bench(a):
     runs = {}
     for name, prec in (("fp64", bie2d.BIE_FP64), ("mixed", bie2d.BIE_MIXED)):
         o = bie2d.default_opts(precision=prec, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
-                               max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy])
+                               max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
+                               fmm_leaf=a.fmm_leaf)
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_mobility_solve(g, ft, o)
         torch.cuda.synchronize()
@@ -373,7 +430,7 @@ def mobility_bench(a):
     # the float64 order-40 kernels timed with HIP events over one more solve, each class in a
     # solve of its own: the M2L (three charge sets per right-hand side) and the Stokes near field
     o = bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
-                           max_iter=2000)
+                           max_iter=2000, fmm_leaf=a.fmm_leaf)
     rls = {}
     for key, kc, flops, bound, kern in (
             ("roofline_m2l", bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(40), "mfma", "k_m2l<40>"),
@@ -388,6 +445,8 @@ def mobility_bench(a):
         rls[key] = rl
         bie2d.bie_profile_enable(False)
     bie2d.bie_profile_select(None)
+    leaf = a.fmm_leaf if a.fmm_leaf > 0 else \
+        "autotuned (float64 %d, mixed %d)" % bie2d.bie_autotune(g, 1, bie2d.BIE_MIXED)
     g.close()
     best = max(runs, key=lambda k: runs[k]["solves_per_s"])
     print(json.dumps({
@@ -400,7 +459,8 @@ def mobility_bench(a):
         "data": "synthetic (seeded ellipse ensemble, F ~ N(0,1)^2 with zero total, T ~ N(0,1))",
         "config": {"workload": "mobility, 200 ellipses (aspect 1..3, gaps >= 0.2) x 512 nodes "
                                "(204,800 unknowns), FMM, GMRES tol %g" % a.tol,
-                   "fastest": best},
+                   "fastest": best,
+                   "fmm_leaf": leaf},
         "runs": runs, **rls}))
 
 
@@ -528,10 +588,11 @@ def main():
     curve_d = torch.from_numpy(np.ascontiguousarray(c)).to(dev)
     q_d = torch.as_tensor(q[None], device=dev)
     meth = bie2d.BIE_FMM if a.method == "fmm" else bie2d.BIE_DIRECT
-    precision = a.precision or ("fp64" if a.method == "fmm" else "mixed")
+    precision = a.precision or "mixed"
     prec = bie2d.BIE_MIXED if precision == "mixed" else bie2d.BIE_FP64
     opts = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100, max_iter=2000,
-                              mixed_strategy=MIXED_STRATEGY[a.mixed_strategy])
+                              mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
+                              fmm_leaf=a.fmm_leaf)
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -546,6 +607,7 @@ def main():
     torch.cuda.synchronize()
 
     order = (opts.fmm_order + 7) // 8 * 8
+    order32 = min(64, (max(8, (opts.fmm_order * 11 + 19) // 20) + 7) // 8 * 8)  # mixed applies
     classes = {  # class, algorithmic flops per unit, dtype, bound, kernel name in the profiles
         "k_lap_far_f32": (bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32", "alu",
                           "k_lap_far_f32<1>"),
@@ -553,6 +615,9 @@ def main():
                           "k_lap_far_f64<1>"),
         "k_m2l": (bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(order), "f64", "mfma", f"k_m2l<{order}>"),
         "k_near": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near<false>"),
+        "k_m2l_f32": (bie2d.BIE_K_FMM_M2L_F32, m2l_flops_per_entry(order32), "f32", "mfma",
+                      f"k_m2l_fac_f32<{order32}>"),
+        "k_near_f32": (bie2d.BIE_K_FMM_NEAR_F32, FLOPS_PER_PAIR, "f32", "alu", "k_near_f32"),
         "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64", "alu", "k_lap_epilogue"),
     }
     # one untimed solve with every class recorded picks the dominant kernel class; the timed
@@ -586,15 +651,79 @@ def main():
     rl["sampled_every"] = PROFILE_EVERY
     bie2d.bie_profile_enable(False)
     bie2d.bie_profile_sample(1)
-    # the matrix-core kernel (M2L) on its own, from one more solve that times only that class
-    cm = classes["k_m2l"]
-    bie2d.bie_profile_select([cm[0]])
-    bie2d.bie_profile_enable(True)
-    bie2d.bie_elastance_solve(g, q_d, opts)
-    rl_m2l = roofline(bie2d.bie_profile_read(cm[0]), cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
-    rl_m2l["kernel"] = cm[4]
-    bie2d.bie_profile_enable(False)
+    # the matrix-core kernels (M2L, float64 and, in mixed solves, float32) on their own, from one
+    # more solve that times only those classes
+    rl_m2ls = {}
+    for name in ("k_m2l", "k_m2l_f32"):
+        cm = classes[name]
+        bie2d.bie_profile_select([cm[0]])
+        bie2d.bie_profile_enable(True)
+        bie2d.bie_elastance_solve(g, q_d, opts)
+        pr = bie2d.bie_profile_read(cm[0])
+        bie2d.bie_profile_enable(False)
+        if pr["launches"] > 0:
+            rl_m2ls[name] = roofline(pr, cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
+            rl_m2ls[name]["kernel"] = cm[4]
     bie2d.bie_profile_select(None)
+
+    # where a solve's time goes: the FMM applies of each precision timed on their own (events on
+    # the stream), times the counts of the timed solve, and the rest (Arnoldi, read-off, host)
+    breakdown = None
+    if meth == bie2d.BIE_FMM:
+        mu_t = torch.randn(1, g.M, dtype=torch.float64, device=dev)
+        ms_apply = {}
+        for name, pr in (("fp64", bie2d.BIE_FP64), ("fp32", bie2d.BIE_MIXED)):
+            bie2d.bie_laplace_apply(g, mu_t, pr, bie2d.BIE_FMM)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                bie2d.bie_laplace_apply(g, mu_t, pr, bie2d.BIE_FMM)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_apply[name] = e0.elapsed_time(e1) / 20
+        ms_solve = 1e3 * elapsed / a.steps
+        n64, n32 = info["applies_fp64"], info["applies_fp32"]
+
+        def apply_flops(near, m2l, order_):
+            u = lambda k: profs[k]["pairs"] / max(profs[k]["launches"], 1)  # units per launch
+            return u(near) * FLOPS_PER_PAIR + u(m2l) * m2l_flops_per_entry(order_)
+        fl64 = apply_flops("k_near", "k_m2l", order) if profs["k_near"]["launches"] else None
+        fl32 = apply_flops("k_near_f32", "k_m2l_f32", order32) if profs["k_near_f32"]["launches"] else None
+        breakdown = {
+            "ms_per_solve": ms_solve,
+            "applies_fp64": n64, "apply_fp64_ms": ms_apply["fp64"],
+            "applies_fp32": n32, "apply_fp32_ms": ms_apply["fp32"],
+            "applies_ms": n64 * ms_apply["fp64"] + n32 * ms_apply["fp32"],
+            "arnoldi_readoff_host_ms": ms_solve - n64 * ms_apply["fp64"] - n32 * ms_apply["fp32"],
+            "whole_apply_near_plus_m2l_flops": {
+                "note": "algorithmic near-field and M2L flops of one apply over the whole apply's "
+                        "time (P2M, M2M, evaluation and epilogue flops not counted)",
+                **({"fp64_tflops": fl64 / (ms_apply["fp64"] * 1e-3) / 1e12,
+                    "fp64_frac_of_78.6": fl64 / (ms_apply["fp64"] * 1e-3) / 1e12 / PEAK["f64"]}
+                   if fl64 else {}),
+                **({"fp32_tflops": fl32 / (ms_apply["fp32"] * 1e-3) / 1e12,
+                    "fp32_frac_of_157.3": fl32 / (ms_apply["fp32"] * 1e-3) / 1e12 / PEAK["f32"]}
+                   if fl32 else {}),
+            },
+        }
+
+    # the plain float64 GPU path on the same solves, for comparison with the mixed solves
+    fp64 = None
+    if prec == bie2d.BIE_MIXED:
+        o64 = bie2d.default_opts(precision=bie2d.BIE_FP64, method=meth, tol=a.tol, restart=100,
+                                 max_iter=2000, fmm_leaf=a.fmm_leaf)
+        for _ in range(max(a.warmup, 1)):
+            bie2d.bie_elastance_solve(g, q_d, o64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        for _ in range(a.steps):
+            phi64_, info64_ = bie2d.bie_elastance_solve(g, q_d, o64)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t64
+        fp64 = {"ms_per_solve": 1e3 * el64 / a.steps, "solves_per_s": a.steps / el64,
+                "gmres": {k: info64_[k] for k in ("iters", "applies_fp64", "rel_residual")},
+                "mixed_speedup": el64 / elapsed}
 
     # the same solves replaying captured HIP graphs of every Arnoldi step (the timed solves
     # above launch each step's kernels on the stream, the library default)
@@ -633,6 +762,9 @@ def main():
     if os.path.exists(gold):
         ref = np.asarray(json.load(open(gold))["phi"])
         acc["rel_err_vs_fp64_oracle"] = float(np.abs(phi.cpu().numpy()[0] - ref).max() / np.abs(ref).max())
+        if fp64 is not None:
+            fp64["rel_err_vs_fp64_oracle"] = float(
+                np.abs(phi64_.cpu().numpy()[0] - ref).max() / np.abs(ref).max())
     phi64, info64 = bie2d.bie_elastance_solve(
         g, q_d, bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_DIRECT, tol=1e-12,
                                    restart=100))
@@ -654,6 +786,8 @@ def main():
         "config": {"workload": "elastance, 1000 starfish r0(1+0.3cos5t) x 256 nodes (M=256000), "
                                "q~N(0,1), GMRES tol 1e-10",
                    "method": a.method, "precision": precision, "fmm_order": opts.fmm_order,
+                   "fmm_leaf": a.fmm_leaf if a.fmm_leaf > 0 else
+                   "autotuned (float64 %d, mixed %d)" % bie2d.bie_autotune(g, 0, prec),
                    **({"mixed_strategy": a.mixed_strategy} if prec == bie2d.BIE_MIXED else {}),
                    "nodes": curves.M, "bodies": curves.nbodies},
         "solves_per_s": a.steps / elapsed,
@@ -664,8 +798,11 @@ def main():
                                        "rel_residual")},
         "accuracy": acc,
         "roofline": rl,
-        "roofline_m2l": rl_m2l,
+        **({"roofline_m2l": rl_m2ls["k_m2l"]} if "k_m2l" in rl_m2ls else {}),
+        **({"roofline_m2l_f32": rl_m2ls["k_m2l_f32"]} if "k_m2l_f32" in rl_m2ls else {}),
         "roofline_direct_p2p": rl_direct,
+        **({"fp64_path": fp64} if fp64 is not None else {}),
+        **({"solve_breakdown": breakdown} if breakdown is not None else {}),
         "kernel_ms_per_solve_untimed": {k: v["ms_total"] for k, v in profs.items()},
         "fmm_ms_per_apply": fmm_total["ms_total"] / max(fmm_total["launches"], 1),
         "graphs": graphs,

@@ -95,8 +95,8 @@ typedef struct {
   int max_refine;   /* BIE_MIXED: cap on outer refinement steps                       */
   int fmm_order;    /* BIE_FMM: expansion order p (terms per expansion)               */
   int fmm_leaf;     /* BIE_FMM: mean nodes per leaf box the tree depth aims at; 0 = tuned:
-                       the solves take it from the autotuner (bie_autotune) for the
-                       geometry's shape class, per precision                            */
+                       the solves and batches take it from the autotuner (bie_autotune)
+                       for the geometry's shape class, per precision; the server uses 64 */
   double viscosity; /* mobility / resistance: fluid viscosity > 0 (mobility problem
                        statement: viscosity 1 there). Velocities scale as 1/viscosity,
                        forces and torques as viscosity; densities do not change.        */
@@ -415,7 +415,9 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 #define BIE_K_FMM_M2L 6         /* FMM multipole-to-local; units: interaction-list entries (box pairs) per set */
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
-#define BIE_K_COUNT 9
+#define BIE_K_FMM_M2L_F32 9     /* float32 M2L of the mixed Laplace apply; units as BIE_K_FMM_M2L */
+#define BIE_K_FMM_NEAR_F32 10   /* float32 near field of the mixed Laplace apply; units: pairs  */
+#define BIE_K_COUNT 11
 /* ---- autotuning of the FMM leaf size -------------------------------------------------------
  * The leaf population trades near-field pair work against expansion work; the best value
  * depends on the kernel, the precision and the node density. bie_autotune times the operator

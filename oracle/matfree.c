@@ -16,7 +16,14 @@
  * for Stokes); otherwise all M targets.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
+
+/* Threads of the loops below (n >= 1); returns the number in use afterwards. Timing only. */
+int oracle_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 
 #define PI 3.14159265358979323846
 

@@ -34,8 +34,7 @@ def build(force=True):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
+        build(force=False)  # compiles when missing or older than the source
         _lib = ctypes.CDLL(_LIB)
     return _lib
 
@@ -63,6 +62,11 @@ class _Keep:
         a = np.ascontiguousarray(a, dtype=np.int32)
         self.refs.append(a)
         return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (for timing); returns the number in use."""
+    return int(lib().oracle_set_threads(ctypes.c_int(n)))
 
 
 def laplace_apply(geo, mu, with_L=True, rows=None):

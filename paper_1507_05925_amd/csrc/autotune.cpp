@@ -143,4 +143,11 @@ int tune_cache_stats(bie_tune_cache *c, long long *tunings, long long *hits) {
   return BIE_OK;
 }
 
+int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s) {
+  if (o.fmm_leaf == 0 && tune) return autotune_leaf(g, kind, o.precision, nrhs, s);
+  g->fmm_leaf = o.fmm_leaf > 0 ? o.fmm_leaf : 64;
+  g->fmm_leaf_mixed = 0;
+  return BIE_OK;
+}
+
 }  // namespace bie

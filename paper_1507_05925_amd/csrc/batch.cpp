@@ -98,7 +98,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
     in_off[i + 1] = in_off[i] + (long long)cols * (it.in ? 0 : it.nrhs);
     pairs += (long long)it.nrhs * it.g->M * (long long)it.g->M;
     it.g->fmm_order = o.fmm_order;
-    it.g->fmm_leaf = o.fmm_leaf;
+    // leaf sizes (fmm_leaf 0: the tuner's, for items the FMM applies)
+    BIE_TRY(resolve_leaf(it.g, it.kind, o, it.nrhs, method_is_fmm(o.method, it.g->M), s));
   }
   const long long Ntot = item_off[nitems];
   BIE_TRY(b->seg.build(lens, s, &starts));
@@ -131,8 +132,7 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   for (int i = 0; i < nitems; ++i) {
     bie_geom *g = items[i].g;
     mitems[i] = {g, items[i].kind, items[i].nrhs, item_off[i],
-                 method_is_fmm(o.method, g->M), o.fmm_order,
-                 o.fmm_leaf};
+                 method_is_fmm(o.method, g->M), o.fmm_order, g->fmm_leaf};
     first_sys[i + 1] = first_sys[i] + items[i].nrhs;
   }
   ss.group_ptr = first_sys;  // items: a relaxed mixed solve picks precisions per item

@@ -642,12 +642,8 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
   g->fmm_order = effective_order(o);
   const int meth = o.method == BIE_AUTO ? (method_is_fmm(o.method, g->M) ? BIE_FMM : BIE_DIRECT) : o.method;
-  if (o.fmm_leaf == 0 && meth == BIE_FMM) {  // leaf sizes from the tuner (cached per class)
-    BIE_TRY(autotune_leaf(g, kind, o.precision, nrhs, s));
-  } else {
-    g->fmm_leaf = o.fmm_leaf > 0 ? o.fmm_leaf : 64;
-    g->fmm_leaf_mixed = 0;
-  }
+  // leaf sizes (fmm_leaf 0: from the tuner, cached per shape class)
+  BIE_TRY(resolve_leaf(g, kind, o, nrhs, meth == BIE_FMM, s));
   // ws_out: dens [nrhs][len], f [nrhs][len], mu [nrhs][len]
   BIE_TRY(g->ws_out.reserve(3 * len * nrhs * 8));
   double *dens = g->ws_out.as<double>();

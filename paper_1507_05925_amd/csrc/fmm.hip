@@ -1848,7 +1848,8 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   m2m_passes<P, T>(t, nsets, Mexp, s);
   if (near_at == 2) BIE_TRY(launch_near());
   if (t.ngroup > 0) {
-    ProfScope pm(BIE_K_FMM_M2L, s, t.m2l_entries * nsets);
+    ProfScope pm(std::is_same<T, float>::value ? BIE_K_FMM_M2L_F32 : BIE_K_FMM_M2L, s,
+                 t.m2l_entries * nsets);
     BIE_TRY(launch_m2l<P>(t, 0, t.ngroup, nsets, Mexp, Lexp, s));
   }
   BIE_HIP_CHECK(hipStreamWaitEvent(s, plan.join, 0));
@@ -2143,7 +2144,8 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   auto launch_near = [&]() -> int {
     BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
     {
-      ProfScope pe(BIE_K_FMM_EVAL, plan.side, (t.near_pairs - M) * R);
+      ProfScope pe(kind == 0 && f32 ? BIE_K_FMM_NEAR_F32 : BIE_K_FMM_EVAL, plan.side,
+                   (t.near_pairs - M) * R);
       if (kind == 0 && f32)
         hipLaunchKernelGGL(k_near_f32, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
                            t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,

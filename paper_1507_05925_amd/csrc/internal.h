@@ -296,6 +296,9 @@ void fmm_drop_tree(bie_geom *g, int precision, int order, int leaf);
 // sides: from the cache of g's context (or the process cache) for g's shape class, else by
 // timing applies on g over the candidate leaf sizes and storing the fastest.
 int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s);
+// Sets g's FMM leaf sizes for a solve with opts o: o.fmm_leaf > 0 for both precisions; 0 = the
+// autotuner's (tune true) or 64 (tune false: callers that must not pause to time applies).
+int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s);
 int fmm_current_order();
 
 

@@ -108,7 +108,8 @@ int prepare(Request &r, const bie_opts &o, hipStream_t s) {
   r.x = r.f + (size_t)r.nrhs * r.n;
   r.res = r.x + (size_t)r.nrhs * r.n;
   r.g->fmm_order = o.fmm_order;
-  r.g->fmm_leaf = o.fmm_leaf;
+  // fmm_leaf 0 serves with 64 nodes per leaf: timing leaf sizes would pause the other requests
+  BIE_TRY(resolve_leaf(r.g, r.kind, o, r.nrhs, false, s));
   // stage the input in the result buffer, then incident density and rhs f = -(1/2 I + K) inc
   BIE_HIP_CHECK(hipMemcpyAsync(r.res, r.in.data(), r.in.size() * sizeof(double),
                                hipMemcpyHostToDevice, s));
@@ -152,7 +153,7 @@ Layout layout(const std::vector<std::shared_ptr<Request>> &reqs, const bie_opts 
     if (new_group) {
       cur = align8(cur);
       L.first.push_back(i);
-      L.items.push_back({r.g, r.kind, 0, cur, uses_fmm(o, r.g), o.fmm_order, o.fmm_leaf});
+      L.items.push_back({r.g, r.kind, 0, cur, uses_fmm(o, r.g), o.fmm_order, r.g->fmm_leaf});
     }
     L.off[i] = cur;
     L.items.back().nrhs += r.nrhs;

@@ -41,9 +41,9 @@ def items():
     return _CACHE["items"]
 
 
-def opts(precision, method=bie2d.BIE_AUTO):
+def opts(precision, method=bie2d.BIE_AUTO, leaf=64):
     return bie2d.default_opts(precision=precision, method=method, tol=1e-12, restart=150,
-                              max_iter=3000)
+                              max_iter=3000, fmm_leaf=leaf)
 
 
 def check(outs, gold, tol, what):
@@ -59,13 +59,20 @@ def test_items_cross_the_threshold():
     assert its[2][1].M <= 32768 and its[3][1].M <= 32768
 
 
+@pytest.mark.parametrize("leaf", [64, 0])
 @pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
-def test_batch_fmm_items_vs_oracle(precision):
+def test_batch_fmm_items_vs_oracle(precision, leaf):
+    """leaf 0: the FMM items take their leaf sizes from the autotuner (a tree built for a leaf
+    size of 0 would have the minimum depth and turn the far field into near-field work)."""
     b = bie2d.Batch()
     req = [(g, k, dev(inp)) for k, g, inp in items()]
-    outs, info, rel = bie2d.bie_batch_solve(b, req, opts(precision))
+    outs, info, rel = bie2d.bie_batch_solve(b, req, opts(precision, leaf=leaf))
     check([o.cpu().numpy() for o in outs], golden(), TOL[precision], "batch")
     assert (rel <= 1e-12).all(), rel
+    if leaf == 0:
+        for k, g, _ in items()[:2]:  # the FMM items: the tuner's sizes, among those it times
+            lf64, lfmx = bie2d.bie_autotune(g, k, precision)
+            assert lf64 in (24, 32, 48, 64, 96, 128) and lfmx in (24, 32, 48, 64, 96, 128)
 
 
 def test_one_batch_direct_then_auto_then_direct():
@@ -79,9 +86,10 @@ def test_one_batch_direct_then_auto_then_direct():
         check([o.cpu().numpy() for o in outs], golden(), 1e-10, method)
 
 
-@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
-def test_server_fmm_items_vs_oracle(precision):
-    srv = bie2d.Server(opts(precision), max_cycles=400)
+@pytest.mark.parametrize("precision,leaf", [(bie2d.BIE_FP64, 64), (bie2d.BIE_MIXED, 64),
+                                          (bie2d.BIE_MIXED, 0)])
+def test_server_fmm_items_vs_oracle(precision, leaf):
+    srv = bie2d.Server(opts(precision, leaf=leaf), max_cycles=400)
     tickets = []
     for k, g, inp in items():
         tickets.append([srv.submit(g, k, v) for v in inp])
