@@ -180,28 +180,66 @@ __global__ __launch_bounds__(kBlock) void k_scale_to(const int *__restrict__ csy
 // = Z / nu - sum_{k<=j} c_k V_k with c_k = (H s)_k / nu + g'_k.
 
 // partial rows over chunk c: 2l = V_l . U and 2l + 1 = V_l . Z (l < nv); 2 nv = U . U and
-// 2 nv + 1 = U . Z. Z NULL: the odd rows are zero. Grid (C, nv + 1).
+// 2 nv + 1 = U . Z. Z NULL: the odd rows are zero. Grid (C, ceil((nv + 1) / kDotsVecs)): a
+// workgroup holds its chunk of U and Z in registers (entries i0 + t + 256 k, k < kSub) and takes
+// kDotsVecs of the vectors, so U and Z are read once per kDotsVecs vectors instead of once per
+// vector. Each row's sum has the order of a one-vector reduction: per thread in entry order, the
+// wave's shuffle tree, then the four waves as (w0 + w1) + (w2 + w3).
+constexpr int kDotsVecs = 8;
+
 __global__ __launch_bounds__(kBlock) void k_dots_uz(int C, const long long *__restrict__ c0,
                                                    const long long *__restrict__ c1, int nv,
                                                    const double *__restrict__ V, long long vstride,
                                                    const double *__restrict__ U,
                                                    const double *__restrict__ Z,
                                                    double *__restrict__ partial) {
-  __shared__ double sh[4];
-  const int c = blockIdx.x, l = blockIdx.y;
+  __shared__ double sh[4][2 * kDotsVecs];
+  const int c = blockIdx.x, l0 = blockIdx.y * kDotsVecs;
+  const int nl = min(kDotsVecs, nv + 1 - l0);
   const long long i0 = c0[c], i1 = c1[c];
-  const double *a = l < nv ? V + l * vstride : U;
-  double su = 0.0, sz = 0.0;
-  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    const double x = a[i];
-    su = fma(x, U[i], su);
-    if (Z) sz = fma(x, Z[i], sz);
+  double u[kSub], z[kSub];
+#pragma unroll
+  for (int k = 0; k < kSub; ++k) {
+    const long long i = i0 + threadIdx.x + (long long)k * kBlock;
+    u[k] = i < i1 ? U[i] : 0.0;
+    z[k] = (Z && i < i1) ? Z[i] : 0.0;
   }
-  su = block_sum(su, sh);
-  sz = block_sum(sz, sh);
-  if (threadIdx.x == 0) {
-    partial[(long long)(2 * l) * C + c] = su;
-    partial[(long long)(2 * l + 1) * C + c] = sz;
+  double su[kDotsVecs], sz[kDotsVecs];
+#pragma unroll
+  for (int q = 0; q < kDotsVecs; ++q) {
+    su[q] = sz[q] = 0.0;
+    if (q < nl) {
+      const int l = l0 + q;
+      const double *a = l < nv ? V + l * vstride : U;
+#pragma unroll
+      for (int k = 0; k < kSub; ++k) {
+        const long long i = i0 + threadIdx.x + (long long)k * kBlock;
+        if (i < i1) {
+          const double x = a[i];
+          su[q] = fma(x, u[k], su[q]);
+          sz[q] = fma(x, z[k], sz[q]);
+        }
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kDotsVecs; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      su[q] += __shfl_down(su[q], off, 64);
+      sz[q] += __shfl_down(sz[q], off, 64);
+    }
+    if (lane == 0) {
+      sh[wid][2 * q] = su[q];
+      sh[wid][2 * q + 1] = sz[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nl) {
+    const int x = threadIdx.x;
+    const double t = (sh[0][x] + sh[1][x]) + (sh[2][x] + sh[3][x]);
+    partial[(long long)(2 * l0 + x) * C + c] = t;
   }
 }
 
@@ -266,9 +304,18 @@ __global__ __launch_bounds__(kBlock) void k_dcgs_small(
   if (finalize) return;
   __syncthreads();  // column j - 1 of H is written (and G read)
   // (H s)_k = sum_{i < j} H[k][i] s_i, k = 0..j (H[k][i] = 0 for k > i + 1)
+  // (eight loads in flight per step; the sum keeps the order of i)
   for (int k = threadIdx.x; k <= j; k += kBlock) {
     double a = 0.0;
-    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) a = fma(H[(long long)i * ldh + k], sv[i], a);
+    int i = k > 0 ? k - 1 : 0;
+    for (; i + 8 <= j; i += 8) {
+      double h[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) h[e] = H[(long long)(i + e) * ldh + k];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a = fma(h[e], sv[i + e], a);
+    }
+    for (; i < j; ++i) a = fma(H[(long long)i * ldh + k], sv[i], a);
     hv[k] = a;
   }
   __syncthreads();
@@ -378,8 +425,8 @@ int seg_combination_column(const Segments &sg, int nvec, const double *V, long l
 
 int dcgs_dots(const Segments &sg, int nv, const double *V, long long vstride, const double *U,
               const double *Z, double *raw, long long rstride, double *scratch, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_uz, dim3(sg.C, nv + 1), dim3(kBlock), 0, s, sg.C, sg.c0, sg.c1, nv, V,
-                     vstride, U, Z, scratch);
+  hipLaunchKernelGGL(k_dots_uz, dim3(sg.C, (nv + kDotsVecs) / kDotsVecs), dim3(kBlock), 0, s,
+                     sg.C, sg.c0, sg.c1, nv, V, vstride, U, Z, scratch);
   hipLaunchKernelGGL(k_dots_stage2, dim3(2 * nv + 2, sg.S), dim3(64), 0, s, sg.C, sg.sys_chunk,
                      scratch, raw, rstride, 0);
   BIE_HIP_CHECK(hipGetLastError());

@@ -975,17 +975,46 @@ __device__ __forceinline__ int chunk_leaves(const int *__restrict__ leaf_start,
   return nslot;
 }
 
+// The apply's last terms, added by the Laplace evaluation when out is set (see FmmFinish):
+// out = alpha (1/2 mu - s kappa / (4 pi) [+ charge of the node's body] + near + far), in the
+// order of the separate epilogue, so that both give the same bits.
+struct L2pFinish {
+  const double *mu, *s64, *kappa, *charge;  // charge [R][N]: sum of s over each body
+  const int *body_of;
+  double *out;
+  double alpha;
+  int N, with_L;
+};
+
+// Per body b and rhs r: charge[r][b] = sum of s over the body's nodes (the epilogue's order).
+__global__ __launch_bounds__(256) void k_body_sums(int M, int N, const int *__restrict__ body_ptr,
+                                                   const double *__restrict__ s64,
+                                                   double *__restrict__ charge) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x, r = blockIdx.y;
+  const int k0 = body_ptr[b], k1 = body_ptr[b + 1];
+  const double *sr = s64 + (size_t)r * M;
+  double part = 0.0;
+  for (int k = k0 + threadIdx.x; k < k1; k += 256) part += sr[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) charge[(size_t)r * N + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 // Both evaluation kernels take their chunks in XCD-contiguous order (xcd_item): sibling leaves,
 // which stage the same ancestors, then share one XCD's L2.
-// L2P, Laplace: adds -(1/2pi) Re(nu F(z)). Grid (evaluation chunks, R); dynamic LDS:
-// ev_maxslot P coefficients.
+// L2P, Laplace: adds -(1/2pi) Re(nu F(z)) to the near-field sums in out, or (fin.out set) writes
+// the finished apply. Grid (evaluation chunks, R); dynamic LDS: ev_maxslot P coefficients.
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_l2p_laplace(
     int M, int nbox, int L, double ih_leaf, const int *__restrict__ leaf_start,
     const int *__restrict__ leaf_anc, const double2 *__restrict__ center,
     const double2 *__restrict__ xs, const double2 *__restrict__ nrm, const int *__restrict__ perm,
     const int *__restrict__ ev_start, const int *__restrict__ ev_leaf,
-    const cx<T> *__restrict__ Lexp, double *__restrict__ out) {
+    const cx<T> *__restrict__ Lexp, double *__restrict__ out, const L2pFinish fin) {
   __builtin_amdgcn_s_setprio(kChainPrio);
   extern __shared__ char l2p_lds[];
   cx<T> *cf = reinterpret_cast<cx<T> *>(l2p_lds);
@@ -1013,8 +1042,17 @@ __global__ __launch_bounds__(64) void k_l2p_laplace(
     off += a1[i] - a0[i] + 1;
     ih *= 0.5;
   }
-  double *o = out + (size_t)r * M + perm[j];
-  *o -= (nv.x * (double)F.x - nv.y * (double)F.y) / (2.0 * kPi);  // Re(nu F)
+  const int i = perm[j];
+  const size_t ri = (size_t)r * M + i;
+  const double part = out[ri] - (nv.x * (double)F.x - nv.y * (double)F.y) / (2.0 * kPi);  // Re(nu F)
+  if (fin.out) {
+    double v = 0.5 * fin.mu[ri] - fin.s64[ri] * fin.kappa[i] / (4.0 * kPi);
+    if (fin.with_L) v += fin.charge[(size_t)r * fin.N + fin.body_of[i]];
+    v += part;
+    fin.out[ri] = fin.alpha * v;
+  } else {
+    out[ri] = part;
+  }
 }
 
 // L2P, Stokes: sets 3r, 3r+1, 3r+2 are the expansions of A, B, C; adds -(1/pi) of
@@ -1833,7 +1871,7 @@ constexpr int kNearAtF32 = 0;
 template <int P, class T, class Near>
 int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
                      const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
-                     Near &&launch_near) {
+                     Near &&launch_near, const L2pFinish &fin) {
   const int M = t.M;
   // Where the near field (it depends only on the gather) is submitted: float64 expansions after
   // the multipole passes, so that it runs beside the M2L, whose products are on the matrix cores,
@@ -1857,7 +1895,7 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
     hipLaunchKernelGGL((k_l2p_laplace<P, T>), dim3(t.nev, R), dim3(64),
                        (size_t)t.ev_maxslot * P * sizeof(cx<T>), s, M, t.nbox, t.L, ih_leaf,
                        t.leaf_start, t.leaf_anc, t.center, t.xs, t.nrm, t.perm, t.ev_start,
-                       t.ev_leaf, Lexp, partial);
+                       t.ev_leaf, Lexp, partial, fin);
   } else {
     if constexpr (std::is_same<T, double>::value)
       hipLaunchKernelGGL((k_l2p_stokes<P>), dim3(t.nev, R), dim3(64),
@@ -2096,7 +2134,8 @@ long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order,
     }
     if (tree == 0) tree = 96LL * g->M + 1024LL * nbox + 16LL * 8 * p * p;
     total += tree + (long long)R * g->M * 32 +
-             (long long)((size_t)nsets * g->M + 2 * (size_t)nsets * nbox * p) * (long long)csz;
+             (long long)((size_t)nsets * g->M + 2 * (size_t)nsets * nbox * p) * (long long)csz +
+             (kind == 0 ? (long long)R * g->N * 8 + 64 : 0) + 512;
   }
   return total;
 }
@@ -2104,7 +2143,7 @@ long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order,
 // Far field of all pairs k != i (sets: Laplace R, Stokes 3R) into partial [R][len] (nsplit 1).
 int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu, double *s64,
                   double *partial,
-                  hipStream_t s, int order, int leaf) {
+                  hipStream_t s, int order, int leaf, const FmmFinish *finish) {
   const int p = fmm_length(order, precision);
   if (leaf <= 0) leaf = 64;
   FmmTree *tp = nullptr;
@@ -2117,12 +2156,21 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   const size_t csz = f32 ? sizeof(float2) : sizeof(double2);
   // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
   // locals [nsets][nbox][p]
-  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * csz + 512;
+  // (and, when the evaluation finishes the apply, the body charges [R][N])
+  const bool fuse = finish && kind == 0;
+  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * csz +
+                      (fuse ? (size_t)R * g->N * 8 + 64 : 0) + 512;
   BIE_TRY(t.work.reserve(need));
   double4 *S4 = t.work.as<double4>();
   char *wq = reinterpret_cast<char *>(S4 + (size_t)R * M);
   char *wm = wq + (size_t)nsets * M * csz;
   char *wl = wm + (size_t)nsets * t.nbox * p * csz;
+  double *charge = reinterpret_cast<double *>(
+      (reinterpret_cast<uintptr_t>(wl + (size_t)nsets * t.nbox * p * csz) + 63) & ~uintptr_t(63));
+  L2pFinish fin{};
+  if (fuse)
+    fin = L2pFinish{finish->mu, s64, g->kappa, charge, g->body_of, finish->out, finish->alpha,
+                    g->N, finish->with_L};
   FmmPlan &plan = *g->fmm;
   if (!plan.side) {  // side stream for the near field (default priority) and its fork/join events
     BIE_HIP_CHECK(hipStreamCreateWithFlags(&plan.side, hipStreamNonBlocking));
@@ -2143,6 +2191,9 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
   auto launch_near = [&]() -> int {
     BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
+    if (fuse && finish->with_L)  // the body charges for the finishing evaluation
+      hipLaunchKernelGGL(k_body_sums, dim3(g->N, R), dim3(256), 0, plan.side, M, g->N,
+                         g->body_ptr, s64, charge);
     {
       ProfScope pe(kind == 0 && f32 ? BIE_K_FMM_NEAR_F32 : BIE_K_FMM_EVAL, plan.side,
                    (t.near_pairs - M) * R);
@@ -2170,11 +2221,13 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
       return expansion_passes<P, float>(t, plan, kind, R, nsets, ih_leaf,
                                         reinterpret_cast<const float2 *>(wq),
                                         reinterpret_cast<float2 *>(wm),
-                                        reinterpret_cast<float2 *>(wl), partial, s, launch_near);
+                                        reinterpret_cast<float2 *>(wl), partial, s, launch_near,
+                                        fin);
     return expansion_passes<P, double>(t, plan, kind, R, nsets, ih_leaf,
                                        reinterpret_cast<const double2 *>(wq),
                                        reinterpret_cast<double2 *>(wm),
-                                       reinterpret_cast<double2 *>(wl), partial, s, launch_near);
+                                       reinterpret_cast<double2 *>(wl), partial, s, launch_near,
+                                       fin);
   }));
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;

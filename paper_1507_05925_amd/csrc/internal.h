@@ -278,8 +278,18 @@ int gmres_cycle(SysSet &ss, int precision, const double *r, double *d,
 
 // ---- fmm.hip ------------------------------------------------------------------------------
 // mu [nrhs][len] in; s64 [nrhs][len] out (the strengths w mu, for the epilogue)
+// The per-node terms a Laplace FMM apply can add in its evaluation kernel instead of a separate
+// epilogue: out = alpha (1/2 mu - s kappa / (4 pi) [+ with_L: the sum of s over the node's body]
+// + near + far), [R][M] in node order.
+struct FmmFinish {
+  const double *mu = nullptr;
+  double *out = nullptr;
+  double alpha = 1.0;
+  int with_L = 0;
+};
 int fmm_far_field(bie_geom *g, int kind, int precision, int nrhs, const double *mu, double *s64,
-                  double *partial, hipStream_t s, int order, int leaf);
+                  double *partial, hipStream_t s, int order, int leaf,
+                  const FmmFinish *finish = nullptr);
 void fmm_destroy(FmmPlan *p);
 // single-layer potentials at points by the treecode over the float64 FMM tree (see kernels.hip
 // eval_points for the layouts)

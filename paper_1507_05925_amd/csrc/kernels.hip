@@ -806,6 +806,17 @@ int apply_operator_ws(bie_geom *g, int kind, int precision, int method, int with
     if (method == BIE_FMM) {
       const int leaf = precision == BIE_MIXED && g->fmm_leaf_mixed > 0 ? g->fmm_leaf_mixed
                                                                         : g->fmm_leaf;
+      if (kind == 0) {  // the Laplace evaluation finishes the apply itself (no epilogue launch)
+        FmmFinish fin;
+        fin.mu = mu + off;
+        fin.out = out + off;
+        fin.alpha = alpha;
+        fin.with_L = with_L;
+        BIE_TRY(fmm_far_field(g, kind, precision, R, mu + off, s64 + off, partial, st,
+                              g->fmm_order, leaf, &fin));
+        r0 += R;
+        continue;
+      }
       BIE_TRY(fmm_far_field(g, kind, precision, R, mu + off, s64 + off, partial, st, g->fmm_order,
                             leaf));
     } else {
