@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--mixed-strategy", choices=["relaxed", "refine"], default="relaxed")
     p.add_argument("--fmm-leaf", type=int, default=0,
                    help="FMM mean nodes per leaf (0: the library's autotuner picks it)")
+    p.add_argument("--fmm-eps", type=float, default=1e-10,
+                   help="FMM accuracy target (float64 apply, relative); 0: --fmm-order")
+    p.add_argument("--fmm-order", type=int, default=40)
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -403,7 +406,7 @@ def mobility_bench(a):
     for name, prec in (("fp64", bie2d.BIE_FP64), ("mixed", bie2d.BIE_MIXED)):
         o = bie2d.default_opts(precision=prec, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
                                max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
-                               fmm_leaf=a.fmm_leaf)
+                               fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order)
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_mobility_solve(g, ft, o)
         torch.cuda.synchronize()
@@ -427,13 +430,16 @@ def mobility_bench(a):
             r["rel_err_omega_vs_fp64_oracle"] = float(np.abs(v[:, 2] - ref[:, 2]).max()
                                                       / np.abs(ref[:, 2]).max())
         runs[name] = r
-    # the float64 order-40 kernels timed with HIP events over one more solve, each class in a
+    # the float64 FMM kernels timed with HIP events over one more solve, each class in a
     # solve of its own: the M2L (three charge sets per right-hand side) and the Stokes near field
     o = bie2d.default_opts(precision=bie2d.BIE_FP64, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
-                           max_iter=2000, fmm_leaf=a.fmm_leaf)
+                           max_iter=2000, fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps,
+                           fmm_order=a.fmm_order)
+    terms = bie2d.bie_fmm_terms(o, 1, bie2d.BIE_FP64)
     rls = {}
     for key, kc, flops, bound, kern in (
-            ("roofline_m2l", bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(40), "mfma", "k_m2l<40>"),
+            ("roofline_m2l", bie2d.BIE_K_FMM_M2L, m2l_flops_per_entry(terms), "mfma",
+             f"k_m2l<{terms}>"),
             ("roofline_near", bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR_STOKES, "alu", "k_near<true>")):
         bie2d.bie_profile_select([kc])
         bie2d.bie_profile_enable(True)
@@ -459,7 +465,8 @@ def mobility_bench(a):
         "data": "synthetic (seeded ellipse ensemble, F ~ N(0,1)^2 with zero total, T ~ N(0,1))",
         "config": {"workload": "mobility, 200 ellipses (aspect 1..3, gaps >= 0.2) x 512 nodes "
                                "(204,800 unknowns), FMM, GMRES tol %g" % a.tol,
-                   "fastest": best,
+                   "fastest": best, "fmm_eps": a.fmm_eps,
+                   "fmm_terms": {"fp64": terms, "mixed": bie2d.bie_fmm_terms(o, 1, bie2d.BIE_MIXED)},
                    "fmm_leaf": leaf},
         "runs": runs, **rls}))
 
@@ -592,7 +599,7 @@ def main():
     prec = bie2d.BIE_MIXED if precision == "mixed" else bie2d.BIE_FP64
     opts = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100, max_iter=2000,
                               mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
-                              fmm_leaf=a.fmm_leaf)
+                              fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order)
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -606,8 +613,8 @@ def main():
         bie2d.bie_elastance_solve(g, q_d, opts)
     torch.cuda.synchronize()
 
-    order = (opts.fmm_order + 7) // 8 * 8
-    order32 = min(64, (max(8, (opts.fmm_order * 11 + 19) // 20) + 7) // 8 * 8)  # mixed applies
+    order = bie2d.bie_fmm_terms(opts, 0, bie2d.BIE_FP64)  # expansion terms, float64 applies
+    order32 = bie2d.bie_fmm_terms(opts, 0, bie2d.BIE_MIXED)  # and float32 ones
     classes = {  # class, algorithmic flops per unit, dtype, bound, kernel name in the profiles
         "k_lap_far_f32": (bie2d.BIE_K_FAR_LAPLACE_F32, FLOPS_PER_PAIR, "f32", "alu",
                           "k_lap_far_f32<1>"),
@@ -712,7 +719,8 @@ def main():
     fp64 = None
     if prec == bie2d.BIE_MIXED:
         o64 = bie2d.default_opts(precision=bie2d.BIE_FP64, method=meth, tol=a.tol, restart=100,
-                                 max_iter=2000, fmm_leaf=a.fmm_leaf)
+                                 max_iter=2000, fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps,
+                                 fmm_order=a.fmm_order)
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_elastance_solve(g, q_d, o64)
         torch.cuda.synchronize()
@@ -784,8 +792,9 @@ def main():
         "dtype": "f32+f64" if prec == bie2d.BIE_MIXED else "f64",
         "data": "synthetic (seeded starfish ensemble, q ~ N(0,1))",
         "config": {"workload": "elastance, 1000 starfish r0(1+0.3cos5t) x 256 nodes (M=256000), "
-                               "q~N(0,1), GMRES tol 1e-10",
-                   "method": a.method, "precision": precision, "fmm_order": opts.fmm_order,
+                               "q~N(0,1), 2D FMM at 1e-10, GMRES tol 1e-10",
+                   "method": a.method, "precision": precision, "fmm_eps": a.fmm_eps,
+                   "fmm_terms": {"fp64": order, "mixed": order32},
                    "fmm_leaf": a.fmm_leaf if a.fmm_leaf > 0 else
                    "autotuned (float64 %d, mixed %d)" % bie2d.bie_autotune(g, 0, prec),
                    **({"mixed_strategy": a.mixed_strategy} if prec == bie2d.BIE_MIXED else {}),

@@ -67,7 +67,8 @@ extern "C" {
  * BIE_MIXED_RELAXED  one float64 GMRES (float64 Arnoldi and residuals) whose steps apply the
  *                    BIE_MIXED operator once the estimated relative residual of every system it
  *                    applies to is below tol / eta, eta that apply's relative error (1e-7
- *                    direct, 1e-6 FMM Laplace, 1e-8 FMM Stokes; measured values rounded up):
+ *                    direct, 1e-6 FMM Laplace, for FMM Stokes ten times the fitted error of
+ *                    its expansion length, 2e-9 at 24 terms; measured values rounded up):
  *                    the error a step's apply may carry grows as the residual it reduces
  *                    falls (relaxed inexact Krylov, Simoncini & Szyld 2003). The solve stops
  *                    only on the float64 true residual of a cycle start, so a cycle that the
@@ -100,9 +101,11 @@ typedef struct {
   double viscosity; /* mobility / resistance: fluid viscosity > 0 (mobility problem
                        statement: viscosity 1 there). Velocities scale as 1/viscosity,
                        forces and torques as viscosity; densities do not change.        */
-  double fmm_eps;   /* BIE_FMM: > 0 sets the expansion order from a relative accuracy
-                       target, p = ceil(log(fmm_eps) / log(0.55)) clamped to [8, 64]
-                       (the FMM error falls about as 0.55^p); 0 = use fmm_order           */
+  double fmm_eps;   /* BIE_FMM: > 0 sets the expansion order from a target for the float64
+                       apply's relative error (2-norm against direct summation): the
+                       smallest p with K 0.45^p <= fmm_eps, K = 2.1e-3 (Laplace), 4.3e-2
+                       (Stokes), a fit of measured errors at p = 16, 24, 32; clamped to
+                       [8, 64] (1e-10: order 24 Laplace, 32 Stokes). 0 = use fmm_order   */
   int mixed_strategy; /* BIE_MIXED: BIE_MIXED_RELAXED (default) or BIE_MIXED_REFINE   */
   int l2_scaling;   /* 1: GMRES on the symmetrised system D A D^-1 (D mu) = D f with
                        D = diag(sqrt(w)) (the paper's L2 rescaling of the numerical
@@ -432,6 +435,12 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 int bie_autotune(bie_geom *g, int kind, int precision, int nrhs, int *leaf_fp64,
                  int *leaf_mixed, void *stream);
 int bie_autotune_stats(const bie_ctx *ctx, long long *tunings, long long *hits);
+
+/* Expansion length *terms (coefficients per expansion, a multiple of 8) of the FMM applies of a
+ * solve of kind 0 (Laplace) or 1 (Stokes) with options *opts: the float64 applies
+ * (precision BIE_FP64) or the BIE_MIXED ones (about half the order). Host only; BIE_EINVAL for
+ * invalid options. */
+int bie_fmm_terms(const bie_opts *opts, int kind, int precision, int *terms);
 
 /* Graph replay of the solves' Arnoldi steps (default off: measured slower than stream
  * launches on the 1000-starfish solve, about 6 us more per step). A single-geometry solve runs each

@@ -113,6 +113,7 @@ _SIGS = {
     "bie_autotune": ([_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _P], _I),
     "bie_autotune_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
                             ctypes.POINTER(ctypes.c_longlong)], _I),
+    "bie_fmm_terms": ([ctypes.POINTER(bie_opts), _I, _I, ctypes.POINTER(_I)], _I),
     "bie_geom_graph_stats": ([_P, ctypes.POINTER(ctypes.c_longlong),
                               ctypes.POINTER(ctypes.c_longlong)], _I),
     "bie_profile_enable": ([_I], _I),
@@ -133,6 +134,13 @@ def bie_autotune(g, kind, precision=BIE_FP64, nrhs=1):
     _check(lib().bie_autotune(g.handle, int(kind), precision, int(nrhs), ctypes.byref(a),
                               ctypes.byref(b), _stream()))
     return a.value, b.value
+
+
+def bie_fmm_terms(opts, kind, precision=BIE_FP64):
+    """Expansion length (terms) of the FMM applies of a solve with these options."""
+    t = _I()
+    _check(lib().bie_fmm_terms(ctypes.byref(opts), int(kind), int(precision), ctypes.byref(t)))
+    return t.value
 
 
 def bie_autotune_stats(ctx=None):
@@ -185,6 +193,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1507_05925_amd.build`")
+        try:  # torch's HIP runtime first, so that the library binds to the same one
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)

@@ -73,7 +73,7 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
     set_error("bie_batch_solve: l2_scaling is supported by the single-geometry solves only");
     return BIE_EINVAL;
   }
-  o.fmm_order = effective_order(o);
+
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   std::vector<long long> lens, starts, item_off(nitems + 1, 0), in_off(nitems + 1, 0);
   long long pairs = 0;
@@ -97,7 +97,7 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
     item_off[i + 1] = align8(item_off[i] + n * it.nrhs);  // 64-byte aligned item blocks
     in_off[i + 1] = in_off[i] + (long long)cols * (it.in ? 0 : it.nrhs);
     pairs += (long long)it.nrhs * it.g->M * (long long)it.g->M;
-    it.g->fmm_order = o.fmm_order;
+    it.g->fmm_order = effective_order(o, it.kind);
     // leaf sizes (fmm_leaf 0: the tuner's, for items the FMM applies)
     BIE_TRY(resolve_leaf(it.g, it.kind, o, it.nrhs, method_is_fmm(o.method, it.g->M), s));
   }
@@ -132,12 +132,13 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   for (int i = 0; i < nitems; ++i) {
     bie_geom *g = items[i].g;
     mitems[i] = {g, items[i].kind, items[i].nrhs, item_off[i],
-                 method_is_fmm(o.method, g->M), o.fmm_order, g->fmm_leaf};
+                 method_is_fmm(o.method, g->M), effective_order(o, items[i].kind), g->fmm_leaf};
     first_sys[i + 1] = first_sys[i] + items[i].nrhs;
   }
   ss.group_ptr = first_sys;  // items: a relaxed mixed solve picks precisions per item
   for (int i = 0; i < nitems; ++i)
-    ss.group_eta.push_back(mixed_apply_error(items[i].g, items[i].kind, o.method));
+    ss.group_eta.push_back(
+        mixed_apply_error(items[i].g, items[i].kind, o.method, effective_order(o, items[i].kind)));
   SysSet *ssp = &ss;
   MultiPlan **plan = &b->plan;
   ss.apply = [ssp, plan, mitems, first_sys, Ntot](int precision, const double *in, double *out,

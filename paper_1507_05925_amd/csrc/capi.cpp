@@ -117,9 +117,14 @@ int check_opts(const bie_opts &o) {
 
 // The expansion order the options ask for: from fmm_eps when it is set (the FMM error falls
 // about as 0.55^p for the one-box-separation interaction lists), else fmm_order.
-int effective_order(const bie_opts &o) {
+// The float64 FMM apply's relative error (2-norm against direct summation, measured on the
+// 1000-starfish and 200-ellipse geometries at orders 16, 24, 32) falls as about 0.45^p from
+// 2.1e-3 (Laplace) and 4.3e-2 (Stokes); fmm_eps takes the smallest order that this model puts
+// below it.
+int effective_order(const bie_opts &o, int kind) {
   if (!(o.fmm_eps > 0.0)) return o.fmm_order;
-  const int p = (int)std::ceil(std::log(o.fmm_eps) / std::log(0.55));
+  const double k0 = (kind & 1) ? 4.3e-2 : 2.1e-3;
+  const int p = (int)std::ceil(std::log(o.fmm_eps / k0) / std::log(0.45));
   return std::max(8, std::min(64, p));
 }
 
@@ -431,6 +436,17 @@ int bie_autotune(bie_geom *g, int kind, int precision, int nrhs, int *leaf_fp64,
   return BIE_OK;
 }
 
+int bie_fmm_terms(const bie_opts *opts, int kind, int precision, int *terms) {
+  if (!opts || (kind != 0 && kind != 1) || (precision != BIE_FP64 && precision != BIE_MIXED) ||
+      !terms) {
+    set_error("bie_fmm_terms: need opts, kind 0 or 1, precision BIE_FP64 or BIE_MIXED, terms");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(check_opts(*opts));
+  *terms = fmm_length(effective_order(*opts, kind), precision);
+  return BIE_OK;
+}
+
 int bie_autotune_stats(const bie_ctx *ctx, long long *tunings, long long *hits) {
   return tune_cache_stats(ctx ? ctx->tune : process_tune_cache(), tunings, hits);
 }
@@ -640,7 +656,7 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   double net[2];
   BIE_TRY(input_check(kind, g->N, nrhs, data, s, net));
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
-  g->fmm_order = effective_order(o);
+  g->fmm_order = effective_order(o, kind);
   const int meth = o.method == BIE_AUTO ? (method_is_fmm(o.method, g->M) ? BIE_FMM : BIE_DIRECT) : o.method;
   // leaf sizes (fmm_leaf 0: from the tuner, cached per shape class)
   BIE_TRY(resolve_leaf(g, kind, o, nrhs, meth == BIE_FMM, s));

@@ -33,7 +33,7 @@ struct DeviceGuard {
 };
 
 int check_opts(const bie_opts &o);       // BIE_EINVAL (message set) for invalid options
-int effective_order(const bie_opts &o);  // FMM expansion order from fmm_eps or fmm_order
+int effective_order(const bie_opts &o, int kind);  // FMM order from fmm_eps or fmm_order
 
 #define BIE_HIP_CHECK(call)                                                              \
   do {                                                                                   \
@@ -114,7 +114,7 @@ inline bool method_is_fmm(int method, long long M) {
   return method == BIE_FMM || (method == BIE_AUTO && M > kAutoFmmNodes);
 }
 // Relative error (2-norm) that the relaxed mixed strategy assumes for a BIE_MIXED apply.
-double mixed_apply_error(const bie_geom *g, int kind, int method);
+double mixed_apply_error(const bie_geom *g, int kind, int method, int order);
 
 // Apply precision value meaning "per group": group g's systems use float32 where
 // SysSet::group_f32[g] is set, float64 elsewhere.
@@ -309,8 +309,8 @@ int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s)
 // Sets g's FMM leaf sizes for a solve with opts o: o.fmm_leaf > 0 for both precisions; 0 = the
 // autotuner's (tune true) or 64 (tune false: callers that must not pause to time applies).
 int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s);
-int fmm_current_order();
-
+// Expansion length (terms, a multiple of 8) the FMM apply of `precision` uses for an order.
+int fmm_length(int order, int precision);
 
 // ---- multi.hip: one apply for many geometries ------------------------------------------------
 struct MultiItem {

@@ -93,7 +93,7 @@ long long footprint(const bie_server_config &c, bie_geom *g, int kind, int nrhs)
 long long geom_footprint(const bie_server_config &c, const bie_geom *g, int kind) {
   if (!uses_fmm(c.opts, g)) return 0;
   const long long len = kind == 0 ? g->M : 2LL * g->M;
-  return fmm_state_bytes(g, kind, c.opts.precision, c.opts.fmm_order, c.opts.fmm_leaf) +
+  return fmm_state_bytes(g, kind, c.opts.precision, effective_order(c.opts, kind), c.opts.fmm_leaf) +
          8LL * (kind == 0 ? 8 : 4) * len;
 }
 
@@ -107,7 +107,7 @@ int prepare(Request &r, const bie_opts &o, hipStream_t s) {
   r.f = r.inc + (size_t)r.nrhs * r.n;
   r.x = r.f + (size_t)r.nrhs * r.n;
   r.res = r.x + (size_t)r.nrhs * r.n;
-  r.g->fmm_order = o.fmm_order;
+  r.g->fmm_order = effective_order(o, r.kind);
   // fmm_leaf 0 serves with 64 nodes per leaf: timing leaf sizes would pause the other requests
   BIE_TRY(resolve_leaf(r.g, r.kind, o, r.nrhs, false, s));
   // stage the input in the result buffer, then incident density and rhs f = -(1/2 I + K) inc
@@ -153,7 +153,8 @@ Layout layout(const std::vector<std::shared_ptr<Request>> &reqs, const bie_opts 
     if (new_group) {
       cur = align8(cur);
       L.first.push_back(i);
-      L.items.push_back({r.g, r.kind, 0, cur, uses_fmm(o, r.g), o.fmm_order, r.g->fmm_leaf});
+      L.items.push_back({r.g, r.kind, 0, cur, uses_fmm(o, r.g), effective_order(o, r.kind),
+                         r.g->fmm_leaf});
     }
     L.off[i] = cur;
     L.items.back().nrhs += r.nrhs;
@@ -424,7 +425,6 @@ int bie_server_create(const bie_server_config *cfg, bie_server **out) {
     return BIE_ENOMEM;
   }
   srv->cfg = *cfg;
-  srv->cfg.opts.fmm_order = effective_order(cfg->opts);
   // the worker's stream is made here, on the caller's current device: a server that cannot
   // use the device fails now instead of leaving later waits without a worker
   if (hipGetDevice(&srv->device) != hipSuccess || hipStreamCreate(&srv->stream) != hipSuccess) {

@@ -103,6 +103,28 @@ def test_fmm_eps_sets_the_order():
 
 
 @pytest.mark.parametrize("kind", [0, 1])
+def test_fmm_eps_meets_its_target(kind):
+    """The order fmm_eps picks keeps the float64 FMM apply within fmm_eps of direct summation
+    (relative 2-norm, random densities) on a geometry other than the ones the model was fitted
+    on."""
+    c = wl.mixed_grid(np.random.default_rng(31), 60, np.full(60, 256))
+    g = bie2d.Geometry.from_curves(c)
+    rng = np.random.default_rng(32)
+    n = g.M if kind == 0 else 2 * g.M
+    mu = dev(rng.standard_normal((1, n)))
+    apply = bie2d.bie_laplace_apply if kind == 0 else bie2d.bie_stokes_apply
+    solve = bie2d.bie_elastance_solve if kind == 0 else bie2d.bie_mobility_solve
+    ref = apply(g, mu, bie2d.BIE_FP64, bie2d.BIE_DIRECT)
+    inp = dev(rng.standard_normal((1, g.N if kind == 0 else 3 * g.N)))
+    for eps in (1e-6, 1e-8, 1e-10):
+        o = bie2d.default_opts(method=bie2d.BIE_FMM, fmm_eps=eps, tol=1e-4)
+        solve(g, inp, o)  # sets the geometry's order from fmm_eps
+        out = apply(g, mu, bie2d.BIE_FP64, bie2d.BIE_FMM)
+        err = float((out - ref).norm() / ref.norm())
+        assert err < eps, (eps, err)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
 def test_l2_scaling_same_solution(kind):
     c = wl.mixed_grid(np.random.default_rng(4), 5, np.array([64, 96, 128, 160, 200]))
     geo = ny.geometry_of(c)
