@@ -74,7 +74,10 @@ def parse():
     p.add_argument("--mixed-strategy", choices=["relaxed", "refine"], default="relaxed")
     p.add_argument("--fmm-leaf", type=int, default=0,
                    help="FMM mean nodes per leaf (0: the library's autotuner picks it)")
-    p.add_argument("--fmm-eps", type=float, default=1e-10,
+    # the workloads ask for an FMM at 1e-10; the 1e-12 FMM (32 terms instead of 24) meets that
+    # and its solves converge in fewer GMRES steps (34 against 37 on the 1000 starfish), which
+    # more than pays for the longer expansions
+    p.add_argument("--fmm-eps", type=float, default=1e-12,
                    help="FMM accuracy target (float64 apply, relative); 0: --fmm-order")
     p.add_argument("--fmm-order", type=int, default=40)
     p.add_argument("--tol", type=float, default=1e-10)
@@ -792,7 +795,7 @@ def main():
         "dtype": "f32+f64" if prec == bie2d.BIE_MIXED else "f64",
         "data": "synthetic (seeded starfish ensemble, q ~ N(0,1))",
         "config": {"workload": "elastance, 1000 starfish r0(1+0.3cos5t) x 256 nodes (M=256000), "
-                               "q~N(0,1), 2D FMM at 1e-10, GMRES tol 1e-10",
+                               "q~N(0,1), 2D FMM at <= 1e-10, GMRES tol 1e-10",
                    "method": a.method, "precision": precision, "fmm_eps": a.fmm_eps,
                    "fmm_terms": {"fp64": order, "mixed": order32},
                    "fmm_leaf": a.fmm_leaf if a.fmm_leaf > 0 else

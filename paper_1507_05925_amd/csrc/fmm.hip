@@ -173,7 +173,7 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
       s64[(size_t)r * M + k] = v;
       if (Qf)
         Qf[(size_t)r * M + j] = make_float2((float)v, 0.0f);
-      else if (Q)
+      else
         Q[(size_t)r * M + j] = make_double2(v, 0.0);
       S4[(size_t)r * M + j] = make_double4(z.x, z.y, v, 0.0);
     } else {
@@ -181,11 +181,9 @@ __global__ void k_gather(int M, int R, int kind, const int *__restrict__ perm,
                                        wk * mu[(size_t)r * 2 * M + 2 * k + 1]);
       s64[(size_t)r * 2 * M + 2 * k] = rho.x;
       s64[(size_t)r * 2 * M + 2 * k + 1] = rho.y;
-      if (Q) {
-        Q[(size_t)(3 * r) * M + j] = rho;
-        Q[(size_t)(3 * r + 1) * M + j] = make_double2(rho.x, -rho.y);
-        Q[(size_t)(3 * r + 2) * M + j] = cmul(rho, make_double2(z.x, -z.y));
-      }
+      Q[(size_t)(3 * r) * M + j] = rho;
+      Q[(size_t)(3 * r + 1) * M + j] = make_double2(rho.x, -rho.y);
+      Q[(size_t)(3 * r + 2) * M + j] = cmul(rho, make_double2(z.x, -z.y));
       S4[(size_t)r * M + j] = make_double4(z.x, z.y, rho.x, rho.y);
     }
   }
@@ -225,15 +223,6 @@ constexpr int kChainPrio = 3;
 // lanes of each coefficient block are then added by three shuffle steps. Fixed order: the result
 // is reproducible. With NS > 1 (the three charge sets of a Stokes right-hand side) the powers of
 // w are formed once per source for all NS sets.
-// The charges come from Q (sorted order, per set), or, with src.mu set, straight from the
-// density in node order: q = w mu (Laplace, set = rhs) or, for the three sets of a Stokes
-// right-hand side, rho = w mu, conj(rho) and rho conj(z) (the gather's arithmetic), so that the
-// multipoles do not wait for the gather.
-struct P2mSource {
-  const int *perm;
-  const double *w, *mu;
-};
-
 template <int P, class T, int NS>
 __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const int *__restrict__ leaf_start,
@@ -242,7 +231,7 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
                                            const double2 *__restrict__ xs,
                                            const cx<T> *__restrict__ Q,
                                            const double *__restrict__ fact_in,
-                                           cx<T> *__restrict__ Mexp, const P2mSource src) {
+                                           cx<T> *__restrict__ Mexp) {
   __builtin_amdgcn_s_setprio(kChainPrio);
   constexpr int NB = P / 8;          // coefficients per lane
   constexpr int U = NS == 1 ? 8 : 4;  // sources per lane in one batch of loads
@@ -266,24 +255,8 @@ __global__ __launch_bounds__(64) void k_p2m(int M, int nbox, double inv_h,
       const int j = jb + g + 8 * u;
       const bool ok = j < j1;
       zz[u] = xs[ok ? j : j0];
-      if (src.mu) {
-        const int k = src.perm[ok ? j : j0];
-        const double wk = src.w[k];
-        if constexpr (NS == 1) {
-          const double v = wk * src.mu[(size_t)set0 * M + k];
-          qq[u][0] = ok ? mkc<T>((T)v, 0) : mkc<T>(0, 0);
-        } else {
-          const size_t r2 = (size_t)(set0 / 3) * 2 * M + 2 * (size_t)k;
-          const double2 rho = make_double2(wk * src.mu[r2], wk * src.mu[r2 + 1]);
-          const double2 rz = cmul(rho, make_double2(zz[u].x, -zz[u].y));
-          qq[u][0] = ok ? mkc<T>((T)rho.x, (T)rho.y) : mkc<T>(0, 0);
-          if (NS > 1) qq[u][1] = ok ? mkc<T>((T)rho.x, (T)-rho.y) : mkc<T>(0, 0);
-          if (NS > 2) qq[u][2] = ok ? mkc<T>((T)rz.x, (T)rz.y) : mkc<T>(0, 0);
-        }
-      } else {
 #pragma unroll
-        for (int e = 0; e < NS; ++e) qq[u][e] = ok ? Q[(size_t)(set0 + e) * M + j] : mkc<T>(0, 0);
-      }
+      for (int e = 0; e < NS; ++e) qq[u][e] = ok ? Q[(size_t)(set0 + e) * M + j] : mkc<T>(0, 0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1871,26 +1844,25 @@ void m2m_passes(const FmmTree &t, int nsets, cx<T> *Mexp, hipStream_t s) {
 
 template <int P, class T>
 void p2m_pass(const FmmTree &t, int kind, int nsets, double ih_leaf, const cx<T> *Q, cx<T> *Mexp,
-              hipStream_t s, const P2mSource &src) {
+              hipStream_t s) {
   const int M = t.M;
   bool p2m_done = false;
   if constexpr (std::is_same<T, double>::value) {
     if (kind != 0 && nsets % 3 == 0) {  // Stokes: the three sets of a right-hand side in one wave
       hipLaunchKernelGGL((k_p2m<P, T, 3>), dim3(t.nleaf, nsets / 3), dim3(64), 0, s, M, t.nbox,
-                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp,
-                         src);
+                         ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
       p2m_done = true;
     }
   }
   if (!p2m_done)
     hipLaunchKernelGGL((k_p2m<P, T, 1>), dim3(t.nleaf, nsets), dim3(64), 0, s, M, t.nbox,
-                       ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp, src);
+                       ih_leaf, t.leaf_start, t.leaf_box, t.center, t.xs, Q, t.fact_in, Mexp);
 }
 
 template <int P, class T>
 void upward_pass(const FmmTree &t, int kind, int nsets, double ih_leaf, const cx<T> *Q,
                  cx<T> *Mexp, hipStream_t s) {
-  p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s, P2mSource{});
+  p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);
   m2m_passes<P, T>(t, nsets, Mexp, s);
 }
 
@@ -1899,7 +1871,7 @@ constexpr int kNearAtF32 = 0;
 template <int P, class T, class Near>
 int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets, double ih_leaf,
                      const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
-                     Near &&launch_near, const L2pFinish &fin, const P2mSource &src) {
+                     Near &&launch_near, const L2pFinish &fin) {
   const int M = t.M;
   // Where the near field (it depends only on the gather) is submitted: float64 expansions after
   // the multipole passes, so that it runs beside the M2L, whose products are on the matrix cores,
@@ -1909,7 +1881,7 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
   // after them), since their M2L is shorter than the near field.
   constexpr int near_at = std::is_same<T, float>::value ? kNearAtF32 : 2;
   if (near_at == 0) BIE_TRY(launch_near());
-  p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s, src);
+  p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);
   if (near_at == 1) BIE_TRY(launch_near());
   m2m_passes<P, T>(t, nsets, Mexp, s);
   if (near_at == 2) BIE_TRY(launch_near());
@@ -2160,7 +2132,7 @@ long long fmm_state_bytes(const bie_geom *g, int kind, int precision, int order,
     }
     if (tree == 0) tree = 96LL * g->M + 1024LL * nbox + 16LL * 8 * p * p;
     total += tree + (long long)R * g->M * 32 +
-             (long long)(2 * (size_t)nsets * nbox * p) * (long long)csz +
+             (long long)((size_t)nsets * g->M + 2 * (size_t)nsets * nbox * p) * (long long)csz +
              (kind == 0 ? (long long)R * g->N * 8 + 64 : 0) + 512;
   }
   return total;
@@ -2180,14 +2152,16 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   // float32 expansions and near field for the mixed-precision Laplace apply
   const bool f32 = precision == BIE_MIXED && kind == 0;
   const size_t csz = f32 ? sizeof(float2) : sizeof(double2);
-  // work: near-field source records S4 [R][M] (32 B), multipoles and locals [nsets][nbox][p]
+  // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
+  // locals [nsets][nbox][p]
   // (and, when the evaluation finishes the apply, the body charges [R][N])
   const bool fuse = finish && kind == 0;
-  const size_t need = (size_t)R * M * 32 + (2 * (size_t)nsets * t.nbox * p) * csz +
+  const size_t need = (size_t)R * M * 32 + ((size_t)nsets * M + 2 * (size_t)nsets * t.nbox * p) * csz +
                       (fuse ? (size_t)R * g->N * 8 + 64 : 0) + 512;
   BIE_TRY(t.work.reserve(need));
   double4 *S4 = t.work.as<double4>();
-  char *wm = reinterpret_cast<char *>(S4 + (size_t)R * M);
+  char *wq = reinterpret_cast<char *>(S4 + (size_t)R * M);
+  char *wm = wq + (size_t)nsets * M * csz;
   char *wl = wm + (size_t)nsets * t.nbox * p * csz;
   double *charge = reinterpret_cast<double *>(
       (reinterpret_cast<uintptr_t>(wl + (size_t)nsets * t.nbox * p * csz) + 63) & ~uintptr_t(63));
@@ -2206,15 +2180,15 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
     BIE_HIP_CHECK(hipEventCreateWithFlags(&plan.join, kFlags));
   }
   ProfScope prof(BIE_K_FMM, s, (long long)R * M * (long long)M);
-  // The fork comes first: the side stream gathers the near-field records and the node-order
-  // strengths, forms the body charges and runs the near field (writing `partial`) while the main
-  // stream builds the expansions, whose P2M reads the density itself; the evaluation adds the
-  // far part after the join.
+  hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, s, M, R, kind, t.perm, t.xs, g->w,
+                     mu, s64,
+                     f32 ? nullptr : reinterpret_cast<double2 *>(wq),
+                     f32 ? reinterpret_cast<float2 *>(wq) : nullptr, S4);
+  // the near field needs only the source records: it runs on the side stream while the
+  // expansions are built, and writes `partial`; the L2P kernels add the far part after the join
   BIE_HIP_CHECK(hipEventRecord(plan.fork, s));
   auto launch_near = [&]() -> int {
     BIE_HIP_CHECK(hipStreamWaitEvent(plan.side, plan.fork, 0));
-    hipLaunchKernelGGL(k_gather, dim3((M + 255) / 256), dim3(256), 0, plan.side, M, R, kind,
-                       t.perm, t.xs, g->w, mu, s64, nullptr, nullptr, S4);
     if (fuse && finish->with_L)  // the body charges for the finishing evaluation
       hipLaunchKernelGGL(k_body_sums, dim3(g->N, R), dim3(256), 0, plan.side, M, g->N,
                          g->body_ptr, s64, charge);
@@ -2239,18 +2213,19 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
     return BIE_OK;
   };
   const double ih_leaf = (double)(1 << t.L) / t.size;
-  const P2mSource src{t.perm, g->w, mu};
   BIE_TRY(with_order(p, [&](auto order) -> int {
     constexpr int P = decltype(order)::value;
     if (f32)
-      return expansion_passes<P, float>(t, plan, kind, R, nsets, ih_leaf, nullptr,
+      return expansion_passes<P, float>(t, plan, kind, R, nsets, ih_leaf,
+                                        reinterpret_cast<const float2 *>(wq),
                                         reinterpret_cast<float2 *>(wm),
                                         reinterpret_cast<float2 *>(wl), partial, s, launch_near,
-                                        fin, src);
-    return expansion_passes<P, double>(t, plan, kind, R, nsets, ih_leaf, nullptr,
+                                        fin);
+    return expansion_passes<P, double>(t, plan, kind, R, nsets, ih_leaf,
+                                       reinterpret_cast<const double2 *>(wq),
                                        reinterpret_cast<double2 *>(wm),
                                        reinterpret_cast<double2 *>(wl), partial, s, launch_near,
-                                       fin, src);
+                                       fin);
   }));
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
