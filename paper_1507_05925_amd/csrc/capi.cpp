@@ -115,8 +115,7 @@ int check_opts(const bie_opts &o) {
   return BIE_OK;
 }
 
-// The expansion order the options ask for: from fmm_eps when it is set (the FMM error falls
-// about as 0.55^p for the one-box-separation interaction lists), else fmm_order.
+// The expansion order the options ask for: from fmm_eps when it is set, else fmm_order.
 // The float64 FMM apply's relative error (2-norm against direct summation, measured on the
 // 1000-starfish and 200-ellipse geometries at orders 16, 24, 32) falls as about 0.45^p from
 // 2.1e-3 (Laplace) and 4.3e-2 (Stokes); fmm_eps takes the smallest order that this model puts

@@ -45,9 +45,12 @@ double min_gap_ratio(const std::vector<double> &x, const std::vector<double> &y,
   }
   const double cell = gap_factor * wmax;
   if (!(cell > 0.0)) return gap_factor;
-  auto key = [](long long ix, long long iy) { return (ix << 32) ^ (iy & 0xffffffffLL); };
+  // cell indices >= 0, neighbours down to -1: hashed as unsigned (no shift of a negative value)
+  auto key = [](long long ix, long long iy) {
+    return ((unsigned long long)ix << 32) ^ ((unsigned long long)iy & 0xffffffffULL);
+  };
   std::vector<long long> kx(M), ky(M);
-  std::unordered_map<long long, std::vector<int>> grid;
+  std::unordered_map<unsigned long long, std::vector<int>> grid;
   grid.reserve((size_t)M / 4 + 16);
   for (int k = 0; k < M; ++k) {
     kx[k] = (long long)std::floor((x[k] - x0) / cell);
