@@ -80,6 +80,8 @@ def parse():
     p.add_argument("--fmm-eps", type=float, default=1e-12,
                    help="FMM accuracy target (float64 apply, relative); 0: --fmm-order")
     p.add_argument("--fmm-order", type=int, default=40)
+    p.add_argument("--precond", choices=["none", "block"], default="none",
+                   help="GMRES right preconditioner of the elastance solves")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -600,9 +602,11 @@ def main():
     meth = bie2d.BIE_FMM if a.method == "fmm" else bie2d.BIE_DIRECT
     precision = a.precision or "mixed"
     prec = bie2d.BIE_MIXED if precision == "mixed" else bie2d.BIE_FP64
+    pc = bie2d.BIE_PRECOND_BLOCK if a.precond == "block" else bie2d.BIE_PRECOND_NONE
     opts = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100, max_iter=2000,
                               mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
-                              fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order)
+                              fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order,
+                              precond=pc)
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -723,7 +727,7 @@ def main():
     if prec == bie2d.BIE_MIXED:
         o64 = bie2d.default_opts(precision=bie2d.BIE_FP64, method=meth, tol=a.tol, restart=100,
                                  max_iter=2000, fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps,
-                                 fmm_order=a.fmm_order)
+                                 fmm_order=a.fmm_order, precond=pc)
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_elastance_solve(g, q_d, o64)
         torch.cuda.synchronize()
@@ -797,7 +801,7 @@ def main():
         "config": {"workload": "elastance, 1000 starfish r0(1+0.3cos5t) x 256 nodes (M=256000), "
                                "q~N(0,1), 2D FMM at <= 1e-10, GMRES tol 1e-10",
                    "method": a.method, "precision": precision, "fmm_eps": a.fmm_eps,
-                   "fmm_terms": {"fp64": order, "mixed": order32},
+                   "fmm_terms": {"fp64": order, "mixed": order32}, "precond": a.precond,
                    "fmm_leaf": a.fmm_leaf if a.fmm_leaf > 0 else
                    "autotuned (float64 %d, mixed %d)" % bie2d.bie_autotune(g, 0, prec),
                    **({"mixed_strategy": a.mixed_strategy} if prec == bie2d.BIE_MIXED else {}),

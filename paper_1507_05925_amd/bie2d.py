@@ -23,6 +23,7 @@ BIE_OK, BIE_EINVAL, BIE_ENOMEM, BIE_ENOCONV, BIE_EDEVICE, BIE_ERESOLVE = 0, -1, 
 BIE_FP64, BIE_MIXED = 0, 1
 BIE_DIRECT, BIE_FMM, BIE_AUTO = 0, 1, 2
 BIE_MIXED_RELAXED, BIE_MIXED_REFINE = 0, 1
+BIE_PRECOND_NONE, BIE_PRECOND_BLOCK = 0, 1
 
 
 class BieError(RuntimeError):
@@ -42,7 +43,8 @@ class bie_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("fmm_order", ctypes.c_int), ("fmm_leaf", ctypes.c_int),
                 ("viscosity", ctypes.c_double), ("fmm_eps", ctypes.c_double),
-                ("mixed_strategy", ctypes.c_int), ("l2_scaling", ctypes.c_int)]
+                ("mixed_strategy", ctypes.c_int), ("precond", ctypes.c_int),
+                ("l2_scaling", ctypes.c_int)]
 
 
 class bie_batch_item(ctypes.Structure):

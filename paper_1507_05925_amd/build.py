@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbie2d.so")
-SOURCES = ["kernels.hip", "blas.hip", "fmm.hip", "gmres.cpp", "capi.cpp", "profile.cpp", "batch.cpp", "server.cpp", "multi.hip", "dirichlet.hip", "checks.cpp", "autotune.cpp"]
+SOURCES = ["kernels.hip", "blas.hip", "fmm.hip", "gmres.cpp", "capi.cpp", "profile.cpp", "batch.cpp", "server.cpp", "multi.hip", "dirichlet.hip", "checks.cpp", "autotune.cpp", "precond.hip"]
 
 # Packed-FP32 instructions are disabled for every device compile (the backend must not form
 # v_pk_* f32 operations); hipcc's host pass ignores the feature with a warning.

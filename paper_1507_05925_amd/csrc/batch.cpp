@@ -69,6 +69,10 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   bie_opts o;
   if (opts) o = *opts; else bie_default_opts(&o);
   BIE_TRY(check_opts(o));
+  if (o.precond != BIE_PRECOND_NONE) {
+    set_error("bie_batch_solve: precond is supported by the single-geometry elastance solves only");
+    return BIE_EINVAL;
+  }
   if (o.l2_scaling) {
     set_error("bie_batch_solve: l2_scaling is supported by the single-geometry solves only");
     return BIE_EINVAL;

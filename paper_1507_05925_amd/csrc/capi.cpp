@@ -96,6 +96,7 @@ static void fill_defaults(bie_opts *o) {
   o->fmm_order = 40;
   o->fmm_leaf = 64;
   o->mixed_strategy = BIE_MIXED_RELAXED;
+  o->precond = BIE_PRECOND_NONE;
   o->viscosity = 1.0;
   o->fmm_eps = 0.0;
   o->l2_scaling = 0;
@@ -108,7 +109,9 @@ int check_opts(const bie_opts &o) {
       o.max_iter < 1 || !(o.inner_tol > 0.0) || o.max_refine < 0 || o.fmm_order < 4 ||
       o.fmm_order > 64 || o.fmm_leaf < 0 || !(o.viscosity > 0.0) || !std::isfinite(o.viscosity) ||
       !(o.fmm_eps >= 0.0) || !(o.fmm_eps < 1.0) || (o.l2_scaling != 0 && o.l2_scaling != 1) ||
-      (o.mixed_strategy != BIE_MIXED_RELAXED && o.mixed_strategy != BIE_MIXED_REFINE)) {
+      (o.mixed_strategy != BIE_MIXED_RELAXED && o.mixed_strategy != BIE_MIXED_REFINE) ||
+      (o.precond != BIE_PRECOND_NONE && o.precond != BIE_PRECOND_BLOCK) ||
+      (o.precond == BIE_PRECOND_BLOCK && o.l2_scaling)) {
     set_error("invalid bie_opts");
     return BIE_EINVAL;
   }

@@ -606,13 +606,34 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
   const int method = o.method;
   {
     char key[160];
-    std::snprintf(key, sizeof key, "g%llu|k%d|m%d|r%d|o%d|l%d|s%d|%p|%p", g->gen, kind, method,
-                  nrhs, g->fmm_order, g->fmm_leaf, o.l2_scaling, (void *)g->ws_apply.ptr,
-                  (void *)g->ws_scale.ptr);
+    std::snprintf(key, sizeof key, "g%llu|k%d|m%d|r%d|o%d|l%d|s%d|p%d|%p|%p", g->gen, kind,
+                  method, nrhs, g->fmm_order, g->fmm_leaf, o.l2_scaling, o.precond,
+                  (void *)g->ws_apply.ptr, (void *)g->ws_scale.ptr);
     ss.graph_key = key;
   }
   ss.group_eta.assign(1, mixed_apply_error(g, kind, method, g->fmm_order));
   std::vector<double> rel;
+  if (o.precond == BIE_PRECOND_BLOCK) {
+    // right preconditioning: GMRES on (A P) u = f, then x = P u
+    if (kind != 0) {
+      set_error("the block-Jacobi preconditioner is for the Laplace operator (elastance) only");
+      return BIE_EINVAL;
+    }
+    BIE_TRY(bj_build(g, s));
+    BIE_TRY(g->ws_scale.reserve((size_t)nrhs * n * sizeof(double)));
+    double *tmp = g->ws_scale.as<double>();
+    ss.apply = [g, kind, method, nrhs, tmp](int precision, const double *in, double *out,
+                                            hipStream_t st) {
+      BIE_TRY(bj_apply(g, nrhs, in, tmp, st));
+      return apply_operator(g, kind, precision, method, 1, 1.0, nrhs, tmp, out, st);
+    };
+    const int rc = solve_systems(ss, o, f, x, rel, info, s);
+    if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+    BIE_TRY(bj_apply(g, nrhs, x, tmp, s));
+    BIE_HIP_CHECK(hipMemcpyAsync(x, tmp, (size_t)nrhs * n * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+    return rc;
+  }
   if (!o.l2_scaling) {
     ss.apply = [g, kind, method, nrhs](int precision, const double *in, double *out,
                                        hipStream_t st) {

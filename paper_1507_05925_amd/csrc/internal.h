@@ -198,6 +198,9 @@ struct bie_geom {
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box
   int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
+  // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
+  bie::DevBuf bj;
+  bool bj_ready = false;
 };
 
 namespace bie {
@@ -309,6 +312,10 @@ int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s)
 // Sets g's FMM leaf sizes for a solve with opts o: o.fmm_leaf > 0 for both precisions; 0 = the
 // autotuner's (tune true) or 64 (tune false: callers that must not pause to time applies).
 int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s);
+// ---- precond.hip: block-Jacobi right preconditioner of the Laplace operator -----------------
+int bj_build(bie_geom *g, hipStream_t s);  // BIE_EINVAL for bodies of more than 256 nodes
+int bj_apply(bie_geom *g, int nrhs, const double *in, double *out, hipStream_t s);  // [nrhs][M]
+
 // Expansion length (terms, a multiple of 8) the FMM apply of `precision` uses for an order.
 int fmm_length(int order, int precision);
 

@@ -415,6 +415,10 @@ int bie_server_create(const bie_server_config *cfg, bie_server **out) {
     set_error("bie_server_create: invalid configuration");
     return BIE_EINVAL;
   }
+  if (cfg->opts.precond != BIE_PRECOND_NONE) {
+    set_error("bie_server_create: precond is supported by the single-geometry elastance solves only");
+    return BIE_EINVAL;
+  }
   if (cfg->opts.l2_scaling) {
     set_error("bie_server_create: l2_scaling is supported by the single-geometry solves only");
     return BIE_EINVAL;

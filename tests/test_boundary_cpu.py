@@ -83,7 +83,7 @@ def test_option_validation_before_device():
     item = bie2d.bie_batch_item()
     info = bie2d.bie_info()
     for field, value in (("viscosity", 0.0), ("viscosity", float("nan")), ("fmm_eps", -1e-3),
-                         ("mixed_strategy", 2), ("mixed_strategy", -1),
+                         ("mixed_strategy", 2), ("mixed_strategy", -1), ("precond", 2),
                          ("l2_scaling", 2), ("l2_scaling", 1)):
         o = bie2d.default_opts(**{field: value})
         rc = L.bie_batch_solve(b, 1, ctypes.cast(ctypes.pointer(item), ctypes.c_void_p),
@@ -93,7 +93,14 @@ def test_option_validation_before_device():
     L.bie_batch_destroy(b)
     o = bie2d.default_opts()
     assert o.viscosity == 1.0 and o.fmm_eps == 0.0 and o.l2_scaling == 0
-    assert o.mixed_strategy == bie2d.BIE_MIXED_RELAXED
+    assert o.mixed_strategy == bie2d.BIE_MIXED_RELAXED and o.precond == bie2d.BIE_PRECOND_NONE
+    both = bie2d.default_opts(precond=bie2d.BIE_PRECOND_BLOCK, l2_scaling=1)
+    L = bie2d.lib()
+    b2 = ctypes.c_void_p()
+    assert L.bie_batch_create(ctypes.byref(b2)) == bie2d.BIE_OK
+    assert L.bie_batch_solve(b2, 1, ctypes.cast(ctypes.pointer(bie2d.bie_batch_item()), ctypes.c_void_p),
+                             ctypes.byref(both), ctypes.byref(bie2d.bie_info()), None, None) == bie2d.BIE_EINVAL
+    L.bie_batch_destroy(b2)
 
 
 @no_gpu
