@@ -5,8 +5,10 @@ quadrature data are built on the device (bie_geom_create), and one solve builds 
 One timed step = one whole solve on that resident geometry: incident charge and right-hand side,
 GMRES to a relative residual of 1e-10 with the operator apply (far field by the 2D FMM, float64
 self terms, diagonal and completion), potentials read off inside every conductor. By default the
-solves are mixed precision (float64 GMRES whose late steps apply the float32 operator), checked
-against the stored float64 oracle potentials; `fp64_path` times the same solves in plain float64.
+solves are mixed precision (float64 GMRES whose late steps apply the float32 operator) with the
+block-Jacobi right preconditioner, checked against the stored float64 oracle potentials;
+`fp64_path` times the same solves in float64, `unpreconditioned` the mixed solves without the
+preconditioner (the paper's plain GMRES).
 
 Reported value: pair interactions per second, counted as M^2 per operator apply (for the FMM this
 is the equivalent direct count, labelled as such in `metric`), over the timed steps.
@@ -80,8 +82,9 @@ def parse():
     p.add_argument("--fmm-eps", type=float, default=1e-12,
                    help="FMM accuracy target (float64 apply, relative); 0: --fmm-order")
     p.add_argument("--fmm-order", type=int, default=40)
-    p.add_argument("--precond", choices=["none", "block"], default="none",
-                   help="GMRES right preconditioner of the elastance solves")
+    p.add_argument("--precond", choices=["none", "block"], default="block",
+                   help="GMRES right preconditioner of the elastance solves (block: the inverses "
+                        "of the bodies' self blocks; the solution is the same)")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -722,6 +725,21 @@ def main():
             },
         }
 
+    # the same solves without the preconditioner (the paper's plain GMRES), for comparison
+    unpre = None
+    if pc != bie2d.BIE_PRECOND_NONE:
+        onp = bie2d.default_opts(precision=prec, method=meth, tol=a.tol, restart=100,
+                                 max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
+                                 fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order)
+        bie2d.bie_elastance_solve(g, q_d, onp)
+        torch.cuda.synchronize()
+        tn = time.perf_counter()
+        for _ in range(a.steps):
+            _, info_n = bie2d.bie_elastance_solve(g, q_d, onp)
+        torch.cuda.synchronize()
+        unpre = {"ms_per_solve": 1e3 * (time.perf_counter() - tn) / a.steps,
+                 "gmres": {k: info_n[k] for k in ("iters", "applies_fp32", "applies_fp64")}}
+
     # the plain float64 GPU path on the same solves, for comparison with the mixed solves
     fp64 = None
     if prec == bie2d.BIE_MIXED:
@@ -818,6 +836,7 @@ def main():
         **({"roofline_m2l_f32": rl_m2ls["k_m2l_f32"]} if "k_m2l_f32" in rl_m2ls else {}),
         "roofline_direct_p2p": rl_direct,
         **({"fp64_path": fp64} if fp64 is not None else {}),
+        **({"unpreconditioned": unpre} if unpre is not None else {}),
         **({"solve_breakdown": breakdown} if breakdown is not None else {}),
         "kernel_ms_per_solve_untimed": {k: v["ms_total"] for k, v in profs.items()},
         "fmm_ms_per_apply": fmm_total["ms_total"] / max(fmm_total["launches"], 1),

@@ -199,7 +199,7 @@ struct bie_geom {
   int fmm_leaf = 64;   // maximum nodes per leaf box
   int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
   // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
-  bie::DevBuf bj;
+  bie::DevBuf bj, bj_store;  // float32 inverses; the copy the apply reads if narrower
   bool bj_ready = false;
 };
 

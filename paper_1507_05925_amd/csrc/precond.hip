@@ -6,8 +6,10 @@
 //              - (1 - delta_ik) (1/2pi) w_k n_i . (x_i - x_k) / |x_i - x_k|^2 + w_k,
 // the discrete operator of eq. ModRep2 restricted to body b (the same terms as the apply). The
 // preconditioner changes the GMRES iterates, not the solution: every stopping test is on the
-// true residual of A x = f. Bodies of at most 256 nodes; the inverses are stored in float32
-// (a preconditioner need not be exact, only fixed), [N][256][256] column-major, zero-padded.
+// true residual of A x = f. Bodies of at most 256 nodes; the inverses are formed in float32
+// ([N][256][256] column-major, zero-padded) and kept in float16 for the apply (a preconditioner
+// need not be exact, only fixed).
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,9 +107,24 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_invert(const int *__restrict_
 // out = P in for every rhs: per body b, out_b[i] = sum_k Inv_b[i][k] in_b[k] (k ascending, float64
 // accumulation of the float32 entries). Grid (N, ceil(nrhs / R)); thread i = row i; the block's
 // input entries are staged in LDS.
+// The inverses as the apply reads them: float16 (a preconditioner need not be exact; the
+// iteration counts are those of the float32 inverses), entries k, k + 1 of row i side by side:
+// out[((b * 128 + k / 2) * 256 + i) * 2 + k % 2] = Inv_b[i][k].
+__global__ void k_bj_store(long long total, const float *__restrict__ in, __half *__restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (b, k, i) in order
+  if (t >= total) return;
+  const long long bk = t / kBj;
+  const int i = (int)(t % kBj), k = (int)(bk % kBj);
+  const long long b = bk / kBj;
+  out[((b * (kBj / 2) + k / 2) * kBj + i) * 2 + (k & 1)] = __float2half(in[t]);
+}
+
+// out = P in for every rhs: per body b, out_b[i] = sum_k Inv_b[i][k] in_b[k] (k ascending, float64
+// accumulation). Grid (N, ceil(nrhs / R)); thread i = row i reads the pairs (k, k + 1) of its row,
+// sixteen entries per batch of loads; the block's input entries are staged in LDS.
 template <int R>
 __global__ __launch_bounds__(kBj) void k_bj_apply(int M, int nrhs, const int *__restrict__ body_ptr,
-                                                  const float *__restrict__ inv,
+                                                  const __half2 *__restrict__ inv,
                                                   const double *__restrict__ in,
                                                   double *__restrict__ out) {
   __shared__ double v[R][kBj];
@@ -118,26 +135,33 @@ __global__ __launch_bounds__(kBj) void k_bj_apply(int M, int nrhs, const int *__
   for (int r = 0; r < R; ++r) v[r][i] = (r < nr && i < n) ? in[(size_t)(r0 + r) * M + k0 + i] : 0.0;
   __syncthreads();
   if (i >= n) return;
-  const float *col = inv + (size_t)b * kBj * kBj + i;
+  const __half2 *row = inv + (size_t)b * (kBj / 2) * kBj + i;  // pair p at row[p * kBj]
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    const double e0 = col[(size_t)k * kBj], e1 = col[(size_t)(k + 1) * kBj];
-    const double e2 = col[(size_t)(k + 2) * kBj], e3 = col[(size_t)(k + 3) * kBj];
+  const int np = (n + 1) / 2;  // pairs; a missing last column is zero
+  int p = 0;
+  for (; p + 8 <= np; p += 8) {
+    __half2 h[8];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      acc[r] = fma(e0, v[r][k], acc[r]);
-      acc[r] = fma(e1, v[r][k + 1], acc[r]);
-      acc[r] = fma(e2, v[r][k + 2], acc[r]);
-      acc[r] = fma(e3, v[r][k + 3], acc[r]);
+    for (int u = 0; u < 8; ++u) h[u] = row[(size_t)(p + u) * kBj];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float2 e = __half22float2(h[u]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r] = fma((double)e.x, v[r][2 * (p + u)], acc[r]);
+        acc[r] = fma((double)e.y, v[r][2 * (p + u) + 1], acc[r]);
+      }
     }
   }
-  for (; k < n; ++k) {
-    const double e0 = col[(size_t)k * kBj];
+  for (; p < np; ++p) {
+    const float2 e = __half22float2(row[(size_t)p * kBj]);
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = fma(e0, v[r][k], acc[r]);
+    for (int r = 0; r < R; ++r) {
+      acc[r] = fma((double)e.x, v[r][2 * p], acc[r]);
+      acc[r] = fma((double)e.y, v[r][2 * p + 1], acc[r]);
+    }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -160,6 +184,13 @@ int bj_build(bie_geom *g, hipStream_t s) {
   hipLaunchKernelGGL(k_bj_invert, dim3(g->N), dim3(kBjThreads), 0, s, g->body_ptr,
                      g->bj.as<float>());
   BIE_HIP_CHECK(hipGetLastError());
+  const long long total = (long long)g->N * kBj * kBj;
+  BIE_TRY(g->bj_store.reserve((size_t)total * sizeof(__half)));
+  hipLaunchKernelGGL(k_bj_store, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
+                     g->bj.as<float>(), g->bj_store.as<__half>());
+  BIE_HIP_CHECK(hipGetLastError());
+  BIE_HIP_CHECK(hipStreamSynchronize(s));
+  g->bj.release();  // only the float16 copy stays resident
   g->bj_ready = true;
   return BIE_OK;
 }
@@ -171,7 +202,7 @@ int bj_apply(bie_geom *g, int nrhs, const double *in, double *out, hipStream_t s
   }
   constexpr int R = 4;
   hipLaunchKernelGGL(k_bj_apply<R>, dim3(g->N, (nrhs + R - 1) / R), dim3(kBj), 0, s, g->M, nrhs,
-                     g->body_ptr, g->bj.as<float>(), in, out);
+                     g->body_ptr, g->bj_store.as<__half2>(), in, out);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
