@@ -104,9 +104,6 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_invert(const int *__restrict_
     *reinterpret_cast<float4 *>(o + e) = make_float4(a[e], a[e + 1], a[e + 2], a[e + 3]);
 }
 
-// out = P in for every rhs: per body b, out_b[i] = sum_k Inv_b[i][k] in_b[k] (k ascending, float64
-// accumulation of the float32 entries). Grid (N, ceil(nrhs / R)); thread i = row i; the block's
-// input entries are staged in LDS.
 // The inverses as the apply reads them: float16 (a preconditioner need not be exact; the
 // iteration counts are those of the float32 inverses), entries k, k + 1 of row i side by side:
 // out[((b * 128 + k / 2) * 256 + i) * 2 + k % 2] = Inv_b[i][k].
