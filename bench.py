@@ -47,6 +47,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X vector TFLOP/s (float64 MFMA: also 78.6)
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E bandwidth, GB/s
 FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), scale (1), 2 fma (4)
 FLOPS_PER_CMAC = 8   # complex multiply-add
 FLOPS_PER_PAIR_STOKES = 19  # stresslet kernel per node pair (two components)
@@ -183,6 +184,18 @@ def roofline(prof, kc, units_flops, dtype, bound="alu", kernel=None):
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": traffic_bytes(kernel), "avg_launch_ms": ms,
             "launches": prof["launches"], "units_per_launch": units, "flops_per_unit": units_flops}
+
+
+def roofline_hbm(prof, bytes_fixed, bytes_per_unit, kernel=None):
+    """Achieved algorithmic HBM bandwidth of one kernel class from its live HIP-event timings:
+    bytes_per_unit per recorded unit plus bytes_fixed per launch."""
+    ms = prof["ms_total"] / max(prof["launches"], 1)
+    units = prof["pairs"] / max(prof["launches"], 1)
+    nbytes = bytes_fixed + bytes_per_unit * units
+    ach = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic_bytes(kernel), "avg_launch_ms": ms,
+            "launches": prof["launches"], "units_per_launch": units, "bytes_per_launch": nbytes}
 
 
 def traffic_bytes(kernel):
@@ -681,6 +694,16 @@ def main():
         if pr["launches"] > 0:
             rl_m2ls[name] = roofline(pr, cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
             rl_m2ls[name]["kernel"] = cm[4]
+    # the preconditioner apply (HBM-bound: 2 B per float16 block entry, float64 in and out)
+    rl_pre = None
+    if pc != bie2d.BIE_PRECOND_NONE:
+        bie2d.bie_profile_select([bie2d.BIE_K_PRECOND])
+        bie2d.bie_profile_enable(True)
+        bie2d.bie_elastance_solve(g, q_d, opts)
+        pr = bie2d.bie_profile_read(bie2d.BIE_K_PRECOND)
+        bie2d.bie_profile_enable(False)
+        rl_pre = roofline_hbm(pr, 16.0 * g.M, 2.0, kernel="k_bj_apply<4>")
+        rl_pre["kernel"] = "k_bj_apply<4>"
     bie2d.bie_profile_select(None)
 
     # where a solve's time goes: the FMM applies of each precision timed on their own (events on
@@ -712,7 +735,10 @@ def main():
             "applies_fp64": n64, "apply_fp64_ms": ms_apply["fp64"],
             "applies_fp32": n32, "apply_fp32_ms": ms_apply["fp32"],
             "applies_ms": n64 * ms_apply["fp64"] + n32 * ms_apply["fp32"],
-            "arnoldi_readoff_host_ms": ms_solve - n64 * ms_apply["fp64"] - n32 * ms_apply["fp32"],
+            **({"precond_applies": rl_pre["launches"],
+                "precond_ms": rl_pre["launches"] * rl_pre["avg_launch_ms"]} if rl_pre else {}),
+            "arnoldi_readoff_host_ms": ms_solve - n64 * ms_apply["fp64"] - n32 * ms_apply["fp32"]
+            - (rl_pre["launches"] * rl_pre["avg_launch_ms"] if rl_pre else 0.0),
             "whole_apply_near_plus_m2l_flops": {
                 "note": "algorithmic near-field and M2L flops of one apply over the whole apply's "
                         "time (P2M, M2M, evaluation and epilogue flops not counted)",
@@ -834,6 +860,7 @@ def main():
         "roofline": rl,
         **({"roofline_m2l": rl_m2ls["k_m2l"]} if "k_m2l" in rl_m2ls else {}),
         **({"roofline_m2l_f32": rl_m2ls["k_m2l_f32"]} if "k_m2l_f32" in rl_m2ls else {}),
+        **({"roofline_precond": rl_pre} if rl_pre else {}),
         "roofline_direct_p2p": rl_direct,
         **({"fp64_path": fp64} if fp64 is not None else {}),
         **({"unpreconditioned": unpre} if unpre is not None else {}),

@@ -127,7 +127,8 @@ _SIGS = {
 
 BIE_K_FAR_LAPLACE_F32, BIE_K_FAR_LAPLACE_F64, BIE_K_FAR_STOKES_F32, BIE_K_FAR_STOKES_F64 = 0, 1, 2, 3
 BIE_K_EPILOGUE, BIE_K_FMM, BIE_K_FMM_M2L, BIE_K_FMM_EVAL = 4, 5, 6, 7
-BIE_K_DOUBLE_LAYER, BIE_K_FMM_M2L_F32, BIE_K_FMM_NEAR_F32, BIE_K_COUNT = 8, 9, 10, 11
+BIE_K_DOUBLE_LAYER, BIE_K_FMM_M2L_F32, BIE_K_FMM_NEAR_F32, BIE_K_PRECOND = 8, 9, 10, 11
+BIE_K_COUNT = 12
 
 
 def bie_autotune(g, kind, precision=BIE_FP64, nrhs=1):

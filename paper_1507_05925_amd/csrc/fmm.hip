@@ -1873,12 +1873,14 @@ int expansion_passes(const FmmTree &t, FmmPlan &plan, int kind, int R, int nsets
                      const cx<T> *Q, cx<T> *Mexp, cx<T> *Lexp, double *partial, hipStream_t s,
                      Near &&launch_near, const L2pFinish &fin) {
   const int M = t.M;
-  // Where the near field (it depends only on the gather) is submitted: float64 expansions after
-  // the multipole passes, so that it runs beside the M2L, whose products are on the matrix cores,
-  // rather than slowing the M2M passes (running the leaf level's M2L beside the M2M passes on a
-  // second stream, with the near field submitted first, measured 153 us per apply against
-  // 135 us); float32 expansions at kNearAtF32 (0 before the P2M, 1 before the M2M passes, 2
-  // after them), since their M2L is shorter than the near field.
+  // Where the near field is submitted. It waits on the GPU only for the gather (the fork event),
+  // so the order below is the host's submission order: float64 expansions submit it after the
+  // multipole passes, float32 ones at kNearAtF32 (0 before the P2M, 1 before the M2M passes, 2
+  // after them). Either way it overlaps the latency-bound upward chain: making it wait on the
+  // GPU for the whole upward pass measured 166 us per float64 apply against 150 us. A fused
+  // upward pass (P2M and every M2M level in two launches, one workgroup per subtree) measured
+  // slower as well: fewer, larger workgroups serialise the leaves' P2M and, at 1024 threads,
+  // wait for the near field's waves to drain.
   constexpr int near_at = std::is_same<T, float>::value ? kNearAtF32 : 2;
   if (near_at == 0) BIE_TRY(launch_near());
   p2m_pass<P, T>(t, kind, nsets, ih_leaf, Q, Mexp, s);

@@ -201,6 +201,7 @@ struct bie_geom {
   // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
   bie::DevBuf bj, bj_store;  // float32 inverses; the copy the apply reads if narrower
   bool bj_ready = false;
+  long long bj_entries = 0;  // sum over bodies of n_b^2
 };
 
 namespace bie {

@@ -188,6 +188,11 @@ int bj_build(bie_geom *g, hipStream_t s) {
   BIE_HIP_CHECK(hipGetLastError());
   BIE_HIP_CHECK(hipStreamSynchronize(s));
   g->bj.release();  // only the float16 copy stays resident
+  g->bj_entries = 0;
+  for (int b = 0; b < g->N; ++b) {
+    const long long n = g->h_body_ptr[b + 1] - g->h_body_ptr[b];
+    g->bj_entries += n * n;
+  }
   g->bj_ready = true;
   return BIE_OK;
 }
@@ -198,6 +203,8 @@ int bj_apply(bie_geom *g, int nrhs, const double *in, double *out, hipStream_t s
     return BIE_EINVAL;
   }
   constexpr int R = 4;
+  // units: block entries read, sum over bodies of n_b^2 once per chunk of R right-hand sides
+  ProfScope prof(BIE_K_PRECOND, s, g->bj_entries * ((nrhs + R - 1) / R));
   hipLaunchKernelGGL(k_bj_apply<R>, dim3(g->N, (nrhs + R - 1) / R), dim3(kBj), 0, s, g->M, nrhs,
                      g->body_ptr, g->bj_store.as<__half2>(), in, out);
   BIE_HIP_CHECK(hipGetLastError());
