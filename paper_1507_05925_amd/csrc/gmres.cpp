@@ -366,11 +366,21 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       ++mem.graph_captures;
       return BIE_OK;
     };
-    // Column j comes from step j + lag; step j + lag + 1 is queued before the host waits for it.
+    // Column j comes from step j + lag; step j + lag + 1 is queued before the host waits for it,
+    // unless column j is expected to end the cycle: the largest estimated residual over
+    // tolerance, extrapolated from the last two columns at their rate of decrease (no faster
+    // than the last step), is at most kHoldRatio. Then the step is queued only once column j
+    // shows it is needed (the device idles for the host's round trip, a few tens of
+    // microseconds), and a step whose work the converged cycle would discard is not run.
+    constexpr double kHoldRatio = 2.0;
+    double wlast = -1.0, wlast2 = -1.0;  // that ratio for the last two columns
     for (int k = 0; k <= lag; ++k) BIE_TRY(step(k));
     for (int j = 0; j < m; ++j) {
       st.iters += 1;
-      if (j + lag + 1 <= last_step && st.iters < max_iter) BIE_TRY(step(j + lag + 1));
+      const bool more = j + lag + 1 <= last_step && st.iters < max_iter;
+      const bool hold = more && wlast > 0.0 && wlast2 > 0.0 &&
+                        wlast * std::min(1.0, wlast / wlast2) <= kHoldRatio;
+      if (more && !hold) BIE_TRY(step(j + lag + 1));
       BIE_TRY(wait_column(mem.pinned + (j & 1) * slot + (size_t)S * hs, S, seqv[j & 1], s));
       const double *hh2 = mem.pinned + (j & 1) * slot;
       bool all_done = true;
@@ -404,6 +414,9 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       }
       jend = j;
       if (all_done || st.iters >= max_iter) break;
+      if (hold) BIE_TRY(step(j + lag + 1));
+      wlast2 = wlast;
+      wlast = *std::max_element(gworst.begin(), gworst.end());
     }
     BIE_HIP_CHECK(hipStreamSynchronize(s));  // the steps queued ahead, if any, are complete
     // y = H^{-1} g (upper triangular), x += V y
