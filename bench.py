@@ -694,7 +694,8 @@ def main():
         if pr["launches"] > 0:
             rl_m2ls[name] = roofline(pr, cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
             rl_m2ls[name]["kernel"] = cm[4]
-    # the preconditioner apply (HBM-bound: 2 B per float16 block entry, float64 in and out)
+    # the preconditioner apply (HBM-bound: 1 B per int8 block entry, a float64 scale per row,
+    # float64 in and out)
     rl_pre = None
     if pc != bie2d.BIE_PRECOND_NONE:
         bie2d.bie_profile_select([bie2d.BIE_K_PRECOND])
@@ -702,8 +703,8 @@ def main():
         bie2d.bie_elastance_solve(g, q_d, opts)
         pr = bie2d.bie_profile_read(bie2d.BIE_K_PRECOND)
         bie2d.bie_profile_enable(False)
-        rl_pre = roofline_hbm(pr, 16.0 * g.M, 2.0, kernel="k_bj_apply<4>")
-        rl_pre["kernel"] = "k_bj_apply<4>"
+        rl_pre = roofline_hbm(pr, 16.0 * g.M + 8.0 * 256 * g.N, 1.0, kernel="k_bj_apply_i8<1>")
+        rl_pre["kernel"] = "k_bj_apply_i8<1>"
     bie2d.bie_profile_select(None)
 
     # where a solve's time goes: the FMM applies of each precision timed on their own (events on

@@ -83,7 +83,7 @@ extern "C" {
 /* GMRES preconditioning (opts.precond). BIE_PRECOND_BLOCK: right preconditioning by the
  * block-diagonal inverse of the Laplace operator's self blocks (one per body: identity, diagonal
  * limit, same-body double-layer pairs, completion; inverted once per geometry on the device in
- * float32 and kept in float16, 128 KiB per body). The solution is that of the unpreconditioned system (the stopping tests
+ * float32 and kept, less the exact 2 I, as int8 with a float64 scale per row: 66 KiB per body). The solution is that of the unpreconditioned system (the stopping tests
  * use true float64 residuals of A x = f); the iteration count falls when the bodies interact
  * weakly (34 -> 11 steps for 100 starfish at gap >= 0.3). Single-geometry elastance solves and
  * elastance matrices only; BIE_EINVAL elsewhere, for bodies of more than 256 nodes and with

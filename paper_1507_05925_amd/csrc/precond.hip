@@ -7,9 +7,9 @@
 // the discrete operator of eq. ModRep2 restricted to body b (the same terms as the apply). The
 // preconditioner changes the GMRES iterates, not the solution: every stopping test is on the
 // true residual of A x = f. Bodies of at most 256 nodes; the inverses are formed in float32
-// ([N][256][256] column-major, zero-padded) and kept in float16 for the apply (a preconditioner
-// need not be exact, only fixed).
-#include <hip/hip_fp16.h>
+// ([N][256][256] column-major, zero-padded) and kept as int8 with a float64 scale per row, less
+// the exact 2 I (a preconditioner need not be exact, only fixed: the apply is exact arithmetic
+// on the stored entries, in float64).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -104,26 +104,50 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_invert(const int *__restrict_
     *reinterpret_cast<float4 *>(o + e) = make_float4(a[e], a[e + 1], a[e + 2], a[e + 3]);
 }
 
-// The inverses as the apply reads them: float16 (a preconditioner need not be exact; the
-// iteration counts are those of the float32 inverses), entries k, k + 1 of row i side by side:
-// out[((b * 128 + k / 2) * 256 + i) * 2 + k % 2] = Inv_b[i][k].
-__global__ void k_bj_store(long long total, const float *__restrict__ in, __half *__restrict__ out) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (b, k, i) in order
-  if (t >= total) return;
-  const long long bk = t / kBj;
-  const int i = (int)(t % kBj), k = (int)(bk % kBj);
-  const long long b = bk / kBj;
-  out[((b * (kBj / 2) + k / 2) * kBj + i) * 2 + (k & 1)] = __float2half(in[t]);
+// The inverses as the int8 apply reads them: D_b = Inv_b - 2 I (the identity's exact part
+// taken out), each row scaled to its largest magnitude, s_i = max_k |D_b[i][k]| / 127, and
+// rounded, q_ik = rint(D_b[i][k] / s_i); four consecutive entries of a row in one 32-bit word:
+// word ((b * 64 + k / 4) * 256 + i) holds q_i,k .. q_i,k+3 (byte k % 4). Grid N, 256 threads:
+// thread i forms row i. Scales [N][256] after the words.
+__global__ __launch_bounds__(kBj) void k_bj_store_i8(const int *__restrict__ body_ptr,
+                                                    const float *__restrict__ in,
+                                                    unsigned *__restrict__ words,
+                                                    double *__restrict__ scale) {
+  const int b = blockIdx.x, i = threadIdx.x;
+  const int n = body_ptr[b + 1] - body_ptr[b];
+  const float *col = in + (size_t)b * kBj * kBj + i;  // entry (i, k) at col[k * 256]
+  float mx = 0.0f;
+  if (i < n)
+    for (int k = 0; k < n; ++k) mx = fmaxf(mx, fabsf(col[(size_t)k * kBj] - (k == i ? 2.0f : 0.0f)));
+  const double sc = mx > 0.0f ? (double)mx / 127.0 : 1.0;
+  scale[(size_t)b * kBj + i] = sc;
+  const double isc = 1.0 / sc;
+  unsigned *o = words + (size_t)b * (kBj / 4) * kBj + i;
+  for (int k4 = 0; k4 < kBj; k4 += 4) {
+    unsigned w = 0;
+    for (int e = 0; e < 4; ++e) {
+      const int k = k4 + e;
+      int q = 0;
+      if (i < n && k < n) {
+        const double d = (double)col[(size_t)k * kBj] - (k == i ? 2.0 : 0.0);
+        q = (int)rint(d * isc);
+        q = q > 127 ? 127 : (q < -127 ? -127 : q);
+      }
+      w |= (unsigned)(q & 0xff) << (8 * e);
+    }
+    o[(size_t)(k4 / 4) * kBj] = w;
+  }
 }
 
-// out = P in for every rhs: per body b, out_b[i] = sum_k Inv_b[i][k] in_b[k] (k ascending, float64
-// accumulation). Grid (N, ceil(nrhs / R)); thread i = row i reads the pairs (k, k + 1) of its row,
-// sixteen entries per batch of loads; the block's input entries are staged in LDS.
+// out = P in with the int8 inverses: out_b[i] = 2 in_b[i] + s_i sum_k q_ik in_b[k] (k
+// ascending, float64 accumulation of the exact integer entries). Grid (N, ceil(nrhs / R)), thread
+// i = row i reads its row's words, eight per batch of loads.
 template <int R>
-__global__ __launch_bounds__(kBj) void k_bj_apply(int M, int nrhs, const int *__restrict__ body_ptr,
-                                                  const __half2 *__restrict__ inv,
-                                                  const double *__restrict__ in,
-                                                  double *__restrict__ out) {
+__global__ __launch_bounds__(kBj) void k_bj_apply_i8(int M, int nrhs, const int *__restrict__ body_ptr,
+                                                     const unsigned *__restrict__ words,
+                                                     const double *__restrict__ scale,
+                                                     const double *__restrict__ in,
+                                                     double *__restrict__ out) {
   __shared__ double v[R][kBj];
   const int b = blockIdx.x, r0 = blockIdx.y * R;
   const int k0 = body_ptr[b], n = body_ptr[b + 1] - k0, i = threadIdx.x;
@@ -132,37 +156,38 @@ __global__ __launch_bounds__(kBj) void k_bj_apply(int M, int nrhs, const int *__
   for (int r = 0; r < R; ++r) v[r][i] = (r < nr && i < n) ? in[(size_t)(r0 + r) * M + k0 + i] : 0.0;
   __syncthreads();
   if (i >= n) return;
-  const __half2 *row = inv + (size_t)b * (kBj / 2) * kBj + i;  // pair p at row[p * kBj]
+  const unsigned *row = words + (size_t)b * (kBj / 4) * kBj + i;  // word p at row[p * kBj]
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  const int np = (n + 1) / 2;  // pairs; a missing last column is zero
+  const int nw = (n + 3) / 4;  // words; missing entries of the last one are zero
   int p = 0;
-  for (; p + 8 <= np; p += 8) {
-    __half2 h[8];
+  for (; p + 8 <= nw; p += 8) {
+    unsigned h[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) h[u] = row[(size_t)(p + u) * kBj];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float2 e = __half22float2(h[u]);
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        acc[r] = fma((double)e.x, v[r][2 * (p + u)], acc[r]);
-        acc[r] = fma((double)e.y, v[r][2 * (p + u) + 1], acc[r]);
+      for (int e = 0; e < 4; ++e) {
+        const double q = (double)(int)(signed char)(h[u] >> (8 * e));
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(q, v[r][4 * (p + u) + e], acc[r]);
       }
-    }
   }
-  for (; p < np; ++p) {
-    const float2 e = __half22float2(row[(size_t)p * kBj]);
+  for (; p < nw; ++p) {
+    const unsigned h = row[(size_t)p * kBj];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      acc[r] = fma((double)e.x, v[r][2 * p], acc[r]);
-      acc[r] = fma((double)e.y, v[r][2 * p + 1], acc[r]);
+    for (int e = 0; e < 4; ++e) {
+      const double q = (double)(int)(signed char)(h >> (8 * e));
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = fma(q, v[r][4 * p + e], acc[r]);
     }
   }
+  const double sc = scale[(size_t)b * kBj + i];
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (r < nr) out[(size_t)(r0 + r) * M + k0 + i] = acc[r];
+    if (r < nr) out[(size_t)(r0 + r) * M + k0 + i] = fma(sc, acc[r], 2.0 * v[r][i]);
 }
 
 }  // namespace
@@ -181,13 +206,14 @@ int bj_build(bie_geom *g, hipStream_t s) {
   hipLaunchKernelGGL(k_bj_invert, dim3(g->N), dim3(kBjThreads), 0, s, g->body_ptr,
                      g->bj.as<float>());
   BIE_HIP_CHECK(hipGetLastError());
-  const long long total = (long long)g->N * kBj * kBj;
-  BIE_TRY(g->bj_store.reserve((size_t)total * sizeof(__half)));
-  hipLaunchKernelGGL(k_bj_store, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
-                     g->bj.as<float>(), g->bj_store.as<__half>());
+  const size_t total = (size_t)g->N * kBj * kBj;  // int8 entries, then the row scales
+  BIE_TRY(g->bj_store.reserve(total + (size_t)g->N * kBj * sizeof(double)));
+  hipLaunchKernelGGL(k_bj_store_i8, dim3(g->N), dim3(kBj), 0, s, g->body_ptr, g->bj.as<float>(),
+                     g->bj_store.as<unsigned>(),
+                     reinterpret_cast<double *>(g->bj_store.as<char>() + total));
   BIE_HIP_CHECK(hipGetLastError());
   BIE_HIP_CHECK(hipStreamSynchronize(s));
-  g->bj.release();  // only the float16 copy stays resident
+  g->bj.release();  // only the int8 copy stays resident
   g->bj_entries = 0;
   for (int b = 0; b < g->N; ++b) {
     const long long n = g->h_body_ptr[b + 1] - g->h_body_ptr[b];
@@ -205,8 +231,15 @@ int bj_apply(bie_geom *g, int nrhs, const double *in, double *out, hipStream_t s
   constexpr int R = 4;
   // units: block entries read, sum over bodies of n_b^2 once per chunk of R right-hand sides
   ProfScope prof(BIE_K_PRECOND, s, g->bj_entries * ((nrhs + R - 1) / R));
-  hipLaunchKernelGGL(k_bj_apply<R>, dim3(g->N, (nrhs + R - 1) / R), dim3(kBj), 0, s, g->M, nrhs,
-                     g->body_ptr, g->bj_store.as<__half2>(), in, out);
+  const size_t total = (size_t)g->N * kBj * kBj;
+  const unsigned *words = g->bj_store.as<unsigned>();
+  const double *scale = reinterpret_cast<const double *>(g->bj_store.as<char>() + total);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_bj_apply_i8<1>, dim3(g->N, 1), dim3(kBj), 0, s, g->M, nrhs, g->body_ptr,
+                       words, scale, in, out);
+  else
+    hipLaunchKernelGGL(k_bj_apply_i8<R>, dim3(g->N, (nrhs + R - 1) / R), dim3(kBj), 0, s, g->M,
+                       nrhs, g->body_ptr, words, scale, in, out);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }
