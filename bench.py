@@ -47,7 +47,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # MI355X vector TFLOP/s (float64 MFMA: also 78.6)
-PEAK_HBM_GBS = 8000.0  # MI355X HBM3E bandwidth, GB/s
 FLOPS_PER_PAIR = 11  # Laplace traction kernel: 2 sub, r^2 (3), reciprocal (1), scale (1), 2 fma (4)
 FLOPS_PER_CMAC = 8   # complex multiply-add
 FLOPS_PER_PAIR_STOKES = 19  # stresslet kernel per node pair (two components)
@@ -77,15 +76,15 @@ def parse():
     p.add_argument("--mixed-strategy", choices=["relaxed", "refine"], default="relaxed")
     p.add_argument("--fmm-leaf", type=int, default=0,
                    help="FMM mean nodes per leaf (0: the library's autotuner picks it)")
-    # the workloads ask for an FMM at 1e-10; the 1e-12 FMM (32 terms instead of 24) meets that
-    # and its solves converge in fewer GMRES steps (34 against 37 on the 1000 starfish), which
-    # more than pays for the longer expansions
-    p.add_argument("--fmm-eps", type=float, default=1e-12,
+    # the workloads ask for an FMM at 1e-10 (24 terms in the float64 Laplace applies). Without
+    # the preconditioner a 1e-12 FMM (32 terms) paid for itself (34 GMRES steps against 37 on the
+    # 1000 starfish); with it both take 12 steps and the shorter expansions are faster
+    p.add_argument("--fmm-eps", type=float, default=1e-10,
                    help="FMM accuracy target (float64 apply, relative); 0: --fmm-order")
     p.add_argument("--fmm-order", type=int, default=40)
     p.add_argument("--precond", choices=["none", "block"], default="block",
-                   help="GMRES right preconditioner of the elastance solves (block: the inverses "
-                        "of the bodies' self blocks; the solution is the same)")
+                   help="GMRES right preconditioner of the elastance and mobility solves (block: "
+                        "two-grid inverses of the bodies' self blocks; the solution is the same)")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -184,18 +183,6 @@ def roofline(prof, kc, units_flops, dtype, bound="alu", kernel=None):
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": traffic_bytes(kernel), "avg_launch_ms": ms,
             "launches": prof["launches"], "units_per_launch": units, "flops_per_unit": units_flops}
-
-
-def roofline_hbm(prof, bytes_fixed, bytes_per_unit, kernel=None):
-    """Achieved algorithmic HBM bandwidth of one kernel class from its live HIP-event timings:
-    bytes_per_unit per recorded unit plus bytes_fixed per launch."""
-    ms = prof["ms_total"] / max(prof["launches"], 1)
-    units = prof["pairs"] / max(prof["launches"], 1)
-    nbytes = bytes_fixed + bytes_per_unit * units
-    ach = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": traffic_bytes(kernel), "avg_launch_ms": ms,
-            "launches": prof["launches"], "units_per_launch": units, "bytes_per_launch": nbytes}
 
 
 def traffic_bytes(kernel):
@@ -424,10 +411,15 @@ def mobility_bench(a):
     gold = os.path.join(ROOT, "tests", "golden", "ellipses_200x512_vw.json")
     ref = np.asarray(json.load(open(gold))["VW"]).reshape(-1, 3) if os.path.exists(gold) else None
     runs = {}
-    for name, prec in (("fp64", bie2d.BIE_FP64), ("mixed", bie2d.BIE_MIXED)):
+    pc = bie2d.BIE_PRECOND_BLOCK if a.precond == "block" else bie2d.BIE_PRECOND_NONE
+    cases = [("fp64", bie2d.BIE_FP64, pc), ("mixed", bie2d.BIE_MIXED, pc)]
+    if pc != bie2d.BIE_PRECOND_NONE:  # the paper's plain GMRES beside it
+        cases.append(("mixed_unpreconditioned", bie2d.BIE_MIXED, bie2d.BIE_PRECOND_NONE))
+    for name, prec, pcn in cases:
         o = bie2d.default_opts(precision=prec, method=bie2d.BIE_FMM, tol=a.tol, restart=100,
                                max_iter=2000, mixed_strategy=MIXED_STRATEGY[a.mixed_strategy],
-                               fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order)
+                               fmm_leaf=a.fmm_leaf, fmm_eps=a.fmm_eps, fmm_order=a.fmm_order,
+                               precond=pcn)
         for _ in range(max(a.warmup, 1)):
             bie2d.bie_mobility_solve(g, ft, o)
         torch.cuda.synchronize()
@@ -475,7 +467,7 @@ def mobility_bench(a):
     leaf = a.fmm_leaf if a.fmm_leaf > 0 else \
         "autotuned (float64 %d, mixed %d)" % bie2d.bie_autotune(g, 1, bie2d.BIE_MIXED)
     g.close()
-    best = max(runs, key=lambda k: runs[k]["solves_per_s"])
+    best = max((k for k in runs if k in ("fp64", "mixed")), key=lambda k: runs[k]["solves_per_s"])
     print(json.dumps({
         "metric": "pair-interactions/s (equivalent direct, M^2 node pairs per operator apply) of full "
                   "mobility solves",
@@ -486,7 +478,7 @@ def mobility_bench(a):
         "data": "synthetic (seeded ellipse ensemble, F ~ N(0,1)^2 with zero total, T ~ N(0,1))",
         "config": {"workload": "mobility, 200 ellipses (aspect 1..3, gaps >= 0.2) x 512 nodes "
                                "(204,800 unknowns), FMM, GMRES tol %g" % a.tol,
-                   "fastest": best, "fmm_eps": a.fmm_eps,
+                   "fastest": best, "fmm_eps": a.fmm_eps, "precond": a.precond,
                    "fmm_terms": {"fp64": terms, "mixed": bie2d.bie_fmm_terms(o, 1, bie2d.BIE_MIXED)},
                    "fmm_leaf": leaf},
         "runs": runs, **rls}))
@@ -694,8 +686,8 @@ def main():
         if pr["launches"] > 0:
             rl_m2ls[name] = roofline(pr, cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
             rl_m2ls[name]["kernel"] = cm[4]
-    # the preconditioner apply (HBM-bound: 1 B per int8 block entry, a float64 scale per row,
-    # float64 in and out)
+    # the preconditioner apply: exact int8 blocks here (256 unknowns per body), HBM-bound:
+    # one byte per entry (units: entries), a float64 scale per row, float64 in and out
     rl_pre = None
     if pc != bie2d.BIE_PRECOND_NONE:
         bie2d.bie_profile_select([bie2d.BIE_K_PRECOND])
@@ -703,8 +695,15 @@ def main():
         bie2d.bie_elastance_solve(g, q_d, opts)
         pr = bie2d.bie_profile_read(bie2d.BIE_K_PRECOND)
         bie2d.bie_profile_enable(False)
-        rl_pre = roofline_hbm(pr, 16.0 * g.M + 8.0 * 256 * g.N, 1.0, kernel="k_bj_apply_i8<1>")
-        rl_pre["kernel"] = "k_bj_apply_i8<1>"
+        ms = pr["ms_total"] / max(pr["launches"], 1)
+        units = pr["pairs"] / max(pr["launches"], 1)
+        nbytes = units + 8.0 * g.M + 16.0 * g.M
+        ach = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kern = "k_pc_apply_i8<256, 1>"
+        rl_pre = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+                  "frac": ach / 8000.0, "traffic": traffic_bytes(kern), "avg_launch_ms": ms,
+                  "launches": pr["launches"], "units_per_launch": units,
+                  "bytes_per_launch": nbytes, "kernel": kern}
     bie2d.bie_profile_select(None)
 
     # where a solve's time goes: the FMM applies of each precision timed on their own (events on

@@ -80,14 +80,20 @@ extern "C" {
 #define BIE_MIXED_RELAXED 0
 #define BIE_MIXED_REFINE 1
 
-/* GMRES preconditioning (opts.precond). BIE_PRECOND_BLOCK: right preconditioning by the
- * block-diagonal inverse of the Laplace operator's self blocks (one per body: identity, diagonal
- * limit, same-body double-layer pairs, completion; inverted once per geometry on the device in
- * float32 and kept, less the exact 2 I, as int8 with a float64 scale per row: 66 KiB per body). The solution is that of the unpreconditioned system (the stopping tests
- * use true float64 residuals of A x = f); the iteration count falls when the bodies interact
- * weakly (34 -> 11 steps for 100 starfish at gap >= 0.3). Single-geometry elastance solves and
- * elastance matrices only; BIE_EINVAL elsewhere, for bodies of more than 256 nodes and with
- * l2_scaling. */
+/* GMRES preconditioning (opts.precond). BIE_PRECOND_BLOCK: right preconditioning by an
+ * approximate inverse of the operator's block diagonal, one block per body (its self
+ * interactions: identity, diagonal limit, same-body double-layer pairs, completion), built once
+ * per geometry and kind on the device. Bodies of at most 256 unknowns (nodes for Laplace, twice
+ * the nodes for Stokes) when every body has at most 256: the exact block inverses (float32
+ * Gauss-Jordan), kept less the exact 2 I as int8 with a float64 scale per row. Otherwise two-grid
+ * blocks: the inverse's smooth part formed on a coarse grid of each curve (n itself up to 64
+ * nodes, else the largest divisor of n in [16, 64]) with trigonometric restriction and
+ * interpolation. The solution is that of the unpreconditioned system (the stopping tests use
+ * true float64 residuals of A x = f); the iteration count falls when the bodies interact
+ * weakly (34 -> 12 steps for 1000 starfish at gap >= 0.3, 64 -> 18 for 200 ellipses at gap >=
+ * 0.2). Single-geometry elastance and mobility solves and matrices; BIE_EINVAL for the
+ * capacitance and resistance solves, batches and the server, with l2_scaling, and for a body of
+ * more than 2048 nodes or with no such divisor. */
 #define BIE_PRECOND_NONE 0
 #define BIE_PRECOND_BLOCK 1
 
@@ -118,9 +124,9 @@ typedef struct {
                        (Stokes), a fit of measured errors at p = 16, 24, 32; clamped to
                        [8, 64] (1e-10: order 24 Laplace, 32 Stokes). 0 = use fmm_order   */
   int mixed_strategy; /* BIE_MIXED: BIE_MIXED_RELAXED (default) or BIE_MIXED_REFINE   */
-  int precond;      /* BIE_PRECOND_NONE (default) or BIE_PRECOND_BLOCK: elastance solves
-                       (Laplace, bodies of at most 256 nodes) run GMRES on (A P) u = f with
-                       P the block-diagonal inverse of the bodies' self blocks, x = P u     */
+  int precond;      /* BIE_PRECOND_NONE (default) or BIE_PRECOND_BLOCK: elastance and
+                       mobility solves run GMRES on (A P) u = f with P an approximate inverse
+                       of the bodies' self blocks, x = P u                                 */
   int l2_scaling;   /* 1: GMRES on the symmetrised system D A D^-1 (D mu) = D f with
                        D = diag(sqrt(w)) (the paper's L2 rescaling of the numerical
                        section): same solution, the stopping test then uses the discrete

@@ -628,21 +628,21 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
   std::vector<double> rel;
   if (o.precond == BIE_PRECOND_BLOCK) {
     // right preconditioning: GMRES on (A P) u = f, then x = P u
-    if (kind != 0) {
-      set_error("the block-Jacobi preconditioner is for the Laplace operator (elastance) only");
+    if (kind > 1) {
+      set_error("the block preconditioner is for the elastance and mobility solves");
       return BIE_EINVAL;
     }
-    BIE_TRY(bj_build(g, s));
+    BIE_TRY(pc_build(g, kind, s));
     BIE_TRY(g->ws_scale.reserve((size_t)nrhs * n * sizeof(double)));
     double *tmp = g->ws_scale.as<double>();
     ss.apply = [g, kind, method, nrhs, tmp](int precision, const double *in, double *out,
                                             hipStream_t st) {
-      BIE_TRY(bj_apply(g, nrhs, in, tmp, st));
+      BIE_TRY(pc_apply(g, kind, nrhs, in, tmp, st));
       return apply_operator(g, kind, precision, method, 1, 1.0, nrhs, tmp, out, st);
     };
     const int rc = solve_systems(ss, o, f, x, rel, info, s);
     if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
-    BIE_TRY(bj_apply(g, nrhs, x, tmp, s));
+    BIE_TRY(pc_apply(g, kind, nrhs, x, tmp, s));
     BIE_HIP_CHECK(hipMemcpyAsync(x, tmp, (size_t)nrhs * n * sizeof(double),
                                  hipMemcpyDeviceToDevice, s));
     return rc;

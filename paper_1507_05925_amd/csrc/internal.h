@@ -199,9 +199,18 @@ struct bie_geom {
   int fmm_leaf = 64;   // maximum nodes per leaf box
   int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
   // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
-  bie::DevBuf bj, bj_store;  // float32 inverses; the copy the apply reads if narrower
-  bool bj_ready = false;
-  long long bj_entries = 0;  // sum over bodies of n_b^2
+  // block preconditioner per kind (precond.hip): exact blocks as int8 words and row scales
+  // (q), or inverted coarse blocks [N][BJ][BJ] (float32, column-major, inv); per body the
+  // coarse node count and the offset of its transfer table
+  struct Precond {
+    bie::DevBuf inv, q, meta;
+    bool ready = false, exact = false;
+    int BJ = 0;
+    int *ncoarse = nullptr, *rho_off = nullptr;
+    double *rho = nullptr;
+    long long macs = 0;  // multiply-adds per apply and right-hand side
+    size_t lds = 0;      // dynamic LDS of the apply
+  } pc[2];
 };
 
 namespace bie {
@@ -314,8 +323,10 @@ int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s)
 // autotuner's (tune true) or 64 (tune false: callers that must not pause to time applies).
 int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s);
 // ---- precond.hip: block-Jacobi right preconditioner of the Laplace operator -----------------
-int bj_build(bie_geom *g, hipStream_t s);  // BIE_EINVAL for bodies of more than 256 nodes
-int bj_apply(bie_geom *g, int nrhs, const double *in, double *out, hipStream_t s);  // [nrhs][M]
+// Block preconditioner of kind 0 (Laplace) or 1 (Stokes): built once per geometry and kind
+// (BIE_EINVAL for a body it cannot coarsen); apply out = P in, [nrhs][M] resp. [nrhs][2M].
+int pc_build(bie_geom *g, int kind, hipStream_t s);
+int pc_apply(bie_geom *g, int kind, int nrhs, const double *in, double *out, hipStream_t s);
 
 // Expansion length (terms, a multiple of 8) the FMM apply of `precision` uses for an order.
 int fmm_length(int order, int precision);

@@ -1,7 +1,8 @@
-"""GPU: the block-Jacobi right preconditioner (opts.precond = BIE_PRECOND_BLOCK) leaves the solution
-unchanged (against the float64 oracle and against the unpreconditioned solves) and cuts the GMRES
-steps on multi-body elastance problems; it is refused where it does not apply (Stokes, bodies
-of more than 256 nodes)."""
+"""GPU: the block right preconditioner (opts.precond = BIE_PRECOND_BLOCK; exact int8 blocks up to
+256 unknowns per body, two-grid blocks beyond) leaves the solution unchanged (against the float64 oracle and
+against the unpreconditioned solves), for elastance and mobility, and cuts the GMRES steps on
+multi-body problems; it is refused where it does not apply (bodies it cannot coarsen, the
+capacitance and resistance solves)."""
 import numpy as np
 import pytest
 
@@ -40,10 +41,49 @@ def test_precond_small_vs_oracle(precision, tol):
     assert rel(P, ny.elastance_matrix(geo)) < tol
 
 
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+@pytest.mark.parametrize("n", [48, 192])
+def test_precond_mobility_small_vs_oracle(precision, tol, n):
+    """Four ellipses: exact int8 blocks (48 nodes, 96 unknowns each) and two-grid blocks (192
+    nodes, 64 coarse)."""
+    c, FT = wl.mobility_ellipses(nbodies=4, n=n)
+    g = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    rng = np.random.default_rng(43)
+    X = np.vstack([FT, rng.standard_normal((2, 3 * geo["N"]))])
+    ref = ny.mobility_solve(geo, X)
+    o = bie2d.default_opts(precision=precision, precond=bie2d.BIE_PRECOND_BLOCK, tol=1e-12)
+    VW, info, mu = bie2d.bie_mobility_solve(g, dev(X), o, want_mu=True)
+    assert rel(VW, ref["VW"]) < tol, info
+    assert rel(mu, ref["mu"]) < 100 * tol, info
+    Mm, _ = bie2d.bie_mobility_matrix(g, max_rhs=5, opts=o)
+    assert rel(Mm, ny.mobility_matrix(geo)) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_precond_elastance_two_grid_vs_oracle(precision, tol):
+    """Six starfish of 320 nodes: more than 256 unknowns per body, so two-grid blocks (64
+    coarse nodes)."""
+    c, q = wl.elastance_starfish(nbodies=6, n=320)
+    g = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    rng = np.random.default_rng(47)
+    Q = np.vstack([q, rng.standard_normal((2, geo["N"]))])
+    ref = ny.elastance_solve(geo, Q)
+    o = bie2d.default_opts(precision=precision, precond=bie2d.BIE_PRECOND_BLOCK, tol=1e-12)
+    phi, info, mu = bie2d.bie_elastance_solve(g, dev(Q), o, want_mu=True)
+    assert rel(phi, ref["phi"]) < tol, info
+    assert rel(mu, ref["mu"]) < 100 * tol, info
+    base = bie2d.default_opts(precision=precision, tol=1e-12)
+    _, i0 = bie2d.bie_elastance_solve(g, dev(Q), base)
+    assert info["iters"] < i0["iters"], (info, i0)
+
+
 @pytest.mark.parametrize("method", [bie2d.BIE_DIRECT, bie2d.BIE_FMM])
 def test_precond_same_solution_fewer_steps(method):
-    """100 starfish of 256 nodes (gap >= 0.3): the same potentials as without the
-    preconditioner, in at most half the GMRES steps (34 -> 11 measured with the oracle)."""
+    """100 starfish of 256 nodes (gap >= 0.3; exact int8 blocks): the same potentials as without
+    the preconditioner, in at most half the GMRES steps (34 -> 11 measured with exact blocks and
+    the oracle)."""
     c, q = wl.elastance_starfish(nbodies=100)
     g = bie2d.Geometry.from_curves(c)
     qd = dev(q[None])
@@ -61,14 +101,34 @@ def test_precond_same_solution_fewer_steps(method):
     assert i2["rel_residual"] < 1e-11
 
 
+@pytest.mark.parametrize("method", [bie2d.BIE_DIRECT, bie2d.BIE_FMM])
+def test_precond_mobility_fewer_steps(method):
+    """40 ellipses of 256 nodes (two-grid blocks on 64 nodes): the same rigid motions, in at
+    most half the steps (55 -> 17 measured with the oracle on 20 such ellipses)."""
+    c, FT = wl.mobility_ellipses(nbodies=40, n=256)
+    g = bie2d.Geometry.from_curves(c)
+    x = dev(FT[None])
+    base = bie2d.default_opts(method=method, tol=1e-11)
+    v0, i0 = bie2d.bie_mobility_solve(g, x, base)
+    pre = bie2d.default_opts(method=method, tol=1e-11, precond=bie2d.BIE_PRECOND_BLOCK)
+    v1, i1 = bie2d.bie_mobility_solve(g, x, pre)
+    assert float((v1 - v0).abs().max() / v0.abs().max()) < 1e-9, (i0, i1)
+    assert i1["rel_residual"] < 1e-11 and 2 * i1["iters"] <= i0["iters"], (i0, i1)
+
+
 def test_precond_refused_where_it_does_not_apply():
     o = bie2d.default_opts(precond=bie2d.BIE_PRECOND_BLOCK)
-    c, FT = wl.mobility_ellipses(nbodies=4, n=128)
+    # 257 nodes: more than 256 unknowns and no divisor in [16, 64]
+    odd = bie2d.Geometry.from_curves(wl.two_discs(0.5, 257))
+    with pytest.raises(bie2d.BieError) as e:
+        bie2d.bie_elastance_solve(odd, dev([[1.0, -1.0]]), o)
+    assert e.value.code == bie2d.BIE_EINVAL and "divisor" in str(e.value)
+    big = bie2d.Geometry.from_curves(wl.two_discs(0.5, 4096))
+    with pytest.raises(bie2d.BieError) as e:
+        bie2d.bie_mobility_solve(big, dev([[1.0, 0.0, 0.0, -1.0, 0.0, 0.0]]), o)
+    assert e.value.code == bie2d.BIE_EINVAL and "2048" in str(e.value)
+    c, _ = wl.elastance_small()
     g = bie2d.Geometry.from_curves(c)
     with pytest.raises(bie2d.BieError) as e:
-        bie2d.bie_mobility_solve(g, dev(FT[None]), o)
-    assert e.value.code == bie2d.BIE_EINVAL and "Laplace" in str(e.value)
-    big = bie2d.Geometry.from_curves(wl.two_discs(0.5, 512))
-    with pytest.raises(bie2d.BieError) as e:
-        bie2d.bie_elastance_solve(big, dev([[1.0, -1.0]]), o)
-    assert e.value.code == bie2d.BIE_EINVAL and "256 nodes" in str(e.value)
+        bie2d.bie_capacitance_solve(g, dev(np.ones((1, g.N))), o)
+    assert e.value.code == bie2d.BIE_EINVAL and "elastance and mobility" in str(e.value)
