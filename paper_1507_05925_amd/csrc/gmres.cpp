@@ -201,15 +201,17 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
                              : ss.group_eta[q];
   while (cycles < max_cycles) {
     ++cycles;
-    if (first && x_is_zero) {
-      BIE_HIP_CHECK(hipMemcpyAsync(wk.r, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    // the first cycle from x = 0 starts from r = f, whose norms wk.nrm already holds
+    const bool from_f = first && x_is_zero;
+    if (from_f) {
+      beta = fnorm;
     } else {
       BIE_TRY(apply(ss, relaxed ? BIE_FP64 : precision, x, wk.r, st, s));
       BIE_TRY(vec_axpby(N, 1.0, f, -1.0, wk.r, s));
+      BIE_TRY(seg_nrm2(sg, wk.r, wk.nrm, wk.scratch, s));
+      BIE_TRY(read_host(mem, wk.nrm, S, beta, s));
     }
     first = false;
-    BIE_TRY(seg_nrm2(sg, wk.r, wk.nrm, wk.scratch, s));
-    BIE_TRY(read_host(mem, wk.nrm, S, beta, s));
     std::vector<int> active(S, 0);
     int nact = 0;
     for (int r = 0; r < S; ++r) {
@@ -224,10 +226,14 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       std::fprintf(stderr, "[bie] gmres prec=%d cycle start: iters=%d active=%d true rel res[0]=%.3e\n",
                    precision, st.iters, nact, relres[0]);
     if (nact == 0 || st.iters >= max_iter) break;
+    bool zeroed = false;  // the device norms change only where a converged system had one
     for (int r = 0; r < S; ++r)
-      if (!active[r]) beta[r] = 0.0;
-    BIE_TRY(write_dev(mem, wk.nrm, beta, s));
-    BIE_TRY(seg_scale_to(sg, wk.r, wk.nrm, wk.V, s));
+      if (!active[r]) {
+        zeroed = zeroed || beta[r] != 0.0;
+        beta[r] = 0.0;
+      }
+    if (zeroed) BIE_TRY(write_dev(mem, wk.nrm, beta, s));
+    BIE_TRY(seg_scale_to(sg, from_f ? f : wk.r, wk.nrm, wk.V, s));
     std::fill(gv.begin(), gv.end(), 0.0);
     for (int r = 0; r < S; ++r) gv[(size_t)r * (m + 1)] = beta[r];
     std::vector<int> jdone(S, -1);
@@ -435,7 +441,12 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
         yr[i] = d != 0.0 ? acc / d : 0.0;
       }
     }
-    BIE_TRY(write_dev(mem, wk.y, yv, s));
+    // y to the device: the stream is idle (synchronised above), so the pinned staging area is
+    // free; the host writes it again only after a later synchronisation
+    BIE_TRY(mem.ensure_pinned(yv.size() * sizeof(double)));
+    std::memcpy(mem.pinned, yv.data(), yv.size() * sizeof(double));
+    BIE_HIP_CHECK(hipMemcpyAsync(wk.y, mem.pinned, yv.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
     BIE_TRY(seg_combination(sg, nv, wk.V, N, wk.y, hs, x, 1.0, s));
   }
   return BIE_OK;
@@ -642,9 +653,7 @@ int solve_system(bie_geom *g, int kind, const bie_opts &o, int nrhs, const doubl
     };
     const int rc = solve_systems(ss, o, f, x, rel, info, s);
     if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
-    BIE_TRY(pc_apply(g, kind, nrhs, x, tmp, s));
-    BIE_HIP_CHECK(hipMemcpyAsync(x, tmp, (size_t)nrhs * n * sizeof(double),
-                                 hipMemcpyDeviceToDevice, s));
+    BIE_TRY(pc_apply(g, kind, nrhs, x, x, s));  // in place: each body is staged before written
     return rc;
   }
   if (!o.l2_scaling) {
