@@ -700,23 +700,34 @@ __device__ inline V eval_value(const V *b, V w) {
 constexpr double kSelfFloor = 1e-100;
 constexpr double kNearPad = 1e50;  // coordinates of a padding record
 
-// One step over the eight records rec (this lane's group).
+// One step over the eight records rec (this lane's group). The reciprocals of |r|^2 are formed
+// two at a time from one reciprocal of their product, 1/a = b / (ab) and 1/b = a / (ab): the
+// quarter-rate reciprocal is issued once per two pairs. |r|^2 lies in [kSelfFloor, about
+// 2 kNearPad^2], so ab stays within the float64 range.
 template <bool STOKES>
 __device__ __forceinline__ void near_step(const double4 *rec, double2 z, double2 nv, double &gx,
                                           double &gy) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const double dx = z.x - rec[u].x, dy = z.y - rec[u].y;
-    const double inv = rcp64(fmax(fma(dx, dx, dy * dy), kSelfFloor));
-    double t;
+  for (int u = 0; u < 8; u += 2) {
+    const double dx0 = z.x - rec[u].x, dy0 = z.y - rec[u].y;
+    const double dx1 = z.x - rec[u + 1].x, dy1 = z.y - rec[u + 1].y;
+    const double a = fmax(fma(dx0, dx0, dy0 * dy0), kSelfFloor);
+    const double b = fmax(fma(dx1, dx1, dy1 * dy1), kSelfFloor);
+    const double y = rcp64(a * b);
+    const double inv0 = b * y, inv1 = a * y;
+    double t0, t1;
     if (STOKES) {
-      const double rn = fma(dx, nv.x, dy * nv.y);
-      t = fma(dx, rec[u].z, dy * rec[u].w) * rn * (inv * inv);
+      const double rn0 = fma(dx0, nv.x, dy0 * nv.y), rn1 = fma(dx1, nv.x, dy1 * nv.y);
+      t0 = fma(dx0, rec[u].z, dy0 * rec[u].w) * rn0 * (inv0 * inv0);
+      t1 = fma(dx1, rec[u + 1].z, dy1 * rec[u + 1].w) * rn1 * (inv1 * inv1);
     } else {
-      t = rec[u].z * inv;
+      t0 = rec[u].z * inv0;
+      t1 = rec[u + 1].z * inv1;
     }
-    gx = fma(dx, t, gx);
-    gy = fma(dy, t, gy);
+    gx = fma(dx0, t0, gx);
+    gy = fma(dy0, t0, gy);
+    gx = fma(dx1, t1, gx);
+    gy = fma(dy1, t1, gy);
   }
 }
 
