@@ -686,8 +686,9 @@ def main():
         if pr["launches"] > 0:
             rl_m2ls[name] = roofline(pr, cm[0], cm[1], cm[2], bound=cm[3], kernel=cm[4])
             rl_m2ls[name]["kernel"] = cm[4]
-    # the preconditioner apply: exact int8 blocks here (256 unknowns per body), HBM-bound:
-    # one byte per entry (units: entries), a float64 scale per row, float64 in and out
+    # the preconditioner apply (two-grid blocks): algorithmic bytes = the float32 coarse
+    # inverses (U^2 entries per body, U = the coarse node count: n up to 64, else the largest
+    # divisor of n not above 64) and the float64 vector in and out
     rl_pre = None
     if pc != bie2d.BIE_PRECOND_NONE:
         bie2d.bie_profile_select([bie2d.BIE_K_PRECOND])
@@ -696,14 +697,14 @@ def main():
         pr = bie2d.bie_profile_read(bie2d.BIE_K_PRECOND)
         bie2d.bie_profile_enable(False)
         ms = pr["ms_total"] / max(pr["launches"], 1)
-        units = pr["pairs"] / max(pr["launches"], 1)
-        nbytes = units + 8.0 * g.M + 16.0 * g.M
+        coarse = lambda n: n if n <= 64 else max(d for d in range(16, 65) if n % d == 0)
+        nbytes = sum(4.0 * coarse(int(n)) ** 2 for n in curves.nodes_per_body) + 16.0 * g.M
         ach = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kern = "k_pc_apply_i8<256, 1>"
+        kern = "k_pc_apply<64, 256>"
         rl_pre = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
                   "frac": ach / 8000.0, "traffic": traffic_bytes(kern), "avg_launch_ms": ms,
-                  "launches": pr["launches"], "units_per_launch": units,
-                  "bytes_per_launch": nbytes, "kernel": kern}
+                  "launches": pr["launches"], "multiply_adds_per_launch": pr["pairs"] /
+                  max(pr["launches"], 1), "bytes_per_launch": nbytes, "kernel": kern}
     bie2d.bie_profile_select(None)
 
     # where a solve's time goes: the FMM applies of each precision timed on their own (events on

@@ -83,17 +83,15 @@ extern "C" {
 /* GMRES preconditioning (opts.precond). BIE_PRECOND_BLOCK: right preconditioning by an
  * approximate inverse of the operator's block diagonal, one block per body (its self
  * interactions: identity, diagonal limit, same-body double-layer pairs, completion), built once
- * per geometry and kind on the device. Bodies of at most 256 unknowns (nodes for Laplace, twice
- * the nodes for Stokes) when every body has at most 256: the exact block inverses (float32
- * Gauss-Jordan), kept less the exact 2 I as int8 with a float64 scale per row. Otherwise two-grid
- * blocks: the inverse's smooth part formed on a coarse grid of each curve (n itself up to 64
- * nodes, else the largest divisor of n in [16, 64]) with trigonometric restriction and
- * interpolation. The solution is that of the unpreconditioned system (the stopping tests use
- * true float64 residuals of A x = f); the iteration count falls when the bodies interact
- * weakly (34 -> 12 steps for 1000 starfish at gap >= 0.3, 64 -> 18 for 200 ellipses at gap >=
- * 0.2). Single-geometry elastance and mobility solves and matrices; BIE_EINVAL for the
- * capacitance and resistance solves, batches and the server, with l2_scaling, and for a body of
- * more than 2048 nodes or with no such divisor. */
+ * per geometry and kind on the device. A block's inverse is 2 I plus a smooth part, formed on a
+ * coarse grid of the curve (n itself up to 64 nodes, exact; else every s-th node, n / s the
+ * largest divisor of n in [16, 64]) with full-weighting restriction and linear interpolation;
+ * the coarse blocks are inverted in float32 and applied in float64. The solution is that of the
+ * unpreconditioned system (the stopping tests use true float64 residuals of A x = f); the
+ * iteration count falls when the bodies interact weakly (37 -> 12 steps for 1000 starfish at
+ * gap >= 0.3, 64 -> 18 for 200 ellipses at gap >= 0.2). Single-geometry elastance and mobility
+ * solves and matrices; BIE_EINVAL for the capacitance and resistance solves, batches and the
+ * server, with l2_scaling, and for a body of more than 2048 nodes or with no such divisor. */
 #define BIE_PRECOND_NONE 0
 #define BIE_PRECOND_BLOCK 1
 

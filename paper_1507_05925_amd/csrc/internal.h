@@ -199,15 +199,13 @@ struct bie_geom {
   int fmm_leaf = 64;   // maximum nodes per leaf box
   int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
   // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
-  // block preconditioner per kind (precond.hip): exact blocks as int8 words and row scales
-  // (q), or inverted coarse blocks [N][BJ][BJ] (float32, column-major, inv); per body the
-  // coarse node count and the offset of its transfer table
+  // block preconditioner per kind (precond.hip): inverted coarse blocks [N][BJ][BJ] (float32,
+  // column-major, inv); per body the coarse node count (meta)
   struct Precond {
-    bie::DevBuf inv, q, meta;
-    bool ready = false, exact = false;
+    bie::DevBuf inv, meta;
+    bool ready = false;
     int BJ = 0;
-    int *ncoarse = nullptr, *rho_off = nullptr;
-    double *rho = nullptr;
+    int *ncoarse = nullptr;
     long long macs = 0;  // multiply-adds per apply and right-hand side
     size_t lds = 0;      // dynamic LDS of the apply
   } pc[2];

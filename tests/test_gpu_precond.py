@@ -1,8 +1,8 @@
-"""GPU: the block right preconditioner (opts.precond = BIE_PRECOND_BLOCK; exact int8 blocks up to
-256 unknowns per body, two-grid blocks beyond) leaves the solution unchanged (against the float64 oracle and
-against the unpreconditioned solves), for elastance and mobility, and cuts the GMRES steps on
-multi-body problems; it is refused where it does not apply (bodies it cannot coarsen, the
-capacitance and resistance solves)."""
+"""GPU: the block right preconditioner (opts.precond = BIE_PRECOND_BLOCK; exact blocks for bodies
+of at most 64 nodes, two-grid blocks beyond) leaves the solution unchanged (against the float64
+oracle and against the unpreconditioned solves), for elastance and mobility, and cuts the GMRES
+steps on multi-body problems; it is refused where it does not apply (bodies it cannot coarsen,
+the capacitance and resistance solves)."""
 import numpy as np
 import pytest
 
@@ -44,8 +44,7 @@ def test_precond_small_vs_oracle(precision, tol):
 @pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
 @pytest.mark.parametrize("n", [48, 192])
 def test_precond_mobility_small_vs_oracle(precision, tol, n):
-    """Four ellipses: exact int8 blocks (48 nodes, 96 unknowns each) and two-grid blocks (192
-    nodes, 64 coarse)."""
+    """Four ellipses: exact blocks (48 nodes) and two-grid blocks (192 nodes, 64 coarse)."""
     c, FT = wl.mobility_ellipses(nbodies=4, n=n)
     g = bie2d.Geometry.from_curves(c)
     geo = ny.geometry_of(c)
@@ -62,8 +61,7 @@ def test_precond_mobility_small_vs_oracle(precision, tol, n):
 
 @pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
 def test_precond_elastance_two_grid_vs_oracle(precision, tol):
-    """Six starfish of 320 nodes: more than 256 unknowns per body, so two-grid blocks (64
-    coarse nodes)."""
+    """Six starfish of 320 nodes: two-grid blocks on 64 coarse nodes (every fifth)."""
     c, q = wl.elastance_starfish(nbodies=6, n=320)
     g = bie2d.Geometry.from_curves(c)
     geo = ny.geometry_of(c)
@@ -81,9 +79,9 @@ def test_precond_elastance_two_grid_vs_oracle(precision, tol):
 
 @pytest.mark.parametrize("method", [bie2d.BIE_DIRECT, bie2d.BIE_FMM])
 def test_precond_same_solution_fewer_steps(method):
-    """100 starfish of 256 nodes (gap >= 0.3; exact int8 blocks): the same potentials as without
-    the preconditioner, in at most half the GMRES steps (34 -> 11 measured with exact blocks and
-    the oracle)."""
+    """100 starfish of 256 nodes (gap >= 0.3; two-grid blocks on 64 nodes): the same potentials
+    as without the preconditioner, in at most half the GMRES steps (34 -> 11 measured with exact
+    blocks and the oracle)."""
     c, q = wl.elastance_starfish(nbodies=100)
     g = bie2d.Geometry.from_curves(c)
     qd = dev(q[None])
@@ -118,7 +116,7 @@ def test_precond_mobility_fewer_steps(method):
 
 def test_precond_refused_where_it_does_not_apply():
     o = bie2d.default_opts(precond=bie2d.BIE_PRECOND_BLOCK)
-    # 257 nodes: more than 256 unknowns and no divisor in [16, 64]
+    # 257 nodes: more than 64 and no divisor in [16, 64]
     odd = bie2d.Geometry.from_curves(wl.two_discs(0.5, 257))
     with pytest.raises(bie2d.BieError) as e:
         bie2d.bie_elastance_solve(odd, dev([[1.0, -1.0]]), o)
