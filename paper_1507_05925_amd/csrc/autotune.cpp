@@ -38,14 +38,14 @@ std::tuple<int, int, int, int, int> shape_class(const bie_geom *g, int kind, int
 }
 
 // Average time of `reps` applies of the precision's operator with leaf size `leaf` (ms), after
-// one untimed apply that builds the tree.
+// one untimed apply (which builds the tree the first time).
 int time_leaf(bie_geom *g, int kind, int precision, int R, int leaf, const double *mu,
               double *out, hipStream_t s, double &ms) {
   const int keep = g->fmm_leaf, keepm = g->fmm_leaf_mixed;
   if (precision == BIE_MIXED) g->fmm_leaf_mixed = leaf; else g->fmm_leaf = leaf;
   int rc = apply_operator(g, kind, precision, BIE_FMM, 1, 1.0, R, mu, out, s);
   hipEvent_t a = nullptr, b = nullptr;
-  constexpr int reps = 4;
+  constexpr int reps = 3;
   if (rc == BIE_OK && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) {
     set_error("autotune: event creation failed");
     rc = BIE_EDEVICE;
@@ -78,21 +78,30 @@ int tune_one(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s, int 
                    hipStreamSynchronize(s) == hipSuccess
                ? BIE_OK
                : BIE_EDEVICE;
-  double best_ms = 1e300;
   best = 64;
   const int current = precision == BIE_MIXED && g->fmm_leaf_mixed > 0 ? g->fmm_leaf_mixed
                                                                        : g->fmm_leaf;
-  for (int leaf : kCandidates) {
-    if (rc != BIE_OK) break;
-    if (leaf * 4 > g->M) continue;  // a tree of a handful of leaves: not a candidate
-    double ms = 0.0;
-    rc = time_leaf(g, kind, precision, R, leaf, mu, out, s, ms);
-    if (rc != BIE_OK) break;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = leaf;
+  // kRounds passes over the candidates, each candidate keeping its fastest pass: neighbouring
+  // candidates often differ by a few percent, less than the spread of a single timing
+  constexpr int kRounds = 3;
+  constexpr int nc = sizeof(kCandidates) / sizeof(kCandidates[0]);
+  double cand_ms[nc];
+  for (int i = 0; i < nc; ++i) cand_ms[i] = 1e300;
+  for (int round = 0; round < kRounds && rc == BIE_OK; ++round)
+    for (int i = 0; i < nc; ++i) {
+      const int leaf = kCandidates[i];
+      if (leaf * 4 > g->M) continue;  // a tree of a handful of leaves: not a candidate
+      double ms = 0.0;
+      rc = time_leaf(g, kind, precision, R, leaf, mu, out, s, ms);
+      if (rc != BIE_OK) break;
+      cand_ms[i] = std::min(cand_ms[i], ms);
     }
-  }
+  double best_ms = 1e300;
+  for (int i = 0; i < nc; ++i)
+    if (cand_ms[i] < best_ms) {
+      best_ms = cand_ms[i];
+      best = kCandidates[i];
+    }
   // the losers' trees are freed (each holds its own work area)
   for (int leaf : kCandidates)
     if (leaf != best && leaf != current) fmm_drop_tree(g, precision, g->fmm_order, leaf);
