@@ -89,9 +89,10 @@ extern "C" {
  * the coarse blocks are inverted in float32 and applied in float64. The solution is that of the
  * unpreconditioned system (the stopping tests use true float64 residuals of A x = f); the
  * iteration count falls when the bodies interact weakly (37 -> 12 steps for 1000 starfish at
- * gap >= 0.3, 64 -> 18 for 200 ellipses at gap >= 0.2). Single-geometry elastance and mobility
- * solves and matrices; BIE_EINVAL for the capacitance and resistance solves, batches and the
- * server, with l2_scaling, and for a body of more than 2048 nodes or with no such divisor. */
+ * gap >= 0.3, 64 -> 18 for 200 ellipses at gap >= 0.2). Elastance and mobility solves,
+ * matrices and batches (one launch applies every item's blocks); BIE_EINVAL for the capacitance
+ * and resistance solves and the server, with l2_scaling, and for a body of more than 2048 nodes
+ * or with no such divisor. */
 #define BIE_PRECOND_NONE 0
 #define BIE_PRECOND_BLOCK 1
 

@@ -12,7 +12,8 @@
 struct bie_batch {
   bie::SolverMem sm;
   bie::Segments seg;
-  bie::DevBuf flat;  // incident densities, rhs, solutions [Ntot] each
+  bie::DevBuf flat;  // incident densities, rhs, solutions [Ntot] each (and P u, preconditioned)
+  bie::DevBuf pcitems;  // the batched preconditioner's item descriptors
   bie::DevBuf ident; // identity blocks
   bie::MultiPlan *plan = nullptr;
 };
@@ -69,10 +70,6 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   bie_opts o;
   if (opts) o = *opts; else bie_default_opts(&o);
   BIE_TRY(check_opts(o));
-  if (o.precond != BIE_PRECOND_NONE) {
-    set_error("bie_batch_solve: precond is supported by the single-geometry elastance solves only");
-    return BIE_EINVAL;
-  }
   if (o.l2_scaling) {
     set_error("bie_batch_solve: l2_scaling is supported by the single-geometry solves only");
     return BIE_EINVAL;
@@ -107,8 +104,10 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   }
   const long long Ntot = item_off[nitems];
   BIE_TRY(b->seg.build(lens, s, &starts));
-  BIE_TRY(b->flat.reserve(3 * (size_t)Ntot * sizeof(double)));
+  const bool pcb = o.precond == BIE_PRECOND_BLOCK;
+  BIE_TRY(b->flat.reserve((pcb ? 4 : 3) * (size_t)Ntot * sizeof(double)));
   double *dens = b->flat.as<double>(), *f = dens + Ntot, *mu = f + Ntot;
+  double *ptmp = pcb ? mu + Ntot : nullptr;  // P u, the operator's input, when preconditioned
   if (in_off[nitems] > 0) BIE_TRY(b->ident.reserve((size_t)in_off[nitems] * sizeof(double)));
   // incident densities and right-hand sides, per item
   for (int i = 0; i < nitems; ++i) {
@@ -143,10 +142,38 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   for (int i = 0; i < nitems; ++i)
     ss.group_eta.push_back(
         mixed_apply_error(items[i].g, items[i].kind, o.method, effective_order(o, items[i].kind)));
+  // right preconditioning (GMRES on (A P) u = f, x = P u): every item's geometry's blocks, one
+  // batched launch per apply
+  size_t pc_lds = 0;
+  long long pc_blocks = 0, pc_macs = 0;
+  const PcBatchItem *pc_items = nullptr;
+  if (pcb) {
+    std::vector<bie_geom *> gs(nitems);
+    std::vector<int> kinds(nitems), nr(nitems);
+    std::vector<long long> offs(nitems);
+    for (int i = 0; i < nitems; ++i) {
+      BIE_TRY(pc_build(items[i].g, items[i].kind, s));
+      gs[i] = items[i].g;
+      kinds[i] = items[i].kind;
+      nr[i] = items[i].nrhs;
+      offs[i] = item_off[i];
+    }
+    std::vector<PcBatchItem> pit;
+    BIE_TRY(pc_batch_items(gs, kinds, nr, offs, pit, pc_lds, pc_blocks, pc_macs));
+    BIE_TRY(b->pcitems.reserve(pit.size() * sizeof(PcBatchItem)));
+    BIE_HIP_CHECK(hipMemcpyAsync(b->pcitems.ptr, pit.data(), pit.size() * sizeof(PcBatchItem),
+                                 hipMemcpyHostToDevice, s));
+    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the host descriptors go out of scope
+    pc_items = reinterpret_cast<const PcBatchItem *>(b->pcitems.ptr);
+  }
   SysSet *ssp = &ss;
   MultiPlan **plan = &b->plan;
-  ss.apply = [ssp, plan, mitems, first_sys, Ntot](int precision, const double *in, double *out,
-                                                  hipStream_t st) {
+  ss.apply = [ssp, plan, mitems, first_sys, Ntot, pc_items, pc_lds, pc_blocks, pc_macs, ptmp,
+              nitems](int precision, const double *in, double *out, hipStream_t st) {
+    if (pc_items) {
+      BIE_TRY(pc_apply_batch(nitems, pc_items, pc_lds, pc_blocks, pc_macs, in, ptmp, st));
+      in = ptmp;
+    }
     // an item is applied when any of its systems is still active
     std::vector<char> act(mitems.size(), 1);
     if (!ssp->active.empty())
@@ -163,6 +190,8 @@ int bie_batch_solve(bie_batch *b, int nitems, const bie_batch_item *items, const
   bie_info inf{};
   int rc = solve_systems(ss, o, f, mu, rel, &inf, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
+  if (pc_items)  // x = P u, in place (each body is staged before it is written)
+    BIE_TRY(pc_apply_batch(nitems, pc_items, pc_lds, pc_blocks, pc_macs, mu, mu, s));
   BIE_TRY(vec_axpby(Ntot, 1.0, mu, 1.0, dens, s));
   for (int i = 0; i < nitems; ++i) {
     BIE_TRY(read_off(items[i].g, items[i].kind, items[i].nrhs, dens + item_off[i], items[i].out, s,

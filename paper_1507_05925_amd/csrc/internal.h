@@ -325,6 +325,20 @@ int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, 
 // (BIE_EINVAL for a body it cannot coarsen); apply out = P in, [nrhs][M] resp. [nrhs][2M].
 int pc_build(bie_geom *g, int kind, hipStream_t s);
 int pc_apply(bie_geom *g, int kind, int nrhs, const double *in, double *out, hipStream_t s);
+// Batched apply over geometries whose preconditioners are built: per item its geometry's data,
+// the item's offset in the flat vector and its first workgroup (prefix of N nrhs).
+struct PcBatchItem {
+  const int *body_ptr, *ncoarse;
+  const float *inv;
+  long long off;
+  int BJ, N, M, kind, nrhs, block0;
+};
+int pc_batch_items(const std::vector<bie_geom *> &geoms, const std::vector<int> &kinds,
+                   const std::vector<int> &nrhs, const std::vector<long long> &offs,
+                   std::vector<PcBatchItem> &items, size_t &lds, long long &blocks,
+                   long long &macs);
+int pc_apply_batch(int nitems, const PcBatchItem *d_items, size_t lds, long long blocks,
+                   long long macs, const double *in, double *out, hipStream_t s);
 
 // Expansion length (terms, a multiple of 8) the FMM apply of `precision` uses for an order.
 int fmm_length(int order, int precision);

@@ -129,23 +129,19 @@ __global__ __launch_bounds__(BJ *(BJ / kPcRows)) void k_pc_invert(int kind,
     *reinterpret_cast<float4 *>(o + e) = make_float4(a[e], a[e + 1], a[e + 2], a[e + 3]);
 }
 
-// out = P in for one body and right-hand side per workgroup (grid (N, nrhs), NT threads), the
-// body's values staged in LDS in their node-major order. Coarse node j is fine node j s; the
-// restriction is full weighting, w_j = sum_{|d| < s} (1 - |d| / s) v_{j s + d} / s (indices
-// mod n), the interpolation linear, (E y)_i = (1 - t) y_{i / s} + t y_{i / s + 1} with
-// t = (i mod s) / s; then y = B^-1 w (the sum over k cut into `parts` ranges whose partial sums
-// are added in range order) and out = 2 v + E (y - 2 w); with s = 1, out = B^-1 v. Dynamic LDS:
-// C n doubles.
-template <int BJ, int NT>
-__global__ __launch_bounds__(NT) void k_pc_apply(int kind, int M,
-                                                 const int *__restrict__ body_ptr,
-                                                 const int *__restrict__ ncoarse,
-                                                 const float *__restrict__ inv,
-                                                 const double *__restrict__ in,
-                                                 double *__restrict__ out) {
-  extern __shared__ double vs[];
-  __shared__ double wv[2 * kPcNodes], yv[2 * kPcNodes], part[NT];
-  const int b = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
+// out = P in for body b of one geometry and right-hand side r (in and out point at the
+// geometry's [nrhs][C M] block), by one workgroup of NT threads, the body's values staged in LDS
+// (vs, C n doubles) in their node-major order. Coarse node j is fine node j s; the restriction is
+// full weighting, w_j = sum_{|d| < s} (1 - |d| / s) v_{j s + d} / s (indices mod n), the
+// interpolation linear, (E y)_i = (1 - t) y_{i / s} + t y_{i / s + 1} with t = (i mod s) / s;
+// then y = B^-1 w (the sum over k cut into `parts` ranges whose partial sums are added in range
+// order) and out = 2 v + E (y - 2 w); with s = 1, out = B^-1 v.
+template <int NT>
+__device__ void pc_body(int kind, int M, int b, int r, const int *__restrict__ body_ptr,
+                        const int *__restrict__ ncoarse, const float *__restrict__ inv, int BJ,
+                        const double *__restrict__ in, double *__restrict__ out, double *vs,
+                        double *wv, double *yv, double *part) {
+  const int t = threadIdx.x;
   const int off = body_ptr[b], n = body_ptr[b + 1] - off, nc = ncoarse[b], s = n / nc;
   const int C = kind == 0 ? 1 : 2, U = C * nc, F = C * n;
   const double *vin = in + (size_t)r * C * M + (size_t)C * off;
@@ -197,6 +193,43 @@ __global__ __launch_bounds__(NT) void k_pc_apply(int kind, int M,
     const double tt = (double)(i - j0 * s) * is;
     vout[e] = fma(tt, yv[C * j1 + a], fma(1.0 - tt, yv[C * j0 + a], 2.0 * vs[e]));
   }
+}
+
+// One geometry: grid (N, nrhs). Dynamic LDS: C n_max doubles.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pc_apply(int kind, int M, int BJ,
+                                                 const int *__restrict__ body_ptr,
+                                                 const int *__restrict__ ncoarse,
+                                                 const float *__restrict__ inv,
+                                                 const double *__restrict__ in,
+                                                 double *__restrict__ out) {
+  extern __shared__ double vs[];
+  __shared__ double wv[2 * kPcNodes], yv[2 * kPcNodes], part[NT];
+  pc_body<NT>(kind, M, blockIdx.x, blockIdx.y, body_ptr, ncoarse, inv, BJ, in, out, vs, wv, yv,
+              part);
+}
+
+// A batch of geometries in one launch: workgroup w belongs to the item i with
+// items[i].block0 <= w < items[i + 1].block0 (binary search), and takes its body
+// (w - block0) mod N and right-hand side (w - block0) / N. Dynamic LDS: C n_max doubles over the
+// items.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pc_apply_batch(int nitems,
+                                                       const PcBatchItem *__restrict__ items,
+                                                       const double *__restrict__ in,
+                                                       double *__restrict__ out) {
+  extern __shared__ double vs[];
+  __shared__ double wv[2 * kPcNodes], yv[2 * kPcNodes], part[NT];
+  const int w = blockIdx.x;
+  int lo = 0, hi = nitems - 1;  // the last item whose block0 <= w
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (items[mid].block0 <= w) lo = mid; else hi = mid - 1;
+  }
+  const PcBatchItem it = items[lo];
+  const int local = w - it.block0;
+  pc_body<NT>(it.kind, it.M, local % it.N, local / it.N, it.body_ptr, it.ncoarse, it.inv, it.BJ,
+              in + it.off, out + it.off, vs, wv, yv, part);
 }
 
 // Coarse node count of a body of n nodes: n itself up to kPcNodes, else the largest divisor of
@@ -269,19 +302,6 @@ int pc_build(bie_geom *g, int kind, hipStream_t s) {
 
 namespace {
 
-template <int BJ>
-void launch_two_grid(const bie_geom *g, const bie_geom::Precond &pc, int kind, int nrhs,
-                     const double *in, double *out, hipStream_t s) {
-  // few bodies: 1024 threads per body shorten each one's sums; many: 256 threads, more
-  // workgroups per compute unit
-  if (g->N < 512)
-    hipLaunchKernelGGL((k_pc_apply<BJ, 1024>), dim3(g->N, nrhs), dim3(1024), pc.lds, s, kind,
-                       g->M, g->body_ptr, pc.ncoarse, pc.inv.as<float>(), in, out);
-  else
-    hipLaunchKernelGGL((k_pc_apply<BJ, 256>), dim3(g->N, nrhs), dim3(256), pc.lds, s, kind, g->M,
-                       g->body_ptr, pc.ncoarse, pc.inv.as<float>(), in, out);
-}
-
 }  // namespace
 
 int pc_apply(bie_geom *g, int kind, int nrhs, const double *in, double *out, hipStream_t s) {
@@ -292,8 +312,51 @@ int pc_apply(bie_geom *g, int kind, int nrhs, const double *in, double *out, hip
   }
   // units: multiply-adds (restriction, coarse product and interpolation) per right-hand side
   ProfScope prof(BIE_K_PRECOND, s, pc.macs * nrhs);
-  if (pc.BJ == 64) launch_two_grid<64>(g, pc, kind, nrhs, in, out, s);
-  else launch_two_grid<128>(g, pc, kind, nrhs, in, out, s);
+  // few bodies: 1024 threads per body shorten each one's sums; many: 256 threads, more
+  // workgroups per compute unit
+  if (g->N < 512)
+    hipLaunchKernelGGL(k_pc_apply<1024>, dim3(g->N, nrhs), dim3(1024), pc.lds, s, kind, g->M,
+                       pc.BJ, g->body_ptr, pc.ncoarse, pc.inv.as<float>(), in, out);
+  else
+    hipLaunchKernelGGL(k_pc_apply<256>, dim3(g->N, nrhs), dim3(256), pc.lds, s, kind, g->M,
+                       pc.BJ, g->body_ptr, pc.ncoarse, pc.inv.as<float>(), in, out);
+  BIE_HIP_CHECK(hipGetLastError());
+  return BIE_OK;
+}
+
+int pc_batch_items(const std::vector<bie_geom *> &geoms, const std::vector<int> &kinds,
+                   const std::vector<int> &nrhs, const std::vector<long long> &offs,
+                   std::vector<PcBatchItem> &items, size_t &lds, long long &blocks,
+                   long long &macs) {
+  items.clear();
+  lds = 0;
+  blocks = 0;
+  macs = 0;
+  for (size_t i = 0; i < geoms.size(); ++i) {
+    const bie_geom::Precond &pc = geoms[i]->pc[kinds[i] & 1];
+    if (!pc.ready) {
+      set_error("block preconditioner not built");
+      return BIE_EINVAL;
+    }
+    if (blocks + (long long)geoms[i]->N * nrhs[i] > (1LL << 31) - 1) {
+      set_error("batched preconditioner: more than 2^31 - 1 (body, right-hand side) pairs");
+      return BIE_EINVAL;
+    }
+    items.push_back(PcBatchItem{geoms[i]->body_ptr, pc.ncoarse, pc.inv.as<float>(), offs[i],
+                                pc.BJ, geoms[i]->N, geoms[i]->M, kinds[i], nrhs[i], (int)blocks});
+    blocks += (long long)geoms[i]->N * nrhs[i];
+    lds = std::max(lds, pc.lds);
+    macs += pc.macs * nrhs[i];
+  }
+  return BIE_OK;
+}
+
+int pc_apply_batch(int nitems, const PcBatchItem *d_items, size_t lds, long long blocks,
+                   long long macs, const double *in, double *out, hipStream_t s) {
+  ProfScope prof(BIE_K_PRECOND, s, macs);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_pc_apply_batch<256>, dim3((unsigned)blocks), dim3(256), lds, s, nitems,
+                       d_items, in, out);
   BIE_HIP_CHECK(hipGetLastError());
   return BIE_OK;
 }

@@ -416,7 +416,7 @@ int bie_server_create(const bie_server_config *cfg, bie_server **out) {
     return BIE_EINVAL;
   }
   if (cfg->opts.precond != BIE_PRECOND_NONE) {
-    set_error("bie_server_create: precond is supported by the single-geometry elastance solves only");
+    set_error("bie_server_create: precond is supported by the solves, matrices and batches, not the server");
     return BIE_EINVAL;
   }
   if (cfg->opts.l2_scaling) {

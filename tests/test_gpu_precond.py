@@ -130,3 +130,59 @@ def test_precond_refused_where_it_does_not_apply():
     with pytest.raises(bie2d.BieError) as e:
         bie2d.bie_capacitance_solve(g, dev(np.ones((1, g.N))), o)
     assert e.value.code == bie2d.BIE_EINVAL and "elastance and mobility" in str(e.value)
+
+
+def precond_batch():
+    """Geometries whose every body the preconditioner takes (node counts with a divisor in
+    [16, 64] past 64 nodes): exact blocks, two-grid blocks and a mix of both."""
+    rng = np.random.default_rng(23)
+    return [("elastance", wl.elastance_small()[0]),
+            ("mobility", wl.mixed_grid(rng, 5, np.array([64, 96, 32, 130, 256]))),
+            ("elastance", wl.splash(128)),
+            ("mobility", wl.two_discs(0.5, 96)),
+            ("elastance", wl.mixed_grid(rng, 9, np.full(9, 64)))]
+
+
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_precond_batch_matrices_vs_oracle(precision, tol):
+    items, refs = [], []
+    for kind, c in precond_batch():
+        geo = ny.geometry_of(c)
+        items.append((bie2d.Geometry.from_curves(c), 0 if kind == "elastance" else 1, None))
+        refs.append(ny.elastance_matrix(geo) if kind == "elastance" else ny.mobility_matrix(geo))
+    o = bie2d.default_opts(precision=precision, tol=1e-12, restart=120, max_iter=3000,
+                           precond=bie2d.BIE_PRECOND_BLOCK)
+    outs, info, rel = bie2d.bie_batch_solve(bie2d.Batch(), items, o)
+    for out, r in zip(outs, refs):
+        assert rel_err(out, r) < tol, info
+    assert (rel <= 1e-12).all()
+    base = bie2d.default_opts(precision=precision, tol=1e-12, restart=120, max_iter=3000)
+    _, info0, _ = bie2d.bie_batch_solve(bie2d.Batch(), items, base)
+    assert info["iters"] < info0["iters"], (info, info0)
+
+
+def rel_err(a, b):
+    return float(np.abs(a.cpu().numpy() - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_precond_batch_alone_and_in_the_mix(precision):
+    """Each item's preconditioned result is bitwise the same alone and in the mix, and equals
+    the single-geometry preconditioned solve to rounding."""
+    rng = np.random.default_rng(24)
+    items = []
+    for kind, c in precond_batch():
+        g = bie2d.Geometry.from_curves(c)
+        k = 0 if kind == "elastance" else 1
+        width = g.N if k == 0 else 3 * g.N
+        items.append((g, k, dev(rng.standard_normal((int(rng.integers(1, 4)), width)))))
+    o = bie2d.default_opts(precision=precision, tol=1e-12, restart=120, max_iter=3000,
+                           precond=bie2d.BIE_PRECOND_BLOCK)
+    b = bie2d.Batch()
+    mix, _, _ = bie2d.bie_batch_solve(b, items, o)
+    for it, m in zip(items, mix):
+        alone, _, _ = bie2d.bie_batch_solve(b, [it], o)
+        assert torch.equal(alone[0], m)
+    g, k, inp = items[1]
+    vw, _ = bie2d.bie_mobility_solve(g, inp, o)
+    assert float((vw - mix[1]).abs().max() / vw.abs().max()) < 1e-10
