@@ -90,9 +90,9 @@ extern "C" {
  * unpreconditioned system (the stopping tests use true float64 residuals of A x = f); the
  * iteration count falls when the bodies interact weakly (37 -> 12 steps for 1000 starfish at
  * gap >= 0.3, 64 -> 18 for 200 ellipses at gap >= 0.2). Elastance and mobility solves,
- * matrices and batches (one launch applies every item's blocks); BIE_EINVAL for the capacitance
- * and resistance solves and the server, with l2_scaling, and for a body of more than 2048 nodes
- * or with no such divisor. */
+ * matrices, batches and the server (one launch applies every item's blocks); BIE_EINVAL for the
+ * capacitance and resistance solves, with l2_scaling, and for a body of more than 2048 nodes or
+ * with no such divisor (a server request on such a geometry fails with it). */
 #define BIE_PRECOND_NONE 0
 #define BIE_PRECOND_BLOCK 1
 

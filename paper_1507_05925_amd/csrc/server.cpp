@@ -63,6 +63,7 @@ struct bie_server {
   bie::Segments seg;
   bie::SolverMem sm;
   bie::DevBuf flat;  // F, X, R, D [Ntot] each
+  bie::DevBuf pcitems;  // the block preconditioner's item descriptors of a cycle
   bie::MultiPlan *plan = nullptr;
   void run();
   int cycle();
@@ -91,9 +92,15 @@ long long footprint(const bie_server_config &c, bie_geom *g, int kind, int nrhs)
 // the FMM tree and work area of the orders the solve uses, and the far-field partial sums of
 // the geometry's own apply workspace.
 long long geom_footprint(const bie_server_config &c, const bie_geom *g, int kind) {
-  if (!uses_fmm(c.opts, g)) return 0;
+  // the block preconditioner's coarse inverses (float32, padded to 64 x 64 Laplace, 128 x 128
+  // Stokes, per body) and node counts
+  const long long pc = c.opts.precond == BIE_PRECOND_BLOCK
+                           ? (long long)g->N * ((kind == 0 ? 64LL * 64 : 128LL * 128) * 4 + 4)
+                           : 0;
+  if (!uses_fmm(c.opts, g)) return pc;
   const long long len = kind == 0 ? g->M : 2LL * g->M;
-  return fmm_state_bytes(g, kind, c.opts.precision, effective_order(c.opts, kind), c.opts.fmm_leaf) +
+  return pc + fmm_state_bytes(g, kind, c.opts.precision, effective_order(c.opts, kind),
+                              c.opts.fmm_leaf) +
          8LL * (kind == 0 ? 8 : 4) * len;
 }
 
@@ -110,6 +117,7 @@ int prepare(Request &r, const bie_opts &o, hipStream_t s) {
   r.g->fmm_order = effective_order(o, r.kind);
   // fmm_leaf 0 serves with 64 nodes per leaf: timing leaf sizes would pause the other requests
   BIE_TRY(resolve_leaf(r.g, r.kind, o, r.nrhs, false, s));
+  if (o.precond == BIE_PRECOND_BLOCK) BIE_TRY(pc_build(r.g, r.kind, s));  // once per geometry
   // stage the input in the result buffer, then incident density and rhs f = -(1/2 I + K) inc
   BIE_HIP_CHECK(hipMemcpyAsync(r.res, r.in.data(), r.in.size() * sizeof(double),
                                hipMemcpyHostToDevice, s));
@@ -318,6 +326,30 @@ int bie_server::cycle() {
                                  sizeof(double) * active[i]->nrhs * active[i]->n,
                                  hipMemcpyDeviceToDevice, s));
   BIE_TRY(seg.build(lens2, s, &starts2));
+  // right preconditioning of the cycle: GMRES on (A P) u = r, then d = P u (R, no longer read
+  // this cycle, holds P u); one launch applies every item's blocks
+  const PcBatchItem *pc_items = nullptr;
+  size_t pc_lds = 0;
+  long long pc_blocks = 0, pc_macs = 0;
+  const int pc_n = (int)L2.items.size();
+  if (o.precond == BIE_PRECOND_BLOCK) {
+    std::vector<bie_geom *> gs;
+    std::vector<int> kinds, nr;
+    std::vector<long long> offs;
+    for (const MultiItem &it : L2.items) {
+      gs.push_back(it.g);
+      kinds.push_back(it.kind);
+      nr.push_back(it.nrhs);
+      offs.push_back(it.io);
+    }
+    std::vector<PcBatchItem> pit;
+    BIE_TRY(pc_batch_items(gs, kinds, nr, offs, pit, pc_lds, pc_blocks, pc_macs));
+    BIE_TRY(pcitems.reserve(pit.size() * sizeof(PcBatchItem)));
+    BIE_HIP_CHECK(hipMemcpyAsync(pcitems.ptr, pit.data(), pit.size() * sizeof(PcBatchItem),
+                                 hipMemcpyHostToDevice, s));
+    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the host descriptors go out of scope
+    pc_items = reinterpret_cast<const PcBatchItem *>(pcitems.ptr);
+  }
   {
     const std::vector<MultiItem> mi = L2.items;
     // systems of item k: those of requests L2.first[k] .. L2.first[k+1]-1
@@ -327,8 +359,13 @@ int bie_server::cycle() {
     for (size_t q = 0; q <= mi.size(); ++q) first[q] = sys0[L2.first[q]];
     SysSet *ssp = &ss;
     const long long N2 = L2.total;
-    ss.apply = [mi, planp, N2, first, ssp](int precision, const double *in, double *out,
-                                           hipStream_t st) {
+    double *pu = R;
+    ss.apply = [mi, planp, N2, first, ssp, pc_items, pc_n, pc_lds, pc_blocks, pc_macs, pu](
+                   int precision, const double *in, double *out, hipStream_t st) {
+      if (pc_items) {
+        BIE_TRY(pc_apply_batch(pc_n, pc_items, pc_lds, pc_blocks, pc_macs, in, pu, st));
+        in = pu;
+      }
       std::vector<char> act(mi.size(), 1);
       if (!ssp->active.empty())
         for (size_t i = 0; i < mi.size(); ++i) {
@@ -341,6 +378,8 @@ int bie_server::cycle() {
   }
   int iters = 0, applies = 0;
   BIE_TRY(gmres_cycle(ss, o.precision, T, D, itol, m, iters, applies, s));
+  if (pc_items)  // d = P u, in place (each body is staged before it is written)
+    BIE_TRY(pc_apply_batch(pc_n, pc_items, pc_lds, pc_blocks, pc_macs, D, D, s));
   for (size_t i = 0; i < active.size(); ++i) {
     BIE_TRY(vec_axpby((long long)active[i]->nrhs * active[i]->n, 1.0, D + off2[i], 1.0,
                       active[i]->x, s));
@@ -413,10 +452,6 @@ int bie_server_create(const bie_server_config *cfg, bie_server **out) {
   }
   if (cfg->max_cycles < 1 || check_opts(cfg->opts) != BIE_OK) {
     set_error("bie_server_create: invalid configuration");
-    return BIE_EINVAL;
-  }
-  if (cfg->opts.precond != BIE_PRECOND_NONE) {
-    set_error("bie_server_create: precond is supported by the solves, matrices and batches, not the server");
     return BIE_EINVAL;
   }
   if (cfg->opts.l2_scaling) {

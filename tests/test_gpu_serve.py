@@ -1,6 +1,7 @@
 """GPU: the serving loop (continuous batching). Requests of both kinds and uneven sizes are
-submitted while others are in flight; every result matches the float64 oracle, is the same
-alone and in the mix, and admission respects the device-memory budget."""
+submitted while others are in flight; every result matches the float64 oracle (with and without
+the block preconditioner), is the same alone and in the mix, and admission respects the
+device-memory budget."""
 import threading
 import time
 
@@ -42,11 +43,12 @@ def oracle_answers(sess):
     return ans
 
 
+@pytest.mark.parametrize("precond", [bie2d.BIE_PRECOND_NONE, bie2d.BIE_PRECOND_BLOCK])
 @pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
-def test_serve_mix_matches_oracle_and_alone(precision, tol):
+def test_serve_mix_matches_oracle_and_alone(precision, tol, precond):
     sess = sessions()
     ref = oracle_answers(sess)
-    opts = bie2d.default_opts(precision=precision, tol=1e-12, restart=30)
+    opts = bie2d.default_opts(precision=precision, tol=1e-12, restart=30, precond=precond)
     geoms = [bie2d.Geometry.from_curves(c) for _, c, _ in sess]
     # in the mix: submit everything from two threads with small random gaps
     srv = bie2d.Server(opts)
