@@ -419,6 +419,11 @@ int bie_geom_destroy(bie_geom *g) {
   g->ws_out.release();
   g->ws_read.release();
   g->ws_scale.release();
+  for (auto &pc : g->pc) {
+    pc.inv.release();
+    pc.meta.release();
+  }
+  if (g->in_ev) (void)hipEventDestroy(g->in_ev);
   if (g->fmm) fmm_destroy(g->fmm);
   delete g;
   return BIE_OK;
@@ -605,19 +610,15 @@ int bie_stokes_rigid_motion(bie_geom *g, int nrhs, const double *dens, double *V
   return read_off(g, 1, nrhs, dens, VW, as_stream(stream));
 }
 
-// Reads a solve's input ([nrhs][N] charges, or [nrhs][3N] (F, T)) to the host once: rejects
-// non-finite entries, and returns the net charge (sum q) or net force (sum F) of the
+// Checks a solve's input ([nrhs][N] charges, or [nrhs][3N] (F, T)) once it is on the host (h):
+// rejects non-finite entries, and returns the net charge (sum q) or net force (sum F) of the
 // right-hand side with the largest magnitude.
-static int input_check(int kind, int N, int nrhs, const double *data, hipStream_t s,
-                       double net[2]) {
+static int input_check(int kind, int N, int nrhs, const double *h, double net[2]) {
   const size_t width = kind == 0 ? (size_t)N : 3 * (size_t)N;
-  std::vector<double> h((size_t)nrhs * width);
-  BIE_HIP_CHECK(hipMemcpyAsync(h.data(), data, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  BIE_HIP_CHECK(hipStreamSynchronize(s));
   net[0] = net[1] = 0.0;
   double best = -1.0;
   for (int r = 0; r < nrhs; ++r) {
-    const double *v = h.data() + (size_t)r * width;
+    const double *v = h + (size_t)r * width;
     double a = 0.0, b = 0.0;
     for (size_t j = 0; j < width; ++j)
       if (!std::isfinite(v[j])) {
@@ -655,8 +656,13 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   const bie_opts o = opts_for(g, opts);
   BIE_TRY(check_opts(o));
   hipStream_t s = as_stream(stream);
-  double net[2];
-  BIE_TRY(input_check(kind, g->N, nrhs, data, s, net));
+  // the input goes to pinned host memory ahead of the right-hand side's work, and is checked
+  // while that work runs (a rejected input leaves only scratch written)
+  const size_t in_bytes = (size_t)nrhs * (kind == 0 ? g->N : 3 * (size_t)g->N) * sizeof(double);
+  BIE_TRY(g->sm.ensure_pinned(in_bytes));
+  if (!g->in_ev) BIE_HIP_CHECK(hipEventCreateWithFlags(&g->in_ev, hipEventDisableTiming));
+  BIE_HIP_CHECK(hipMemcpyAsync(g->sm.pinned, data, in_bytes, hipMemcpyDeviceToHost, s));
+  BIE_HIP_CHECK(hipEventRecord(g->in_ev, s));
   const size_t len = (size_t)g->M * (kind == 0 ? 1 : 2);
   g->fmm_order = effective_order(o, kind);
   const int meth = o.method == BIE_AUTO ? (method_is_fmm(o.method, g->M) ? BIE_FMM : BIE_DIRECT) : o.method;
@@ -669,6 +675,15 @@ static int solve_entry(bie_geom *g, int kind, int nrhs, const double *data, doub
   double *mu = mu_out ? mu_out : f + len * nrhs;
   BIE_TRY(incident_density(g, kind, nrhs, data, dens, s));
   BIE_TRY(apply_operator(g, kind, BIE_FP64, o.method, 0, -1.0, nrhs, dens, f, s));
+  double net[2];
+  BIE_HIP_CHECK(hipEventSynchronize(g->in_ev));
+  {
+    const int rc = input_check(kind, g->N, nrhs, g->sm.pinned, net);
+    if (rc != BIE_OK) {
+      (void)hipStreamSynchronize(s);
+      return rc;
+    }
+  }
   int rc = solve_system(g, kind, o, nrhs, f, mu, info, s);
   if (rc != BIE_OK && rc != BIE_ENOCONV) return rc;
   BIE_TRY(vec_axpby((long long)nrhs * len, 1.0, mu, 1.0, dens, s));  // dens = mu + incident
@@ -803,8 +818,12 @@ static int matrix_entry(bie_geom *g, int kind, double *out, int max_rhs, const b
       acc.net_charge_or_force[1] = one.net_charge_or_force[1];
     }
   }
-  hipStreamSynchronize(s);
+  const hipError_t se = hipStreamSynchronize(s);
   idbuf.release();
+  if (se != hipSuccess) {
+    set_error(std::string("matrix: stream synchronisation failed: ") + hipGetErrorString(se));
+    return BIE_EDEVICE;
+  }
   acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = acc;
   return rc_all;

@@ -188,6 +188,7 @@ struct bie_geom {
   // workspaces
   bie::DevBuf ws_apply;   // strengths + far-field partials
   bie::SolverMem sm;      // Krylov basis, vectors, reductions, pinned staging
+  hipEvent_t in_ev = nullptr;  // a solve's input has reached the pinned staging area
   bie::Segments seg;      // chunk list of the current nrhs systems
   int seg_nrhs = -1;
   long long seg_len = -1;
