@@ -55,6 +55,7 @@ int bie_batch_destroy(bie_batch *b) {
   b->seg.buf.release();
   b->flat.release();
   b->ident.release();
+  b->pcitems.release();
   bie::multi_destroy(b->plan);
   delete b;
   return BIE_OK;

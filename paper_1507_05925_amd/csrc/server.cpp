@@ -572,6 +572,7 @@ int bie_server_destroy(bie_server *srv) {
   srv->seg.buf.release();
   srv->sm.release();
   srv->flat.release();
+  srv->pcitems.release();
   bie::multi_destroy(srv->plan);
   delete srv;
   return BIE_OK;
