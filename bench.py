@@ -721,7 +721,7 @@ def main():
         coarse = lambda n: n if n <= 64 else max(d for d in range(16, 65) if n % d == 0)
         nbytes = sum(4.0 * coarse(int(n)) ** 2 for n in curves.nodes_per_body) + 16.0 * g.M
         ach = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kern = "k_pc_apply<256>"
+        kern = "k_pc_apply<512>"
         rl_pre = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
                   "frac": ach / 8000.0, "traffic": traffic_bytes(kern), "avg_launch_ms": ms,
                   "launches": pr["launches"], "multiply_adds_per_launch": pr["pairs"] /
