@@ -75,6 +75,20 @@ def test_batch_fmm_items_vs_oracle(precision, leaf):
             assert lf64 in (24, 32, 48, 64, 96, 128) and lfmx in (24, 32, 48, 64, 96, 128)
 
 
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_batch_fmm_items_preconditioned(precision):
+    """The same items with the block preconditioner (two-grid blocks for the FMM items' 256- and
+    512-node bodies): the oracle's outputs, in fewer lock-step steps."""
+    req = [(g, k, dev(inp)) for k, g, inp in items()]
+    o = opts(precision)
+    o.precond = bie2d.BIE_PRECOND_BLOCK
+    outs, info, rel = bie2d.bie_batch_solve(bie2d.Batch(), req, o)
+    check([x.cpu().numpy() for x in outs], golden(), TOL[precision], "batch, preconditioned")
+    assert (rel <= 1e-12).all(), rel
+    _, info0, _ = bie2d.bie_batch_solve(bie2d.Batch(), req, opts(precision))
+    assert info["iters"] < info0["iters"], (info, info0)
+
+
 def test_one_batch_direct_then_auto_then_direct():
     """The same batch object is solved with BIE_DIRECT, BIE_AUTO (FMM for the two large items)
     and BIE_DIRECT again: each must match the oracle (a plan kept across the method switch
