@@ -495,7 +495,9 @@ def mobility_bench(a):
         "pair_interactions_per_s": runs[best]["pair_interactions_per_s"],
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": runs[best]["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64",  # the mixed Stokes FMM keeps float64 expansions
+        "vs_baseline": None,
+        # the mixed Stokes FMM: float64 expansions, float32 near field and float64 refinement
+        "dtype": "f32+f64" if best == "mixed" else "f64",
         "data": "synthetic (seeded ellipse ensemble, F ~ N(0,1)^2 with zero total, T ~ N(0,1))",
         "config": {"workload": "mobility, 200 ellipses (aspect 1..3, gaps >= 0.2) x 512 nodes "
                                "(204,800 unknowns), FMM, GMRES tol %g" % a.tol,
@@ -660,7 +662,7 @@ def main():
         "k_near": (bie2d.BIE_K_FMM_EVAL, FLOPS_PER_PAIR, "f64", "alu", "k_near<false>"),
         "k_m2l_f32": (bie2d.BIE_K_FMM_M2L_F32, m2l_flops_per_entry(order32), "f32", "mfma",
                       f"k_m2l_fac_f32<{order32}>"),
-        "k_near_f32": (bie2d.BIE_K_FMM_NEAR_F32, FLOPS_PER_PAIR, "f32", "alu", "k_near_f32"),
+        "k_near_f32": (bie2d.BIE_K_FMM_NEAR_F32, FLOPS_PER_PAIR, "f32", "alu", "k_near_f32<false>"),
         "k_lap_epilogue": (bie2d.BIE_K_EPILOGUE, 0, "f64", "alu", "k_lap_epilogue"),
     }
     # one untimed solve with every class recorded picks the dominant kernel class; the timed

@@ -58,17 +58,17 @@ extern "C" {
 #define BIE_MIXED 1  /* float32 far field in the late GMRES steps (or the inner solves of a
                         refinement: mixed_strategy). Direct: float32 pair sums (body-relative
                         coordinates, float64 accumulation across source bodies), float64
-                        self-body blocks. FMM: float64 near field, expansions of about half the
-                        order, float32 for Laplace (multipoles, M2M, M2L, evaluation), float64
-                        for Stokes. Both: float64 diagonal, completion, Arnoldi and true
-                        residuals (float64 operator). */
+                        self-body blocks. FMM: float32 near field pair terms (float64
+                        accumulation), expansions of about half the order, float32 for Laplace
+                        (multipoles, M2M, M2L, evaluation), float64 for Stokes. Both: float64
+                        diagonal, completion, Arnoldi and true residuals (float64 operator). */
 
 /* How BIE_MIXED wins the float64 accuracy back:
  * BIE_MIXED_RELAXED  one float64 GMRES (float64 Arnoldi and residuals) whose steps apply the
  *                    BIE_MIXED operator once the estimated relative residual of every system it
  *                    applies to is below tol / eta, eta that apply's relative error (1e-7
- *                    direct, 1e-6 FMM Laplace, for FMM Stokes ten times the fitted error of
- *                    its expansion length, 2e-9 at 24 terms; measured values rounded up):
+ *                    direct, 1e-6 FMM, or for FMM Stokes ten times the fitted error of its
+ *                    expansion length where that is larger; measured values rounded up):
  *                    the error a step's apply may carry grows as the residual it reduces
  *                    falls (relaxed inexact Krylov, Simoncini & Szyld 2003). The solve stops
  *                    only on the float64 true residual of a cycle start, so a cycle that the
@@ -438,7 +438,7 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 #define BIE_K_FMM_EVAL 7        /* FMM local evaluation + near field; units: near-field pairs */
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_FMM_M2L_F32 9     /* float32 M2L of the mixed Laplace apply; units as BIE_K_FMM_M2L */
-#define BIE_K_FMM_NEAR_F32 10   /* float32 near field of the mixed Laplace apply; units: pairs  */
+#define BIE_K_FMM_NEAR_F32 10   /* float32 near field of the mixed applies; units: pairs        */
 #define BIE_K_PRECOND 11        /* block-Jacobi preconditioner apply; units: block entries read */
 #define BIE_K_COUNT 12
 /* ---- autotuning of the FMM leaf size -------------------------------------------------------

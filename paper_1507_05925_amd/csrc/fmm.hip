@@ -828,7 +828,7 @@ __global__ __launch_bounds__(256, 5) void k_near(
   }
 }
 
-// Float32 near field of the mixed-precision Laplace apply: k_near<false>'s neighbour lists,
+// Float32 near field of the mixed-precision applies: k_near's neighbour lists,
 // chunks and summation pattern, with the staged records converted to float32 coordinates
 // relative to the chunk's first target (one float64 difference, rounded once, so a target and its
 // own record still give r = 0 exactly) and float32 pair terms; each lane adds its eight-record
@@ -837,8 +837,12 @@ __global__ __launch_bounds__(256, 5) void k_near(
 constexpr float kSelfFloor32 = 1e-20f;  // |r|^2 floor (self pair): s / floor stays finite
 constexpr float kNearPad32 = 1e18f;     // padding record coordinates: |r|^2 stays finite
 
-__device__ __forceinline__ void near_seg32(const float4 *buf, int n, int g, float2 z, double &gx,
-                                           double &gy) {
+// Stokes (STOKES): records (x, y, rho_x, rho_y) and the term (r.n)(r.rho) r/|r|^4, formed as
+// (((r.rho)(r.n)) / |r|^2) / |r|^2 so that the self pair, whose r.rho is 0, gives 0 and not 0
+// times an overflowed square of the floored reciprocal.
+template <bool STOKES>
+__device__ __forceinline__ void near_seg32(const float4 *buf, int n, int g, float2 z, float2 nv,
+                                           double &gx, double &gy) {
   for (int k = 0; k < n; k += 32) {
     float4 rec[8];
 #pragma unroll
@@ -848,7 +852,13 @@ __device__ __forceinline__ void near_seg32(const float4 *buf, int n, int g, floa
     for (int u = 0; u < 8; ++u) {
       const float dx = z.x - rec[u].x, dy = z.y - rec[u].y;
       const float inv = __builtin_amdgcn_rcpf(fmaxf(fmaf(dx, dx, dy * dy), kSelfFloor32));
-      const float t = rec[u].z * inv;
+      float t;
+      if (STOKES) {
+        const float rn = fmaf(dx, nv.x, dy * nv.y);
+        t = ((fmaf(dx, rec[u].z, dy * rec[u].w) * rn) * inv) * inv;
+      } else {
+        t = rec[u].z * inv;
+      }
       sx = fmaf(dx, t, sx);
       sy = fmaf(dy, t, sy);
     }
@@ -857,7 +867,9 @@ __device__ __forceinline__ void near_seg32(const float4 *buf, int n, int g, floa
   }
 }
 
-// Stages n records src[0 .. n) at buf[at ..] relative to o, then padding up to a multiple of 32.
+// Stages n records src[0 .. n) at buf[at ..] relative to o, then padding up to a multiple of 32
+// (the fourth component: rho_y for Stokes, 0 for Laplace).
+template <bool STOKES>
 __device__ __forceinline__ int near_stage32(const double4 *__restrict__ src, int n, float4 *buf,
                                             int at, double2 o) {
   const int np = (n + 31) & ~31;
@@ -865,13 +877,15 @@ __device__ __forceinline__ int near_stage32(const double4 *__restrict__ src, int
     float4 v = make_float4(kNearPad32, kNearPad32, 0.0f, 0.0f);
     if (t < n) {
       const double4 r = src[t];
-      v = make_float4((float)(r.x - o.x), (float)(r.y - o.y), (float)r.z, 0.0f);
+      v = make_float4((float)(r.x - o.x), (float)(r.y - o.y), (float)r.z,
+                      STOKES ? (float)r.w : 0.0f);
     }
     buf[at + t] = v;
   }
   return np;
 }
 
+template <bool STOKES>
 __global__ __launch_bounds__(256, 6) void k_near_f32(
     int M, const int *__restrict__ leaf_start, const double2 *__restrict__ xs,
     const double2 *__restrict__ nrm, const int *__restrict__ perm,
@@ -889,6 +903,7 @@ __global__ __launch_bounds__(256, 6) void k_near_f32(
   const double2 o = xs[chunk_start[cb]];  // origin of the chunk's float32 coordinates
   const double2 zd = xs[min(jj, M - 1)], nv = nrm[min(jj, M - 1)];
   const float2 z = make_float2((float)(zd.x - o.x), (float)(zd.y - o.y));
+  const float2 nvf = make_float2((float)nv.x, (float)nv.y);
   const double4 *src = S4 + (size_t)r * M;
   __shared__ float4 buf[kNearCap];
   double gx = 0.0, gy = 0.0;
@@ -902,7 +917,8 @@ __global__ __launch_bounds__(256, 6) void k_near_f32(
       const int n = kr.y - kr.x;
       for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const double4 v = src[kr.x + t];
-        buf[at + t] = make_float4((float)(v.x - o.x), (float)(v.y - o.y), (float)v.z, 0.0f);
+        buf[at + t] = make_float4((float)(v.x - o.x), (float)(v.y - o.y), (float)v.z,
+                                  STOKES ? (float)v.w : 0.0f);
       }
       at += n;
     }
@@ -910,15 +926,15 @@ __global__ __launch_bounds__(256, 6) void k_near_f32(
     for (int t = total + threadIdx.x; t < padded; t += blockDim.x)
       buf[t] = make_float4(kNearPad32, kNearPad32, 0.0f, 0.0f);
     __syncthreads();
-    if (busy) near_seg32(buf, padded, g, z, gx, gy);
+    if (busy) near_seg32<STOKES>(buf, padded, g, z, nvf, gx, gy);
   } else {
     for (int e = e0; e < e1; ++e) {
       const int2 kr = run[e];
       for (int base = kr.x; base < kr.y; base += kNearCap) {
         __syncthreads();  // the previous block is no longer read
-        const int n = near_stage32(src + base, min(kNearCap, kr.y - base), buf, 0, o);
+        const int n = near_stage32<STOKES>(src + base, min(kNearCap, kr.y - base), buf, 0, o);
         __syncthreads();
-        if (busy) near_seg32(buf, n, g, z, gx, gy);
+        if (busy) near_seg32<STOKES>(buf, n, g, z, nvf, gx, gy);
       }
     }
   }
@@ -927,7 +943,13 @@ __global__ __launch_bounds__(256, 6) void k_near_f32(
   gx += __shfl_xor(gx, 32, 64);
   gy += __shfl_xor(gy, 32, 64);
   if (!valid || g != 0) return;
-  out[(size_t)r * M + perm[j]] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+  const int i = perm[j];
+  if (STOKES) {
+    out[(size_t)r * 2 * M + 2 * i] = -gx / kPi;
+    out[(size_t)r * 2 * M + 2 * i + 1] = -gy / kPi;
+  } else {
+    out[(size_t)r * M + i] = -(nv.x * gx + nv.y * gy) / (2.0 * kPi);
+  }
 }
 
 // Downward pass and evaluation in one: the local expansion of a leaf is the sum over its
@@ -2162,7 +2184,8 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
   FmmTree &t = *tp;
   const int M = t.M;
   const int nsets = kind == 0 ? R : 3 * R;
-  // float32 expansions and near field for the mixed-precision Laplace apply
+  // float32 expansions for the mixed-precision Laplace apply (the near field of every mixed
+  // apply is float32)
   const bool f32 = precision == BIE_MIXED && kind == 0;
   const size_t csz = f32 ? sizeof(float2) : sizeof(double2);
   // work: near-field source records S4 [R][M] (32 B), charges Q [nsets][M], multipoles and
@@ -2206,10 +2229,16 @@ int fmm_far_field(bie_geom *g, int kind, int precision, int R, const double *mu,
       hipLaunchKernelGGL(k_body_sums, dim3(g->N, R), dim3(256), 0, plan.side, M, g->N,
                          g->body_ptr, s64, charge);
     {
-      ProfScope pe(kind == 0 && f32 ? BIE_K_FMM_NEAR_F32 : BIE_K_FMM_EVAL, plan.side,
+      // the float32 near field in every mixed apply (Laplace and Stokes)
+      const bool near32 = precision == BIE_MIXED;
+      ProfScope pe(near32 ? BIE_K_FMM_NEAR_F32 : BIE_K_FMM_EVAL, plan.side,
                    (t.near_pairs - M) * R);
-      if (kind == 0 && f32)
-        hipLaunchKernelGGL(k_near_f32, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
+      if (kind == 0 && near32)
+        hipLaunchKernelGGL(k_near_f32<false>, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
+                           t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
+                           t.chunk_start, S4, partial);
+      else if (near32)
+        hipLaunchKernelGGL(k_near_f32<true>, dim3(t.nchunk, R), dim3(256), 0, plan.side, M,
                            t.leaf_start, t.xs, t.nrm, t.perm, t.run_ptr, t.run, t.chunk_leaf,
                            t.chunk_start, S4, partial);
       else if (kind == 0)

@@ -153,9 +153,9 @@ def test_fmm_full_size_elastance(precision, tol):
 
 @pytest.mark.parametrize("kind", ["laplace", "stokes"])
 def test_fmm_mixed_apply_accuracy(kind):
-    """The inner apply of mixed-precision refinement: float32 expansions (Laplace) or a
-    half-length float64 FMM (Stokes), the near field in float64. Its error against the float64
-    direct apply sits at the float32 / truncation level that the refinement removes."""
+    """The inner apply of mixed-precision refinement: float32 expansions (Laplace) or float64
+    ones of about half the length (Stokes), the near field in float32 for both. Its error against
+    the float64 direct apply sits at the float32 / truncation level that the refinement removes."""
     rng = np.random.default_rng(4)
     for name, c in _cases().items():
         g = bie2d.Geometry.from_curves(c)
