@@ -439,7 +439,7 @@ int bie_server_inject_failure(bie_server *srv, int cycles);
 #define BIE_K_DOUBLE_LAYER 8    /* double-layer applies of the capacitance / resistance solves; units: M^2 per rhs */
 #define BIE_K_FMM_M2L_F32 9     /* float32 M2L of the mixed Laplace apply; units as BIE_K_FMM_M2L */
 #define BIE_K_FMM_NEAR_F32 10   /* float32 near field of the mixed applies; units: pairs        */
-#define BIE_K_PRECOND 11        /* block-Jacobi preconditioner apply; units: block entries read */
+#define BIE_K_PRECOND 11        /* block preconditioner apply; units: its multiply-adds         */
 #define BIE_K_COUNT 12
 /* ---- autotuning of the FMM leaf size -------------------------------------------------------
  * The leaf population trades near-field pair work against expansion work; the best value

@@ -321,7 +321,7 @@ int autotune_leaf(bie_geom *g, int kind, int precision, int nrhs, hipStream_t s)
 // Sets g's FMM leaf sizes for a solve with opts o: o.fmm_leaf > 0 for both precisions; 0 = the
 // autotuner's (tune true) or 64 (tune false: callers that must not pause to time applies).
 int resolve_leaf(bie_geom *g, int kind, const bie_opts &o, int nrhs, bool tune, hipStream_t s);
-// ---- precond.hip: block-Jacobi right preconditioner of the Laplace operator -----------------
+// ---- precond.hip: block right preconditioner of the Laplace and Stokes operators ------------
 // Block preconditioner of kind 0 (Laplace) or 1 (Stokes): built once per geometry and kind
 // (BIE_EINVAL for a body it cannot coarsen); apply out = P in, [nrhs][M] resp. [nrhs][2M].
 int pc_build(bie_geom *g, int kind, hipStream_t s);

@@ -160,8 +160,8 @@ __global__ __launch_bounds__(BJ) void k_pc_check(int kind, const int *__restrict
 template <int NT>
 __device__ void pc_body(int kind, int M, int b, int r, const int *__restrict__ body_ptr,
                         const int *__restrict__ ncoarse, const float *__restrict__ inv, int BJ,
-                        const double *__restrict__ in, double *__restrict__ out, double *vs,
-                        double *wv, double *yv, double *part) {
+                        const double *in, double *out, double *vs, double *wv, double *yv,
+                        double *part) {  // in == out allowed: the body is staged first
   const int t = threadIdx.x;
   const int off = body_ptr[b], n = body_ptr[b + 1] - off, nc = ncoarse[b], s = n / nc;
   const int C = kind == 0 ? 1 : 2, U = C * nc, F = C * n;
@@ -222,8 +222,8 @@ __global__ __launch_bounds__(NT) void k_pc_apply(int kind, int M, int BJ,
                                                  const int *__restrict__ body_ptr,
                                                  const int *__restrict__ ncoarse,
                                                  const float *__restrict__ inv,
-                                                 const double *__restrict__ in,
-                                                 double *__restrict__ out) {
+                                                 const double *in,
+                                                 double *out) {  // in == out allowed
   extern __shared__ double vs[];
   __shared__ double wv[2 * kPcNodes], yv[2 * kPcNodes], part[NT];
   pc_body<NT>(kind, M, blockIdx.x, blockIdx.y, body_ptr, ncoarse, inv, BJ, in, out, vs, wv, yv,
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(NT) void k_pc_apply(int kind, int M, int BJ,
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pc_apply_batch(int nitems,
                                                        const PcBatchItem *__restrict__ items,
-                                                       const double *__restrict__ in,
-                                                       double *__restrict__ out) {
+                                                       const double *in,
+                                                       double *out) {  // in == out allowed
   extern __shared__ double vs[];
   __shared__ double wv[2 * kPcNodes], yv[2 * kPcNodes], part[NT];
   const int w = blockIdx.x;
@@ -329,10 +329,6 @@ int pc_build(bie_geom *g, int kind, hipStream_t s) {
   pc.ready = true;
   return BIE_OK;
 }
-
-namespace {
-
-}  // namespace
 
 int pc_apply(bie_geom *g, int kind, int nrhs, const double *in, double *out, hipStream_t s) {
   const bie_geom::Precond &pc = g->pc[kind & 1];
