@@ -139,3 +139,24 @@ def test_serve_failed_cycle_fails_only_its_requests():
     assert float(np.abs(out - ref).max() / np.abs(ref).max()) < 1e-10
     assert srv.stats()["requests"] == 2
     srv.close()
+
+
+def test_serve_precond_refusal_fails_only_that_request():
+    """With the block preconditioner, a request on a geometry whose bodies it cannot coarsen (a
+    body of 257 nodes: no divisor in [16, 64]) fails alone with BIE_EINVAL while it is being
+    admitted; a request submitted beside it completes and matches the oracle."""
+    rng = np.random.default_rng(47)
+    bad = bie2d.Geometry.from_curves(wl.mixed_grid(rng, 3, np.array([64, 257, 96])))
+    kind, c, qs = sessions()[0]
+    good = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    ref = ny.elastance_solve(geo, qs[0])["phi"] if kind == 0 else ny.mobility_solve(geo, qs[0])["VW"]
+    srv = bie2d.Server(bie2d.default_opts(tol=1e-12, restart=30, precond=bie2d.BIE_PRECOND_BLOCK))
+    tb = srv.submit(bad, 0, rng.standard_normal((1, 3)))
+    tg = srv.submit(good, kind, qs[0])
+    _, info = srv.wait(tb, timeout=120, raise_on_error=False)
+    assert info["status"] == bie2d.BIE_EINVAL, info
+    out, info = srv.wait(tg, timeout=120)
+    assert info["status"] == 0
+    assert float(np.abs(out - ref).max() / np.abs(ref).max()) < 1e-10
+    srv.close()
