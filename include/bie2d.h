@@ -67,7 +67,7 @@ extern "C" {
  * BIE_MIXED_RELAXED  one float64 GMRES (float64 Arnoldi and residuals) whose steps apply the
  *                    BIE_MIXED operator once the estimated relative residual of every system it
  *                    applies to is below tol / eta, eta that apply's relative error (1e-7
- *                    direct, 1e-6 FMM, or for FMM Stokes ten times the fitted error of its
+ *                    direct, 5e-7 FMM, or for FMM Stokes ten times the fitted error of its
  *                    expansion length where that is larger; measured values rounded up):
  *                    the error a step's apply may carry grows as the residual it reduces
  *                    falls (relaxed inexact Krylov, Simoncini & Szyld 2003). The solve stops

@@ -457,8 +457,10 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
 // The BIE_MIXED apply's relative error (2-norm, random densities, against the float64 direct
 // apply), from measurements on the 1000-starfish and 200-ellipse geometries: direct float32 far
 // field 2.4e-8 .. 4.4e-8 (taken as 1e-7); FMM Laplace with float32 expansions and near field
-// 2.6e-7 .. 3.1e-7 at 24 terms, set by the float32 rounding (taken as 1e-6); FMM Stokes with
-// float64 expansions and the float32 near field: the larger of the same rounding level and ten
+// 2.6e-7 .. 3.1e-7 at 24 terms, set by the float32 rounding (taken as 5e-7: on the preconditioned
+// 1000-starfish solve one more of the 12 steps runs in float32 than with 1e-6, same accuracy);
+// FMM Stokes with float64 expansions and the float32 near field (4.3e-7 on the 200 ellipses):
+// the larger of the same rounding level and ten
 // times the fitted truncation error 4.3e-2 * 0.45^terms (which alone measured 1.4e-10 .. 2.0e-10
 // at 24 terms, 0.8e-7 .. 1.2e-7 at 16). A value set too large only delays the switch; one too
 // small can cost a further restart cycle, never accuracy (the solve stops on float64 true
@@ -467,7 +469,7 @@ double mixed_apply_error(const bie_geom *g, int kind, int method, int order) {
   if (!method_is_fmm(method, g->M)) return 1e-7;
   const int terms = fmm_length(order, BIE_MIXED);
   const double trunc = ((kind & 1) ? 4.3e-2 : 2.1e-3) * std::pow(0.45, terms);
-  return std::max(1e-6, 10.0 * trunc);
+  return std::max(5e-7, 10.0 * trunc);
 }
 
 // One Arnoldi cycle (at most m steps, x0 = 0) on A d = r for every system, each system stopping
