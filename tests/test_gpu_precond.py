@@ -77,6 +77,27 @@ def test_precond_elastance_two_grid_vs_oracle(precision, tol):
     assert info["iters"] < i0["iters"], (info, i0)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("precision,tol", [(bie2d.BIE_FP64, 1e-10), (bie2d.BIE_MIXED, 1e-9)])
+def test_precond_uneven_bodies_vs_oracle(kind, precision, tol):
+    """Every block regime in one geometry: exact blocks of 16, 40 and 64 nodes, two-grid blocks of
+    66 nodes (33 coarse, every second), 100 nodes (50 coarse) and 2048 nodes (64 coarse, every
+    32nd: the largest body the apply stages); for mobility the blocks of more than 32 coarse nodes
+    take the 128-wide layout."""
+    rng = np.random.default_rng(53)
+    c = wl.mixed_grid(rng, 6, np.array([16, 40, 64, 66, 100, 2048]))
+    g = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    width = geo["N"] if kind == 0 else 3 * geo["N"]
+    X = rng.standard_normal((2, width))
+    ref = (ny.elastance_solve if kind == 0 else ny.mobility_solve)(geo, X)
+    key = "phi" if kind == 0 else "VW"
+    o = bie2d.default_opts(precision=precision, precond=bie2d.BIE_PRECOND_BLOCK, tol=1e-12)
+    solve = bie2d.bie_elastance_solve if kind == 0 else bie2d.bie_mobility_solve
+    out, info = solve(g, dev(X), o)
+    assert rel(out, ref[key]) < tol, info
+
+
 @pytest.mark.parametrize("method", [bie2d.BIE_DIRECT, bie2d.BIE_FMM])
 def test_precond_same_solution_fewer_steps(method):
     """100 starfish of 256 nodes (gap >= 0.3; two-grid blocks on 64 nodes): the same potentials
