@@ -177,7 +177,27 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   std::vector<double> fnorm, beta;
   if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
   BIE_TRY(seg_nrm2(sg, f, wk.nrm, wk.scratch, s));
-  BIE_TRY(read_host(mem, wk.nrm, S, fnorm, s));
+  // pinned host memory of a cycle: two column slots (the S columns, then one flag word per
+  // system), the tag base, then (from x = 0) the norms of f
+  const size_t slot = (size_t)S * hs + S, fn_at = 2 * slot + 1;
+  // From x = 0 the first cycle starts from r = f without a host round trip: its Givens
+  // recurrence runs on f / ||f|| (beta 1, relative residuals directly), and the norms, copied to
+  // pinned memory behind the norm kernel, are read once the cycle's steps are complete, to scale
+  // its coefficients y. Every system then starts active (a zero f gives V_0 = 0 and a zero
+  // correction); with a tolerance of 1 or more a system would start converged, and its device
+  // norm would have to be cleared from the host: those calls read the norms first.
+  bool defer = x_is_zero;
+  for (int r = 0; r < S; ++r) defer = defer && tol[r] < 1.0;
+  bool fn_pending = false;
+  if (defer) {
+    BIE_TRY(mem.ensure_pinned((fn_at + S) * sizeof(double)));
+    BIE_HIP_CHECK(hipMemcpyAsync(mem.pinned + fn_at, wk.nrm, S * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    fnorm.assign(S, 1.0);
+    fn_pending = true;
+  } else {
+    BIE_TRY(read_host(mem, wk.nrm, S, fnorm, s));
+  }
   relres.assign(S, 0.0);
   conv.assign(S, 0);
   std::vector<char> done(S, 0);  // converged systems stay converged (their x no longer changes)
@@ -242,10 +262,9 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     // column, written by the last kernel into pinned slot j % 2. Steps run one ahead of the
     // host: step j+1 is queued before the host waits for step j's column (a cycle that stops at
     // step j leaves step j+1's work unused).
-    // pinned: two slots (the S columns, then one flag word per system), then the tag base of
-    // this cycle (step j stores the tag of base + j + 1); the base is written before the
-    // cycle's first step, when no earlier step is in flight
-    const size_t slot = (size_t)S * hs + S;
+    // pinned: the two column slots, then the tag base of this cycle (step j stores the tag of
+    // base + j + 1); the base is written before the cycle's first step, when no earlier step is
+    // in flight (the norms of f behind it, if pending, stay untouched)
     BIE_TRY(mem.ensure_pinned((2 * slot + 1) * sizeof(double)));
     volatile unsigned long long *base_h =
         reinterpret_cast<volatile unsigned long long *>(mem.pinned + 2 * slot);
@@ -425,6 +444,12 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       wlast = *std::max_element(gworst.begin(), gworst.end());
     }
     BIE_HIP_CHECK(hipStreamSynchronize(s));  // the steps queued ahead, if any, are complete
+    // the first cycle from f ran on f / ||f||: its coefficients scale by ||f||
+    std::vector<double> yscale(S, 1.0);
+    if (fn_pending) {
+      for (int r = 0; r < S; ++r) fnorm[r] = yscale[r] = mem.pinned[fn_at + r];
+      fn_pending = false;
+    }
     // y = H^{-1} g (upper triangular), x += V y
     const int nv = jend + 1;
     std::vector<double> yv((size_t)S * hs, 0.0);
@@ -440,6 +465,7 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
         const double d = Hc[(size_t)i * (m + 1) + i];
         yr[i] = d != 0.0 ? acc / d : 0.0;
       }
+      for (int i = 0; i < k; ++i) yr[i] *= yscale[r];
     }
     // y to the device: the stream is idle (synchronised above), so the pinned staging area is
     // free; the host writes it again only after a later synchronisation

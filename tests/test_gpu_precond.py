@@ -207,3 +207,28 @@ def test_precond_batch_alone_and_in_the_mix(precision):
     g, k, inp = items[1]
     vw, _ = bie2d.bie_mobility_solve(g, inp, o)
     assert float((vw - mix[1]).abs().max() / vw.abs().max()) < 1e-10
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("precision", [bie2d.BIE_FP64, bie2d.BIE_MIXED])
+def test_zero_rhs_among_others(kind, precision):
+    """A zero right-hand side among others (its first GMRES cycle runs on a zero vector before the
+    norms of f reach the host): its result is exactly zero, the others match the oracle, with and
+    without the preconditioner."""
+    c, data = wl.elastance_small() if kind == 0 else wl.mobility_ellipses(nbodies=4, n=64)
+    g = bie2d.Geometry.from_curves(c)
+    geo = ny.geometry_of(c)
+    rng = np.random.default_rng(59)
+    width = geo["N"] if kind == 0 else 3 * geo["N"]
+    X = np.vstack([rng.standard_normal((1, width)), np.zeros((1, width)),
+                   rng.standard_normal((1, width))])
+    key = "phi" if kind == 0 else "VW"
+    ref = (ny.elastance_solve if kind == 0 else ny.mobility_solve)(geo, X[[0, 2]])[key]
+    solve = bie2d.bie_elastance_solve if kind == 0 else bie2d.bie_mobility_solve
+    tol = 1e-10 if precision == bie2d.BIE_FP64 else 1e-9
+    for pc in (bie2d.BIE_PRECOND_NONE, bie2d.BIE_PRECOND_BLOCK):
+        o = bie2d.default_opts(precision=precision, precond=pc, tol=1e-12)
+        out, info = solve(g, dev(X), o)
+        out = out.cpu().numpy()
+        assert np.all(out[1] == 0.0), (pc, np.abs(out[1]).max())
+        assert rel(out[[0, 2]], ref) < tol, (pc, info)
