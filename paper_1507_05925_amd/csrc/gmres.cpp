@@ -178,8 +178,9 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   if (x_is_zero) BIE_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
   BIE_TRY(seg_nrm2(sg, f, wk.nrm, wk.scratch, s));
   // pinned host memory of a cycle: two column slots (the S columns, then one flag word per
-  // system), the tag base, then (from x = 0) the norms of f
-  const size_t slot = (size_t)S * hs + S, fn_at = 2 * slot + 1;
+  // system), the tag base, (from x = 0) the norms of f, and the staging of the coefficients y
+  const size_t slot = (size_t)S * hs + S, fn_at = 2 * slot + 1, y_at = fn_at + S;
+  BIE_TRY(mem.ensure_pinned((y_at + (size_t)S * hs) * sizeof(double)));
   // From x = 0 the first cycle starts from r = f without a host round trip: its Givens
   // recurrence runs on f / ||f|| (beta 1, relative residuals directly), and the norms, copied to
   // pinned memory behind the norm kernel, are read once the cycle's steps are complete, to scale
@@ -190,7 +191,6 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
   for (int r = 0; r < S; ++r) defer = defer && tol[r] < 1.0;
   bool fn_pending = false;
   if (defer) {
-    BIE_TRY(mem.ensure_pinned((fn_at + S) * sizeof(double)));
     BIE_HIP_CHECK(hipMemcpyAsync(mem.pinned + fn_at, wk.nrm, S * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     fnorm.assign(S, 1.0);
@@ -443,7 +443,10 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       wlast2 = wlast;
       wlast = *std::max_element(gworst.begin(), gworst.end());
     }
-    BIE_HIP_CHECK(hipStreamSynchronize(s));  // the steps queued ahead, if any, are complete
+    // No stream synchronisation here: the last column's flag shows that every step whose basis
+    // vectors y combines has run (a step queued ahead writes only the next column slot, the
+    // next basis vector and candidate), and that the copy of the norms of f, queued before the
+    // first step, is complete.
     // the first cycle from f ran on f / ||f||: its coefficients scale by ||f||
     std::vector<double> yscale(S, 1.0);
     if (fn_pending) {
@@ -467,11 +470,10 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
       }
       for (int i = 0; i < k; ++i) yr[i] *= yscale[r];
     }
-    // y to the device: the stream is idle (synchronised above), so the pinned staging area is
-    // free; the host writes it again only after a later synchronisation
-    BIE_TRY(mem.ensure_pinned(yv.size() * sizeof(double)));
-    std::memcpy(mem.pinned, yv.data(), yv.size() * sizeof(double));
-    BIE_HIP_CHECK(hipMemcpyAsync(wk.y, mem.pinned, yv.size() * sizeof(double),
+    // y to the device through its own pinned area: the previous copy from it is complete, as it
+    // was queued on this stream before this cycle's steps, whose columns the host has seen
+    std::memcpy(mem.pinned + y_at, yv.data(), yv.size() * sizeof(double));
+    BIE_HIP_CHECK(hipMemcpyAsync(wk.y, mem.pinned + y_at, yv.size() * sizeof(double),
                                  hipMemcpyHostToDevice, s));
     BIE_TRY(seg_combination(sg, nv, wk.V, N, wk.y, hs, x, 1.0, s));
   }
