@@ -263,8 +263,12 @@ int gmres(SysSet &ss, int precision, const double *f, double *x, bool x_is_zero,
     // host: step j+1 is queued before the host waits for step j's column (a cycle that stops at
     // step j leaves step j+1's work unused).
     // pinned: the two column slots, then the tag base of this cycle (step j stores the tag of
-    // base + j + 1); the base is written before the cycle's first step, when no earlier step is
-    // in flight (the norms of f behind it, if pending, stay untouched)
+    // base + j + 1; its kernels read the base when they run). The base is written before the
+    // cycle's first step, when no earlier step is in flight: a later cycle starts after the
+    // host read of its true residual (a stream synchronisation), and every caller synchronises
+    // the stream between two calls of this function (a solve ends with one; the serving loop
+    // and the refinement read a residual norm in between). The norms of f behind the base, if
+    // pending, stay untouched.
     BIE_TRY(mem.ensure_pinned((2 * slot + 1) * sizeof(double)));
     volatile unsigned long long *base_h =
         reinterpret_cast<volatile unsigned long long *>(mem.pinned + 2 * slot);
