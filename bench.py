@@ -6,12 +6,12 @@ One timed step = one whole solve on that resident geometry: incident charge and 
 GMRES to a relative residual of 1e-10 with the operator apply (far field by the 2D FMM, float64
 self terms, diagonal and completion), potentials read off inside every conductor. By default the
 solves are mixed precision (float64 GMRES whose late steps apply the float32 operator) with the
-block-Jacobi right preconditioner, checked against the stored float64 oracle potentials;
-`fp64_path` times the same solves in float64, `unpreconditioned` the mixed solves without the
-preconditioner (the paper's plain GMRES).
+block right preconditioner (two-grid blocks on 64 coarse nodes per body), checked against the
+stored float64 oracle potentials; `fp64_path` times the same solves in float64,
+`unpreconditioned` the mixed solves without the preconditioner (the paper's plain GMRES).
 
-Reported value: pair interactions per second, counted as M^2 per operator apply (for the FMM this
-is the equivalent direct count, labelled as such in `metric`), over the timed steps.
+Reported value: solves per second over the timed steps; pair interactions per second (M^2 per
+operator apply, for the FMM the equivalent direct count, labelled as such) alongside.
 `roofline` is for the kernel that takes the most time in the timed steps, measured with HIP
 events on the launch stream; `roofline_direct_p2p` is the direct float32 far-field sweep on the
 same workload.

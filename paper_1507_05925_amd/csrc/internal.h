@@ -199,7 +199,6 @@ struct bie_geom {
   int fmm_order = 40;  // expansion order of the float64 FMM apply (set from bie_opts)
   int fmm_leaf = 64;   // maximum nodes per leaf box
   int fmm_leaf_mixed = 0;  // leaf size of the mixed-precision applies (0: fmm_leaf)
-  // block-Jacobi preconditioner (Laplace): float32 inverses of the bodies' self blocks
   // block preconditioner per kind (precond.hip): inverted coarse blocks [N][BJ][BJ] (float32,
   // column-major, inv); per body the coarse node count (meta)
   struct Precond {
