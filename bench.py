@@ -826,7 +826,7 @@ def main():
               "us_per_step_graph_minus_stream": 1e3 * (ms_graph - ms_stream) / max(info["iters"], 1),
               "steps_captured": captured, "steps_replayed": replayed}
 
-    # the direct float32 far-field sweep on the same workload (survey row a3), 5 applies
+    # the direct float32 far-field sweep on the same workload, 5 applies
     mu = torch.randn(1, g.M, dtype=torch.float64, device=dev)
     bie2d.bie_laplace_apply(g, mu, bie2d.BIE_MIXED, bie2d.BIE_DIRECT)
     torch.cuda.synchronize()
